@@ -1,0 +1,295 @@
+/*
+ * kpa.h -- C ABI of the Key Pointer Array (KPA) grouping library for AMD
+ * Instinct MI355X (gfx950).
+ *
+ * A KPA (StreamBox-HBM, ASPLOS'19, Sec. 4.1) is a sequence of pairs of one
+ * resident key column and a pointer to the full record.  Here the pointer is a
+ * 32-bit row index ("rid") into the caller's arena of fixed-size rows, and a
+ * KPA is stored as two parallel device arrays: uint64_t keys[n], uint32_t
+ * rids[n] (12 bytes per entry).  The calls implement the primitives of the
+ * paper's Table 2 (Extract, Partition, Sort, Merge, Join, Keyed reduction,
+ * Materialize) and the compound operators of Sec. 4.2 built on them
+ * (windowing = partition on the timestamp column; keyed aggregation = sort
+ * then per-key reduction; temporal join = sort both sides then one scan).
+ *
+ * Conventions for every call
+ *  - Return value: kpa_status (0 = KPA_OK).  No C++ exception crosses the ABI.
+ *    On failure nothing has been enqueued unless the status is KPA_EHIP; the
+ *    message is available from kpa_last_error_string() (thread-local).
+ *  - Ownership: every array is allocated and owned by the caller.  Arrays named
+ *    "device" must be device memory (or host memory mapped for device access)
+ *    of the current HIP device.  The stateless calls never allocate: a call
+ *    that needs scratch memory takes a workspace pointer (device memory, 256-
+ *    byte aligned) and its size; kpa_<op>_workspace_size() reports the size.
+ *    Too small a workspace returns KPA_EWORKSPACE.
+ *  - Asynchrony: every call enqueues work on `stream` and returns; outputs are
+ *    valid once the stream has been synchronized.  Scalar outputs (counts,
+ *    sums) are device pointers.  Calls on one stream run in order; calls on
+ *    different streams must not share a workspace.
+ *  - Alignment: keys/u64 arrays 8-byte aligned, rids 4-byte aligned, row
+ *    arenas 16-byte aligned, otherwise KPA_EINVAL.
+ *  - Sizes: n = 0 is a valid no-op.  A single KPA or segment holds fewer than
+ *    2^30 entries (KPA_EUNSUPPORTED otherwise); rids are 32-bit.
+ *  - Keys are unsigned 64-bit and compared as unsigned.
+ *  - Sums and products wrap modulo 2^64.
+ */
+#ifndef KPA_H_
+#define KPA_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t kpa_status;
+enum {
+  KPA_OK = 0,
+  KPA_EINVAL = -1,       /* bad argument (null pointer, misalignment, bad layout) */
+  KPA_EWORKSPACE = -2,   /* workspace too small; *needed bytes written where asked */
+  KPA_ECAPACITY = -3,    /* an output exceeds the capacity the caller gave */
+  KPA_EBUDGET = -4,      /* serving admission: memory budget exhausted */
+  KPA_EUNSUPPORTED = -5, /* size or parameter beyond what this build handles */
+  KPA_EHIP = -6          /* a HIP runtime call failed; see kpa_last_error_string() */
+};
+
+/* Byte layout of a fixed-size little-endian row ("full record").  The key is a
+ * u64 at key_off; value and timestamp are u32 or u64 (width 4 or 8). */
+typedef struct kpa_row_layout {
+  uint32_t row_bytes; /* multiple of 4, at most 256 */
+  uint32_t key_off;   /* 8-byte aligned offset of the u64 key */
+  uint32_t val_off;   /* offset of the value column, aligned to val_w */
+  uint32_t val_w;     /* 4 or 8 */
+  uint32_t ts_off;    /* offset of the event timestamp, aligned to ts_w */
+  uint32_t ts_w;      /* 4 or 8 */
+} kpa_row_layout;
+
+/* Library version (major*10000 + minor*100 + patch). */
+int32_t kpa_version(void);
+/* Message of the last failing call on this thread ("" if none). */
+const char* kpa_last_error_string(void);
+/* Sets *out to 1 if the current HIP device is gfx950, else 0. */
+kpa_status kpa_device_check(int32_t* out);
+
+/* ---------------------------------------------------------------------------
+ * Extract (Table 2: bundle -> KPA, sequential).  keys[i] = u64 at key_off of
+ * row i, rids[i] = rid_base + i.  rows: device, n rows.  out_keys/out_rids:
+ * device, n entries each.
+ */
+kpa_status kpa_extract(const void* rows, uint64_t n, const kpa_row_layout* layout,
+                       uint32_t rid_base, uint64_t* out_keys, uint32_t* out_rids,
+                       hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Extract fused with windowing (Sec. 4.2 "Windowing": Partition on the
+ * timestamp column with the window length as the range of each partition).
+ * Window w holds the rows whose timestamp ts satisfies
+ *   win_origin + w*win_len <= ts < win_origin + (w+1)*win_len,  0 <= w < n_win,
+ * in arrival order (ascending rid = rid_base + row index).  The windows are
+ * written back to back into out_keys/out_rids (device, capacity n each);
+ * out_win_off (device, n_win+1 u64) receives the start of each window and the
+ * total.  Rows outside all windows are not written; their number goes to
+ * *out_oob (device u64).  1 <= n_win <= 256, win_len >= 1.
+ */
+kpa_status kpa_partition_windows_workspace_size(uint64_t n, uint32_t n_win, size_t* bytes);
+kpa_status kpa_partition_windows(const void* rows, uint64_t n, const kpa_row_layout* layout,
+                                 uint64_t win_len, uint64_t win_origin, uint32_t n_win,
+                                 uint32_t rid_base, uint64_t* out_keys, uint32_t* out_rids,
+                                 uint64_t* out_win_off, uint64_t* out_oob, void* ws,
+                                 size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Sort (Table 2: KPA(c) -> KPA(c), sequential access).  Stable sort by key:
+ * equal keys keep their input order (for KPAs from Extract/Partition, that is
+ * ascending rid).  Segmented form: segment s is [seg_off[s], seg_off[s+1])
+ * (seg_off: device, n_seg+1 u64, nondecreasing, seg_off[n_seg] <= n_cap) and
+ * is sorted on its own; all segments go through the same launches.  n_cap is
+ * a host-side upper bound on seg_off[n_seg] used to size launches.  keys_in
+ * must not alias keys_out (likewise rids).  The inputs are not modified.
+ *
+ * algo KPA_SORT_RADIX: least-significant-digit radix sort with 8-bit digits;
+ * digits that are constant within a segment are skipped.
+ * algo KPA_SORT_LEARNED: a learned-splitter sort.  models (device, one
+ * kpa_pwl_model per segment) give a nondecreasing CDF estimate F; each key goes
+ * to bucket floor(B*F(key)), buckets are formed by stable scatters and each
+ * bucket is finished in on-chip memory.  Buckets too large for that, or whose
+ * order the model would break, are re-sorted by the radix path.  The model
+ * affects only speed: the output equals the radix sort's, byte for byte.
+ * stats (device, may be NULL) receives counters of the learned path.
+ */
+typedef enum kpa_sort_algo { KPA_SORT_RADIX = 0, KPA_SORT_LEARNED = 1 } kpa_sort_algo;
+
+#define KPA_PWL_MAX_SEG 1024
+/* Piecewise-linear CDF model with n_seg equal-width segments over
+ * [kmin, kmax]; knots[j] = estimate of F at kmin + floor(j*(kmax-kmin)/n_seg).
+ * F(key) = 0 below kmin, 1 above kmax, linear between knots (clamped to the
+ * segment's knots so that F never decreases).  Lives in device memory. */
+typedef struct kpa_pwl_model {
+  uint64_t kmin;
+  uint64_t kmax;
+  uint32_t n_seg; /* 1..KPA_PWL_MAX_SEG; 0 marks an empty (unusable) model */
+  uint32_t reserved;
+  float knots[KPA_PWL_MAX_SEG + 1];
+  float pad[3];
+} kpa_pwl_model;
+
+typedef struct kpa_sort_stats {
+  uint64_t n_buckets;          /* buckets formed by the learned path */
+  uint64_t finished_on_chip;   /* entries sorted in on-chip memory */
+  uint64_t equal_key_entries;  /* entries in single-key buckets (no sort needed) */
+  uint64_t fallback_entries;   /* entries re-sorted by the radix path */
+  uint64_t fallback_buckets;   /* buckets re-sorted by the radix path */
+  uint64_t order_violations;   /* buckets whose key range overlapped a neighbour */
+} kpa_sort_stats;
+
+kpa_status kpa_sort_workspace_size(uint64_t n_cap, uint32_t n_seg, kpa_sort_algo algo,
+                                   size_t* bytes);
+kpa_status kpa_sort_segmented(const uint64_t* keys_in, const uint32_t* rids_in,
+                              uint64_t* keys_out, uint32_t* rids_out, const uint64_t* seg_off,
+                              uint32_t n_seg, uint64_t n_cap, kpa_sort_algo algo,
+                              const kpa_pwl_model* models, kpa_sort_stats* stats, void* ws,
+                              size_t ws_bytes, hipStream_t stream);
+/* One segment of n entries (n known on the host). */
+kpa_status kpa_sort(const uint64_t* keys_in, const uint32_t* rids_in, uint64_t n,
+                    uint64_t* keys_out, uint32_t* rids_out, kpa_sort_algo algo,
+                    const kpa_pwl_model* model, kpa_sort_stats* stats, void* ws, size_t ws_bytes,
+                    hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Merge (Table 2: two sorted KPAs -> one sorted KPA, sequential).  Stable: on
+ * equal keys every entry of A precedes every entry of B.  All arrays device;
+ * outputs hold na+nb entries and must not alias the inputs.
+ */
+kpa_status kpa_merge_workspace_size(uint64_t na, uint64_t nb, size_t* bytes);
+kpa_status kpa_merge(const uint64_t* a_keys, const uint32_t* a_rids, uint64_t na,
+                     const uint64_t* b_keys, const uint32_t* b_rids, uint64_t nb,
+                     uint64_t* out_keys, uint32_t* out_rids, void* ws, size_t ws_bytes,
+                     hipStream_t stream);
+/* Merge n_runs consecutive sorted runs [run_off[r], run_off[r+1]) of one array
+ * (run_off: HOST array of n_runs+1 u64) into one sorted KPA; ties keep run
+ * order.  keys/rids are used as scratch and hold garbage afterwards. */
+kpa_status kpa_merge_runs_workspace_size(uint64_t n, size_t* bytes);
+kpa_status kpa_merge_runs(uint64_t* keys, uint32_t* rids, const uint64_t* run_off,
+                          uint32_t n_runs, uint64_t* out_keys, uint32_t* out_rids, void* ws,
+                          size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Keyed reduction (Table 2; Sec. 4.1 per-key aggregation: scan a sorted KPA,
+ * follow the pointers, coalesce a nonresident column over each run of equal
+ * keys).  Input: a KPA sorted by key within each segment (segments as in
+ * kpa_sort_segmented); rows: device arena of full records (the rids index it).
+ * A group is a maximal run of equal keys inside one segment.  For each group,
+ * in order: out_gkey = key, out_cnt = entries, out_sum = sum of values mod
+ * 2^64, out_max = largest value, out_gstart = index of its first entry.  Any
+ * of out_cnt/out_sum/out_max/out_gstart may be NULL.  Outputs (device) need
+ * capacity n_cap.  out_gseg_off (device, n_seg+1 u64): first group of each
+ * segment and the total number of groups.
+ */
+kpa_status kpa_reduce_by_key_workspace_size(uint64_t n_cap, uint32_t n_seg, size_t* bytes);
+kpa_status kpa_reduce_by_key(const uint64_t* keys, const uint32_t* rids, const uint64_t* seg_off,
+                             uint32_t n_seg, uint64_t n_cap, const void* rows,
+                             const kpa_row_layout* layout, uint64_t* out_gkey, uint64_t* out_cnt,
+                             uint64_t* out_sum, uint64_t* out_max, uint64_t* out_gstart,
+                             uint64_t* out_gseg_off, void* ws, size_t ws_bytes,
+                             hipStream_t stream);
+
+/* Top-k groups per segment by sum: descending sum, ascending key among equal
+ * sums (k <= 16).  gkey/gsum/gseg_off as produced by kpa_reduce_by_key.
+ * out_key/out_sum: device, n_seg*k entries (segment s at s*k); out_n: device,
+ * n_seg u32, the number written (min(k, groups of s)).  g_cap: host upper
+ * bound on the total number of groups. */
+kpa_status kpa_topk_by_sum_workspace_size(uint64_t g_cap, uint32_t n_seg, size_t* bytes);
+kpa_status kpa_topk_by_sum(const uint64_t* gkey, const uint64_t* gsum, const uint64_t* gseg_off,
+                           uint32_t n_seg, uint64_t g_cap, uint32_t k, uint64_t* out_key,
+                           uint64_t* out_sum, uint32_t* out_n, void* ws, size_t ws_bytes,
+                           hipStream_t stream);
+
+/* Median per key (Sec. 6 "Windowed Median Per Key"; percentile by key via sort
+ * and reduction, Sec. 4.2): for each group (as in kpa_reduce_by_key) the lower
+ * median of its values, v[(c-1)/2] of the ascending values.  Outputs: out_gkey,
+ * out_med (device, capacity n_cap), out_gseg_off (device, n_seg+1). */
+kpa_status kpa_median_by_key_workspace_size(uint64_t n_cap, uint32_t n_seg, size_t* bytes);
+kpa_status kpa_median_by_key(const uint64_t* keys, const uint32_t* rids, const uint64_t* seg_off,
+                             uint32_t n_seg, uint64_t n_cap, const void* rows,
+                             const kpa_row_layout* layout, uint64_t* out_gkey, uint64_t* out_med,
+                             uint64_t* out_gseg_off, void* ws, size_t ws_bytes,
+                             hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Join (Table 2: two sorted KPAs, one pass; Sec. 4.2 "Temporal Join").  For
+ * each segment s (a window), over all pairs (l, r) of L's segment s and R's
+ * segment s with equal keys: out_count[s] = number of pairs, out_sumprod[s] =
+ * sum of val(l)*val(r) mod 2^64.  Both KPAs sorted by key within segments;
+ * l_seg_off/r_seg_off: device, n_seg+1 each.  rows_l/rows_r: the two arenas
+ * (same layout).  out_count/out_sumprod: device, n_seg u64 each.  If out_pairs
+ * (device, pairs_cap triples of u64 {key, ridL, ridR}) is not NULL, the pairs
+ * are written in (segment, key, ridL, ridR) order up to pairs_cap of them;
+ * *out_npairs (device u64, may be NULL) receives the total number of pairs of
+ * all segments, so a caller sees that the capacity was too small when
+ * *out_npairs > pairs_cap.
+ */
+kpa_status kpa_join_workspace_size(uint64_t nl_cap, uint64_t nr_cap, uint32_t n_seg,
+                                   size_t* bytes);
+kpa_status kpa_join(const uint64_t* lk, const uint32_t* lr, const uint64_t* l_seg_off,
+                    uint64_t nl_cap, const uint64_t* rk, const uint32_t* rr,
+                    const uint64_t* r_seg_off, uint64_t nr_cap, uint32_t n_seg,
+                    const void* rows_l, const void* rows_r, const kpa_row_layout* layout,
+                    uint64_t* out_count, uint64_t* out_sumprod, uint64_t* out_pairs,
+                    uint64_t pairs_cap, uint64_t* out_npairs, void* ws, size_t ws_bytes,
+                    hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Materialize (Table 2: KPA -> bundle, random access): out_rows[i] =
+ * rows[rids[i]] (row_bytes each).  All device. */
+kpa_status kpa_materialize(const uint32_t* rids, uint64_t n, const void* rows, uint32_t row_bytes,
+                           void* out_rows, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * CDF models for the learned-splitter sort.
+ *
+ * kpa_pwl_fit: for each segment of a sorted KPA, kmin/kmax = first/last key and
+ * knots[j] = (number of keys < kmin + floor(j*(kmax-kmin)/n_seg_model)) / n,
+ * rounded once to float.  Empty segments get n_seg = 0.  out_models: device,
+ * n_seg entries.
+ */
+kpa_status kpa_pwl_fit(const uint64_t* sorted_keys, const uint64_t* seg_off, uint32_t n_seg,
+                       uint32_t n_seg_model, kpa_pwl_model* out_models, hipStream_t stream);
+
+/* Monotone CDF network 1 -> 32 -> 32 -> 1 (nonnegative weights, ramp
+ * activation r(z) = min(max(z,0),1)); parameters as 1153 floats
+ * [W1(32), b1(32), W2(32x32 row-major, W2[o][i]), b2(32), W3(32), b3].
+ * kpa_mlp_training_set: S training pairs from a sorted KPA of n keys: sample
+ * s takes index i = floor(s*n/S); x = (key_i - kmin)/(kmax - kmin) in float
+ * (0 when kmax == kmin), y = i/n.  Writes x, y (device, S floats) and the
+ * model range into out_model->kmin/kmax. */
+#define KPA_MLP_PARAMS 1153
+kpa_status kpa_mlp_training_set(const uint64_t* sorted_keys, uint64_t n, uint32_t S, float* x,
+                                float* y, kpa_pwl_model* out_model, hipStream_t stream);
+kpa_status kpa_mlp_forward(const float* params, const float* x, uint32_t m, float* out_f,
+                           hipStream_t stream);
+/* Mean squared error and its gradient over m samples (deterministic). */
+kpa_status kpa_mlp_loss_grad_workspace_size(uint32_t m, size_t* bytes);
+kpa_status kpa_mlp_loss_grad(const float* params, const float* x, const float* y, uint32_t m,
+                             float* out_loss, float* out_grad, void* ws, size_t ws_bytes,
+                             hipStream_t stream);
+/* One Adam step (step number t >= 1), then weights projected onto >= 0. */
+kpa_status kpa_mlp_adam_step(float* params, const float* grad, float* adam_m, float* adam_v,
+                             uint32_t t, float lr, float beta1, float beta2, float eps,
+                             hipStream_t stream);
+/* `steps` full-batch Adam steps starting at step t0 (loss of the last step in
+ * *out_loss, device float, may be NULL). */
+kpa_status kpa_mlp_train(float* params, float* adam_m, float* adam_v, const float* x,
+                         const float* y, uint32_t m, uint32_t t0, uint32_t steps, float lr,
+                         float* out_loss, void* ws, size_t ws_bytes, hipStream_t stream);
+/* Distill the network into model->knots: F_j = running max of clamp(f(j/n_seg),
+ * 0, 1), j = 0..n_seg; kmin/kmax are kept from kpa_mlp_training_set. */
+kpa_status kpa_mlp_to_pwl(const float* params, uint32_t n_seg_model, kpa_pwl_model* model,
+                          hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KPA_H_ */

@@ -1,0 +1,210 @@
+// Extract fused with windowing (Sec. 4.2 "Windowing": Partition on the
+// timestamp column, the window length being the range of each partition).
+//
+// Two passes over the rows:
+//   1. histogram of window ids (plus out-of-range rows) into global counters;
+//   2. a single onesweep scatter pass with digit = window id, which reads the
+//      key and timestamp of each row and writes (key, rid) into its window.
+// The scatter is stable, so each window lists its rows in arrival order.
+#include "onesweep.hpp"
+
+namespace kpa {
+
+constexpr u32 PART_HIST_ROWS = 1u << 16;  // rows per histogram workgroup
+
+struct WinParams {
+  u64 origin;
+  u64 win_len;
+  u64 limit;  // n_win * win_len (exclusive end of the last window, relative)
+  double inv; // 1 / win_len
+  u32 n_win;
+  u32 fast;   // (n_win + 1) * win_len fits in 64 bits: quotient by estimate + correction
+};
+
+// Window of a timestamp, exactly as the integer quotient (ts - origin) / win_len.
+__device__ __forceinline__ bool window_of(u64 ts, const WinParams& p, u32& w) {
+  if (ts < p.origin) return false;
+  const u64 x = ts - p.origin;
+  if (p.fast) {
+    if (x >= p.limit) return false;
+    // The double-precision estimate is within one of the true quotient (which
+    // is below 256); fix it with exact integer products.
+    u64 q = (u64)((double)x * p.inv);
+    if (q * p.win_len > x) --q;
+    else if ((q + 1) * p.win_len <= x) ++q;
+    w = (u32)q;
+    return true;
+  }
+  const u64 q = x / p.win_len;
+  if (q >= p.n_win) return false;
+  w = (u32)q;
+  return true;
+}
+
+__device__ __forceinline__ u64 load_ts(const unsigned char* row, u32 ts_off, u32 ts_w) {
+  return ts_w == 8 ? *reinterpret_cast<const u64*>(row + ts_off)
+                   : (u64)*reinterpret_cast<const u32*>(row + ts_off);
+}
+
+__global__ void __launch_bounds__(BLOCK) k_part_hist(const unsigned char* __restrict__ rows,
+                                                     u64 n, u32 row_bytes, u32 ts_off, u32 ts_w,
+                                                     WinParams wp, u32* __restrict__ counts) {
+  __shared__ u32 h[RADIX + 1];
+  const u32 tid = threadIdx.x;
+  h[tid] = 0;
+  if (tid == 0) h[RADIX] = 0;
+  __syncthreads();
+  const u64 r0 = (u64)blockIdx.x * PART_HIST_ROWS;
+  const u64 r1 = min(n, r0 + PART_HIST_ROWS);
+  for (u64 i = r0 + tid; i < r1; i += BLOCK) {
+    u32 w;
+    if (window_of(load_ts(rows + i * row_bytes, ts_off, ts_w), wp, w))
+      atomicAdd(&h[w], 1u);
+    else
+      atomicAdd(&h[RADIX], 1u);
+  }
+  __syncthreads();
+  if (tid < wp.n_win && h[tid]) atomicAdd(&counts[tid], h[tid]);
+  if (tid == 0 && h[RADIX]) atomicAdd(&counts[RADIX], h[RADIX]);
+}
+
+// counts -> exclusive window offsets (u32 for the scatter, u64 for the caller).
+__global__ void __launch_bounds__(BLOCK) k_part_scan(u32* __restrict__ counts, u32 n_win,
+                                                     u64* __restrict__ win_off,
+                                                     u64* __restrict__ oob) {
+  __shared__ u32 sc[WAVES + 1];
+  const u32 tid = threadIdx.x;
+  const u32 c = tid < n_win ? counts[tid] : 0u;
+  u32 tot;
+  const u32 ex = block_excl_sum(c, sc, &tot);
+  counts[tid] = ex;
+  if (tid < n_win) win_off[tid] = ex;
+  if (tid == 0) {
+    win_off[n_win] = tot;
+    *oob = counts[RADIX];
+  }
+}
+
+__global__ void __launch_bounds__(BLOCK) k_part_pass(const unsigned char* __restrict__ rows,
+                                                     u64 n, u32 row_bytes, u32 key_off,
+                                                     u32 ts_off, u32 ts_w, WinParams wp,
+                                                     u32 rid_base, const u32* __restrict__ woff,
+                                                     u32 n_tiles, u32* __restrict__ status,
+                                                     u32* __restrict__ counter,
+                                                     u64* __restrict__ keys_out,
+                                                     u32* __restrict__ rids_out) {
+  __shared__ OnesweepSmem sm;
+  const u32 tid = threadIdx.x;
+  if (tid == 0) sm.tile = atomicAdd(counter, 1u);
+  __syncthreads();
+  const u32 tile = sm.tile;
+  if (tile >= n_tiles) return;
+  const u64 base = (u64)tile * TILE;
+  u64 kk[ITEMS];
+  u32 rr[ITEMS], dd[ITEMS];
+  u32 valid = 0;
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    const u64 e = base + tile_offset(j);
+    kk[j] = 0;
+    dd[j] = 0;
+    rr[j] = rid_base + (u32)e;
+    if (e < n) {
+      const unsigned char* row = rows + e * row_bytes;
+      u32 w;
+      if (window_of(load_ts(row, ts_off, ts_w), wp, w)) {
+        kk[j] = *reinterpret_cast<const u64*>(row + key_off);
+        dd[j] = w;
+        valid |= 1u << j;
+      }
+    }
+  }
+  const u64 my_base = tid < wp.n_win ? (u64)woff[tid] : 0ull;
+  onesweep_tile(sm, kk, rr, dd, valid, status, tile, tile == 0, my_base, keys_out, rids_out);
+}
+
+struct PartWs {
+  u32* counts;  // RADIX + 1
+  u32* counter;
+  u32* status;
+  u64 n_tiles;
+};
+
+static void part_plan(u64 n, Carver& c, PartWs* w) {
+  w->n_tiles = ceil_div(n ? n : 1, TILE);
+  w->counts = c.take<u32>(RADIX + 1);
+  w->counter = c.take<u32>(1);
+  w->status = c.take<u32>(w->n_tiles * RADIX);
+}
+
+}  // namespace kpa
+
+using namespace kpa;
+
+extern "C" {
+
+kpa_status kpa_partition_windows_workspace_size(uint64_t n, uint32_t n_win, size_t* bytes) {
+  clear_error();
+  KPA_REQUIRE(bytes != nullptr, KPA_EINVAL, "bytes is null");
+  (void)n_win;
+  Carver c(nullptr);
+  PartWs w;
+  part_plan(n, c, &w);
+  *bytes = c.used + 256;
+  return KPA_OK;
+}
+
+kpa_status kpa_partition_windows(const void* rows, uint64_t n, const kpa_row_layout* layout,
+                                 uint64_t win_len, uint64_t win_origin, uint32_t n_win,
+                                 uint32_t rid_base, uint64_t* out_keys, uint32_t* out_rids,
+                                 uint64_t* out_win_off, uint64_t* out_oob, void* ws,
+                                 size_t ws_bytes, hipStream_t stream) {
+  clear_error();
+  KPA_CHECK(check_layout(layout, false, true));
+  KPA_REQUIRE(n_win >= 1 && n_win <= RADIX, KPA_EUNSUPPORTED, "n_win must be in [1, 256]");
+  KPA_REQUIRE(win_len >= 1, KPA_EINVAL, "win_len must be >= 1");
+  KPA_REQUIRE(out_win_off && out_oob && ws, KPA_EINVAL, "null pointer");
+  KPA_REQUIRE(n < MAX_SEG_ENTRIES, KPA_EUNSUPPORTED, "n must be below 2^30");
+  KPA_REQUIRE(n + rid_base <= (1ull << 32), KPA_EUNSUPPORTED, "rids exceed 32 bits");
+  KPA_REQUIRE(n == 0 || (rows && out_keys && out_rids), KPA_EINVAL, "null pointer");
+  KPA_REQUIRE(aligned(ws, 256) && aligned(out_win_off, 8) && aligned(out_oob, 8) &&
+                  (n == 0 || (aligned(rows, 16) && aligned(out_keys, 8) && aligned(out_rids, 4))),
+              KPA_EINVAL, "misaligned pointer");
+  Carver c(ws);
+  PartWs w;
+  part_plan(n, c, &w);
+  KPA_REQUIRE(c.used <= ws_bytes, KPA_EWORKSPACE, "workspace too small: need %zu bytes", c.used);
+
+  WinParams wp;
+  wp.origin = win_origin;
+  wp.win_len = win_len;
+  wp.n_win = n_win;
+  unsigned __int128 lim = (unsigned __int128)win_len * (n_win + 1);
+  wp.fast = lim < ((unsigned __int128)1 << 64) ? 1u : 0u;
+  wp.limit = wp.fast ? win_len * n_win : ~0ull;
+  wp.inv = 1.0 / (double)win_len;
+
+  KPA_CHECK(launch_fill_u32(w.counts, RADIX + 1, 0, stream));
+  KPA_CHECK(launch_fill_u32(w.counter, 1, 0, stream));
+  KPA_CHECK(launch_fill_u32(w.status, w.n_tiles * RADIX, 0, stream));
+  const auto* r = static_cast<const unsigned char*>(rows);
+  if (n) {
+    hipLaunchKernelGGL(k_part_hist, dim3((u32)ceil_div(n, PART_HIST_ROWS)), dim3(BLOCK), 0,
+                       stream, r, n, layout->row_bytes, layout->ts_off, layout->ts_w, wp,
+                       w.counts);
+    KPA_LAUNCHED();
+  }
+  hipLaunchKernelGGL(k_part_scan, dim3(1), dim3(BLOCK), 0, stream, w.counts, n_win, out_win_off,
+                     out_oob);
+  KPA_LAUNCHED();
+  if (n) {
+    hipLaunchKernelGGL(k_part_pass, dim3((u32)w.n_tiles), dim3(BLOCK), 0, stream, r, n,
+                       layout->row_bytes, layout->key_off, layout->ts_off, layout->ts_w, wp,
+                       rid_base, w.counts, (u32)w.n_tiles, w.status, w.counter, out_keys,
+                       out_rids);
+    KPA_LAUNCHED();
+  }
+  return KPA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,557 @@
+// Keyed reduction (Table 2; Sec. 4.1: scan a sorted KPA, follow the pointers
+// and coalesce a nonresident column over each contiguous run of equal keys)
+// and top-k groups by sum.
+//
+// Reduction in three launches over 4096-entry tiles of every segment:
+//   1. summary: per tile, the number of runs that start in it and the
+//      aggregate of its last run (values gathered only for that run);
+//   2. scan (one workgroup): groups started before each tile, and the open run
+//      entering each tile (a segmented scan of the tile summaries);
+//   3. main: per tile, gather values, segmented scan in registers/LDS with the
+//      carried run prepended, and write every run at its last entry.
+// Integer addition is associative modulo 2^64, so the result does not depend on
+// how the work is split.
+#include "reduce_internal.hpp"
+
+namespace kpa {
+
+constexpr u32 GT = 4096;  // groups per top-k tile
+constexpr int TOPK_MAX = 16;
+
+__device__ __forceinline__ SegAgg shfl_up_agg(const SegAgg& a, int o) {
+  SegAgg r;
+  r.f = __shfl_up(a.f, o, 64);
+  r.c = __shfl_up(a.c, o, 64);
+  r.s = __shfl_up(a.s, o, 64);
+  r.m = __shfl_up(a.m, o, 64);
+  r.hp = __shfl_up(a.hp, o, 64);
+  return r;
+}
+
+// Exclusive segmented scan over the block, with `carry_in` before thread 0.
+template <int NW>
+__device__ __forceinline__ SegAgg block_excl_segscan(SegAgg v, const SegAgg& carry_in,
+                                                     SegAgg* sm) {
+  const u32 lane = __lane_id(), w = threadIdx.x >> 6;
+  SegAgg incl = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    SegAgg t = shfl_up_agg(incl, o);
+    if (lane >= (u32)o) incl = seg_combine(t, incl);
+  }
+  SegAgg ex = shfl_up_agg(incl, 1);
+  if (lane == 0) ex = seg_identity();
+  if (lane == 63) sm[w] = incl;
+  __syncthreads();
+  SegAgg pre = carry_in;
+  for (u32 i = 0; i < w; ++i) pre = seg_combine(pre, sm[i]);
+  __syncthreads();
+  return seg_combine(pre, ex);
+}
+
+__device__ __forceinline__ u64 block_sum_u64(u64 v, u64* sm) {
+  v = wave_sum(v);
+  const u32 w = threadIdx.x >> 6;
+  if (__lane_id() == 0) sm[w] = v;
+  __syncthreads();
+  u64 r = 0;
+  for (int i = 0; i < WAVES; ++i) r += sm[i];
+  __syncthreads();
+  return r;
+}
+__device__ __forceinline__ u64 block_max_u64(u64 v, u64* sm) {
+  v = wave_max(v);
+  const u32 w = threadIdx.x >> 6;
+  if (__lane_id() == 0) sm[w] = v;
+  __syncthreads();
+  u64 r = 0;
+  for (int i = 0; i < WAVES; ++i) r = sm[i] > r ? sm[i] : r;
+  __syncthreads();
+  return r;
+}
+
+struct TileRange {
+  u32 seg;
+  u64 a, b, base;
+  u32 cnt;
+};
+
+__device__ __forceinline__ TileRange tile_range(const u64* seg_off, const u32* tile_start,
+                                                u32 n_seg, u32 tile, u32 tsize) {
+  TileRange r;
+  r.seg = find_seg(tile_start, n_seg, tile);
+  r.a = seg_off[r.seg];
+  r.b = seg_off[r.seg + 1];
+  r.base = r.a + (u64)(tile - tile_start[r.seg]) * tsize;
+  r.cnt = r.base < r.b ? (u32)min<u64>(tsize, r.b - r.base) : 0u;
+  return r;
+}
+
+struct ValSrc {
+  const unsigned char* rows;
+  u32 row_bytes, val_off, val_w, on;
+  __device__ __forceinline__ u64 operator()(u32 rid) const {
+    return on ? load_val(rows, rid, row_bytes, val_off, val_w) : 0ull;
+  }
+};
+
+__global__ void __launch_bounds__(BLOCK) k_reduce_summary(const u64* __restrict__ keys,
+                                                          const u32* __restrict__ rids,
+                                                          const u64* __restrict__ seg_off,
+                                                          const u32* __restrict__ tile_start,
+                                                          u32 n_seg, ValSrc vs,
+                                                          TileSummary* __restrict__ summary) {
+  __shared__ u64 sk[TILE];
+  __shared__ u64 red[WAVES];
+  const u32 tile = blockIdx.x;
+  if (tile >= tile_start[n_seg]) return;
+  const TileRange tr = tile_range(seg_off, tile_start, n_seg, tile, TILE);
+  const u32 tid = threadIdx.x;
+  for (u32 i = tid; i < tr.cnt; i += BLOCK) sk[i] = keys[tr.base + i];
+  const bool has_prev = tr.base > tr.a;
+  const u64 prev = has_prev ? keys[tr.base - 1] : 0ull;
+  __syncthreads();
+  u32 nh = 0;
+  int last = -1;
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    const u32 idx = tid * ITEMS + j;
+    if (idx < tr.cnt) {
+      const bool h = idx == 0 ? (!has_prev || sk[0] != prev) : (sk[idx] != sk[idx - 1]);
+      if (h) {
+        ++nh;
+        last = (int)idx;
+      }
+    }
+  }
+  const u64 heads = block_sum_u64(nh, red);
+  const u64 lastp1 = block_max_u64((u64)(last + 1), red);  // 0: no head in the tile
+  const u32 start = lastp1 ? (u32)(lastp1 - 1) : 0u;
+  u64 s = 0, m = 0;
+  if (vs.on) {
+    for (u32 i = start + tid; i < tr.cnt; i += BLOCK) {
+      const u64 v = vs(rids[tr.base + i]);
+      s += v;
+      m = v > m ? v : m;
+    }
+  }
+  s = block_sum_u64(s, red);
+  m = block_max_u64(m, red);
+  if (tid == 0) {
+    TileSummary t;
+    t.heads = (u32)heads;
+    t.pad = 0;
+    t.trail = SegAgg{lastp1 ? 1u : 0u, (u64)(tr.cnt - start), s, m, tr.base + start};
+    summary[tile] = t;
+  }
+}
+
+__global__ void __launch_bounds__(1024) k_reduce_scan(const TileSummary* __restrict__ summ,
+                                                      const u32* __restrict__ tile_start,
+                                                      u32 n_seg, u64* __restrict__ gbase,
+                                                      SegAgg* __restrict__ carry,
+                                                      u64* __restrict__ gseg_off) {
+  __shared__ SegAgg wa[16];
+  __shared__ u64 wh[17];
+  const u32 tid = threadIdx.x, lane = __lane_id(), w = tid >> 6;
+  const u32 n_tiles = tile_start[n_seg];
+  const u32 per = (n_tiles + 1023) / 1024;
+  const u32 t0 = min(n_tiles, tid * per), t1 = min(n_tiles, t0 + per);
+  u64 H = 0;
+  SegAgg A = seg_identity();
+  for (u32 t = t0; t < t1; ++t) {
+    H += summ[t].heads;
+    A = seg_combine(A, summ[t].trail);
+  }
+  // exclusive scans over 1024 threads
+  u64 hi = H;
+  SegAgg ai = A;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    u64 th = __shfl_up(hi, o, 64);
+    SegAgg ta = shfl_up_agg(ai, o);
+    if (lane >= (u32)o) {
+      hi += th;
+      ai = seg_combine(ta, ai);
+    }
+  }
+  u64 hx = __shfl_up(hi, 1, 64);
+  SegAgg ax = shfl_up_agg(ai, 1);
+  if (lane == 0) {
+    hx = 0;
+    ax = seg_identity();
+  }
+  if (lane == 63) {
+    wh[w] = hi;
+    wa[w] = ai;
+  }
+  __syncthreads();
+  u64 hp = 0;
+  SegAgg ap = seg_identity();
+  for (u32 i = 0; i < w; ++i) {
+    hp += wh[i];
+    ap = seg_combine(ap, wa[i]);
+  }
+  u64 h = hp + hx;
+  SegAgg c = seg_combine(ap, ax);
+  for (u32 t = t0; t < t1; ++t) {
+    gbase[t] = h;
+    carry[t] = c;
+    h += summ[t].heads;
+    c = seg_combine(c, summ[t].trail);
+  }
+  if (tid == 1023) wh[16] = h;  // total: the last thread's running count
+  __syncthreads();
+  for (u32 s = tid; s < n_seg; s += 1024) gseg_off[s] = gbase[tile_start[s]];
+  if (tid == 0) gseg_off[n_seg] = wh[16];
+}
+
+__global__ void __launch_bounds__(BLOCK) k_reduce_main(
+    const u64* __restrict__ keys, const u32* __restrict__ rids, const u64* __restrict__ seg_off,
+    const u32* __restrict__ tile_start, u32 n_seg, ValSrc vs, const u64* __restrict__ gbase,
+    const SegAgg* __restrict__ carry, u64* __restrict__ o_key, u64* __restrict__ o_cnt,
+    u64* __restrict__ o_sum, u64* __restrict__ o_max, u64* __restrict__ o_start) {
+  __shared__ u64 sk[TILE];
+  __shared__ u32 sr[TILE];
+  __shared__ SegAgg wsm[WAVES];
+  __shared__ u32 hsm[WAVES + 1];
+  const u32 tile = blockIdx.x;
+  if (tile >= tile_start[n_seg]) return;
+  const TileRange tr = tile_range(seg_off, tile_start, n_seg, tile, TILE);
+  const u32 tid = threadIdx.x;
+  for (u32 i = tid; i < tr.cnt; i += BLOCK) {
+    sk[i] = keys[tr.base + i];
+    sr[i] = rids[tr.base + i];
+  }
+  const bool has_prev = tr.base > tr.a;
+  const u64 prev = has_prev ? keys[tr.base - 1] : 0ull;
+  const bool has_next = tr.base + tr.cnt < tr.b;
+  const u64 next = has_next ? keys[tr.base + tr.cnt] : 0ull;
+  __syncthreads();
+
+  u64 v[ITEMS];
+  u32 hmask = 0, tmask = 0;
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    const u32 idx = tid * ITEMS + j;
+    v[j] = 0;
+    if (idx < tr.cnt) v[j] = vs(sr[idx]);
+  }
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    const u32 idx = tid * ITEMS + j;
+    if (idx < tr.cnt) {
+      const u64 k = sk[idx];
+      const bool h = idx == 0 ? (!has_prev || k != prev) : (k != sk[idx - 1]);
+      const bool t = idx + 1 == tr.cnt ? (!has_next || k != next) : (k != sk[idx + 1]);
+      hmask |= (u32)h << j;
+      tmask |= (u32)t << j;
+    }
+  }
+  SegAgg A = seg_identity();
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    const u32 idx = tid * ITEMS + j;
+    if (idx < tr.cnt) {
+      const SegAgg e{(hmask >> j) & 1u, 1ull, v[j], v[j], tr.base + idx};
+      A = seg_combine(A, e);
+    }
+  }
+  u32 htot;
+  const u32 hex = block_excl_sum((u32)__popc(hmask), hsm, &htot);
+  SegAgg run = block_excl_segscan<WAVES>(A, carry[tile], wsm);
+  const u64 gb = gbase[tile];
+  u32 hs = hex;
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    const u32 idx = tid * ITEMS + j;
+    if (idx < tr.cnt) {
+      const u32 h = (hmask >> j) & 1u;
+      const SegAgg e{h, 1ull, v[j], v[j], tr.base + idx};
+      run = seg_combine(run, e);
+      hs += h;
+      if ((tmask >> j) & 1u) {
+        const u64 gi = gb + hs - 1;
+        o_key[gi] = sk[idx];
+        if (o_cnt) o_cnt[gi] = run.c;
+        if (o_sum) o_sum[gi] = run.s;
+        if (o_max) o_max[gi] = run.m;
+        if (o_start) o_start[gi] = run.hp;
+      }
+    }
+  }
+}
+
+void reduce_plan(u64 n_cap, u32 n_seg, Carver& c, ReduceWs* w) {
+  w->max_tiles = max_tiles(n_cap, n_seg, TILE);
+  w->tile_start = c.take<u32>((u64)n_seg + 1);
+  w->summary = c.take<TileSummary>(w->max_tiles);
+  w->gbase = c.take<u64>(w->max_tiles);
+  w->carry = c.take<SegAgg>(w->max_tiles);
+}
+
+kpa_status reduce_launch(const u64* keys, const u32* rids, const u64* seg_off, u32 n_seg,
+                         const unsigned char* rows, const kpa_row_layout* L, bool need_val,
+                         const ReduceOut& o, const ReduceWs& w, hipStream_t st) {
+  ValSrc vs;
+  vs.rows = rows;
+  vs.row_bytes = L ? L->row_bytes : 0;
+  vs.val_off = L ? L->val_off : 0;
+  vs.val_w = L ? L->val_w : 8;
+  vs.on = need_val ? 1u : 0u;
+  KPA_CHECK(launch_seg_tiles(seg_off, nullptr, n_seg, TILE, w.tile_start, st));
+  hipLaunchKernelGGL(k_reduce_summary, dim3((u32)w.max_tiles), dim3(BLOCK), 0, st, keys, rids,
+                     seg_off, w.tile_start, n_seg, vs, w.summary);
+  KPA_LAUNCHED();
+  hipLaunchKernelGGL(k_reduce_scan, dim3(1), dim3(1024), 0, st, w.summary, w.tile_start, n_seg,
+                     w.gbase, w.carry, o.gseg_off);
+  KPA_LAUNCHED();
+  hipLaunchKernelGGL(k_reduce_main, dim3((u32)w.max_tiles), dim3(BLOCK), 0, st, keys, rids,
+                     seg_off, w.tile_start, n_seg, vs, w.gbase, w.carry, o.gkey, o.cnt, o.sum,
+                     o.max, o.gstart);
+  KPA_LAUNCHED();
+  return KPA_OK;
+}
+
+// ------------------------------------------------------------------ top-k --
+
+// (sum desc, key asc) is a total order on groups of one segment.
+__device__ __forceinline__ bool better(u64 sa, u64 ka, u64 sb, u64 kb) {
+  return sa > sb || (sa == sb && ka < kb);
+}
+
+struct TopList {
+  u64 s[TOPK_MAX], k[TOPK_MAX];
+  u32 n;
+  __device__ __forceinline__ void init() { n = 0; }
+  // Keeps the best TOPK_MAX entries seen (a superset of the best k <= TOPK_MAX).
+  __device__ __forceinline__ void insert(u64 xs, u64 xk) {
+    if (n == TOPK_MAX && !better(xs, xk, s[TOPK_MAX - 1], k[TOPK_MAX - 1])) return;
+#pragma unroll
+    for (int j = 0; j < TOPK_MAX; ++j) {
+      if ((u32)j < n) {
+        if (better(xs, xk, s[j], k[j])) {
+          u64 ts = s[j], tk = k[j];
+          s[j] = xs;
+          k[j] = xk;
+          xs = ts;
+          xk = tk;
+        }
+      } else if ((u32)j == n) {
+        s[j] = xs;
+        k[j] = xk;
+      }
+    }
+    if (n < TOPK_MAX) ++n;
+  }
+  __device__ __forceinline__ void pop() {
+#pragma unroll
+    for (int j = 0; j + 1 < TOPK_MAX; ++j) {
+      s[j] = s[j + 1];
+      k[j] = k[j + 1];
+    }
+    --n;
+  }
+};
+
+// Block-wide: emit the best `cap` entries of all threads' lists in order.
+__device__ __forceinline__ u32 pop_merge(TopList& L, u32 cap, u64* out_s, u64* out_k, u64* sm_s,
+                                         u64* sm_k, u32* sm_t) {
+  const u32 tid = threadIdx.x, w = tid >> 6, lane = __lane_id();
+  u32 got = 0;
+  for (u32 r = 0; r < cap; ++r) {
+    u32 has = L.n > 0;
+    u64 bs = has ? L.s[0] : 0, bk = has ? L.k[0] : 0;
+    u32 bt = tid;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      u32 oh = __shfl_xor(has, o, 64);
+      u64 os = __shfl_xor(bs, o, 64), ok = __shfl_xor(bk, o, 64);
+      u32 ot = __shfl_xor(bt, o, 64);
+      bool take = oh && (!has || better(os, ok, bs, bk));
+      if (take) {
+        has = 1;
+        bs = os;
+        bk = ok;
+        bt = ot;
+      }
+    }
+    if (lane == 0) {
+      sm_s[w] = bs;
+      sm_k[w] = bk;
+      sm_t[w] = has ? bt : 0xFFFFFFFFu;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      u32 win = 0xFFFFFFFFu;
+      u64 ws = 0, wk = 0;
+      for (int i = 0; i < WAVES; ++i) {
+        if (sm_t[i] == 0xFFFFFFFFu) continue;
+        if (win == 0xFFFFFFFFu || better(sm_s[i], sm_k[i], ws, wk)) {
+          win = sm_t[i];
+          ws = sm_s[i];
+          wk = sm_k[i];
+        }
+      }
+      sm_t[WAVES] = win;
+      if (win != 0xFFFFFFFFu) {
+        out_s[r] = ws;
+        out_k[r] = wk;
+      }
+    }
+    __syncthreads();
+    const u32 win = sm_t[WAVES];
+    __syncthreads();
+    if (win == 0xFFFFFFFFu) break;
+    if (win == tid) L.pop();
+    ++got;
+  }
+  return got;
+}
+
+__global__ void __launch_bounds__(BLOCK) k_topk_local(const u64* __restrict__ gkey,
+                                                      const u64* __restrict__ gsum,
+                                                      const u64* __restrict__ gseg_off,
+                                                      const u32* __restrict__ tile_start,
+                                                      u32 n_seg, u32 k, u64* __restrict__ cs,
+                                                      u64* __restrict__ ck,
+                                                      u32* __restrict__ cn) {
+  __shared__ u64 ss[WAVES], sk2[WAVES];
+  __shared__ u32 st[WAVES + 1];
+  __shared__ u64 os[TOPK_MAX], ok[TOPK_MAX];
+  const u32 tile = blockIdx.x;
+  if (tile >= tile_start[n_seg]) return;
+  const TileRange tr = tile_range(gseg_off, tile_start, n_seg, tile, GT);
+  TopList L;
+  L.init();
+  for (u32 i = threadIdx.x; i < tr.cnt; i += BLOCK) L.insert(gsum[tr.base + i], gkey[tr.base + i]);
+  const u32 got = pop_merge(L, k, os, ok, ss, sk2, st);
+  if (threadIdx.x < got) {
+    cs[(u64)tile * TOPK_MAX + threadIdx.x] = os[threadIdx.x];
+    ck[(u64)tile * TOPK_MAX + threadIdx.x] = ok[threadIdx.x];
+  }
+  if (threadIdx.x == 0) cn[tile] = got;
+}
+
+__global__ void __launch_bounds__(BLOCK) k_topk_final(const u64* __restrict__ cs,
+                                                      const u64* __restrict__ ck,
+                                                      const u32* __restrict__ cn,
+                                                      const u32* __restrict__ tile_start, u32 k,
+                                                      u64* __restrict__ out_key,
+                                                      u64* __restrict__ out_sum,
+                                                      u32* __restrict__ out_n) {
+  __shared__ u64 ss[WAVES], sk2[WAVES];
+  __shared__ u32 st[WAVES + 1];
+  __shared__ u64 os[TOPK_MAX], ok[TOPK_MAX];
+  const u32 s = blockIdx.x;
+  const u32 t0 = tile_start[s], t1 = tile_start[s + 1];
+  TopList L;
+  L.init();
+  const u64 total = (u64)(t1 - t0) * TOPK_MAX;
+  for (u64 i = threadIdx.x; i < total; i += BLOCK) {
+    const u32 t = t0 + (u32)(i / TOPK_MAX);
+    const u32 r = (u32)(i % TOPK_MAX);
+    if (r < cn[t]) L.insert(cs[(u64)t * TOPK_MAX + r], ck[(u64)t * TOPK_MAX + r]);
+  }
+  const u32 got = pop_merge(L, k, os, ok, ss, sk2, st);
+  if (threadIdx.x < got) {
+    out_key[(u64)s * k + threadIdx.x] = ok[threadIdx.x];
+    out_sum[(u64)s * k + threadIdx.x] = os[threadIdx.x];
+  }
+  if (threadIdx.x == 0) out_n[s] = got;
+}
+
+struct TopkWs {
+  u32* tile_start;
+  u64* cs;
+  u64* ck;
+  u32* cn;
+  u64 max_tiles;
+};
+
+static void topk_plan(u64 g_cap, u32 n_seg, Carver& c, TopkWs* w) {
+  w->max_tiles = max_tiles(g_cap, n_seg, GT);
+  w->tile_start = c.take<u32>((u64)n_seg + 1);
+  w->cs = c.take<u64>(w->max_tiles * TOPK_MAX);
+  w->ck = c.take<u64>(w->max_tiles * TOPK_MAX);
+  w->cn = c.take<u32>(w->max_tiles);
+}
+
+}  // namespace kpa
+
+using namespace kpa;
+
+extern "C" {
+
+kpa_status kpa_reduce_by_key_workspace_size(uint64_t n_cap, uint32_t n_seg, size_t* bytes) {
+  clear_error();
+  KPA_REQUIRE(bytes, KPA_EINVAL, "bytes is null");
+  Carver c(nullptr);
+  ReduceWs w;
+  reduce_plan(n_cap, n_seg ? n_seg : 1, c, &w);
+  *bytes = c.used + 256;
+  return KPA_OK;
+}
+
+kpa_status kpa_reduce_by_key(const uint64_t* keys, const uint32_t* rids, const uint64_t* seg_off,
+                             uint32_t n_seg, uint64_t n_cap, const void* rows,
+                             const kpa_row_layout* layout, uint64_t* out_gkey, uint64_t* out_cnt,
+                             uint64_t* out_sum, uint64_t* out_max, uint64_t* out_gstart,
+                             uint64_t* out_gseg_off, void* ws, size_t ws_bytes,
+                             hipStream_t stream) {
+  clear_error();
+  const bool need_val = out_sum || out_max;
+  if (need_val) KPA_CHECK(check_layout(layout, true, false));
+  if (n_seg == 0) return KPA_OK;
+  KPA_REQUIRE(keys && rids && seg_off && out_gkey && out_gseg_off && ws, KPA_EINVAL,
+              "null pointer");
+  KPA_REQUIRE(!need_val || rows, KPA_EINVAL, "rows needed for sum/max");
+  KPA_REQUIRE(aligned(keys, 8) && aligned(rids, 4) && aligned(seg_off, 8) &&
+                  aligned(out_gkey, 8) && aligned(out_gseg_off, 8) && aligned(ws, 256) &&
+                  (!rows || aligned(rows, 16)),
+              KPA_EINVAL, "misaligned pointer");
+  KPA_REQUIRE(n_cap < (1ull << 32), KPA_EUNSUPPORTED, "n_cap must be below 2^32");
+  Carver c(ws);
+  ReduceWs w;
+  reduce_plan(n_cap, n_seg, c, &w);
+  KPA_REQUIRE(c.used <= ws_bytes, KPA_EWORKSPACE, "workspace too small: need %zu bytes", c.used);
+  ReduceOut o{out_gkey, out_cnt, out_sum, out_max, out_gstart, out_gseg_off};
+  return reduce_launch(keys, rids, seg_off, n_seg, static_cast<const unsigned char*>(rows),
+                       layout, need_val, o, w, stream);
+}
+
+kpa_status kpa_topk_by_sum_workspace_size(uint64_t g_cap, uint32_t n_seg, size_t* bytes) {
+  clear_error();
+  KPA_REQUIRE(bytes, KPA_EINVAL, "bytes is null");
+  Carver c(nullptr);
+  TopkWs w;
+  topk_plan(g_cap, n_seg ? n_seg : 1, c, &w);
+  *bytes = c.used + 256;
+  return KPA_OK;
+}
+
+kpa_status kpa_topk_by_sum(const uint64_t* gkey, const uint64_t* gsum, const uint64_t* gseg_off,
+                           uint32_t n_seg, uint64_t g_cap, uint32_t k, uint64_t* out_key,
+                           uint64_t* out_sum, uint32_t* out_n, void* ws, size_t ws_bytes,
+                           hipStream_t stream) {
+  clear_error();
+  KPA_REQUIRE(k >= 1 && k <= TOPK_MAX, KPA_EUNSUPPORTED, "k must be in [1, 16]");
+  if (n_seg == 0) return KPA_OK;
+  KPA_REQUIRE(gkey && gsum && gseg_off && out_key && out_sum && out_n && ws, KPA_EINVAL,
+              "null pointer");
+  KPA_REQUIRE(aligned(ws, 256), KPA_EINVAL, "misaligned workspace");
+  Carver c(ws);
+  TopkWs w;
+  topk_plan(g_cap, n_seg, c, &w);
+  KPA_REQUIRE(c.used <= ws_bytes, KPA_EWORKSPACE, "workspace too small: need %zu bytes", c.used);
+  KPA_CHECK(launch_seg_tiles(gseg_off, nullptr, n_seg, GT, w.tile_start, stream));
+  hipLaunchKernelGGL(k_topk_local, dim3((u32)w.max_tiles), dim3(BLOCK), 0, stream, gkey, gsum,
+                     gseg_off, w.tile_start, n_seg, k, w.cs, w.ck, w.cn);
+  KPA_LAUNCHED();
+  hipLaunchKernelGGL(k_topk_final, dim3(n_seg), dim3(BLOCK), 0, stream, w.cs, w.ck, w.cn,
+                     w.tile_start, k, out_key, out_sum, out_n);
+  KPA_LAUNCHED();
+  return KPA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,50 @@
+// Keyed reduction internals shared by reduce, median and join.
+#pragma once
+
+#include "kpa_internal.hpp"
+
+namespace kpa {
+
+// Aggregate of a (partial) run of equal keys.  f: the run contains its head.
+struct SegAgg {
+  u32 f;
+  u64 c, s, m, hp;  // count, sum (mod 2^64), max, global index of the head
+};
+
+__device__ __forceinline__ SegAgg seg_identity() { return SegAgg{0u, 0ull, 0ull, 0ull, 0ull}; }
+
+// Segmented-scan operator: b continues a unless b starts a new run.
+__device__ __forceinline__ SegAgg seg_combine(const SegAgg& a, const SegAgg& b) {
+  if (b.f) return b;
+  return SegAgg{a.f, a.c + b.c, a.s + b.s, a.m > b.m ? a.m : b.m, a.hp};
+}
+
+struct TileSummary {
+  u32 heads;
+  u32 pad;
+  SegAgg trail;  // aggregate of the tile's last (possibly unfinished) run
+};
+
+struct ReduceWs {
+  u32* tile_start;
+  TileSummary* summary;
+  u64* gbase;    // groups started before each tile
+  SegAgg* carry; // open run entering each tile
+  u64 max_tiles;
+};
+
+struct ReduceOut {
+  u64* gkey;
+  u64* cnt;
+  u64* sum;
+  u64* max;
+  u64* gstart;
+  u64* gseg_off;
+};
+
+void reduce_plan(u64 n_cap, u32 n_seg, Carver& c, ReduceWs* w);
+kpa_status reduce_launch(const u64* keys, const u32* rids, const u64* seg_off, u32 n_seg,
+                         const unsigned char* rows, const kpa_row_layout* L, bool need_val,
+                         const ReduceOut& o, const ReduceWs& w, hipStream_t st);
+
+}  // namespace kpa

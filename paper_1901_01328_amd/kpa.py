@@ -1,0 +1,417 @@
+"""ctypes binding of libkpa.so: the C-ABI calls under the same names.
+
+Arguments are torch tensors on the current HIP device (PyTorch provides only
+device memory and streams here).  Each function checks dtypes and shapes,
+allocates the workspace the call asks for when none is given, and passes raw
+pointers and the current stream.  Every step runs in the library's kernels;
+there is no fallback: if libkpa.so is missing the import fails.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkpa.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python {_HERE}/build.py` "
+                      "(or __graft_entry__.build())")
+
+_lib = C.CDLL(LIB_PATH)
+
+KPA_OK = 0
+KPA_EINVAL = -1
+KPA_EWORKSPACE = -2
+KPA_ECAPACITY = -3
+KPA_EBUDGET = -4
+KPA_EUNSUPPORTED = -5
+KPA_EHIP = -6
+KPA_SORT_RADIX = 0
+KPA_SORT_LEARNED = 1
+KPA_PWL_MAX_SEG = 1024
+KPA_MLP_PARAMS = 1153
+PWL_MODEL_BYTES = 8 + 8 + 4 + 4 + 4 * (KPA_PWL_MAX_SEG + 1) + 12  # sizeof(kpa_pwl_model)
+SORT_STATS_WORDS = 6
+
+
+class KpaError(RuntimeError):
+    def __init__(self, fn, code):
+        msg = _lib.kpa_last_error_string().decode(errors="replace")
+        super().__init__(f"{fn} failed with status {code}: {msg}")
+        self.code = code
+
+
+class kpa_row_layout(C.Structure):
+    _fields_ = [("row_bytes", C.c_uint32), ("key_off", C.c_uint32), ("val_off", C.c_uint32),
+                ("val_w", C.c_uint32), ("ts_off", C.c_uint32), ("ts_w", C.c_uint32)]
+
+
+_vp = C.c_void_p
+_u64 = C.c_uint64
+_u32 = C.c_uint32
+_f32 = C.c_float
+_sz = C.POINTER(C.c_size_t)
+_lay = C.POINTER(kpa_row_layout)
+
+_SIGS = {
+    "kpa_version": ([], C.c_int32),
+    "kpa_last_error_string": ([], C.c_char_p),
+    "kpa_device_check": ([C.POINTER(C.c_int32)], C.c_int32),
+    "kpa_extract": ([_vp, _u64, _lay, _u32, _vp, _vp, _vp], C.c_int32),
+    "kpa_partition_windows_workspace_size": ([_u64, _u32, _sz], C.c_int32),
+    "kpa_partition_windows": ([_vp, _u64, _lay, _u64, _u64, _u32, _u32, _vp, _vp, _vp, _vp, _vp,
+                               C.c_size_t, _vp], C.c_int32),
+    "kpa_sort_workspace_size": ([_u64, _u32, C.c_int, _sz], C.c_int32),
+    "kpa_sort_segmented": ([_vp, _vp, _vp, _vp, _vp, _u32, _u64, C.c_int, _vp, _vp, _vp,
+                            C.c_size_t, _vp], C.c_int32),
+    "kpa_sort": ([_vp, _vp, _u64, _vp, _vp, C.c_int, _vp, _vp, _vp, C.c_size_t, _vp], C.c_int32),
+    "kpa_merge_workspace_size": ([_u64, _u64, _sz], C.c_int32),
+    "kpa_merge": ([_vp, _vp, _u64, _vp, _vp, _u64, _vp, _vp, _vp, C.c_size_t, _vp], C.c_int32),
+    "kpa_merge_runs_workspace_size": ([_u64, _sz], C.c_int32),
+    "kpa_merge_runs": ([_vp, _vp, C.POINTER(_u64), _u32, _vp, _vp, _vp, C.c_size_t, _vp],
+                       C.c_int32),
+    "kpa_reduce_by_key_workspace_size": ([_u64, _u32, _sz], C.c_int32),
+    "kpa_reduce_by_key": ([_vp, _vp, _vp, _u32, _u64, _vp, _lay, _vp, _vp, _vp, _vp, _vp, _vp,
+                           _vp, C.c_size_t, _vp], C.c_int32),
+    "kpa_topk_by_sum_workspace_size": ([_u64, _u32, _sz], C.c_int32),
+    "kpa_topk_by_sum": ([_vp, _vp, _vp, _u32, _u64, _u32, _vp, _vp, _vp, _vp, C.c_size_t, _vp],
+                        C.c_int32),
+    "kpa_median_by_key_workspace_size": ([_u64, _u32, _sz], C.c_int32),
+    "kpa_median_by_key": ([_vp, _vp, _vp, _u32, _u64, _vp, _lay, _vp, _vp, _vp, _vp, C.c_size_t,
+                           _vp], C.c_int32),
+    "kpa_join_workspace_size": ([_u64, _u64, _u32, _sz], C.c_int32),
+    "kpa_join": ([_vp, _vp, _vp, _u64, _vp, _vp, _vp, _u64, _u32, _vp, _vp, _lay, _vp, _vp, _vp,
+                  _u64, _vp, _vp, C.c_size_t, _vp], C.c_int32),
+    "kpa_materialize": ([_vp, _u64, _vp, _u32, _vp, _vp], C.c_int32),
+    "kpa_pwl_fit": ([_vp, _vp, _u32, _u32, _vp, _vp], C.c_int32),
+    "kpa_mlp_training_set": ([_vp, _u64, _u32, _vp, _vp, _vp, _vp], C.c_int32),
+    "kpa_mlp_forward": ([_vp, _vp, _u32, _vp, _vp], C.c_int32),
+    "kpa_mlp_loss_grad_workspace_size": ([_u32, _sz], C.c_int32),
+    "kpa_mlp_loss_grad": ([_vp, _vp, _vp, _u32, _vp, _vp, _vp, C.c_size_t, _vp], C.c_int32),
+    "kpa_mlp_adam_step": ([_vp, _vp, _vp, _vp, _u32, _f32, _f32, _f32, _f32, _vp], C.c_int32),
+    "kpa_mlp_train": ([_vp, _vp, _vp, _vp, _vp, _u32, _u32, _u32, _f32, _vp, _vp, C.c_size_t,
+                       _vp], C.c_int32),
+    "kpa_mlp_to_pwl": ([_vp, _u32, _vp, _vp], C.c_int32),
+}
+
+EXPORTED = []
+for _name, (_args, _res) in _SIGS.items():
+    if hasattr(_lib, _name):
+        _f = getattr(_lib, _name)
+        _f.argtypes = _args
+        _f.restype = _res
+        EXPORTED.append(_name)
+
+
+def _call(name, *args):
+    rc = getattr(_lib, name)(*args)
+    if rc != KPA_OK:
+        raise KpaError(name, rc)
+
+
+def _p(t):
+    if t is None:
+        return None
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ws_size(fn, *args):
+    n = C.c_size_t(0)
+    _call(fn, *args, C.byref(n))
+    return int(n.value)
+
+
+def _ws(nbytes, device, ws=None):
+    if ws is not None:
+        if ws.numel() * ws.element_size() < nbytes:
+            raise ValueError(f"workspace of {ws.numel()} bytes < {nbytes}")
+        return ws
+    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+
+
+def _check(t, dtype, name):
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def layout_struct(layout):
+    return kpa_row_layout(layout.row_bytes, layout.key_off, layout.val_off, layout.val_w,
+                          layout.ts_off, layout.ts_w)
+
+
+def rows_count(rows, layout):
+    return rows.numel() * rows.element_size() // layout.row_bytes
+
+
+# ------------------------------------------------------------------ calls --
+
+def kpa_version():
+    return int(_lib.kpa_version())
+
+
+def kpa_device_check():
+    v = C.c_int32(0)
+    _call("kpa_device_check", C.byref(v))
+    return bool(v.value)
+
+
+def kpa_extract(rows, layout, rid_base=0, out_keys=None, out_rids=None, stream=None):
+    n = rows_count(rows, layout)
+    dev = rows.device
+    out_keys = torch.empty(n, dtype=torch.int64, device=dev) if out_keys is None else out_keys
+    out_rids = torch.empty(n, dtype=torch.int32, device=dev) if out_rids is None else out_rids
+    L = layout_struct(layout)
+    _call("kpa_extract", _p(rows), n, C.byref(L), rid_base, _p(out_keys), _p(out_rids),
+          _stream(stream))
+    return out_keys, out_rids
+
+
+def kpa_partition_windows(rows, layout, win_len, n_win, win_origin=0, rid_base=0, n=None,
+                          out_keys=None, out_rids=None, out_win_off=None, out_oob=None, ws=None,
+                          stream=None):
+    n = rows_count(rows, layout) if n is None else n
+    dev = rows.device
+    out_keys = torch.empty(max(n, 1), dtype=torch.int64, device=dev) if out_keys is None else out_keys
+    out_rids = torch.empty(max(n, 1), dtype=torch.int32, device=dev) if out_rids is None else out_rids
+    out_win_off = (torch.empty(n_win + 1, dtype=torch.int64, device=dev)
+                   if out_win_off is None else out_win_off)
+    out_oob = torch.empty(1, dtype=torch.int64, device=dev) if out_oob is None else out_oob
+    nb = _ws_size("kpa_partition_windows_workspace_size", n, n_win)
+    ws = _ws(nb, dev, ws)
+    L = layout_struct(layout)
+    _call("kpa_partition_windows", _p(rows), n, C.byref(L), win_len, win_origin, n_win, rid_base,
+          _p(out_keys), _p(out_rids), _p(out_win_off), _p(out_oob), _p(ws),
+          ws.numel() * ws.element_size(), _stream(stream))
+    return out_keys, out_rids, out_win_off, out_oob
+
+
+def kpa_sort_workspace_size(n_cap, n_seg=1, algo=KPA_SORT_RADIX):
+    return _ws_size("kpa_sort_workspace_size", n_cap, n_seg, algo)
+
+
+def kpa_sort_segmented(keys_in, rids_in, seg_off, n_cap=None, algo=KPA_SORT_RADIX, models=None,
+                       stats=None, keys_out=None, rids_out=None, ws=None, stream=None):
+    _check(keys_in, torch.int64, "keys_in")
+    _check(rids_in, torch.int32, "rids_in")
+    n_seg = seg_off.numel() - 1
+    n_cap = keys_in.numel() if n_cap is None else n_cap
+    dev = keys_in.device
+    keys_out = torch.empty_like(keys_in) if keys_out is None else keys_out
+    rids_out = torch.empty_like(rids_in) if rids_out is None else rids_out
+    nb = kpa_sort_workspace_size(n_cap, n_seg, algo)
+    ws = _ws(nb, dev, ws)
+    _call("kpa_sort_segmented", _p(keys_in), _p(rids_in), _p(keys_out), _p(rids_out), _p(seg_off),
+          n_seg, n_cap, algo, _p(models), _p(stats), _p(ws), ws.numel() * ws.element_size(),
+          _stream(stream))
+    return keys_out, rids_out
+
+
+def kpa_sort(keys_in, rids_in, algo=KPA_SORT_RADIX, model=None, stats=None, keys_out=None,
+             rids_out=None, ws=None, stream=None):
+    _check(keys_in, torch.int64, "keys_in")
+    _check(rids_in, torch.int32, "rids_in")
+    n = keys_in.numel()
+    dev = keys_in.device
+    keys_out = torch.empty_like(keys_in) if keys_out is None else keys_out
+    rids_out = torch.empty_like(rids_in) if rids_out is None else rids_out
+    nb = kpa_sort_workspace_size(n, 1, algo)
+    ws = _ws(nb, dev, ws)
+    _call("kpa_sort", _p(keys_in), _p(rids_in), n, _p(keys_out), _p(rids_out), algo, _p(model),
+          _p(stats), _p(ws), ws.numel() * ws.element_size(), _stream(stream))
+    return keys_out, rids_out
+
+
+def kpa_merge(a_keys, a_rids, b_keys, b_rids, out_keys=None, out_rids=None, ws=None, stream=None):
+    na, nb_ = a_keys.numel(), b_keys.numel()
+    dev = a_keys.device
+    out_keys = torch.empty(na + nb_, dtype=torch.int64, device=dev) if out_keys is None else out_keys
+    out_rids = torch.empty(na + nb_, dtype=torch.int32, device=dev) if out_rids is None else out_rids
+    nb = _ws_size("kpa_merge_workspace_size", na, nb_)
+    ws = _ws(nb, dev, ws)
+    _call("kpa_merge", _p(a_keys), _p(a_rids), na, _p(b_keys), _p(b_rids), nb_, _p(out_keys),
+          _p(out_rids), _p(ws), ws.numel() * ws.element_size(), _stream(stream))
+    return out_keys, out_rids
+
+
+def kpa_merge_runs(keys, rids, run_off, out_keys=None, out_rids=None, ws=None, stream=None):
+    """run_off: host list/array of n_runs+1 offsets.  keys/rids are clobbered."""
+    n = keys.numel()
+    dev = keys.device
+    offs = (C.c_uint64 * len(run_off))(*[int(x) for x in run_off])
+    out_keys = torch.empty_like(keys) if out_keys is None else out_keys
+    out_rids = torch.empty_like(rids) if out_rids is None else out_rids
+    nb = _ws_size("kpa_merge_runs_workspace_size", n)
+    ws = _ws(nb, dev, ws)
+    _call("kpa_merge_runs", _p(keys), _p(rids), offs, len(run_off) - 1, _p(out_keys), _p(out_rids),
+          _p(ws), ws.numel() * ws.element_size(), _stream(stream))
+    return out_keys, out_rids
+
+
+def kpa_reduce_by_key(keys, rids, seg_off, rows, layout, n_cap=None, want=("cnt", "sum", "max"),
+                      ws=None, stream=None, outs=None):
+    n_seg = seg_off.numel() - 1
+    n_cap = keys.numel() if n_cap is None else n_cap
+    dev = keys.device
+    cap = max(n_cap, 1)
+    o = outs or {}
+    gkey = o.get("gkey", torch.empty(cap, dtype=torch.int64, device=dev))
+    outs_t = {w: o.get(w, torch.empty(cap, dtype=torch.int64, device=dev)) for w in want}
+    gseg = o.get("gseg_off", torch.empty(n_seg + 1, dtype=torch.int64, device=dev))
+    nb = _ws_size("kpa_reduce_by_key_workspace_size", n_cap, n_seg)
+    ws = _ws(nb, dev, ws)
+    L = layout_struct(layout)
+    _call("kpa_reduce_by_key", _p(keys), _p(rids), _p(seg_off), n_seg, n_cap, _p(rows), C.byref(L),
+          _p(gkey), _p(outs_t.get("cnt")), _p(outs_t.get("sum")), _p(outs_t.get("max")),
+          _p(outs_t.get("gstart")), _p(gseg), _p(ws), ws.numel() * ws.element_size(),
+          _stream(stream))
+    return gkey, outs_t, gseg
+
+
+def kpa_topk_by_sum(gkey, gsum, gseg_off, k=10, g_cap=None, ws=None, stream=None, outs=None):
+    n_seg = gseg_off.numel() - 1
+    g_cap = gkey.numel() if g_cap is None else g_cap
+    dev = gkey.device
+    o = outs or {}
+    ok = o.get("key", torch.empty(n_seg * k, dtype=torch.int64, device=dev))
+    osum = o.get("sum", torch.empty(n_seg * k, dtype=torch.int64, device=dev))
+    on = o.get("n", torch.empty(n_seg, dtype=torch.int32, device=dev))
+    nb = _ws_size("kpa_topk_by_sum_workspace_size", g_cap, n_seg)
+    ws = _ws(nb, dev, ws)
+    _call("kpa_topk_by_sum", _p(gkey), _p(gsum), _p(gseg_off), n_seg, g_cap, k, _p(ok), _p(osum),
+          _p(on), _p(ws), ws.numel() * ws.element_size(), _stream(stream))
+    return ok, osum, on
+
+
+def kpa_median_by_key(keys, rids, seg_off, rows, layout, n_cap=None, ws=None, stream=None):
+    n_seg = seg_off.numel() - 1
+    n_cap = keys.numel() if n_cap is None else n_cap
+    dev = keys.device
+    cap = max(n_cap, 1)
+    gkey = torch.empty(cap, dtype=torch.int64, device=dev)
+    gmed = torch.empty(cap, dtype=torch.int64, device=dev)
+    gseg = torch.empty(n_seg + 1, dtype=torch.int64, device=dev)
+    nb = _ws_size("kpa_median_by_key_workspace_size", n_cap, n_seg)
+    ws = _ws(nb, dev, ws)
+    L = layout_struct(layout)
+    _call("kpa_median_by_key", _p(keys), _p(rids), _p(seg_off), n_seg, n_cap, _p(rows), C.byref(L),
+          _p(gkey), _p(gmed), _p(gseg), _p(ws), ws.numel() * ws.element_size(), _stream(stream))
+    return gkey, gmed, gseg
+
+
+def kpa_join(lk, lr, l_seg_off, rk, rr, r_seg_off, rows_l, rows_r, layout, pairs_cap=0,
+             nl_cap=None, nr_cap=None, ws=None, stream=None):
+    n_seg = l_seg_off.numel() - 1
+    nl_cap = lk.numel() if nl_cap is None else nl_cap
+    nr_cap = rk.numel() if nr_cap is None else nr_cap
+    dev = lk.device
+    count = torch.empty(n_seg, dtype=torch.int64, device=dev)
+    sumprod = torch.empty(n_seg, dtype=torch.int64, device=dev)
+    pairs = torch.empty((max(pairs_cap, 1), 3), dtype=torch.int64, device=dev) if pairs_cap else None
+    npairs = torch.empty(1, dtype=torch.int64, device=dev)
+    nb = _ws_size("kpa_join_workspace_size", nl_cap, nr_cap, n_seg)
+    ws = _ws(nb, dev, ws)
+    L = layout_struct(layout)
+    _call("kpa_join", _p(lk), _p(lr), _p(l_seg_off), nl_cap, _p(rk), _p(rr), _p(r_seg_off), nr_cap,
+          n_seg, _p(rows_l), _p(rows_r), C.byref(L), _p(count), _p(sumprod), _p(pairs), pairs_cap,
+          _p(npairs), _p(ws), ws.numel() * ws.element_size(), _stream(stream))
+    return count, sumprod, pairs, npairs
+
+
+def kpa_materialize(rids, rows, row_bytes, out_rows=None, stream=None):
+    n = rids.numel()
+    dev = rids.device
+    if out_rows is None:
+        out_rows = torch.empty(max(n, 1) * row_bytes // 8, dtype=torch.int64, device=dev)
+    _call("kpa_materialize", _p(rids), n, _p(rows), row_bytes, _p(out_rows), _stream(stream))
+    return out_rows
+
+
+def new_models(n, device):
+    """Uninitialised kpa_pwl_model array (bytes) for n segments."""
+    return torch.zeros(n * PWL_MODEL_BYTES, dtype=torch.uint8, device=device)
+
+
+def kpa_pwl_fit(sorted_keys, seg_off, n_seg_model=1024, models=None, stream=None):
+    n_seg = seg_off.numel() - 1
+    models = new_models(n_seg, sorted_keys.device) if models is None else models
+    _call("kpa_pwl_fit", _p(sorted_keys), _p(seg_off), n_seg, n_seg_model, _p(models),
+          _stream(stream))
+    return models
+
+
+def model_fields(models):
+    """Host view of a models buffer: list of (kmin, kmax, n_seg, knots)."""
+    raw = models.detach().cpu().numpy().tobytes()
+    import numpy as np
+    out = []
+    for i in range(len(raw) // PWL_MODEL_BYTES):
+        b = raw[i * PWL_MODEL_BYTES:(i + 1) * PWL_MODEL_BYTES]
+        kmin = int.from_bytes(b[0:8], "little")
+        kmax = int.from_bytes(b[8:16], "little")
+        ns = int.from_bytes(b[16:20], "little")
+        knots = np.frombuffer(b[24:24 + 4 * (KPA_PWL_MAX_SEG + 1)], dtype=np.float32)
+        out.append((kmin, kmax, ns, knots[:ns + 1].copy()))
+    return out
+
+
+def new_sort_stats(device):
+    return torch.zeros(SORT_STATS_WORDS, dtype=torch.int64, device=device)
+
+
+def kpa_mlp_training_set(sorted_keys, S, model, stream=None):
+    dev = sorted_keys.device
+    x = torch.empty(S, dtype=torch.float32, device=dev)
+    y = torch.empty(S, dtype=torch.float32, device=dev)
+    _call("kpa_mlp_training_set", _p(sorted_keys), sorted_keys.numel(), S, _p(x), _p(y), _p(model),
+          _stream(stream))
+    return x, y
+
+
+def kpa_mlp_forward(params, x, stream=None):
+    out = torch.empty_like(x)
+    _call("kpa_mlp_forward", _p(params), _p(x), x.numel(), _p(out), _stream(stream))
+    return out
+
+
+def kpa_mlp_loss_grad(params, x, y, ws=None, stream=None):
+    m = x.numel()
+    loss = torch.empty(1, dtype=torch.float32, device=x.device)
+    grad = torch.empty(KPA_MLP_PARAMS, dtype=torch.float32, device=x.device)
+    nb = _ws_size("kpa_mlp_loss_grad_workspace_size", m)
+    ws = _ws(nb, x.device, ws)
+    _call("kpa_mlp_loss_grad", _p(params), _p(x), _p(y), m, _p(loss), _p(grad), _p(ws),
+          ws.numel() * ws.element_size(), _stream(stream))
+    return loss, grad
+
+
+def kpa_mlp_adam_step(params, grad, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+                      stream=None):
+    _call("kpa_mlp_adam_step", _p(params), _p(grad), _p(m), _p(v), t, lr, beta1, beta2, eps,
+          _stream(stream))
+
+
+def kpa_mlp_train(params, m, v, x, y, t0, steps, lr=1e-3, ws=None, stream=None):
+    n = x.numel()
+    loss = torch.empty(1, dtype=torch.float32, device=x.device)
+    nb = _ws_size("kpa_mlp_loss_grad_workspace_size", n)
+    ws = _ws(nb, x.device, ws)
+    _call("kpa_mlp_train", _p(params), _p(m), _p(v), _p(x), _p(y), n, t0, steps, lr, _p(loss),
+          _p(ws), ws.numel() * ws.element_size(), _stream(stream))
+    return loss
+
+
+def kpa_mlp_to_pwl(params, model, n_seg_model=1024, stream=None):
+    _call("kpa_mlp_to_pwl", _p(params), n_seg_model, _p(model), _stream(stream))
+    return model
