@@ -59,7 +59,7 @@ enum {
 /* Byte layout of a fixed-size little-endian row ("full record").  The key is a
  * u64 at key_off; value and timestamp are u32 or u64 (width 4 or 8). */
 typedef struct kpa_row_layout {
-  uint32_t row_bytes; /* multiple of 4, at most 256 */
+  uint32_t row_bytes; /* multiple of 8, at most 256 */
   uint32_t key_off;   /* 8-byte aligned offset of the u64 key */
   uint32_t val_off;   /* offset of the value column, aligned to val_w */
   uint32_t val_w;     /* 4 or 8 */
@@ -73,6 +73,17 @@ int32_t kpa_version(void);
 const char* kpa_last_error_string(void);
 /* Sets *out to 1 if the current HIP device is gfx950, else 0. */
 kpa_status kpa_device_check(int32_t* out);
+
+/* Per-kernel timing (tracing aid; not part of any primitive).  While enabled,
+ * every launch is bracketed by HIP events on its own stream.  enable(1) also
+ * clears earlier records.  collect() waits for the recorded events and adds
+ * their durations to per-kernel totals; get() returns the number of launches
+ * and total milliseconds of one kernel name; names() lists the names seen, comma
+ * separated, into buf. */
+kpa_status kpa_profile_enable(int32_t on);
+kpa_status kpa_profile_collect(void);
+kpa_status kpa_profile_get(const char* name, uint64_t* launches, double* total_ms);
+kpa_status kpa_profile_names(char* buf, size_t len);
 
 /* ---------------------------------------------------------------------------
  * Extract (Table 2: bundle -> KPA, sequential).  keys[i] = u64 at key_off of
@@ -93,13 +104,17 @@ kpa_status kpa_extract(const void* rows, uint64_t n, const kpa_row_layout* layou
  * out_win_off (device, n_win+1 u64) receives the start of each window and the
  * total.  Rows outside all windows are not written; their number goes to
  * *out_oob (device u64).  1 <= n_win <= 256, win_len >= 1.
+ * out_vals (device, n u64, may be NULL): the value column (layout->val_off,
+ * zero-extended) of every row in arrival order, out_vals[i] for row i.  It is
+ * a compact copy of one nonresident column: a keyed reduction can read its
+ * values there (as 8-byte rows) instead of in the full rows.
  */
 kpa_status kpa_partition_windows_workspace_size(uint64_t n, uint32_t n_win, size_t* bytes);
 kpa_status kpa_partition_windows(const void* rows, uint64_t n, const kpa_row_layout* layout,
                                  uint64_t win_len, uint64_t win_origin, uint32_t n_win,
                                  uint32_t rid_base, uint64_t* out_keys, uint32_t* out_rids,
-                                 uint64_t* out_win_off, uint64_t* out_oob, void* ws,
-                                 size_t ws_bytes, hipStream_t stream);
+                                 uint64_t* out_vals, uint64_t* out_win_off, uint64_t* out_oob,
+                                 void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Sort (Table 2: KPA(c) -> KPA(c), sequential access).  Stable sort by key:

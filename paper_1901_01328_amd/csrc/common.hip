@@ -78,9 +78,8 @@ __global__ void __launch_bounds__(1024) k_seg_tiles(const u64* __restrict__ off_
 
 kpa_status launch_seg_tiles(const u64* off_a, const u64* off_b, u32 n_seg, u32 tile,
                             u32* tile_start, hipStream_t st) {
-  hipLaunchKernelGGL(k_seg_tiles, dim3(1), dim3(1024), 0, st, off_a, off_b, n_seg, tile,
+  KPA_LAUNCH("seg_tiles", k_seg_tiles, dim3(1), dim3(1024), 0, st, off_a, off_b, n_seg, tile,
                      tile_start);
-  KPA_LAUNCHED();
   return KPA_OK;
 }
 
@@ -94,15 +93,13 @@ __global__ void __launch_bounds__(256) k_fill(T* __restrict__ p, u64 n, T v) {
 kpa_status launch_fill_u32(u32* p, u64 n, u32 v, hipStream_t st) {
   if (n == 0) return KPA_OK;
   u64 blocks = std::min<u64>(ceil_div(n, 256), 8192);
-  hipLaunchKernelGGL(k_fill<u32>, dim3((u32)blocks), dim3(256), 0, st, p, n, v);
-  KPA_LAUNCHED();
+  KPA_LAUNCH("fill", k_fill<u32>, dim3((u32)blocks), dim3(256), 0, st, p, n, v);
   return KPA_OK;
 }
 kpa_status launch_fill_u64(u64* p, u64 n, u64 v, hipStream_t st) {
   if (n == 0) return KPA_OK;
   u64 blocks = std::min<u64>(ceil_div(n, 256), 8192);
-  hipLaunchKernelGGL(k_fill<u64>, dim3((u32)blocks), dim3(256), 0, st, p, n, v);
-  KPA_LAUNCHED();
+  KPA_LAUNCH("fill", k_fill<u64>, dim3((u32)blocks), dim3(256), 0, st, p, n, v);
   return KPA_OK;
 }
 
@@ -177,10 +174,9 @@ kpa_status kpa_extract(const void* rows, uint64_t n, const kpa_row_layout* layou
               "misaligned pointer");
   KPA_REQUIRE(n + rid_base <= (1ull << 32), KPA_EUNSUPPORTED, "rids exceed 32 bits");
   u64 blocks = std::min<u64>(ceil_div(n, 256), 16384);
-  hipLaunchKernelGGL(k_extract, dim3((u32)blocks), dim3(256), 0, stream,
+  KPA_LAUNCH("extract", k_extract, dim3((u32)blocks), dim3(256), 0, stream,
                      static_cast<const unsigned char*>(rows), n, layout->row_bytes,
                      layout->key_off, rid_base, out_keys, out_rids);
-  KPA_LAUNCHED();
   return KPA_OK;
 }
 
@@ -195,15 +191,15 @@ kpa_status kpa_materialize(const uint32_t* rids, uint64_t n, const void* rows, u
               "misaligned pointer");
   if (row_bytes == 32) {
     u64 blocks = std::min<u64>(ceil_div(n * 2, 256), 32768);
-    hipLaunchKernelGGL(k_materialize32, dim3((u32)blocks), dim3(256), 0, stream, rids, n,
-                       static_cast<const uint4*>(rows), static_cast<uint4*>(out_rows));
+    KPA_LAUNCH("materialize", k_materialize32, dim3((u32)blocks), dim3(256), 0, stream, rids, n,
+               static_cast<const uint4*>(rows), static_cast<uint4*>(out_rows));
   } else {
     u32 words = row_bytes / 8;
     u64 blocks = std::min<u64>(ceil_div(n * words, 256), 32768);
-    hipLaunchKernelGGL(k_materialize, dim3((u32)blocks), dim3(256), 0, stream, rids, n,
-                       static_cast<const u64*>(rows), words, static_cast<u64*>(out_rows));
+    KPA_LAUNCH("materialize", k_materialize, dim3((u32)blocks), dim3(256), 0, stream, rids, n,
+               static_cast<const u64*>(rows), words, static_cast<u64*>(out_rows));
   }
-  KPA_LAUNCHED();
+  
   return KPA_OK;
 }
 

@@ -48,6 +48,18 @@ void clear_error();
     }                                                                                        \
   } while (0)
 
+int prof_begin(const char* name, hipStream_t st);
+void prof_end(int slot, hipStream_t st);
+
+// Launch a kernel, timed by the profiler when it is enabled.
+#define KPA_LAUNCH(name, kernel, grid, block, shmem, st, ...)         \
+  do {                                                               \
+    int slot_ = ::kpa::prof_begin(name, st);                         \
+    hipLaunchKernelGGL(kernel, grid, block, shmem, st, __VA_ARGS__); \
+    ::kpa::prof_end(slot_, st);                                      \
+    KPA_LAUNCHED();                                                  \
+  } while (0)
+
 #define KPA_CHECK(expr)            \
   do {                             \
     kpa_status s_ = (expr);        \

@@ -1,13 +1,766 @@
+// Learned-splitter sort.
+//
+// A monotone model F (kpa_pwl_model: piecewise-linear CDF fitted on the sorted
+// KPA of an earlier window) maps each key to a bucket b = floor(B*F(key)),
+// B = 2^bits chosen per segment so that buckets hold about 1024 entries.
+// Because F never decreases, every key of bucket b precedes every key of
+// bucket b+1, so the sort reduces to
+//   1. a stable scatter by bucket id: one or two onesweep passes over the
+//      bucket id's bytes (digit_sort.hpp with the model as digit function);
+//   2. a finishing pass: each workgroup owns the buckets that start in its
+//      2048-entry stretch of the output and sorts them (at most 4096 entries)
+//      in LDS with a stable LSD radix over the bytes that vary among them;
+//   3. oversize chunks (a bucket larger than the on-chip capacity, typically
+//      a heavy key plus a few light keys the model could not separate) are
+//      listed.  Each is split stably three ways around its most frequent key
+//      (a sample's mode): the equal part is final (one key, input order), the
+//      parts below and above are sorted on chip when small enough, else split
+//      again; after two rounds what remains goes to the radix path.
+// A segment whose model fails validation (knots not finite, outside [0, 1],
+// or decreasing) gets a single bucket and so goes to the radix path whole.
+// The output equals the radix sort's byte for byte: both are the stable sort.
+#include "digit_sort.hpp"
 #include "learned_internal.hpp"
 
 namespace kpa {
 
-kpa_status learned_sort_plan(u64, u32, Carver&, LearnedWs*) { return KPA_OK; }
+struct LearnedDF {
+  static constexpr int PASSES = 2;
+  static constexpr int SMEM = KPA_PWL_MAX_SEG + 1;  // floats of LDS for the knots
+  struct Params {
+    const SegModel* segm;
+  };
+  SegModel m;
+  __device__ __forceinline__ LearnedDF(const Params& p, u32 seg) : m(p.segm[seg]) {}
+  // All threads: copy the knots to LDS and evaluate from there (the caller
+  // synchronizes before the first use).
+  __device__ __forceinline__ void bind(float* sm) {
+    if (m.bits) {
+      for (u32 j = threadIdx.x; j <= m.nseg; j += BLOCK) sm[j] = m.knots[j];
+      m.knots = sm;
+    }
+  }
+  __device__ __forceinline__ u32 digit(u64 k, u32 pass) const {
+    return (model_bucket(m, k) >> (8 * pass)) & 255u;
+  }
+  __device__ __forceinline__ void digits(u64 k, u32 (&d)[PASSES]) const {
+    const u32 b = model_bucket(m, k);
+    d[0] = b & 255u;
+    d[1] = (b >> 8) & 255u;
+  }
+};
 
-kpa_status learned_sort_launch(const u64*, const u32*, u64*, u32*, const u64*, u32, u64,
-                               const kpa_pwl_model*, kpa_sort_stats*, const RadixWs&,
-                               const LearnedWs&, hipStream_t) {
-  KPA_REQUIRE(false, KPA_EUNSUPPORTED, "learned sort not built yet");
+enum StatIdx { ST_BUCKETS = 0, ST_ONCHIP, ST_EQUAL, ST_FB_ENTRIES, ST_FB_BUCKETS, ST_VIOL };
+
+__device__ __forceinline__ void stat_add(kpa_sort_stats* st, int idx, u64 v) {
+  if (st && v) atomicAdd(reinterpret_cast<unsigned long long*>(st) + idx, (unsigned long long)v);
+}
+
+// One workgroup per segment (grid-stride): validate the model, choose the
+// bucket count.
+__global__ void __launch_bounds__(BLOCK) k_learned_setup(const kpa_pwl_model* __restrict__ models,
+                                                         const u64* __restrict__ seg_off,
+                                                         u32 n_seg, SegModel* __restrict__ segm,
+                                                         kpa_sort_stats* stats) {
+  for (u32 s = blockIdx.x; s < n_seg; s += gridDim.x) {
+    const kpa_pwl_model& M = models[s];
+    const u64 n = seg_off[s + 1] - seg_off[s];
+    const u32 nseg = M.n_seg;
+    bool ok = nseg >= 1 && nseg <= KPA_PWL_MAX_SEG && M.kmax >= M.kmin;
+    if (ok) {
+      for (u32 j = threadIdx.x; j <= nseg; j += BLOCK) {
+        const float a = M.knots[j];
+        bool good = a >= 0.0f && a <= 1.0f;  // false for NaN
+        if (j > 0) good = good && a >= M.knots[j - 1];
+        ok = ok && good;
+      }
+    }
+    ok = __syncthreads_and(ok);
+    if (threadIdx.x == 0) {
+      SegModel m;
+      m.kmin = M.kmin;
+      m.kmax = M.kmax;
+      m.nseg = ok ? nseg : 1;
+      const u64 span = M.kmax - M.kmin;
+      m.scale = (ok && span) ? (float)nseg / (float)span : 0.0f;
+      m.valid = ok ? 1u : 0u;
+      m.knots = M.knots;
+      u32 bits = 0;
+      if (ok && n > FCAP) {
+        const u64 want = (n + BUCKET_TARGET - 1) / BUCKET_TARGET;
+        while (bits < MAX_BUCKET_BITS && (1ull << bits) < want) ++bits;
+      }
+      m.bits = bits;
+      segm[s] = m;
+      if (n) {
+        stat_add(stats, ST_BUCKETS, 1ull << bits);
+        if (!ok) stat_add(stats, ST_VIOL, 1);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+struct FinishSmem {
+  u32 whist[WAVES][RADIX];
+  u32 lstart[RADIX];
+  u32 scan[WAVES + 1];
+  u32 red[WAVES];
+  u64 red64[2 * WAVES];
+  float knots[KPA_PWL_MAX_SEG + 1];
+  u64 skeys[FCAP + 1];
+  u32 srids[FCAP];
+  u32 srel[FCAP];  // refined bucket id relative to the chunk's first bucket
+  u32 flag;
+};
+
+__device__ __forceinline__ u32 block_min_u32(u32 v, u32* sm) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const u32 t = __shfl_xor(v, o, 64);
+    v = t < v ? t : v;
+  }
+  __syncthreads();
+  if (__lane_id() == 0) sm[threadIdx.x >> 6] = v;
+  __syncthreads();
+  u32 r = sm[0];
+  for (int i = 1; i < WAVES; ++i) r = sm[i] < r ? sm[i] : r;
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ void block_or_and(u64& o, u64& a, u64* sm) {
+#pragma unroll
+  for (int s = 32; s > 0; s >>= 1) {
+    o |= __shfl_xor(o, s, 64);
+    a &= __shfl_xor(a, s, 64);
+  }
+  __syncthreads();
+  if (__lane_id() == 0) {
+    sm[threadIdx.x >> 6] = o;
+    sm[WAVES + (threadIdx.x >> 6)] = a;
+  }
+  __syncthreads();
+  o = sm[0];
+  a = sm[WAVES];
+  for (int i = 1; i < WAVES; ++i) {
+    o |= sm[i];
+    a &= sm[WAVES + i];
+  }
+  __syncthreads();
+}
+
+constexpr u32 NONE = 0xFFFFFFFFu;
+
+// Stable on-chip sort of the m <= FCAP entries held in sm.skeys/sm.srids
+// [0, m): LSD over the bytes that vary among the keys, one rank-and-move per
+// byte, data kept in LDS between passes.  Returns with the sorted entries in
+// sm (and false when nothing varied).
+__device__ bool lds_sort(FinishSmem& sm, u32 m) {
+  const u32 tid = threadIdx.x;
+  const u32 w = tid >> 6;
+  __syncthreads();
+  u64 vor = 0, vand = ~0ull;
+  for (u32 i = tid; i < m; i += BLOCK) {
+    vor |= sm.skeys[i];
+    vand &= sm.skeys[i];
+  }
+  block_or_and(vor, vand, sm.red64);
+  const u64 vary = vor ^ vand;
+  if (vary == 0) return false;
+  u32 valid = 0;
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j)
+    if (tile_offset(j) < m) valid |= 1u << j;
+#pragma unroll 1
+  for (u32 p = 0; p < 8; ++p) {
+    if (((vary >> (8 * p)) & 255u) == 0) continue;
+    u64 kk[ITEMS];
+    u32 rr[ITEMS], d[ITEMS], rank[ITEMS], tc;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      const u32 o = tile_offset(j);
+      kk[j] = ((valid >> j) & 1) ? sm.skeys[o] : 0ull;
+      rr[j] = ((valid >> j) & 1) ? sm.srids[o] : 0u;
+      d[j] = (u32)(kk[j] >> (8 * p)) & 255u;
+    }
+    __syncthreads();
+    rank_tile(sm.whist, sm.lstart, sm.scan, d, valid, rank, &tc);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j)
+      if ((valid >> j) & 1) {
+        const u32 pos = sm.lstart[d[j]] + sm.whist[w][d[j]] + rank[j];
+        sm.skeys[pos] = kk[j];
+        sm.srids[pos] = rr[j];
+      }
+    __syncthreads();
+  }
+  return true;
+}
+
+// Stable on-chip sort of the chunk [0, m) in sm using the model once more:
+// entries are ranked by their refined bucket id (8 more bits of F, given in
+// sm.srel, taken relative to the chunk's first bucket) in one or two byte passes, which leaves runs of
+// entries sharing a refined id -- a handful each when the model fits -- that
+// are insertion-sorted by key.  A long run of distinct keys (the model does
+// not separate them) sends the chunk to the byte-wise LSD sort.  Returns false
+// when all keys are equal (nothing to do).
+__device__ bool lds_sort_model(FinishSmem& sm, const SegModel& m, u32 mcount) {
+  const u32 tid = threadIdx.x;
+  const u32 w = tid >> 6;
+  __syncthreads();
+  u64 vor = 0, vand = ~0ull;
+  u32 rmax = 0;
+  // sm.srel holds each entry's refined bucket id; make it relative to the
+  // chunk's first bucket
+  const u32 base = (sm.srel[0] >> 8) << 8;
+  __syncthreads();
+  for (u32 i = tid; i < mcount; i += BLOCK) {
+    const u64 k = sm.skeys[i];
+    vor |= k;
+    vand &= k;
+    const u32 r = sm.srel[i] - base;
+    sm.srel[i] = r;
+    rmax = r > rmax ? r : rmax;
+  }
+  block_or_and(vor, vand, sm.red64);
+  if (vor == vand) return false;
+  rmax = ~block_min_u32(~rmax, sm.red);
+  if (!m.valid || rmax >= (1u << 16)) return lds_sort(sm, mcount);
+  u32 valid = 0;
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j)
+    if (tile_offset(j) < mcount) valid |= 1u << j;
+#pragma unroll 1
+  for (u32 p = 0; p < 2; ++p) {
+    if (p == 1 && rmax < 256u) break;
+    u64 kk[ITEMS];
+    u32 rr[ITEMS], re[ITEMS], d[ITEMS], rank[ITEMS], tc;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      const u32 o = tile_offset(j);
+      const bool v = (valid >> j) & 1;
+      kk[j] = v ? sm.skeys[o] : 0ull;
+      rr[j] = v ? sm.srids[o] : 0u;
+      re[j] = v ? sm.srel[o] : 0u;
+      d[j] = (re[j] >> (8 * p)) & 255u;
+    }
+    __syncthreads();
+    rank_tile(sm.whist, sm.lstart, sm.scan, d, valid, rank, &tc);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j)
+      if ((valid >> j) & 1) {
+        const u32 pos = sm.lstart[d[j]] + sm.whist[w][d[j]] + rank[j];
+        sm.skeys[pos] = kk[j];
+        sm.srids[pos] = rr[j];
+        sm.srel[pos] = re[j];
+      }
+    __syncthreads();
+  }
+  // Runs of equal refined id: insertion sort by key (stable).  Run starts,
+  // run ends and adjacent inversions are found in parallel; each short run is
+  // sorted by the thread holding its start; a long run is left alone when it
+  // has no inversion (typically one repeated key) and otherwise sends the
+  // chunk to the byte-wise sort.
+  if (tid == 0) sm.flag = 0;
+  u32 stm = 0, lastm = 0, invm = 0, rs[ITEMS];
+  u32 carry = 0;
+  const u32 lane = __lane_id();
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    const u32 i = tile_offset(j);
+    bool st = false, la = false, inv = false;
+    if (i < mcount) {
+      const u32 r = sm.srel[i];
+      st = i == 0 || sm.srel[i - 1] != r;
+      la = i + 1 == mcount || sm.srel[i + 1] != r;
+      inv = !st && sm.skeys[i] < sm.skeys[i - 1];
+    }
+    stm |= (u32)st << j;
+    lastm |= (u32)la << j;
+    invm |= (u32)inv << j;
+    // run start of position i: max start position <= i (wave scan + carry)
+    u32 v = st ? i : 0u;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const u32 t = __shfl_up(v, o, 64);
+      if (lane >= (u32)o) v = t > v ? t : v;
+    }
+    v = carry > v ? carry : v;
+    rs[j] = v;
+    carry = __shfl(v, 63, 64);
+  }
+  // earlier waves' last run start
+  sm.red[w] = carry;
+  __syncthreads();
+  u32 before = 0;
+  for (u32 q = 0; q < w; ++q) before = sm.red[q] > before ? sm.red[q] : before;
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) rs[j] = rs[j] > before ? rs[j] : before;
+  __syncthreads();
+  // the last entry of each run stores the run's end at the run's start; an
+  // inversion inside a run marks the run (bit 31) as needing the sort
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j)
+    if ((lastm >> j) & 1) sm.srel[rs[j]] = tile_offset(j) + 1;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j)
+    if ((invm >> j) & 1) atomicOr(&sm.srel[rs[j]], 0x80000000u);
+  __syncthreads();
+  // Each entry of a short run counts the run's entries that must precede it
+  // (smaller key, or equal key earlier): its position within the run.
+  u64 nk[ITEMS];
+  u32 nr[ITEMS], np[ITEMS];
+  u32 movem = 0;
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    const u32 i = tile_offset(j);
+    np[j] = i;
+    if (i >= mcount) continue;
+    const u32 s0 = rs[j], re = sm.srel[s0], e = re & 0x7FFFFFFFu;
+    if (!(re >> 31)) continue;  // run already in order
+    if (e - s0 > 64) {
+      sm.flag = 1;
+      continue;
+    }
+    const u64 k = sm.skeys[i];
+    u32 rank = 0;
+    for (u32 q = s0; q < e; ++q) {
+      const u64 kq = sm.skeys[q];
+      rank += (kq < k) || (kq == k && q < i);
+    }
+    np[j] = s0 + rank;
+    nk[j] = k;
+    nr[j] = sm.srids[i];
+    movem |= (u32)(np[j] != i) << j;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j)
+    if ((movem >> j) & 1) {
+      sm.skeys[np[j]] = nk[j];
+      sm.srids[np[j]] = nr[j];
+    }
+  __syncthreads();
+  if (sm.flag) lds_sort(sm, mcount);
+  return true;
+}
+
+__device__ __forceinline__ void load_knots(FinishSmem& sm, SegModel& m) {
+  if (m.bits) {
+    for (u32 j = threadIdx.x; j <= m.nseg; j += BLOCK) sm.knots[j] = m.knots[j];
+    m.knots = sm.knots;
+  }
+  __syncthreads();
+}
+
+// Finishing pass: one workgroup per 2048-entry stretch [pos0, pos0+FH) of a
+// segment.  It owns the buckets whose first entry lies in its stretch: the
+// chunk [start, end) from its first bucket start to the first bucket start at
+// or after pos0+FH (or the segment end).  Chunks of at most FCAP entries are
+// sorted on chip; larger ones are listed for the pivot rounds.
+//
+// Other workgroups rewrite neighbouring chunks while this one reads entries
+// there to find bucket edges; a chunk's sort only permutes entries inside the
+// chunk's buckets, so the bucket of every position never changes and the
+// edges found do not depend on timing.
+__global__ void __launch_bounds__(BLOCK, 2) k_learned_finish(
+    u64* __restrict__ keys, u32* __restrict__ rids, const u64* __restrict__ seg_off, u32 n_seg,
+    const u32* __restrict__ ftile_start, const SegModel* __restrict__ segm,
+    u64* __restrict__ fb_lo, u64* __restrict__ fb_hi, u32* __restrict__ fb_count, u32 max_fb,
+    kpa_sort_stats* stats) {
+  __shared__ FinishSmem sm;
+  const u32 tid = threadIdx.x;
+  const u32 tile = blockIdx.x;
+  if (tile >= ftile_start[n_seg]) return;
+  const u32 seg = find_seg(ftile_start, n_seg, tile);
+  const u32 k = tile - ftile_start[seg];
+  const u64 a = seg_off[seg], b = seg_off[seg + 1];
+  const u64 pos0 = a + (u64)k * FH;
+  if (pos0 >= b) return;
+  SegModel m = segm[seg];
+  load_knots(sm, m);
+
+  // --- first bucket start in [pos0, pos0 + FH) ---------------------------
+  u64 start = a;
+  if (k > 0) {
+    const u32 span = (u32)min<u64>(FH, b - pos0);
+    for (u32 i = tid; i <= span; i += BLOCK) sm.skeys[i] = keys[pos0 - 1 + i];
+    __syncthreads();
+    u32 first = NONE;
+    for (u32 i = tid + 1; i <= span; i += BLOCK)
+      if (model_bucket(m, sm.skeys[i]) != model_bucket(m, sm.skeys[i - 1]) && i - 1 < first)
+        first = i - 1;
+    first = block_min_u32(first, sm.red);
+    if (first == NONE) return;  // the bucket at pos0 started earlier and covers the stretch
+    start = pos0 + first;
+  }
+
+  // --- window [start, start + FCAP] and the chunk's end ---------------------
+  const u32 wn = (u32)min<u64>(FCAP, b - start);
+  const bool beyond = start + wn < b;  // an entry exists right after the window
+  __syncthreads();
+  for (u32 i = tid; i < wn; i += BLOCK) {
+    sm.skeys[i] = keys[start + i];
+    sm.srids[i] = rids[start + i];
+  }
+  if (tid == 0 && beyond) sm.skeys[wn] = keys[start + wn];
+  __syncthreads();
+  // refined bucket ids of the window, once per entry (bucket = id >> 8)
+  const u32 wl = wn + (beyond ? 1u : 0u);
+  for (u32 o = tid; o < wl; o += BLOCK) sm.srel[o] = m.valid ? model_fine(m, sm.skeys[o]) : 0u;
+  __syncthreads();
+  const u64 lo_e = max(pos0 + FH, start + 1);
+  u32 endo = NONE;  // end as an offset from start
+  for (u32 o = tid + 1; o <= wn; o += BLOCK) {
+    // position start+o begins a bucket (or is the segment end); the chunk
+    // ends at the first such position at or after pos0+FH, or at the end
+    const bool seg_end = o == wn && !beyond;
+    const bool edge = seg_end || (sm.srel[o] >> 8) != (sm.srel[o - 1] >> 8);
+    if (edge && (seg_end || start + o >= lo_e) && o < endo) endo = o;
+  }
+  endo = block_min_u32(endo, sm.red);
+
+  if (endo == NONE) {
+    // Oversize: the bucket running through the window end reaches past it.
+    if (tid == 0) {
+      const u32 beta = sm.srel[wn] >> 8;
+      u64 lo = start + wn, hi = b;  // first p in (lo, hi] with p == b or bucket > beta
+      while (hi - lo > 1) {
+        const u64 mid = lo + (hi - lo) / 2;
+        if (model_bucket(m, keys[mid]) > beta) hi = mid; else lo = mid;
+      }
+      const u32 idx = atomicAdd(fb_count, 1u);
+      if (idx < max_fb) {
+        fb_lo[idx] = start;
+        fb_hi[idx] = hi;
+      }
+    }
+    return;
+  }
+
+  const u32 mcount = endo;
+  const bool moved = lds_sort_model(sm, m, mcount);
+  if (tid == 0) stat_add(stats, moved ? ST_ONCHIP : ST_EQUAL, mcount);
+  if (!moved) return;  // one key: already in input order
+  for (u32 i = tid; i < mcount; i += BLOCK) {
+    keys[start + i] = sm.skeys[i];
+    rids[start + i] = sm.srids[i];
+  }
+}
+
+// Sorts listed ranges of at most FCAP entries in place, one workgroup each.
+__global__ void __launch_bounds__(BLOCK, 2) k_lds_sort_ranges(u64* __restrict__ keys,
+                                                           u32* __restrict__ rids,
+                                                           const u64* __restrict__ lo,
+                                                           const u64* __restrict__ hi,
+                                                           const u32* __restrict__ count,
+                                                           u32 max_count) {
+  __shared__ FinishSmem sm;
+  const u32 n = min(*count, max_count);
+  for (u32 r = blockIdx.x; r < n; r += gridDim.x) {
+    const u64 a = lo[r];
+    const u32 m = (u32)(hi[r] - a);
+    __syncthreads();
+    for (u32 i = threadIdx.x; i < m; i += BLOCK) {
+      sm.skeys[i] = keys[a + i];
+      sm.srids[i] = rids[a + i];
+    }
+    if (lds_sort(sm, m)) {
+      for (u32 i = threadIdx.x; i < m; i += BLOCK) {
+        keys[a + i] = sm.skeys[i];
+        rids[a + i] = sm.srids[i];
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------- pivot rounds --
+
+struct PivotDF {
+  static constexpr int PASSES = 1;
+  static constexpr int SMEM = 1;
+  __device__ __forceinline__ void bind(float*) {}
+  struct Params {
+    const u64* pivot;
+  };
+  u64 h;
+  __device__ __forceinline__ PivotDF(const Params& p, u32 seg) : h(p.pivot[seg]) {}
+  __device__ __forceinline__ u32 digit(u64 k, u32) const { return k < h ? 0u : (k == h ? 1u : 2u); }
+  __device__ __forceinline__ void digits(u64 k, u32 (&d)[PASSES]) const { d[0] = digit(k, 0); }
+};
+
+// Pivot of each listed chunk: the most frequent of 256 evenly spaced keys
+// (ties: the smaller key).  Also clears the chunk's counters.
+__global__ void __launch_bounds__(BLOCK) k_fb_pivot(const u64* __restrict__ keys, SegList sl,
+                                                    u64* __restrict__ pivot,
+                                                    u64* __restrict__ cnt3) {
+  __shared__ u64 samp[BLOCK];
+  __shared__ u64 bk[WAVES];
+  __shared__ u32 bc[WAVES];
+  const u32 n = sl.n();
+  for (u32 c = blockIdx.x; c < n; c += gridDim.x) {
+    const u64 a = sl.lo[c], m = sl.hi[c] - a;
+    __syncthreads();
+    samp[threadIdx.x] = keys[a + (m - 1) * threadIdx.x / (BLOCK - 1)];
+    __syncthreads();
+    const u64 mine = samp[threadIdx.x];
+    u32 cnt = 0;
+    for (int i = 0; i < BLOCK; ++i) cnt += samp[i] == mine;
+    // block argmax over (count desc, key asc)
+    u64 key = mine;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const u32 oc = __shfl_xor(cnt, o, 64);
+      const u64 okey = __shfl_xor(key, o, 64);
+      if (oc > cnt || (oc == cnt && okey < key)) {
+        cnt = oc;
+        key = okey;
+      }
+    }
+    if (__lane_id() == 0) {
+      bc[threadIdx.x >> 6] = cnt;
+      bk[threadIdx.x >> 6] = key;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      u32 best = bc[0];
+      u64 bkey = bk[0];
+      for (int i = 1; i < WAVES; ++i)
+        if (bc[i] > best || (bc[i] == best && bk[i] < bkey)) {
+          best = bc[i];
+          bkey = bk[i];
+        }
+      pivot[c] = bkey;
+      cnt3[3 * c] = cnt3[3 * c + 1] = cnt3[3 * c + 2] = 0;
+    }
+  }
+}
+
+// Entries below / equal to the pivot, per chunk (comparisons and wave sums;
+// no per-entry atomics).
+__global__ void __launch_bounds__(BLOCK) k_fb_count(const u64* __restrict__ keys, SegList sl,
+                                                    const u32* __restrict__ tile_start,
+                                                    const u64* __restrict__ pivot,
+                                                    u64* __restrict__ cnt3) {
+  __shared__ u64 red[2 * WAVES];
+  const u32 n_seg = sl.n();
+  const u32 total = tile_start[n_seg];
+  for (u32 tile = blockIdx.x; tile < total; tile += gridDim.x) {
+    u32 seg, t_in, cnt;
+    u64 a, b, base;
+    seg_tile_range(sl, tile_start, n_seg, tile, seg, t_in, a, b, base, cnt);
+    const u64 h = pivot[seg];
+    u64 lt = 0, eq = 0;
+    for (u32 i = threadIdx.x; i < cnt; i += BLOCK) {
+      const u64 k = keys[base + i];
+      lt += k < h;
+      eq += k == h;
+    }
+    lt = wave_sum(lt);
+    eq = wave_sum(eq);
+    __syncthreads();
+    if (__lane_id() == 0) {
+      red[threadIdx.x >> 6] = lt;
+      red[WAVES + (threadIdx.x >> 6)] = eq;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && cnt) {
+      u64 l = 0, e = 0;
+      for (int i = 0; i < WAVES; ++i) {
+        l += red[i];
+        e += red[WAVES + i];
+      }
+      atomicAdd(reinterpret_cast<unsigned long long*>(cnt3 + 3 * seg), (unsigned long long)l);
+      atomicAdd(reinterpret_cast<unsigned long long*>(cnt3 + 3 * seg + 1), (unsigned long long)e);
+    }
+  }
+}
+
+// One thread per chunk: the three-way split's digit offsets, whether the chunk
+// needs the scatter at all (not when it holds only the pivot key), and the
+// parts still to sort: on chip when small, else in the next round.
+__global__ void __launch_bounds__(BLOCK) k_fb_plan(SegList sl, const u64* __restrict__ cnt3,
+                                                   u64* __restrict__ rhi, u32* __restrict__ p_hist,
+                                                   u32* __restrict__ p_mask,
+                                                   u64* __restrict__ sm_lo, u64* __restrict__ sm_hi,
+                                                   u32* __restrict__ sm_count, u32 sm_max,
+                                                   u64* __restrict__ nx_lo, u64* __restrict__ nx_hi,
+                                                   u32* __restrict__ nx_count, u32 nx_max,
+                                                   kpa_sort_stats* stats) {
+  const u32 n = sl.n();
+  for (u32 c = blockIdx.x * BLOCK + threadIdx.x; c < n; c += gridDim.x * BLOCK) {
+    const u64 a = sl.lo[c], m = sl.hi[c] - a;
+    const u64 lt = cnt3[3 * c], eq = cnt3[3 * c + 1];
+    const u64 gt = m - lt - eq;
+    const bool pure = eq == m;
+    rhi[c] = pure ? a : sl.hi[c];
+    p_mask[c] = pure ? 0u : 1u;
+    p_hist[(u64)c * RADIX + 0] = 0;
+    p_hist[(u64)c * RADIX + 1] = (u32)lt;
+    p_hist[(u64)c * RADIX + 2] = (u32)(lt + eq);
+    if (stats) {
+      stat_add(stats, ST_EQUAL, eq);
+      stat_add(stats, ST_FB_ENTRIES, m - eq);
+      if (!pure) stat_add(stats, ST_FB_BUCKETS, 1);
+    }
+    const u64 parts_lo[2] = {a, a + lt + eq};
+    const u64 parts_n[2] = {lt, gt};
+    for (int p = 0; p < 2; ++p) {
+      if (parts_n[p] < 2) continue;
+      if (parts_n[p] <= FCAP) {
+        const u32 i = atomicAdd(sm_count, 1u);
+        if (i < sm_max) {
+          sm_lo[i] = parts_lo[p];
+          sm_hi[i] = parts_lo[p] + parts_n[p];
+        }
+      } else {
+        const u32 i = atomicAdd(nx_count, 1u);
+        if (i < nx_max) {
+          nx_lo[i] = parts_lo[p];
+          nx_hi[i] = parts_lo[p] + parts_n[p];
+        }
+      }
+    }
+  }
+}
+
+// Copies every listed chunk to the radix fallback's input buffer.
+__global__ void __launch_bounds__(BLOCK) k_fb_copy_all(const u64* __restrict__ keys,
+                                                       const u32* __restrict__ rids, SegList sl,
+                                                       const u32* __restrict__ tile_start,
+                                                       u64* __restrict__ keys_dst,
+                                                       u32* __restrict__ rids_dst) {
+  const u32 n_seg = sl.n();
+  const u32 total = tile_start[n_seg];
+  for (u32 tile = blockIdx.x; tile < total; tile += gridDim.x) {
+    u32 seg, t_in, cnt;
+    u64 a, b, base;
+    seg_tile_range(sl, tile_start, n_seg, tile, seg, t_in, a, b, base, cnt);
+    for (u32 i = threadIdx.x; i < cnt; i += BLOCK) {
+      keys_dst[base + i] = keys[base + i];
+      rids_dst[base + i] = rids[base + i];
+    }
+  }
+}
+
+// Copies the chunks that need the scatter to its input buffer.
+__global__ void __launch_bounds__(BLOCK) k_fb_copy(const u64* __restrict__ keys,
+                                                   const u32* __restrict__ rids, SegList sl,
+                                                   const u32* __restrict__ tile_start,
+                                                   const u32* __restrict__ p_mask,
+                                                   u64* __restrict__ keys_dst,
+                                                   u32* __restrict__ rids_dst) {
+  const u32 n_seg = sl.n();
+  const u32 total = tile_start[n_seg];
+  for (u32 tile = blockIdx.x; tile < total; tile += gridDim.x) {
+    u32 seg, t_in, cnt;
+    u64 a, b, base;
+    seg_tile_range(sl, tile_start, n_seg, tile, seg, t_in, a, b, base, cnt);
+    if (!p_mask[seg]) continue;
+    for (u32 i = threadIdx.x; i < cnt; i += BLOCK) {
+      keys_dst[base + i] = keys[base + i];
+      rids_dst[base + i] = rids[base + i];
+    }
+  }
+}
+
+kpa_status learned_sort_plan(u64 n_cap, u32 n_seg, Carver& c, LearnedWs* w) {
+  w->max_tiles = max_tiles(n_cap, n_seg, TILE);
+  w->max_ftiles = max_tiles(n_cap, n_seg, FH);
+  // an oversize chunk holds more than FCAP entries
+  w->max_fb = (u32)(n_cap / FCAP + n_seg + 1);
+  w->keys_tmp = c.take<u64>(n_cap);
+  w->rids_tmp = c.take<u32>(n_cap);
+  w->segm = c.take<SegModel>(n_seg);
+  w->ltile_start = c.take<u32>((u64)n_seg + 1);
+  w->ftile_start = c.take<u32>((u64)n_seg + 1);
+  w->hist = c.take<u32>((u64)n_seg * 2 * RADIX);
+  w->seg_mask = c.take<u32>(n_seg);
+  w->status0 = c.take<u32>(w->max_tiles * RADIX);
+  w->status1 = c.take<u32>(w->max_tiles * RADIX);
+  w->counters = c.take<u32>(16);
+  w->fb_lo = c.take<u64>(w->max_fb);
+  w->fb_hi = c.take<u64>(w->max_fb);
+  w->fb_rhi = c.take<u64>(w->max_fb);
+  w->fb_min = c.take<u64>(1);
+  w->fb_max = c.take<u64>(1);
+  w->fb_count = c.take<u32>(1);
+  w->fb_tile_start = c.take<u32>((u64)w->max_fb + 1);
+  for (int r = 0; r < 2; ++r) {
+    w->rl_lo[r] = c.take<u64>(w->max_fb);
+    w->rl_hi[r] = c.take<u64>(w->max_fb);
+  }
+  w->rl_count = c.take<u32>(4);
+  w->sm_lo = c.take<u64>(6ull * w->max_fb);
+  w->sm_hi = c.take<u64>(6ull * w->max_fb);
+  w->pivot = c.take<u64>(w->max_fb);
+  w->cnt3 = c.take<u64>(3ull * w->max_fb);
+  w->p_hist = c.take<u32>((u64)w->max_fb * RADIX);
+  w->p_mask = c.take<u32>(w->max_fb);
+  w->p_tile_start = c.take<u32>((u64)w->max_fb + 1);
+  // The radix path for what the pivot rounds leave: its own ping-pong buffer
+  // and per-chunk state.
+  return radix_sort_plan(n_cap, w->max_fb, c, &w->fb_radix);
+}
+
+kpa_status learned_sort_launch(const u64* keys_in, const u32* rids_in, u64* keys_out,
+                               u32* rids_out, const u64* seg_off, u32 n_seg, u64 n_cap,
+                               const kpa_pwl_model* models, kpa_sort_stats* stats,
+                               const LearnedWs& lw, hipStream_t st) {
+  (void)n_cap;
+  if (stats) KPA_CHECK(launch_fill_u64(reinterpret_cast<u64*>(stats), 6, 0, st));
+  KPA_CHECK(launch_fill_u32(lw.fb_count, 1, 0, st));
+  KPA_CHECK(launch_fill_u32(lw.rl_count, 4, 0, st));
+  KPA_LAUNCH("learned_setup", k_learned_setup, dim3(std::min<u32>(n_seg, 2048)), dim3(BLOCK), 0,
+             st, models, seg_off, n_seg, lw.segm, stats);
+  const SegList sl = seg_list_from_offsets(seg_off, n_seg);
+  DigitSortBufs b{keys_in, rids_in, keys_out, rids_out, lw.keys_tmp, lw.rids_tmp, lw.hist,
+                  lw.seg_mask, lw.ltile_start, lw.status0, lw.status1, lw.counters,
+                  lw.max_tiles};
+  KPA_CHECK(digit_sort_launch<LearnedDF>(sl, LearnedDF::Params{lw.segm}, b, st));
+
+  KPA_CHECK(launch_seg_tiles_list(sl, FH, lw.ftile_start, st));
+  KPA_LAUNCH("learned_finish", k_learned_finish, dim3((u32)lw.max_ftiles), dim3(BLOCK), 0, st,
+             keys_out, rids_out, seg_off, n_seg, lw.ftile_start, lw.segm, lw.fb_lo, lw.fb_hi,
+             lw.fb_count, lw.max_fb, stats);
+
+  // Pivot rounds over the oversize chunks: round 0 reads the finishing pass's
+  // list, round 1 the parts round 0 left over; small parts collect in one list.
+  const u64* lo_in[2] = {lw.fb_lo, lw.rl_lo[0]};
+  const u64* hi_in[2] = {lw.fb_hi, lw.rl_hi[0]};
+  const u32* cnt_in[2] = {lw.fb_count, lw.rl_count + 0};
+  for (int r = 0; r < 2; ++r) {
+    const SegList fl{lo_in[r], hi_in[r], cnt_in[r], lw.max_fb};
+    KPA_LAUNCH("pivot_select", k_fb_pivot, dim3(1024), dim3(BLOCK), 0, st, keys_out, fl, lw.pivot,
+               lw.cnt3);
+    KPA_CHECK(launch_seg_tiles_list(fl, TILE, lw.fb_tile_start, st));
+    KPA_LAUNCH("pivot_count", k_fb_count, dim3(2048), dim3(BLOCK), 0, st, keys_out, fl,
+               lw.fb_tile_start, lw.pivot, lw.cnt3);
+    KPA_LAUNCH("pivot_plan", k_fb_plan, dim3(64), dim3(BLOCK), 0, st, fl, lw.cnt3, lw.fb_rhi,
+               lw.p_hist, lw.p_mask, lw.sm_lo, lw.sm_hi, lw.rl_count + 2, 6 * lw.max_fb,
+               lw.rl_lo[r], lw.rl_hi[r], lw.rl_count + r, lw.max_fb, r == 0 ? stats : nullptr);
+    KPA_LAUNCH("pivot_copy", k_fb_copy, dim3(2048), dim3(BLOCK), 0, st, keys_out, rids_out, fl,
+               lw.fb_tile_start, lw.p_mask, lw.keys_tmp, lw.rids_tmp);
+    const SegList pl{lo_in[r], lw.fb_rhi, cnt_in[r], lw.max_fb};
+    DigitSortBufs pb{lw.keys_tmp, lw.rids_tmp, keys_out, rids_out, lw.fb_radix.keys_tmp,
+                     lw.fb_radix.rids_tmp, lw.p_hist, lw.p_mask, lw.p_tile_start,
+                     lw.fb_radix.status0, lw.fb_radix.status1, lw.fb_radix.counters,
+                     lw.fb_radix.max_tiles};
+    KPA_CHECK(digit_sort_launch<PivotDF>(pl, PivotDF::Params{lw.pivot}, pb, st, false));
+  }
+  KPA_LAUNCH("lds_sort_ranges", k_lds_sort_ranges, dim3(2048), dim3(BLOCK), 0, st, keys_out,
+             rids_out, lw.sm_lo, lw.sm_hi, lw.rl_count + 2, 6 * lw.max_fb);
+
+  // What two rounds did not resolve goes through the radix path.
+  const SegList rl{lw.rl_lo[1], lw.rl_hi[1], lw.rl_count + 1, lw.max_fb};
+  KPA_CHECK(launch_seg_tiles_list(rl, TILE, lw.fb_tile_start, st));
+  KPA_LAUNCH("fallback_copy", k_fb_copy_all, dim3(2048), dim3(BLOCK), 0, st, keys_out, rids_out,
+             rl, lw.fb_tile_start, lw.keys_tmp, lw.rids_tmp);
+  return radix_sort_launch(lw.keys_tmp, lw.rids_tmp, keys_out, rids_out, rl, lw.fb_radix, st);
 }
 
 }  // namespace kpa

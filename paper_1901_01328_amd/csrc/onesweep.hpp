@@ -13,6 +13,7 @@
 namespace kpa {
 
 constexpr int RADIX = 256;
+constexpr int LB_WINDOW = 16;  // look-back tiles probed per round trip
 static_assert(RADIX == BLOCK, "one thread per digit");
 
 struct OnesweepSmem {
@@ -33,28 +34,23 @@ __device__ __forceinline__ u32 tile_offset(int j) {
   return (threadIdx.x >> 6) * (64 * ITEMS) + j * 64 + __lane_id();
 }
 
-// Ranks, publishes, looks back and scatters.  k/r/d hold this thread's items;
-// item j is present iff bit j of `valid` is set.  my_digit_base is, for the
-// digit equal to this thread's index, the global index where that digit of
-// the segment begins (segment start plus the segment's exclusive digit count).  status points at the look-back words of
-// tile 0; the tile's own row is status + tile*RADIX.  first: the tile is the
-// first of its segment (its prefix is its own count).
-__device__ __forceinline__ void onesweep_tile(OnesweepSmem& sm, const u64 (&k)[ITEMS],
-                                              const u32 (&r)[ITEMS], const u32 (&d)[ITEMS],
-                                              u32 valid, u32* __restrict__ status, u32 tile,
-                                              bool first, u64 my_digit_base,
-                                              u64* __restrict__ keys_out,
-                                              u32* __restrict__ rids_out) {
+// Stable rank of a tile's entries by digit.  Item j of this thread (tile
+// offset tile_offset(j)) is present iff bit j of `valid` is set.  On return:
+// rank[j] = position of item j among the tile's entries with the same digit
+// that precede it in the wave, whist[w][d] = entries with digit d in waves
+// before w, lstart[d] = entries of the tile with a smaller digit, and the
+// return value is this thread's digit (d = threadIdx.x) count in the tile.
+// *tile_count receives the number of present entries.  Lanes holding the same
+// digit ("peers") are found with one ballot per digit bit.
+__device__ __forceinline__ u32 rank_tile(u32 (&whist)[WAVES][RADIX], u32* lstart, u32* scan,
+                                         const u32 (&d)[ITEMS], u32 valid, u32 (&rank)[ITEMS],
+                                         u32* tile_count) {
   const u32 tid = threadIdx.x;
   const u32 w = tid >> 6;
   const u32 lane = __lane_id();
-  u32* wh = sm.whist[w];
+  u32* wh = whist[w];
 #pragma unroll
   for (int i = 0; i < RADIX / 64; ++i) wh[lane + 64 * i] = 0;
-
-  // Stable rank within the wave, item by item: lanes holding the same digit
-  // ("peers") are found with one ballot per digit bit.
-  u32 rank[ITEMS];
   const u64 lt = lanemask_lt();
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) {
@@ -73,37 +69,73 @@ __device__ __forceinline__ void onesweep_tile(OnesweepSmem& sm, const u64 (&k)[I
     rank[j] = before + below;
   }
   __syncthreads();
-
   // Thread t owns digit t: per-wave exclusive offsets and the tile's count.
-  u32 c0 = sm.whist[0][tid], c1 = sm.whist[1][tid], c2 = sm.whist[2][tid], c3 = sm.whist[3][tid];
-  sm.whist[0][tid] = 0;
-  sm.whist[1][tid] = c0;
-  sm.whist[2][tid] = c0 + c1;
-  sm.whist[3][tid] = c0 + c1 + c2;
+  const u32 c0 = whist[0][tid], c1 = whist[1][tid], c2 = whist[2][tid], c3 = whist[3][tid];
+  whist[0][tid] = 0;
+  whist[1][tid] = c0;
+  whist[2][tid] = c0 + c1;
+  whist[3][tid] = c0 + c1 + c2;
   const u32 total = c0 + c1 + c2 + c3;
-  u32* my = status + (u64)tile * RADIX + tid;
-  st_status(my, (first ? ST_PRE : ST_AGG) | total);
+  lstart[tid] = block_excl_sum(total, scan, tile_count);
+  return total;
+}
 
+// Ranks, publishes, looks back and scatters.  k/r/d hold this thread's items;
+// item j is present iff bit j of `valid` is set.  my_digit_base is, for the
+// digit equal to this thread's index, the global index where that digit of
+// the segment begins (segment start plus the segment's exclusive digit count).
+// status points at the look-back words of tile 0; the tile's own row is
+// status + tile*RADIX.  tile_in_seg: index of the tile within its segment (the
+// first tile's prefix is its own count).
+__device__ __forceinline__ void onesweep_tile(OnesweepSmem& sm, const u64 (&k)[ITEMS],
+                                              const u32 (&r)[ITEMS], const u32 (&d)[ITEMS],
+                                              u32 valid, u32* __restrict__ status, u32 tile,
+                                              u32 tile_in_seg, u64 my_digit_base,
+                                              u64* __restrict__ keys_out,
+                                              u32* __restrict__ rids_out) {
+  const u32 tid = threadIdx.x;
+  const u32 w = tid >> 6;
+  const bool first = tile_in_seg == 0;
+  u32 rank[ITEMS];
   u32 tile_count;
-  const u32 ls = block_excl_sum(total, sm.scan, &tile_count);
-  sm.lstart[tid] = ls;
+  // Publish the tile's counts as soon as they are known (inside rank_tile the
+  // counts are complete before the block scan).
+  const u32 total = rank_tile(sm.whist, sm.lstart, sm.scan, d, valid, rank, &tile_count);
+  u32* my = status + (u64)tile * RADIX + tid;
+  if (first) st_status(my, ST_PRE | total);
+  else st_status(my, ST_AGG | total);
 
-  // Decoupled look-back over earlier tiles of the segment.  Every tile with a
-  // lower index was claimed by a running workgroup before this one and
-  // publishes its count without waiting, so the loop ends.
+  // Decoupled look-back over earlier tiles of the segment, LB_WINDOW tiles
+  // per round trip.  Every tile with a lower index was claimed by a running
+  // workgroup before this one and publishes its count without waiting, so the
+  // loop ends; the segment's first tile always holds a prefix.
   u32 excl = 0;
   if (!first) {
     const u32* p = my - RADIX;
+    u32 left = tile_in_seg;  // predecessors in the segment
     while (true) {
-      u32 s;
-      s = ld_status(p);
-      while ((s & ~ST_VAL) == 0) {
-        __builtin_amdgcn_s_sleep(1);
-        s = ld_status(p);
+      u32 s[LB_WINDOW];
+#pragma unroll
+      for (int i = 0; i < LB_WINDOW; ++i) s[i] = (u32)i < left ? ld_status(p - i * RADIX) : ST_PRE;
+      u32 acc = 0, used = 0;
+      bool done = false, stalled = false;
+#pragma unroll
+      for (int i = 0; i < LB_WINDOW; ++i) {
+        if (!done && !stalled) {
+          if ((s[i] & ~ST_VAL) == 0) {
+            stalled = true;
+          } else {
+            acc += s[i] & ST_VAL;
+            ++used;
+            if (s[i] & ST_PRE) done = true;
+          }
+        }
       }
-      excl += s & ST_VAL;
-      if (s & ST_PRE) break;
-      p -= RADIX;
+      excl += acc;
+      if (done) break;
+      p -= used * RADIX;
+      left -= used;
+      if (stalled) __builtin_amdgcn_s_sleep(1);
     }
     st_status(my, ST_PRE | (excl + total));
   }
@@ -124,11 +156,15 @@ __device__ __forceinline__ void onesweep_tile(OnesweepSmem& sm, const u64 (&k)[I
   __syncthreads();
 
   const u32 n = sm.count;
-  for (u32 i = tid; i < n; i += BLOCK) {
-    const u32 dd = sm.sdig[i];
-    const u64 dst = sm.gbase[dd] + (i - sm.lstart[dd]);
-    keys_out[dst] = sm.skeys[i];
-    rids_out[dst] = sm.srids[i];
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    const u32 i = tid + j * BLOCK;
+    if (i < n) {
+      const u32 dd = sm.sdig[i];
+      const u64 dst = sm.gbase[dd] + (i - sm.lstart[dd]);
+      keys_out[dst] = sm.skeys[i];
+      rids_out[dst] = sm.srids[i];
+    }
   }
 }
 

@@ -48,7 +48,9 @@ __device__ __forceinline__ u64 load_ts(const unsigned char* row, u32 ts_off, u32
 
 __global__ void __launch_bounds__(BLOCK) k_part_hist(const unsigned char* __restrict__ rows,
                                                      u64 n, u32 row_bytes, u32 ts_off, u32 ts_w,
-                                                     WinParams wp, u32* __restrict__ counts) {
+                                                     WinParams wp, u32* __restrict__ counts,
+                                                     u32 val_off, u32 val_w,
+                                                     u64* __restrict__ out_vals) {
   __shared__ u32 h[RADIX + 1];
   const u32 tid = threadIdx.x;
   h[tid] = 0;
@@ -58,7 +60,9 @@ __global__ void __launch_bounds__(BLOCK) k_part_hist(const unsigned char* __rest
   const u64 r1 = min(n, r0 + PART_HIST_ROWS);
   for (u64 i = r0 + tid; i < r1; i += BLOCK) {
     u32 w;
-    if (window_of(load_ts(rows + i * row_bytes, ts_off, ts_w), wp, w))
+    const unsigned char* row = rows + i * row_bytes;
+    if (out_vals) out_vals[i] = load_ts(row, val_off, val_w);
+    if (window_of(load_ts(row, ts_off, ts_w), wp, w))
       atomicAdd(&h[w], 1u);
     else
       atomicAdd(&h[RADIX], 1u);
@@ -120,7 +124,7 @@ __global__ void __launch_bounds__(BLOCK) k_part_pass(const unsigned char* __rest
     }
   }
   const u64 my_base = tid < wp.n_win ? (u64)woff[tid] : 0ull;
-  onesweep_tile(sm, kk, rr, dd, valid, status, tile, tile == 0, my_base, keys_out, rids_out);
+  onesweep_tile(sm, kk, rr, dd, valid, status, tile, tile, my_base, keys_out, rids_out);
 }
 
 struct PartWs {
@@ -157,10 +161,11 @@ kpa_status kpa_partition_windows_workspace_size(uint64_t n, uint32_t n_win, size
 kpa_status kpa_partition_windows(const void* rows, uint64_t n, const kpa_row_layout* layout,
                                  uint64_t win_len, uint64_t win_origin, uint32_t n_win,
                                  uint32_t rid_base, uint64_t* out_keys, uint32_t* out_rids,
-                                 uint64_t* out_win_off, uint64_t* out_oob, void* ws,
-                                 size_t ws_bytes, hipStream_t stream) {
+                                 uint64_t* out_vals, uint64_t* out_win_off, uint64_t* out_oob,
+                                 void* ws, size_t ws_bytes, hipStream_t stream) {
   clear_error();
-  KPA_CHECK(check_layout(layout, false, true));
+  KPA_CHECK(check_layout(layout, out_vals != nullptr, true));
+  KPA_REQUIRE(!out_vals || aligned(out_vals, 8), KPA_EINVAL, "misaligned out_vals");
   KPA_REQUIRE(n_win >= 1 && n_win <= RADIX, KPA_EUNSUPPORTED, "n_win must be in [1, 256]");
   KPA_REQUIRE(win_len >= 1, KPA_EINVAL, "win_len must be >= 1");
   KPA_REQUIRE(out_win_off && out_oob && ws, KPA_EINVAL, "null pointer");
@@ -189,20 +194,17 @@ kpa_status kpa_partition_windows(const void* rows, uint64_t n, const kpa_row_lay
   KPA_CHECK(launch_fill_u32(w.status, w.n_tiles * RADIX, 0, stream));
   const auto* r = static_cast<const unsigned char*>(rows);
   if (n) {
-    hipLaunchKernelGGL(k_part_hist, dim3((u32)ceil_div(n, PART_HIST_ROWS)), dim3(BLOCK), 0,
+    KPA_LAUNCH("part_hist", k_part_hist, dim3((u32)ceil_div(n, PART_HIST_ROWS)), dim3(BLOCK), 0,
                        stream, r, n, layout->row_bytes, layout->ts_off, layout->ts_w, wp,
-                       w.counts);
-    KPA_LAUNCHED();
+                       w.counts, layout->val_off, layout->val_w, out_vals);
   }
-  hipLaunchKernelGGL(k_part_scan, dim3(1), dim3(BLOCK), 0, stream, w.counts, n_win, out_win_off,
+  KPA_LAUNCH("part_scan", k_part_scan, dim3(1), dim3(BLOCK), 0, stream, w.counts, n_win, out_win_off,
                      out_oob);
-  KPA_LAUNCHED();
   if (n) {
-    hipLaunchKernelGGL(k_part_pass, dim3((u32)w.n_tiles), dim3(BLOCK), 0, stream, r, n,
+    KPA_LAUNCH("part_pass", k_part_pass, dim3((u32)w.n_tiles), dim3(BLOCK), 0, stream, r, n,
                        layout->row_bytes, layout->key_off, layout->ts_off, layout->ts_w, wp,
                        rid_base, w.counts, (u32)w.n_tiles, w.status, w.counter, out_keys,
                        out_rids);
-    KPA_LAUNCHED();
   }
   return KPA_OK;
 }

@@ -3,14 +3,14 @@
 // and top-k groups by sum.
 //
 // Reduction in three launches over 4096-entry tiles of every segment:
-//   1. summary: per tile, the number of runs that start in it and the
-//      aggregate of its last run (values gathered only for that run);
-//   2. scan (one workgroup): groups started before each tile, and the open run
-//      entering each tile (a segmented scan of the tile summaries);
-//   3. main: per tile, gather values, segmented scan in registers/LDS with the
-//      carried run prepended, and write every run at its last entry.
-// Integer addition is associative modulo 2^64, so the result does not depend on
-// how the work is split.
+//   1. heads: per tile, the number of runs that start in it (keys only);
+//   2. scan (one workgroup): groups started before each tile; output slots of
+//      runs that cross a tile edge are zeroed;
+//   3. main: per tile, gather values, segmented scan in registers/LDS, write
+//      each run at its last entry in the tile -- stored when the run lies in
+//      the tile, added atomically when it crosses an edge.
+// Integer addition and max are associative and commutative (sums modulo
+// 2^64), so the result does not depend on how the work is split.
 #include "reduce_internal.hpp"
 
 namespace kpa {
@@ -95,124 +95,105 @@ struct ValSrc {
   }
 };
 
-__global__ void __launch_bounds__(BLOCK) k_reduce_summary(const u64* __restrict__ keys,
-                                                          const u32* __restrict__ rids,
-                                                          const u64* __restrict__ seg_off,
-                                                          const u32* __restrict__ tile_start,
-                                                          u32 n_seg, ValSrc vs,
-                                                          TileSummary* __restrict__ summary) {
-  __shared__ u64 sk[TILE];
+// LDS index with one pad word per 16 entries, so that lanes reading
+// consecutive-per-thread entries fall into different banks.
+__device__ __forceinline__ u32 pidx(u32 i) { return i + (i >> 4); }
+constexpr u32 PTILE = TILE + TILE / 16;
+
+// Pass 1: runs that start in each tile; whether the tile's last run goes on
+// into the next tile (flag bit 0).
+__global__ void __launch_bounds__(BLOCK) k_reduce_heads(const u64* __restrict__ keys,
+                                                        const u64* __restrict__ seg_off,
+                                                        const u32* __restrict__ tile_start,
+                                                        u32 n_seg, u32* __restrict__ heads,
+                                                        u32* __restrict__ flags) {
+  __shared__ u64 sk[PTILE];
   __shared__ u64 red[WAVES];
   const u32 tile = blockIdx.x;
   if (tile >= tile_start[n_seg]) return;
   const TileRange tr = tile_range(seg_off, tile_start, n_seg, tile, TILE);
   const u32 tid = threadIdx.x;
-  for (u32 i = tid; i < tr.cnt; i += BLOCK) sk[i] = keys[tr.base + i];
+  for (u32 i = tid; i < tr.cnt; i += BLOCK) sk[pidx(i)] = keys[tr.base + i];
   const bool has_prev = tr.base > tr.a;
   const u64 prev = has_prev ? keys[tr.base - 1] : 0ull;
+  const bool has_next = tr.base + tr.cnt < tr.b;
+  const u64 next = has_next ? keys[tr.base + tr.cnt] : 0ull;
   __syncthreads();
   u32 nh = 0;
-  int last = -1;
+  u64 before = tid == 0 ? prev : sk[pidx(tid * ITEMS - 1)];
+  const bool first_has_prev = tid == 0 ? has_prev : true;
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) {
     const u32 idx = tid * ITEMS + j;
     if (idx < tr.cnt) {
-      const bool h = idx == 0 ? (!has_prev || sk[0] != prev) : (sk[idx] != sk[idx - 1]);
-      if (h) {
-        ++nh;
-        last = (int)idx;
-      }
+      const u64 k = sk[pidx(idx)];
+      const bool h = j == 0 ? (!first_has_prev || k != before) : (k != before);
+      nh += h;
+      before = k;
     }
   }
-  const u64 heads = block_sum_u64(nh, red);
-  const u64 lastp1 = block_max_u64((u64)(last + 1), red);  // 0: no head in the tile
-  const u32 start = lastp1 ? (u32)(lastp1 - 1) : 0u;
-  u64 s = 0, m = 0;
-  if (vs.on) {
-    for (u32 i = start + tid; i < tr.cnt; i += BLOCK) {
-      const u64 v = vs(rids[tr.base + i]);
-      s += v;
-      m = v > m ? v : m;
-    }
-  }
-  s = block_sum_u64(s, red);
-  m = block_max_u64(m, red);
+  const u64 total = block_sum_u64(nh, red);
   if (tid == 0) {
-    TileSummary t;
-    t.heads = (u32)heads;
-    t.pad = 0;
-    t.trail = SegAgg{lastp1 ? 1u : 0u, (u64)(tr.cnt - start), s, m, tr.base + start};
-    summary[tile] = t;
+    heads[tile] = (u32)total;
+    flags[tile] = (tr.cnt && has_next && sk[pidx(tr.cnt - 1)] == next) ? 1u : 0u;
   }
 }
 
-__global__ void __launch_bounds__(1024) k_reduce_scan(const TileSummary* __restrict__ summ,
+// Pass 2 (one workgroup): groups started before each tile, first group of each
+// segment, and zeroed output slots for runs that cross a tile boundary (those
+// are accumulated with atomics in pass 3).
+__global__ void __launch_bounds__(1024) k_reduce_scan(const u32* __restrict__ heads,
+                                                      const u32* __restrict__ flags,
                                                       const u32* __restrict__ tile_start,
                                                       u32 n_seg, u64* __restrict__ gbase,
-                                                      SegAgg* __restrict__ carry,
-                                                      u64* __restrict__ gseg_off) {
-  __shared__ SegAgg wa[16];
+                                                      u64* __restrict__ gseg_off,
+                                                      u64* __restrict__ o_cnt,
+                                                      u64* __restrict__ o_sum,
+                                                      u64* __restrict__ o_max) {
   __shared__ u64 wh[17];
   const u32 tid = threadIdx.x, lane = __lane_id(), w = tid >> 6;
   const u32 n_tiles = tile_start[n_seg];
   const u32 per = (n_tiles + 1023) / 1024;
   const u32 t0 = min(n_tiles, tid * per), t1 = min(n_tiles, t0 + per);
   u64 H = 0;
-  SegAgg A = seg_identity();
-  for (u32 t = t0; t < t1; ++t) {
-    H += summ[t].heads;
-    A = seg_combine(A, summ[t].trail);
-  }
-  // exclusive scans over 1024 threads
+  for (u32 t = t0; t < t1; ++t) H += heads[t];
   u64 hi = H;
-  SegAgg ai = A;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
     u64 th = __shfl_up(hi, o, 64);
-    SegAgg ta = shfl_up_agg(ai, o);
-    if (lane >= (u32)o) {
-      hi += th;
-      ai = seg_combine(ta, ai);
-    }
+    if (lane >= (u32)o) hi += th;
   }
-  u64 hx = __shfl_up(hi, 1, 64);
-  SegAgg ax = shfl_up_agg(ai, 1);
-  if (lane == 0) {
-    hx = 0;
-    ax = seg_identity();
-  }
-  if (lane == 63) {
-    wh[w] = hi;
-    wa[w] = ai;
-  }
+  if (lane == 63) wh[w] = hi;
   __syncthreads();
-  u64 hp = 0;
-  SegAgg ap = seg_identity();
-  for (u32 i = 0; i < w; ++i) {
-    hp += wh[i];
-    ap = seg_combine(ap, wa[i]);
-  }
-  u64 h = hp + hx;
-  SegAgg c = seg_combine(ap, ax);
+  u64 h = hi - H;
+  for (u32 i = 0; i < w; ++i) h += wh[i];
   for (u32 t = t0; t < t1; ++t) {
     gbase[t] = h;
-    carry[t] = c;
-    h += summ[t].heads;
-    c = seg_combine(c, summ[t].trail);
+    h += heads[t];
+    if (flags[t] & 1u) {
+      const u64 g = h - 1;
+      if (o_cnt) o_cnt[g] = 0;
+      if (o_sum) o_sum[g] = 0;
+      if (o_max) o_max[g] = 0;
+    }
   }
-  if (tid == 1023) wh[16] = h;  // total: the last thread's running count
+  if (tid == 1023) wh[16] = h;
   __syncthreads();
   for (u32 s = tid; s < n_seg; s += 1024) gseg_off[s] = gbase[tile_start[s]];
   if (tid == 0) gseg_off[n_seg] = wh[16];
 }
 
+// Pass 3: gather values, segmented reduction of each tile in registers and
+// LDS, write every run at its last entry in the tile.  A run wholly inside
+// the tile is stored; a run crossing a tile edge adds its part atomically
+// (integer sums and maxima are exact in any order).
 __global__ void __launch_bounds__(BLOCK) k_reduce_main(
     const u64* __restrict__ keys, const u32* __restrict__ rids, const u64* __restrict__ seg_off,
     const u32* __restrict__ tile_start, u32 n_seg, ValSrc vs, const u64* __restrict__ gbase,
-    const SegAgg* __restrict__ carry, u64* __restrict__ o_key, u64* __restrict__ o_cnt,
-    u64* __restrict__ o_sum, u64* __restrict__ o_max, u64* __restrict__ o_start) {
-  __shared__ u64 sk[TILE];
-  __shared__ u32 sr[TILE];
+    u64* __restrict__ o_key, u64* __restrict__ o_cnt, u64* __restrict__ o_sum,
+    u64* __restrict__ o_max, u64* __restrict__ o_start) {
+  __shared__ u64 sk[PTILE];
+  __shared__ u32 sr[PTILE];
   __shared__ SegAgg wsm[WAVES];
   __shared__ u32 hsm[WAVES + 1];
   const u32 tile = blockIdx.x;
@@ -220,8 +201,8 @@ __global__ void __launch_bounds__(BLOCK) k_reduce_main(
   const TileRange tr = tile_range(seg_off, tile_start, n_seg, tile, TILE);
   const u32 tid = threadIdx.x;
   for (u32 i = tid; i < tr.cnt; i += BLOCK) {
-    sk[i] = keys[tr.base + i];
-    sr[i] = rids[tr.base + i];
+    sk[pidx(i)] = keys[tr.base + i];
+    sr[pidx(i)] = rids[tr.base + i];
   }
   const bool has_prev = tr.base > tr.a;
   const u64 prev = has_prev ? keys[tr.base - 1] : 0ull;
@@ -230,36 +211,37 @@ __global__ void __launch_bounds__(BLOCK) k_reduce_main(
   __syncthreads();
 
   u64 v[ITEMS];
-  u32 hmask = 0, tmask = 0;
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) {
     const u32 idx = tid * ITEMS + j;
-    v[j] = 0;
-    if (idx < tr.cnt) v[j] = vs(sr[idx]);
+    v[j] = idx < tr.cnt ? vs(sr[pidx(idx)]) : 0ull;
   }
+  u32 hmask = 0, tmask = 0;
+  u64 before = tid == 0 ? prev : (tid * ITEMS - 1 < tr.cnt ? sk[pidx(tid * ITEMS - 1)] : 0ull);
+  const bool lead_has_prev = tid == 0 ? has_prev : true;
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) {
     const u32 idx = tid * ITEMS + j;
     if (idx < tr.cnt) {
-      const u64 k = sk[idx];
-      const bool h = idx == 0 ? (!has_prev || k != prev) : (k != sk[idx - 1]);
-      const bool t = idx + 1 == tr.cnt ? (!has_next || k != next) : (k != sk[idx + 1]);
+      const u64 k = sk[pidx(idx)];
+      const bool h = j == 0 ? (!lead_has_prev || k != before) : (k != before);
+      const bool last = idx + 1 == tr.cnt;
+      const u64 after = last ? next : sk[pidx(idx + 1)];
+      const bool t = last ? (!has_next || k != after) : (k != after);
       hmask |= (u32)h << j;
       tmask |= (u32)t << j;
+      before = k;
     }
   }
   SegAgg A = seg_identity();
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) {
     const u32 idx = tid * ITEMS + j;
-    if (idx < tr.cnt) {
-      const SegAgg e{(hmask >> j) & 1u, 1ull, v[j], v[j], tr.base + idx};
-      A = seg_combine(A, e);
-    }
+    if (idx < tr.cnt) A = seg_combine(A, SegAgg{(hmask >> j) & 1u, 1ull, v[j], v[j], tr.base + idx});
   }
   u32 htot;
   const u32 hex = block_excl_sum((u32)__popc(hmask), hsm, &htot);
-  SegAgg run = block_excl_segscan<WAVES>(A, carry[tile], wsm);
+  SegAgg run = block_excl_segscan<WAVES>(A, seg_identity(), wsm);
   const u64 gb = gbase[tile];
   u32 hs = hex;
 #pragma unroll
@@ -267,16 +249,27 @@ __global__ void __launch_bounds__(BLOCK) k_reduce_main(
     const u32 idx = tid * ITEMS + j;
     if (idx < tr.cnt) {
       const u32 h = (hmask >> j) & 1u;
-      const SegAgg e{h, 1ull, v[j], v[j], tr.base + idx};
-      run = seg_combine(run, e);
+      run = seg_combine(run, SegAgg{h, 1ull, v[j], v[j], tr.base + idx});
       hs += h;
-      if ((tmask >> j) & 1u) {
+      const bool t = (tmask >> j) & 1u;
+      const bool cont = idx + 1 == tr.cnt && !t;  // the run goes on in the next tile
+      if (t || cont) {
         const u64 gi = gb + hs - 1;
-        o_key[gi] = sk[idx];
-        if (o_cnt) o_cnt[gi] = run.c;
-        if (o_sum) o_sum[gi] = run.s;
-        if (o_max) o_max[gi] = run.m;
-        if (o_start) o_start[gi] = run.hp;
+        if (run.f && t) {  // the whole run lies in this tile
+          o_key[gi] = sk[pidx(idx)];
+          if (o_cnt) o_cnt[gi] = run.c;
+          if (o_sum) o_sum[gi] = run.s;
+          if (o_max) o_max[gi] = run.m;
+          if (o_start) o_start[gi] = run.hp;
+        } else {
+          if (run.f) {
+            o_key[gi] = sk[pidx(idx)];
+            if (o_start) o_start[gi] = run.hp;
+          }
+          if (o_cnt) atomicAdd(reinterpret_cast<unsigned long long*>(o_cnt + gi), run.c);
+          if (o_sum) atomicAdd(reinterpret_cast<unsigned long long*>(o_sum + gi), run.s);
+          if (o_max) atomicMax(reinterpret_cast<unsigned long long*>(o_max + gi), run.m);
+        }
       }
     }
   }
@@ -285,9 +278,9 @@ __global__ void __launch_bounds__(BLOCK) k_reduce_main(
 void reduce_plan(u64 n_cap, u32 n_seg, Carver& c, ReduceWs* w) {
   w->max_tiles = max_tiles(n_cap, n_seg, TILE);
   w->tile_start = c.take<u32>((u64)n_seg + 1);
-  w->summary = c.take<TileSummary>(w->max_tiles);
+  w->heads = c.take<u32>(w->max_tiles);
+  w->flags = c.take<u32>(w->max_tiles);
   w->gbase = c.take<u64>(w->max_tiles);
-  w->carry = c.take<SegAgg>(w->max_tiles);
 }
 
 kpa_status reduce_launch(const u64* keys, const u32* rids, const u64* seg_off, u32 n_seg,
@@ -300,16 +293,12 @@ kpa_status reduce_launch(const u64* keys, const u32* rids, const u64* seg_off, u
   vs.val_w = L ? L->val_w : 8;
   vs.on = need_val ? 1u : 0u;
   KPA_CHECK(launch_seg_tiles(seg_off, nullptr, n_seg, TILE, w.tile_start, st));
-  hipLaunchKernelGGL(k_reduce_summary, dim3((u32)w.max_tiles), dim3(BLOCK), 0, st, keys, rids,
-                     seg_off, w.tile_start, n_seg, vs, w.summary);
-  KPA_LAUNCHED();
-  hipLaunchKernelGGL(k_reduce_scan, dim3(1), dim3(1024), 0, st, w.summary, w.tile_start, n_seg,
-                     w.gbase, w.carry, o.gseg_off);
-  KPA_LAUNCHED();
-  hipLaunchKernelGGL(k_reduce_main, dim3((u32)w.max_tiles), dim3(BLOCK), 0, st, keys, rids,
-                     seg_off, w.tile_start, n_seg, vs, w.gbase, w.carry, o.gkey, o.cnt, o.sum,
-                     o.max, o.gstart);
-  KPA_LAUNCHED();
+  KPA_LAUNCH("reduce_heads", k_reduce_heads, dim3((u32)w.max_tiles), dim3(BLOCK), 0, st, keys,
+             seg_off, w.tile_start, n_seg, w.heads, w.flags);
+  KPA_LAUNCH("reduce_scan", k_reduce_scan, dim3(1), dim3(1024), 0, st, w.heads, w.flags,
+             w.tile_start, n_seg, w.gbase, o.gseg_off, o.cnt, o.sum, o.max);
+  KPA_LAUNCH("reduce_main", k_reduce_main, dim3((u32)w.max_tiles), dim3(BLOCK), 0, st, keys, rids,
+             seg_off, w.tile_start, n_seg, vs, w.gbase, o.gkey, o.cnt, o.sum, o.max, o.gstart);
   return KPA_OK;
 }
 
@@ -545,12 +534,10 @@ kpa_status kpa_topk_by_sum(const uint64_t* gkey, const uint64_t* gsum, const uin
   topk_plan(g_cap, n_seg, c, &w);
   KPA_REQUIRE(c.used <= ws_bytes, KPA_EWORKSPACE, "workspace too small: need %zu bytes", c.used);
   KPA_CHECK(launch_seg_tiles(gseg_off, nullptr, n_seg, GT, w.tile_start, stream));
-  hipLaunchKernelGGL(k_topk_local, dim3((u32)w.max_tiles), dim3(BLOCK), 0, stream, gkey, gsum,
+  KPA_LAUNCH("topk_local", k_topk_local, dim3((u32)w.max_tiles), dim3(BLOCK), 0, stream, gkey, gsum,
                      gseg_off, w.tile_start, n_seg, k, w.cs, w.ck, w.cn);
-  KPA_LAUNCHED();
-  hipLaunchKernelGGL(k_topk_final, dim3(n_seg), dim3(BLOCK), 0, stream, w.cs, w.ck, w.cn,
+  KPA_LAUNCH("topk_final", k_topk_final, dim3(n_seg), dim3(BLOCK), 0, stream, w.cs, w.ck, w.cn,
                      w.tile_start, k, out_key, out_sum, out_n);
-  KPA_LAUNCHED();
   return KPA_OK;
 }
 

@@ -19,17 +19,11 @@ __device__ __forceinline__ SegAgg seg_combine(const SegAgg& a, const SegAgg& b) 
   return SegAgg{a.f, a.c + b.c, a.s + b.s, a.m > b.m ? a.m : b.m, a.hp};
 }
 
-struct TileSummary {
-  u32 heads;
-  u32 pad;
-  SegAgg trail;  // aggregate of the tile's last (possibly unfinished) run
-};
-
 struct ReduceWs {
   u32* tile_start;
-  TileSummary* summary;
-  u64* gbase;    // groups started before each tile
-  SegAgg* carry; // open run entering each tile
+  u32* heads;   // runs starting in each tile
+  u32* flags;   // bit 0: the tile's last run continues into the next tile
+  u64* gbase;   // groups started before each tile
   u64 max_tiles;
 };
 

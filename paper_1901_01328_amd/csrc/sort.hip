@@ -9,9 +9,8 @@ namespace {
 
 kpa_status sort_plan(u64 n_cap, u32 n_seg, kpa_sort_algo algo, Carver& c, RadixWs* rw,
                      LearnedWs* lw) {
-  KPA_CHECK(radix_sort_plan(n_cap, n_seg, c, rw));
-  if (algo == KPA_SORT_LEARNED) KPA_CHECK(learned_sort_plan(n_cap, n_seg, c, lw));
-  return KPA_OK;
+  if (algo == KPA_SORT_LEARNED) return learned_sort_plan(n_cap, n_seg, c, lw);
+  return radix_sort_plan(n_cap, n_seg, c, rw);
 }
 
 __global__ void k_one_segment(u64* seg_off, u64 n) {
@@ -63,11 +62,12 @@ kpa_status kpa_sort_segmented(const uint64_t* keys_in, const uint32_t* rids_in,
   KPA_REQUIRE(c.used <= ws_bytes, KPA_EWORKSPACE, "workspace too small: need %zu bytes",
               c.used);
   if (algo == KPA_SORT_RADIX) {
-    KPA_CHECK(radix_sort_launch(keys_in, rids_in, keys_out, rids_out, seg_off, n_seg, rw, stream));
+    KPA_CHECK(radix_sort_launch(keys_in, rids_in, keys_out, rids_out,
+                                seg_list_from_offsets(seg_off, n_seg), rw, stream));
     if (stats) KPA_CHECK(launch_fill_u64(reinterpret_cast<u64*>(stats), 6, 0, stream));
   } else {
     KPA_CHECK(learned_sort_launch(keys_in, rids_in, keys_out, rids_out, seg_off, n_seg, n_cap,
-                                  models, stats, rw, lw, stream));
+                                  models, stats, lw, stream));
   }
   return KPA_OK;
 }
@@ -81,8 +81,7 @@ kpa_status kpa_sort(const uint64_t* keys_in, const uint32_t* rids_in, uint64_t n
   KPA_REQUIRE(ws && aligned(ws, 256), KPA_EINVAL, "workspace null or misaligned");
   KPA_REQUIRE(n < MAX_SEG_ENTRIES, KPA_EUNSUPPORTED, "a segment must hold fewer than 2^30 keys");
   u64* off = reinterpret_cast<u64*>(ws);  // first 16 bytes of the workspace
-  hipLaunchKernelGGL(k_one_segment, dim3(1), dim3(1), 0, stream, off, (u64)n);
-  KPA_LAUNCHED();
+  KPA_LAUNCH("one_segment", k_one_segment, dim3(1), dim3(1), 0, stream, off, (u64)n);
   return kpa_sort_segmented(keys_in, rids_in, keys_out, rids_out, off, 1, n, algo, model, stats,
                             ws, ws_bytes, stream);
 }

@@ -1,11 +1,33 @@
 // Workspace layouts and launch entry points shared between the sort files.
 #pragma once
 
-#include "kpa_internal.hpp"
+#include "onesweep.hpp"
 
 namespace kpa {
 
 constexpr u32 SEG_UNSUPPORTED = 1u << 31;
+
+// Segments [lo[s], hi[s]) for s < n, n = *n_dev when n_dev is set (a count
+// produced on the device), else n_max.
+struct SegList {
+  const u64* lo;
+  const u64* hi;
+  const u32* n_dev;
+  u32 n_max;
+  __device__ __forceinline__ u32 n() const { return n_dev ? min(*n_dev, n_max) : n_max; }
+};
+
+inline SegList seg_list_from_offsets(const u64* off, u32 n_seg) {
+  return SegList{off, off + 1, nullptr, n_seg};
+}
+
+// tile_start[s] = sum over s' < s of max(1, ceil(len(s')/tile)); tile_start[n] = total.
+kpa_status launch_seg_tiles_list(const SegList& sl, u32 tile, u32* tile_start, hipStream_t st);
+
+struct RadixDigit {
+  u32 shift;
+  __device__ __forceinline__ u32 operator()(u64 k) const { return (u32)(k >> shift) & 255u; }
+};
 
 struct RadixWs {
   u64* keys_tmp;
@@ -17,11 +39,11 @@ struct RadixWs {
   u32* status1;
   u32* counters;    // 16 tile counters (one per pass)
   u64 max_tiles;
+  u32 max_seg;
 };
 
 kpa_status radix_sort_plan(u64 n_cap, u32 n_seg, Carver& c, RadixWs* w);
 kpa_status radix_sort_launch(const u64* keys_in, const u32* rids_in, u64* keys_out,
-                             u32* rids_out, const u64* seg_off, u32 n_seg, const RadixWs& w,
-                             hipStream_t st);
+                             u32* rids_out, const SegList& sl, const RadixWs& w, hipStream_t st);
 
 }  // namespace kpa

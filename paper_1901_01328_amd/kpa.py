@@ -60,10 +60,14 @@ _SIGS = {
     "kpa_version": ([], C.c_int32),
     "kpa_last_error_string": ([], C.c_char_p),
     "kpa_device_check": ([C.POINTER(C.c_int32)], C.c_int32),
+    "kpa_profile_enable": ([C.c_int32], C.c_int32),
+    "kpa_profile_collect": ([], C.c_int32),
+    "kpa_profile_get": ([C.c_char_p, C.POINTER(_u64), C.POINTER(C.c_double)], C.c_int32),
+    "kpa_profile_names": ([C.c_char_p, C.c_size_t], C.c_int32),
     "kpa_extract": ([_vp, _u64, _lay, _u32, _vp, _vp, _vp], C.c_int32),
     "kpa_partition_windows_workspace_size": ([_u64, _u32, _sz], C.c_int32),
     "kpa_partition_windows": ([_vp, _u64, _lay, _u64, _u64, _u32, _u32, _vp, _vp, _vp, _vp, _vp,
-                               C.c_size_t, _vp], C.c_int32),
+                               _vp, C.c_size_t, _vp], C.c_int32),
     "kpa_sort_workspace_size": ([_u64, _u32, C.c_int, _sz], C.c_int32),
     "kpa_sort_segmented": ([_vp, _vp, _vp, _vp, _vp, _u32, _u64, C.c_int, _vp, _vp, _vp,
                             C.c_size_t, _vp], C.c_int32),
@@ -167,6 +171,29 @@ def kpa_device_check():
     return bool(v.value)
 
 
+def kpa_profile_enable(on=True):
+    _call("kpa_profile_enable", 1 if on else 0)
+
+
+def kpa_profile_collect():
+    _call("kpa_profile_collect")
+
+
+def kpa_profile_get(name):
+    """(launches, total milliseconds) of one kernel since the last enable."""
+    n = C.c_uint64(0)
+    ms = C.c_double(0.0)
+    _call("kpa_profile_get", name.encode(), C.byref(n), C.byref(ms))
+    return int(n.value), float(ms.value)
+
+
+def kpa_profile_names():
+    buf = C.create_string_buffer(4096)
+    _call("kpa_profile_names", buf, 4096)
+    v = buf.value.decode()
+    return [x for x in v.split(",") if x]
+
+
 def kpa_extract(rows, layout, rid_base=0, out_keys=None, out_rids=None, stream=None):
     n = rows_count(rows, layout)
     dev = rows.device
@@ -180,7 +207,9 @@ def kpa_extract(rows, layout, rid_base=0, out_keys=None, out_rids=None, stream=N
 
 def kpa_partition_windows(rows, layout, win_len, n_win, win_origin=0, rid_base=0, n=None,
                           out_keys=None, out_rids=None, out_win_off=None, out_oob=None, ws=None,
-                          stream=None):
+                          stream=None, out_vals=None):
+    """Returns (keys, rids, win_off, oob).  out_vals, when given (n int64), also
+    receives the value column of every row in arrival order."""
     n = rows_count(rows, layout) if n is None else n
     dev = rows.device
     out_keys = torch.empty(max(n, 1), dtype=torch.int64, device=dev) if out_keys is None else out_keys
@@ -192,7 +221,7 @@ def kpa_partition_windows(rows, layout, win_len, n_win, win_origin=0, rid_base=0
     ws = _ws(nb, dev, ws)
     L = layout_struct(layout)
     _call("kpa_partition_windows", _p(rows), n, C.byref(L), win_len, win_origin, n_win, rid_base,
-          _p(out_keys), _p(out_rids), _p(out_win_off), _p(out_oob), _p(ws),
+          _p(out_keys), _p(out_rids), _p(out_vals), _p(out_win_off), _p(out_oob), _p(ws),
           ws.numel() * ws.element_size(), _stream(stream))
     return out_keys, out_rids, out_win_off, out_oob
 

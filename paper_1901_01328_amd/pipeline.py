@@ -1,0 +1,89 @@
+"""Compound operators (Sec. 4.2) composed from the C-ABI primitives, with all
+buffers allocated once so that repeated steps allocate nothing.
+
+WindowAggregation: windowing (partition on the timestamp column) -> per-window
+sort of the KPA -> keyed reduction (count, sum, max) -> top-k keys by sum.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import kpa as K
+
+
+class _Layout:
+    def __init__(self, row_bytes, key_off, val_off, val_w, ts_off, ts_w):
+        self.row_bytes, self.key_off, self.val_off = row_bytes, key_off, val_off
+        self.val_w, self.ts_off, self.ts_w = val_w, ts_off, ts_w
+
+
+# A staged value column read as 8-byte rows whose only field is the value.
+VALUE_COLUMN = _Layout(8, 0, 0, 8, 0, 8)
+
+
+class WindowAggregation:
+    def __init__(self, n, layout, win_len, n_win, algo=K.KPA_SORT_RADIX, k=10, device="cuda",
+                 win_origin=0, want=("cnt", "sum", "max"), stage_values=True):
+        self.n, self.layout, self.win_len, self.n_win = n, layout, win_len, n_win
+        self.algo, self.k, self.origin = algo, k, win_origin
+        self.want = tuple(want)
+        d = torch.device(device)
+        cap = max(n, 1)
+        i64 = dict(dtype=torch.int64, device=d)
+        i32 = dict(dtype=torch.int32, device=d)
+        self.keys = torch.empty(cap, **i64)
+        self.rids = torch.empty(cap, **i32)
+        self.skeys = torch.empty(cap, **i64)
+        self.srids = torch.empty(cap, **i32)
+        self.win_off = torch.empty(n_win + 1, **i64)
+        self.oob = torch.empty(1, **i64)
+        # the value column staged compactly at partition time (8 bytes per row);
+        # the reduction gathers from it instead of from the full rows
+        self.vals = torch.empty(cap, **i64) if stage_values else None
+        self.gkey = torch.empty(cap, **i64)
+        self.g = {w: torch.empty(cap, **i64) for w in self.want}
+        self.gseg = torch.empty(n_win + 1, **i64)
+        self.top_key = torch.empty(n_win * k, **i64)
+        self.top_sum = torch.empty(n_win * k, **i64)
+        self.top_n = torch.empty(n_win, **i32)
+        u8 = dict(dtype=torch.uint8, device=d)
+        self.ws_part = torch.empty(
+            K._ws_size("kpa_partition_windows_workspace_size", n, n_win), **u8)
+        self.ws_sort = torch.empty(max(K.kpa_sort_workspace_size(n, n_win, K.KPA_SORT_RADIX),
+                                       K.kpa_sort_workspace_size(n, n_win, algo)), **u8)
+        self.ws_red = torch.empty(K._ws_size("kpa_reduce_by_key_workspace_size", n, n_win), **u8)
+        self.ws_top = torch.empty(K._ws_size("kpa_topk_by_sum_workspace_size", n, n_win), **u8)
+        self.models = K.new_models(n_win, d)
+        self.next_models = K.new_models(n_win, d)
+        self.stats = K.new_sort_stats(d)
+        self.have_models = False
+
+    def step(self, rows, stream=None):
+        K.kpa_partition_windows(rows, self.layout, self.win_len, self.n_win,
+                                win_origin=self.origin, n=self.n, out_keys=self.keys,
+                                out_rids=self.rids, out_win_off=self.win_off, out_oob=self.oob,
+                                ws=self.ws_part, stream=stream, out_vals=self.vals)
+        algo = self.algo if (self.algo == K.KPA_SORT_RADIX or self.have_models) else K.KPA_SORT_RADIX
+        K.kpa_sort_segmented(self.keys, self.rids, self.win_off, n_cap=self.n, algo=algo,
+                             models=self.models if algo == K.KPA_SORT_LEARNED else None,
+                             stats=self.stats, keys_out=self.skeys, rids_out=self.srids,
+                             ws=self.ws_sort, stream=stream)
+        if self.algo == K.KPA_SORT_LEARNED:
+            # Window w of the next batch is bucketed with the model fitted on
+            # window w-1 of this batch (window 0 with this batch's last window):
+            # each model comes from an earlier window, never its own data.
+            K.kpa_pwl_fit(self.skeys, self.win_off, 1024, models=self.next_models, stream=stream)
+            mb = K.PWL_MODEL_BYTES
+            self.models[mb:].copy_(self.next_models[:-mb])
+            self.models[:mb].copy_(self.next_models[-mb:])
+            self.have_models = True
+        outs = dict(self.g)
+        outs["gkey"] = self.gkey
+        outs["gseg_off"] = self.gseg
+        src, lay = (self.vals, VALUE_COLUMN) if self.vals is not None else (rows, self.layout)
+        K.kpa_reduce_by_key(self.skeys, self.srids, self.win_off, src, lay, n_cap=self.n,
+                            want=self.want, ws=self.ws_red, stream=stream, outs=outs)
+        if "sum" in self.g:
+            K.kpa_topk_by_sum(self.gkey, self.g["sum"], self.gseg, k=self.k, g_cap=self.n,
+                              ws=self.ws_top, stream=stream,
+                              outs={"key": self.top_key, "sum": self.top_sum, "n": self.top_n})

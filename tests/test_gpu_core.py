@@ -260,3 +260,52 @@ def test_c1_end_to_end(K, orc):
     assert np.array_equal(u64(gkey)[:1000], ek)
     assert np.array_equal(u64(outs["cnt"])[:1000], ec)
     assert np.array_equal(u64(outs["sum"])[:1000], es)
+
+
+def test_reduce_from_staged_value_column(K, orc):
+    """Partition stages the value column; the reduction reading it as 8-byte rows
+    equals the oracle reading full rows."""
+    from paper_1901_01328_amd.pipeline import VALUE_COLUMN
+    n = 123457
+    rows = c2_rows(n, seed=41, n_keys=20)   # long runs crossing many tiles
+    W, nw = 10 ** 5, 10
+    d = rows.cuda()
+    vals = torch.empty(n, dtype=torch.int64, device="cuda")
+    say("reduce from staged values")
+    keys, rids, off, oob = K.kpa_partition_windows(d, LAYOUT32, W, nw, out_vals=vals)
+    sk, sr = K.kpa_sort_segmented(keys, rids, off, n_cap=n)
+    gkey, outs, gseg = K.kpa_reduce_by_key(sk, sr, off, vals, VALUE_COLUMN, n_cap=n,
+                                           want=("cnt", "sum", "max", "gstart"))
+    torch.cuda.synchronize()
+    assert np.array_equal(u64(vals), u64(rows[:, 1].contiguous()))
+    hk, hr, hoff, _ = orc.partition(rows, LAYOUT32, W, nw)
+    esk, esr = orc.sort_segmented(hk, hr, hoff)
+    ek, ec, es, em, eoff = reduce_expect(orc, esk, esr, hoff, rows, LAYOUT32)
+    g = int(eoff[-1])
+    assert np.array_equal(u64(gseg), eoff)
+    assert np.array_equal(u64(gkey)[:g], ek)
+    assert np.array_equal(u64(outs["cnt"])[:g], ec)
+    assert np.array_equal(u64(outs["sum"])[:g], es)
+    assert np.array_equal(u64(outs["max"])[:g], em)
+
+
+def test_pipeline_twice_same_result(K, orc):
+    """Run-to-run equality of the whole windowed step (race canary)."""
+    from paper_1901_01328_amd.pipeline import WindowAggregation
+    n = 300001
+    rows = c2_rows(n, seed=42, n_keys=3000)
+    d = rows.cuda()
+    p = WindowAggregation(n, LAYOUT32, 10 ** 5, 10, device="cuda")
+    p.step(d)
+    torch.cuda.synchronize()
+    g = int(p.gseg[-1].item())
+    first = [p.skeys.clone(), p.srids.clone()] + [t[:g].clone() for t in
+                                                 (p.gkey, p.g["sum"], p.g["max"])]
+    first.append(p.top_key.clone())
+    p.step(d)
+    torch.cuda.synchronize()
+    second = [p.skeys, p.srids] + [t[:g] for t in (p.gkey, p.g["sum"], p.g["max"])]
+    second.append(p.top_key)
+    assert int(p.gseg[-1].item()) == g
+    for a, b in zip(first, second):
+        assert torch.equal(a, b)

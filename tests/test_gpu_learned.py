@@ -1,0 +1,186 @@
+"""GPU parity of the learned-splitter sort and its model fit.
+
+The learned sort must equal the oracle's stable sort byte for byte whatever the
+model: fitted on the same data, on an earlier (drifted) window, a constant
+model that puts every key in one bucket (forced overflow), and invalid models
+(decreasing or NaN knots), which must be detected and counted."""
+import numpy as np
+import pytest
+import torch
+
+import datagen
+from datagen.rows import mix64_int
+from gpu_util import dev_u32, dev_u64, kpa_mod, need_gpu, say, u32, u64
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def K():
+    need_gpu()
+    return kpa_mod()
+
+
+def zipf_mix_keys(n, s, k, seed):
+    """Zipf ranks mapped to pseudo-random 64-bit keys (heavy hitters)."""
+    u = datagen.splitmix64(seed, 1, torch.arange(n, dtype=torch.int64))
+    r = datagen.zipf_ranks(u, s, k)
+    table = datagen.key_table(k, seed ^ 77)
+    return table[r - 1].numpy().view(np.uint64).copy()
+
+
+def rank_zipf_keys(n, s, seed, offset=0):
+    """Rank-ordered Zipf keys: o + (r-1)*2^12 (steep CDF at the low end)."""
+    u = datagen.splitmix64(seed, 1, torch.arange(n, dtype=torch.int64))
+    r = datagen.zipf_ranks(u, s, 1 << 20).numpy().astype(np.uint64)
+    return np.uint64(offset) + (r - np.uint64(1)) * np.uint64(4096)
+
+
+def gen_keys(dist, n, seed):
+    rng = np.random.default_rng(seed)
+    if dist == "uniform64":
+        return rng.integers(0, 1 << 63, size=n, dtype=np.uint64) * np.uint64(2) + \
+            rng.integers(0, 2, size=n, dtype=np.uint64)
+    if dist == "zipf_mix":
+        return zipf_mix_keys(n, 1.1, 1 << 16, seed)
+    if dist == "zipf_rank":
+        return rank_zipf_keys(n, 1.2, seed, offset=(5 << 40))
+    if dist == "few":
+        pool = rng.integers(0, 1 << 63, size=5, dtype=np.uint64)
+        return pool[rng.integers(0, 5, size=n)]
+    if dist == "narrow":
+        return np.uint64(1 << 50) + rng.integers(0, 3000, size=n, dtype=np.uint64)
+    raise ValueError(dist)
+
+
+def seg_offsets(sizes):
+    return np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+
+
+def fit_models(K, keys, off):
+    """Sort with the radix path, then fit per-segment models on the GPU."""
+    sk, _ = K.kpa_sort_segmented(dev_u64(keys), dev_u32(np.arange(len(keys), dtype=np.uint32)),
+                                 dev_u64(off))
+    return K.kpa_pwl_fit(sk, dev_u64(off), 1024), sk
+
+
+def check_learned(K, orc, keys, rids, off, models):
+    stats = K.new_sort_stats("cuda")
+    ok, orr = K.kpa_sort_segmented(dev_u64(keys), dev_u32(rids), dev_u64(off),
+                                   algo=K.KPA_SORT_LEARNED, models=models, stats=stats)
+    torch.cuda.synchronize()
+    ek, er = orc.sort_segmented(keys, rids, off)
+    assert np.array_equal(u64(ok), ek), "keys differ from the oracle"
+    assert np.array_equal(u32(orr), er), "rids (tie order) differ from the oracle"
+    st = stats.cpu().numpy()
+    # every entry is accounted for once: on chip, single-key chunk, or fallback
+    assert int(st[1] + st[2] + st[3]) == len(keys), st
+    return st
+
+
+def test_pwl_fit_matches_oracle(K, orc):
+    rng = np.random.default_rng(1)
+    sizes = [0, 1, 2, 1000, 4097, 100000, 7]
+    off = seg_offsets(sizes)
+    keys = np.concatenate([np.sort(gen_keys(d, s, i)) for i, (d, s) in enumerate(
+        zip(["uniform64", "few", "narrow", "zipf_mix", "zipf_rank", "uniform64", "narrow"],
+            sizes))])
+    for S in (1, 7, 1024):
+        say(f"pwl_fit S={S}")
+        models = K.kpa_pwl_fit(dev_u64(keys), dev_u64(off), S)
+        torch.cuda.synchronize()
+        got = K.model_fields(models)
+        for s, (a, b) in enumerate(zip(off[:-1], off[1:])):
+            a, b = int(a), int(b)
+            kmin, kmax, ns, knots = got[s]
+            if b == a:
+                assert ns == 0
+                continue
+            ekmin, ekmax, eknots = orc.pwl_fit(keys[a:b], S)
+            assert (kmin, kmax, ns) == (ekmin, ekmax, S)
+            assert np.array_equal(knots, eknots)   # bit-exact floats
+
+
+@pytest.mark.parametrize("dist", ["uniform64", "zipf_mix", "zipf_rank", "few", "narrow"])
+@pytest.mark.parametrize("n", [3000, 70001, 1 << 20])
+def test_learned_sort_with_fitted_model(K, orc, dist, n):
+    keys = gen_keys(dist, n, 11)
+    rids = np.arange(n, dtype=np.uint32)
+    off = seg_offsets([n])
+    say(f"learned {dist} n={n} (model from the same data)")
+    models, _ = fit_models(K, keys, off)
+    st = check_learned(K, orc, keys, rids, off, models)
+    if dist in ("uniform64", "narrow") and n >= 70001:
+        assert st[1] > 0.9 * n   # a good model finishes nearly everything on chip
+    # drifted: the model comes from another draw of the distribution
+    keys2 = gen_keys(dist, n, 12)
+    if dist == "zipf_rank":
+        keys2 = keys2 + np.uint64(1 << 26)      # key offset drift between windows
+    say(f"learned {dist} n={n} (model from an earlier window)")
+    check_learned(K, orc, keys2, rids, off, models)
+
+
+def test_learned_sort_segmented_ragged(K, orc):
+    rng = np.random.default_rng(3)
+    sizes = [0, 5, 4096, 4097, 0, 150000, 1, 33333, 8192, 0, 600001]
+    dists = ["uniform64", "few", "zipf_mix", "narrow", "uniform64", "zipf_rank", "few",
+             "uniform64", "zipf_mix", "narrow", "zipf_rank"]
+    keys = np.concatenate([gen_keys(d, s, 20 + i) for i, (d, s) in enumerate(zip(dists, sizes))])
+    rids = rng.permutation(len(keys)).astype(np.uint32)
+    off = seg_offsets(sizes)
+    models, _ = fit_models(K, keys, off)
+    keys2 = np.concatenate([gen_keys(d, s, 40 + i) for i, (d, s) in enumerate(zip(dists, sizes))])
+    say("learned segmented ragged")
+    check_learned(K, orc, keys2, rids, off, models)
+
+
+def test_forced_overflow_constant_model(K, orc):
+    """All knots 0: every key lands in bucket 0 -> the whole segment overflows."""
+    n = 200003
+    keys = gen_keys("uniform64", n, 5)
+    off = seg_offsets([n])
+    models, _ = fit_models(K, keys, off)
+    raw = models.view(torch.uint8)
+    knots = raw[24:24 + 4 * 1025].view(torch.float32)
+    knots.zero_()
+    say("forced overflow")
+    st = check_learned(K, orc, keys, np.arange(n, dtype=np.uint32), off, models)
+    # all but the one maximal key overflow; the pivot split settles one more
+    assert st[3] >= n - 2 and st[4] >= 1
+
+
+@pytest.mark.parametrize("bad", ["decreasing", "nan", "above_one"])
+def test_invalid_model_detected(K, orc, bad):
+    n = 100001
+    keys = gen_keys("uniform64", n, 6)
+    off = seg_offsets([n])
+    models, _ = fit_models(K, keys, off)
+    knots = models.view(torch.uint8)[24:24 + 4 * 1025].view(torch.float32)
+    if bad == "decreasing":
+        knots[500] = 0.9
+        knots[501] = 0.1
+    elif bad == "nan":
+        knots[10] = float("nan")
+    else:
+        knots[1024] = 1.5
+    say(f"invalid model {bad}")
+    st = check_learned(K, orc, keys, np.arange(n, dtype=np.uint32), off, models)
+    assert st[5] == 1   # order violation counted
+
+
+def test_learned_equals_radix_bytes(K, orc):
+    """Cross-algorithm equality on a C2-shaped window set."""
+    rows = datagen.gen_c2(1 << 21, seed=8, n_keys=1 << 16, span_ns=10 ** 6)
+    from datagen.rows import LAYOUT32
+    d = rows.cuda()
+    keys, rids, woff, _ = K.kpa_partition_windows(d, LAYOUT32, 10 ** 5, 10)
+    rk, rr = K.kpa_sort_segmented(keys, rids, woff, algo=K.KPA_SORT_RADIX)
+    models = K.kpa_pwl_fit(rk, woff, 1024)
+    rows2 = datagen.gen_c2(1 << 21, seed=9, n_keys=1 << 16, span_ns=10 ** 6)
+    d2 = rows2.cuda()
+    keys2, rids2, woff2, _ = K.kpa_partition_windows(d2, LAYOUT32, 10 ** 5, 10)
+    say("learned vs radix bytes")
+    lk, lr = K.kpa_sort_segmented(keys2, rids2, woff2, algo=K.KPA_SORT_LEARNED, models=models)
+    rk2, rr2 = K.kpa_sort_segmented(keys2, rids2, woff2, algo=K.KPA_SORT_RADIX)
+    torch.cuda.synchronize()
+    assert torch.equal(lk, rk2) and torch.equal(lr, rr2)
