@@ -1,0 +1,228 @@
+// Merge (Table 2: two sorted KPAs -> one sorted KPA, sequential access).
+//
+// Merge path (Green, McColl & Bader, 2012): output position d of the merge is
+// reached after taking i entries of A and d - i of B, where i is found by a
+// binary search along the cross diagonal.  One kernel computes the split at
+// every 4096-entry output tile boundary; a second loads each tile's A and B
+// ranges into LDS, lets each thread find its own 16-output split inside them
+// and merge sequentially, then writes the tile out coalesced.  Stable: on
+// equal keys A's entries come first.
+#include <vector>
+
+#include "kpa_internal.hpp"
+
+namespace kpa {
+
+// Number of A entries among the first d outputs (ties taken from A first).
+__device__ __forceinline__ u64 merge_split(const u64* a, u64 na, const u64* b, u64 nb, u64 d) {
+  u64 lo = d > nb ? d - nb : 0, hi = d < na ? d : na;
+  while (lo < hi) {
+    const u64 mid = (lo + hi) >> 1;
+    if (a[mid] <= b[d - mid - 1]) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ void __launch_bounds__(BLOCK) k_merge_splits(const u64* __restrict__ a, u64 na,
+                                                        const u64* __restrict__ b, u64 nb,
+                                                        u64 n_tiles, u64* __restrict__ split) {
+  const u64 t = (u64)blockIdx.x * BLOCK + threadIdx.x;
+  if (t > n_tiles) return;
+  const u64 d = min(t * (u64)TILE, na + nb);
+  split[t] = merge_split(a, na, b, nb, d);
+}
+
+struct MergeSmem {
+  u64 k[TILE];
+  u32 r[TILE];
+};
+
+__global__ void __launch_bounds__(BLOCK) k_merge_tiles(const u64* __restrict__ ak,
+                                                       const u32* __restrict__ ar, u64 na,
+                                                       const u64* __restrict__ bk,
+                                                       const u32* __restrict__ br, u64 nb,
+                                                       const u64* __restrict__ split,
+                                                       u64* __restrict__ ok, u32* __restrict__ orr) {
+  __shared__ MergeSmem sm;
+  const u64 t = blockIdx.x;
+  const u64 d0 = t * TILE, d1 = min(d0 + TILE, na + nb);
+  const u64 i0 = split[t], i1 = split[t + 1];
+  const u64 j0 = d0 - i0, j1 = d1 - i1;
+  const u32 la = (u32)(i1 - i0), lb = (u32)(j1 - j0);
+  // A part at [0, la), B part at [la, la + lb)
+  for (u32 x = threadIdx.x; x < la; x += BLOCK) {
+    sm.k[x] = ak[i0 + x];
+    sm.r[x] = ar[i0 + x];
+  }
+  for (u32 x = threadIdx.x; x < lb; x += BLOCK) {
+    sm.k[la + x] = bk[j0 + x];
+    sm.r[la + x] = br[j0 + x];
+  }
+  __syncthreads();
+  const u64* A = sm.k;
+  const u64* B = sm.k + la;
+  const u32 dd = min((u32)threadIdx.x * ITEMS, la + lb);
+  u32 lo = dd > lb ? dd - lb : 0, hi = dd < la ? dd : la;
+  while (lo < hi) {
+    const u32 mid = (lo + hi) >> 1;
+    if (A[mid] <= B[dd - mid - 1]) lo = mid + 1; else hi = mid;
+  }
+  u32 ia = lo, ib = dd - lo;
+  u64 outk[ITEMS];
+  u32 outr[ITEMS];
+#pragma unroll
+  for (int q = 0; q < ITEMS; ++q) {
+    const bool takea = ib >= lb || (ia < la && A[ia] <= B[ib]);
+    const u32 src = takea ? ia : la + ib;
+    outk[q] = src < la + lb ? sm.k[src] : 0ull;
+    outr[q] = src < la + lb ? sm.r[src] : 0u;
+    ia += takea;
+    ib += !takea;
+  }
+  __syncthreads();
+  const u32 n = (u32)(d1 - d0);
+#pragma unroll
+  for (int q = 0; q < ITEMS; ++q) {
+    const u32 o = threadIdx.x * ITEMS + q;
+    if (o < n) {
+      sm.k[o] = outk[q];
+      sm.r[o] = outr[q];
+    }
+  }
+  __syncthreads();
+  for (u32 x = threadIdx.x; x < n; x += BLOCK) {
+    ok[d0 + x] = sm.k[x];
+    orr[d0 + x] = sm.r[x];
+  }
+}
+
+__global__ void __launch_bounds__(BLOCK) k_copy_kpa(const u64* __restrict__ k, const u32* __restrict__ r,
+                                                    u64 n, u64* __restrict__ ok,
+                                                    u32* __restrict__ orr) {
+  for (u64 i = (u64)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (u64)gridDim.x * BLOCK) {
+    ok[i] = k[i];
+    orr[i] = r[i];
+  }
+}
+
+kpa_status merge_launch(const u64* ak, const u32* ar, u64 na, const u64* bk, const u32* br, u64 nb,
+                        u64* ok, u32* orr, u64* split, hipStream_t st) {
+  const u64 n = na + nb;
+  if (n == 0) return KPA_OK;
+  const u64 tiles = ceil_div(n, TILE);
+  KPA_LAUNCH("merge_splits", k_merge_splits, dim3((u32)ceil_div(tiles + 1, BLOCK)), dim3(BLOCK), 0,
+             st, ak, na, bk, nb, tiles, split);
+  KPA_LAUNCH("merge_tiles", k_merge_tiles, dim3((u32)tiles), dim3(BLOCK), 0, st, ak, ar, na, bk, br,
+             nb, split, ok, orr);
+  return KPA_OK;
+}
+
+}  // namespace kpa
+
+using namespace kpa;
+
+extern "C" {
+
+kpa_status kpa_merge_workspace_size(uint64_t na, uint64_t nb, size_t* bytes) {
+  clear_error();
+  KPA_REQUIRE(bytes, KPA_EINVAL, "bytes is null");
+  *bytes = (ceil_div(na + nb, TILE) + 2) * sizeof(u64) + 256;
+  return KPA_OK;
+}
+
+kpa_status kpa_merge(const uint64_t* a_keys, const uint32_t* a_rids, uint64_t na,
+                     const uint64_t* b_keys, const uint32_t* b_rids, uint64_t nb,
+                     uint64_t* out_keys, uint32_t* out_rids, void* ws, size_t ws_bytes,
+                     hipStream_t stream) {
+  clear_error();
+  if (na + nb == 0) return KPA_OK;
+  KPA_REQUIRE((na == 0 || (a_keys && a_rids)) && (nb == 0 || (b_keys && b_rids)) && out_keys &&
+                  out_rids && ws,
+              KPA_EINVAL, "null pointer");
+  KPA_REQUIRE(aligned(ws, 8) && aligned(out_keys, 8) && aligned(out_rids, 4) &&
+                  (na == 0 || (aligned(a_keys, 8) && aligned(a_rids, 4))) &&
+                  (nb == 0 || (aligned(b_keys, 8) && aligned(b_rids, 4))),
+              KPA_EINVAL, "misaligned pointer");
+  KPA_REQUIRE(out_keys != a_keys && out_keys != b_keys, KPA_EINVAL, "outputs alias inputs");
+  size_t need = 0;
+  kpa_merge_workspace_size(na, nb, &need);
+  KPA_REQUIRE(ws_bytes >= need, KPA_EWORKSPACE, "workspace too small: need %zu bytes", need);
+  return merge_launch(a_keys, a_rids, na, b_keys, b_rids, nb, out_keys, out_rids,
+                      static_cast<u64*>(ws), stream);
+}
+
+kpa_status kpa_merge_runs_workspace_size(uint64_t n, size_t* bytes) {
+  clear_error();
+  KPA_REQUIRE(bytes, KPA_EINVAL, "bytes is null");
+  Carver c(nullptr);
+  c.take<u64>(n);
+  c.take<u32>(n);
+  c.take<u64>(ceil_div(n, TILE) + 2);
+  *bytes = c.used + 256;
+  return KPA_OK;
+}
+
+// Pairwise rounds: runs 2k and 2k+1 merge into run k of the next round (an
+// unpaired last run is carried over), alternating between the caller's arrays
+// and a workspace copy; the last round writes the output.
+kpa_status kpa_merge_runs(uint64_t* keys, uint32_t* rids, const uint64_t* run_off, uint32_t n_runs,
+                          uint64_t* out_keys, uint32_t* out_rids, void* ws, size_t ws_bytes,
+                          hipStream_t stream) {
+  clear_error();
+  KPA_REQUIRE(run_off != nullptr, KPA_EINVAL, "run_off is null");
+  if (n_runs == 0) return KPA_OK;
+  const u64 n = run_off[n_runs] - run_off[0];
+  for (u32 r = 0; r < n_runs; ++r)
+    KPA_REQUIRE(run_off[r + 1] >= run_off[r], KPA_EINVAL, "run offsets decrease");
+  if (n == 0) return KPA_OK;
+  KPA_REQUIRE(keys && rids && out_keys && out_rids && ws, KPA_EINVAL, "null pointer");
+  KPA_REQUIRE(aligned(ws, 256), KPA_EINVAL, "misaligned workspace");
+  size_t need = 0;
+  kpa_merge_runs_workspace_size(n, &need);
+  KPA_REQUIRE(ws_bytes >= need, KPA_EWORKSPACE, "workspace too small: need %zu bytes", need);
+  Carver c(ws);
+  u64* tk = c.take<u64>(n);
+  u32* tr = c.take<u32>(n);
+  u64* split = c.take<u64>(ceil_div(n, TILE) + 2);
+  const u64 base = run_off[0];
+  std::vector<u64> off(run_off, run_off + n_runs + 1);
+  for (auto& o : off) o -= base;
+  u64* ck = keys + base;
+  u32* cr = rids + base;
+  if (n_runs == 1) {
+    KPA_LAUNCH("copy_kpa", k_copy_kpa, dim3((u32)std::min<u64>(ceil_div(n, BLOCK), 8192)),
+               dim3(BLOCK), 0, stream, ck, cr, n, out_keys, out_rids);
+    return KPA_OK;
+  }
+  // buffers: current source, and the next destination
+  u64* src_k = ck;
+  u32* src_r = cr;
+  bool src_is_ws = false;
+  while (off.size() > 2) {
+    const size_t runs = off.size() - 1;
+    const bool last = runs <= 2;
+    u64* dst_k = last ? out_keys : (src_is_ws ? ck : tk);
+    u32* dst_r = last ? out_rids : (src_is_ws ? cr : tr);
+    std::vector<u64> next{0};
+    for (size_t p = 0; p < runs; p += 2) {
+      const u64 a0 = off[p], a1 = off[p + 1];
+      if (p + 1 < runs) {
+        const u64 b1 = off[p + 2];
+        KPA_CHECK(merge_launch(src_k + a0, src_r + a0, a1 - a0, src_k + a1, src_r + a1, b1 - a1,
+                               dst_k + a0, dst_r + a0, split, stream));
+        next.push_back(b1);
+      } else {
+        KPA_LAUNCH("copy_kpa", k_copy_kpa, dim3((u32)std::min<u64>(ceil_div(a1 - a0, BLOCK), 8192)),
+                   dim3(BLOCK), 0, stream, src_k + a0, src_r + a0, a1 - a0, dst_k + a0, dst_r + a0);
+        next.push_back(a1);
+      }
+    }
+    off.swap(next);
+    src_k = dst_k;
+    src_r = dst_r;
+    src_is_ws = !src_is_ws;
+  }
+  return KPA_OK;
+}
+
+}  // extern "C"

@@ -434,7 +434,7 @@ def kpa_mlp_adam_step(params, grad, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, ep
 def kpa_mlp_train(params, m, v, x, y, t0, steps, lr=1e-3, ws=None, stream=None):
     n = x.numel()
     loss = torch.empty(1, dtype=torch.float32, device=x.device)
-    nb = _ws_size("kpa_mlp_loss_grad_workspace_size", n)
+    nb = _ws_size("kpa_mlp_loss_grad_workspace_size", n) + 4 * KPA_MLP_PARAMS + 512
     ws = _ws(nb, x.device, ws)
     _call("kpa_mlp_train", _p(params), _p(m), _p(v), _p(x), _p(y), n, t0, steps, lr, _p(loss),
           _p(ws), ws.numel() * ws.element_size(), _stream(stream))

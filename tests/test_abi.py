@@ -47,7 +47,7 @@ def test_host_side_errors_without_gpu():
     L = k.kpa_row_layout(32, 0, 8, 8, 16, 8)
     # n_win out of range, before anything is enqueued
     rc = lib.kpa_partition_windows(None, 0, ctypes.byref(L), 10, 0, 0, 0, None, None, None, None,
-                                   None, 0, None)
+                                   None, None, 0, None)
     assert rc == k.KPA_EUNSUPPORTED
     bad = k.kpa_row_layout(30, 0, 8, 8, 16, 8)
     rc = lib.kpa_extract(None, 5, ctypes.byref(bad), 0, None, None, None)

@@ -1,0 +1,183 @@
+"""GPU parity: merge, multiway merge, join (count, sum of products, pairs) and
+median per key, element by element against the CPU oracle."""
+import numpy as np
+import pytest
+import torch
+
+import datagen
+from datagen.rows import LAYOUT16, LAYOUT32
+from gpu_util import dev_u32, dev_u64, kpa_mod, need_gpu, say, u32, u64
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def K():
+    need_gpu()
+    return kpa_mod()
+
+
+def sorted_kpa(orc, rng, n, pool_size, rid0=0):
+    pool = rng.integers(0, 1 << 63, size=max(pool_size, 1), dtype=np.uint64) * np.uint64(2)
+    keys = pool[rng.integers(0, len(pool), size=n)]
+    rids = np.arange(rid0, rid0 + n, dtype=np.uint32)
+    return orc.sort(keys, rids)
+
+
+@pytest.mark.parametrize("na,nb", [(0, 5), (7, 0), (1, 1), (4096, 4096), (5000, 123),
+                                   (100003, 77777), (300000, 1)])
+def test_merge(K, orc, na, nb):
+    rng = np.random.default_rng(na * 7 + nb)
+    pool = 50 if na + nb > 1000 else 5     # many equal keys across A and B
+    ak, ar = sorted_kpa(orc, rng, na, pool, 0)
+    bk, br = sorted_kpa(orc, rng, nb, pool, na)
+    say(f"merge {na}+{nb}")
+    ok, orr = K.kpa_merge(dev_u64(ak), dev_u32(ar), dev_u64(bk), dev_u32(br))
+    torch.cuda.synchronize()
+    ek, er = orc.merge(ak, ar, bk, br)
+    assert np.array_equal(u64(ok)[:na + nb], ek) and np.array_equal(u32(orr)[:na + nb], er)
+
+
+@pytest.mark.parametrize("sizes", [[10], [3, 0, 9], [4096] * 7, [0, 50000, 1, 0, 7777, 30000, 2],
+                                   [1000] * 16])
+def test_merge_runs(K, orc, sizes):
+    rng = np.random.default_rng(len(sizes))
+    ks, rs = [], []
+    base = 0
+    for s in sizes:
+        k, r = sorted_kpa(orc, rng, s, 200, base)
+        ks.append(k)
+        rs.append(r)
+        base += s
+    keys = np.concatenate(ks) if ks else np.zeros(0, np.uint64)
+    rids = np.concatenate(rs) if rs else np.zeros(0, np.uint32)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    say(f"merge_runs {sizes}")
+    ok, orr = K.kpa_merge_runs(dev_u64(keys), dev_u32(rids), off.tolist())
+    torch.cuda.synchronize()
+    ek, er = orc.sort(keys, rids)   # stable: equal keys keep run order
+    n = int(off[-1])
+    assert np.array_equal(u64(ok)[:n], ek) and np.array_equal(u32(orr)[:n], er)
+
+
+def windows(K, rows, layout, W, nw):
+    keys, rids, off, oob = K.kpa_partition_windows(rows, layout, W, nw)
+    sk, sr = K.kpa_sort_segmented(keys, rids, off, n_cap=keys.numel())
+    return sk, sr, off
+
+
+def c3_rows(n, side, n_keys, seed=3, span=10 ** 6):
+    return datagen.gen_c3(n, seed=seed, side=side, n_keys=n_keys, span_ns=span)
+
+
+@pytest.mark.parametrize("n,n_keys", [(1, 3), (5000, 1 << 20), (70001, 30000), (200000, 1 << 24),
+                                      (40000, 7)])
+def test_join_count_sumprod(K, orc, n, n_keys):
+    W, nw = 10 ** 5, 10
+    L = c3_rows(n, 0, n_keys)
+    R = c3_rows(n + 17, 1, n_keys)
+    dl, dr = L.cuda(), R.cuda()
+    lk, lr, loff = windows(K, dl, LAYOUT32, W, nw)
+    rk, rr, roff = windows(K, dr, LAYOUT32, W, nw)
+    say(f"join n={n} keys={n_keys}")
+    cnt, sp, _, npairs = K.kpa_join(lk, lr, loff, rk, rr, roff, dl, dr, LAYOUT32)
+    torch.cuda.synchronize()
+    hl = orc.partition(L, LAYOUT32, W, nw)
+    hr = orc.partition(R, LAYOUT32, W, nw)
+    tot = 0
+    for w in range(nw):
+        a0, a1 = int(hl[2][w]), int(hl[2][w + 1])
+        b0, b1 = int(hr[2][w]), int(hr[2][w + 1])
+        ec, es, _, enp = orc.join(hl[0][a0:a1], hl[1][a0:a1], hr[0][b0:b1], hr[1][b0:b1], L, R,
+                                  LAYOUT32)
+        assert int(u64(cnt)[w]) == ec and int(u64(sp)[w]) == es
+        tot += ec
+    assert int(u64(npairs)[0]) == tot
+
+
+def test_join_pairs_with_heavy_key_and_capacity(K, orc):
+    W, nw = 10 ** 5, 4
+    n = 20000
+    L = c3_rows(n, 0, 500)
+    R = c3_rows(n, 1, 500)
+    L[::3, 0] = R[0, 0]          # one key heavy on both sides
+    R[::5, 0] = R[0, 0]
+    dl, dr = L.cuda(), R.cuda()
+    lk, lr, loff = windows(K, dl, LAYOUT32, W, nw)
+    rk, rr, roff = windows(K, dr, LAYOUT32, W, nw)
+    hl = orc.partition(L, LAYOUT32, W, nw)
+    hr = orc.partition(R, LAYOUT32, W, nw)
+    exp_pairs, exp_cnt = [], []
+    for w in range(nw):
+        a0, a1 = int(hl[2][w]), int(hl[2][w + 1])
+        b0, b1 = int(hr[2][w]), int(hr[2][w + 1])
+        ec, es, pairs, enp = orc.join(hl[0][a0:a1], hl[1][a0:a1], hr[0][b0:b1], hr[1][b0:b1], L, R,
+                                      LAYOUT32, pairs_cap=10 ** 7)
+        exp_pairs.append(pairs)
+        exp_cnt.append(ec)
+    exp = np.concatenate(exp_pairs)
+    total = len(exp)
+    say(f"join pairs total={total}")
+    cnt, sp, pairs, npairs = K.kpa_join(lk, lr, loff, rk, rr, roff, dl, dr, LAYOUT32,
+                                        pairs_cap=total + 5)
+    torch.cuda.synchronize()
+    assert int(u64(npairs)[0]) == total == sum(exp_cnt)
+    assert np.array_equal(u64(pairs)[:total], exp)
+    # a capacity below the total: the first `cap` pairs are written, the total reported
+    cap = total // 3
+    cnt, sp, pairs, npairs = K.kpa_join(lk, lr, loff, rk, rr, roff, dl, dr, LAYOUT32,
+                                        pairs_cap=cap)
+    torch.cuda.synchronize()
+    assert int(u64(npairs)[0]) == total
+    assert np.array_equal(u64(pairs)[:cap], exp[:cap])
+
+
+def test_join_no_match_and_empty_windows(K, orc):
+    W, nw = 10 ** 5, 6
+    L = c3_rows(3000, 0, 1 << 24, seed=1, span=3 * 10 ** 5)   # windows 3..5 empty
+    R = c3_rows(3000, 1, 1 << 24, seed=2, span=3 * 10 ** 5)
+    L[:, 0] |= 1     # odd keys on the left,
+    R[:, 0] &= ~1    # even keys on the right: no match anywhere
+    dl, dr = L.cuda(), R.cuda()
+    lk, lr, loff = windows(K, dl, LAYOUT32, W, nw)
+    rk, rr, roff = windows(K, dr, LAYOUT32, W, nw)
+    cnt, sp, _, npairs = K.kpa_join(lk, lr, loff, rk, rr, roff, dl, dr, LAYOUT32)
+    torch.cuda.synchronize()
+    assert u64(cnt).tolist() == [0] * nw and u64(sp).tolist() == [0] * nw
+    assert int(u64(npairs)[0]) == 0
+
+
+def median_expect(orc, keys, rids, off, rows, layout):
+    gk, gm, goff = [], [], [0]
+    for a, b in zip(off[:-1], off[1:]):
+        k, m = orc.median_by_key(keys[int(a):int(b)], rids[int(a):int(b)], rows, layout)
+        gk.append(k)
+        gm.append(m)
+        goff.append(goff[-1] + len(k))
+    return np.concatenate(gk), np.concatenate(gm), np.array(goff, np.uint64)
+
+
+@pytest.mark.parametrize("case", ["uniform", "medium_runs", "big_runs", "u32_values"])
+def test_median_by_key(K, orc, case):
+    W, nw = 10 ** 5, 10
+    if case == "uniform":
+        rows, lay = c3_rows(150001, 0, 1 << 17), LAYOUT32
+    elif case == "medium_runs":
+        rows, lay = c3_rows(150001, 0, 400), LAYOUT32
+    elif case == "big_runs":
+        rows, lay = c3_rows(150001, 0, 2), LAYOUT32
+        rows[::7, 1] = 12345        # repeated values inside big runs
+    else:
+        rows, lay = datagen.gen_c1(100001, seed=5), LAYOUT16
+        W, nw = 100, 10
+    d = rows.cuda()
+    sk, sr, off = windows(K, d, lay, W, nw)
+    say(f"median {case}")
+    gk, gm, gseg = K.kpa_median_by_key(sk, sr, off, d, lay)
+    torch.cuda.synchronize()
+    hk, hr, hoff, _ = orc.partition(rows, lay, W, nw)
+    ek, em, eoff = median_expect(orc, hk, hr, hoff, rows, lay)
+    assert np.array_equal(u64(gseg), eoff)
+    g = int(eoff[-1])
+    assert np.array_equal(u64(gk)[:g], ek)
+    assert np.array_equal(u64(gm)[:g], em)
