@@ -45,6 +45,8 @@ def parse():
                     help="rows of the oracle's CPU-baseline sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--probe-copy-mib", type=int, default=0,
+                    help="first copy this many MiB device-to-device (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
@@ -65,6 +67,12 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if a.probe_copy_mib:
+        src = torch.empty(a.probe_copy_mib << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     n = a.rows
     n_win, W = 10, 10 ** 9
     t0 = time.time()

@@ -236,7 +236,11 @@ kpa_status digit_sort_launch(const SegList& sl, const typename DF::Params& prm,
     KPA_LAUNCH(radix ? "radix_scan" : "learned_scan", k_ds_scan<DF>,
                dim3(std::min<u32>(sl.n_max, 2048)), dim3(BLOCK), 0, st, sl, b.hist, b.seg_mask);
   }
+#ifdef KPA_ONE_TILE_PER_BLOCK
+  const u32 grid = (u32)b.max_tiles;
+#else
   const u32 grid = resident_grid(k_ds_pass<DF>, (u32)std::min<u64>(b.max_tiles, 1u << 20));
+#endif
   const char* pname = radix ? "radix_pass" : (DF::PASSES == 2 ? "learned_scatter" : "pivot_scatter");
   for (u32 p = 0; p < (u32)DF::PASSES; ++p) {
     u32* cur = (p & 1) ? b.status1 : b.status0;

@@ -88,7 +88,10 @@ struct Carver {
 // ------------------------------------------------------------- constants --
 constexpr int BLOCK = 256;           // threads per workgroup (4 waves of 64)
 constexpr int WAVES = BLOCK / 64;
-constexpr int ITEMS = 16;            // entries per thread in a tile
+#ifndef KPA_ITEMS
+#define KPA_ITEMS 16
+#endif
+constexpr int ITEMS = KPA_ITEMS;     // entries per thread in a tile
 constexpr int TILE = BLOCK * ITEMS;  // 4096 entries per tile
 constexpr u32 ST_AGG = 1u << 30;     // look-back word: tile aggregate ready
 constexpr u32 ST_PRE = 2u << 30;     // look-back word: inclusive prefix ready

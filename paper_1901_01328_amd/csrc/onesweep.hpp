@@ -13,7 +13,10 @@
 namespace kpa {
 
 constexpr int RADIX = 256;
-constexpr int LB_WINDOW = 16;  // look-back tiles probed per round trip
+#ifndef KPA_LB_WINDOW
+#define KPA_LB_WINDOW 16
+#endif
+constexpr int LB_WINDOW = KPA_LB_WINDOW;  // look-back tiles probed per round trip
 static_assert(RADIX == BLOCK, "one thread per digit");
 
 struct OnesweepSmem {
