@@ -174,6 +174,73 @@ kpa_status kpa_sort(const uint64_t* keys_in, const uint32_t* rids_in, uint64_t n
                     hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * Batched sort of many uneven segments (the windows of many substreams, all
+ * in flight at once; the paper gets its parallelism from many bundles and
+ * windows processed concurrently and out of order, Sec. 3).  Same contract
+ * as kpa_sort_segmented (stable; the output equals it byte for byte), with
+ * the segments split by size:
+ *   n <= small_cap           one workgroup sorts the segment in LDS;
+ *   small_cap < n <= mid_cap one workgroup runs the radix passes through
+ *                            device memory, with no cross-workgroup traffic;
+ *   n > mid_cap              the multi-workgroup path of large_algo
+ *                            (KPA_SORT_RADIX or KPA_SORT_LEARNED; models as
+ *                            in kpa_sort_segmented, used for these segments).
+ * A device-side work table (largest segments first) is drained by one
+ * persistent kernel; segment sizes are read from seg_off on the device only,
+ * so a captured graph of this call serves any segmentation with the same
+ * n_seg and n_cap.  small_cap <= 4096, small_cap <= mid_cap < 2^30; grid = 0
+ * sizes the persistent kernel to the workgroups resident at once. */
+typedef struct kpa_batch_config {
+  uint32_t small_cap;
+  uint32_t mid_cap;
+  uint32_t grid;
+  uint32_t large_algo; /* a kpa_sort_algo */
+} kpa_batch_config;
+
+/* small_cap 4096, mid_cap 65536, grid 0. */
+kpa_status kpa_batch_config_default(kpa_sort_algo large_algo, kpa_batch_config* cfg);
+kpa_status kpa_batch_sort_workspace_size(uint64_t n_cap, uint32_t n_seg,
+                                         const kpa_batch_config* cfg, size_t* bytes);
+kpa_status kpa_batch_sort(const uint64_t* keys_in, const uint32_t* rids_in, uint64_t* keys_out,
+                          uint32_t* rids_out, const uint64_t* seg_off, uint32_t n_seg,
+                          uint64_t n_cap, const kpa_batch_config* cfg,
+                          const kpa_pwl_model* models, kpa_sort_stats* stats, void* ws,
+                          size_t ws_bytes, hipStream_t stream);
+/* Autotuner: times kpa_batch_sort on the given batch (one warm-up and `reps`
+ * timed runs per candidate) over the class boundaries small_cap in {1024,
+ * 2048, 4096} and mid_cap in {small_cap, 2^14, 2^16, 2^18}, and returns the
+ * fastest configuration in *best (its mean time in *best_ms, may be NULL).
+ * cache_path (host file, may be NULL): a text file of earlier results keyed by
+ * the batch's signature (segment count, capacity, large_algo and a coarse
+ * histogram of segment sizes); a hit returns the stored result without timing,
+ * a miss appends the new one.  Synchronizes `stream` (reads seg_off to the
+ * host); not to be captured in a graph.  Workspace as kpa_batch_sort with the
+ * default configuration.  keys_out/rids_out hold the sorted batch on return
+ * unless the cache answered. */
+kpa_status kpa_batch_autotune(const uint64_t* keys_in, const uint32_t* rids_in,
+                              uint64_t* keys_out, uint32_t* rids_out, const uint64_t* seg_off,
+                              uint32_t n_seg, uint64_t n_cap, kpa_sort_algo large_algo,
+                              const kpa_pwl_model* models, void* ws, size_t ws_bytes,
+                              uint32_t reps, const char* cache_path, kpa_batch_config* best,
+                              float* best_ms, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Graph capture of a sequence of calls (launch overhead of a many-launch
+ * epoch paid once).  kpa_graph_begin starts capturing `stream` (not the null
+ * stream; per-kernel timing must be off); every library call enqueued on it
+ * until kpa_graph_end is recorded, not run.  kpa_graph_end instantiates the
+ * graph into *out (owned by the caller, freed by kpa_graph_destroy).
+ * kpa_graph_launch replays it on `stream`.  The library's launches take their
+ * sizes from device memory and record no memsets or host copies, so a replay
+ * reads the current contents of the same buffers; host-side arguments (n_cap,
+ * n_seg, pointers, configurations) are frozen at capture. */
+typedef struct kpa_graph_s* kpa_graph;
+kpa_status kpa_graph_begin(hipStream_t stream);
+kpa_status kpa_graph_end(hipStream_t stream, kpa_graph* out);
+kpa_status kpa_graph_launch(kpa_graph graph, hipStream_t stream);
+kpa_status kpa_graph_destroy(kpa_graph graph);
+
+/* ---------------------------------------------------------------------------
  * Merge (Table 2: two sorted KPAs -> one sorted KPA, sequential).  Stable: on
  * equal keys every entry of A precedes every entry of B.  All arrays device;
  * outputs hold na+nb entries and must not alias the inputs.

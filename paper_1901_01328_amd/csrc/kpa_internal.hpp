@@ -48,6 +48,7 @@ void clear_error();
     }                                                                                        \
   } while (0)
 
+bool prof_enabled();
 int prof_begin(const char* name, hipStream_t st);
 void prof_end(int slot, hipStream_t st);
 

@@ -21,6 +21,7 @@
 // The output equals the radix sort's byte for byte: both are the stable sort.
 #include "digit_sort.hpp"
 #include "learned_internal.hpp"
+#include "onchip_sort.hpp"
 
 namespace kpa {
 
@@ -59,12 +60,12 @@ __device__ __forceinline__ void stat_add(kpa_sort_stats* st, int idx, u64 v) {
 // One workgroup per segment (grid-stride): validate the model, choose the
 // bucket count.
 __global__ void __launch_bounds__(BLOCK) k_learned_setup(const kpa_pwl_model* __restrict__ models,
-                                                         const u64* __restrict__ seg_off,
-                                                         u32 n_seg, SegModel* __restrict__ segm,
+                                                         SegList sl, SegModel* __restrict__ segm,
                                                          kpa_sort_stats* stats) {
+  const u32 n_seg = sl.n();
   for (u32 s = blockIdx.x; s < n_seg; s += gridDim.x) {
     const kpa_pwl_model& M = models[s];
-    const u64 n = seg_off[s + 1] - seg_off[s];
+    const u64 n = sl.hi[s] - sl.lo[s];
     const u32 nseg = M.n_seg;
     bool ok = nseg >= 1 && nseg <= KPA_PWL_MAX_SEG && M.kmax >= M.kmin;
     if (ok) {
@@ -113,91 +114,6 @@ struct FinishSmem {
   u32 srel[FCAP];  // refined bucket id relative to the chunk's first bucket
   u32 flag;
 };
-
-__device__ __forceinline__ u32 block_min_u32(u32 v, u32* sm) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const u32 t = __shfl_xor(v, o, 64);
-    v = t < v ? t : v;
-  }
-  __syncthreads();
-  if (__lane_id() == 0) sm[threadIdx.x >> 6] = v;
-  __syncthreads();
-  u32 r = sm[0];
-  for (int i = 1; i < WAVES; ++i) r = sm[i] < r ? sm[i] : r;
-  __syncthreads();
-  return r;
-}
-
-__device__ __forceinline__ void block_or_and(u64& o, u64& a, u64* sm) {
-#pragma unroll
-  for (int s = 32; s > 0; s >>= 1) {
-    o |= __shfl_xor(o, s, 64);
-    a &= __shfl_xor(a, s, 64);
-  }
-  __syncthreads();
-  if (__lane_id() == 0) {
-    sm[threadIdx.x >> 6] = o;
-    sm[WAVES + (threadIdx.x >> 6)] = a;
-  }
-  __syncthreads();
-  o = sm[0];
-  a = sm[WAVES];
-  for (int i = 1; i < WAVES; ++i) {
-    o |= sm[i];
-    a &= sm[WAVES + i];
-  }
-  __syncthreads();
-}
-
-constexpr u32 NONE = 0xFFFFFFFFu;
-
-// Stable on-chip sort of the m <= FCAP entries held in sm.skeys/sm.srids
-// [0, m): LSD over the bytes that vary among the keys, one rank-and-move per
-// byte, data kept in LDS between passes.  Returns with the sorted entries in
-// sm (and false when nothing varied).
-__device__ bool lds_sort(FinishSmem& sm, u32 m) {
-  const u32 tid = threadIdx.x;
-  const u32 w = tid >> 6;
-  __syncthreads();
-  u64 vor = 0, vand = ~0ull;
-  for (u32 i = tid; i < m; i += BLOCK) {
-    vor |= sm.skeys[i];
-    vand &= sm.skeys[i];
-  }
-  block_or_and(vor, vand, sm.red64);
-  const u64 vary = vor ^ vand;
-  if (vary == 0) return false;
-  u32 valid = 0;
-#pragma unroll
-  for (int j = 0; j < ITEMS; ++j)
-    if (tile_offset(j) < m) valid |= 1u << j;
-#pragma unroll 1
-  for (u32 p = 0; p < 8; ++p) {
-    if (((vary >> (8 * p)) & 255u) == 0) continue;
-    u64 kk[ITEMS];
-    u32 rr[ITEMS], d[ITEMS], rank[ITEMS], tc;
-#pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-      const u32 o = tile_offset(j);
-      kk[j] = ((valid >> j) & 1) ? sm.skeys[o] : 0ull;
-      rr[j] = ((valid >> j) & 1) ? sm.srids[o] : 0u;
-      d[j] = (u32)(kk[j] >> (8 * p)) & 255u;
-    }
-    __syncthreads();
-    rank_tile(sm.whist, sm.lstart, sm.scan, d, valid, rank, &tc);
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < ITEMS; ++j)
-      if ((valid >> j) & 1) {
-        const u32 pos = sm.lstart[d[j]] + sm.whist[w][d[j]] + rank[j];
-        sm.skeys[pos] = kk[j];
-        sm.srids[pos] = rr[j];
-      }
-    __syncthreads();
-  }
-  return true;
-}
 
 // Stable on-chip sort of the chunk [0, m) in sm using the model once more:
 // entries are ranked by their refined bucket id (8 more bits of F, given in
@@ -368,17 +284,18 @@ __device__ __forceinline__ void load_knots(FinishSmem& sm, SegModel& m) {
 // chunk's buckets, so the bucket of every position never changes and the
 // edges found do not depend on timing.
 __global__ void __launch_bounds__(BLOCK, 2) k_learned_finish(
-    u64* __restrict__ keys, u32* __restrict__ rids, const u64* __restrict__ seg_off, u32 n_seg,
+    u64* __restrict__ keys, u32* __restrict__ rids, SegList sl,
     const u32* __restrict__ ftile_start, const SegModel* __restrict__ segm,
     u64* __restrict__ fb_lo, u64* __restrict__ fb_hi, u32* __restrict__ fb_count, u32 max_fb,
     kpa_sort_stats* stats) {
   __shared__ FinishSmem sm;
   const u32 tid = threadIdx.x;
   const u32 tile = blockIdx.x;
+  const u32 n_seg = sl.n();
   if (tile >= ftile_start[n_seg]) return;
   const u32 seg = find_seg(ftile_start, n_seg, tile);
   const u32 k = tile - ftile_start[seg];
-  const u64 a = seg_off[seg], b = seg_off[seg + 1];
+  const u64 a = sl.lo[seg], b = sl.hi[seg];
   const u64 pos0 = a + (u64)k * FH;
   if (pos0 >= b) return;
   SegModel m = segm[seg];
@@ -708,16 +625,14 @@ kpa_status learned_sort_plan(u64 n_cap, u32 n_seg, Carver& c, LearnedWs* w) {
 }
 
 kpa_status learned_sort_launch(const u64* keys_in, const u32* rids_in, u64* keys_out,
-                               u32* rids_out, const u64* seg_off, u32 n_seg, u64 n_cap,
-                               const kpa_pwl_model* models, kpa_sort_stats* stats,
-                               const LearnedWs& lw, hipStream_t st) {
-  (void)n_cap;
+                               u32* rids_out, const SegList& sl, const kpa_pwl_model* models,
+                               kpa_sort_stats* stats, const LearnedWs& lw, hipStream_t st) {
+  const u32 n_seg = sl.n_max;
   if (stats) KPA_CHECK(launch_fill_u64(reinterpret_cast<u64*>(stats), 6, 0, st));
   KPA_CHECK(launch_fill_u32(lw.fb_count, 1, 0, st));
   KPA_CHECK(launch_fill_u32(lw.rl_count, 4, 0, st));
   KPA_LAUNCH("learned_setup", k_learned_setup, dim3(std::min<u32>(n_seg, 2048)), dim3(BLOCK), 0,
-             st, models, seg_off, n_seg, lw.segm, stats);
-  const SegList sl = seg_list_from_offsets(seg_off, n_seg);
+             st, models, sl, lw.segm, stats);
   DigitSortBufs b{keys_in, rids_in, keys_out, rids_out, lw.keys_tmp, lw.rids_tmp, lw.hist,
                   lw.seg_mask, lw.ltile_start, lw.status0, lw.status1, lw.counters,
                   lw.max_tiles};
@@ -725,7 +640,7 @@ kpa_status learned_sort_launch(const u64* keys_in, const u32* rids_in, u64* keys
 
   KPA_CHECK(launch_seg_tiles_list(sl, FH, lw.ftile_start, st));
   KPA_LAUNCH("learned_finish", k_learned_finish, dim3((u32)lw.max_ftiles), dim3(BLOCK), 0, st,
-             keys_out, rids_out, seg_off, n_seg, lw.ftile_start, lw.segm, lw.fb_lo, lw.fb_hi,
+             keys_out, rids_out, sl, lw.ftile_start, lw.segm, lw.fb_lo, lw.fb_hi,
              lw.fb_count, lw.max_fb, stats);
 
   // Pivot rounds over the oversize chunks: round 0 reads the finishing pass's

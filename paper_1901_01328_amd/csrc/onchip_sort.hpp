@@ -1,0 +1,96 @@
+// Stable sort of up to one tile (4096 entries) held in on-chip memory, and the
+// block-wide reductions it uses.  Shared by the learned sort's finishing pass
+// and the batched small-segment path.
+#pragma once
+
+#include "onesweep.hpp"
+
+namespace kpa {
+
+__device__ __forceinline__ u32 block_min_u32(u32 v, u32* sm) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const u32 t = __shfl_xor(v, o, 64);
+    v = t < v ? t : v;
+  }
+  __syncthreads();
+  if (__lane_id() == 0) sm[threadIdx.x >> 6] = v;
+  __syncthreads();
+  u32 r = sm[0];
+  for (int i = 1; i < WAVES; ++i) r = sm[i] < r ? sm[i] : r;
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ void block_or_and(u64& o, u64& a, u64* sm) {
+#pragma unroll
+  for (int s = 32; s > 0; s >>= 1) {
+    o |= __shfl_xor(o, s, 64);
+    a &= __shfl_xor(a, s, 64);
+  }
+  __syncthreads();
+  if (__lane_id() == 0) {
+    sm[threadIdx.x >> 6] = o;
+    sm[WAVES + (threadIdx.x >> 6)] = a;
+  }
+  __syncthreads();
+  o = sm[0];
+  a = sm[WAVES];
+  for (int i = 1; i < WAVES; ++i) {
+    o |= sm[i];
+    a &= sm[WAVES + i];
+  }
+  __syncthreads();
+}
+
+constexpr u32 NONE = 0xFFFFFFFFu;
+
+// Stable on-chip sort of the m <= TILE entries held in sm.skeys/sm.srids
+// [0, m): LSD over the bytes that vary among the keys, one rank-and-move per
+// byte, data kept in LDS between passes.  Returns with the sorted entries in
+// sm (and false when nothing varied).
+template <class SM>
+__device__ bool lds_sort(SM& sm, u32 m) {
+  const u32 tid = threadIdx.x;
+  const u32 w = tid >> 6;
+  __syncthreads();
+  u64 vor = 0, vand = ~0ull;
+  for (u32 i = tid; i < m; i += BLOCK) {
+    vor |= sm.skeys[i];
+    vand &= sm.skeys[i];
+  }
+  block_or_and(vor, vand, sm.red64);
+  const u64 vary = vor ^ vand;
+  if (vary == 0) return false;
+  u32 valid = 0;
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j)
+    if (tile_offset(j) < m) valid |= 1u << j;
+#pragma unroll 1
+  for (u32 p = 0; p < 8; ++p) {
+    if (((vary >> (8 * p)) & 255u) == 0) continue;
+    u64 kk[ITEMS];
+    u32 rr[ITEMS], d[ITEMS], rank[ITEMS], tc;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      const u32 o = tile_offset(j);
+      kk[j] = ((valid >> j) & 1) ? sm.skeys[o] : 0ull;
+      rr[j] = ((valid >> j) & 1) ? sm.srids[o] : 0u;
+      d[j] = (u32)(kk[j] >> (8 * p)) & 255u;
+    }
+    __syncthreads();
+    rank_tile(sm.whist, sm.lstart, sm.scan, d, valid, rank, &tc);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j)
+      if ((valid >> j) & 1) {
+        const u32 pos = sm.lstart[d[j]] + sm.whist[w][d[j]] + rank[j];
+        sm.skeys[pos] = kk[j];
+        sm.srids[pos] = rr[j];
+      }
+    __syncthreads();
+  }
+  return true;
+}
+
+}  // namespace kpa

@@ -83,6 +83,41 @@ __device__ __forceinline__ u32 rank_tile(u32 (&whist)[WAVES][RADIX], u32* lstart
   return total;
 }
 
+// Moves a ranked tile (rank_tile's outputs still in sm.whist/sm.lstart)
+// through LDS in digit order, then writes each digit's entries contiguously
+// from sm.gbase[digit].  The caller has set sm.gbase and sm.count and passed
+// a barrier since.
+template <class SM>
+__device__ __forceinline__ void stage_scatter(SM& sm, const u64 (&k)[ITEMS], const u32 (&r)[ITEMS],
+                                              const u32 (&d)[ITEMS], const u32 (&rank)[ITEMS],
+                                              u32 valid, u64* __restrict__ keys_out,
+                                              u32* __restrict__ rids_out) {
+  const u32 tid = threadIdx.x;
+  const u32 w = tid >> 6;
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    if ((valid >> j) & 1) {
+      const u32 pos = sm.lstart[d[j]] + sm.whist[w][d[j]] + rank[j];
+      sm.skeys[pos] = k[j];
+      sm.srids[pos] = r[j];
+      sm.sdig[pos] = (unsigned char)d[j];
+    }
+  }
+  __syncthreads();
+
+  const u32 n = sm.count;
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    const u32 i = tid + j * BLOCK;
+    if (i < n) {
+      const u32 dd = sm.sdig[i];
+      const u64 dst = sm.gbase[dd] + (i - sm.lstart[dd]);
+      keys_out[dst] = sm.skeys[i];
+      rids_out[dst] = sm.srids[i];
+    }
+  }
+}
+
 // Ranks, publishes, looks back and scatters.  k/r/d hold this thread's items;
 // item j is present iff bit j of `valid` is set.  my_digit_base is, for the
 // digit equal to this thread's index, the global index where that digit of
@@ -146,29 +181,7 @@ __device__ __forceinline__ void onesweep_tile(OnesweepSmem& sm, const u64 (&k)[I
   if (tid == 0) sm.count = tile_count;
   __syncthreads();
 
-  // Stage the tile in digit order.
-#pragma unroll
-  for (int j = 0; j < ITEMS; ++j) {
-    if ((valid >> j) & 1) {
-      const u32 pos = sm.lstart[d[j]] + sm.whist[w][d[j]] + rank[j];
-      sm.skeys[pos] = k[j];
-      sm.srids[pos] = r[j];
-      sm.sdig[pos] = (unsigned char)d[j];
-    }
-  }
-  __syncthreads();
-
-  const u32 n = sm.count;
-#pragma unroll
-  for (int j = 0; j < ITEMS; ++j) {
-    const u32 i = tid + j * BLOCK;
-    if (i < n) {
-      const u32 dd = sm.sdig[i];
-      const u64 dst = sm.gbase[dd] + (i - sm.lstart[dd]);
-      keys_out[dst] = sm.skeys[i];
-      rids_out[dst] = sm.srids[i];
-    }
-  }
+  stage_scatter(sm, k, r, d, rank, valid, keys_out, rids_out);
 }
 
 }  // namespace kpa

@@ -34,6 +34,8 @@ hipEvent_t take_event() {
 }
 }  // namespace
 
+bool prof_enabled() { return g_on.load(std::memory_order_relaxed) != 0; }
+
 int prof_begin(const char* name, hipStream_t st) {
   if (!g_on.load(std::memory_order_relaxed)) return -1;
   std::lock_guard<std::mutex> lk(g_mu);

@@ -66,8 +66,9 @@ kpa_status kpa_sort_segmented(const uint64_t* keys_in, const uint32_t* rids_in,
                                 seg_list_from_offsets(seg_off, n_seg), rw, stream));
     if (stats) KPA_CHECK(launch_fill_u64(reinterpret_cast<u64*>(stats), 6, 0, stream));
   } else {
-    KPA_CHECK(learned_sort_launch(keys_in, rids_in, keys_out, rids_out, seg_off, n_seg, n_cap,
-                                  models, stats, lw, stream));
+    KPA_CHECK(learned_sort_launch(keys_in, rids_in, keys_out, rids_out,
+                                  seg_list_from_offsets(seg_off, n_seg), models, stats, lw,
+                                  stream));
   }
   return KPA_OK;
 }

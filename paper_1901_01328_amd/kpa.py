@@ -44,6 +44,14 @@ class KpaError(RuntimeError):
         self.code = code
 
 
+class kpa_batch_config(C.Structure):
+    _fields_ = [("small_cap", C.c_uint32), ("mid_cap", C.c_uint32), ("grid", C.c_uint32),
+                ("large_algo", C.c_uint32)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
 class kpa_row_layout(C.Structure):
     _fields_ = [("row_bytes", C.c_uint32), ("key_off", C.c_uint32), ("val_off", C.c_uint32),
                 ("val_w", C.c_uint32), ("ts_off", C.c_uint32), ("ts_w", C.c_uint32)]
@@ -72,6 +80,17 @@ _SIGS = {
     "kpa_sort_segmented": ([_vp, _vp, _vp, _vp, _vp, _u32, _u64, C.c_int, _vp, _vp, _vp,
                             C.c_size_t, _vp], C.c_int32),
     "kpa_sort": ([_vp, _vp, _u64, _vp, _vp, C.c_int, _vp, _vp, _vp, C.c_size_t, _vp], C.c_int32),
+    "kpa_batch_config_default": ([C.c_int, C.POINTER(kpa_batch_config)], C.c_int32),
+    "kpa_batch_sort_workspace_size": ([_u64, _u32, C.POINTER(kpa_batch_config), _sz], C.c_int32),
+    "kpa_batch_sort": ([_vp, _vp, _vp, _vp, _vp, _u32, _u64, C.POINTER(kpa_batch_config), _vp,
+                        _vp, _vp, C.c_size_t, _vp], C.c_int32),
+    "kpa_batch_autotune": ([_vp, _vp, _vp, _vp, _vp, _u32, _u64, C.c_int, _vp, _vp, C.c_size_t,
+                            _u32, C.c_char_p, C.POINTER(kpa_batch_config), C.POINTER(_f32), _vp],
+                           C.c_int32),
+    "kpa_graph_begin": ([_vp], C.c_int32),
+    "kpa_graph_end": ([_vp, C.POINTER(_vp)], C.c_int32),
+    "kpa_graph_launch": ([_vp, _vp], C.c_int32),
+    "kpa_graph_destroy": ([_vp], C.c_int32),
     "kpa_merge_workspace_size": ([_u64, _u64, _sz], C.c_int32),
     "kpa_merge": ([_vp, _vp, _u64, _vp, _vp, _u64, _vp, _vp, _vp, C.c_size_t, _vp], C.c_int32),
     "kpa_merge_runs_workspace_size": ([_u64, _sz], C.c_int32),
@@ -262,6 +281,119 @@ def kpa_sort(keys_in, rids_in, algo=KPA_SORT_RADIX, model=None, stats=None, keys
     return keys_out, rids_out
 
 
+def kpa_batch_config_default(large_algo=KPA_SORT_RADIX):
+    cfg = kpa_batch_config()
+    _call("kpa_batch_config_default", large_algo, C.byref(cfg))
+    return cfg
+
+
+def batch_config(small_cap=4096, mid_cap=1 << 16, grid=0, large_algo=KPA_SORT_RADIX):
+    return kpa_batch_config(small_cap, mid_cap, grid, large_algo)
+
+
+def kpa_batch_sort_workspace_size(n_cap, n_seg, cfg):
+    return _ws_size("kpa_batch_sort_workspace_size", n_cap, n_seg, C.byref(cfg))
+
+
+def kpa_batch_sort(keys_in, rids_in, seg_off, cfg=None, n_cap=None, models=None, stats=None,
+                   keys_out=None, rids_out=None, ws=None, stream=None):
+    _check(keys_in, torch.int64, "keys_in")
+    _check(rids_in, torch.int32, "rids_in")
+    cfg = kpa_batch_config_default() if cfg is None else cfg
+    n_seg = seg_off.numel() - 1
+    n_cap = keys_in.numel() if n_cap is None else n_cap
+    dev = keys_in.device
+    keys_out = torch.empty_like(keys_in) if keys_out is None else keys_out
+    rids_out = torch.empty_like(rids_in) if rids_out is None else rids_out
+    ws = _ws(kpa_batch_sort_workspace_size(n_cap, n_seg, cfg), dev, ws)
+    _call("kpa_batch_sort", _p(keys_in), _p(rids_in), _p(keys_out), _p(rids_out), _p(seg_off),
+          n_seg, n_cap, C.byref(cfg), _p(models), _p(stats), _p(ws),
+          ws.numel() * ws.element_size(), _stream(stream))
+    return keys_out, rids_out
+
+
+def kpa_batch_autotune(keys_in, rids_in, seg_off, large_algo=KPA_SORT_RADIX, n_cap=None,
+                       models=None, reps=2, cache_path=None, keys_out=None, rids_out=None,
+                       ws=None, stream=None):
+    """Returns (best kpa_batch_config, its mean milliseconds)."""
+    _check(keys_in, torch.int64, "keys_in")
+    _check(rids_in, torch.int32, "rids_in")
+    n_seg = seg_off.numel() - 1
+    n_cap = keys_in.numel() if n_cap is None else n_cap
+    dev = keys_in.device
+    keys_out = torch.empty_like(keys_in) if keys_out is None else keys_out
+    rids_out = torch.empty_like(rids_in) if rids_out is None else rids_out
+    ws = _ws(kpa_batch_sort_workspace_size(n_cap, n_seg, kpa_batch_config_default(large_algo)),
+             dev, ws)
+    best = kpa_batch_config()
+    ms = C.c_float(0.0)
+    _call("kpa_batch_autotune", _p(keys_in), _p(rids_in), _p(keys_out), _p(rids_out), _p(seg_off),
+          n_seg, n_cap, large_algo, _p(models), _p(ws), ws.numel() * ws.element_size(), reps,
+          None if cache_path is None else os.fsencode(cache_path), C.byref(best), C.byref(ms),
+          _stream(stream))
+    return best, float(ms.value)
+
+
+class Graph:
+    """A captured sequence of library calls (kpa_graph_*).  Use as
+    ``with Graph.capture(stream) as g: ...calls on stream...`` then
+    ``g.launch(stream)``.  Buffers used inside must outlive the graph."""
+
+    def __init__(self):
+        self.h = C.c_void_p(None)
+        self._stream = None
+
+    @classmethod
+    def capture(cls, stream):
+        g = cls()
+        g._stream = stream
+        return g
+
+    def __enter__(self):
+        _call("kpa_graph_begin", _stream(self._stream))
+        return self
+
+    def __exit__(self, et, ev, tb):
+        h = C.c_void_p(None)
+        rc = _lib.kpa_graph_end(_stream(self._stream), C.byref(h))
+        self.h = h
+        if et is None and rc != KPA_OK:
+            raise KpaError("kpa_graph_end", rc)
+        return False
+
+    def launch(self, stream=None):
+        _call("kpa_graph_launch", self.h, _stream(stream if stream is not None else self._stream))
+
+    def destroy(self):
+        if self.h:
+            _call("kpa_graph_destroy", self.h)
+            self.h = C.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def kpa_graph_begin(stream):
+    _call("kpa_graph_begin", _stream(stream))
+
+
+def kpa_graph_end(stream):
+    h = C.c_void_p(None)
+    _call("kpa_graph_end", _stream(stream), C.byref(h))
+    return h
+
+
+def kpa_graph_launch(graph, stream=None):
+    _call("kpa_graph_launch", graph, _stream(stream))
+
+
+def kpa_graph_destroy(graph):
+    _call("kpa_graph_destroy", graph)
+
+
 def kpa_merge(a_keys, a_rids, b_keys, b_rids, out_keys=None, out_rids=None, ws=None, stream=None):
     na, nb_ = a_keys.numel(), b_keys.numel()
     dev = a_keys.device
@@ -295,9 +427,11 @@ def kpa_reduce_by_key(keys, rids, seg_off, rows, layout, n_cap=None, want=("cnt"
     dev = keys.device
     cap = max(n_cap, 1)
     o = outs or {}
-    gkey = o.get("gkey", torch.empty(cap, dtype=torch.int64, device=dev))
-    outs_t = {w: o.get(w, torch.empty(cap, dtype=torch.int64, device=dev)) for w in want}
-    gseg = o.get("gseg_off", torch.empty(n_seg + 1, dtype=torch.int64, device=dev))
+    def get(name, size):   # allocate only what the caller did not pass
+        return o[name] if name in o else torch.empty(size, dtype=torch.int64, device=dev)
+    gkey = get("gkey", cap)
+    outs_t = {w: get(w, cap) for w in want}
+    gseg = get("gseg_off", n_seg + 1)
     nb = _ws_size("kpa_reduce_by_key_workspace_size", n_cap, n_seg)
     ws = _ws(nb, dev, ws)
     L = layout_struct(layout)
@@ -313,9 +447,9 @@ def kpa_topk_by_sum(gkey, gsum, gseg_off, k=10, g_cap=None, ws=None, stream=None
     g_cap = gkey.numel() if g_cap is None else g_cap
     dev = gkey.device
     o = outs or {}
-    ok = o.get("key", torch.empty(n_seg * k, dtype=torch.int64, device=dev))
-    osum = o.get("sum", torch.empty(n_seg * k, dtype=torch.int64, device=dev))
-    on = o.get("n", torch.empty(n_seg, dtype=torch.int32, device=dev))
+    ok = o["key"] if "key" in o else torch.empty(n_seg * k, dtype=torch.int64, device=dev)
+    osum = o["sum"] if "sum" in o else torch.empty(n_seg * k, dtype=torch.int64, device=dev)
+    on = o["n"] if "n" in o else torch.empty(n_seg, dtype=torch.int32, device=dev)
     nb = _ws_size("kpa_topk_by_sum_workspace_size", g_cap, n_seg)
     ws = _ws(nb, dev, ws)
     _call("kpa_topk_by_sum", _p(gkey), _p(gsum), _p(gseg_off), n_seg, g_cap, k, _p(ok), _p(osum),
