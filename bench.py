@@ -1,13 +1,20 @@
 """Benchmark of the KPA grouping hot path on one MI355X.
 
-Workload (windowed aggregation at scale): 2^28 rows of 32 bytes {u64 key Zipf
-s=1.1 over 2^20 distinct 64-bit keys, u64 value uniform [0, 2^20), u64
-timestamp ns over 10 s with +-1 ms disorder, u64 pad}, 10 tumbling 1 s
+Default workload (windowed aggregation at scale): 2^28 rows of 32 bytes {u64
+key Zipf s=1.1 over 2^20 distinct 64-bit keys, u64 value uniform [0, 2^20),
+u64 timestamp ns over 10 s with +-1 ms disorder, u64 pad}, 10 tumbling 1 s
 windows.  One step = partition the rows into window KPAs, sort every window's
 KPA, count/sum/max per key, top-10 keys by sum per window, with the rows
 already resident in device memory.  Prints one JSON line.
 
+--workload c4: 4096 substreams with one window each, sizes log-uniform over
+[2^10, 2^22) rows, rank-ordered Zipf keys whose exponent and offset drift from
+epoch 0 (the models' training data) to epoch 1 (measured).  One step = extract
++ batched sort (learned or radix for the large windows) + count/sum/max per
+key of every window, replayed as one captured graph.
+
   python bench.py [--steps K] [--warmup W] [--algo radix|learned] [--rows N]
+                  [--workload c2|c4]
 """
 from __future__ import annotations
 
@@ -45,6 +52,10 @@ def parse():
                     help="rows of the oracle's CPU-baseline sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--workload", choices=["c2", "c4"], default="c2")
+    ap.add_argument("--c4-windows", type=int, default=4096)
+    ap.add_argument("--c4-hi-log2", type=int, default=22)
+    ap.add_argument("--no-tune", action="store_true", help="c4: default batch configuration")
     ap.add_argument("--probe-copy-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -73,6 +84,8 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if a.workload == "c4":
+        return bench_c4(a)
     n = a.rows
     n_win, W = 10, 10 ** 9
     t0 = time.time()
@@ -188,6 +201,168 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "passes": passes,
+        "check": check,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def kernel_passes(K, steps, n, pass_bytes):
+    """Per-kernel launches per step, mean ms and algorithmic GB/s (recorded
+    with events on each launch's own stream since the last profile enable)."""
+    K.kpa_profile_collect()
+    passes = {}
+    for name in K.kpa_profile_names():
+        cnt, tot = K.kpa_profile_get(name)
+        if cnt == 0:
+            continue
+        avg = tot / cnt
+        entry = {"launches_per_step": cnt / steps, "avg_ms": round(avg, 4)}
+        if name in pass_bytes:
+            gbs = pass_bytes[name] * n / (avg / 1000.0) / 1e9
+            entry["alg_GBps"] = round(gbs, 1)
+            entry["hbm_frac"] = round(gbs / HBM_PEAK_GBS, 4)
+        passes[name] = entry
+    return passes
+
+
+def bench_c4(a):
+    import concurrent.futures as cf
+
+    import numpy as np
+    import torch
+
+    import datagen
+    import oracle
+    import paper_1901_01328_amd as P
+    from datagen.rows import LAYOUT32
+    from paper_1901_01328_amd.pipeline import BatchAggregation
+    K = P.load()
+    dev = torch.device("cuda:0")
+    sizes = datagen.c4_window_sizes(a.c4_windows, hi_log2=a.c4_hi_log2)
+    n = int(sizes.sum())
+    n_seg = len(sizes)
+    algo = K.KPA_SORT_LEARNED if a.algo == "learned" else K.KPA_SORT_RADIX
+    t0 = time.time()
+    rows = datagen.gen_c4(0, sizes, device=dev)
+    torch.cuda.synchronize()
+    print(f"[bench] c4 epoch 0: {n} rows in {n_seg} windows generated in {time.time() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    pipe = BatchAggregation(n, n_seg, LAYOUT32, device=dev,
+                            learned_ws=algo == K.KPA_SORT_LEARNED)
+    pipe.set_sizes(sizes)
+    radix = K.batch_config(large_algo=K.KPA_SORT_RADIX)
+    pipe.step(rows, cfg=radix)
+    pipe.fit_models()                      # epoch 1's models: epoch 0's sorted windows
+    datagen.gen_c4(1, sizes, out=rows)
+    pipe.step(rows, cfg=radix)             # extracts epoch 1 (the tuner sorts pipe.keys)
+    torch.cuda.synchronize()
+    print(f"[bench] c4 epoch 1 generated; models fitted ({time.time() - t0:.1f} s)",
+          file=sys.stderr, flush=True)
+    if a.no_tune:
+        cfg, tune_ms = K.batch_config(large_algo=algo), None
+    else:
+        cfg, tune_ms = K.kpa_batch_autotune(
+            pipe.keys, pipe.rids, pipe.seg_off, large_algo=algo, n_cap=n,
+            models=pipe.models if algo == K.KPA_SORT_LEARNED else None, reps=2,
+            keys_out=pipe.skeys, rids_out=pipe.srids, ws=pipe.ws_sort)
+        print(f"[bench] autotuned {cfg.as_dict()} ({tune_ms:.2f} ms sort)", file=sys.stderr,
+              flush=True)
+    stream = torch.cuda.Stream()
+    graph = pipe.capture(rows, stream, cfg=cfg)
+    for _ in range(a.warmup):
+        graph.launch(stream)
+    stream.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(a.steps):
+        graph.launch(stream)
+    ev1.record(stream)
+    stream.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_step = max(ev0.elapsed_time(ev1), wall * 1000) / a.steps
+    value = n / (ms_step / 1000.0) / 1e6
+    print(f"[bench] c4 timed {a.steps} graph replays: {ms_step:.3f} ms/step", file=sys.stderr,
+          flush=True)
+    # Per-kernel times: the same step run eagerly with event timing per launch.
+    K.kpa_profile_enable(True)
+    prof_steps = 2
+    for _ in range(prof_steps):
+        pipe.step(rows, stream=stream, cfg=cfg)
+    stream.synchronize()
+    c4_bytes = dict(PASS_BYTES, extract=44)
+    passes = kernel_passes(K, prof_steps, n, c4_bytes)
+    K.kpa_profile_enable(False)
+    st = pipe.stats.cpu().numpy().tolist()
+    graph.destroy()
+
+    # Oracle: every 16th window (their rows copied to the host), per window
+    # the ordered-map keyed aggregation; the GPU's groups of those windows
+    # must match exactly.
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    sample = list(range(0, n_seg, 16))
+    goff = pipe.gseg.cpu().numpy().view(np.uint64)
+    gk, gc, gs, gm = (t.cpu().numpy().view(np.uint64) for t in
+                      (pipe.gkey, pipe.g["cnt"], pipe.g["sum"], pipe.g["max"]))
+    host = {j: rows[off[j]:off[j + 1]].cpu() for j in sample}
+    threads = min(16, os.cpu_count() or 1)
+
+    def one(j):
+        r = host[j]
+        keys, rids = oracle.extract(r, LAYOUT32)
+        return j, oracle.reduce_by_key(keys, rids, r, LAYOUT32)
+
+    t1 = time.perf_counter()
+    with cf.ThreadPoolExecutor(threads) as ex:
+        res = list(ex.map(one, sample))
+    dt = time.perf_counter() - t1
+    m = int(sum(sizes[j] for j in sample))
+    ok = True
+    for j, (ek, ec, es, em) in res:
+        a0, b0 = int(goff[j]), int(goff[j + 1])
+        ok = ok and b0 - a0 == len(ek) and np.array_equal(gk[a0:b0], ek) and \
+            np.array_equal(gc[a0:b0], ec) and np.array_equal(gs[a0:b0], es) and \
+            np.array_equal(gm[a0:b0], em)
+    check = {"windows_checked": len(sample), "groups_match_oracle": bool(ok)}
+    cpu = {"value": round(m / dt / 1e6, 3), "unit": "Mrec/s", "cores": threads, "kind": "oracle",
+           "sample": f"every 16th window ({len(sample)} windows, {m} rows): extract + "
+           f"ordered-map count/sum/max per key, {dt:.1f} s"}
+    dom = "radix_pass" if algo == K.KPA_SORT_RADIX else "learned_scatter"
+    roof = None
+    if dom in passes:
+        # bytes: 24 per entry of the large windows that take part in a launch;
+        # all of them for the learned scatter, the active windows for radix
+        large = int(sizes[sizes > cfg.mid_cap].sum())
+        pl = passes[dom]
+        per_launch = 24 * large if dom == "learned_scatter" else None
+        if per_launch is None:
+            # C4 keys vary in bits 12..31 (plus carries of the offset): count
+            # the radix passes each large window needs from its own keys
+            sk = pipe.skeys
+            act = 0
+            for j in np.nonzero(sizes > cfg.mid_cap)[0]:
+                seg = sk[int(off[j]):int(off[j + 1])]
+                x = seg ^ seg[0]
+                act += int(sizes[j]) * sum(1 for p in range(8)
+                                           if bool((((x >> (8 * p)) & 255) != 0).any()))
+            per_launch = 24 * act / pl["launches_per_step"]
+        achieved = per_launch / (pl["avg_ms"] / 1000.0) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": dom, "avg_ms": pl["avg_ms"], "bytes_per_launch": int(per_launch)}
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "Mrec/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": f"{n_seg} substream windows, log-uniform 2^10..2^{a.c4_hi_log2} "
+                   "rows of 32 bytes, drifting rank-Zipf keys; extract + batched sort + "
+                   "count/sum/max per key, one graph replay per step",
+                   "rows": n, "windows": n_seg, "sort": a.algo, "batch_config": cfg.as_dict(),
+                   "autotune_sort_ms": tune_ms},
+        "roofline": roof, "cpu_baseline": cpu, "passes": passes, "sort_stats": st,
         "check": check,
     }
     print(json.dumps(out), flush=True)

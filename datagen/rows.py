@@ -203,23 +203,58 @@ def c4_zipf_s(j: int, epoch: int, n_windows: int = 4096) -> float:
     return min(1.4, 0.8 + 0.6 * j / max(n_windows - 1, 1) + 0.02 * epoch)
 
 
+def zipf_cdf_table_torch(s: float, k: int, device) -> torch.Tensor:
+    """Zipf(s, k) CDF built with torch on ``device`` (float64; the summation
+    order is the device's, so the table may differ from the host-built one in
+    the last bits).  Used where thousands of distinct exponents are needed."""
+    r = torch.arange(1, k + 1, dtype=torch.float64, device=device)
+    c = torch.cumsum(r.pow(-float(s)), 0)
+    return c / c[-1]
+
+
 def gen_c4_window(j: int, epoch: int, n: int, seed: int = 4, device="cpu",
-                  n_windows: int = 4096, control: bool = False, k: int = 1 << 20):
+                  n_windows: int = 4096, control: bool = False, k: int = 1 << 20,
+                  out: torch.Tensor | None = None):
     """Rows of substream ``j`` in ``epoch``: rank-ordered Zipf keys
     o + (r-1)*2^12 with o = j*2^40 + epoch*2^26 (drifting skew and offset), or
-    the control variant o + (mix64(r) >> 32)."""
-    i = torch.arange(n, dtype=torch.int64, device=device)
+    the control variant o + (mix64(r) >> 32).  Values uniform [0, 2^20),
+    timestamps spread over one 1 s window, pad = mix64(i).  The Zipf table is
+    built on ``device``."""
+    dev = out.device if out is not None else device
+    i = torch.arange(n, dtype=torch.int64, device=dev)
     sseed = (seed << 20) ^ (j << 4) ^ epoch
     s = c4_zipf_s(j, epoch, n_windows)
-    r = zipf_ranks(splitmix64(sseed, 1, i), s, k)
+    cdf = zipf_cdf_table_torch(s, k, dev)
+    r = torch.clamp(torch.searchsorted(cdf, uniform_f64(splitmix64(sseed, 1, i)), right=True) + 1,
+                    max=k)
     o = (j << 40) + (epoch << 26)
+    if out is None:
+        out = torch.empty((n, 4), dtype=torch.int64, device=dev)
     if control:
-        key = o + _srl(mix64(r), 32)
+        out[:, 0] = o + _srl(mix64(r), 32)
     else:
-        key = o + (r - 1) * (1 << 12)
-    val = _srl(splitmix64(sseed, 2, i), 44)
-    ts = (i * 10 ** 9) // max(n, 1)
-    return pack_rows32(key, val, ts, mix64(i))
+        out[:, 0] = o + (r - 1) * (1 << 12)
+    out[:, 1] = _srl(splitmix64(sseed, 2, i), 44)
+    out[:, 2] = (i * 10 ** 9) // max(n, 1)
+    out[:, 3] = mix64(i)
+    return out
+
+
+def gen_c4(epoch: int, sizes: np.ndarray, seed: int = 4, device="cpu",
+           out: torch.Tensor | None = None, control: bool = False):
+    """All substreams' windows of one epoch back to back (substream j's rows at
+    [sum(sizes[:j]), sum(sizes[:j+1])))."""
+    total = int(np.sum(sizes))
+    if out is None:
+        out = torch.empty((total, 4), dtype=torch.int64, device=device)
+    a = 0
+    for j, n in enumerate(sizes):
+        n = int(n)
+        if n:
+            gen_c4_window(j, epoch, n, seed, n_windows=len(sizes), control=control,
+                          out=out[a:a + n])
+        a += n
+    return out
 
 
 def as_u64(t: torch.Tensor) -> np.ndarray:

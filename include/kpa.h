@@ -88,11 +88,13 @@ kpa_status kpa_profile_names(char* buf, size_t len);
 /* ---------------------------------------------------------------------------
  * Extract (Table 2: bundle -> KPA, sequential).  keys[i] = u64 at key_off of
  * row i, rids[i] = rid_base + i.  rows: device, n rows.  out_keys/out_rids:
- * device, n entries each.
+ * device, n entries each.  out_vals (device, n u64, may be NULL): the value
+ * column (val_off, zero-extended) of row i, a compact copy a keyed reduction
+ * can read as 8-byte rows (see kpa_partition_windows).
  */
 kpa_status kpa_extract(const void* rows, uint64_t n, const kpa_row_layout* layout,
                        uint32_t rid_base, uint64_t* out_keys, uint32_t* out_rids,
-                       hipStream_t stream);
+                       uint64_t* out_vals, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Extract fused with windowing (Sec. 4.2 "Windowing": Partition on the

@@ -105,13 +105,15 @@ kpa_status launch_fill_u64(u64* p, u64 n, u64 v, hipStream_t st) {
 
 // Extract: one thread per row, key copied, rid = base + row.
 __global__ void __launch_bounds__(256) k_extract(const unsigned char* __restrict__ rows, u64 n,
-                                                 u32 row_bytes, u32 key_off, u32 rid_base,
-                                                 u64* __restrict__ keys, u32* __restrict__ rids) {
+                                                 u32 row_bytes, u32 key_off, u32 val_off,
+                                                 u32 val_w, u32 rid_base, u64* __restrict__ keys,
+                                                 u32* __restrict__ rids, u64* __restrict__ vals) {
   u64 i = (u64)blockIdx.x * 256 + threadIdx.x;
   u64 stride = (u64)gridDim.x * 256;
   for (; i < n; i += stride) {
     keys[i] = *reinterpret_cast<const u64*>(rows + i * row_bytes + key_off);
     rids[i] = rid_base + (u32)i;
+    if (vals) vals[i] = load_val(rows, (u32)i, row_bytes, val_off, val_w);
   }
 }
 
@@ -165,18 +167,19 @@ kpa_status kpa_device_check(int32_t* out) {
 
 kpa_status kpa_extract(const void* rows, uint64_t n, const kpa_row_layout* layout,
                        uint32_t rid_base, uint64_t* out_keys, uint32_t* out_rids,
-                       hipStream_t stream) {
+                       uint64_t* out_vals, hipStream_t stream) {
   clear_error();
-  KPA_CHECK(check_layout(layout, false, false));
+  KPA_CHECK(check_layout(layout, out_vals != nullptr, false));
   if (n == 0) return KPA_OK;
   KPA_REQUIRE(rows && out_keys && out_rids, KPA_EINVAL, "null pointer");
-  KPA_REQUIRE(aligned(rows, 16) && aligned(out_keys, 8) && aligned(out_rids, 4), KPA_EINVAL,
-              "misaligned pointer");
+  KPA_REQUIRE(aligned(rows, 16) && aligned(out_keys, 8) && aligned(out_rids, 4) &&
+                  aligned(out_vals, 8),
+              KPA_EINVAL, "misaligned pointer");
   KPA_REQUIRE(n + rid_base <= (1ull << 32), KPA_EUNSUPPORTED, "rids exceed 32 bits");
   u64 blocks = std::min<u64>(ceil_div(n, 256), 16384);
   KPA_LAUNCH("extract", k_extract, dim3((u32)blocks), dim3(256), 0, stream,
-                     static_cast<const unsigned char*>(rows), n, layout->row_bytes,
-                     layout->key_off, rid_base, out_keys, out_rids);
+             static_cast<const unsigned char*>(rows), n, layout->row_bytes, layout->key_off,
+             layout->val_off, layout->val_w, rid_base, out_keys, out_rids, out_vals);
   return KPA_OK;
 }
 

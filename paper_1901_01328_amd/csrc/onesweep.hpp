@@ -14,7 +14,7 @@ namespace kpa {
 
 constexpr int RADIX = 256;
 #ifndef KPA_LB_WINDOW
-#define KPA_LB_WINDOW 16
+#define KPA_LB_WINDOW 4
 #endif
 constexpr int LB_WINDOW = KPA_LB_WINDOW;  // look-back tiles probed per round trip
 static_assert(RADIX == BLOCK, "one thread per digit");

@@ -72,7 +72,7 @@ _SIGS = {
     "kpa_profile_collect": ([], C.c_int32),
     "kpa_profile_get": ([C.c_char_p, C.POINTER(_u64), C.POINTER(C.c_double)], C.c_int32),
     "kpa_profile_names": ([C.c_char_p, C.c_size_t], C.c_int32),
-    "kpa_extract": ([_vp, _u64, _lay, _u32, _vp, _vp, _vp], C.c_int32),
+    "kpa_extract": ([_vp, _u64, _lay, _u32, _vp, _vp, _vp, _vp], C.c_int32),
     "kpa_partition_windows_workspace_size": ([_u64, _u32, _sz], C.c_int32),
     "kpa_partition_windows": ([_vp, _u64, _lay, _u64, _u64, _u32, _u32, _vp, _vp, _vp, _vp, _vp,
                                _vp, C.c_size_t, _vp], C.c_int32),
@@ -213,14 +213,17 @@ def kpa_profile_names():
     return [x for x in v.split(",") if x]
 
 
-def kpa_extract(rows, layout, rid_base=0, out_keys=None, out_rids=None, stream=None):
-    n = rows_count(rows, layout)
+def kpa_extract(rows, layout, rid_base=0, out_keys=None, out_rids=None, stream=None,
+                out_vals=None, n=None):
+    """Returns (keys, rids); out_vals (n int64), when given, also receives the
+    value column."""
+    n = rows_count(rows, layout) if n is None else n
     dev = rows.device
     out_keys = torch.empty(n, dtype=torch.int64, device=dev) if out_keys is None else out_keys
     out_rids = torch.empty(n, dtype=torch.int32, device=dev) if out_rids is None else out_rids
     L = layout_struct(layout)
     _call("kpa_extract", _p(rows), n, C.byref(L), rid_base, _p(out_keys), _p(out_rids),
-          _stream(stream))
+          _p(out_vals), _stream(stream))
     return out_keys, out_rids
 
 

@@ -87,3 +87,76 @@ class WindowAggregation:
             K.kpa_topk_by_sum(self.gkey, self.g["sum"], self.gseg, k=self.k, g_cap=self.n,
                               ws=self.ws_top, stream=stream,
                               outs={"key": self.top_key, "sum": self.top_sum, "n": self.top_n})
+
+
+class BatchAggregation:
+    """Many substreams' windows at once, one segment each (substream j's rows
+    back to back in the arena): extract with the value column staged ->
+    batched sort (small / mid / large classes, radix or learned for the large
+    ones) -> keyed reduction (count, sum, max) per window.  Every buffer is
+    allocated here, so a step can be captured once in a graph and replayed.
+    """
+
+    def __init__(self, n_rows, n_seg, layout, cfg=None, device="cuda",
+                 want=("cnt", "sum", "max"), learned_ws=True):
+        self.n, self.n_seg, self.layout = n_rows, n_seg, layout
+        self.cfg = K.kpa_batch_config_default() if cfg is None else cfg
+        self.want = tuple(want)
+        d = torch.device(device)
+        cap = max(n_rows, 1)
+        i64 = dict(dtype=torch.int64, device=d)
+        i32 = dict(dtype=torch.int32, device=d)
+        self.keys = torch.empty(cap, **i64)
+        self.rids = torch.empty(cap, **i32)
+        self.vals = torch.empty(cap, **i64)
+        self.skeys = torch.empty(cap, **i64)
+        self.srids = torch.empty(cap, **i32)
+        self.seg_off = torch.zeros(n_seg + 1, **i64)
+        self.gkey = torch.empty(cap, **i64)
+        self.g = {w: torch.empty(cap, **i64) for w in self.want}
+        self.gseg = torch.empty(n_seg + 1, **i64)
+        u8 = dict(dtype=torch.uint8, device=d)
+        sizes = [K.kpa_batch_sort_workspace_size(n_rows, n_seg, K.batch_config(
+            large_algo=K.KPA_SORT_RADIX))]
+        if learned_ws:
+            sizes.append(K.kpa_batch_sort_workspace_size(n_rows, n_seg, K.batch_config(
+                large_algo=K.KPA_SORT_LEARNED)))
+        self.ws_sort = torch.empty(max(sizes), **u8)
+        self.ws_red = torch.empty(K._ws_size("kpa_reduce_by_key_workspace_size", n_rows, n_seg),
+                                  **u8)
+        self.models = K.new_models(n_seg, d)
+        self.stats = K.new_sort_stats(d)
+
+    def set_sizes(self, sizes):
+        off = torch.zeros(self.n_seg + 1, dtype=torch.int64)
+        off[1:] = torch.cumsum(torch.as_tensor(sizes, dtype=torch.int64), 0)
+        if int(off[-1]) > self.n:
+            raise ValueError("segments exceed the capacity")
+        self.seg_off.copy_(off)
+
+    def fit_models(self, stream=None):
+        """PWL models of every window from the current sorted KPA (to be used
+        on the next epoch's windows)."""
+        K.kpa_pwl_fit(self.skeys, self.seg_off, 1024, models=self.models, stream=stream)
+
+    def step(self, rows, stream=None, cfg=None):
+        cfg = self.cfg if cfg is None else cfg
+        K.kpa_extract(rows, self.layout, out_keys=self.keys, out_rids=self.rids,
+                      out_vals=self.vals, n=self.n, stream=stream)
+        K.kpa_batch_sort(self.keys, self.rids, self.seg_off, cfg=cfg, n_cap=self.n,
+                         models=self.models if cfg.large_algo == K.KPA_SORT_LEARNED else None,
+                         stats=self.stats, keys_out=self.skeys, rids_out=self.srids,
+                         ws=self.ws_sort, stream=stream)
+        outs = dict(self.g)
+        outs["gkey"] = self.gkey
+        outs["gseg_off"] = self.gseg
+        K.kpa_reduce_by_key(self.skeys, self.srids, self.seg_off, self.vals, VALUE_COLUMN,
+                            n_cap=self.n, want=self.want, ws=self.ws_red, stream=stream,
+                            outs=outs)
+
+    def capture(self, rows, stream, cfg=None):
+        """A graph of one step on `stream` (replay with .launch())."""
+        g = K.Graph.capture(stream)
+        with g:
+            self.step(rows, stream=stream, cfg=cfg)
+        return g

@@ -50,7 +50,7 @@ def test_host_side_errors_without_gpu():
                                    None, None, 0, None)
     assert rc == k.KPA_EUNSUPPORTED
     bad = k.kpa_row_layout(30, 0, 8, 8, 16, 8)
-    rc = lib.kpa_extract(None, 5, ctypes.byref(bad), 0, None, None, None)
+    rc = lib.kpa_extract(None, 5, ctypes.byref(bad), 0, None, None, None, None)
     assert rc == k.KPA_EINVAL
     assert b"row_bytes" in lib.kpa_last_error_string()
     rc = lib.kpa_topk_by_sum(None, None, None, 1, 10, 17, None, None, None, None, 0, None)

@@ -33,6 +33,21 @@ def test_extract(K, orc, n):
     assert np.array_equal(u64(k), ek) and np.array_equal(u32(r), er)
 
 
+@pytest.mark.parametrize("layout", ["16", "32"])
+def test_extract_value_column(K, layout):
+    n = 9001
+    if layout == "32":
+        rows, lay = c2_rows(n), LAYOUT32
+        expect = rows[:, 1].numpy().view(np.uint64)
+    else:
+        rows, lay = datagen.gen_c1(n, seed=3), LAYOUT16
+        expect = rows.numpy().view(np.uint32).reshape(n, 4)[:, 2].astype(np.uint64)
+    vals = torch.empty(n, dtype=torch.int64, device="cuda")
+    k, r = K.kpa_extract(rows.cuda(), lay, out_vals=vals)
+    torch.cuda.synchronize()
+    assert np.array_equal(u64(vals), expect)
+
+
 @pytest.mark.parametrize("n", SIZES)
 def test_partition_c2_layout(K, orc, n):
     rows = c2_rows(n, span=10 ** 6)
