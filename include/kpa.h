@@ -132,7 +132,12 @@ kpa_status kpa_partition_windows(const void* rows, uint64_t n, const kpa_row_lay
  * algo KPA_SORT_LEARNED: a learned-splitter sort.  models (device, one
  * kpa_pwl_model per segment) give a nondecreasing CDF estimate F; each key goes
  * to bucket floor(B*F(key)), buckets are formed by stable scatters and each
- * bucket is finished in on-chip memory.  Buckets too large for that, or whose
+ * bucket is finished in on-chip memory.  The knots are used as the shape of
+ * the CDF over the segment's own key range: F(key) interpolates the knots at
+ * n_seg*(key - min)/(max - min), with min/max the smallest and largest key of
+ * the segment (counted in a first pass over the keys), so that a model fitted
+ * on an earlier window still applies when the keys have moved by an offset;
+ * the model's kmin/kmax record the range it was fitted on.  Buckets too large for that, or whose
  * order the model would break, are re-sorted by the radix path.  The model
  * affects only speed: the output equals the radix sort's, byte for byte.
  * stats (device, may be NULL) receives counters of the learned path.

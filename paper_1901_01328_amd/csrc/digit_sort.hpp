@@ -26,8 +26,9 @@ struct DigitSortBufs {
   u32* tile_start;
   u32* status0;
   u32* status1;
-  u32* counters;
+  u32* counters;    // [p]: tile claims of pass p; [15]: passes needed by any segment
   u64 max_tiles;
+  OrderBufs order;
 };
 
 __device__ __forceinline__ void seg_tile_range(const SegList& sl, const u32* tile_start,
@@ -41,32 +42,62 @@ __device__ __forceinline__ void seg_tile_range(const SegList& sl, const u32* til
   cnt = base < b ? (u32)min<u64>(TILE, b - base) : 0u;
 }
 
+// Adds one wave's items to a histogram: the lanes holding the first active
+// lane's digit add their count with one atomic (a digit that is constant in
+// the segment, or a heavy key, costs one LDS atomic per wave instead of 64
+// colliding ones); the other lanes add one each.
+__device__ __forceinline__ void wave_hist_add(u32* h, u32 d, bool v) {
+  if (v) {
+    const u32 d0 = __builtin_amdgcn_readfirstlane(d);  // first active lane's digit
+    const bool mine = d == d0;
+    const u64 same = ballot(mine);  // among the active lanes
+    if (mine) {
+      if ((same & lanemask_lt()) == 0) atomicAdd(&h[d0], (u32)__popcll(same));
+    } else {
+      atomicAdd(&h[d], 1u);
+    }
+  }
+}
+
+// Digit counts of every pass per segment: each workgroup takes
+// HIST_TILES_PER_BLOCK tiles at a time, loads a tile coalesced (ITEMS per
+// thread), counts into per-wave LDS histograms and flushes them with one
+// global atomic per nonzero (pass, digit) whenever the segment changes.
 template <class DF>
 __global__ void __launch_bounds__(BLOCK) k_ds_hist(const u64* __restrict__ keys, SegList sl,
                                                    const u32* __restrict__ tile_start,
                                                    typename DF::Params prm,
                                                    u32* __restrict__ hist) {
-  __shared__ u32 h[DF::PASSES][RADIX];
+  __shared__ u32 h[WAVES][DF::PASSES][RADIX];
   __shared__ float dfsm[DF::SMEM];
   const u32 tid = threadIdx.x;
+  const u32 w = tid >> 6;
   const u32 n_seg = sl.n();
   const u32 total = tile_start[n_seg];
+  auto flush = [&](u32 seg) {
+    __syncthreads();
+    for (int p = 0; p < DF::PASSES; ++p) {
+      u32 c = 0;
+#pragma unroll
+      for (int ww = 0; ww < WAVES; ++ww) {
+        c += h[ww][p][tid];
+        h[ww][p][tid] = 0;
+      }
+      if (c) atomicAdd(&hist[((u64)seg * DF::PASSES + p) * RADIX + tid], c);
+    }
+    __syncthreads();
+  };
+  for (int p = 0; p < DF::PASSES; ++p)
+#pragma unroll
+    for (int ww = 0; ww < WAVES; ++ww) h[ww][p][tid] = 0;
   for (u32 t0 = blockIdx.x * HIST_TILES_PER_BLOCK; t0 < total;
        t0 += gridDim.x * HIST_TILES_PER_BLOCK) {
     const u32 t1 = min(total, t0 + HIST_TILES_PER_BLOCK);
-    __syncthreads();
-    for (int p = 0; p < DF::PASSES; ++p) h[p][tid] = 0;
     u32 cur = find_seg(tile_start, n_seg, t0);
     __syncthreads();
     for (u32 t = t0; t < t1; ++t) {
       while (cur + 1 < n_seg && tile_start[cur + 1] <= t) {
-        __syncthreads();
-        for (int p = 0; p < DF::PASSES; ++p) {
-          const u32 c = h[p][tid];
-          if (c) atomicAdd(&hist[((u64)cur * DF::PASSES + p) * RADIX + tid], c);
-          h[p][tid] = 0;
-        }
-        __syncthreads();
+        flush(cur);
         ++cur;
       }
       DF df(prm, cur);
@@ -75,20 +106,23 @@ __global__ void __launch_bounds__(BLOCK) k_ds_hist(const u64* __restrict__ keys,
       __syncthreads();
       const u64 a = sl.lo[cur], b = sl.hi[cur];
       const u64 base = a + (u64)(t - tile_start[cur]) * TILE;
-      const u64 end = min(b, base + TILE);
-      for (u64 i = base + tid; i < end; i += BLOCK) {
-        const u64 k = keys[i];
-        u32 dg[DF::PASSES];
-        df.digits(k, dg);
+      const u32 cnt = base < b ? (u32)min<u64>(TILE, b - base) : 0u;
+      u64 kk[ITEMS];
 #pragma unroll
-        for (int p = 0; p < DF::PASSES; ++p) atomicAdd(&h[p][dg[p]], 1u);
+      for (int j = 0; j < ITEMS; ++j) {
+        const u32 o = tile_offset(j);
+        kk[j] = o < cnt ? keys[base + o] : 0ull;
+      }
+#pragma unroll
+      for (int j = 0; j < ITEMS; ++j) {
+        const bool v = tile_offset(j) < cnt;
+        u32 dg[DF::PASSES];
+        df.digits(kk[j], dg);
+#pragma unroll
+        for (int p = 0; p < DF::PASSES; ++p) wave_hist_add(h[w][p], dg[p], v);
       }
     }
-    __syncthreads();
-    for (int p = 0; p < DF::PASSES; ++p) {
-      const u32 c = h[p][tid];
-      if (c) atomicAdd(&hist[((u64)cur * DF::PASSES + p) * RADIX + tid], c);
-    }
+    flush(cur);
   }
 }
 
@@ -98,13 +132,18 @@ template <int UNUSED = 0>
 __global__ void __launch_bounds__(BLOCK) k_ds_prepare(SegList sl, const u32* __restrict__ tile_start,
                                                       u32* __restrict__ hist, u32 hist_passes,
                                                       u32* __restrict__ status0,
-                                                      u32* __restrict__ counters) {
+                                                      u32* __restrict__ counters, OrderBufs order,
+                                                      u64 max_tiles) {
   const u32 n_seg = sl.n();
   const u64 nh = hist ? (u64)n_seg * hist_passes * RADIX : 0ull;
   const u64 ns = (u64)tile_start[n_seg] * RADIX;
   const u64 stride = (u64)gridDim.x * BLOCK;
   for (u64 i = (u64)blockIdx.x * BLOCK + threadIdx.x; i < nh; i += stride) hist[i] = 0;
   for (u64 i = (u64)blockIdx.x * BLOCK + threadIdx.x; i < ns; i += stride) status0[i] = 0;
+  for (u64 i = (u64)blockIdx.x * BLOCK + threadIdx.x; i < max_tiles + 2; i += stride) {
+    order.more[i] = 0;
+    order.ties[i] = 0;
+  }
   if (blockIdx.x == 0 && threadIdx.x < 16) counters[threadIdx.x] = 0;
 }
 
@@ -137,34 +176,153 @@ __global__ void __launch_bounds__(BLOCK) k_ds_scan(SegList sl, u32* __restrict__
 // Persistent: each workgroup claims tiles in increasing order until none is
 // left.  A tile only waits (look-back) on tiles claimed earlier by running
 // workgroups, so every wait ends.
+// Claim order, step 1: more[r] = segments with exactly r+1 tiles,
+// counters[14] = most tiles of a segment (R).  Cleared by k_ds_prepare.
+template <int UNUSED = 0>
+__global__ void __launch_bounds__(BLOCK) k_ds_count(SegList sl, const u32* __restrict__ tile_start,
+                                                    u32* __restrict__ more,
+                                                    u32* __restrict__ counters) {
+  const u32 n_seg = sl.n();
+  u32 m = 0;
+  for (u32 s = blockIdx.x * BLOCK + threadIdx.x; s < n_seg; s += gridDim.x * BLOCK) {
+    const u32 nt = tile_start[s + 1] - tile_start[s];
+    atomicAdd(&more[nt - 1], 1u);
+    m = max(m, nt);
+  }
+  m = wave_max(m);
+  if (__lane_id() == 0 && m) atomicMax(&counters[14], m);
+}
+
+// Step 2 (one workgroup of 1024 threads): more[r] = segments with more than
+// r tiles (suffix sums), round0[r] = first claim index of round r (prefix
+// sums of more), round0[R] = all tiles.
+template <int UNUSED = 0>
+__global__ void __launch_bounds__(1024) k_ds_rounds(const u32* __restrict__ counters,
+                                                    u32* __restrict__ more,
+                                                    u32* __restrict__ round0) {
+  __shared__ u32 sm[17];
+  const u32 tid = threadIdx.x;
+  const u32 R = counters[14];
+  const u32 chunk = (R + 1023) / 1024;
+  {
+    const u32 ct = 1023 - tid;  // chunks in reverse thread order: exclusive = later chunks
+    const u32 lo = min(R, ct * chunk), hi = min(R, lo + chunk);
+    u32 local = 0;
+    for (u32 i = lo; i < hi; ++i) local += more[i];
+    u32 tot;
+    u32 acc = block_excl_sum<16>(local, sm, &tot);
+    for (u32 i = hi; i > lo; --i) {
+      acc += more[i - 1];
+      more[i - 1] = acc;
+    }
+  }
+  __syncthreads();
+  {
+    const u32 lo = min(R, tid * chunk), hi = min(R, lo + chunk);
+    u32 local = 0;
+    for (u32 i = lo; i < hi; ++i) local += more[i];
+    u32 tot;
+    u32 acc = block_excl_sum<16>(local, sm, &tot);
+    for (u32 i = lo; i < hi; ++i) {
+      round0[i] = acc;
+      acc += more[i];
+    }
+    if (tid == 0) round0[R] = tot;
+  }
+}
+
+// Position of every segment inside the rounds it takes part in: segments
+// with more tiles first (ties in any order), so that the segments active in
+// round r occupy positions [0, more[r]).  Also collects the passes any
+// segment needs into counters[15].
+template <int UNUSED = 0>
+__global__ void __launch_bounds__(BLOCK) k_ds_pos(SegList sl, const u32* __restrict__ tile_start,
+                                                  const u32* __restrict__ more,
+                                                  u32* __restrict__ ties, u32* __restrict__ pos,
+                                                  const u32* __restrict__ seg_mask,
+                                                  u32* __restrict__ counters) {
+  const u32 n_seg = sl.n();
+  u32 need = 0;
+  for (u32 s = blockIdx.x * BLOCK + threadIdx.x; s < n_seg; s += gridDim.x * BLOCK) {
+    const u32 nt = tile_start[s + 1] - tile_start[s];
+    pos[s] = more[nt] + atomicAdd(&ties[nt - 1], 1u);
+    need |= seg_mask[s] & 0xFFu;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) need |= __shfl_xor(need, o, 64);
+  if (__lane_id() == 0 && need) atomicOr(&counters[15], need);
+}
+
+// Descriptor of every tile at its claim index round0[t_in] + pos[seg].
+template <int UNUSED = 0>
+__global__ void __launch_bounds__(BLOCK) k_ds_desc(SegList sl, const u32* __restrict__ tile_start,
+                                                   const u32* __restrict__ round0,
+                                                   const u32* __restrict__ pos,
+                                                   const u32* __restrict__ seg_mask,
+                                                   TileDesc* __restrict__ desc) {
+  const u32 n_seg = sl.n();
+  const u32 total = tile_start[n_seg];
+  for (u32 g = blockIdx.x * BLOCK + threadIdx.x; g < total; g += gridDim.x * BLOCK) {
+    const u32 s = find_seg(tile_start, n_seg, g);
+    const u32 t = g - tile_start[s];
+    const u64 a = sl.lo[s], b = sl.hi[s];
+    const u64 base = a + (u64)t * TILE;
+    TileDesc d;
+    d.base = base;
+    d.seg = s;
+    d.t_in = t;
+    d.cnt = base < b ? (u32)min<u64>(TILE, b - base) : 0u;
+    d.g = g;
+    d.mask = seg_mask[s];
+    d.pad = 0;
+    desc[round0[t] + pos[s]] = d;
+  }
+}
+
+// Geometry of the scatter pass: PASS_WAVES waves per workgroup, so that two
+// workgroups per CU keep 4*PASS_WAVES/4 waves on each SIMD while the tile stays
+// TILE entries.
+#ifndef KPA_PASS_WAVES
+#define KPA_PASS_WAVES 8
+#endif
+constexpr int PASS_WAVES = KPA_PASS_WAVES;
+constexpr int PASS_THREADS = PASS_WAVES * 64;
+constexpr int PASS_ITEMS = TILE / PASS_THREADS;
+static_assert(PASS_THREADS >= RADIX && PASS_ITEMS * PASS_THREADS == TILE, "pass geometry");
+
 template <class DF>
-__global__ void __launch_bounds__(BLOCK) k_ds_pass(DigitSortBufs bf, SegList sl,
-                                                   typename DF::Params prm, u32 pass,
-                                                   u32* __restrict__ status_cur,
-                                                   u32* __restrict__ status_next,
-                                                   u32* __restrict__ counter) {
-  __shared__ OnesweepSmem sm;
+__global__ void __launch_bounds__(PASS_THREADS, PASS_WAVES / 2)
+    k_ds_pass(DigitSortBufs bf, SegList sl, typename DF::Params prm, u32 pass,
+              u32* __restrict__ status_cur, u32* __restrict__ status_next) {
+  __shared__ OnesweepSmemT<PASS_WAVES> sm;
   __shared__ float dfsm[DF::SMEM];
   const u32 tid = threadIdx.x;
   const u32 n_seg = sl.n();
   const u32 total = bf.tile_start[n_seg];
+  if (pass > 0 && !((bf.counters[15] >> pass) & 1)) {
+    // No segment needs this pass: only prepare the next pass's look-back words.
+    const u64 nw = (u64)total * RADIX;
+    for (u64 i = (u64)blockIdx.x * PASS_THREADS + tid; i < nw; i += (u64)gridDim.x * PASS_THREADS)
+      status_next[i] = 0;
+    return;
+  }
+  u32* counter = bf.counters + pass;
   while (true) {
     __syncthreads();
     if (tid == 0) sm.tile = atomicAdd(counter, 1u);
     __syncthreads();
-    const u32 tile = sm.tile;
-    if (tile >= total) return;
-    status_next[(u64)tile * RADIX + tid] = 0;  // ready for the next pass
-
-    u32 seg, t_in, cnt;
-    u64 a, b, base;
-    seg_tile_range(sl, bf.tile_start, n_seg, tile, seg, t_in, a, b, base, cnt);
-    const u32 mask = bf.seg_mask[seg];
+    const u32 c = sm.tile;
+    if (c >= total) return;
+    const TileDesc td = bf.order.desc[c];
+    if (tid < RADIX) status_next[(u64)td.g * RADIX + tid] = 0;  // ready for the next pass
+    const u32 mask = td.mask;
     if (mask & SEG_UNSUPPORTED) continue;
+    const u32 seg = td.seg, cnt = td.cnt;
+    const u64 base = td.base;
     const u32 k = __popc(mask);
     if (k == 0) {
       if (pass == 0 && bf.keys_in != bf.keys_out) {
-        for (u32 i = tid; i < cnt; i += BLOCK) {
+        for (u32 i = tid; i < cnt; i += PASS_THREADS) {
           bf.keys_out[base + i] = bf.keys_in[base + i];
           bf.rids_out[base + i] = bf.rids_in[base + i];
         }
@@ -178,15 +336,12 @@ __global__ void __launch_bounds__(BLOCK) k_ds_pass(DigitSortBufs bf, SegList sl,
     u64* dst_k = ((k - 1 - q) & 1) == 0 ? bf.keys_out : bf.keys_tmp;
     u32* dst_r = ((k - 1 - q) & 1) == 0 ? bf.rids_out : bf.rids_tmp;
 
-    DF df(prm, seg);
-    df.bind(dfsm);
-    __syncthreads();
-    u64 kk[ITEMS];
-    u32 rr[ITEMS], dd[ITEMS];
+    u64 kk[PASS_ITEMS];
+    u32 rr[PASS_ITEMS], dd[PASS_ITEMS];
     u32 valid = 0;
 #pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-      const u32 o = tile_offset(j);
+    for (int j = 0; j < PASS_ITEMS; ++j) {
+      const u32 o = tile_offset_t<PASS_WAVES>(j);
       if (o < cnt) {
         kk[j] = src_k[base + o];
         rr[j] = src_r[base + o];
@@ -196,22 +351,28 @@ __global__ void __launch_bounds__(BLOCK) k_ds_pass(DigitSortBufs bf, SegList sl,
         rr[j] = 0;
       }
     }
+    const u64 seg_start = base - (u64)td.t_in * TILE;
+    const u64 my_base =
+        tid < RADIX ? seg_start + bf.hist[((u64)seg * DF::PASSES + pass) * RADIX + tid] : 0ull;
+    DF df(prm, seg);
+    df.bind(dfsm);
+    if (DF::SMEM > 1) __syncthreads();
 #pragma unroll
-    for (int j = 0; j < ITEMS; ++j) dd[j] = ((valid >> j) & 1) ? df.digit(kk[j], pass) : 0u;
-    const u64 my_base = a + bf.hist[((u64)seg * DF::PASSES + pass) * RADIX + tid];
-    onesweep_tile(sm, kk, rr, dd, valid, status_cur, tile, t_in, my_base, dst_k, dst_r);
+    for (int j = 0; j < PASS_ITEMS; ++j) dd[j] = ((valid >> j) & 1) ? df.digit(kk[j], pass) : 0u;
+    onesweep_tile(sm, kk, rr, dd, valid, status_cur, td.g, td.t_in, my_base, dst_k, dst_r);
   }
 }
 
-// Workgroups that fit on the device at once for a kernel (persistent grids).
+// Workgroups of `threads` threads that fit on the device at once for a kernel
+// (persistent grids); computed once per kernel instantiation.
 template <class K>
-u32 resident_grid(K kernel, u32 cap) {
+u32 resident_grid(K kernel, u32 cap, int threads = BLOCK) {
   static u32 cached = 0;
   if (!cached) {
     int dev = 0, per_cu = 1;
     hipDeviceProp_t p;
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) return cap;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, BLOCK, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
         per_cu < 1)
       per_cu = 1;
     cached = (u32)(p.multiProcessorCount * per_cu);
@@ -228,7 +389,8 @@ kpa_status digit_sort_launch(const SegList& sl, const typename DF::Params& prm,
   const bool radix = DF::PASSES == 8;
   KPA_CHECK(launch_seg_tiles_list(sl, TILE, b.tile_start, st));
   KPA_LAUNCH("sort_prepare", k_ds_prepare<0>, dim3(1024), dim3(BLOCK), 0, st, sl, b.tile_start,
-             with_hist ? b.hist : nullptr, (u32)DF::PASSES, b.status0, b.counters);
+             with_hist ? b.hist : nullptr, (u32)DF::PASSES, b.status0, b.counters, b.order,
+             b.max_tiles);
   if (with_hist) {
     const u32 hist_blocks = (u32)std::min<u64>(ceil_div(b.max_tiles, HIST_TILES_PER_BLOCK), 4096);
     KPA_LAUNCH(radix ? "radix_hist" : "learned_hist", k_ds_hist<DF>, dim3(hist_blocks),
@@ -236,17 +398,24 @@ kpa_status digit_sort_launch(const SegList& sl, const typename DF::Params& prm,
     KPA_LAUNCH(radix ? "radix_scan" : "learned_scan", k_ds_scan<DF>,
                dim3(std::min<u32>(sl.n_max, 2048)), dim3(BLOCK), 0, st, sl, b.hist, b.seg_mask);
   }
-#ifdef KPA_ONE_TILE_PER_BLOCK
-  const u32 grid = (u32)b.max_tiles;
-#else
-  const u32 grid = resident_grid(k_ds_pass<DF>, (u32)std::min<u64>(b.max_tiles, 1u << 20));
-#endif
+  const dim3 seg_grid((u32)std::min<u64>(ceil_div(std::max<u32>(sl.n_max, 1), BLOCK), 1024));
+  KPA_LAUNCH("sort_count", k_ds_count<0>, seg_grid, dim3(BLOCK), 0, st, sl, b.tile_start,
+             b.order.more, b.counters);
+  KPA_LAUNCH("sort_rounds", k_ds_rounds<0>, dim3(1), dim3(1024), 0, st, b.counters, b.order.more,
+             b.order.round0);
+  KPA_LAUNCH("sort_order", k_ds_pos<0>, seg_grid, dim3(BLOCK), 0, st, sl, b.tile_start,
+             b.order.more, b.order.ties, b.order.pos, b.seg_mask, b.counters);
+  KPA_LAUNCH("sort_desc", k_ds_desc<0>,
+             dim3((u32)std::min<u64>(ceil_div(b.max_tiles, BLOCK), 4096)), dim3(BLOCK), 0, st,
+             sl, b.tile_start, b.order.round0, b.order.pos, b.seg_mask, b.order.desc);
+  const u32 grid =
+      resident_grid(k_ds_pass<DF>, (u32)std::min<u64>(b.max_tiles, 1u << 20), PASS_THREADS);
   const char* pname = radix ? "radix_pass" : (DF::PASSES == 2 ? "learned_scatter" : "pivot_scatter");
   for (u32 p = 0; p < (u32)DF::PASSES; ++p) {
     u32* cur = (p & 1) ? b.status1 : b.status0;
     u32* nxt = (p & 1) ? b.status0 : b.status1;
-    KPA_LAUNCH(pname, k_ds_pass<DF>, dim3(grid), dim3(BLOCK), 0, st, b, sl, prm, p, cur, nxt,
-               b.counters + p);
+    KPA_LAUNCH(pname, k_ds_pass<DF>, dim3(grid), dim3(PASS_THREADS), 0, st, b, sl, prm, p, cur,
+               nxt);
   }
   return KPA_OK;
 }

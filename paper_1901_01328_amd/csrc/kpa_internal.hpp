@@ -152,8 +152,10 @@ __device__ __forceinline__ u32 wave_incl_sum(u32 v) {
   return v;
 }
 
-// Block-wide exclusive sum of one u32 per thread (BLOCK threads); returns the
-// exclusive prefix and writes the block total to *total.  Uses `sm` (WAVES+1 u32).
+// Block-wide exclusive sum of one u32 per thread (NW waves of 64 threads);
+// returns the exclusive prefix and writes the block total to *total.  Uses
+// `sm` (NW+1 u32).
+template <int NW = WAVES>
 __device__ __forceinline__ u32 block_excl_sum(u32 v, u32* sm, u32* total) {
   u32 incl = wave_incl_sum(v);
   u32 w = threadIdx.x >> 6;
@@ -161,16 +163,16 @@ __device__ __forceinline__ u32 block_excl_sum(u32 v, u32* sm, u32* total) {
   __syncthreads();
   if (threadIdx.x == 0) {
     u32 acc = 0;
-    for (int i = 0; i < WAVES; ++i) {
+    for (int i = 0; i < NW; ++i) {
       u32 t = sm[i];
       sm[i] = acc;
       acc += t;
     }
-    sm[WAVES] = acc;
+    sm[NW] = acc;
   }
   __syncthreads();
   u32 r = sm[w] + incl - v;
-  *total = sm[WAVES];
+  *total = sm[NW];
   __syncthreads();
   return r;
 }

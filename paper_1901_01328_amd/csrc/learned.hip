@@ -37,7 +37,7 @@ struct LearnedDF {
   // synchronizes before the first use).
   __device__ __forceinline__ void bind(float* sm) {
     if (m.bits) {
-      for (u32 j = threadIdx.x; j <= m.nseg; j += BLOCK) sm[j] = m.knots[j];
+      for (u32 j = threadIdx.x; j <= m.nseg; j += blockDim.x) sm[j] = m.knots[j];
       m.knots = sm;
     }
   }
@@ -59,15 +59,66 @@ __device__ __forceinline__ void stat_add(kpa_sort_stats* st, int idx, u64 v) {
 
 // One workgroup per segment (grid-stride): validate the model, choose the
 // bucket count.
+// Smallest and largest key of every segment (one atomic pair per tile).
+__global__ void __launch_bounds__(BLOCK) k_seg_minmax(const u64* __restrict__ keys, SegList sl,
+                                                      const u32* __restrict__ tile_start,
+                                                      u64* __restrict__ kmin,
+                                                      u64* __restrict__ kmax) {
+  __shared__ u64 red[2 * WAVES];
+  const u32 n_seg = sl.n();
+  const u32 total = tile_start[n_seg];
+  for (u32 t = blockIdx.x; t < total; t += gridDim.x) {
+    const u32 s = find_seg(tile_start, n_seg, t);
+    const u64 a = sl.lo[s], b = sl.hi[s];
+    const u64 base = a + (u64)(t - tile_start[s]) * TILE;
+    const u64 end = min(b, base + TILE);
+    u64 lo = ~0ull, hi = 0;
+    for (u64 i = base + threadIdx.x; i < end; i += BLOCK) {
+      const u64 k = keys[i];
+      lo = k < lo ? k : lo;
+      hi = k > hi ? k : hi;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const u64 l2 = __shfl_xor(lo, o, 64), h2 = __shfl_xor(hi, o, 64);
+      lo = l2 < lo ? l2 : lo;
+      hi = h2 > hi ? h2 : hi;
+    }
+    __syncthreads();
+    if (__lane_id() == 0) {
+      red[threadIdx.x >> 6] = lo;
+      red[WAVES + (threadIdx.x >> 6)] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && base < end) {
+      for (int w = 1; w < WAVES; ++w) {
+        lo = red[w] < lo ? red[w] : lo;
+        hi = red[WAVES + w] > hi ? red[WAVES + w] : hi;
+      }
+      lo = red[0] < lo ? red[0] : lo;
+      hi = red[WAVES] > hi ? red[WAVES] : hi;
+      atomicMin(reinterpret_cast<unsigned long long*>(kmin + s), (unsigned long long)lo);
+      atomicMax(reinterpret_cast<unsigned long long*>(kmax + s), (unsigned long long)hi);
+    }
+  }
+}
+
+// The model's knots describe the shape of the CDF over the key range it was
+// fitted on; it is applied over the segment's own range [kmin, kmax] (taken
+// from the keys), so that a window whose keys moved by an offset since the
+// model's window keeps the model's resolution.
 __global__ void __launch_bounds__(BLOCK) k_learned_setup(const kpa_pwl_model* __restrict__ models,
-                                                         SegList sl, SegModel* __restrict__ segm,
+                                                         SegList sl,
+                                                         const u64* __restrict__ cur_min,
+                                                         const u64* __restrict__ cur_max,
+                                                         SegModel* __restrict__ segm,
                                                          kpa_sort_stats* stats) {
   const u32 n_seg = sl.n();
   for (u32 s = blockIdx.x; s < n_seg; s += gridDim.x) {
     const kpa_pwl_model& M = models[s];
     const u64 n = sl.hi[s] - sl.lo[s];
     const u32 nseg = M.n_seg;
-    bool ok = nseg >= 1 && nseg <= KPA_PWL_MAX_SEG && M.kmax >= M.kmin;
+    bool ok = nseg >= 1 && nseg <= KPA_PWL_MAX_SEG && M.kmax >= M.kmin && n > 0;
     if (ok) {
       for (u32 j = threadIdx.x; j <= nseg; j += BLOCK) {
         const float a = M.knots[j];
@@ -79,10 +130,10 @@ __global__ void __launch_bounds__(BLOCK) k_learned_setup(const kpa_pwl_model* __
     ok = __syncthreads_and(ok);
     if (threadIdx.x == 0) {
       SegModel m;
-      m.kmin = M.kmin;
-      m.kmax = M.kmax;
+      m.kmin = ok ? cur_min[s] : M.kmin;
+      m.kmax = ok ? cur_max[s] : M.kmax;
       m.nseg = ok ? nseg : 1;
-      const u64 span = M.kmax - M.kmin;
+      const u64 span = m.kmax - m.kmin;
       m.scale = (ok && span) ? (float)nseg / (float)span : 0.0f;
       m.valid = ok ? 1u : 0u;
       m.knots = M.knots;
@@ -593,6 +644,8 @@ kpa_status learned_sort_plan(u64 n_cap, u32 n_seg, Carver& c, LearnedWs* w) {
   w->keys_tmp = c.take<u64>(n_cap);
   w->rids_tmp = c.take<u32>(n_cap);
   w->segm = c.take<SegModel>(n_seg);
+  w->cur_min = c.take<u64>(n_seg);
+  w->cur_max = c.take<u64>(n_seg);
   w->ltile_start = c.take<u32>((u64)n_seg + 1);
   w->ftile_start = c.take<u32>((u64)n_seg + 1);
   w->hist = c.take<u32>((u64)n_seg * 2 * RADIX);
@@ -600,6 +653,7 @@ kpa_status learned_sort_plan(u64 n_cap, u32 n_seg, Carver& c, LearnedWs* w) {
   w->status0 = c.take<u32>(w->max_tiles * RADIX);
   w->status1 = c.take<u32>(w->max_tiles * RADIX);
   w->counters = c.take<u32>(16);
+  order_plan(c, w->max_tiles, n_seg, &w->order);
   w->fb_lo = c.take<u64>(w->max_fb);
   w->fb_hi = c.take<u64>(w->max_fb);
   w->fb_rhi = c.take<u64>(w->max_fb);
@@ -631,11 +685,16 @@ kpa_status learned_sort_launch(const u64* keys_in, const u32* rids_in, u64* keys
   if (stats) KPA_CHECK(launch_fill_u64(reinterpret_cast<u64*>(stats), 6, 0, st));
   KPA_CHECK(launch_fill_u32(lw.fb_count, 1, 0, st));
   KPA_CHECK(launch_fill_u32(lw.rl_count, 4, 0, st));
+  KPA_CHECK(launch_seg_tiles_list(sl, TILE, lw.ltile_start, st));
+  KPA_CHECK(launch_fill_u64(lw.cur_min, n_seg, ~0ull, st));
+  KPA_CHECK(launch_fill_u64(lw.cur_max, n_seg, 0ull, st));
+  KPA_LAUNCH("learned_minmax", k_seg_minmax, dim3((u32)std::min<u64>(lw.max_tiles, 8192)),
+             dim3(BLOCK), 0, st, keys_in, sl, lw.ltile_start, lw.cur_min, lw.cur_max);
   KPA_LAUNCH("learned_setup", k_learned_setup, dim3(std::min<u32>(n_seg, 2048)), dim3(BLOCK), 0,
-             st, models, sl, lw.segm, stats);
-  DigitSortBufs b{keys_in, rids_in, keys_out, rids_out, lw.keys_tmp, lw.rids_tmp, lw.hist,
-                  lw.seg_mask, lw.ltile_start, lw.status0, lw.status1, lw.counters,
-                  lw.max_tiles};
+             st, models, sl, lw.cur_min, lw.cur_max, lw.segm, stats);
+  DigitSortBufs b{keys_in,     rids_in,      keys_out,   rids_out,       lw.keys_tmp,
+                  lw.rids_tmp, lw.hist,      lw.seg_mask, lw.ltile_start, lw.status0,
+                  lw.status1,  lw.counters,  lw.max_tiles, lw.order};
   KPA_CHECK(digit_sort_launch<LearnedDF>(sl, LearnedDF::Params{lw.segm}, b, st));
 
   KPA_CHECK(launch_seg_tiles_list(sl, FH, lw.ftile_start, st));
@@ -661,10 +720,11 @@ kpa_status learned_sort_launch(const u64* keys_in, const u32* rids_in, u64* keys
     KPA_LAUNCH("pivot_copy", k_fb_copy, dim3(2048), dim3(BLOCK), 0, st, keys_out, rids_out, fl,
                lw.fb_tile_start, lw.p_mask, lw.keys_tmp, lw.rids_tmp);
     const SegList pl{lo_in[r], lw.fb_rhi, cnt_in[r], lw.max_fb};
-    DigitSortBufs pb{lw.keys_tmp, lw.rids_tmp, keys_out, rids_out, lw.fb_radix.keys_tmp,
-                     lw.fb_radix.rids_tmp, lw.p_hist, lw.p_mask, lw.p_tile_start,
-                     lw.fb_radix.status0, lw.fb_radix.status1, lw.fb_radix.counters,
-                     lw.fb_radix.max_tiles};
+    DigitSortBufs pb{lw.keys_tmp,         lw.rids_tmp,          keys_out,
+                     rids_out,            lw.fb_radix.keys_tmp, lw.fb_radix.rids_tmp,
+                     lw.p_hist,           lw.p_mask,            lw.p_tile_start,
+                     lw.fb_radix.status0, lw.fb_radix.status1,  lw.fb_radix.counters,
+                     lw.fb_radix.max_tiles, lw.fb_radix.order};
     KPA_CHECK(digit_sort_launch<PivotDF>(pl, PivotDF::Params{lw.pivot}, pb, st, false));
   }
   KPA_LAUNCH("lds_sort_ranges", k_lds_sort_ranges, dim3(2048), dim3(BLOCK), 0, st, keys_out,

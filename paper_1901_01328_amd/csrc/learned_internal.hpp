@@ -65,6 +65,8 @@ struct LearnedWs {
   u64* keys_tmp;   // scatter ping-pong buffer; later the fallback's input
   u32* rids_tmp;
   SegModel* segm;  // n_seg
+  u64* cur_min;    // n_seg: smallest and largest key of each segment
+  u64* cur_max;
   u32* ltile_start;  // tile map of the scatter passes (n_seg + 1)
   u32* ftile_start;  // tile map of the finishing pass (n_seg + 1)
   u32* hist;       // n_seg * 8 * 256 (only 2 passes used)
@@ -72,6 +74,7 @@ struct LearnedWs {
   u32* status0;
   u32* status1;
   u32* counters;
+  OrderBufs order;
   u64* fb_lo;      // oversize chunks: [lo, hi)
   u64* fb_hi;
   u64* fb_rhi;     // hi for chunks to re-sort, lo for single-key chunks

@@ -84,6 +84,7 @@ kpa_status radix_sort_plan(u64 n_cap, u32 n_seg, Carver& c, RadixWs* w) {
   w->status0 = c.take<u32>(tiles * RADIX);
   w->status1 = c.take<u32>(tiles * RADIX);
   w->counters = c.take<u32>(16);
+  order_plan(c, tiles, n_seg, &w->order);
   w->max_tiles = tiles;
   w->max_seg = n_seg;
   return KPA_OK;
@@ -92,8 +93,9 @@ kpa_status radix_sort_plan(u64 n_cap, u32 n_seg, Carver& c, RadixWs* w) {
 kpa_status radix_sort_launch(const u64* keys_in, const u32* rids_in, u64* keys_out,
                              u32* rids_out, const SegList& sl, const RadixWs& w,
                              hipStream_t st) {
-  DigitSortBufs b{keys_in, rids_in, keys_out, rids_out, w.keys_tmp, w.rids_tmp, w.hist,
-                  w.seg_mask, w.tile_start, w.status0, w.status1, w.counters, w.max_tiles};
+  DigitSortBufs b{keys_in,    rids_in,       keys_out,   rids_out,  w.keys_tmp,
+                  w.rids_tmp, w.hist,        w.seg_mask, w.tile_start, w.status0,
+                  w.status1,  w.counters,    w.max_tiles, w.order};
   return digit_sort_launch<RadixDF>(sl, RadixDF::Params{}, b, st);
 }
 

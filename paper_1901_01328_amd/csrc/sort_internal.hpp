@@ -24,6 +24,37 @@ inline SegList seg_list_from_offsets(const u64* off, u32 n_seg) {
 // tile_start[s] = sum over s' < s of max(1, ceil(len(s')/tile)); tile_start[n] = total.
 kpa_status launch_seg_tiles_list(const SegList& sl, u32 tile, u32* tile_start, hipStream_t st);
 
+// One claimable tile of a scatter pass: where its entries are and which
+// look-back row (g, the tile's index in the segment-major tile map) it uses.
+struct TileDesc {
+  u64 base;   // first entry
+  u32 seg;
+  u32 t_in;   // tile index within the segment
+  u32 cnt;    // entries (0 for the one tile of an empty segment)
+  u32 g;      // tile_start[seg] + t_in
+  u32 mask;   // the segment's pass mask
+  u32 pad;
+};
+
+// Claim order of the scatter passes: round r holds tile r of every segment
+// that has more than r tiles, so that the workgroups in flight spread over
+// the segments and each segment's tiles are still claimed in order.
+struct OrderBufs {
+  TileDesc* desc;  // max_tiles, in claim order
+  u32* more;       // more[r] = segments with more than r tiles (max_tiles + 2)
+  u32* round0;     // round0[r] = first claim index of round r (max_tiles + 2)
+  u32* ties;       // per tile count: next position among equal segments (max_tiles + 2)
+  u32* pos;        // n_seg: position of the segment inside every round
+};
+
+inline void order_plan(Carver& c, u64 max_tiles, u32 n_seg, OrderBufs* o) {
+  o->desc = c.take<TileDesc>(max_tiles);
+  o->more = c.take<u32>(max_tiles + 2);
+  o->round0 = c.take<u32>(max_tiles + 2);
+  o->ties = c.take<u32>(max_tiles + 2);
+  o->pos = c.take<u32>(n_seg);
+}
+
 struct RadixDigit {
   u32 shift;
   __device__ __forceinline__ u32 operator()(u64 k) const { return (u32)(k >> shift) & 255u; }
@@ -37,7 +68,8 @@ struct RadixWs {
   u32* tile_start;  // n_seg + 1
   u32* status0;     // look-back words, max_tiles * 256, two alternating buffers
   u32* status1;
-  u32* counters;    // 16 tile counters (one per pass)
+  u32* counters;    // 16 tile counters (one per pass; [15]: passes needed by any segment)
+  OrderBufs order;
   u64 max_tiles;
   u32 max_seg;
 };
