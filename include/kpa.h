@@ -378,6 +378,118 @@ kpa_status kpa_mlp_train(float* params, float* adam_m, float* adam_v, const floa
 kpa_status kpa_mlp_to_pwl(const float* params, uint32_t n_seg_model, kpa_pwl_model* model,
                           hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Ingest (the engine receives record bundles in arrival order and keeps them
+ * as rows; Sec. 3 and 5): copies n rows from host memory (pinned for an
+ * asynchronous copy) to dev_rows (device, n*row_bytes, 16-byte aligned) on
+ * `stream` and, when ts_add != 0, adds ts_add (mod 2^64 for 8-byte, mod 2^32
+ * for 4-byte timestamps) to every row's timestamp on the device, so that a
+ * replayed bundle can be moved to a new event time.  The caller assigns rids
+ * (e.g. rid_base of kpa_partition_windows = the rows' arena index). */
+kpa_status kpa_ingest_bundle(const void* host_rows, uint64_t n, const kpa_row_layout* layout,
+                             uint64_t ts_add, void* dev_rows, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Serving loop (the runtime of Sec. 3 and 5: bundles processed as they
+ * arrive, windows closed by watermarks, merge of the window's sorted runs at
+ * close, a reserved pool for that urgent work, back-pressure when memory is
+ * short).  A server owns one device allocation of budget_bytes, `slots`
+ * streams for bundle work and one for window closes (all at the default
+ * priority), a dispatcher and a closer thread.
+ *
+ * Queries: KPA_Q_SUM (per key count/sum/max, top-10 keys by sum),
+ * KPA_Q_MEDIAN (lower median per key), KPA_Q_JOIN (two sides; per window the
+ * number of equal-key pairs and the sum of value products mod 2^64).  Windows
+ * are tumbling: [origin + w*win_len, origin + (w+1)*win_len).
+ *
+ * kpa_server_submit: one bundle of n rows (host memory that must stay valid
+ * and unchanged until kpa_server_drain returns or the server is destroyed;
+ * pinned memory for asynchronous copies) for query qid, side 0 (or 1 for the
+ * right side of a join).  Row timestamps are taken as ts + ts_base; every row
+ * must satisfy ts_lo <= ts <= ts_hi (the producer's bounds), and the bundle
+ * may span at most 8 windows.  The bundle is queued; the dispatcher admits it
+ * when a slot, ring rows and pool memory are free (rows of windows already
+ * closed are dropped and counted as late).  When max_pending bundles are
+ * queued, a blocking submit waits and a non-blocking one returns
+ * KPA_EBUDGET (back-pressure).
+ * kpa_server_watermark: no row with timestamp < t will follow for qid; every
+ * window of qid ending at or before t that received rows is closed and
+ * yields one kpa_window_result.  Watermarks are queued in order with the
+ * bundles and never refused.
+ * kpa_server_poll: takes one finished result (waits up to timeout_ms; *got=0
+ * if none).  kpa_server_drain: waits until every queued bundle and watermark
+ * has been processed and every close has finished (timeout_ms < 0: no limit).
+ * Latency of a window = time its result reached the host - time the closing
+ * watermark was submitted.
+ * A failure inside the server threads stops it; later calls return the
+ * failing status with the message in kpa_last_error_string(). */
+typedef enum kpa_query_kind { KPA_Q_SUM = 0, KPA_Q_MEDIAN = 1, KPA_Q_JOIN = 2 } kpa_query_kind;
+
+typedef struct kpa_server_config {
+  uint64_t budget_bytes;     /* device memory of the server, allocated once */
+  uint32_t slots;            /* bundles on the device at once (1..64) */
+  uint32_t rows_in_host;     /* 1: full rows are not kept in device memory */
+  uint64_t max_bundle_rows;  /* largest bundle */
+  uint32_t max_row_bytes;    /* largest row of any query (multiple of 8, <= 256) */
+  uint32_t max_pending;      /* queued bundles before submit applies back-pressure */
+  uint32_t reserve_pct;      /* % of the pool reserved for window closes (<= 90) */
+  uint32_t max_live_bundles; /* bundles admitted and not yet released */
+} kpa_server_config;
+
+typedef struct kpa_window_result {
+  uint32_t query;
+  uint32_t kind;        /* kpa_query_kind */
+  uint64_t window;      /* w: [origin + w*win_len, origin + (w+1)*win_len) */
+  uint64_t rows[2];     /* entries of the window per side */
+  uint64_t groups;      /* SUM/MEDIAN: distinct keys; JOIN: number of pairs */
+  uint64_t total;       /* SUM: sum of all values; JOIN: sum of value products (mod 2^64) */
+  uint64_t digest;      /* SUM/MEDIAN: sum over keys of h (mod 2^64), see below */
+  uint32_t n_top;       /* SUM: number of top keys (<= 10) */
+  uint32_t reserved;
+  uint64_t top_key[10]; /* SUM: keys by descending sum, ascending key */
+  uint64_t top_sum[10];
+  double latency_ms;
+} kpa_window_result;
+/* digest: with m(z) the SplitMix64 finalizer (z ^= z>>30; z *= 0xBF58476D1CE4E5B9;
+ * z ^= z>>27; z *= 0x94D049BB133111EB; z ^= z>>31), SUM: h = m(key ^ m(count ^
+ * m(sum ^ m(max)))); MEDIAN: h = m(key ^ m(median ^ m(0 ^ m(0)))).  It depends
+ * on every per-key result but not on their order. */
+
+typedef struct kpa_server_stats {
+  uint64_t bundles;            /* admitted */
+  uint64_t rows;               /* admitted rows */
+  uint64_t late_rows;          /* rows outside the open windows (dropped) */
+  uint64_t windows_closed;
+  uint64_t backpressure_waits; /* admissions that had to wait */
+  uint64_t pool_peak_bytes;
+  uint64_t pool_bytes;
+  double p50_ms, p99_ms, max_ms; /* window latency */
+  double elapsed_s;            /* first submit -> last result */
+  double mrec_per_s;           /* admitted rows / elapsed_s */
+} kpa_server_statistics;
+
+typedef struct kpa_server_s* kpa_server;
+
+/* budget 64 GiB, 8 slots, rows in device memory, bundles up to 2^20 rows of
+ * up to 32 bytes, 256 pending, 25% reserve, 65536 live bundles. */
+kpa_status kpa_server_config_default(kpa_server_config* cfg);
+kpa_status kpa_server_create(const kpa_server_config* cfg, kpa_server* out);
+/* ring_rows: rows of each side's value ring (and row ring), at least
+ * max_bundle_rows; rows stay there until every window they fall in is
+ * closed.  Served rows must be a multiple of 16 bytes. */
+kpa_status kpa_server_add_query(kpa_server server, kpa_query_kind kind,
+                                const kpa_row_layout* layout, uint64_t win_len,
+                                uint64_t win_origin, uint64_t ring_rows, uint32_t* qid);
+kpa_status kpa_server_submit(kpa_server server, uint32_t qid, uint32_t side, const void* rows,
+                             uint64_t n, uint64_t ts_base, uint64_t ts_lo, uint64_t ts_hi,
+                             int32_t blocking);
+kpa_status kpa_server_watermark(kpa_server server, uint32_t qid, uint64_t t);
+kpa_status kpa_server_poll(kpa_server server, kpa_window_result* out, int32_t* got,
+                           int32_t timeout_ms);
+kpa_status kpa_server_drain(kpa_server server, int32_t timeout_ms);
+kpa_status kpa_server_stats(kpa_server server, kpa_server_statistics* out);
+kpa_status kpa_server_destroy(kpa_server server);
+
 #ifdef __cplusplus
 }
 #endif

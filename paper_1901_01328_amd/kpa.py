@@ -31,6 +31,9 @@ KPA_EUNSUPPORTED = -5
 KPA_EHIP = -6
 KPA_SORT_RADIX = 0
 KPA_SORT_LEARNED = 1
+KPA_Q_SUM = 0
+KPA_Q_MEDIAN = 1
+KPA_Q_JOIN = 2
 KPA_PWL_MAX_SEG = 1024
 KPA_MLP_PARAMS = 1153
 PWL_MODEL_BYTES = 8 + 8 + 4 + 4 + 4 * (KPA_PWL_MAX_SEG + 1) + 12  # sizeof(kpa_pwl_model)
@@ -50,6 +53,38 @@ class kpa_batch_config(C.Structure):
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+class kpa_server_config(C.Structure):
+    _fields_ = [("budget_bytes", C.c_uint64), ("slots", C.c_uint32), ("rows_in_host", C.c_uint32),
+                ("max_bundle_rows", C.c_uint64), ("max_row_bytes", C.c_uint32),
+                ("max_pending", C.c_uint32), ("reserve_pct", C.c_uint32),
+                ("max_live_bundles", C.c_uint32)]
+
+
+class kpa_window_result(C.Structure):
+    _fields_ = [("query", C.c_uint32), ("kind", C.c_uint32), ("window", C.c_uint64),
+                ("rows", C.c_uint64 * 2), ("groups", C.c_uint64), ("total", C.c_uint64),
+                ("digest", C.c_uint64), ("n_top", C.c_uint32), ("reserved", C.c_uint32),
+                ("top_key", C.c_uint64 * 10), ("top_sum", C.c_uint64 * 10),
+                ("latency_ms", C.c_double)]
+
+    def as_dict(self):
+        return {"query": self.query, "kind": self.kind, "window": self.window,
+                "rows": (self.rows[0], self.rows[1]), "groups": self.groups, "total": self.total,
+                "digest": self.digest, "top_key": list(self.top_key)[:self.n_top],
+                "top_sum": list(self.top_sum)[:self.n_top], "latency_ms": self.latency_ms}
+
+
+class kpa_server_statistics(C.Structure):
+    _fields_ = [("bundles", C.c_uint64), ("rows", C.c_uint64), ("late_rows", C.c_uint64),
+                ("windows_closed", C.c_uint64), ("backpressure_waits", C.c_uint64),
+                ("pool_peak_bytes", C.c_uint64), ("pool_bytes", C.c_uint64),
+                ("p50_ms", C.c_double), ("p99_ms", C.c_double), ("max_ms", C.c_double),
+                ("elapsed_s", C.c_double), ("mrec_per_s", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class kpa_row_layout(C.Structure):
@@ -91,6 +126,17 @@ _SIGS = {
     "kpa_graph_end": ([_vp, C.POINTER(_vp)], C.c_int32),
     "kpa_graph_launch": ([_vp, _vp], C.c_int32),
     "kpa_graph_destroy": ([_vp], C.c_int32),
+    "kpa_ingest_bundle": ([_vp, _u64, _lay, _u64, _vp, _vp], C.c_int32),
+    "kpa_server_config_default": ([C.POINTER(kpa_server_config)], C.c_int32),
+    "kpa_server_create": ([C.POINTER(kpa_server_config), C.POINTER(_vp)], C.c_int32),
+    "kpa_server_add_query": ([_vp, C.c_int, _lay, _u64, _u64, _u64, C.POINTER(_u32)], C.c_int32),
+    "kpa_server_submit": ([_vp, _u32, _u32, _vp, _u64, _u64, _u64, _u64, C.c_int32], C.c_int32),
+    "kpa_server_watermark": ([_vp, _u32, _u64], C.c_int32),
+    "kpa_server_poll": ([_vp, C.POINTER(kpa_window_result), C.POINTER(C.c_int32), C.c_int32],
+                        C.c_int32),
+    "kpa_server_drain": ([_vp, C.c_int32], C.c_int32),
+    "kpa_server_stats": ([_vp, C.POINTER(kpa_server_statistics)], C.c_int32),
+    "kpa_server_destroy": ([_vp], C.c_int32),
     "kpa_merge_workspace_size": ([_u64, _u64, _sz], C.c_int32),
     "kpa_merge": ([_vp, _vp, _u64, _vp, _vp, _u64, _vp, _vp, _vp, C.c_size_t, _vp], C.c_int32),
     "kpa_merge_runs_workspace_size": ([_u64, _sz], C.c_int32),
@@ -581,3 +627,104 @@ def kpa_mlp_train(params, m, v, x, y, t0, steps, lr=1e-3, ws=None, stream=None):
 def kpa_mlp_to_pwl(params, model, n_seg_model=1024, stream=None):
     _call("kpa_mlp_to_pwl", _p(params), n_seg_model, _p(model), _stream(stream))
     return model
+
+
+# ---------------------------------------------------------------- serving --
+
+def kpa_ingest_bundle(host_rows, layout, dev_rows, ts_add=0, stream=None):
+    n = rows_count(host_rows, layout)
+    L = layout_struct(layout)
+    _call("kpa_ingest_bundle", C.c_void_p(host_rows.data_ptr()), n, C.byref(L), ts_add,
+          _p(dev_rows), _stream(stream))
+
+
+def _ts_column(rows, layout):
+    import numpy as np
+    a = rows.numpy() if hasattr(rows, "numpy") else rows
+    b = a.view(np.uint8).reshape(-1, layout.row_bytes)
+    w = layout.ts_w
+    col = b[:, layout.ts_off:layout.ts_off + w].copy().view(np.uint64 if w == 8 else np.uint32)
+    return col.reshape(-1)
+
+
+class Server:
+    """The serving loop (kpa_server_*).  Bundles are host tensors (pinned for
+    asynchronous copies) that the server reads until drain(); this object
+    keeps them alive until then."""
+
+    def __init__(self, **cfg):
+        c = kpa_server_config()
+        _call("kpa_server_config_default", C.byref(c))
+        for k, v in cfg.items():
+            setattr(c, k, int(v))
+        self.cfg = c
+        h = C.c_void_p(None)
+        _call("kpa_server_create", C.byref(c), C.byref(h))
+        self.h = h
+        self._keep = []
+        self._layouts = {}
+
+    def add_query(self, kind, layout, win_len, win_origin=0, ring_rows=1 << 24):
+        q = C.c_uint32(0)
+        L = layout_struct(layout)
+        _call("kpa_server_add_query", self.h, kind, C.byref(L), win_len, win_origin, ring_rows,
+              C.byref(q))
+        self._layouts[q.value] = layout
+        return q.value
+
+    def submit(self, qid, rows, side=0, ts_base=0, ts_lo=None, ts_hi=None, blocking=True):
+        lay = self._layouts[qid]
+        n = rows_count(rows, lay)
+        if n == 0:
+            return
+        if ts_lo is None or ts_hi is None:
+            ts = _ts_column(rows, lay)
+            ts_lo, ts_hi = int(ts.min()), int(ts.max())
+        self._keep.append(rows)
+        _call("kpa_server_submit", self.h, qid, side, C.c_void_p(rows.data_ptr()), n, ts_base,
+              ts_lo, ts_hi, 1 if blocking else 0)
+
+    def watermark(self, qid, t):
+        _call("kpa_server_watermark", self.h, qid, t)
+
+    def poll(self, timeout_ms=0):
+        r = kpa_window_result()
+        got = C.c_int32(0)
+        _call("kpa_server_poll", self.h, C.byref(r), C.byref(got), timeout_ms)
+        return r.as_dict() if got.value else None
+
+    def results(self):
+        out = []
+        while True:
+            r = self.poll(0)
+            if r is None:
+                return out
+            out.append(r)
+
+    def drain(self, timeout_ms=-1):
+        _call("kpa_server_drain", self.h, timeout_ms)
+        self._keep.clear()
+
+    def stats(self):
+        st = kpa_server_statistics()
+        _call("kpa_server_stats", self.h, C.byref(st))
+        return st.as_dict()
+
+    def close(self):
+        if self.h:
+            _call("kpa_server_destroy", self.h)
+            self.h = C.c_void_p(None)
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+        return False
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

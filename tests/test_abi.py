@@ -55,3 +55,22 @@ def test_host_side_errors_without_gpu():
     assert b"row_bytes" in lib.kpa_last_error_string()
     rc = lib.kpa_topk_by_sum(None, None, None, 1, 10, 17, None, None, None, None, 0, None)
     assert rc == k.KPA_EUNSUPPORTED
+
+
+def test_server_config_checked_on_the_host():
+    """Invalid serving configurations are refused before any device call."""
+    import paper_1901_01328_amd as P
+    k = P.load()
+    lib = k._lib
+    cfg = k.kpa_server_config()
+    assert lib.kpa_server_config_default(ctypes.byref(cfg)) == 0
+    assert cfg.budget_bytes == 64 << 30 and cfg.slots == 8
+    h = ctypes.c_void_p(None)
+    bad = k.kpa_server_config.from_buffer_copy(cfg)
+    bad.slots = 0
+    assert lib.kpa_server_create(ctypes.byref(bad), ctypes.byref(h)) == k.KPA_EINVAL
+    bad = k.kpa_server_config.from_buffer_copy(cfg)
+    bad.budget_bytes = 1 << 20          # cannot hold the slots' scratch
+    assert lib.kpa_server_create(ctypes.byref(bad), ctypes.byref(h)) == k.KPA_EBUDGET
+    assert b"budget" in lib.kpa_last_error_string()
+    assert not h.value

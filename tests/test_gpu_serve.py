@@ -1,0 +1,266 @@
+"""GPU tests of the serving loop: bundles admitted as slots and memory free
+up, windows closed by watermarks (merge of the window's sorted runs, then the
+query's operator), results compared window by window with the oracle, and
+the same query's results alone and in a mix of concurrent queries (and with
+rows kept on the host) are identical.  Back-pressure, late rows and early
+watermark application are forced from the host."""
+import numpy as np
+import pytest
+import torch
+
+import datagen
+from datagen.rows import LAYOUT32
+from gpu_util import kpa_mod, need_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+W = 10 ** 5          # window length (ns)
+SPAN = 12 * W        # event-time span of a stream
+
+
+@pytest.fixture(scope="module")
+def K():
+    need_gpu()
+    return kpa_mod()
+
+
+M1 = np.uint64(0xBF58476D1CE4E5B9)
+M2 = np.uint64(0x94D049BB133111EB)
+
+
+def fmix(z):
+    with np.errstate(over="ignore"):
+        z = (z ^ (z >> np.uint64(30))) * M1
+        z = (z ^ (z >> np.uint64(27))) * M2
+        return z ^ (z >> np.uint64(31))
+
+
+def digest(key, a, b=None, c=None):
+    z = np.zeros_like(key)
+    b = z if b is None else b
+    c = z if c is None else c
+    with np.errstate(over="ignore"):
+        return int(np.sum(fmix(key ^ fmix(a ^ fmix(b ^ fmix(c)))), dtype=np.uint64))
+
+
+def u64col(rows, i):
+    return rows[:, i].numpy().view(np.uint64)
+
+
+def stream_rows(kind, n, seed, side=0):
+    if kind == "sum":
+        return datagen.gen_c2(n, seed=seed, n_keys=3000, span_ns=SPAN)
+    return datagen.gen_c3(n, seed=seed, side=side, n_keys=20000, span_ns=SPAN)
+
+
+def bundles(n, seed, lo=9, hi=13):
+    rng = np.random.default_rng(seed)
+    cuts = [0]
+    while cuts[-1] < n:
+        cuts.append(min(n, cuts[-1] + int(2 ** rng.uniform(lo, hi))))
+    return list(zip(cuts[:-1], cuts[1:]))
+
+
+def expected(orc, kind, rows, rows_r=None):
+    """Per window (index -> summary) from the oracle's ordered-map operators."""
+    out = {}
+    ts = u64col(rows, 2)
+    wins = set((ts // W).tolist())
+    if rows_r is not None:
+        wins |= set((u64col(rows_r, 2) // W).tolist())
+    for w in sorted(wins):
+        m = np.nonzero(ts // W == w)[0]
+        keys = u64col(rows, 0)[m]
+        rids = m.astype(np.uint32)
+        if kind == "sum":
+            gk, gc, gs, gm = orc.reduce_by_key(keys, rids, rows, LAYOUT32)
+            tk, tsum = orc.topk_by_sum(gk, gs, 10)
+            with np.errstate(over="ignore"):
+                tot = int(np.sum(gs, dtype=np.uint64))
+            out[w] = {"rows": (len(m), 0), "groups": len(gk), "total": tot,
+                      "digest": digest(gk, gc, gs, gm), "top_key": list(map(int, tk)),
+                      "top_sum": list(map(int, tsum))}
+        elif kind == "median":
+            gk, gmed = orc.median_by_key(keys, rids, rows, LAYOUT32)
+            out[w] = {"rows": (len(m), 0), "groups": len(gk), "total": 0,
+                      "digest": digest(gk, gmed), "top_key": [], "top_sum": []}
+        else:
+            tr = u64col(rows_r, 2)
+            mr = np.nonzero(tr // W == w)[0]
+            cnt, sp, _, _ = orc.join(keys, rids, u64col(rows_r, 0)[mr], mr.astype(np.uint32),
+                                     rows, rows_r, LAYOUT32)
+            out[w] = {"rows": (len(m), len(mr)), "groups": cnt, "total": sp, "digest": 0,
+                      "top_key": [], "top_sum": []}
+    return out
+
+
+def summary(r):
+    return {k: r[k] for k in ("rows", "groups", "total", "digest", "top_key", "top_sum")}
+
+
+class Stream:
+    """One query's input: rows in arrival order, cut into bundles."""
+
+    def __init__(self, kind, n, seed):
+        self.kind = kind
+        self.rows = stream_rows(kind, n, seed)
+        self.rows_r = stream_rows(kind, n + 101, seed + 1, side=1) if kind == "join" else None
+        self.parts = [(0, a, b) for a, b in bundles(n, seed)]
+        if self.rows_r is not None:
+            self.parts += [(1, a, b) for a, b in bundles(n + 101, seed + 7)]
+            self.parts.sort(key=lambda p: (p[1], p[0]))
+        self.pinned = {}
+
+    def side_rows(self, side):
+        return self.rows if side == 0 else self.rows_r
+
+    def bundle(self, i):
+        side, a, b = self.parts[i]
+        key = (side, a, b)
+        if key not in self.pinned:
+            self.pinned[key] = self.side_rows(side)[a:b].contiguous().pin_memory()
+        return side, self.pinned[key]
+
+    def rid_layout(self):
+        return LAYOUT32
+
+    def watermark_after(self, i):
+        """Largest watermark that no later bundle violates: the smallest
+        timestamp still to come."""
+        rest = self.parts[i + 1:]
+        if not rest:
+            return SPAN + W
+        return min(int(u64col(self.side_rows(s)[a:b], 2).min()) for s, a, b in rest)
+
+
+def run(K, streams, order, **cfg):
+    """Submits the streams' bundles in `order` (list of (stream index, bundle
+    index)) with a watermark after every third bundle of a stream; returns
+    {stream index: {window: summary}} and the server's stats."""
+    srv = K.Server(budget_bytes=4 << 30, max_bundle_rows=1 << 14, **cfg)
+    kinds = {"sum": K.KPA_Q_SUM, "median": K.KPA_Q_MEDIAN, "join": K.KPA_Q_JOIN}
+    qids = [srv.add_query(kinds[s.kind], LAYOUT32, W, 0, ring_rows=1 << 20) for s in streams]
+    for si, bi in order:
+        s = streams[si]
+        side, rows = s.bundle(bi)
+        srv.submit(qids[si], rows, side=side)
+        if bi % 3 == 2:
+            srv.watermark(qids[si], s.watermark_after(bi))
+    for si, s in enumerate(streams):
+        srv.watermark(qids[si], SPAN + W)
+    srv.drain(timeout_ms=60000)
+    res = {si: {} for si in range(len(streams))}
+    for r in srv.results():
+        si = qids.index(r["query"])
+        assert r["window"] not in res[si], "window closed twice"
+        res[si][r["window"]] = summary(r)
+    st = srv.stats()
+    srv.close()
+    return res, st
+
+
+def order_alone(streams, si):
+    return [(si, b) for b in range(len(streams[si].parts))]
+
+
+def order_mixed(streams):
+    out, pos = [], [0] * len(streams)
+    while any(pos[i] < len(s.parts) for i, s in enumerate(streams)):
+        for i, s in enumerate(streams):
+            if pos[i] < len(s.parts):
+                out.append((i, pos[i]))
+                pos[i] += 1
+    return out
+
+
+@pytest.fixture(scope="module")
+def streams():
+    return [Stream("sum", 120000, 11), Stream("median", 90000, 21), Stream("join", 60000, 31)]
+
+
+@pytest.fixture(scope="module")
+def oracle_results(orc, streams):
+    return [expected(orc, s.kind, s.rows, s.rows_r) for s in streams]
+
+
+def check_against_oracle(res, exp):
+    assert set(res) == set(exp), (sorted(res), sorted(exp))
+    for w in exp:
+        assert res[w] == exp[w], (w, res[w], exp[w])
+
+
+@pytest.mark.parametrize("si", [0, 1, 2])
+def test_alone_matches_oracle(K, streams, oracle_results, si):
+    say(f"serve alone {streams[si].kind}")
+    res, st = run(K, streams, order_alone(streams, si))
+    check_against_oracle(res[si], oracle_results[si])
+    assert st["late_rows"] == 0 and st["windows_closed"] == len(oracle_results[si])
+
+
+@pytest.mark.parametrize("host_rows", [0, 1])
+def test_mixed_equals_alone_and_oracle(K, streams, oracle_results, host_rows):
+    say(f"serve mixed host_rows={host_rows}")
+    res, st = run(K, streams, order_mixed(streams), rows_in_host=host_rows, slots=4)
+    for si in range(len(streams)):
+        check_against_oracle(res[si], oracle_results[si])
+    assert st["p99_ms"] >= st["p50_ms"] > 0 and st["rows"] > 0
+
+
+def test_backpressure_and_early_watermarks(K, streams, oracle_results):
+    """A ring of two bundles per query and a pending queue of two: admission
+    must wait for closes, and watermarks queued behind a waiting bundle are
+    applied early when safe; a non-blocking submit reports back-pressure."""
+    s = streams[0]
+    srv = K.Server(budget_bytes=2 << 30, max_bundle_rows=1 << 13, max_pending=2, slots=1)
+    q = srv.add_query(K.KPA_Q_SUM, LAYOUT32, W, 0, ring_rows=6 << 13)
+    refused = 0
+    # cut the stream into bundles of at most 2^13 rows
+    parts = bundles(s.rows.shape[0], 5, lo=11, hi=13)
+    for i, (a, b) in enumerate(parts):
+        rows = s.rows[a:b].contiguous().pin_memory()
+        try:
+            srv.submit(q, rows, blocking=False)
+        except K.KpaError as e:
+            assert e.code == K.KPA_EBUDGET
+            refused += 1
+            srv.submit(q, rows, blocking=True)
+        nxt = parts[i + 1][0] if i + 1 < len(parts) else None
+        wm = SPAN + W if nxt is None else int(u64col(s.rows[nxt:], 2).min())
+        srv.watermark(q, wm)
+    srv.drain(timeout_ms=60000)
+    res = {r["window"]: summary(r) for r in srv.results()}
+    st = srv.stats()
+    srv.close()
+    say(f"refused {refused}, waits {st['backpressure_waits']}")
+    assert st["backpressure_waits"] > 0
+    check_against_oracle(res, oracle_results[0])
+
+
+def test_late_rows_are_counted_not_merged(K, streams):
+    s = streams[0]
+    ts = u64col(s.rows, 2)
+    first = np.nonzero(ts < W)[0]          # rows of window 0
+    srv = K.Server(budget_bytes=2 << 30, max_bundle_rows=1 << 17)
+    q = srv.add_query(K.KPA_Q_SUM, LAYOUT32, W, 0, ring_rows=1 << 18)
+    a = s.rows[first].contiguous().pin_memory()
+    srv.submit(q, a)
+    srv.watermark(q, W)                    # closes window 0
+    srv.submit(q, a)                       # the same rows again: all late
+    srv.watermark(q, 2 * W)
+    srv.drain(timeout_ms=60000)
+    res = srv.results()
+    st = srv.stats()
+    srv.close()
+    assert len(res) == 1 and res[0]["window"] == 0 and res[0]["rows"][0] == len(first)
+    assert st["late_rows"] == len(first)
+
+
+def test_ingest_rebases_timestamps(K):
+    rows = datagen.gen_c2(5000, seed=3, n_keys=100, span_ns=W).pin_memory()
+    dev = torch.empty_like(rows, device="cuda")
+    K.kpa_ingest_bundle(rows, LAYOUT32, dev, ts_add=7 * W + 3)
+    torch.cuda.synchronize()
+    got = dev.cpu()
+    exp = rows.clone()
+    exp[:, 2] += 7 * W + 3
+    assert torch.equal(got, exp)
