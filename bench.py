@@ -52,7 +52,10 @@ def parse():
                     help="rows of the oracle's CPU-baseline sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-check", action="store_true")
-    ap.add_argument("--workload", choices=["c2", "c4"], default="c2")
+    ap.add_argument("--workload", choices=["c2", "c4", "c5"], default="c2")
+    ap.add_argument("--duration", type=float, default=30.0, help="c5: seconds of offered load")
+    ap.add_argument("--rate", type=float, default=200e6, help="c5: offered records per second")
+    ap.add_argument("--host-rows", action="store_true", help="c5: keep full rows in host memory")
     ap.add_argument("--c4-windows", type=int, default=4096)
     ap.add_argument("--c4-hi-log2", type=int, default=22)
     ap.add_argument("--no-tune", action="store_true", help="c4: default batch configuration")
@@ -86,6 +89,8 @@ def main():
         del src, dst
     if a.workload == "c4":
         return bench_c4(a)
+    if a.workload == "c5":
+        return bench_c5(a)
     n = a.rows
     n_win, W = 10, 10 ** 9
     t0 = time.time()
@@ -364,6 +369,107 @@ def bench_c4(a):
                    "autotune_sort_ms": tune_ms},
         "roofline": roof, "cpu_baseline": cpu, "passes": passes, "sort_stats": st,
         "check": check,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_c5(a):
+    """Serving: Poisson-arriving bundles (sizes log-uniform 2^13..2^20 rows)
+    at the offered rate over 16 queries (8 windowed sums, 4 medians, 4 joins
+    whose bundles alternate sides), 1 s tumbling windows with origins
+    staggered by 1/16 s, a watermark per query every 100 ms of event time.
+    Bundles are replayed from pinned pools of pre-generated rows, moved to
+    their event time at ingest.  Reports sustained Mrec/s and the p50/p99 of
+    window-close-to-result latency."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_1901_01328_amd as P
+    from datagen.rows import LAYOUT32
+    K = P.load()
+    dev = torch.device("cuda:0")
+    pool_rows = 1 << 25
+    t0 = time.time()
+    pools = []
+    for kind in ("sum", "c3"):
+        rows = (datagen.gen_c2(pool_rows, seed=52, device=dev) if kind == "sum"
+                else datagen.gen_c3(pool_rows, seed=53, device=dev))
+        i = torch.arange(pool_rows, dtype=torch.int64, device=dev)
+        rows[:, 2] = datagen.uniform_int(datagen.splitmix64(54, 9, i), 10 ** 6)  # 1 ms jitter
+        host = torch.empty(rows.shape, dtype=rows.dtype, pin_memory=True)
+        host.copy_(rows)
+        pools.append(host)
+        del rows, i
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    print(f"[bench] c5 pools of {pool_rows} rows generated in {time.time() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    W = 10 ** 9
+    srv = K.Server(budget_bytes=64 << 30, slots=8, rows_in_host=1 if a.host_rows else 0,
+                   max_bundle_rows=1 << 20, max_pending=1024)
+    kinds = [K.KPA_Q_SUM] * 8 + [K.KPA_Q_MEDIAN] * 4 + [K.KPA_Q_JOIN] * 4
+    qids = [srv.add_query(k, LAYOUT32, W, q * (W // 16)) for q, k in enumerate(kinds)]
+    rng = np.random.default_rng(55)
+    mean_rows = (2 ** 20 - 2 ** 13) / np.log(2 ** 7)      # log-uniform mean
+    lam = a.rate / mean_rows                             # bundles per second
+    side_next = [0] * len(qids)
+    n_sub = 0
+    last_wm = [0] * len(qids)
+    start = time.perf_counter()
+    t_next = 0.0
+    last_print = 0.0
+    while True:
+        t_next += rng.exponential(1.0 / lam)
+        if t_next > a.duration:
+            break
+        now = time.perf_counter() - start
+        if t_next > now:
+            time.sleep(t_next - now)
+        n = int(2 ** rng.uniform(13, 20))
+        q = n_sub % len(qids)
+        pool = pools[0] if kinds[q] == K.KPA_Q_SUM else pools[1]
+        off = int(rng.integers(0, pool_rows - n))
+        side = 0
+        if kinds[q] == K.KPA_Q_JOIN:
+            side = side_next[q]
+            side_next[q] ^= 1
+        ev = int(t_next * 1e9) + W        # event time of the bundle (ns)
+        srv.submit(qids[q], pool[off:off + n], side=side, ts_base=ev, ts_lo=0, ts_hi=10 ** 6 - 1)
+        n_sub += 1
+        # watermarks: every 100 ms of event time, at the latest arrival
+        for qq in range(len(qids)):
+            if ev - last_wm[qq] >= 10 ** 8:
+                srv.watermark(qids[qq], ev)
+                last_wm[qq] = ev
+        if now - last_print > 5:
+            st = srv.stats()
+            print(f"[bench] c5 t={now:.1f}s bundles={n_sub} closed={st['windows_closed']} "
+                  f"p99={st['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
+            last_print = now
+    end_ev = int(a.duration * 1e9) + 2 * W + 10 ** 6
+    for qq in range(len(qids)):
+        srv.watermark(qids[qq], end_ev)
+    srv.drain(timeout_ms=120000)
+    st = srv.stats()
+    res = srv.results()
+    srv.close()
+    lat = sorted(r["latency_ms"] for r in res)
+    # the closes at the end (after the last watermark) are not steady state
+    steady = [r["latency_ms"] for r in res if r["window"] < int(a.duration) - 1]
+    steady.sort()
+    pct = (lambda v, p: v[min(len(v) - 1, int(p * (len(v) - 1) + 0.5))] if v else None)
+    out = {
+        "metric": METRIC, "value": round(st["mrec_per_s"], 2), "unit": "Mrec/s", "n_gpus": 1,
+        "steps": n_sub, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "serving: Poisson bundles of 2^13..2^20 32-byte rows at "
+                   f"{a.rate / 1e6:.0f} M rec/s offered, 8 sum + 4 median + 4 join queries, "
+                   "1 s windows, watermark every 100 ms", "duration_s": a.duration,
+                   "rows_in_host": bool(a.host_rows), "budget_gib": 64},
+        "latency_ms": {"p50": pct(steady, 0.5), "p99": pct(steady, 0.99), "max": lat[-1] if lat
+                       else None, "windows": len(steady)},
+        "server": st, "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
 

@@ -474,12 +474,12 @@ typedef struct kpa_server_s* kpa_server;
  * up to 32 bytes, 256 pending, 25% reserve, 65536 live bundles. */
 kpa_status kpa_server_config_default(kpa_server_config* cfg);
 kpa_status kpa_server_create(const kpa_server_config* cfg, kpa_server* out);
-/* ring_rows: rows of each side's value ring (and row ring), at least
- * max_bundle_rows; rows stay there until every window they fall in is
- * closed.  Served rows must be a multiple of 16 bytes. */
+/* A bundle's memory (sorted keys and values, plus the rows when they are kept
+ * on the device) is taken from the pool at admission and returned when every
+ * window it has rows in is closed. */
 kpa_status kpa_server_add_query(kpa_server server, kpa_query_kind kind,
                                 const kpa_row_layout* layout, uint64_t win_len,
-                                uint64_t win_origin, uint64_t ring_rows, uint32_t* qid);
+                                uint64_t win_origin, uint32_t* qid);
 kpa_status kpa_server_submit(kpa_server server, uint32_t qid, uint32_t side, const void* rows,
                              uint64_t n, uint64_t ts_base, uint64_t ts_lo, uint64_t ts_hi,
                              int32_t blocking);

@@ -9,11 +9,14 @@
 //
 // Per bundle (dispatcher thread, on one of `slots` streams): ingest
 // (host -> device copy, timestamps rebased), partition into the windows the
-// bundle touches (values staged into the query's value ring), stable sort of
-// each window's part.  The bundle keeps its sorted runs in the pool until
-// every window it touches is closed.
+// bundle touches with the value column staged, stable sort of each window's
+// part, and the values gathered into the sorted order.  The bundle keeps its
+// sorted runs (key and value per entry) in the pool until every window it
+// touches is closed, then releases them; nothing is held in arrival order, so
+// a bundle that straddles two windows pins only its own memory.
 // Per closed window (closer thread, own stream): the runs of all bundles of
-// that window are gathered and merged into one sorted KPA, then reduced
+// that window are concatenated (keys, and values that the KPA's pointers
+// index) and merged into one sorted KPA, then reduced
 // (SUM: count/sum/max per key and top-10 by sum; MEDIAN: lower median per
 // key; JOIN: merge-join of the two sides' KPAs), and a small summary is
 // copied to the host.
@@ -32,6 +35,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <set>
 #include <thread>
 #include <vector>
 
@@ -161,25 +165,16 @@ class Pool {
 struct Bundle {
   u32 q = 0, side = 0;
   u64 n = 0;
-  u64 ring_abs = 0;  // absolute ring position of the first row (monotone)
-  u64 ring_off = 0;  // position in the ring (the rows' rid base)
   u64 w_lo = 0;      // first window
   u32 n_win = 0;
-  u64* keys = nullptr;  // sorted runs (n keys then n rids) in the pool
-  u32* rids = nullptr;
-  u64 kpa_bytes = 0;
-  u64* h_off = nullptr;  // pinned: window offsets [n_win + 1], then out-of-range count
+  void* block = nullptr;  // pool memory: keys | values | rows (rows only when kept on the device)
+  u64 bytes = 0;
+  u64* keys = nullptr;    // sorted runs of the windows, back to back
+  u64* vals = nullptr;    // value of each sorted entry
+  unsigned char* rows = nullptr;
+  u64* h_off = nullptr;   // pinned: window offsets [n_win + 1], then out-of-range count
   hipEvent_t done = nullptr;
-  int refs = 0;          // windows of this bundle not yet closed
-  bool released = false;
-};
-
-struct Side {
-  u64 cap = 0;                    // ring capacity in rows
-  u64* vals = nullptr;            // value ring (device)
-  unsigned char* rows = nullptr;  // row ring (device; null when rows stay on the host)
-  u64 head = 0, tail = 0;         // absolute positions
-  std::deque<Bundle*> live;       // in ring order
+  int refs = 0;           // windows of this bundle not yet closed
 };
 
 struct Query {
@@ -187,7 +182,6 @@ struct Query {
   kpa_row_layout layout{};
   u64 win_len = 1, origin = 0;
   int sides = 1;
-  Side side[2];
   u64 next_close = 0;  // first window not closed
   u64 wm = 0;
   bool have_wm = false;
@@ -216,6 +210,8 @@ struct Slot {
   bool used = false;
   u64* pkeys = nullptr;  // partition output (max_n)
   u32* prids = nullptr;
+  u64* pvals = nullptr;  // staged values in arrival order (max_n)
+  u32* srids = nullptr;  // sorted rids (max_n)
   u64* win_off = nullptr;  // MAX_BUNDLE_WINDOWS + 1
   u64* oob = nullptr;
   void* part_ws = nullptr;
@@ -238,6 +234,7 @@ struct kpa_server_s {
   std::vector<std::unique_ptr<kpa::Query>> queries;
   u64* h_records = nullptr;  // pinned per-bundle offset records
   std::vector<u32> free_records;
+  std::set<kpa::Bundle*> live_bundles;
   std::vector<hipEvent_t> event_pool;
 
   std::mutex mu;
@@ -294,32 +291,37 @@ hipEvent_t take_event(Server* s) {
   return e;
 }
 
-u64 kpa_bytes_for(u64 n) { return (n * 8 + ALIGN) + (n * 4 + ALIGN); }
+u64 rnd(u64 x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
-// Releases a bundle's pool memory and ring rows once no window needs it.
-// Caller holds the lock.
+// Releases a bundle once no window needs it.  Caller holds the lock.
 void release_bundle(Server* s, Bundle* b) {
-  s->pool.release(b->keys, b->kpa_bytes);
-  b->keys = nullptr;
-  b->rids = nullptr;
-  b->released = true;
-  Side& sd = s->queries[b->q]->side[b->side];
-  while (!sd.live.empty() && sd.live.front()->released) {
-    Bundle* f = sd.live.front();
-    sd.live.pop_front();
-    sd.tail = sd.live.empty() ? sd.head : sd.live.front()->ring_abs;
-    const u32 rec = (u32)((f->h_off - s->h_records) / RECORD_WORDS);
-    s->free_records.push_back(rec);
-    if (f->done) s->event_pool.push_back(f->done);
-    delete f;
-  }
+  s->pool.release(b->block, b->bytes);
+  s->free_records.push_back((u32)((b->h_off - s->h_records) / RECORD_WORDS));
+  if (b->done) s->event_pool.push_back(b->done);
+  s->live_bundles.erase(b);
+  delete b;
+}
+
+// vals_out[i] = vals[rids[i]] for i < *count (values into sorted order).
+__global__ void __launch_bounds__(BLOCK) k_gather_vals(const u32* __restrict__ rids,
+                                                       const u64* __restrict__ vals,
+                                                       const u64* __restrict__ count,
+                                                       u64* __restrict__ out) {
+  const u64 n = *count;
+  for (u64 i = (u64)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (u64)gridDim.x * BLOCK)
+    out[i] = vals[rids[i]];
+}
+
+__global__ void __launch_bounds__(BLOCK) k_iota(u32* __restrict__ out, u64 n) {
+  for (u64 i = (u64)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (u64)gridDim.x * BLOCK)
+    out[i] = (u32)i;
 }
 
 // --------------------------------------------------------- dispatcher --
 
 void close_windows(Server* s, const Cmd& c);
 
-// While bundle B waits for memory or ring rows, watermarks queued behind it
+// While bundle B waits for memory or a slot, watermarks queued behind it
 // may be the only way to free them.  A queued watermark is applied early
 // when it cannot close a window that a bundle still waiting before it (B
 // included) has rows in.  Caller holds the lock.
@@ -366,7 +368,7 @@ bool run_bundle(Server* s, const Cmd& c) {
       return true;
     }
     w_lo = std::max(w_lo, q.next_close);
-    Side& sd = q.side[c.side];
+    const u64 bytes = rnd(c.n * 8) * 2 + (s->cfg.rows_in_host ? 0 : rnd(c.n * L.row_bytes));
     bool waited = false;
     while (true) {
       if (s->stop) return false;
@@ -379,34 +381,28 @@ bool run_bundle(Server* s, const Cmd& c) {
           break;
         }
       }
-      // ring rows, contiguous
-      u64 pos = sd.head;
-      const u64 off = pos % sd.cap;
-      if (off + c.n > sd.cap) pos += sd.cap - off;
-      const bool ring_ok = pos + c.n - sd.tail <= sd.cap;
       const bool rec_ok = !s->free_records.empty();
       void* mem = nullptr;
-      if (si < s->slots.size() && ring_ok && rec_ok) mem = s->pool.try_alloc(kpa_bytes_for(c.n), false);
+      if (si < s->slots.size() && rec_ok) mem = s->pool.try_alloc(bytes, false);
       if (mem) {
         b = new Bundle;
         b->q = c.q;
         b->side = c.side;
         b->n = c.n;
-        b->ring_abs = pos;
-        b->ring_off = pos % sd.cap;
         b->w_lo = w_lo;
         b->n_win = (u32)(w_hi - w_lo + 1);
+        b->block = mem;
+        b->bytes = bytes;
         b->keys = static_cast<u64*>(mem);
-        b->rids = reinterpret_cast<u32*>(static_cast<char*>(mem) +
-                                         (c.n * 8 + ALIGN - 1) / ALIGN * ALIGN);
-        b->kpa_bytes = kpa_bytes_for(c.n);
+        b->vals = reinterpret_cast<u64*>(static_cast<char*>(mem) + rnd(c.n * 8));
+        if (!s->cfg.rows_in_host)
+          b->rows = reinterpret_cast<unsigned char*>(static_cast<char*>(mem) + 2 * rnd(c.n * 8));
         const u32 rec = s->free_records.back();
         s->free_records.pop_back();
         b->h_off = s->h_records + (u64)rec * RECORD_WORDS;
         b->done = take_event(s);
         b->refs = (int)b->n_win;
-        sd.head = pos + c.n;
-        sd.live.push_back(b);
+        s->live_bundles.insert(b);
         for (u64 w = w_lo; w <= w_hi; ++w) q.by_win[c.side][w].push_back(b);
         s->slots[si].used = true;
         s->n_bundles++;
@@ -417,7 +413,7 @@ bool run_bundle(Server* s, const Cmd& c) {
         s->n_waits++;
         waited = true;
       }
-      // back-pressure: wait for a close to free memory or ring rows, or for a slot
+      // back-pressure: wait for a close to free memory, or for a slot
       early_watermarks(s, c.q, w_lo);
       s->cv_space.wait_for(lk, std::chrono::microseconds(200));
     }
@@ -427,17 +423,20 @@ bool run_bundle(Server* s, const Cmd& c) {
     return false;
   }
   Slot& sl = s->slots[si];
-  Side& sd = q.side[c.side];
-  unsigned char* dev_rows =
-      sd.rows ? sd.rows + b->ring_off * L.row_bytes : sl.staging;
+  unsigned char* dev_rows = b->rows ? b->rows : sl.staging;
   kpa_status rc = kpa_ingest_bundle(c.rows, c.n, &L, c.ts_base, dev_rows, sl.st);
   if (rc == KPA_OK)
     rc = kpa_partition_windows(dev_rows, c.n, &L, q.win_len, q.origin + w_lo * q.win_len, b->n_win,
-                               (uint32_t)b->ring_off, sl.pkeys, sl.prids, sd.vals + b->ring_off,
-                               sl.win_off, sl.oob, sl.part_ws, sl.part_ws_bytes, sl.st);
+                               0, sl.pkeys, sl.prids, sl.pvals, sl.win_off, sl.oob, sl.part_ws,
+                               sl.part_ws_bytes, sl.st);
   if (rc == KPA_OK)
-    rc = kpa_sort_segmented(sl.pkeys, sl.prids, b->keys, b->rids, sl.win_off, b->n_win, c.n,
+    rc = kpa_sort_segmented(sl.pkeys, sl.prids, b->keys, sl.srids, sl.win_off, b->n_win, c.n,
                             KPA_SORT_RADIX, nullptr, nullptr, sl.sort_ws, sl.sort_ws_bytes, sl.st);
+  if (rc == KPA_OK) {
+    hipLaunchKernelGGL(k_gather_vals, dim3((u32)std::min<u64>(ceil_div(c.n, BLOCK), 2048)),
+                       dim3(BLOCK), 0, sl.st, sl.srids, sl.pvals, sl.win_off + b->n_win, b->vals);
+    if (hipGetLastError() != hipSuccess) rc = KPA_EHIP;
+  }
   if (rc == KPA_OK &&
       (hipMemcpyAsync(b->h_off, sl.win_off, (b->n_win + 1) * sizeof(u64), hipMemcpyDeviceToHost,
                       sl.st) != hipSuccess ||
@@ -548,10 +547,11 @@ struct CloseBufs {
   }
 };
 
-// Gathers the window's runs of one side into one sorted KPA (merge of the
-// runs).  Returns the entry count, or -1 on failure.
+// Concatenates the window's runs of one side (keys, and their values) and
+// merges them into one sorted KPA whose rids index the concatenated values.
+// Returns the entry count, or -1 on failure.
 long long merge_side(Server* s, CloseBufs& cb, const CloseJob& j, int side, u64** out_k,
-                     u32** out_r, hipStream_t st) {
+                     u32** out_r, u64** out_v, hipStream_t st) {
   std::vector<u64> off{0};
   std::vector<std::pair<const Bundle*, std::pair<u64, u64>>> parts;
   for (const Bundle* b : j.runs[side]) {
@@ -566,13 +566,16 @@ long long merge_side(Server* s, CloseBufs& cb, const CloseJob& j, int side, u64*
   const u64 n = off.back();
   *out_k = nullptr;
   *out_r = nullptr;
+  *out_v = nullptr;
   if (n == 0) return 0;
   u64* ck = static_cast<u64*>(cb.take(n * 8));
   u32* cr = static_cast<u32*>(cb.take(n * 4));
+  u64* cv = static_cast<u64*>(cb.take(n * 8));
   u64* mk = static_cast<u64*>(cb.take(n * 8));
   u32* mr = static_cast<u32*>(cb.take(n * 4));
   size_t wsb = 0;
-  if (!ck || !cr || !mk || !mr || kpa_merge_runs_workspace_size(n, &wsb) != KPA_OK) return -1;
+  if (!ck || !cr || !cv || !mk || !mr || kpa_merge_runs_workspace_size(n, &wsb) != KPA_OK)
+    return -1;
   void* ws = cb.take(wsb);
   if (!ws) return -1;
   for (size_t i = 0; i < parts.size(); ++i) {
@@ -580,14 +583,18 @@ long long merge_side(Server* s, CloseBufs& cb, const CloseJob& j, int side, u64*
     const u64 a = parts[i].second.first, len = parts[i].second.second;
     if (hipMemcpyAsync(ck + off[i], b->keys + a, len * 8, hipMemcpyDeviceToDevice, st) !=
             hipSuccess ||
-        hipMemcpyAsync(cr + off[i], b->rids + a, len * 4, hipMemcpyDeviceToDevice, st) !=
+        hipMemcpyAsync(cv + off[i], b->vals + a, len * 8, hipMemcpyDeviceToDevice, st) !=
             hipSuccess)
       return -1;
   }
+  hipLaunchKernelGGL(k_iota, dim3((u32)std::min<u64>(ceil_div(n, BLOCK), 4096)), dim3(BLOCK), 0,
+                     st, cr, n);
+  if (hipGetLastError() != hipSuccess) return -1;
   if (kpa_merge_runs(ck, cr, off.data(), (u32)parts.size(), mk, mr, ws, wsb, st) != KPA_OK)
     return -1;
   *out_k = mk;
   *out_r = mr;
+  *out_v = cv;
   return (long long)n;
 }
 
@@ -601,9 +608,10 @@ bool do_close(Server* s, const CloseJob& j, kpa_window_result* res) {
   res->window = j.w;
   u64* mk[2] = {nullptr, nullptr};
   u32* mr[2] = {nullptr, nullptr};
+  u64* mv[2] = {nullptr, nullptr};
   long long n[2] = {0, 0};
   for (int sd = 0; sd < q.sides; ++sd) {
-    n[sd] = merge_side(s, cb, j, sd, &mk[sd], &mr[sd], st);
+    n[sd] = merge_side(s, cb, j, sd, &mk[sd], &mr[sd], &mv[sd], st);
     if (n[sd] < 0) return false;
     res->rows[sd] = (u64)n[sd];
   }
@@ -615,7 +623,7 @@ bool do_close(Server* s, const CloseJob& j, kpa_window_result* res) {
   hipLaunchKernelGGL(k_set2, dim3(1), dim3(1), 0, st, small, (u64)0, (u64)n[0]);
   hipLaunchKernelGGL(k_set2, dim3(1), dim3(1), 0, st, small + 2, (u64)0, (u64)n[1]);
   if (hipGetLastError() != hipSuccess) return false;
-  const kpa_row_layout V{8, 0, 0, 8, 0, 8};  // value ring read as 8-byte rows
+  const kpa_row_layout V{8, 0, 0, 8, 0, 8};  // concatenated values read as 8-byte rows
   u64 host[8 + 2 * 10];
   std::memset(host, 0, sizeof(host));
   u32 n_top = 0;
@@ -631,7 +639,7 @@ bool do_close(Server* s, const CloseJob& j, kpa_window_result* res) {
     u64* top = static_cast<u64*>(cb.take(24 * 8));
     if (!rws || !tws || !top) return false;
     u64 *gk = g, *gc = g + N, *gs = g + 2 * N, *gm = g + 3 * N;
-    if (kpa_reduce_by_key(mk[0], mr[0], small, 1, N, q.side[0].vals, &V, gk, gc, gs, gm, nullptr,
+    if (kpa_reduce_by_key(mk[0], mr[0], small, 1, N, mv[0], &V, gk, gc, gs, gm, nullptr,
                           small + 8, rws, rwb, st) != KPA_OK ||
         kpa_topk_by_sum(gk, gs, small + 8, 1, N, 10, top, top + 10,
                         reinterpret_cast<u32*>(top + 20), tws, twb, st) != KPA_OK)
@@ -649,7 +657,7 @@ bool do_close(Server* s, const CloseJob& j, kpa_window_result* res) {
     if (!g || kpa_median_by_key_workspace_size(N, 1, &mwb) != KPA_OK) return false;
     void* mws = cb.take(mwb);
     if (!mws) return false;
-    if (kpa_median_by_key(mk[0], mr[0], small, 1, N, q.side[0].vals, &V, g, g + N, small + 8, mws,
+    if (kpa_median_by_key(mk[0], mr[0], small, 1, N, mv[0], &V, g, g + N, small + 8, mws,
                           mwb, st) != KPA_OK)
       return false;
     hipLaunchKernelGGL(k_digest, dim3(256), dim3(BLOCK), 0, st, g, g + N, nullptr, nullptr,
@@ -661,7 +669,7 @@ bool do_close(Server* s, const CloseJob& j, kpa_window_result* res) {
     void* jws = cb.take(jwb);
     if (!jws) return false;
     if (kpa_join(mk[0], mr[0], small, (u64)n[0], mk[1], mr[1], small + 2, (u64)n[1], 1,
-                 q.side[0].vals, q.side[1].vals, &V, small + 6, small + 7, nullptr, 0, nullptr,
+                 mv[0], mv[1], &V, small + 6, small + 7, nullptr, 0, nullptr,
                  jws, jwb, st) != KPA_OK)
       return false;
   }
@@ -754,12 +762,11 @@ void teardown(Server* s) {
     if (sl.st) (void)hipStreamSynchronize(sl.st);
   }
   if (s->close_st) (void)hipStreamSynchronize(s->close_st);
-  for (auto& qp : s->queries)
-    for (auto& sd : qp->side)
-      for (Bundle* b : sd.live) {
-        if (b->done) s->event_pool.push_back(b->done);
-        delete b;
-      }
+  for (Bundle* b : s->live_bundles) {
+    if (b->done) s->event_pool.push_back(b->done);
+    delete b;
+  }
+  s->live_bundles.clear();
   for (auto& sl : s->slots) {
     if (sl.last) (void)hipEventDestroy(sl.last);
     if (sl.st) (void)hipStreamDestroy(sl.st);
@@ -817,8 +824,8 @@ kpa_status kpa_server_create(const kpa_server_config* cfg, kpa_server* out) {
   size_t part_ws = 0, sort_ws = 0;
   KPA_CHECK(kpa_partition_windows_workspace_size(mb, MAX_BUNDLE_WINDOWS, &part_ws));
   KPA_CHECK(kpa_sort_workspace_size(mb, MAX_BUNDLE_WINDOWS, KPA_SORT_RADIX, &sort_ws));
-  auto rnd = [](u64 x) { return (x + ALIGN - 1) / ALIGN * ALIGN; };
-  const u64 slot_bytes = rnd(mb * 8) + rnd(mb * 4) + rnd((MAX_BUNDLE_WINDOWS + 2) * 8) +
+  const u64 slot_bytes = rnd(mb * 8) + rnd(mb * 4) + rnd(mb * 8) + rnd(mb * 4) +
+                         rnd((MAX_BUNDLE_WINDOWS + 2) * 8) +
                          rnd(part_ws) + rnd(sort_ws) +
                          (cfg->rows_in_host ? rnd(mb * cfg->max_row_bytes) : 0);
   const u64 fixed = slot_bytes * cfg->slots;
@@ -842,6 +849,10 @@ kpa_status kpa_server_create(const kpa_server_config* cfg, kpa_server* out) {
     sl.pkeys = reinterpret_cast<u64*>(p);
     p += rnd(mb * 8);
     sl.prids = reinterpret_cast<u32*>(p);
+    p += rnd(mb * 4);
+    sl.pvals = reinterpret_cast<u64*>(p);
+    p += rnd(mb * 8);
+    sl.srids = reinterpret_cast<u32*>(p);
     p += rnd(mb * 4);
     sl.win_off = reinterpret_cast<u64*>(p);
     sl.oob = sl.win_off + MAX_BUNDLE_WINDOWS + 1;
@@ -885,8 +896,7 @@ kpa_status kpa_server_create(const kpa_server_config* cfg, kpa_server* out) {
 }
 
 kpa_status kpa_server_add_query(kpa_server s, kpa_query_kind kind, const kpa_row_layout* layout,
-                                uint64_t win_len, uint64_t win_origin, uint64_t ring_rows,
-                                uint32_t* qid) {
+                                uint64_t win_len, uint64_t win_origin, uint32_t* qid) {
   clear_error();
   KPA_REQUIRE(s != nullptr && qid != nullptr, KPA_EINVAL, "null argument");
   KPA_REQUIRE(kind == KPA_Q_SUM || kind == KPA_Q_MEDIAN || kind == KPA_Q_JOIN, KPA_EINVAL,
@@ -894,11 +904,7 @@ kpa_status kpa_server_add_query(kpa_server s, kpa_query_kind kind, const kpa_row
   KPA_CHECK(check_layout(layout, true, true));
   KPA_REQUIRE(layout->row_bytes <= s->cfg.max_row_bytes, KPA_EINVAL,
               "row_bytes exceeds the server's max_row_bytes");
-  KPA_REQUIRE(layout->row_bytes % 16 == 0, KPA_EINVAL,
-              "served rows must be a multiple of 16 bytes (rows are placed back to back)");
   KPA_REQUIRE(win_len >= 1, KPA_EINVAL, "win_len must be >= 1");
-  KPA_REQUIRE(ring_rows >= s->cfg.max_bundle_rows && ring_rows <= (1ull << 32), KPA_EINVAL,
-              "ring_rows must lie in [max_bundle_rows, 2^32]");
   std::unique_ptr<Query> q(new Query);
   q->kind = (u32)kind;
   q->layout = *layout;
@@ -907,23 +913,6 @@ kpa_status kpa_server_add_query(kpa_server s, kpa_query_kind kind, const kpa_row
   q->sides = kind == KPA_Q_JOIN ? 2 : 1;
   std::lock_guard<std::mutex> lk(s->mu);
   KPA_REQUIRE(s->failed == KPA_OK, s->failed, "server failed: %s", s->fail_msg.c_str());
-  std::vector<std::pair<void*, u64>> got;
-  for (int sd = 0; sd < q->sides; ++sd) {
-    Side& side = q->side[sd];
-    side.cap = ring_rows;
-    const u64 vb = ring_rows * 8;
-    const u64 rb = s->cfg.rows_in_host ? 0 : ring_rows * layout->row_bytes;
-    side.vals = static_cast<u64*>(s->pool.try_alloc(vb, false));
-    if (side.vals) got.emplace_back(side.vals, vb);
-    if (rb) {
-      side.rows = static_cast<unsigned char*>(s->pool.try_alloc(rb, false));
-      if (side.rows) got.emplace_back(side.rows, rb);
-    }
-    if (!side.vals || (rb && !side.rows)) {
-      for (auto& g : got) s->pool.release(g.first, g.second);
-      KPA_REQUIRE(false, KPA_EBUDGET, "the budget cannot hold this query's rings");
-    }
-  }
   *qid = (u32)s->queries.size();
   s->queries.push_back(std::move(q));
   return KPA_OK;

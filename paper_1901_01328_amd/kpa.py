@@ -129,7 +129,7 @@ _SIGS = {
     "kpa_ingest_bundle": ([_vp, _u64, _lay, _u64, _vp, _vp], C.c_int32),
     "kpa_server_config_default": ([C.POINTER(kpa_server_config)], C.c_int32),
     "kpa_server_create": ([C.POINTER(kpa_server_config), C.POINTER(_vp)], C.c_int32),
-    "kpa_server_add_query": ([_vp, C.c_int, _lay, _u64, _u64, _u64, C.POINTER(_u32)], C.c_int32),
+    "kpa_server_add_query": ([_vp, C.c_int, _lay, _u64, _u64, C.POINTER(_u32)], C.c_int32),
     "kpa_server_submit": ([_vp, _u32, _u32, _vp, _u64, _u64, _u64, _u64, C.c_int32], C.c_int32),
     "kpa_server_watermark": ([_vp, _u32, _u64], C.c_int32),
     "kpa_server_poll": ([_vp, C.POINTER(kpa_window_result), C.POINTER(C.c_int32), C.c_int32],
@@ -664,11 +664,10 @@ class Server:
         self._keep = []
         self._layouts = {}
 
-    def add_query(self, kind, layout, win_len, win_origin=0, ring_rows=1 << 24):
+    def add_query(self, kind, layout, win_len, win_origin=0):
         q = C.c_uint32(0)
         L = layout_struct(layout)
-        _call("kpa_server_add_query", self.h, kind, C.byref(L), win_len, win_origin, ring_rows,
-              C.byref(q))
+        _call("kpa_server_add_query", self.h, kind, C.byref(L), win_len, win_origin, C.byref(q))
         self._layouts[q.value] = layout
         return q.value
 

@@ -139,7 +139,7 @@ def run(K, streams, order, **cfg):
     {stream index: {window: summary}} and the server's stats."""
     srv = K.Server(budget_bytes=4 << 30, max_bundle_rows=1 << 14, **cfg)
     kinds = {"sum": K.KPA_Q_SUM, "median": K.KPA_Q_MEDIAN, "join": K.KPA_Q_JOIN}
-    qids = [srv.add_query(kinds[s.kind], LAYOUT32, W, 0, ring_rows=1 << 20) for s in streams]
+    qids = [srv.add_query(kinds[s.kind], LAYOUT32, W, 0) for s in streams]
     for si, bi in order:
         s = streams[si]
         side, rows = s.bundle(bi)
@@ -207,12 +207,14 @@ def test_mixed_equals_alone_and_oracle(K, streams, oracle_results, host_rows):
 
 
 def test_backpressure_and_early_watermarks(K, streams, oracle_results):
-    """A ring of two bundles per query and a pending queue of two: admission
-    must wait for closes, and watermarks queued behind a waiting bundle are
-    applied early when safe; a non-blocking submit reports back-pressure."""
+    """A pool that holds only a few bundles beside the close reserve, one
+    slot and a pending queue of two: admission must wait for closes, and
+    watermarks queued behind a waiting bundle are applied early when safe; a
+    non-blocking submit reports back-pressure."""
     s = streams[0]
-    srv = K.Server(budget_bytes=2 << 30, max_bundle_rows=1 << 13, max_pending=2, slots=1)
-    q = srv.add_query(K.KPA_Q_SUM, LAYOUT32, W, 0, ring_rows=6 << 13)
+    srv = K.Server(budget_bytes=80 << 20, max_bundle_rows=1 << 13, max_pending=2, slots=1,
+                   reserve_pct=90)
+    q = srv.add_query(K.KPA_Q_SUM, LAYOUT32, W, 0)
     refused = 0
     # cut the stream into bundles of at most 2^13 rows
     parts = bundles(s.rows.shape[0], 5, lo=11, hi=13)
@@ -241,7 +243,7 @@ def test_late_rows_are_counted_not_merged(K, streams):
     ts = u64col(s.rows, 2)
     first = np.nonzero(ts < W)[0]          # rows of window 0
     srv = K.Server(budget_bytes=2 << 30, max_bundle_rows=1 << 17)
-    q = srv.add_query(K.KPA_Q_SUM, LAYOUT32, W, 0, ring_rows=1 << 18)
+    q = srv.add_query(K.KPA_Q_SUM, LAYOUT32, W, 0)
     a = s.rows[first].contiguous().pin_memory()
     srv.submit(q, a)
     srv.watermark(q, W)                    # closes window 0
