@@ -41,6 +41,28 @@ PASS_BYTES = {
 }
 
 
+def counted_traffic(kernel_row):
+    """HBM bytes per dispatch of a kernel from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the scatter
+    pass's sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "c2_radix_hbm_bytes.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    h = hashlib.sha256()
+    for f in ("onesweep.hpp", "digit_sort.hpp", "radix.hip"):
+        with open(os.path.join(ROOT, "paper_1901_01328_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if f"sha256 {h.hexdigest()[:16]}" not in text:
+        return None
+    for line in text.splitlines():
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) == 4 and cells[0] == kernel_row:
+            return int((float(cells[2]) + float(cells[3])) * 1e6)
+    return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -48,11 +70,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--algo", choices=["radix", "learned"], default="radix")
     ap.add_argument("--rows", type=int, default=1 << 28)
-    ap.add_argument("--cpu-rows", type=int, default=1 << 26,
+    ap.add_argument("--cpu-rows", type=int, default=3 << 26,
                     help="rows of the oracle's CPU-baseline sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-check", action="store_true")
-    ap.add_argument("--workload", choices=["c2", "c4", "c5"], default="c2")
+    ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5"], default="c2")
     ap.add_argument("--duration", type=float, default=30.0, help="c5: seconds of offered load")
     ap.add_argument("--rate", type=float, default=200e6, help="c5: offered records per second")
     ap.add_argument("--host-rows", action="store_true", help="c5: keep full rows in host memory")
@@ -91,6 +113,8 @@ def main():
         return bench_c4(a)
     if a.workload == "c5":
         return bench_c5(a)
+    if a.workload == "c3":
+        return bench_c3(a)
     n = a.rows
     n_win, W = 10, 10 ** 9
     t0 = time.time()
@@ -159,8 +183,10 @@ def main():
         bytes_per_launch = PASS_BYTES.get(dom, 24) * n * (active / n_win) / launches \
             if dom == "radix_pass" else PASS_BYTES.get(dom, 24) * n
         achieved = bytes_per_launch / (avg_ms / 1000.0) / 1e9
+        traffic = counted_traffic("k_ds_pass<RadixDF>") if dom == "radix_pass" and \
+            n == 1 << 28 else None
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": dom, "avg_ms": avg_ms, "bytes_per_launch": int(bytes_per_launch)}
 
     check = None
@@ -369,6 +395,105 @@ def bench_c4(a):
                    "autotune_sort_ms": tune_ms},
         "roofline": roof, "cpu_baseline": cpu, "passes": passes, "sort_stats": st,
         "check": check,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_c3(a):
+    """Temporal join + median: two streams of 2^26 32-byte rows, keys uniform
+    over 2^24 (one key table for both), values uniform over u64, 10 tumbling
+    1 s windows.  One step = partition + sort both streams, lower median per
+    key on both, merge-join per window (count, sum of products mod 2^64)."""
+    import concurrent.futures as cf
+
+    import numpy as np
+    import torch
+
+    import datagen
+    import oracle
+    import paper_1901_01328_amd as P
+    from datagen.rows import LAYOUT32
+    from paper_1901_01328_amd.pipeline import JoinMedian
+    K = P.load()
+    dev = torch.device("cuda:0")
+    n = 1 << 26
+    n_win, W = 10, 10 ** 9
+    rows_l = datagen.gen_c3(n, seed=3, side=0, device=dev)
+    rows_r = datagen.gen_c3(n, seed=3, side=1, device=dev)
+    pipe = JoinMedian(n, n, LAYOUT32, W, n_win, device=dev)
+    stream = torch.cuda.current_stream()
+    for _ in range(a.warmup):
+        pipe.step(rows_l, rows_r)
+    torch.cuda.synchronize()
+    K.kpa_profile_enable(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(a.steps):
+        pipe.step(rows_l, rows_r)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_step = max(ev0.elapsed_time(ev1), wall * 1000) / a.steps
+    passes = kernel_passes(K, a.steps, 2 * n, PASS_BYTES)
+    K.kpa_profile_enable(False)
+    value = 2 * n / (ms_step / 1000.0) / 1e6
+    print(f"[bench] c3 timed {a.steps} steps: {ms_step:.3f} ms/step", file=sys.stderr, flush=True)
+    # oracle: two windows (every entry of them), both operators
+    L, R = pipe.side
+    hl, hr = rows_l.cpu(), rows_r.cpu()
+    cnt = pipe.join["count"].cpu().numpy().view(np.uint64)
+    sp = pipe.join["sumprod"].cpu().numpy().view(np.uint64)
+    checked, ok = [3, 7], True
+    t1 = time.perf_counter()
+
+    def win(rows, w):
+        ts = rows[:, 2].numpy().view(np.uint64)
+        m = np.nonzero(ts // W == w)[0]
+        return rows[:, 0].numpy().view(np.uint64)[m], m.astype(np.uint32)
+
+    def one(w):
+        lk, lr = win(hl, w)
+        rk, rr = win(hr, w)
+        c, s_, _, _ = oracle.join(lk, lr, rk, rr, hl, hr, LAYOUT32)
+        mk, mm = oracle.median_by_key(lk, lr, hl, LAYOUT32)
+        return w, c, s_, mk, mm, len(lk) + len(rk)
+
+    with cf.ThreadPoolExecutor(len(checked)) as ex:
+        res = list(ex.map(one, checked))
+    dt = time.perf_counter() - t1
+    goff = L["med"]["gseg_off"].cpu().numpy().view(np.uint64)
+    gk = L["med"]["gkey"].cpu().numpy().view(np.uint64)
+    gm = L["med"]["gmed"].cpu().numpy().view(np.uint64)
+    m_rows = 0
+    for w, c, s_, mk, mm, nr in res:
+        a0, b0 = int(goff[w]), int(goff[w + 1])
+        ok = ok and int(cnt[w]) == c and int(sp[w]) == s_ and np.array_equal(gk[a0:b0], mk) \
+            and np.array_equal(gm[a0:b0], mm)
+        m_rows += nr
+    check = {"windows_checked": checked, "join_and_left_median_match_oracle": bool(ok),
+             "pairs_per_window": int(cnt[checked[0]])}
+    cpu = {"value": round(m_rows / dt / 1e6, 3), "unit": "Mrec/s", "cores": len(checked),
+           "kind": "oracle", "sample": f"windows {checked} of both streams ({m_rows} rows): "
+           f"ordered-map join + median per key, {dt:.1f} s"}
+    roof = None
+    if "radix_pass" in passes:
+        pl = passes["radix_pass"]
+        per_launch = 24 * 2 * n * 8 / pl["launches_per_step"]   # all 8 digits vary
+        achieved = per_launch / (pl["avg_ms"] / 1000.0) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "radix_pass", "avg_ms": pl["avg_ms"], "bytes_per_launch": int(per_launch)}
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "Mrec/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "temporal join + median per key: 2 x 2^26 32-byte rows, keys "
+                   "uniform over 2^24, 10 tumbling 1 s windows", "rows": 2 * n, "windows": n_win},
+        "roofline": roof, "cpu_baseline": cpu, "passes": passes, "check": check,
     }
     print(json.dumps(out), flush=True)
 

@@ -506,14 +506,17 @@ def kpa_topk_by_sum(gkey, gsum, gseg_off, k=10, g_cap=None, ws=None, stream=None
     return ok, osum, on
 
 
-def kpa_median_by_key(keys, rids, seg_off, rows, layout, n_cap=None, ws=None, stream=None):
+def kpa_median_by_key(keys, rids, seg_off, rows, layout, n_cap=None, ws=None, stream=None,
+                      outs=None):
     n_seg = seg_off.numel() - 1
     n_cap = keys.numel() if n_cap is None else n_cap
     dev = keys.device
     cap = max(n_cap, 1)
-    gkey = torch.empty(cap, dtype=torch.int64, device=dev)
-    gmed = torch.empty(cap, dtype=torch.int64, device=dev)
-    gseg = torch.empty(n_seg + 1, dtype=torch.int64, device=dev)
+    o = outs or {}
+    gkey = o["gkey"] if "gkey" in o else torch.empty(cap, dtype=torch.int64, device=dev)
+    gmed = o["gmed"] if "gmed" in o else torch.empty(cap, dtype=torch.int64, device=dev)
+    gseg = o["gseg_off"] if "gseg_off" in o else torch.empty(n_seg + 1, dtype=torch.int64,
+                                                               device=dev)
     nb = _ws_size("kpa_median_by_key_workspace_size", n_cap, n_seg)
     ws = _ws(nb, dev, ws)
     L = layout_struct(layout)
@@ -523,15 +526,20 @@ def kpa_median_by_key(keys, rids, seg_off, rows, layout, n_cap=None, ws=None, st
 
 
 def kpa_join(lk, lr, l_seg_off, rk, rr, r_seg_off, rows_l, rows_r, layout, pairs_cap=0,
-             nl_cap=None, nr_cap=None, ws=None, stream=None):
+             nl_cap=None, nr_cap=None, ws=None, stream=None, outs=None):
     n_seg = l_seg_off.numel() - 1
     nl_cap = lk.numel() if nl_cap is None else nl_cap
     nr_cap = rk.numel() if nr_cap is None else nr_cap
     dev = lk.device
-    count = torch.empty(n_seg, dtype=torch.int64, device=dev)
-    sumprod = torch.empty(n_seg, dtype=torch.int64, device=dev)
-    pairs = torch.empty((max(pairs_cap, 1), 3), dtype=torch.int64, device=dev) if pairs_cap else None
-    npairs = torch.empty(1, dtype=torch.int64, device=dev)
+    o = outs or {}
+    count = o["count"] if "count" in o else torch.empty(n_seg, dtype=torch.int64, device=dev)
+    sumprod = o["sumprod"] if "sumprod" in o else torch.empty(n_seg, dtype=torch.int64,
+                                                               device=dev)
+    pairs = None
+    if pairs_cap:
+        pairs = o["pairs"] if "pairs" in o else torch.empty((max(pairs_cap, 1), 3),
+                                                            dtype=torch.int64, device=dev)
+    npairs = o["npairs"] if "npairs" in o else torch.empty(1, dtype=torch.int64, device=dev)
     nb = _ws_size("kpa_join_workspace_size", nl_cap, nr_cap, n_seg)
     ws = _ws(nb, dev, ws)
     L = layout_struct(layout)

@@ -160,3 +160,56 @@ class BatchAggregation:
         with g:
             self.step(rows, stream=stream, cfg=cfg)
         return g
+
+
+class JoinMedian:
+    """Temporal join and median per key of two streams over tumbling windows
+    (Sec. 4.2 temporal join; Sec. 6 windowed median per key): each stream is
+    partitioned into window KPAs (value column staged), each window's KPA is
+    sorted, the lower median of every key is computed on both streams, and
+    the two sorted KPAs are merge-joined window by window (count and sum of
+    value products mod 2^64)."""
+
+    def __init__(self, n_l, n_r, layout, win_len, n_win, device="cuda", win_origin=0):
+        self.n = (n_l, n_r)
+        self.layout, self.win_len, self.n_win, self.origin = layout, win_len, n_win, win_origin
+        d = torch.device(device)
+        i64 = dict(dtype=torch.int64, device=d)
+        i32 = dict(dtype=torch.int32, device=d)
+        u8 = dict(dtype=torch.uint8, device=d)
+        self.side = []
+        for n in self.n:
+            cap = max(n, 1)
+            sd = {
+                "keys": torch.empty(cap, **i64), "rids": torch.empty(cap, **i32),
+                "vals": torch.empty(cap, **i64), "skeys": torch.empty(cap, **i64),
+                "srids": torch.empty(cap, **i32), "off": torch.empty(n_win + 1, **i64),
+                "oob": torch.empty(1, **i64),
+                "med": {"gkey": torch.empty(cap, **i64), "gmed": torch.empty(cap, **i64),
+                        "gseg_off": torch.empty(n_win + 1, **i64)},
+                "ws_part": torch.empty(K._ws_size("kpa_partition_windows_workspace_size", n,
+                                                  n_win), **u8),
+                "ws_sort": torch.empty(K.kpa_sort_workspace_size(n, n_win), **u8),
+                "ws_med": torch.empty(K._ws_size("kpa_median_by_key_workspace_size", n, n_win),
+                                      **u8),
+            }
+            self.side.append(sd)
+        self.ws_join = torch.empty(K._ws_size("kpa_join_workspace_size", n_l, n_r, n_win), **u8)
+        self.join = {"count": torch.empty(n_win, **i64), "sumprod": torch.empty(n_win, **i64),
+                     "npairs": torch.empty(1, **i64)}
+
+    def step(self, rows_l, rows_r, stream=None):
+        for sd, rows, n in zip(self.side, (rows_l, rows_r), self.n):
+            K.kpa_partition_windows(rows, self.layout, self.win_len, self.n_win,
+                                    win_origin=self.origin, n=n, out_keys=sd["keys"],
+                                    out_rids=sd["rids"], out_win_off=sd["off"], out_oob=sd["oob"],
+                                    ws=sd["ws_part"], stream=stream, out_vals=sd["vals"])
+            K.kpa_sort_segmented(sd["keys"], sd["rids"], sd["off"], n_cap=n,
+                                 keys_out=sd["skeys"], rids_out=sd["srids"], ws=sd["ws_sort"],
+                                 stream=stream)
+            K.kpa_median_by_key(sd["skeys"], sd["srids"], sd["off"], sd["vals"], VALUE_COLUMN,
+                                n_cap=n, ws=sd["ws_med"], stream=stream, outs=sd["med"])
+        L, R = self.side
+        K.kpa_join(L["skeys"], L["srids"], L["off"], R["skeys"], R["srids"], R["off"], L["vals"],
+                   R["vals"], VALUE_COLUMN, nl_cap=self.n[0], nr_cap=self.n[1], ws=self.ws_join,
+                   stream=stream, outs=self.join)
