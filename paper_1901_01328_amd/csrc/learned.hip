@@ -153,6 +153,9 @@ __global__ void __launch_bounds__(BLOCK) k_learned_setup(const kpa_pwl_model* __
   }
 }
 
+constexpr u32 SHORT_RUN = 64;  // runs up to this length are ranked by counting
+constexpr u32 LONG_RUNS = 64;  // long runs a chunk may split before the byte-wise sort
+
 struct FinishSmem {
   u32 whist[WAVES][RADIX];
   u32 lstart[RADIX];
@@ -164,7 +167,124 @@ struct FinishSmem {
   u32 srids[FCAP];
   u32 srel[FCAP];  // refined bucket id relative to the chunk's first bucket
   u32 flag;
+  u32 n_long;                // long runs with inversions still to split
+  u32 long_lo[LONG_RUNS];
+  u32 long_hi[LONG_RUNS];
 };
+
+// Stable ranks of the entries of a short stretch [s, e) of sm by (key,
+// position): each of the first e-s threads counts the entries that precede
+// its own, then all move at once.  e - s <= BLOCK.
+__device__ __forceinline__ void rank_short(FinishSmem& sm, u32 s, u32 e) {
+  const u32 tid = threadIdx.x;
+  u64 k = 0;
+  u32 r = 0, dst = 0;
+  const bool mine = tid < e - s;
+  if (mine) {
+    const u32 i = s + tid;
+    k = sm.skeys[i];
+    r = sm.srids[i];
+    u32 rank = 0;
+    for (u32 q = s; q < e; ++q) {
+      const u64 kq = sm.skeys[q];
+      rank += (kq < k) || (kq == k && q < i);
+    }
+    dst = s + rank;
+  }
+  __syncthreads();
+  if (mine) {
+    sm.skeys[dst] = k;
+    sm.srids[dst] = r;
+  }
+  __syncthreads();
+}
+
+// Sorts the registered long runs (runs of one refined id longer than
+// SHORT_RUN that are out of key order; typically a frequent key next to a
+// few others).  Each run is split stably three ways around the most frequent
+// of 64 evenly spaced sample keys: the equal part is final, a part of at
+// most SHORT_RUN entries is ranked by counting, a longer one is split again.
+// When more than LONG_RUNS runs or parts need splitting the chunk is left to
+// the byte-wise sort (sm.flag).
+__device__ void split_long_runs(FinishSmem& sm) {
+  const u32 tid = threadIdx.x;
+  const u32 lane = __lane_id();
+  __syncthreads();
+  for (u32 head = 0;; ++head) {
+    const u32 n_long = min(sm.n_long, LONG_RUNS);
+    if (head >= n_long || sm.flag) break;
+    const u32 s = sm.long_lo[head], e = sm.long_hi[head];
+    const u32 len = e - s;
+    // pivot: the mode of 64 evenly spaced keys (wave 0)
+    if (tid < 64) {
+      const u64 kv = sm.skeys[s + (u32)(((u64)lane * len) / 64)];
+      u32 c = 0;
+      for (int q = 0; q < 64; ++q) c += __shfl(kv, q, 64) == kv;
+      u32 best = (c << 6) | (63u - lane);
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const u32 t = __shfl_xor(best, o, 64);
+        best = t > best ? t : best;
+      }
+      const u64 piv = __shfl(kv, 63 - (int)(best & 63u), 64);
+      if (lane == 0) sm.red64[0] = piv;
+    }
+    __syncthreads();
+    const u64 piv = sm.red64[0];
+    // each thread owns a contiguous part of the run (at most ITEMS entries)
+    const u32 per = (len + BLOCK - 1) / BLOCK;
+    const u32 b0 = min(len, tid * per), b1 = min(len, b0 + per);
+    u64 kk[ITEMS];
+    u32 rr[ITEMS];
+    u32 lt = 0, eq = 0;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      const u32 o = b0 + (u32)j;
+      if (o < b1) {
+        kk[j] = sm.skeys[s + o];
+        rr[j] = sm.srids[s + o];
+        lt += kk[j] < piv;
+        eq += kk[j] == piv;
+      }
+    }
+    u32 tot;
+    const u32 ex = block_excl_sum(lt | (eq << 16), sm.scan, &tot);  // ends with a barrier
+    const u32 LT = tot & 0xFFFFu, EQ = tot >> 16;
+    u32 plt = s + (ex & 0xFFFFu), peq = s + LT + (ex >> 16);
+    u32 pgt = s + LT + EQ + (b0 - (ex & 0xFFFFu) - (ex >> 16));
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      const u32 o = b0 + (u32)j;
+      if (o < b1) {
+        const u32 d = kk[j] < piv ? plt++ : (kk[j] == piv ? peq++ : pgt++);
+        sm.skeys[d] = kk[j];
+        sm.srids[d] = rr[j];
+      }
+    }
+    __syncthreads();
+    // the parts below and above the pivot
+    const u32 part_lo[2] = {s, s + LT + EQ};
+    const u32 part_hi[2] = {s + LT, e};
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const u32 pl = part_lo[q], ph = part_hi[q];
+      if (ph - pl <= 1) continue;
+      if (ph - pl <= SHORT_RUN) {
+        rank_short(sm, pl, ph);
+      } else if (tid == 0) {
+        const u32 idx = sm.n_long;
+        if (idx < LONG_RUNS) {
+          sm.long_lo[idx] = pl;
+          sm.long_hi[idx] = ph;
+          sm.n_long = idx + 1;
+        } else {
+          sm.flag = 1;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
 
 // Stable on-chip sort of the chunk [0, m) in sm using the model once more:
 // entries are ranked by their refined bucket id (8 more bits of F, given in
@@ -231,7 +351,10 @@ __device__ bool lds_sort_model(FinishSmem& sm, const SegModel& m, u32 mcount) {
   // sorted by the thread holding its start; a long run is left alone when it
   // has no inversion (typically one repeated key) and otherwise sends the
   // chunk to the byte-wise sort.
-  if (tid == 0) sm.flag = 0;
+  if (tid == 0) {
+    sm.flag = 0;
+    sm.n_long = 0;
+  }
   u32 stm = 0, lastm = 0, invm = 0, rs[ITEMS];
   u32 carry = 0;
   const u32 lane = __lane_id();
@@ -289,8 +412,16 @@ __device__ bool lds_sort_model(FinishSmem& sm, const SegModel& m, u32 mcount) {
     if (i >= mcount) continue;
     const u32 s0 = rs[j], re = sm.srel[s0], e = re & 0x7FFFFFFFu;
     if (!(re >> 31)) continue;  // run already in order
-    if (e - s0 > 64) {
-      sm.flag = 1;
+    if (e - s0 > SHORT_RUN) {
+      if (i == s0) {  // the run's start registers it for the three-way splits
+        const u32 idx = atomicAdd(&sm.n_long, 1u);
+        if (idx < LONG_RUNS) {
+          sm.long_lo[idx] = s0;
+          sm.long_hi[idx] = e;
+        } else {
+          sm.flag = 1;
+        }
+      }
       continue;
     }
     const u64 k = sm.skeys[i];
@@ -312,6 +443,7 @@ __device__ bool lds_sort_model(FinishSmem& sm, const SegModel& m, u32 mcount) {
       sm.srids[np[j]] = nr[j];
     }
   __syncthreads();
+  if (!sm.flag) split_long_runs(sm);
   if (sm.flag) lds_sort(sm, mcount);
   return true;
 }
@@ -356,6 +488,9 @@ __global__ void __launch_bounds__(BLOCK, 2) k_learned_finish(
   u64 start = a;
   if (k > 0) {
     const u32 span = (u32)min<u64>(FH, b - pos0);
+    // bucket ids never decrease along the segment: no bucket starts in the
+    // stretch when both ends lie in the same bucket
+    if (model_bucket(m, keys[pos0 - 1]) == model_bucket(m, keys[pos0 - 1 + span])) return;
     for (u32 i = tid; i <= span; i += BLOCK) sm.skeys[i] = keys[pos0 - 1 + i];
     __syncthreads();
     u32 first = NONE;
