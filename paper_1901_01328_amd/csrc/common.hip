@@ -90,6 +90,20 @@ __global__ void __launch_bounds__(256) k_fill(T* __restrict__ p, u64 n, T v) {
   for (; i < n; i += stride) p[i] = v;
 }
 
+__global__ void __launch_bounds__(BLOCK) k_tile_seg(const u32* __restrict__ tile_start, u32 n_seg,
+                                                   u64 max_tiles, u32* __restrict__ tile_seg) {
+  const u64 total = min<u64>(tile_start[n_seg], max_tiles);
+  for (u64 t = (u64)blockIdx.x * BLOCK + threadIdx.x; t < total; t += (u64)gridDim.x * BLOCK)
+    tile_seg[t] = find_seg(tile_start, n_seg, (u32)t);
+}
+
+kpa_status launch_tile_seg(const u32* tile_start, u32 n_seg, u64 max_tiles, u32* tile_seg,
+                           hipStream_t st) {
+  KPA_LAUNCH("tile_seg", k_tile_seg, dim3((u32)std::min<u64>(ceil_div(max_tiles, BLOCK), 4096)),
+             dim3(BLOCK), 0, st, tile_start, n_seg, max_tiles, tile_seg);
+  return KPA_OK;
+}
+
 kpa_status launch_fill_u32(u32* p, u64 n, u32 v, hipStream_t st) {
   if (n == 0) return KPA_OK;
   u64 blocks = std::min<u64>(ceil_div(n, 256), 8192);

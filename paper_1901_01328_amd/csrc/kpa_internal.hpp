@@ -108,6 +108,11 @@ inline u64 max_tiles(u64 n_cap, u32 n_seg, u64 tile) { return ceil_div(n_cap, ti
 kpa_status launch_seg_tiles(const u64* off_a, const u64* off_b, u32 n_seg, u32 tile,
                             u32* tile_start, hipStream_t st);
 kpa_status launch_fill_u32(u32* p, u64 n, u32 v, hipStream_t st);
+// tile_seg[t] = segment of tile t for every tile of a tile map (tile_start,
+// n_seg + 1 entries), so that per-tile kernels look their segment up with one
+// load instead of a binary search.  tile_seg holds max_tiles entries.
+kpa_status launch_tile_seg(const u32* tile_start, u32 n_seg, u64 max_tiles, u32* tile_seg,
+                           hipStream_t st);
 kpa_status launch_fill_u64(u64* p, u64 n, u64 v, hipStream_t st);
 
 }  // namespace kpa

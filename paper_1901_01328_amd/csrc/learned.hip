@@ -62,13 +62,14 @@ __device__ __forceinline__ void stat_add(kpa_sort_stats* st, int idx, u64 v) {
 // Smallest and largest key of every segment (one atomic pair per tile).
 __global__ void __launch_bounds__(BLOCK) k_seg_minmax(const u64* __restrict__ keys, SegList sl,
                                                       const u32* __restrict__ tile_start,
+                                                      const u32* __restrict__ tile_seg,
                                                       u64* __restrict__ kmin,
                                                       u64* __restrict__ kmax) {
   __shared__ u64 red[2 * WAVES];
   const u32 n_seg = sl.n();
   const u32 total = tile_start[n_seg];
   for (u32 t = blockIdx.x; t < total; t += gridDim.x) {
-    const u32 s = find_seg(tile_start, n_seg, t);
+    const u32 s = tile_seg[t];
     const u64 a = sl.lo[s], b = sl.hi[s];
     const u64 base = a + (u64)(t - tile_start[s]) * TILE;
     const u64 end = min(b, base + TILE);
@@ -468,7 +469,8 @@ __device__ __forceinline__ void load_knots(FinishSmem& sm, SegModel& m) {
 // edges found do not depend on timing.
 __global__ void __launch_bounds__(BLOCK, 2) k_learned_finish(
     u64* __restrict__ keys, u32* __restrict__ rids, SegList sl,
-    const u32* __restrict__ ftile_start, const SegModel* __restrict__ segm,
+    const u32* __restrict__ ftile_start, const u32* __restrict__ ftile_seg,
+    const SegModel* __restrict__ segm,
     u64* __restrict__ fb_lo, u64* __restrict__ fb_hi, u32* __restrict__ fb_count, u32 max_fb,
     kpa_sort_stats* stats) {
   __shared__ FinishSmem sm;
@@ -476,7 +478,7 @@ __global__ void __launch_bounds__(BLOCK, 2) k_learned_finish(
   const u32 tile = blockIdx.x;
   const u32 n_seg = sl.n();
   if (tile >= ftile_start[n_seg]) return;
-  const u32 seg = find_seg(ftile_start, n_seg, tile);
+  const u32 seg = ftile_seg[tile];
   const u32 k = tile - ftile_start[seg];
   const u64 a = sl.lo[seg], b = sl.hi[seg];
   const u64 pos0 = a + (u64)k * FH;
@@ -783,6 +785,8 @@ kpa_status learned_sort_plan(u64 n_cap, u32 n_seg, Carver& c, LearnedWs* w) {
   w->cur_max = c.take<u64>(n_seg);
   w->ltile_start = c.take<u32>((u64)n_seg + 1);
   w->ftile_start = c.take<u32>((u64)n_seg + 1);
+  w->ltile_seg = c.take<u32>(w->max_tiles);
+  w->ftile_seg = c.take<u32>(w->max_ftiles);
   w->hist = c.take<u32>((u64)n_seg * 2 * RADIX);
   w->seg_mask = c.take<u32>(n_seg);
   w->status0 = c.take<u32>(w->max_tiles * RADIX);
@@ -821,10 +825,12 @@ kpa_status learned_sort_launch(const u64* keys_in, const u32* rids_in, u64* keys
   KPA_CHECK(launch_fill_u32(lw.fb_count, 1, 0, st));
   KPA_CHECK(launch_fill_u32(lw.rl_count, 4, 0, st));
   KPA_CHECK(launch_seg_tiles_list(sl, TILE, lw.ltile_start, st));
+  KPA_CHECK(launch_tile_seg(lw.ltile_start, n_seg, lw.max_tiles, lw.ltile_seg, st));
   KPA_CHECK(launch_fill_u64(lw.cur_min, n_seg, ~0ull, st));
   KPA_CHECK(launch_fill_u64(lw.cur_max, n_seg, 0ull, st));
   KPA_LAUNCH("learned_minmax", k_seg_minmax, dim3((u32)std::min<u64>(lw.max_tiles, 8192)),
-             dim3(BLOCK), 0, st, keys_in, sl, lw.ltile_start, lw.cur_min, lw.cur_max);
+             dim3(BLOCK), 0, st, keys_in, sl, lw.ltile_start, lw.ltile_seg, lw.cur_min,
+             lw.cur_max);
   KPA_LAUNCH("learned_setup", k_learned_setup, dim3(std::min<u32>(n_seg, 2048)), dim3(BLOCK), 0,
              st, models, sl, lw.cur_min, lw.cur_max, lw.segm, stats);
   DigitSortBufs b{keys_in,     rids_in,      keys_out,   rids_out,       lw.keys_tmp,
@@ -833,8 +839,9 @@ kpa_status learned_sort_launch(const u64* keys_in, const u32* rids_in, u64* keys
   KPA_CHECK(digit_sort_launch<LearnedDF>(sl, LearnedDF::Params{lw.segm}, b, st));
 
   KPA_CHECK(launch_seg_tiles_list(sl, FH, lw.ftile_start, st));
+  KPA_CHECK(launch_tile_seg(lw.ftile_start, n_seg, lw.max_ftiles, lw.ftile_seg, st));
   KPA_LAUNCH("learned_finish", k_learned_finish, dim3((u32)lw.max_ftiles), dim3(BLOCK), 0, st,
-             keys_out, rids_out, sl, lw.ftile_start, lw.segm, lw.fb_lo, lw.fb_hi,
+             keys_out, rids_out, sl, lw.ftile_start, lw.ftile_seg, lw.segm, lw.fb_lo, lw.fb_hi,
              lw.fb_count, lw.max_fb, stats);
 
   // Pivot rounds over the oversize chunks: round 0 reads the finishing pass's

@@ -77,9 +77,9 @@ struct TileRange {
 };
 
 __device__ __forceinline__ TileRange tile_range(const u64* seg_off, const u32* tile_start,
-                                                u32 n_seg, u32 tile, u32 tsize) {
+                                                const u32* tile_seg, u32 tile, u32 tsize) {
   TileRange r;
-  r.seg = find_seg(tile_start, n_seg, tile);
+  r.seg = tile_seg[tile];
   r.a = seg_off[r.seg];
   r.b = seg_off[r.seg + 1];
   r.base = r.a + (u64)(tile - tile_start[r.seg]) * tsize;
@@ -105,13 +105,14 @@ constexpr u32 PTILE = TILE + TILE / 16;
 __global__ void __launch_bounds__(BLOCK) k_reduce_heads(const u64* __restrict__ keys,
                                                         const u64* __restrict__ seg_off,
                                                         const u32* __restrict__ tile_start,
+                                                        const u32* __restrict__ tile_seg,
                                                         u32 n_seg, u32* __restrict__ heads,
                                                         u32* __restrict__ flags) {
   __shared__ u64 sk[PTILE];
   __shared__ u64 red[WAVES];
   const u32 tile = blockIdx.x;
   if (tile >= tile_start[n_seg]) return;
-  const TileRange tr = tile_range(seg_off, tile_start, n_seg, tile, TILE);
+  const TileRange tr = tile_range(seg_off, tile_start, tile_seg, tile, TILE);
   const u32 tid = threadIdx.x;
   for (u32 i = tid; i < tr.cnt; i += BLOCK) sk[pidx(i)] = keys[tr.base + i];
   const bool has_prev = tr.base > tr.a;
@@ -189,7 +190,8 @@ __global__ void __launch_bounds__(1024) k_reduce_scan(const u32* __restrict__ he
 // (integer sums and maxima are exact in any order).
 __global__ void __launch_bounds__(BLOCK) k_reduce_main(
     const u64* __restrict__ keys, const u32* __restrict__ rids, const u64* __restrict__ seg_off,
-    const u32* __restrict__ tile_start, u32 n_seg, ValSrc vs, const u64* __restrict__ gbase,
+    const u32* __restrict__ tile_start, const u32* __restrict__ tile_seg, u32 n_seg, ValSrc vs,
+    const u64* __restrict__ gbase,
     u64* __restrict__ o_key, u64* __restrict__ o_cnt, u64* __restrict__ o_sum,
     u64* __restrict__ o_max, u64* __restrict__ o_start) {
   __shared__ u64 sk[PTILE];
@@ -198,7 +200,7 @@ __global__ void __launch_bounds__(BLOCK) k_reduce_main(
   __shared__ u32 hsm[WAVES + 1];
   const u32 tile = blockIdx.x;
   if (tile >= tile_start[n_seg]) return;
-  const TileRange tr = tile_range(seg_off, tile_start, n_seg, tile, TILE);
+  const TileRange tr = tile_range(seg_off, tile_start, tile_seg, tile, TILE);
   const u32 tid = threadIdx.x;
   for (u32 i = tid; i < tr.cnt; i += BLOCK) {
     sk[pidx(i)] = keys[tr.base + i];
@@ -278,6 +280,7 @@ __global__ void __launch_bounds__(BLOCK) k_reduce_main(
 void reduce_plan(u64 n_cap, u32 n_seg, Carver& c, ReduceWs* w) {
   w->max_tiles = max_tiles(n_cap, n_seg, TILE);
   w->tile_start = c.take<u32>((u64)n_seg + 1);
+  w->tile_seg = c.take<u32>(w->max_tiles);
   w->heads = c.take<u32>(w->max_tiles);
   w->flags = c.take<u32>(w->max_tiles);
   w->gbase = c.take<u64>(w->max_tiles);
@@ -293,12 +296,14 @@ kpa_status reduce_launch(const u64* keys, const u32* rids, const u64* seg_off, u
   vs.val_w = L ? L->val_w : 8;
   vs.on = need_val ? 1u : 0u;
   KPA_CHECK(launch_seg_tiles(seg_off, nullptr, n_seg, TILE, w.tile_start, st));
+  KPA_CHECK(launch_tile_seg(w.tile_start, n_seg, w.max_tiles, w.tile_seg, st));
   KPA_LAUNCH("reduce_heads", k_reduce_heads, dim3((u32)w.max_tiles), dim3(BLOCK), 0, st, keys,
-             seg_off, w.tile_start, n_seg, w.heads, w.flags);
+             seg_off, w.tile_start, w.tile_seg, n_seg, w.heads, w.flags);
   KPA_LAUNCH("reduce_scan", k_reduce_scan, dim3(1), dim3(1024), 0, st, w.heads, w.flags,
              w.tile_start, n_seg, w.gbase, o.gseg_off, o.cnt, o.sum, o.max);
   KPA_LAUNCH("reduce_main", k_reduce_main, dim3((u32)w.max_tiles), dim3(BLOCK), 0, st, keys, rids,
-             seg_off, w.tile_start, n_seg, vs, w.gbase, o.gkey, o.cnt, o.sum, o.max, o.gstart);
+             seg_off, w.tile_start, w.tile_seg, n_seg, vs, w.gbase, o.gkey, o.cnt, o.sum, o.max,
+             o.gstart);
   return KPA_OK;
 }
 
@@ -402,6 +407,7 @@ __global__ void __launch_bounds__(BLOCK) k_topk_local(const u64* __restrict__ gk
                                                       const u64* __restrict__ gsum,
                                                       const u64* __restrict__ gseg_off,
                                                       const u32* __restrict__ tile_start,
+                                                      const u32* __restrict__ tile_seg,
                                                       u32 n_seg, u32 k, u64* __restrict__ cs,
                                                       u64* __restrict__ ck,
                                                       u32* __restrict__ cn) {
@@ -410,7 +416,7 @@ __global__ void __launch_bounds__(BLOCK) k_topk_local(const u64* __restrict__ gk
   __shared__ u64 os[TOPK_MAX], ok[TOPK_MAX];
   const u32 tile = blockIdx.x;
   if (tile >= tile_start[n_seg]) return;
-  const TileRange tr = tile_range(gseg_off, tile_start, n_seg, tile, GT);
+  const TileRange tr = tile_range(gseg_off, tile_start, tile_seg, tile, GT);
   TopList L;
   L.init();
   for (u32 i = threadIdx.x; i < tr.cnt; i += BLOCK) L.insert(gsum[tr.base + i], gkey[tr.base + i]);
@@ -452,6 +458,7 @@ __global__ void __launch_bounds__(BLOCK) k_topk_final(const u64* __restrict__ cs
 
 struct TopkWs {
   u32* tile_start;
+  u32* tile_seg;
   u64* cs;
   u64* ck;
   u32* cn;
@@ -461,6 +468,7 @@ struct TopkWs {
 static void topk_plan(u64 g_cap, u32 n_seg, Carver& c, TopkWs* w) {
   w->max_tiles = max_tiles(g_cap, n_seg, GT);
   w->tile_start = c.take<u32>((u64)n_seg + 1);
+  w->tile_seg = c.take<u32>(w->max_tiles);
   w->cs = c.take<u64>(w->max_tiles * TOPK_MAX);
   w->ck = c.take<u64>(w->max_tiles * TOPK_MAX);
   w->cn = c.take<u32>(w->max_tiles);
@@ -534,8 +542,9 @@ kpa_status kpa_topk_by_sum(const uint64_t* gkey, const uint64_t* gsum, const uin
   topk_plan(g_cap, n_seg, c, &w);
   KPA_REQUIRE(c.used <= ws_bytes, KPA_EWORKSPACE, "workspace too small: need %zu bytes", c.used);
   KPA_CHECK(launch_seg_tiles(gseg_off, nullptr, n_seg, GT, w.tile_start, stream));
+  KPA_CHECK(launch_tile_seg(w.tile_start, n_seg, w.max_tiles, w.tile_seg, stream));
   KPA_LAUNCH("topk_local", k_topk_local, dim3((u32)w.max_tiles), dim3(BLOCK), 0, stream, gkey, gsum,
-                     gseg_off, w.tile_start, n_seg, k, w.cs, w.ck, w.cn);
+                     gseg_off, w.tile_start, w.tile_seg, n_seg, k, w.cs, w.ck, w.cn);
   KPA_LAUNCH("topk_final", k_topk_final, dim3(n_seg), dim3(BLOCK), 0, stream, w.cs, w.ck, w.cn,
                      w.tile_start, k, out_key, out_sum, out_n);
   return KPA_OK;

@@ -21,6 +21,7 @@ __device__ __forceinline__ SegAgg seg_combine(const SegAgg& a, const SegAgg& b) 
 
 struct ReduceWs {
   u32* tile_start;
+  u32* tile_seg;  // segment of each tile
   u32* heads;   // runs starting in each tile
   u32* flags;   // bit 0: the tile's last run continues into the next tile
   u64* gbase;   // groups started before each tile
