@@ -90,17 +90,19 @@ __global__ void __launch_bounds__(256) k_fill(T* __restrict__ p, u64 n, T v) {
   for (; i < n; i += stride) p[i] = v;
 }
 
-__global__ void __launch_bounds__(BLOCK) k_tile_seg(const u32* __restrict__ tile_start, u32 n_seg,
-                                                   u64 max_tiles, u32* __restrict__ tile_seg) {
+__global__ void __launch_bounds__(BLOCK) k_tile_seg(const u32* __restrict__ tile_start, u32 n_max,
+                                                   const u32* __restrict__ n_dev, u64 max_tiles,
+                                                   u32* __restrict__ tile_seg) {
+  const u32 n_seg = n_dev ? min(*n_dev, n_max) : n_max;
   const u64 total = min<u64>(tile_start[n_seg], max_tiles);
   for (u64 t = (u64)blockIdx.x * BLOCK + threadIdx.x; t < total; t += (u64)gridDim.x * BLOCK)
     tile_seg[t] = find_seg(tile_start, n_seg, (u32)t);
 }
 
-kpa_status launch_tile_seg(const u32* tile_start, u32 n_seg, u64 max_tiles, u32* tile_seg,
-                           hipStream_t st) {
+kpa_status launch_tile_seg(const u32* tile_start, u32 n_seg, const u32* n_dev, u64 max_tiles,
+                           u32* tile_seg, hipStream_t st) {
   KPA_LAUNCH("tile_seg", k_tile_seg, dim3((u32)std::min<u64>(ceil_div(max_tiles, BLOCK), 4096)),
-             dim3(BLOCK), 0, st, tile_start, n_seg, max_tiles, tile_seg);
+             dim3(BLOCK), 0, st, tile_start, n_seg, n_dev, max_tiles, tile_seg);
   return KPA_OK;
 }
 

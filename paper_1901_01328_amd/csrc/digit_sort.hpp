@@ -33,8 +33,9 @@ struct DigitSortBufs {
 
 __device__ __forceinline__ void seg_tile_range(const SegList& sl, const u32* tile_start,
                                                u32 n_seg, u32 tile, u32& seg, u32& t_in,
-                                               u64& a, u64& b, u64& base, u32& cnt) {
-  seg = find_seg(tile_start, n_seg, tile);
+                                               u64& a, u64& b, u64& base, u32& cnt,
+                                               const u32* tile_seg = nullptr) {
+  seg = tile_seg ? tile_seg[tile] : find_seg(tile_start, n_seg, tile);
   t_in = tile - tile_start[seg];
   a = sl.lo[seg];
   b = sl.hi[seg];

@@ -111,8 +111,9 @@ kpa_status launch_fill_u32(u32* p, u64 n, u32 v, hipStream_t st);
 // tile_seg[t] = segment of tile t for every tile of a tile map (tile_start,
 // n_seg + 1 entries), so that per-tile kernels look their segment up with one
 // load instead of a binary search.  tile_seg holds max_tiles entries.
-kpa_status launch_tile_seg(const u32* tile_start, u32 n_seg, u64 max_tiles, u32* tile_seg,
-                           hipStream_t st);
+// When n_dev is given the map has *n_dev (at most n_seg) segments.
+kpa_status launch_tile_seg(const u32* tile_start, u32 n_seg, const u32* n_dev, u64 max_tiles,
+                           u32* tile_seg, hipStream_t st);
 kpa_status launch_fill_u64(u64* p, u64 n, u64 v, hipStream_t st);
 
 }  // namespace kpa

@@ -649,6 +649,7 @@ __global__ void __launch_bounds__(BLOCK) k_fb_pivot(const u64* __restrict__ keys
 // no per-entry atomics).
 __global__ void __launch_bounds__(BLOCK) k_fb_count(const u64* __restrict__ keys, SegList sl,
                                                     const u32* __restrict__ tile_start,
+                                                    const u32* __restrict__ tile_seg,
                                                     const u64* __restrict__ pivot,
                                                     u64* __restrict__ cnt3) {
   __shared__ u64 red[2 * WAVES];
@@ -657,7 +658,7 @@ __global__ void __launch_bounds__(BLOCK) k_fb_count(const u64* __restrict__ keys
   for (u32 tile = blockIdx.x; tile < total; tile += gridDim.x) {
     u32 seg, t_in, cnt;
     u64 a, b, base;
-    seg_tile_range(sl, tile_start, n_seg, tile, seg, t_in, a, b, base, cnt);
+    seg_tile_range(sl, tile_start, n_seg, tile, seg, t_in, a, b, base, cnt, tile_seg);
     const u64 h = pivot[seg];
     u64 lt = 0, eq = 0;
     for (u32 i = threadIdx.x; i < cnt; i += BLOCK) {
@@ -737,6 +738,7 @@ __global__ void __launch_bounds__(BLOCK) k_fb_plan(SegList sl, const u64* __rest
 __global__ void __launch_bounds__(BLOCK) k_fb_copy_all(const u64* __restrict__ keys,
                                                        const u32* __restrict__ rids, SegList sl,
                                                        const u32* __restrict__ tile_start,
+                                                       const u32* __restrict__ tile_seg,
                                                        u64* __restrict__ keys_dst,
                                                        u32* __restrict__ rids_dst) {
   const u32 n_seg = sl.n();
@@ -744,7 +746,7 @@ __global__ void __launch_bounds__(BLOCK) k_fb_copy_all(const u64* __restrict__ k
   for (u32 tile = blockIdx.x; tile < total; tile += gridDim.x) {
     u32 seg, t_in, cnt;
     u64 a, b, base;
-    seg_tile_range(sl, tile_start, n_seg, tile, seg, t_in, a, b, base, cnt);
+    seg_tile_range(sl, tile_start, n_seg, tile, seg, t_in, a, b, base, cnt, tile_seg);
     for (u32 i = threadIdx.x; i < cnt; i += BLOCK) {
       keys_dst[base + i] = keys[base + i];
       rids_dst[base + i] = rids[base + i];
@@ -756,6 +758,7 @@ __global__ void __launch_bounds__(BLOCK) k_fb_copy_all(const u64* __restrict__ k
 __global__ void __launch_bounds__(BLOCK) k_fb_copy(const u64* __restrict__ keys,
                                                    const u32* __restrict__ rids, SegList sl,
                                                    const u32* __restrict__ tile_start,
+                                                   const u32* __restrict__ tile_seg,
                                                    const u32* __restrict__ p_mask,
                                                    u64* __restrict__ keys_dst,
                                                    u32* __restrict__ rids_dst) {
@@ -764,7 +767,7 @@ __global__ void __launch_bounds__(BLOCK) k_fb_copy(const u64* __restrict__ keys,
   for (u32 tile = blockIdx.x; tile < total; tile += gridDim.x) {
     u32 seg, t_in, cnt;
     u64 a, b, base;
-    seg_tile_range(sl, tile_start, n_seg, tile, seg, t_in, a, b, base, cnt);
+    seg_tile_range(sl, tile_start, n_seg, tile, seg, t_in, a, b, base, cnt, tile_seg);
     if (!p_mask[seg]) continue;
     for (u32 i = threadIdx.x; i < cnt; i += BLOCK) {
       keys_dst[base + i] = keys[base + i];
@@ -774,6 +777,7 @@ __global__ void __launch_bounds__(BLOCK) k_fb_copy(const u64* __restrict__ keys,
 }
 
 kpa_status learned_sort_plan(u64 n_cap, u32 n_seg, Carver& c, LearnedWs* w) {
+  w->n_cap = n_cap;
   w->max_tiles = max_tiles(n_cap, n_seg, TILE);
   w->max_ftiles = max_tiles(n_cap, n_seg, FH);
   // an oversize chunk holds more than FCAP entries
@@ -800,6 +804,7 @@ kpa_status learned_sort_plan(u64 n_cap, u32 n_seg, Carver& c, LearnedWs* w) {
   w->fb_max = c.take<u64>(1);
   w->fb_count = c.take<u32>(1);
   w->fb_tile_start = c.take<u32>((u64)w->max_fb + 1);
+  w->fb_tile_seg = c.take<u32>(max_tiles(n_cap, w->max_fb, TILE));
   for (int r = 0; r < 2; ++r) {
     w->rl_lo[r] = c.take<u64>(w->max_fb);
     w->rl_hi[r] = c.take<u64>(w->max_fb);
@@ -825,7 +830,7 @@ kpa_status learned_sort_launch(const u64* keys_in, const u32* rids_in, u64* keys
   KPA_CHECK(launch_fill_u32(lw.fb_count, 1, 0, st));
   KPA_CHECK(launch_fill_u32(lw.rl_count, 4, 0, st));
   KPA_CHECK(launch_seg_tiles_list(sl, TILE, lw.ltile_start, st));
-  KPA_CHECK(launch_tile_seg(lw.ltile_start, n_seg, lw.max_tiles, lw.ltile_seg, st));
+  KPA_CHECK(launch_tile_seg(lw.ltile_start, n_seg, nullptr, lw.max_tiles, lw.ltile_seg, st));
   KPA_CHECK(launch_fill_u64(lw.cur_min, n_seg, ~0ull, st));
   KPA_CHECK(launch_fill_u64(lw.cur_max, n_seg, 0ull, st));
   KPA_LAUNCH("learned_minmax", k_seg_minmax, dim3((u32)std::min<u64>(lw.max_tiles, 8192)),
@@ -839,7 +844,7 @@ kpa_status learned_sort_launch(const u64* keys_in, const u32* rids_in, u64* keys
   KPA_CHECK(digit_sort_launch<LearnedDF>(sl, LearnedDF::Params{lw.segm}, b, st));
 
   KPA_CHECK(launch_seg_tiles_list(sl, FH, lw.ftile_start, st));
-  KPA_CHECK(launch_tile_seg(lw.ftile_start, n_seg, lw.max_ftiles, lw.ftile_seg, st));
+  KPA_CHECK(launch_tile_seg(lw.ftile_start, n_seg, nullptr, lw.max_ftiles, lw.ftile_seg, st));
   KPA_LAUNCH("learned_finish", k_learned_finish, dim3((u32)lw.max_ftiles), dim3(BLOCK), 0, st,
              keys_out, rids_out, sl, lw.ftile_start, lw.ftile_seg, lw.segm, lw.fb_lo, lw.fb_hi,
              lw.fb_count, lw.max_fb, stats);
@@ -854,13 +859,15 @@ kpa_status learned_sort_launch(const u64* keys_in, const u32* rids_in, u64* keys
     KPA_LAUNCH("pivot_select", k_fb_pivot, dim3(1024), dim3(BLOCK), 0, st, keys_out, fl, lw.pivot,
                lw.cnt3);
     KPA_CHECK(launch_seg_tiles_list(fl, TILE, lw.fb_tile_start, st));
+    KPA_CHECK(launch_tile_seg(lw.fb_tile_start, lw.max_fb, cnt_in[r],
+                              max_tiles(lw.n_cap, lw.max_fb, TILE), lw.fb_tile_seg, st));
     KPA_LAUNCH("pivot_count", k_fb_count, dim3(2048), dim3(BLOCK), 0, st, keys_out, fl,
-               lw.fb_tile_start, lw.pivot, lw.cnt3);
+               lw.fb_tile_start, lw.fb_tile_seg, lw.pivot, lw.cnt3);
     KPA_LAUNCH("pivot_plan", k_fb_plan, dim3(64), dim3(BLOCK), 0, st, fl, lw.cnt3, lw.fb_rhi,
                lw.p_hist, lw.p_mask, lw.sm_lo, lw.sm_hi, lw.rl_count + 2, 6 * lw.max_fb,
                lw.rl_lo[r], lw.rl_hi[r], lw.rl_count + r, lw.max_fb, r == 0 ? stats : nullptr);
     KPA_LAUNCH("pivot_copy", k_fb_copy, dim3(2048), dim3(BLOCK), 0, st, keys_out, rids_out, fl,
-               lw.fb_tile_start, lw.p_mask, lw.keys_tmp, lw.rids_tmp);
+               lw.fb_tile_start, lw.fb_tile_seg, lw.p_mask, lw.keys_tmp, lw.rids_tmp);
     const SegList pl{lo_in[r], lw.fb_rhi, cnt_in[r], lw.max_fb};
     DigitSortBufs pb{lw.keys_tmp,         lw.rids_tmp,          keys_out,
                      rids_out,            lw.fb_radix.keys_tmp, lw.fb_radix.rids_tmp,
@@ -875,8 +882,10 @@ kpa_status learned_sort_launch(const u64* keys_in, const u32* rids_in, u64* keys
   // What two rounds did not resolve goes through the radix path.
   const SegList rl{lw.rl_lo[1], lw.rl_hi[1], lw.rl_count + 1, lw.max_fb};
   KPA_CHECK(launch_seg_tiles_list(rl, TILE, lw.fb_tile_start, st));
+  KPA_CHECK(launch_tile_seg(lw.fb_tile_start, lw.max_fb, lw.rl_count + 1,
+                            max_tiles(lw.n_cap, lw.max_fb, TILE), lw.fb_tile_seg, st));
   KPA_LAUNCH("fallback_copy", k_fb_copy_all, dim3(2048), dim3(BLOCK), 0, st, keys_out, rids_out,
-             rl, lw.fb_tile_start, lw.keys_tmp, lw.rids_tmp);
+             rl, lw.fb_tile_start, lw.fb_tile_seg, lw.keys_tmp, lw.rids_tmp);
   return radix_sort_launch(lw.keys_tmp, lw.rids_tmp, keys_out, rids_out, rl, lw.fb_radix, st);
 }
 

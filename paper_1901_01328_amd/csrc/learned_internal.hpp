@@ -84,6 +84,7 @@ struct LearnedWs {
   u64* fb_max;
   u32* fb_count;
   u32* fb_tile_start;
+  u32* fb_tile_seg;  // segment of each tile of the chunk lists
   // pivot rounds: the oversize chunks of round r are split three ways around
   // their most frequent key; parts still larger than FCAP go to round r+1
   u64* rl_lo[2];
@@ -96,6 +97,7 @@ struct LearnedWs {
   u32* p_hist;       // digit offsets for the pivot scatter (n * 8 * 256)
   u32* p_mask;
   u32* p_tile_start;
+  u64 n_cap;
   u64 max_tiles;
   u64 max_ftiles;
   u32 max_fb;

@@ -296,7 +296,7 @@ kpa_status reduce_launch(const u64* keys, const u32* rids, const u64* seg_off, u
   vs.val_w = L ? L->val_w : 8;
   vs.on = need_val ? 1u : 0u;
   KPA_CHECK(launch_seg_tiles(seg_off, nullptr, n_seg, TILE, w.tile_start, st));
-  KPA_CHECK(launch_tile_seg(w.tile_start, n_seg, w.max_tiles, w.tile_seg, st));
+  KPA_CHECK(launch_tile_seg(w.tile_start, n_seg, nullptr, w.max_tiles, w.tile_seg, st));
   KPA_LAUNCH("reduce_heads", k_reduce_heads, dim3((u32)w.max_tiles), dim3(BLOCK), 0, st, keys,
              seg_off, w.tile_start, w.tile_seg, n_seg, w.heads, w.flags);
   KPA_LAUNCH("reduce_scan", k_reduce_scan, dim3(1), dim3(1024), 0, st, w.heads, w.flags,
@@ -542,7 +542,7 @@ kpa_status kpa_topk_by_sum(const uint64_t* gkey, const uint64_t* gsum, const uin
   topk_plan(g_cap, n_seg, c, &w);
   KPA_REQUIRE(c.used <= ws_bytes, KPA_EWORKSPACE, "workspace too small: need %zu bytes", c.used);
   KPA_CHECK(launch_seg_tiles(gseg_off, nullptr, n_seg, GT, w.tile_start, stream));
-  KPA_CHECK(launch_tile_seg(w.tile_start, n_seg, w.max_tiles, w.tile_seg, stream));
+  KPA_CHECK(launch_tile_seg(w.tile_start, n_seg, nullptr, w.max_tiles, w.tile_seg, stream));
   KPA_LAUNCH("topk_local", k_topk_local, dim3((u32)w.max_tiles), dim3(BLOCK), 0, stream, gkey, gsum,
                      gseg_off, w.tile_start, w.tile_seg, n_seg, k, w.cs, w.ck, w.cn);
   KPA_LAUNCH("topk_final", k_topk_final, dim3(n_seg), dim3(BLOCK), 0, stream, w.cs, w.ck, w.cn,
