@@ -3,9 +3,9 @@
 // the learned-splitter sort).
 //
 // DF must provide: PASSES (number of 8-bit digits), SMEM (floats of LDS it
-// may use), a Params type, a device constructor DF(params, segment),
-// bind(lds) called by all threads before use (then a barrier), digit(key,
-// pass) -> [0, 256) and digits(key, d[PASSES]).
+// may use), a Params type, a default constructor, a device constructor
+// DF(params, segment), bind(lds) called by all threads before use (then a
+// barrier), digit(key, pass) -> [0, 256) and digits(key, d[PASSES]).
 #pragma once
 
 #include "sort_internal.hpp"
@@ -95,16 +95,22 @@ __global__ void __launch_bounds__(BLOCK) k_ds_hist(const u64* __restrict__ keys,
        t0 += gridDim.x * HIST_TILES_PER_BLOCK) {
     const u32 t1 = min(total, t0 + HIST_TILES_PER_BLOCK);
     u32 cur = find_seg(tile_start, n_seg, t0);
+    DF df(prm, cur);
+    __syncthreads();
+    df.bind(dfsm);
     __syncthreads();
     for (u32 t = t0; t < t1; ++t) {
+      bool next = false;
       while (cur + 1 < n_seg && tile_start[cur + 1] <= t) {
         flush(cur);
         ++cur;
+        next = true;
       }
-      DF df(prm, cur);
-      __syncthreads();
-      df.bind(dfsm);
-      __syncthreads();
+      if (next) {  // the digit function of the new segment (flush ended with a barrier)
+        df = DF(prm, cur);
+        df.bind(dfsm);
+        __syncthreads();
+      }
       const u64 a = sl.lo[cur], b = sl.hi[cur];
       const u64 base = a + (u64)(t - tile_start[cur]) * TILE;
       const u32 cnt = base < b ? (u32)min<u64>(TILE, b - base) : 0u;
@@ -308,6 +314,8 @@ __global__ void __launch_bounds__(PASS_THREADS, PASS_WAVES / 2)
     return;
   }
   u32* counter = bf.counters + pass;
+  u32 bound = 0xFFFFFFFFu;  // segment whose digit function is in dfsm
+  DF df;
   while (true) {
     __syncthreads();
     if (tid == 0) sm.tile = atomicAdd(counter, 1u);
@@ -355,9 +363,13 @@ __global__ void __launch_bounds__(PASS_THREADS, PASS_WAVES / 2)
     const u64 seg_start = base - (u64)td.t_in * TILE;
     const u64 my_base =
         tid < RADIX ? seg_start + bf.hist[((u64)seg * DF::PASSES + pass) * RADIX + tid] : 0ull;
-    DF df(prm, seg);
-    df.bind(dfsm);
-    if (DF::SMEM > 1) __syncthreads();
+    if (seg != bound) {
+      // the previous tile's digits were computed before its barriers
+      df = DF(prm, seg);
+      df.bind(dfsm);
+      if (DF::SMEM > 1) __syncthreads();
+      bound = seg;
+    }
 #pragma unroll
     for (int j = 0; j < PASS_ITEMS; ++j) dd[j] = ((valid >> j) & 1) ? df.digit(kk[j], pass) : 0u;
     onesweep_tile(sm, kk, rr, dd, valid, status_cur, td.g, td.t_in, my_base, dst_k, dst_r);

@@ -32,20 +32,17 @@ struct LearnedDF {
     const SegModel* segm;
   };
   SegModel m;
+  const lds_float* kn;
+  LearnedDF() = default;
   __device__ __forceinline__ LearnedDF(const Params& p, u32 seg) : m(p.segm[seg]) {}
   // All threads: copy the knots to LDS and evaluate from there (the caller
   // synchronizes before the first use).
-  __device__ __forceinline__ void bind(float* sm) {
-    if (m.bits) {
-      for (u32 j = threadIdx.x; j <= m.nseg; j += blockDim.x) sm[j] = m.knots[j];
-      m.knots = sm;
-    }
-  }
+  __device__ __forceinline__ void bind(float* sm) { kn = bind_knots(m, sm); }
   __device__ __forceinline__ u32 digit(u64 k, u32 pass) const {
-    return (model_bucket(m, k) >> (8 * pass)) & 255u;
+    return (model_bucket(m, kn, k) >> (8 * pass)) & 255u;
   }
   __device__ __forceinline__ void digits(u64 k, u32 (&d)[PASSES]) const {
-    const u32 b = model_bucket(m, k);
+    const u32 b = model_bucket(m, kn, k);
     d[0] = b & 255u;
     d[1] = (b >> 8) & 255u;
   }
@@ -135,7 +132,11 @@ __global__ void __launch_bounds__(BLOCK) k_learned_setup(const kpa_pwl_model* __
       m.kmax = ok ? cur_max[s] : M.kmax;
       m.nseg = ok ? nseg : 1;
       const u64 span = m.kmax - m.kmin;
-      m.scale = (ok && span) ? (float)nseg / (float)span : 0.0f;
+      u32 sh = 0;
+      while ((span >> sh) > 0xFFFFFFFFull) ++sh;
+      m.sh = sh;
+      m.hspan = (u32)(span >> sh);
+      m.scale = (ok && m.hspan) ? (float)nseg / (float)m.hspan : 0.0f;
       m.valid = ok ? 1u : 0u;
       m.knots = M.knots;
       u32 bits = 0;
@@ -166,7 +167,7 @@ struct FinishSmem {
   float knots[KPA_PWL_MAX_SEG + 1];
   u64 skeys[FCAP + 1];
   u32 srids[FCAP];
-  u32 srel[FCAP];  // refined bucket id relative to the chunk's first bucket
+  u32 srel[FCAP + 1];  // refined bucket id (relative to the chunk's first bucket)
   u32 flag;
   u32 n_long;                // long runs with inversions still to split
   u32 long_lo[LONG_RUNS];
@@ -287,22 +288,30 @@ __device__ void split_long_runs(FinishSmem& sm) {
   }
 }
 
+enum ChunkResult : u32 { CH_EQUAL = 0, CH_INORDER = 1, CH_MOVED = 2 };
+
 // Stable on-chip sort of the chunk [0, m) in sm using the model once more:
 // entries are ranked by their refined bucket id (8 more bits of F, given in
-// sm.srel, taken relative to the chunk's first bucket) in one or two byte passes, which leaves runs of
-// entries sharing a refined id -- a handful each when the model fits -- that
-// are insertion-sorted by key.  A long run of distinct keys (the model does
-// not separate them) sends the chunk to the byte-wise LSD sort.  Returns false
-// when all keys are equal (nothing to do).
-__device__ bool lds_sort_model(FinishSmem& sm, const SegModel& m, u32 mcount) {
+// sm.srel, taken relative to the chunk's first bucket) in one or two byte
+// passes, which leaves runs of entries sharing a refined id -- a handful each
+// when the model fits -- that are sorted by key.  The m <= WAVES*64*IT
+// entries are spread over IT items per thread, so that every wave has work
+// whatever the chunk's size.  A long run of distinct keys the three-way
+// splits cannot settle sends the chunk to the byte-wise LSD sort.  Returns
+// CH_EQUAL when all keys are equal and CH_INORDER when they already ascend
+// (nothing moved in either case).
+template <int IT>
+__device__ u32 lds_sort_model(FinishSmem& sm, const SegModel& m, u32 mcount) {
   const u32 tid = threadIdx.x;
   const u32 w = tid >> 6;
   __syncthreads();
   u64 vor = 0, vand = ~0ull;
-  u32 rmax = 0;
+  u32 rmax = 0;  // largest relative refined id
+  bool inv = false;  // some entry's key is below its predecessor's
   // sm.srel holds each entry's refined bucket id; make it relative to the
   // chunk's first bucket
   const u32 base = (sm.srel[0] >> 8) << 8;
+  if (tid == 0) sm.flag = 0;
   __syncthreads();
   for (u32 i = tid; i < mcount; i += BLOCK) {
     const u64 k = sm.skeys[i];
@@ -311,23 +320,29 @@ __device__ bool lds_sort_model(FinishSmem& sm, const SegModel& m, u32 mcount) {
     const u32 r = sm.srel[i] - base;
     sm.srel[i] = r;
     rmax = r > rmax ? r : rmax;
+    inv = inv || (i > 0 && k < sm.skeys[i - 1]);
   }
+  if (inv) sm.flag = 1;  // read after the barriers of the reductions below
   block_or_and(vor, vand, sm.red64);
-  if (vor == vand) return false;
+  if (vor == vand) return CH_EQUAL;
   rmax = ~block_min_u32(~rmax, sm.red);
-  if (!m.valid || rmax >= (1u << 16)) return lds_sort(sm, mcount);
+  if (!sm.flag) return CH_INORDER;
+  if (!m.valid || rmax >= (1u << 16)) {
+    lds_sort(sm, mcount);
+    return CH_MOVED;
+  }
   u32 valid = 0;
 #pragma unroll
-  for (int j = 0; j < ITEMS; ++j)
-    if (tile_offset(j) < mcount) valid |= 1u << j;
+  for (int j = 0; j < IT; ++j)
+    if (part_offset<WAVES, IT>(j) < mcount) valid |= 1u << j;
 #pragma unroll 1
   for (u32 p = 0; p < 2; ++p) {
     if (p == 1 && rmax < 256u) break;
-    u64 kk[ITEMS];
-    u32 rr[ITEMS], re[ITEMS], d[ITEMS], rank[ITEMS], tc;
+    u64 kk[IT];
+    u32 rr[IT], re[IT], d[IT], rank[IT], tc;
 #pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-      const u32 o = tile_offset(j);
+    for (int j = 0; j < IT; ++j) {
+      const u32 o = part_offset<WAVES, IT>(j);
       const bool v = (valid >> j) & 1;
       kk[j] = v ? sm.skeys[o] : 0ull;
       rr[j] = v ? sm.srids[o] : 0u;
@@ -338,7 +353,7 @@ __device__ bool lds_sort_model(FinishSmem& sm, const SegModel& m, u32 mcount) {
     rank_tile(sm.whist, sm.lstart, sm.scan, d, valid, rank, &tc);
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < ITEMS; ++j)
+    for (int j = 0; j < IT; ++j)
       if ((valid >> j) & 1) {
         const u32 pos = sm.lstart[d[j]] + sm.whist[w][d[j]] + rank[j];
         sm.skeys[pos] = kk[j];
@@ -347,21 +362,21 @@ __device__ bool lds_sort_model(FinishSmem& sm, const SegModel& m, u32 mcount) {
       }
     __syncthreads();
   }
-  // Runs of equal refined id: insertion sort by key (stable).  Run starts,
-  // run ends and adjacent inversions are found in parallel; each short run is
-  // sorted by the thread holding its start; a long run is left alone when it
-  // has no inversion (typically one repeated key) and otherwise sends the
-  // chunk to the byte-wise sort.
+  // Runs of equal refined id: run starts, run ends and adjacent inversions
+  // are found in parallel; each entry of a short run with an inversion counts
+  // the run's entries that must precede it; a long run is left alone when it
+  // has no inversion (typically one repeated key) and is otherwise split
+  // three ways around a sampled pivot.
   if (tid == 0) {
     sm.flag = 0;
     sm.n_long = 0;
   }
-  u32 stm = 0, lastm = 0, invm = 0, rs[ITEMS];
+  u32 stm = 0, lastm = 0, invm = 0, rs[IT];
   u32 carry = 0;
   const u32 lane = __lane_id();
 #pragma unroll
-  for (int j = 0; j < ITEMS; ++j) {
-    const u32 i = tile_offset(j);
+  for (int j = 0; j < IT; ++j) {
+    const u32 i = part_offset<WAVES, IT>(j);
     bool st = false, la = false, inv = false;
     if (i < mcount) {
       const u32 r = sm.srel[i];
@@ -389,26 +404,26 @@ __device__ bool lds_sort_model(FinishSmem& sm, const SegModel& m, u32 mcount) {
   u32 before = 0;
   for (u32 q = 0; q < w; ++q) before = sm.red[q] > before ? sm.red[q] : before;
 #pragma unroll
-  for (int j = 0; j < ITEMS; ++j) rs[j] = rs[j] > before ? rs[j] : before;
+  for (int j = 0; j < IT; ++j) rs[j] = rs[j] > before ? rs[j] : before;
   __syncthreads();
   // the last entry of each run stores the run's end at the run's start; an
   // inversion inside a run marks the run (bit 31) as needing the sort
 #pragma unroll
-  for (int j = 0; j < ITEMS; ++j)
-    if ((lastm >> j) & 1) sm.srel[rs[j]] = tile_offset(j) + 1;
+  for (int j = 0; j < IT; ++j)
+    if ((lastm >> j) & 1) sm.srel[rs[j]] = part_offset<WAVES, IT>(j) + 1;
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < ITEMS; ++j)
+  for (int j = 0; j < IT; ++j)
     if ((invm >> j) & 1) atomicOr(&sm.srel[rs[j]], 0x80000000u);
   __syncthreads();
   // Each entry of a short run counts the run's entries that must precede it
   // (smaller key, or equal key earlier): its position within the run.
-  u64 nk[ITEMS];
-  u32 nr[ITEMS], np[ITEMS];
+  u64 nk[IT];
+  u32 nr[IT], np[IT];
   u32 movem = 0;
 #pragma unroll
-  for (int j = 0; j < ITEMS; ++j) {
-    const u32 i = tile_offset(j);
+  for (int j = 0; j < IT; ++j) {
+    const u32 i = part_offset<WAVES, IT>(j);
     np[j] = i;
     if (i >= mcount) continue;
     const u32 s0 = rs[j], re = sm.srel[s0], e = re & 0x7FFFFFFFu;
@@ -438,7 +453,7 @@ __device__ bool lds_sort_model(FinishSmem& sm, const SegModel& m, u32 mcount) {
   }
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < ITEMS; ++j)
+  for (int j = 0; j < IT; ++j)
     if ((movem >> j) & 1) {
       sm.skeys[np[j]] = nk[j];
       sm.srids[np[j]] = nr[j];
@@ -446,15 +461,39 @@ __device__ bool lds_sort_model(FinishSmem& sm, const SegModel& m, u32 mcount) {
   __syncthreads();
   if (!sm.flag) split_long_runs(sm);
   if (sm.flag) lds_sort(sm, mcount);
-  return true;
+  return CH_MOVED;
 }
 
-__device__ __forceinline__ void load_knots(FinishSmem& sm, SegModel& m) {
-  if (m.bits) {
-    for (u32 j = threadIdx.x; j <= m.nseg; j += BLOCK) sm.knots[j] = m.knots[j];
-    m.knots = sm.knots;
+#ifndef KPA_FIN_EXTRA
+#define KPA_FIN_EXTRA 1024
+#endif
+// Entries a finishing workgroup reads first: the entry before its stretch,
+// the stretch, and KPA_FIN_EXTRA more, within which most chunks end.
+constexpr u32 FIN_FIRST = FH + 1 + KPA_FIN_EXTRA;
+static_assert(FIN_FIRST <= FCAP + 1, "the first read fits the window");
+constexpr int FIN_IT = (FIN_FIRST + BLOCK - 1) / BLOCK;
+
+// Window entries [from, to): keys from keys[g + i] and their refined ids.
+__device__ __forceinline__ void load_window(FinishSmem& sm, const SegModel& m, const lds_float* kn,
+                                            const u64* __restrict__ keys, u64 g, u32 from,
+                                            u32 to) {
+  for (u32 i = from + threadIdx.x; i < to; i += BLOCK) {
+    const u64 kv = keys[g + i];
+    sm.skeys[i] = kv;
+    sm.srel[i] = m.valid ? model_fine(m, kn, kv) : 0u;
   }
-  __syncthreads();
+}
+
+// First window index o in [lo, hi) (lo >= 1) where a bucket starts, i.e. whose
+// bucket differs from that of o - 1; NONE when there is none.
+__device__ __forceinline__ u32 first_edge(FinishSmem& sm, u32 lo, u32 hi) {
+  u32 e = NONE;
+  for (u32 o = lo + threadIdx.x; o < hi; o += BLOCK)
+    if ((sm.srel[o] >> 8) != (sm.srel[o - 1] >> 8)) {
+      e = o;
+      break;
+    }
+  return block_min_u32(e, sm.red);
 }
 
 // Finishing pass: one workgroup per 2048-entry stretch [pos0, pos0+FH) of a
@@ -463,10 +502,12 @@ __device__ __forceinline__ void load_knots(FinishSmem& sm, SegModel& m) {
 // or after pos0+FH (or the segment end).  Chunks of at most FCAP entries are
 // sorted on chip; larger ones are listed for the pivot rounds.
 //
-// Other workgroups rewrite neighbouring chunks while this one reads entries
-// there to find bucket edges; a chunk's sort only permutes entries inside the
-// chunk's buckets, so the bucket of every position never changes and the
-// edges found do not depend on timing.
+// The workgroup reads keys from the entry before its stretch on, first
+// FIN_FIRST of them and, when the chunk's end is not among them, up to FCAP+1
+// from the chunk's start; row ids only of the chunk.  Other workgroups
+// rewrite neighbouring chunks meanwhile; a chunk's sort only permutes entries
+// inside the chunk's buckets, so the bucket of every position never changes
+// and the edges found do not depend on timing.
 __global__ void __launch_bounds__(BLOCK, 2) k_learned_finish(
     u64* __restrict__ keys, u32* __restrict__ rids, SegList sl,
     const u32* __restrict__ ftile_start, const u32* __restrict__ ftile_seg,
@@ -483,60 +524,79 @@ __global__ void __launch_bounds__(BLOCK, 2) k_learned_finish(
   const u64 a = sl.lo[seg], b = sl.hi[seg];
   const u64 pos0 = a + (u64)k * FH;
   if (pos0 >= b) return;
-  SegModel m = segm[seg];
-  load_knots(sm, m);
+  const SegModel m = segm[seg];
+  const lds_float* kn = bind_knots(m, sm.knots);
+  __syncthreads();
+  const u32 span = (u32)min<u64>(FH, b - pos0);
+  // bucket ids never decrease along the segment: no bucket starts in the
+  // stretch when the entry before it and its last entry share a bucket
+  if (k > 0 && model_bucket(m, kn, keys[pos0 - 1]) == model_bucket(m, kn, keys[pos0 - 1 + span]))
+    return;
 
-  // --- first bucket start in [pos0, pos0 + FH) ---------------------------
-  u64 start = a;
+  // --- window from L0: the entry before the stretch (k > 0) or pos0 = a ---
+  const u64 L0 = k > 0 ? pos0 - 1 : pos0;
+  u32 have = (u32)min<u64>(FIN_FIRST, b - L0);
+  load_window(sm, m, kn, keys, L0, 0, have);
+  __syncthreads();
+  u32 s0 = 0;  // window index of the chunk's first entry
   if (k > 0) {
-    const u32 span = (u32)min<u64>(FH, b - pos0);
-    // bucket ids never decrease along the segment: no bucket starts in the
-    // stretch when both ends lie in the same bucket
-    if (model_bucket(m, keys[pos0 - 1]) == model_bucket(m, keys[pos0 - 1 + span])) return;
-    for (u32 i = tid; i <= span; i += BLOCK) sm.skeys[i] = keys[pos0 - 1 + i];
+    s0 = first_edge(sm, 1, span + 1);
+    if (s0 == NONE) return;  // the bucket at pos0 started earlier and covers the stretch
+  }
+  const u64 start = L0 + s0;
+  // row ids of the chunk's likely extent, in flight during the search below
+  const u32 rguess = min(have - s0, FCAP);
+  u32 rr[FIN_IT];
+#pragma unroll
+  for (int j = 0; j < FIN_IT; ++j) {
+    const u32 i = tid + j * BLOCK;
+    rr[j] = i < rguess ? rids[start + i] : 0u;
+  }
+  if (s0 > 0) {  // move the chunk to window index 0
+    u64 kk[FIN_IT];
+    u32 re[FIN_IT];
+#pragma unroll
+    for (int j = 0; j < FIN_IT; ++j) {
+      const u32 i = tid + j * BLOCK;
+      if (s0 + i < have) {
+        kk[j] = sm.skeys[s0 + i];
+        re[j] = sm.srel[s0 + i];
+      }
+    }
     __syncthreads();
-    u32 first = NONE;
-    for (u32 i = tid + 1; i <= span; i += BLOCK)
-      if (model_bucket(m, sm.skeys[i]) != model_bucket(m, sm.skeys[i - 1]) && i - 1 < first)
-        first = i - 1;
-    first = block_min_u32(first, sm.red);
-    if (first == NONE) return;  // the bucket at pos0 started earlier and covers the stretch
-    start = pos0 + first;
+#pragma unroll
+    for (int j = 0; j < FIN_IT; ++j) {
+      const u32 i = tid + j * BLOCK;
+      if (s0 + i < have) {
+        sm.skeys[i] = kk[j];
+        sm.srel[i] = re[j];
+      }
+    }
+    __syncthreads();
+    have -= s0;
   }
 
-  // --- window [start, start + FCAP] and the chunk's end ---------------------
-  const u32 wn = (u32)min<u64>(FCAP, b - start);
-  const bool beyond = start + wn < b;  // an entry exists right after the window
-  __syncthreads();
-  for (u32 i = tid; i < wn; i += BLOCK) {
-    sm.skeys[i] = keys[start + i];
-    sm.srids[i] = rids[start + i];
+  // --- the chunk's end: the first bucket start at or after pos0 + FH ------
+  const u32 e_lo = (u32)(pos0 + FH - start);  // >= 1: start < pos0 + FH
+  const u32 want = (u32)min<u64>(FCAP + 1, b - start);
+  u32 endo = first_edge(sm, e_lo, have);
+  if (endo == NONE && have < want) {
+    load_window(sm, m, kn, keys, start, have, want);
+    __syncthreads();
+    endo = first_edge(sm, max(e_lo, have), want);
+    have = want;
   }
-  if (tid == 0 && beyond) sm.skeys[wn] = keys[start + wn];
-  __syncthreads();
-  // refined bucket ids of the window, once per entry (bucket = id >> 8)
-  const u32 wl = wn + (beyond ? 1u : 0u);
-  for (u32 o = tid; o < wl; o += BLOCK) sm.srel[o] = m.valid ? model_fine(m, sm.skeys[o]) : 0u;
-  __syncthreads();
-  const u64 lo_e = max(pos0 + FH, start + 1);
-  u32 endo = NONE;  // end as an offset from start
-  for (u32 o = tid + 1; o <= wn; o += BLOCK) {
-    // position start+o begins a bucket (or is the segment end); the chunk
-    // ends at the first such position at or after pos0+FH, or at the end
-    const bool seg_end = o == wn && !beyond;
-    const bool edge = seg_end || (sm.srel[o] >> 8) != (sm.srel[o - 1] >> 8);
-    if (edge && (seg_end || start + o >= lo_e) && o < endo) endo = o;
-  }
-  endo = block_min_u32(endo, sm.red);
+  if (endo == NONE && want == b - start && want <= FCAP) endo = want;  // the segment's end
 
   if (endo == NONE) {
-    // Oversize: the bucket running through the window end reaches past it.
+    // Oversize: no bucket starts among the FCAP+1 entries from the chunk's
+    // start after pos0 + FH; the bucket of the last of them runs on.
     if (tid == 0) {
-      const u32 beta = sm.srel[wn] >> 8;
-      u64 lo = start + wn, hi = b;  // first p in (lo, hi] with p == b or bucket > beta
+      const u32 beta = sm.srel[want - 1] >> 8;
+      u64 lo = start + want - 1, hi = b;  // first p in (lo, hi] with p == b or bucket > beta
       while (hi - lo > 1) {
         const u64 mid = lo + (hi - lo) / 2;
-        if (model_bucket(m, keys[mid]) > beta) hi = mid; else lo = mid;
+        if (model_bucket(m, kn, keys[mid]) > beta) hi = mid; else lo = mid;
       }
       const u32 idx = atomicAdd(fb_count, 1u);
       if (idx < max_fb) {
@@ -547,10 +607,22 @@ __global__ void __launch_bounds__(BLOCK, 2) k_learned_finish(
     return;
   }
 
-  const u32 mcount = endo;
-  const bool moved = lds_sort_model(sm, m, mcount);
-  if (tid == 0) stat_add(stats, moved ? ST_ONCHIP : ST_EQUAL, mcount);
-  if (!moved) return;  // one key: already in input order
+  const u32 mcount = endo;  // <= FCAP
+#pragma unroll
+  for (int j = 0; j < FIN_IT; ++j) {
+    const u32 i = tid + j * BLOCK;
+    if (i < mcount && i < rguess) sm.srids[i] = rr[j];
+  }
+  for (u32 i = rguess + tid; i < mcount; i += BLOCK) sm.srids[i] = rids[start + i];
+  u32 res;
+  if (mcount <= 2048)
+    res = lds_sort_model<8>(sm, m, mcount);
+  else if (mcount <= 3072)
+    res = lds_sort_model<12>(sm, m, mcount);
+  else
+    res = lds_sort_model<16>(sm, m, mcount);
+  if (tid == 0) stat_add(stats, res == CH_EQUAL ? ST_EQUAL : ST_ONCHIP, mcount);
+  if (res != CH_MOVED) return;
   for (u32 i = tid; i < mcount; i += BLOCK) {
     keys[start + i] = sm.skeys[i];
     rids[start + i] = sm.srids[i];
@@ -593,6 +665,7 @@ struct PivotDF {
     const u64* pivot;
   };
   u64 h;
+  PivotDF() = default;
   __device__ __forceinline__ PivotDF(const Params& p, u32 seg) : h(p.pivot[seg]) {}
   __device__ __forceinline__ u32 digit(u64 k, u32) const { return k < h ? 0u : (k == h ? 1u : 2u); }
   __device__ __forceinline__ void digits(u64 k, u32 (&d)[PASSES]) const { d[0] = digit(k, 0); }
@@ -830,7 +903,7 @@ kpa_status learned_sort_launch(const u64* keys_in, const u32* rids_in, u64* keys
   KPA_CHECK(launch_fill_u32(lw.fb_count, 1, 0, st));
   KPA_CHECK(launch_fill_u32(lw.rl_count, 4, 0, st));
   KPA_CHECK(launch_seg_tiles_list(sl, TILE, lw.ltile_start, st));
-  KPA_CHECK(launch_tile_seg(lw.ltile_start, n_seg, nullptr, lw.max_tiles, lw.ltile_seg, st));
+  KPA_CHECK(launch_tile_seg(lw.ltile_start, n_seg, sl.n_dev, lw.max_tiles, lw.ltile_seg, st));
   KPA_CHECK(launch_fill_u64(lw.cur_min, n_seg, ~0ull, st));
   KPA_CHECK(launch_fill_u64(lw.cur_max, n_seg, 0ull, st));
   KPA_LAUNCH("learned_minmax", k_seg_minmax, dim3((u32)std::min<u64>(lw.max_tiles, 8192)),
@@ -844,7 +917,7 @@ kpa_status learned_sort_launch(const u64* keys_in, const u32* rids_in, u64* keys
   KPA_CHECK(digit_sort_launch<LearnedDF>(sl, LearnedDF::Params{lw.segm}, b, st));
 
   KPA_CHECK(launch_seg_tiles_list(sl, FH, lw.ftile_start, st));
-  KPA_CHECK(launch_tile_seg(lw.ftile_start, n_seg, nullptr, lw.max_ftiles, lw.ftile_seg, st));
+  KPA_CHECK(launch_tile_seg(lw.ftile_start, n_seg, sl.n_dev, lw.max_ftiles, lw.ftile_seg, st));
   KPA_LAUNCH("learned_finish", k_learned_finish, dim3((u32)lw.max_ftiles), dim3(BLOCK), 0, st,
              keys_out, rids_out, sl, lw.ftile_start, lw.ftile_seg, lw.segm, lw.fb_lo, lw.fb_hi,
              lw.fb_count, lw.max_fb, stats);

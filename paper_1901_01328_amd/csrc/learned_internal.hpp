@@ -12,41 +12,55 @@ constexpr u32 MAX_BUCKET_BITS = 16;
 
 // Per-segment model state prepared on the device from a kpa_pwl_model.
 struct SegModel {
-  u64 kmin, kmax;
-  float scale;         // n_seg / (kmax - kmin), 0 when kmax == kmin
+  u64 kmin, kmax;      // the segment's own smallest and largest key
+  float scale;         // nseg / hspan, 0 when hspan == 0
   u32 nseg;            // PWL segments
   u32 bits;            // log2 of the bucket count (0: one bucket)
-  u32 valid;           // knots checked: finite, within [0,1], nondecreasing
-  const float* knots;  // n_seg + 1 values
+  u32 valid;           // knots checked: finite, within [0, 1], nondecreasing
+  u32 sh;              // key - kmin is shifted right by sh to fit 32 bits
+  u32 hspan;           // (kmax - kmin) >> sh
+  const float* knots;  // nseg + 1 values in global memory (copied to LDS for use)
 };
 
-// F(key): 0..1, nondecreasing in key for nondecreasing knots.  key <= kmin maps
-// to knots[0], key >= kmax to 1; between, linear interpolation clamped to the
-// segment's two knots.  Each step (u64->float conversion, product with a
-// positive scale, truncation, fraction, a + f*(b-a) with b >= a, clamp) is
-// monotone under round-to-nearest, and segment j's values lie in
-// [knots[j], knots[j+1]], so F never decreases.  Written without branches so
-// that the knot loads of many keys can be in flight together.
-__device__ __forceinline__ float pwl_eval(const SegModel& m, u64 key) {
-  const u64 span = m.kmax - m.kmin;
-  u64 d = key > m.kmin ? key - m.kmin : 0ull;
-  d = d < span ? d : span;
-  const float x = (float)d * m.scale;
-  u32 j = (u32)x;
-  j = j >= m.nseg ? m.nseg - 1 : j;
-  const float f = x - (float)j;
-  const float a = m.knots[j], b = m.knots[j + 1];
-  float F = a + f * (b - a);
-  F = F < a ? a : F;
-  F = F > b ? b : F;
-  F = key <= m.kmin ? m.knots[0] : F;
-  return key >= m.kmax ? 1.0f : F;
+// The knots are read from LDS through a pointer of the LDS address space, so
+// that each evaluation is one two-word LDS read.
+typedef __attribute__((address_space(3))) const float lds_float;
+typedef __attribute__((address_space(1))) const float global_float;
+
+// All threads of the workgroup: copy the segment's knots to `lds` (at least
+// nseg + 1 floats; nseg <= KPA_PWL_MAX_SEG for every prepared model).  The
+// caller synchronizes before the first evaluation.
+__device__ __forceinline__ const lds_float* bind_knots(const SegModel& m, float* lds) {
+  const global_float* g = (const global_float*)m.knots;
+  for (u32 j = threadIdx.x; j <= m.nseg; j += blockDim.x) lds[j] = g[j];
+  return (const lds_float*)lds;
 }
 
-__device__ __forceinline__ u32 model_bucket(const SegModel& m, u64 key) {
+// F(key): 0..1, nondecreasing in key for nondecreasing knots.  The offset
+// key - kmin (0 for keys below kmin), shifted right by sh (so that it fits 32
+// bits) and capped at hspan (keys above kmax), is converted to float and
+// scaled to the segment axis: x = h*scale in [0, nseg].  F interpolates the
+// two knots of segment j = floor(x) (capped at nseg - 1) at the fraction
+// f = h*scale - j (one fused rounding) and is clamped to them.  Each step is
+// monotone under round-to-nearest and segment j's values lie in
+// [knots[j], knots[j+1]], so F never decreases.  The two fused operations
+// are written out so that every kernel evaluating the model computes the
+// same bits, whatever the compiler would contract.
+__device__ __forceinline__ float pwl_eval(const SegModel& m, const lds_float* kn, u64 key) {
+  const u64 d = key > m.kmin ? (key - m.kmin) >> m.sh : 0ull;
+  const float hf = (float)(d < (u64)m.hspan ? (u32)d : m.hspan);
+  const float x = hf * m.scale;
+  u32 j = (u32)x;
+  j = j < m.nseg - 1 ? j : m.nseg - 1;
+  const float f = fmaf(hf, m.scale, -(float)j);
+  const float a = kn[j], b = kn[j + 1];
+  return __builtin_amdgcn_fmed3f(fmaf(f, b - a, a), a, b);
+}
+
+__device__ __forceinline__ u32 model_bucket(const SegModel& m, const lds_float* kn, u64 key) {
   if (m.bits == 0) return 0u;
   const float B = (float)(1u << m.bits);
-  const u32 b = (u32)(pwl_eval(m, key) * B);
+  const u32 b = (u32)(pwl_eval(m, kn, key) * B);
   const u32 top = (1u << m.bits) - 1;
   return b > top ? top : b;
 }
@@ -54,9 +68,9 @@ __device__ __forceinline__ u32 model_bucket(const SegModel& m, u64 key) {
 // Bucket id refined by 8 more bits: floor(F * 2^(bits+8)), capped.  Scaling
 // by a power of two is exact, so model_fine(k) >> 8 == model_bucket(k) for
 // every key (bits <= 16, so the product stays below 2^24 and exact).
-__device__ __forceinline__ u32 model_fine(const SegModel& m, u64 key) {
+__device__ __forceinline__ u32 model_fine(const SegModel& m, const lds_float* kn, u64 key) {
   const float B = (float)(1u << (m.bits + 8));
-  const u32 b = (u32)(pwl_eval(m, key) * B);
+  const u32 b = (u32)(pwl_eval(m, kn, key) * B);
   const u32 top = (1u << (m.bits + 8)) - 1;
   return b > top ? top : b;
 }

@@ -46,16 +46,24 @@ __device__ __forceinline__ u32 tile_offset_t(int j) {
 }
 __device__ __forceinline__ u32 tile_offset(int j) { return tile_offset_t<WAVES>(j); }
 
+// The same layout for a part of a tile: NW waves of IT items each, wave w
+// owning entries [w*64*IT, (w+1)*64*IT).
+template <int NW, int IT>
+__device__ __forceinline__ u32 part_offset(int j) {
+  return (threadIdx.x >> 6) * (64 * IT) + j * 64 + __lane_id();
+}
+
 // First half of the stable rank: lanes holding the same digit ("peers") are
 // found with one ballot per digit bit; rank[j] = position of item j among the
 // tile's entries with the same digit that precede it in its wave.  On return
 // (after a barrier) whist[w][d] = entries with digit d in waves before w, and
 // thread t < 256 gets the tile's count of digit t (0 for other threads).
-// Item j is present iff bit j of `valid` is set.
+// Item j is present iff bit j of `valid` is set.  Items are laid out as in
+// part_offset<NW, IT> (for NW*64*IT == TILE, as in tile_offset_t<NW>).
 template <int NW, int IT>
 __device__ __forceinline__ u32 rank_count(u32 (&whist)[NW][RADIX], const u32 (&d)[IT], u32 valid,
                                           u32 (&rank)[IT]) {
-  static_assert(NW * 64 * IT == TILE, "tile geometry");
+  static_assert(NW * 64 * IT <= TILE && IT <= 32, "tile geometry");
   const u32 tid = threadIdx.x;
   const u32 w = tid >> 6;
   const u32 lane = __lane_id();

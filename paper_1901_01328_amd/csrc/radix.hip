@@ -24,6 +24,7 @@ struct RadixDF {
   static constexpr int SMEM = 1;
   __device__ __forceinline__ void bind(float*) {}
   struct Params {};
+  RadixDF() = default;
   __device__ __forceinline__ RadixDF(const Params&, u32) {}
   __device__ __forceinline__ u32 digit(u64 k, u32 pass) const {
     return (u32)(k >> (8 * pass)) & 255u;

@@ -118,6 +118,31 @@ def test_batch_learned_matches_oracle(K, orc, mid):
     assert st[0] > 0  # buckets were formed for the large segments
 
 
+def test_batch_learned_workspace_reused_with_fewer_large_windows(K, orc):
+    """One workspace serves a batch whose 64 windows are all large, then one
+    with three large windows among small ones: what the first call left in
+    the workspace (tile maps, models, bucket counts) must not leak into the
+    second call's result."""
+    n_seg = 64
+    first = np.full(n_seg, 70000, np.int64)
+    second = np.full(n_seg, 1000, np.int64)
+    second[[5, 30, 61]] = 1_200_000
+    n_cap = int(max(first.sum(), second.sum()))
+    cfg = K.batch_config(4096, 1 << 16, 0, K.KPA_SORT_LEARNED)
+    ws = torch.empty(K.kpa_batch_sort_workspace_size(n_cap, n_seg, cfg), dtype=torch.uint8,
+                     device="cuda")
+    for label, sizes in (("all large", first), ("three large", second)):
+        models = prior_models(K, orc, sizes)
+        keys, rids, off = make_batch(sizes, epoch=1)
+        say(f"batch learned, reused workspace: {label}")
+        ok, orr = K.kpa_batch_sort(dev_u64(keys), dev_u32(rids), dev_u64(off), cfg=cfg,
+                                   n_cap=n_cap, models=models, ws=ws)
+        torch.cuda.synchronize()
+        ek, er = orc.sort_segmented(keys, rids, off)
+        assert np.array_equal(u64(ok), ek), label
+        assert np.array_equal(u32(orr), er), label
+
+
 def test_batch_graph_replay(K, orc):
     """One captured graph of batch sort + keyed reduce, replayed on three
     batches with different segmentations and keys (same segment count and

@@ -134,6 +134,21 @@ def test_learned_sort_segmented_ragged(K, orc):
     check_learned(K, orc, keys2, rids, off, models)
 
 
+def test_learned_chunk_with_few_inversions(K, orc):
+    """One window of the drifting-skew batch's control variant (Zipf ranks
+    hashed over 2^32; window 107 of 300, model fitted on the previous epoch):
+    it has a finishing chunk whose only out-of-order keys lie in its first
+    bucket while a long in-order run of one key holds its largest refined ids,
+    so both byte passes over the refined ids must run."""
+    n = 101515
+    gen = lambda e: datagen.gen_c4_window(107, e, n, n_windows=300, control=True,
+                                          device="cuda")[:, 0].cpu().numpy().view(np.uint64)
+    off = seg_offsets([n])
+    models, _ = fit_models(K, gen(0), off)
+    say("learned, chunk with few inversions")
+    check_learned(K, orc, gen(1), np.arange(n, dtype=np.uint32), off, models)
+
+
 def test_forced_overflow_constant_model(K, orc):
     """All knots 0: every key lands in bucket 0 -> the whole segment overflows."""
     n = 200003
