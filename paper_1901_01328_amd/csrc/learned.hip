@@ -56,7 +56,10 @@ __device__ __forceinline__ void stat_add(kpa_sort_stats* st, int idx, u64 v) {
 
 // One workgroup per segment (grid-stride): validate the model, choose the
 // bucket count.
-// Smallest and largest key of every segment (one atomic pair per tile).
+// Smallest and largest key of every segment.  Each workgroup takes a
+// contiguous run of tiles, loads a tile with ITEMS independent loads per
+// thread, keeps the running extremes of the current segment and publishes
+// them (one atomic pair) when the segment changes and at the end.
 __global__ void __launch_bounds__(BLOCK) k_seg_minmax(const u64* __restrict__ keys, SegList sl,
                                                       const u32* __restrict__ tile_start,
                                                       const u32* __restrict__ tile_seg,
@@ -65,17 +68,11 @@ __global__ void __launch_bounds__(BLOCK) k_seg_minmax(const u64* __restrict__ ke
   __shared__ u64 red[2 * WAVES];
   const u32 n_seg = sl.n();
   const u32 total = tile_start[n_seg];
-  for (u32 t = blockIdx.x; t < total; t += gridDim.x) {
-    const u32 s = tile_seg[t];
-    const u64 a = sl.lo[s], b = sl.hi[s];
-    const u64 base = a + (u64)(t - tile_start[s]) * TILE;
-    const u64 end = min(b, base + TILE);
-    u64 lo = ~0ull, hi = 0;
-    for (u64 i = base + threadIdx.x; i < end; i += BLOCK) {
-      const u64 k = keys[i];
-      lo = k < lo ? k : lo;
-      hi = k > hi ? k : hi;
-    }
+  const u32 per = (total + gridDim.x - 1) / gridDim.x;
+  const u32 t0 = blockIdx.x * per, t1 = min(total, t0 + per);
+  u64 lo = ~0ull, hi = 0;
+  u32 cur = NONE;
+  auto publish = [&]() {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
       const u64 l2 = __shfl_xor(lo, o, 64), h2 = __shfl_xor(hi, o, 64);
@@ -88,17 +85,42 @@ __global__ void __launch_bounds__(BLOCK) k_seg_minmax(const u64* __restrict__ ke
       red[WAVES + (threadIdx.x >> 6)] = hi;
     }
     __syncthreads();
-    if (threadIdx.x == 0 && base < end) {
-      for (int w = 1; w < WAVES; ++w) {
+    if (threadIdx.x == 0) {
+      for (int w = 0; w < WAVES; ++w) {
         lo = red[w] < lo ? red[w] : lo;
         hi = red[WAVES + w] > hi ? red[WAVES + w] : hi;
       }
-      lo = red[0] < lo ? red[0] : lo;
-      hi = red[WAVES] > hi ? red[WAVES] : hi;
-      atomicMin(reinterpret_cast<unsigned long long*>(kmin + s), (unsigned long long)lo);
-      atomicMax(reinterpret_cast<unsigned long long*>(kmax + s), (unsigned long long)hi);
+      if (lo <= hi) {  // the segment had keys in these tiles
+        atomicMin(reinterpret_cast<unsigned long long*>(kmin + cur), (unsigned long long)lo);
+        atomicMax(reinterpret_cast<unsigned long long*>(kmax + cur), (unsigned long long)hi);
+      }
+    }
+    lo = ~0ull;
+    hi = 0;
+  };
+  for (u32 t = t0; t < t1; ++t) {
+    const u32 s = tile_seg[t];
+    if (s != cur) {
+      if (cur != NONE) publish();
+      cur = s;
+    }
+    const u64 base = sl.lo[s] + (u64)(t - tile_start[s]) * TILE;
+    const u64 end = min(sl.hi[s], base + TILE);
+    u64 k[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      const u64 i = base + (u64)j * BLOCK + threadIdx.x;
+      k[j] = i < end ? keys[i] : 0ull;
+    }
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      if (base + (u64)j * BLOCK + threadIdx.x < end) {
+        lo = k[j] < lo ? k[j] : lo;
+        hi = k[j] > hi ? k[j] : hi;
+      }
     }
   }
+  if (cur != NONE) publish();
 }
 
 // The model's knots describe the shape of the CDF over the key range it was
@@ -906,7 +928,7 @@ kpa_status learned_sort_launch(const u64* keys_in, const u32* rids_in, u64* keys
   KPA_CHECK(launch_tile_seg(lw.ltile_start, n_seg, sl.n_dev, lw.max_tiles, lw.ltile_seg, st));
   KPA_CHECK(launch_fill_u64(lw.cur_min, n_seg, ~0ull, st));
   KPA_CHECK(launch_fill_u64(lw.cur_max, n_seg, 0ull, st));
-  KPA_LAUNCH("learned_minmax", k_seg_minmax, dim3((u32)std::min<u64>(lw.max_tiles, 8192)),
+  KPA_LAUNCH("learned_minmax", k_seg_minmax, dim3((u32)std::min<u64>(lw.max_tiles, 2048)),
              dim3(BLOCK), 0, st, keys_in, sl, lw.ltile_start, lw.ltile_seg, lw.cur_min,
              lw.cur_max);
   KPA_LAUNCH("learned_setup", k_learned_setup, dim3(std::min<u32>(n_seg, 2048)), dim3(BLOCK), 0,

@@ -46,7 +46,8 @@ __device__ __forceinline__ const lds_float* bind_knots(const SegModel& m, float*
 // [knots[j], knots[j+1]], so F never decreases.  The two fused operations
 // are written out so that every kernel evaluating the model computes the
 // same bits, whatever the compiler would contract.
-__device__ __forceinline__ float pwl_eval(const SegModel& m, const lds_float* kn, u64 key) {
+template <class KP>
+__device__ __forceinline__ float pwl_eval(const SegModel& m, const KP* kn, u64 key) {
   const u64 d = key > m.kmin ? (key - m.kmin) >> m.sh : 0ull;
   const float hf = (float)(d < (u64)m.hspan ? (u32)d : m.hspan);
   const float x = hf * m.scale;
@@ -57,7 +58,8 @@ __device__ __forceinline__ float pwl_eval(const SegModel& m, const lds_float* kn
   return __builtin_amdgcn_fmed3f(fmaf(f, b - a, a), a, b);
 }
 
-__device__ __forceinline__ u32 model_bucket(const SegModel& m, const lds_float* kn, u64 key) {
+template <class KP>
+__device__ __forceinline__ u32 model_bucket(const SegModel& m, const KP* kn, u64 key) {
   if (m.bits == 0) return 0u;
   const float B = (float)(1u << m.bits);
   const u32 b = (u32)(pwl_eval(m, kn, key) * B);
@@ -68,7 +70,8 @@ __device__ __forceinline__ u32 model_bucket(const SegModel& m, const lds_float* 
 // Bucket id refined by 8 more bits: floor(F * 2^(bits+8)), capped.  Scaling
 // by a power of two is exact, so model_fine(k) >> 8 == model_bucket(k) for
 // every key (bits <= 16, so the product stays below 2^24 and exact).
-__device__ __forceinline__ u32 model_fine(const SegModel& m, const lds_float* kn, u64 key) {
+template <class KP>
+__device__ __forceinline__ u32 model_fine(const SegModel& m, const KP* kn, u64 key) {
   const float B = (float)(1u << (m.bits + 8));
   const u32 b = (u32)(pwl_eval(m, kn, key) * B);
   const u32 top = (1u << (m.bits + 8)) - 1;
