@@ -297,6 +297,13 @@ constexpr int PASS_THREADS = PASS_WAVES * 64;
 constexpr int PASS_ITEMS = TILE / PASS_THREADS;
 static_assert(PASS_THREADS >= RADIX && PASS_ITEMS * PASS_THREADS == TILE, "pass geometry");
 
+// One scatter pass over all tiles (persistent workgroups claiming tiles in
+// the order of the tile descriptors).  A workgroup claims its next tile and
+// issues that tile's loads as soon as the current one is staged in LDS, so
+// that the loads are in flight during the current tile's look-back and
+// write.  The prefetched tile publishes its counts only after the current
+// one is written; every wait of a look-back still goes to a tile claimed
+// earlier, so the waits cannot form a cycle.
 template <class DF>
 __global__ void __launch_bounds__(PASS_THREADS, PASS_WAVES / 2)
     k_ds_pass(DigitSortBufs bf, SegList sl, typename DF::Params prm, u32 pass,
@@ -314,65 +321,89 @@ __global__ void __launch_bounds__(PASS_THREADS, PASS_WAVES / 2)
     return;
   }
   u32* counter = bf.counters + pass;
-  u32 bound = 0xFFFFFFFFu;  // segment whose digit function is in dfsm
-  DF df;
-  while (true) {
-    __syncthreads();
-    if (tid == 0) sm.tile = atomicAdd(counter, 1u);
-    __syncthreads();
-    const u32 c = sm.tile;
-    if (c >= total) return;
-    const TileDesc td = bf.order.desc[c];
-    if (tid < RADIX) status_next[(u64)td.g * RADIX + tid] = 0;  // ready for the next pass
-    const u32 mask = td.mask;
-    if (mask & SEG_UNSUPPORTED) continue;
-    const u32 seg = td.seg, cnt = td.cnt;
-    const u64 base = td.base;
-    const u32 k = __popc(mask);
-    if (k == 0) {
-      if (pass == 0 && bf.keys_in != bf.keys_out) {
-        for (u32 i = tid; i < cnt; i += PASS_THREADS) {
-          bf.keys_out[base + i] = bf.keys_in[base + i];
-          bf.rids_out[base + i] = bf.rids_in[base + i];
+  // Claims tiles until one has work in this pass; false when none is left.
+  // Every claimed tile prepares its look-back words for the next pass; a
+  // segment that needs no pass at all is copied in pass 0.
+  auto claim = [&](TileDesc& td) -> bool {
+    while (true) {
+      __syncthreads();
+      if (tid == 0) sm.tile = atomicAdd(counter, 1u);
+      __syncthreads();
+      const u32 c = sm.tile;
+      if (c >= total) return false;
+      td = bf.order.desc[c];
+      if (tid < RADIX) status_next[(u64)td.g * RADIX + tid] = 0;
+      const u32 mask = td.mask;
+      if (mask & SEG_UNSUPPORTED) continue;
+      if (__popc(mask) == 0) {
+        if (pass == 0 && bf.keys_in != bf.keys_out) {
+          for (u32 i = tid; i < td.cnt; i += PASS_THREADS) {
+            bf.keys_out[td.base + i] = bf.keys_in[td.base + i];
+            bf.rids_out[td.base + i] = bf.rids_in[td.base + i];
+          }
         }
+        continue;
       }
-      continue;
+      if ((mask >> pass) & 1) return true;
     }
-    if (!((mask >> pass) & 1)) continue;
-    const u32 q = __popc(mask & ((1u << pass) - 1));
+  };
+  // Issues a claimed tile's loads (the pass's source buffer depends on how
+  // many of the segment's passes came before); returns the present-item bits.
+  auto load = [&](const TileDesc& td, u64 (&kk)[PASS_ITEMS], u32 (&rr)[PASS_ITEMS]) -> u32 {
+    const u32 k = __popc(td.mask), q = __popc(td.mask & ((1u << pass) - 1));
     const u64* src_k = q == 0 ? bf.keys_in : (((k - q) & 1) == 0 ? bf.keys_out : bf.keys_tmp);
     const u32* src_r = q == 0 ? bf.rids_in : (((k - q) & 1) == 0 ? bf.rids_out : bf.rids_tmp);
-    u64* dst_k = ((k - 1 - q) & 1) == 0 ? bf.keys_out : bf.keys_tmp;
-    u32* dst_r = ((k - 1 - q) & 1) == 0 ? bf.rids_out : bf.rids_tmp;
-
-    u64 kk[PASS_ITEMS];
-    u32 rr[PASS_ITEMS], dd[PASS_ITEMS];
     u32 valid = 0;
 #pragma unroll
     for (int j = 0; j < PASS_ITEMS; ++j) {
       const u32 o = tile_offset_t<PASS_WAVES>(j);
-      if (o < cnt) {
-        kk[j] = src_k[base + o];
-        rr[j] = src_r[base + o];
+      if (o < td.cnt) {
+        kk[j] = src_k[td.base + o];
+        rr[j] = src_r[td.base + o];
         valid |= 1u << j;
       } else {
         kk[j] = 0;
         rr[j] = 0;
       }
     }
-    const u64 seg_start = base - (u64)td.t_in * TILE;
+    return valid;
+  };
+
+  TileDesc td;
+  if (!claim(td)) return;
+  u64 kk[PASS_ITEMS];
+  u32 rr[PASS_ITEMS];
+  u32 valid = load(td, kk, rr);
+  u32 bound = 0xFFFFFFFFu;  // segment whose digit function is in dfsm
+  DF df;
+  while (true) {
+    const u32 k = __popc(td.mask), q = __popc(td.mask & ((1u << pass) - 1));
+    u64* dst_k = ((k - 1 - q) & 1) == 0 ? bf.keys_out : bf.keys_tmp;
+    u32* dst_r = ((k - 1 - q) & 1) == 0 ? bf.rids_out : bf.rids_tmp;
+    const u64 seg_start = td.base - (u64)td.t_in * TILE;
     const u64 my_base =
-        tid < RADIX ? seg_start + bf.hist[((u64)seg * DF::PASSES + pass) * RADIX + tid] : 0ull;
-    if (seg != bound) {
+        tid < RADIX ? seg_start + bf.hist[((u64)td.seg * DF::PASSES + pass) * RADIX + tid] : 0ull;
+    if (td.seg != bound) {
       // the previous tile's digits were computed before its barriers
-      df = DF(prm, seg);
+      df = DF(prm, td.seg);
       df.bind(dfsm);
       if (DF::SMEM > 1) __syncthreads();
-      bound = seg;
+      bound = td.seg;
     }
+    u32 dd[PASS_ITEMS];
 #pragma unroll
     for (int j = 0; j < PASS_ITEMS; ++j) dd[j] = ((valid >> j) & 1) ? df.digit(kk[j], pass) : 0u;
-    onesweep_tile(sm, kk, rr, dd, valid, status_cur, td.g, td.t_in, my_base, dst_k, dst_r);
+    u32 tile_count;
+    const u32 cnt_d =
+        onesweep_rank_stage(sm, kk, rr, dd, valid, status_cur, td.g, td.t_in, &tile_count);
+    TileDesc nt;
+    const bool more = claim(nt);
+    const u32 nvalid = more ? load(nt, kk, rr) : 0u;
+    onesweep_lookback_write(sm, status_cur, td.g, td.t_in, cnt_d, tile_count, my_base, dst_k,
+                            dst_r);
+    if (!more) return;
+    td = nt;
+    valid = nvalid;
   }
 }
 

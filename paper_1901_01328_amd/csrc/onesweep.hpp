@@ -167,41 +167,52 @@ __device__ __forceinline__ void stage_scatter(SM& sm, const u64 (&k)[IT], const 
   write_staged<SM, TILE / (64 * IT)>(sm, keys_out, rids_out);
 }
 
-// Ranks, publishes, looks back and scatters.  k/r/d hold this thread's items;
-// item j is present iff bit j of `valid` is set.  my_digit_base is, for
-// threads t < 256, the global index where digit t of the segment begins
-// (segment start plus the segment's exclusive digit count).  status points at
-// the look-back words of tile 0; the tile's own row is status + tile*RADIX.
-// tile_in_seg: index of the tile within its segment (the first tile's prefix
-// is its own count).
+// First half of a tile's scatter: ranks, publishes and stages.  k/r/d hold
+// this thread's items; item j is present iff bit j of `valid` is set.
+// status points at the look-back words of tile 0; the tile's own row is
+// status + tile*RADIX.  tile_in_seg: index of the tile within its segment
+// (the first tile's prefix is its own count).  Returns the thread's digit
+// count (threads t < 256: digit t) and sets *tile_count; k/r/d are no longer
+// needed afterwards.
 //
 // The tile's counts are published as soon as they are known; the tile is
 // staged in LDS before the look-back, so that predecessors have more time to
 // publish and the wait overlaps useful work.
 template <int NW, int IT>
-__device__ __forceinline__ void onesweep_tile(OnesweepSmemT<NW>& sm, const u64 (&k)[IT],
-                                              const u32 (&r)[IT], const u32 (&d)[IT],
-                                              u32 valid, u32* __restrict__ status, u32 tile,
-                                              u32 tile_in_seg, u64 my_digit_base,
-                                              u64* __restrict__ keys_out,
-                                              u32* __restrict__ rids_out) {
+__device__ __forceinline__ u32 onesweep_rank_stage(OnesweepSmemT<NW>& sm, const u64 (&k)[IT],
+                                                   const u32 (&r)[IT], const u32 (&d)[IT],
+                                                   u32 valid, u32* __restrict__ status, u32 tile,
+                                                   u32 tile_in_seg, u32* tile_count) {
   const u32 tid = threadIdx.x;
-  const bool first = tile_in_seg == 0;
   u32 rank[IT];
   const u32 total = rank_count<NW, IT>(sm.whist, d, valid, rank);
-  u32* my = status + (u64)tile * RADIX + tid;
-  if (tid < RADIX) st_status(my, (first ? ST_PRE : ST_AGG) | total);
-  u32 tile_count;
-  rank_starts<NW>(total, sm.lstart, sm.scan, &tile_count);
+  if (tid < RADIX) st_status(status + (u64)tile * RADIX + tid, (tile_in_seg == 0 ? ST_PRE : ST_AGG) | total);
+  rank_starts<NW>(total, sm.lstart, sm.scan, tile_count);
   stage_tile<OnesweepSmemT<NW>, IT>(sm, k, r, d, rank, valid);
+  return total;
+}
 
-  // Decoupled look-back over earlier tiles of the segment, LB_WINDOW tiles
-  // per round trip.  Every tile with a lower index was claimed by a running
-  // workgroup before this one and publishes its count without waiting, so the
-  // loop ends; the segment's first tile always holds a prefix.
+// Second half: decoupled look-back over earlier tiles of the segment, then
+// the staged tile goes out.  my_digit_base is, for threads t < 256, the
+// global index where digit t of the segment begins (segment start plus the
+// segment's exclusive digit count).
+//
+// The look-back reads LB_WINDOW tiles per round trip.  Every tile with a
+// lower index was claimed by a running workgroup before this one and
+// publishes its count before waiting on anything, so the loop ends; the
+// segment's first tile always holds a prefix.
+template <int NW>
+__device__ __forceinline__ void onesweep_lookback_write(OnesweepSmemT<NW>& sm,
+                                                        u32* __restrict__ status, u32 tile,
+                                                        u32 tile_in_seg, u32 total,
+                                                        u32 tile_count, u64 my_digit_base,
+                                                        u64* __restrict__ keys_out,
+                                                        u32* __restrict__ rids_out) {
+  const u32 tid = threadIdx.x;
   if (tid < RADIX) {
+    u32* my = status + (u64)tile * RADIX + tid;
     u32 excl = 0;
-    if (!first) {
+    if (tile_in_seg != 0) {
       const u32* p = my - RADIX;
       u32 left = tile_in_seg;  // predecessors in the segment
       while (true) {
@@ -236,6 +247,21 @@ __device__ __forceinline__ void onesweep_tile(OnesweepSmemT<NW>& sm, const u64 (
   if (tid == 0) sm.count = tile_count;
   __syncthreads();
   write_staged<OnesweepSmemT<NW>, NW>(sm, keys_out, rids_out);
+}
+
+// Both halves for one tile.
+template <int NW, int IT>
+__device__ __forceinline__ void onesweep_tile(OnesweepSmemT<NW>& sm, const u64 (&k)[IT],
+                                              const u32 (&r)[IT], const u32 (&d)[IT],
+                                              u32 valid, u32* __restrict__ status, u32 tile,
+                                              u32 tile_in_seg, u64 my_digit_base,
+                                              u64* __restrict__ keys_out,
+                                              u32* __restrict__ rids_out) {
+  u32 tile_count;
+  const u32 total =
+      onesweep_rank_stage<NW, IT>(sm, k, r, d, valid, status, tile, tile_in_seg, &tile_count);
+  onesweep_lookback_write<NW>(sm, status, tile, tile_in_seg, total, tile_count, my_digit_base,
+                              keys_out, rids_out);
 }
 
 }  // namespace kpa
