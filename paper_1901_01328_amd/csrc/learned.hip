@@ -496,13 +496,27 @@ static_assert(FIN_FIRST <= FCAP + 1, "the first read fits the window");
 constexpr int FIN_IT = (FIN_FIRST + BLOCK - 1) / BLOCK;
 
 // Window entries [from, to): keys from keys[g + i] and their refined ids.
+// Each thread issues all its loads of a batch of N entries before using any,
+// so that one memory latency covers the batch.
+template <int N>
 __device__ __forceinline__ void load_window(FinishSmem& sm, const SegModel& m, const lds_float* kn,
                                             const u64* __restrict__ keys, u64 g, u32 from,
                                             u32 to) {
-  for (u32 i = from + threadIdx.x; i < to; i += BLOCK) {
-    const u64 kv = keys[g + i];
-    sm.skeys[i] = kv;
-    sm.srel[i] = m.valid ? model_fine(m, kn, kv) : 0u;
+  for (u32 b = from; b < to; b += N * BLOCK) {
+    u64 kv[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const u32 i = b + threadIdx.x + j * BLOCK;
+      kv[j] = i < to ? keys[g + i] : 0ull;
+    }
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const u32 i = b + threadIdx.x + j * BLOCK;
+      if (i < to) {
+        sm.skeys[i] = kv[j];
+        sm.srel[i] = m.valid ? model_fine(m, kn, kv[j]) : 0u;
+      }
+    }
   }
 }
 
@@ -558,7 +572,7 @@ __global__ void __launch_bounds__(BLOCK, 2) k_learned_finish(
   // --- window from L0: the entry before the stretch (k > 0) or pos0 = a ---
   const u64 L0 = k > 0 ? pos0 - 1 : pos0;
   u32 have = (u32)min<u64>(FIN_FIRST, b - L0);
-  load_window(sm, m, kn, keys, L0, 0, have);
+  load_window<FIN_IT>(sm, m, kn, keys, L0, 0, have);
   __syncthreads();
   u32 s0 = 0;  // window index of the chunk's first entry
   if (k > 0) {
@@ -603,7 +617,7 @@ __global__ void __launch_bounds__(BLOCK, 2) k_learned_finish(
   const u32 want = (u32)min<u64>(FCAP + 1, b - start);
   u32 endo = first_edge(sm, e_lo, have);
   if (endo == NONE && have < want) {
-    load_window(sm, m, kn, keys, start, have, want);
+    load_window<8>(sm, m, kn, keys, start, have, want);
     __syncthreads();
     endo = first_edge(sm, max(e_lo, have), want);
     have = want;
