@@ -33,6 +33,7 @@ namespace kpa {
 namespace {
 
 struct BatchSmem {
+  static constexpr int kWaves = WAVES;
   u32 whist[WAVES][RADIX];
   u32 lstart[RADIX];
   u64 gbase[RADIX];

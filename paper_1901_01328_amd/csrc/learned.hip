@@ -177,15 +177,22 @@ __global__ void __launch_bounds__(BLOCK) k_learned_setup(const kpa_pwl_model* __
   }
 }
 
+// The finishing workgroup: 8 waves, two workgroups per CU (LDS-bound), so
+// that each SIMD keeps four waves to hide LDS and memory latency.
+constexpr int FIN_WAVES = 8;
+constexpr u32 FIN_THREADS = FIN_WAVES * 64;
+constexpr int FIN_ITEMS = FCAP / FIN_THREADS;  // entries per thread of a full chunk
 constexpr u32 SHORT_RUN = 64;  // runs up to this length are ranked by counting
 constexpr u32 LONG_RUNS = 64;  // long runs a chunk may split before the byte-wise sort
 
-struct FinishSmem {
-  u32 whist[WAVES][RADIX];
+template <int NW>
+struct FinishSmemT {
+  static constexpr int kWaves = NW;
+  u32 whist[NW][RADIX];
   u32 lstart[RADIX];
-  u32 scan[WAVES + 1];
-  u32 red[WAVES];
-  u64 red64[2 * WAVES];
+  u32 scan[NW + 1];
+  u32 red[NW];
+  u64 red64[2 * NW];
   float knots[KPA_PWL_MAX_SEG + 1];
   u64 skeys[FCAP + 1];
   u32 srids[FCAP];
@@ -195,10 +202,11 @@ struct FinishSmem {
   u32 long_lo[LONG_RUNS];
   u32 long_hi[LONG_RUNS];
 };
+using FinishSmem = FinishSmemT<FIN_WAVES>;
 
 // Stable ranks of the entries of a short stretch [s, e) of sm by (key,
 // position): each of the first e-s threads counts the entries that precede
-// its own, then all move at once.  e - s <= BLOCK.
+// its own, then all move at once.  e - s <= FIN_THREADS.
 __device__ __forceinline__ void rank_short(FinishSmem& sm, u32 s, u32 e) {
   const u32 tid = threadIdx.x;
   u64 k = 0;
@@ -255,14 +263,14 @@ __device__ void split_long_runs(FinishSmem& sm) {
     }
     __syncthreads();
     const u64 piv = sm.red64[0];
-    // each thread owns a contiguous part of the run (at most ITEMS entries)
-    const u32 per = (len + BLOCK - 1) / BLOCK;
+    // each thread owns a contiguous part of the run (at most FIN_ITEMS entries)
+    const u32 per = (len + FIN_THREADS - 1) / FIN_THREADS;
     const u32 b0 = min(len, tid * per), b1 = min(len, b0 + per);
-    u64 kk[ITEMS];
-    u32 rr[ITEMS];
+    u64 kk[FIN_ITEMS];
+    u32 rr[FIN_ITEMS];
     u32 lt = 0, eq = 0;
 #pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
+    for (int j = 0; j < FIN_ITEMS; ++j) {
       const u32 o = b0 + (u32)j;
       if (o < b1) {
         kk[j] = sm.skeys[s + o];
@@ -272,12 +280,12 @@ __device__ void split_long_runs(FinishSmem& sm) {
       }
     }
     u32 tot;
-    const u32 ex = block_excl_sum(lt | (eq << 16), sm.scan, &tot);  // ends with a barrier
+    const u32 ex = block_excl_sum<FIN_WAVES>(lt | (eq << 16), sm.scan, &tot);  // ends with a barrier
     const u32 LT = tot & 0xFFFFu, EQ = tot >> 16;
     u32 plt = s + (ex & 0xFFFFu), peq = s + LT + (ex >> 16);
     u32 pgt = s + LT + EQ + (b0 - (ex & 0xFFFFu) - (ex >> 16));
 #pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
+    for (int j = 0; j < FIN_ITEMS; ++j) {
       const u32 o = b0 + (u32)j;
       if (o < b1) {
         const u32 d = kk[j] < piv ? plt++ : (kk[j] == piv ? peq++ : pgt++);
@@ -316,7 +324,7 @@ enum ChunkResult : u32 { CH_EQUAL = 0, CH_INORDER = 1, CH_MOVED = 2 };
 // entries are ranked by their refined bucket id (8 more bits of F, given in
 // sm.srel, taken relative to the chunk's first bucket) in one or two byte
 // passes, which leaves runs of entries sharing a refined id -- a handful each
-// when the model fits -- that are sorted by key.  The m <= WAVES*64*IT
+// when the model fits -- that are sorted by key.  The m <= FIN_THREADS*IT
 // entries are spread over IT items per thread, so that every wave has work
 // whatever the chunk's size.  A long run of distinct keys the three-way
 // splits cannot settle sends the chunk to the byte-wise LSD sort.  Returns
@@ -335,7 +343,7 @@ __device__ u32 lds_sort_model(FinishSmem& sm, const SegModel& m, u32 mcount) {
   const u32 base = (sm.srel[0] >> 8) << 8;
   if (tid == 0) sm.flag = 0;
   __syncthreads();
-  for (u32 i = tid; i < mcount; i += BLOCK) {
+  for (u32 i = tid; i < mcount; i += FIN_THREADS) {
     const u64 k = sm.skeys[i];
     vor |= k;
     vand &= k;
@@ -345,9 +353,9 @@ __device__ u32 lds_sort_model(FinishSmem& sm, const SegModel& m, u32 mcount) {
     inv = inv || (i > 0 && k < sm.skeys[i - 1]);
   }
   if (inv) sm.flag = 1;  // read after the barriers of the reductions below
-  block_or_and(vor, vand, sm.red64);
+  block_or_and<FIN_WAVES>(vor, vand, sm.red64);
   if (vor == vand) return CH_EQUAL;
-  rmax = ~block_min_u32(~rmax, sm.red);
+  rmax = ~block_min_u32<FIN_WAVES>(~rmax, sm.red);
   if (!sm.flag) return CH_INORDER;
   if (!m.valid || rmax >= (1u << 16)) {
     lds_sort(sm, mcount);
@@ -356,7 +364,7 @@ __device__ u32 lds_sort_model(FinishSmem& sm, const SegModel& m, u32 mcount) {
   u32 valid = 0;
 #pragma unroll
   for (int j = 0; j < IT; ++j)
-    if (part_offset<WAVES, IT>(j) < mcount) valid |= 1u << j;
+    if (part_offset<FIN_WAVES, IT>(j) < mcount) valid |= 1u << j;
 #pragma unroll 1
   for (u32 p = 0; p < 2; ++p) {
     if (p == 1 && rmax < 256u) break;
@@ -364,7 +372,7 @@ __device__ u32 lds_sort_model(FinishSmem& sm, const SegModel& m, u32 mcount) {
     u32 rr[IT], re[IT], d[IT], rank[IT], tc;
 #pragma unroll
     for (int j = 0; j < IT; ++j) {
-      const u32 o = part_offset<WAVES, IT>(j);
+      const u32 o = part_offset<FIN_WAVES, IT>(j);
       const bool v = (valid >> j) & 1;
       kk[j] = v ? sm.skeys[o] : 0ull;
       rr[j] = v ? sm.srids[o] : 0u;
@@ -398,7 +406,7 @@ __device__ u32 lds_sort_model(FinishSmem& sm, const SegModel& m, u32 mcount) {
   const u32 lane = __lane_id();
 #pragma unroll
   for (int j = 0; j < IT; ++j) {
-    const u32 i = part_offset<WAVES, IT>(j);
+    const u32 i = part_offset<FIN_WAVES, IT>(j);
     bool st = false, la = false, inv = false;
     if (i < mcount) {
       const u32 r = sm.srel[i];
@@ -432,7 +440,7 @@ __device__ u32 lds_sort_model(FinishSmem& sm, const SegModel& m, u32 mcount) {
   // inversion inside a run marks the run (bit 31) as needing the sort
 #pragma unroll
   for (int j = 0; j < IT; ++j)
-    if ((lastm >> j) & 1) sm.srel[rs[j]] = part_offset<WAVES, IT>(j) + 1;
+    if ((lastm >> j) & 1) sm.srel[rs[j]] = part_offset<FIN_WAVES, IT>(j) + 1;
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < IT; ++j)
@@ -445,7 +453,7 @@ __device__ u32 lds_sort_model(FinishSmem& sm, const SegModel& m, u32 mcount) {
   u32 movem = 0;
 #pragma unroll
   for (int j = 0; j < IT; ++j) {
-    const u32 i = part_offset<WAVES, IT>(j);
+    const u32 i = part_offset<FIN_WAVES, IT>(j);
     np[j] = i;
     if (i >= mcount) continue;
     const u32 s0 = rs[j], re = sm.srel[s0], e = re & 0x7FFFFFFFu;
@@ -493,7 +501,7 @@ __device__ u32 lds_sort_model(FinishSmem& sm, const SegModel& m, u32 mcount) {
 // the stretch, and KPA_FIN_EXTRA more, within which most chunks end.
 constexpr u32 FIN_FIRST = FH + 1 + KPA_FIN_EXTRA;
 static_assert(FIN_FIRST <= FCAP + 1, "the first read fits the window");
-constexpr int FIN_IT = (FIN_FIRST + BLOCK - 1) / BLOCK;
+constexpr int FIN_IT = (FIN_FIRST + FIN_THREADS - 1) / FIN_THREADS;
 
 // Window entries [from, to): keys from keys[g + i] and their refined ids.
 // Each thread issues all its loads of a batch of N entries before using any,
@@ -502,16 +510,16 @@ template <int N>
 __device__ __forceinline__ void load_window(FinishSmem& sm, const SegModel& m, const lds_float* kn,
                                             const u64* __restrict__ keys, u64 g, u32 from,
                                             u32 to) {
-  for (u32 b = from; b < to; b += N * BLOCK) {
+  for (u32 b = from; b < to; b += N * FIN_THREADS) {
     u64 kv[N];
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-      const u32 i = b + threadIdx.x + j * BLOCK;
+      const u32 i = b + threadIdx.x + j * FIN_THREADS;
       kv[j] = i < to ? keys[g + i] : 0ull;
     }
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-      const u32 i = b + threadIdx.x + j * BLOCK;
+      const u32 i = b + threadIdx.x + j * FIN_THREADS;
       if (i < to) {
         sm.skeys[i] = kv[j];
         sm.srel[i] = m.valid ? model_fine(m, kn, kv[j]) : 0u;
@@ -524,12 +532,12 @@ __device__ __forceinline__ void load_window(FinishSmem& sm, const SegModel& m, c
 // bucket differs from that of o - 1; NONE when there is none.
 __device__ __forceinline__ u32 first_edge(FinishSmem& sm, u32 lo, u32 hi) {
   u32 e = NONE;
-  for (u32 o = lo + threadIdx.x; o < hi; o += BLOCK)
+  for (u32 o = lo + threadIdx.x; o < hi; o += FIN_THREADS)
     if ((sm.srel[o] >> 8) != (sm.srel[o - 1] >> 8)) {
       e = o;
       break;
     }
-  return block_min_u32(e, sm.red);
+  return block_min_u32<FIN_WAVES>(e, sm.red);
 }
 
 // Finishing pass: one workgroup per 2048-entry stretch [pos0, pos0+FH) of a
@@ -544,7 +552,7 @@ __device__ __forceinline__ u32 first_edge(FinishSmem& sm, u32 lo, u32 hi) {
 // rewrite neighbouring chunks meanwhile; a chunk's sort only permutes entries
 // inside the chunk's buckets, so the bucket of every position never changes
 // and the edges found do not depend on timing.
-__global__ void __launch_bounds__(BLOCK, 2) k_learned_finish(
+__global__ void __launch_bounds__(FIN_THREADS, 4) k_learned_finish(
     u64* __restrict__ keys, u32* __restrict__ rids, SegList sl,
     const u32* __restrict__ ftile_start, const u32* __restrict__ ftile_seg,
     const SegModel* __restrict__ segm,
@@ -585,7 +593,7 @@ __global__ void __launch_bounds__(BLOCK, 2) k_learned_finish(
   u32 rr[FIN_IT];
 #pragma unroll
   for (int j = 0; j < FIN_IT; ++j) {
-    const u32 i = tid + j * BLOCK;
+    const u32 i = tid + j * FIN_THREADS;
     rr[j] = i < rguess ? rids[start + i] : 0u;
   }
   if (s0 > 0) {  // move the chunk to window index 0
@@ -593,7 +601,7 @@ __global__ void __launch_bounds__(BLOCK, 2) k_learned_finish(
     u32 re[FIN_IT];
 #pragma unroll
     for (int j = 0; j < FIN_IT; ++j) {
-      const u32 i = tid + j * BLOCK;
+      const u32 i = tid + j * FIN_THREADS;
       if (s0 + i < have) {
         kk[j] = sm.skeys[s0 + i];
         re[j] = sm.srel[s0 + i];
@@ -602,7 +610,7 @@ __global__ void __launch_bounds__(BLOCK, 2) k_learned_finish(
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < FIN_IT; ++j) {
-      const u32 i = tid + j * BLOCK;
+      const u32 i = tid + j * FIN_THREADS;
       if (s0 + i < have) {
         sm.skeys[i] = kk[j];
         sm.srel[i] = re[j];
@@ -646,27 +654,27 @@ __global__ void __launch_bounds__(BLOCK, 2) k_learned_finish(
   const u32 mcount = endo;  // <= FCAP
 #pragma unroll
   for (int j = 0; j < FIN_IT; ++j) {
-    const u32 i = tid + j * BLOCK;
+    const u32 i = tid + j * FIN_THREADS;
     if (i < mcount && i < rguess) sm.srids[i] = rr[j];
   }
-  for (u32 i = rguess + tid; i < mcount; i += BLOCK) sm.srids[i] = rids[start + i];
+  for (u32 i = rguess + tid; i < mcount; i += FIN_THREADS) sm.srids[i] = rids[start + i];
   u32 res;
   if (mcount <= 2048)
-    res = lds_sort_model<8>(sm, m, mcount);
+    res = lds_sort_model<4>(sm, m, mcount);
   else if (mcount <= 3072)
-    res = lds_sort_model<12>(sm, m, mcount);
+    res = lds_sort_model<6>(sm, m, mcount);
   else
-    res = lds_sort_model<16>(sm, m, mcount);
+    res = lds_sort_model<8>(sm, m, mcount);
   if (tid == 0) stat_add(stats, res == CH_EQUAL ? ST_EQUAL : ST_ONCHIP, mcount);
   if (res != CH_MOVED) return;
-  for (u32 i = tid; i < mcount; i += BLOCK) {
+  for (u32 i = tid; i < mcount; i += FIN_THREADS) {
     keys[start + i] = sm.skeys[i];
     rids[start + i] = sm.srids[i];
   }
 }
 
 // Sorts listed ranges of at most FCAP entries in place, one workgroup each.
-__global__ void __launch_bounds__(BLOCK, 2) k_lds_sort_ranges(u64* __restrict__ keys,
+__global__ void __launch_bounds__(FIN_THREADS, 4) k_lds_sort_ranges(u64* __restrict__ keys,
                                                            u32* __restrict__ rids,
                                                            const u64* __restrict__ lo,
                                                            const u64* __restrict__ hi,
@@ -678,12 +686,12 @@ __global__ void __launch_bounds__(BLOCK, 2) k_lds_sort_ranges(u64* __restrict__ 
     const u64 a = lo[r];
     const u32 m = (u32)(hi[r] - a);
     __syncthreads();
-    for (u32 i = threadIdx.x; i < m; i += BLOCK) {
+    for (u32 i = threadIdx.x; i < m; i += FIN_THREADS) {
       sm.skeys[i] = keys[a + i];
       sm.srids[i] = rids[a + i];
     }
     if (lds_sort(sm, m)) {
-      for (u32 i = threadIdx.x; i < m; i += BLOCK) {
+      for (u32 i = threadIdx.x; i < m; i += FIN_THREADS) {
         keys[a + i] = sm.skeys[i];
         rids[a + i] = sm.srids[i];
       }
@@ -954,7 +962,7 @@ kpa_status learned_sort_launch(const u64* keys_in, const u32* rids_in, u64* keys
 
   KPA_CHECK(launch_seg_tiles_list(sl, FH, lw.ftile_start, st));
   KPA_CHECK(launch_tile_seg(lw.ftile_start, n_seg, sl.n_dev, lw.max_ftiles, lw.ftile_seg, st));
-  KPA_LAUNCH("learned_finish", k_learned_finish, dim3((u32)lw.max_ftiles), dim3(BLOCK), 0, st,
+  KPA_LAUNCH("learned_finish", k_learned_finish, dim3((u32)lw.max_ftiles), dim3(FIN_THREADS), 0, st,
              keys_out, rids_out, sl, lw.ftile_start, lw.ftile_seg, lw.segm, lw.fb_lo, lw.fb_hi,
              lw.fb_count, lw.max_fb, stats);
 
@@ -985,7 +993,7 @@ kpa_status learned_sort_launch(const u64* keys_in, const u32* rids_in, u64* keys
                      lw.fb_radix.max_tiles, lw.fb_radix.order};
     KPA_CHECK(digit_sort_launch<PivotDF>(pl, PivotDF::Params{lw.pivot}, pb, st, false));
   }
-  KPA_LAUNCH("lds_sort_ranges", k_lds_sort_ranges, dim3(2048), dim3(BLOCK), 0, st, keys_out,
+  KPA_LAUNCH("lds_sort_ranges", k_lds_sort_ranges, dim3(2048), dim3(FIN_THREADS), 0, st, keys_out,
              rids_out, lw.sm_lo, lw.sm_hi, lw.rl_count + 2, 6 * lw.max_fb);
 
   // What two rounds did not resolve goes through the radix path.

@@ -7,6 +7,8 @@
 
 namespace kpa {
 
+// Block-wide reductions over NW waves (sm: NW u32, resp. 2*NW u64).
+template <int NW = WAVES>
 __device__ __forceinline__ u32 block_min_u32(u32 v, u32* sm) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
@@ -17,11 +19,12 @@ __device__ __forceinline__ u32 block_min_u32(u32 v, u32* sm) {
   if (__lane_id() == 0) sm[threadIdx.x >> 6] = v;
   __syncthreads();
   u32 r = sm[0];
-  for (int i = 1; i < WAVES; ++i) r = sm[i] < r ? sm[i] : r;
+  for (int i = 1; i < NW; ++i) r = sm[i] < r ? sm[i] : r;
   __syncthreads();
   return r;
 }
 
+template <int NW = WAVES>
 __device__ __forceinline__ void block_or_and(u64& o, u64& a, u64* sm) {
 #pragma unroll
   for (int s = 32; s > 0; s >>= 1) {
@@ -31,14 +34,14 @@ __device__ __forceinline__ void block_or_and(u64& o, u64& a, u64* sm) {
   __syncthreads();
   if (__lane_id() == 0) {
     sm[threadIdx.x >> 6] = o;
-    sm[WAVES + (threadIdx.x >> 6)] = a;
+    sm[NW + (threadIdx.x >> 6)] = a;
   }
   __syncthreads();
   o = sm[0];
-  a = sm[WAVES];
-  for (int i = 1; i < WAVES; ++i) {
+  a = sm[NW];
+  for (int i = 1; i < NW; ++i) {
     o |= sm[i];
-    a &= sm[WAVES + i];
+    a &= sm[NW + i];
   }
   __syncthreads();
 }
@@ -46,34 +49,37 @@ __device__ __forceinline__ void block_or_and(u64& o, u64& a, u64* sm) {
 constexpr u32 NONE = 0xFFFFFFFFu;
 
 // Stable on-chip sort of the m <= TILE entries held in sm.skeys/sm.srids
-// [0, m): LSD over the bytes that vary among the keys, one rank-and-move per
-// byte, data kept in LDS between passes.  Returns with the sorted entries in
-// sm (and false when nothing varied).
+// [0, m) by a workgroup of SM::kWaves waves: LSD over the bytes that vary
+// among the keys, one rank-and-move per byte, data kept in LDS between
+// passes.  Returns with the sorted entries in sm (and false when nothing
+// varied).
 template <class SM>
 __device__ bool lds_sort(SM& sm, u32 m) {
+  constexpr int NW = SM::kWaves;
+  constexpr int IT = TILE / (64 * NW);
   const u32 tid = threadIdx.x;
   const u32 w = tid >> 6;
   __syncthreads();
   u64 vor = 0, vand = ~0ull;
-  for (u32 i = tid; i < m; i += BLOCK) {
+  for (u32 i = tid; i < m; i += NW * 64) {
     vor |= sm.skeys[i];
     vand &= sm.skeys[i];
   }
-  block_or_and(vor, vand, sm.red64);
+  block_or_and<NW>(vor, vand, sm.red64);
   const u64 vary = vor ^ vand;
   if (vary == 0) return false;
   u32 valid = 0;
 #pragma unroll
-  for (int j = 0; j < ITEMS; ++j)
-    if (tile_offset(j) < m) valid |= 1u << j;
+  for (int j = 0; j < IT; ++j)
+    if (part_offset<NW, IT>(j) < m) valid |= 1u << j;
 #pragma unroll 1
   for (u32 p = 0; p < 8; ++p) {
     if (((vary >> (8 * p)) & 255u) == 0) continue;
-    u64 kk[ITEMS];
-    u32 rr[ITEMS], d[ITEMS], rank[ITEMS], tc;
+    u64 kk[IT];
+    u32 rr[IT], d[IT], rank[IT], tc;
 #pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-      const u32 o = tile_offset(j);
+    for (int j = 0; j < IT; ++j) {
+      const u32 o = part_offset<NW, IT>(j);
       kk[j] = ((valid >> j) & 1) ? sm.skeys[o] : 0ull;
       rr[j] = ((valid >> j) & 1) ? sm.srids[o] : 0u;
       d[j] = (u32)(kk[j] >> (8 * p)) & 255u;
@@ -82,7 +88,7 @@ __device__ bool lds_sort(SM& sm, u32 m) {
     rank_tile(sm.whist, sm.lstart, sm.scan, d, valid, rank, &tc);
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < ITEMS; ++j)
+    for (int j = 0; j < IT; ++j)
       if ((valid >> j) & 1) {
         const u32 pos = sm.lstart[d[j]] + sm.whist[w][d[j]] + rank[j];
         sm.skeys[pos] = kk[j];
