@@ -690,7 +690,8 @@ __global__ void __launch_bounds__(FIN_THREADS, 4) k_lds_sort_ranges(u64* __restr
       sm.skeys[i] = keys[a + i];
       sm.srids[i] = rids[a + i];
     }
-    if (lds_sort(sm, m)) {
+    const bool moved = m <= FIN_THREADS ? rank_sort_small(sm, m) : lds_sort(sm, m);
+    if (moved) {
       for (u32 i = threadIdx.x; i < m; i += FIN_THREADS) {
         keys[a + i] = sm.skeys[i];
         rids[a + i] = sm.srids[i];

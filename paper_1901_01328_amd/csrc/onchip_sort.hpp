@@ -48,6 +48,35 @@ __device__ __forceinline__ void block_or_and(u64& o, u64& a, u64* sm) {
 
 constexpr u32 NONE = 0xFFFFFFFFu;
 
+// Stable sort of the m <= SM::kWaves*64 entries in sm.skeys/sm.srids [0, m)
+// by counting: thread t takes entry t and counts the entries that precede it
+// (smaller key, or equal key at a lower position); all threads read the same
+// key at the same time, so each read is one LDS broadcast.  Returns false
+// when the entries were already in order (nothing moved).
+template <class SM>
+__device__ bool rank_sort_small(SM& sm, u32 m) {
+  const u32 tid = threadIdx.x;
+  __syncthreads();
+  const bool mine = tid < m;
+  u64 k = 0;
+  u32 r = 0, rank = 0;
+  if (mine) {
+    k = sm.skeys[tid];
+    r = sm.srids[tid];
+    for (u32 q = 0; q < m; ++q) {
+      const u64 kq = sm.skeys[q];
+      rank += (kq < k) || (kq == k && q < tid);
+    }
+  }
+  const bool moved = __syncthreads_or(mine && rank != tid);
+  if (moved && mine) {
+    sm.skeys[rank] = k;
+    sm.srids[rank] = r;
+  }
+  __syncthreads();
+  return moved;
+}
+
 // Stable on-chip sort of the m <= TILE entries held in sm.skeys/sm.srids
 // [0, m) by a workgroup of SM::kWaves waves: LSD over the bytes that vary
 // among the keys, one rank-and-move per byte, data kept in LDS between
