@@ -49,7 +49,7 @@ __device__ __forceinline__ void seg_tile_range(const SegList& sl, const u32* til
 // colliding ones); the other lanes add one each.
 __device__ __forceinline__ void wave_hist_add(u32* h, u32 d, bool v) {
   if (v) {
-    const u32 d0 = __builtin_amdgcn_readfirstlane(d);  // first active lane's digit
+    const u32 d0 = first_lane(d);  // first active lane's digit
     const bool mine = d == d0;
     const u64 same = ballot(mine);  // among the active lanes
     if (mine) {
@@ -286,6 +286,85 @@ __global__ void __launch_bounds__(BLOCK) k_ds_desc(SegList sl, const u32* __rest
   }
 }
 
+// The same descriptor with every field in scalar registers (it is uniform
+// over the workgroup).  Bases reach 2^32 - 1: both halves are taken unsigned.
+__device__ __forceinline__ TileDesc uniform_desc(const TileDesc& d) {
+  TileDesc u;
+  u.base = ((u64)first_lane((u32)(d.base >> 32)) << 32) | (u64)first_lane((u32)d.base);
+  u.seg = first_lane(d.seg);
+  u.t_in = first_lane(d.t_in);
+  u.cnt = first_lane(d.cnt);
+  u.g = first_lane(d.g);
+  u.mask = first_lane(d.mask);
+  u.pad = 0;
+  return u;
+}
+
+// Per-pass claim lists: a tile is sorted in pass p when its segment's digit
+// p varies; pass 0 also takes the segments that need no pass (they are
+// copied), and unsupported segments are in no list.
+__device__ __forceinline__ bool in_pass(u32 mask, u32 p) {
+  if (mask & SEG_UNSUPPORTED) return false;
+  return ((mask >> p) & 1u) || (p == 0 && mask == 0);
+}
+
+// Step 1: per block of LIST_BLK claims, how many are in each pass's list.
+template <int PASSES>
+__global__ void __launch_bounds__(LIST_BLK) k_ds_lcount(const u32* __restrict__ tile_start,
+                                                        SegList sl,
+                                                        const TileDesc* __restrict__ desc,
+                                                        u32* __restrict__ lcount, u32 nblk) {
+  const u32 total = tile_start[sl.n()];
+  const u32 c = blockIdx.x * LIST_BLK + threadIdx.x;
+  const u32 mask = c < total ? desc[c].mask : SEG_UNSUPPORTED;
+#pragma unroll
+  for (int p = 0; p < PASSES; ++p) {
+    const int cnt = __syncthreads_count(in_pass(mask, p));
+    if (threadIdx.x == 0) lcount[(u64)p * (nblk + 1) + blockIdx.x] = (u32)cnt;
+  }
+}
+
+// Step 2 (one workgroup): block counts -> exclusive offsets per pass, and
+// each list's size at index nblk.
+template <int PASSES>
+__global__ void __launch_bounds__(1024) k_ds_lscan(u32* __restrict__ lcount, u32 nblk) {
+  __shared__ u32 sm[17];
+  for (int p = 0; p < PASSES; ++p) {
+    u32* lc = lcount + (u64)p * (nblk + 1);
+    u32 carry = 0;
+    for (u32 b0 = 0; b0 < nblk; b0 += 1024) {
+      const u32 b = b0 + threadIdx.x;
+      const u32 v = b < nblk ? lc[b] : 0u;
+      u32 tot;
+      const u32 ex = block_excl_sum<16>(v, sm, &tot);
+      if (b < nblk) lc[b] = carry + ex;
+      carry += tot;
+    }
+    if (threadIdx.x == 0) lc[nblk] = carry;
+    __syncthreads();
+  }
+}
+
+// Step 3: the lists, in claim order.
+template <int PASSES>
+__global__ void __launch_bounds__(LIST_BLK) k_ds_lfill(const u32* __restrict__ tile_start,
+                                                       SegList sl,
+                                                       const TileDesc* __restrict__ desc,
+                                                       const u32* __restrict__ lcount, u32 nblk,
+                                                       u32* __restrict__ lists, u64 max_tiles) {
+  __shared__ u32 sm[17];
+  const u32 total = tile_start[sl.n()];
+  const u32 c = blockIdx.x * LIST_BLK + threadIdx.x;
+  const u32 mask = c < total ? desc[c].mask : SEG_UNSUPPORTED;
+#pragma unroll
+  for (int p = 0; p < PASSES; ++p) {
+    const bool in = in_pass(mask, p);
+    u32 tot;
+    const u32 ex = block_excl_sum<16>(in ? 1u : 0u, sm, &tot);
+    if (in) lists[(u64)p * max_tiles + lcount[(u64)p * (nblk + 1) + blockIdx.x] + ex] = c;
+  }
+}
+
 // Geometry of the scatter pass: PASS_WAVES waves per workgroup, so that two
 // workgroups per CU keep 4*PASS_WAVES/4 waves on each SIMD while the tile stays
 // TILE entries.
@@ -313,30 +392,32 @@ __global__ void __launch_bounds__(PASS_THREADS, PASS_WAVES / 2)
   const u32 tid = threadIdx.x;
   const u32 n_seg = sl.n();
   const u32 total = bf.tile_start[n_seg];
-  if (pass > 0 && !((bf.counters[15] >> pass) & 1)) {
-    // No segment needs this pass: only prepare the next pass's look-back words.
-    const u64 nw = (u64)total * RADIX;
-    for (u64 i = (u64)blockIdx.x * PASS_THREADS + tid; i < nw; i += (u64)gridDim.x * PASS_THREADS)
-      status_next[i] = 0;
-    return;
+  const u32 nblk = (u32)list_blocks(bf.max_tiles);
+  const u32* list = bf.order.lists + (u64)pass * bf.max_tiles;
+  const u32 nlist = bf.order.lcount[(u64)pass * (nblk + 1) + nblk];
+  const bool full = nlist == total;  // every tile takes part: list index = claim index
+  // The next pass's look-back rows of the tiles it sorts start at zero (that
+  // buffer is not used by this pass).
+  if (pass + 1 < (u32)DF::PASSES) {
+    const u32* nl = bf.order.lists + (u64)(pass + 1) * bf.max_tiles;
+    const u32 nn = bf.order.lcount[(u64)(pass + 1) * (nblk + 1) + nblk];
+    constexpr u32 ROWS = PASS_THREADS / RADIX;
+    for (u32 r = blockIdx.x * ROWS + tid / RADIX; r < nn; r += gridDim.x * ROWS)
+      status_next[(u64)bf.order.desc[nn == total ? r : nl[r]].g * RADIX + tid % RADIX] = 0;
   }
   u32* counter = bf.counters + pass;
-  // Claims tiles until one has work in this pass; false when none is left.
-  // Every claimed tile prepares its look-back words for the next pass; a
+  // Takes the next tile of this pass's list; false when none is left.  A
   // segment that needs no pass at all is copied in pass 0.
   auto claim = [&](TileDesc& td) -> bool {
     while (true) {
       __syncthreads();
       if (tid == 0) sm.tile = atomicAdd(counter, 1u);
       __syncthreads();
-      const u32 c = sm.tile;
-      if (c >= total) return false;
-      td = bf.order.desc[c];
-      if (tid < RADIX) status_next[(u64)td.g * RADIX + tid] = 0;
-      const u32 mask = td.mask;
-      if (mask & SEG_UNSUPPORTED) continue;
-      if (__popc(mask) == 0) {
-        if (pass == 0 && bf.keys_in != bf.keys_out) {
+      const u32 k = first_lane(sm.tile);  // uniform: scalar loads below
+      if (k >= nlist) return false;
+      td = uniform_desc(bf.order.desc[full ? k : first_lane(list[k])]);
+      if (td.mask == 0) {
+        if (bf.keys_in != bf.keys_out) {
           for (u32 i = tid; i < td.cnt; i += PASS_THREADS) {
             bf.keys_out[td.base + i] = bf.keys_in[td.base + i];
             bf.rids_out[td.base + i] = bf.rids_in[td.base + i];
@@ -344,7 +425,7 @@ __global__ void __launch_bounds__(PASS_THREADS, PASS_WAVES / 2)
         }
         continue;
       }
-      if ((mask >> pass) & 1) return true;
+      return true;
     }
   };
   // Issues a claimed tile's loads (the pass's source buffer depends on how
@@ -452,6 +533,14 @@ kpa_status digit_sort_launch(const SegList& sl, const typename DF::Params& prm,
   KPA_LAUNCH("sort_desc", k_ds_desc<0>,
              dim3((u32)std::min<u64>(ceil_div(b.max_tiles, BLOCK), 4096)), dim3(BLOCK), 0, st,
              sl, b.tile_start, b.order.round0, b.order.pos, b.seg_mask, b.order.desc);
+  static_assert(DF::PASSES <= LIST_PASSES, "claim lists per pass");
+  const u32 nblk = (u32)list_blocks(b.max_tiles);
+  KPA_LAUNCH("sort_lists", k_ds_lcount<DF::PASSES>, dim3(nblk), dim3(LIST_BLK), 0, st,
+             b.tile_start, sl, b.order.desc, b.order.lcount, nblk);
+  KPA_LAUNCH("sort_lists", k_ds_lscan<DF::PASSES>, dim3(1), dim3(1024), 0, st, b.order.lcount,
+             nblk);
+  KPA_LAUNCH("sort_lists", k_ds_lfill<DF::PASSES>, dim3(nblk), dim3(LIST_BLK), 0, st,
+             b.tile_start, sl, b.order.desc, b.order.lcount, nblk, b.order.lists, b.max_tiles);
   const u32 grid =
       resident_grid(k_ds_pass<DF>, (u32)std::min<u64>(b.max_tiles, 1u << 20), PASS_THREADS);
   const char* pname = radix ? "radix_pass" : (DF::PASSES == 2 ? "learned_scatter" : "pivot_scatter");

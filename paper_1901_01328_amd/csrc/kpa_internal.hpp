@@ -147,6 +147,11 @@ __device__ __forceinline__ u32 find_seg(const u32* tile_start, u32 n_seg, u32 t)
   return lo;
 }
 
+// The first active lane's value of a u32, in a scalar register.  The builtin
+// returns int; it is converted back here so that widening the result never
+// sign-extends (a 64-bit index assembled from two halves stays unsigned).
+__device__ __forceinline__ u32 first_lane(u32 v) { return (u32)__builtin_amdgcn_readfirstlane(v); }
+
 // Wave-wide inclusive sum of u32.
 __device__ __forceinline__ u32 wave_incl_sum(u32 v) {
   u32 l = __lane_id();

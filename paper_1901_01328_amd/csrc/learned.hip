@@ -702,20 +702,6 @@ __global__ void __launch_bounds__(FIN_THREADS, 4) k_lds_sort_ranges(u64* __restr
 
 // ----------------------------------------------------------- pivot rounds --
 
-struct PivotDF {
-  static constexpr int PASSES = 1;
-  static constexpr int SMEM = 1;
-  __device__ __forceinline__ void bind(float*) {}
-  struct Params {
-    const u64* pivot;
-  };
-  u64 h;
-  PivotDF() = default;
-  __device__ __forceinline__ PivotDF(const Params& p, u32 seg) : h(p.pivot[seg]) {}
-  __device__ __forceinline__ u32 digit(u64 k, u32) const { return k < h ? 0u : (k == h ? 1u : 2u); }
-  __device__ __forceinline__ void digits(u64 k, u32 (&d)[PASSES]) const { d[0] = digit(k, 0); }
-};
-
 // Pivot of each listed chunk: the most frequent of 256 evenly spaced keys
 // (ties: the smaller key).  Also clears the chunk's counters.
 __global__ void __launch_bounds__(BLOCK) k_fb_pivot(const u64* __restrict__ keys, SegList sl,
@@ -763,13 +749,15 @@ __global__ void __launch_bounds__(BLOCK) k_fb_pivot(const u64* __restrict__ keys
   }
 }
 
-// Entries below / equal to the pivot, per chunk (comparisons and wave sums;
-// no per-entry atomics).
+// Entries below / equal to the pivot, per tile of the chunk list and per
+// chunk (comparisons and wave sums; one atomic pair per tile).
 __global__ void __launch_bounds__(BLOCK) k_fb_count(const u64* __restrict__ keys, SegList sl,
                                                     const u32* __restrict__ tile_start,
                                                     const u32* __restrict__ tile_seg,
                                                     const u64* __restrict__ pivot,
-                                                    u64* __restrict__ cnt3) {
+                                                    u64* __restrict__ cnt3,
+                                                    u32* __restrict__ t_lt,
+                                                    u32* __restrict__ t_eq) {
   __shared__ u64 red[2 * WAVES];
   const u32 n_seg = sl.n();
   const u32 total = tile_start[n_seg];
@@ -779,10 +767,18 @@ __global__ void __launch_bounds__(BLOCK) k_fb_count(const u64* __restrict__ keys
     seg_tile_range(sl, tile_start, n_seg, tile, seg, t_in, a, b, base, cnt, tile_seg);
     const u64 h = pivot[seg];
     u64 lt = 0, eq = 0;
-    for (u32 i = threadIdx.x; i < cnt; i += BLOCK) {
-      const u64 k = keys[base + i];
-      lt += k < h;
-      eq += k == h;
+    u64 kv[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      const u32 i = threadIdx.x + j * BLOCK;
+      kv[j] = i < cnt ? keys[base + i] : 0ull;
+    }
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      if (threadIdx.x + j * BLOCK < cnt) {
+        lt += kv[j] < h;
+        eq += kv[j] == h;
+      }
     }
     lt = wave_sum(lt);
     eq = wave_sum(eq);
@@ -792,23 +788,26 @@ __global__ void __launch_bounds__(BLOCK) k_fb_count(const u64* __restrict__ keys
       red[WAVES + (threadIdx.x >> 6)] = eq;
     }
     __syncthreads();
-    if (threadIdx.x == 0 && cnt) {
+    if (threadIdx.x == 0) {
       u64 l = 0, e = 0;
       for (int i = 0; i < WAVES; ++i) {
         l += red[i];
         e += red[WAVES + i];
       }
-      atomicAdd(reinterpret_cast<unsigned long long*>(cnt3 + 3 * seg), (unsigned long long)l);
-      atomicAdd(reinterpret_cast<unsigned long long*>(cnt3 + 3 * seg + 1), (unsigned long long)e);
+      t_lt[tile] = (u32)l;
+      t_eq[tile] = (u32)e;
+      if (cnt) {
+        atomicAdd(reinterpret_cast<unsigned long long*>(cnt3 + 3 * seg), (unsigned long long)l);
+        atomicAdd(reinterpret_cast<unsigned long long*>(cnt3 + 3 * seg + 1), (unsigned long long)e);
+      }
     }
   }
 }
 
-// One thread per chunk: the three-way split's digit offsets, whether the chunk
+// One thread per chunk: whether the chunk
 // needs the scatter at all (not when it holds only the pivot key), and the
 // parts still to sort: on chip when small, else in the next round.
 __global__ void __launch_bounds__(BLOCK) k_fb_plan(SegList sl, const u64* __restrict__ cnt3,
-                                                   u64* __restrict__ rhi, u32* __restrict__ p_hist,
                                                    u32* __restrict__ p_mask,
                                                    u64* __restrict__ sm_lo, u64* __restrict__ sm_hi,
                                                    u32* __restrict__ sm_count, u32 sm_max,
@@ -821,11 +820,7 @@ __global__ void __launch_bounds__(BLOCK) k_fb_plan(SegList sl, const u64* __rest
     const u64 lt = cnt3[3 * c], eq = cnt3[3 * c + 1];
     const u64 gt = m - lt - eq;
     const bool pure = eq == m;
-    rhi[c] = pure ? a : sl.hi[c];
     p_mask[c] = pure ? 0u : 1u;
-    p_hist[(u64)c * RADIX + 0] = 0;
-    p_hist[(u64)c * RADIX + 1] = (u32)lt;
-    p_hist[(u64)c * RADIX + 2] = (u32)(lt + eq);
     if (stats) {
       stat_add(stats, ST_EQUAL, eq);
       stat_add(stats, ST_FB_ENTRIES, m - eq);
@@ -872,14 +867,106 @@ __global__ void __launch_bounds__(BLOCK) k_fb_copy_all(const u64* __restrict__ k
   }
 }
 
-// Copies the chunks that need the scatter to its input buffer.
-__global__ void __launch_bounds__(BLOCK) k_fb_copy(const u64* __restrict__ keys,
+// Per chunk to split (one workgroup each): the counts of entries below and
+// equal to the pivot in the chunk's earlier tiles (exclusive prefix over its
+// tiles, in place).
+__global__ void __launch_bounds__(1024) k_fb_tscan(SegList sl, const u32* __restrict__ tile_start,
+                                                   const u32* __restrict__ p_mask,
+                                                   u32* __restrict__ t_lt, u32* __restrict__ t_eq) {
+  __shared__ u32 sm[17];
+  const u32 n = sl.n();
+  for (u32 c = blockIdx.x; c < n; c += gridDim.x) {
+    if (!p_mask[c]) continue;
+    const u32 t0 = tile_start[c], t1 = tile_start[c + 1];
+    u32 cl = 0, ce = 0;
+    for (u32 b = t0; b < t1; b += 1024) {
+      const u32 t = b + threadIdx.x;
+      const u32 vl = t < t1 ? t_lt[t] : 0u, ve = t < t1 ? t_eq[t] : 0u;
+      u32 tl, te;
+      const u32 xl = block_excl_sum<16>(vl, sm, &tl);
+      const u32 xe = block_excl_sum<16>(ve, sm, &te);
+      if (t < t1) {
+        t_lt[t] = cl + xl;
+        t_eq[t] = ce + xe;
+      }
+      cl += tl;
+      ce += te;
+    }
+  }
+}
+
+// Stable three-way split of a chunk [a, b) around its pivot h, into the
+// temporary buffers at the final positions: entries below h go to
+// [a, a+LT), entries above to [a+LT+EQ, b) (keys and row ids), entries equal
+// to h only send their row ids to [a+LT, a+LT+EQ) (their keys are all h).
+// An entry's place in its class: the class's count in earlier tiles (tscan)
+// plus its stable rank in the tile (ballot ranks per wave, offsets across
+// waves).
+__global__ void __launch_bounds__(BLOCK) k_fb_move(const u64* __restrict__ keys,
                                                    const u32* __restrict__ rids, SegList sl,
                                                    const u32* __restrict__ tile_start,
                                                    const u32* __restrict__ tile_seg,
+                                                   const u64* __restrict__ pivot,
+                                                   const u64* __restrict__ cnt3,
                                                    const u32* __restrict__ p_mask,
-                                                   u64* __restrict__ keys_dst,
-                                                   u32* __restrict__ rids_dst) {
+                                                   const u32* __restrict__ t_lt,
+                                                   const u32* __restrict__ t_eq,
+                                                   u64* __restrict__ keys_tmp,
+                                                   u32* __restrict__ rids_tmp) {
+  __shared__ u32 whist[WAVES][RADIX];
+  const u32 n_seg = sl.n();
+  const u32 total = tile_start[n_seg];
+  const u32 w = threadIdx.x >> 6;
+  for (u32 tile = blockIdx.x; tile < total; tile += gridDim.x) {
+    u32 seg, t_in, cnt;
+    u64 a, b, base;
+    seg_tile_range(sl, tile_start, n_seg, tile, seg, t_in, a, b, base, cnt, tile_seg);
+    if (!p_mask[seg]) continue;
+    const u64 h = pivot[seg];
+    u64 kk[ITEMS];
+    u32 rr[ITEMS], d[ITEMS], rank[ITEMS];
+    u32 valid = 0;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      const u32 o = tile_offset(j);
+      kk[j] = 0;
+      rr[j] = 0;
+      d[j] = 0;
+      if (o < cnt) {
+        kk[j] = keys[base + o];
+        rr[j] = rids[base + o];
+        valid |= 1u << j;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) d[j] = kk[j] < h ? 0u : (kk[j] == h ? 1u : 2u);
+    __syncthreads();  // the previous tile's whist reads are done
+    rank_count<WAVES, ITEMS>(whist, d, valid, rank);
+    __syncthreads();  // rank_count turns the counts into cross-wave offsets after its barrier
+    const u32 lt0 = t_lt[tile], eq0 = t_eq[tile];
+    const u64 LT = cnt3[3 * seg], EQ = cnt3[3 * seg + 1];
+    const u64 start[3] = {a + lt0, a + LT + eq0, a + LT + EQ + ((u64)t_in * TILE - lt0 - eq0)};
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      if ((valid >> j) & 1) {
+        const u64 dst = start[d[j]] + whist[w][d[j]] + rank[j];
+        rids_tmp[dst] = rr[j];
+        if (d[j] != 1) keys_tmp[dst] = kk[j];
+      }
+    }
+  }
+}
+
+// The split chunks back into place: row ids from the temporary buffer; keys
+// from it too, except in the equal part, which is the pivot.
+__global__ void __launch_bounds__(BLOCK) k_fb_back(u64* __restrict__ keys, u32* __restrict__ rids,
+                                                   SegList sl, const u32* __restrict__ tile_start,
+                                                   const u32* __restrict__ tile_seg,
+                                                   const u64* __restrict__ pivot,
+                                                   const u64* __restrict__ cnt3,
+                                                   const u32* __restrict__ p_mask,
+                                                   const u64* __restrict__ keys_tmp,
+                                                   const u32* __restrict__ rids_tmp) {
   const u32 n_seg = sl.n();
   const u32 total = tile_start[n_seg];
   for (u32 tile = blockIdx.x; tile < total; tile += gridDim.x) {
@@ -887,9 +974,24 @@ __global__ void __launch_bounds__(BLOCK) k_fb_copy(const u64* __restrict__ keys,
     u64 a, b, base;
     seg_tile_range(sl, tile_start, n_seg, tile, seg, t_in, a, b, base, cnt, tile_seg);
     if (!p_mask[seg]) continue;
-    for (u32 i = threadIdx.x; i < cnt; i += BLOCK) {
-      keys_dst[base + i] = keys[base + i];
-      rids_dst[base + i] = rids[base + i];
+    const u64 h = pivot[seg];
+    const u64 e0 = a + cnt3[3 * seg], e1 = e0 + cnt3[3 * seg + 1];
+    u64 kv[ITEMS];
+    u32 rv[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      const u64 p = base + threadIdx.x + j * BLOCK;
+      const bool in = threadIdx.x + j * BLOCK < cnt;
+      rv[j] = in ? rids_tmp[p] : 0u;
+      kv[j] = (in && (p < e0 || p >= e1)) ? keys_tmp[p] : h;
+    }
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      const u64 p = base + threadIdx.x + j * BLOCK;
+      if (threadIdx.x + j * BLOCK < cnt) {
+        rids[p] = rv[j];
+        keys[p] = kv[j];
+      }
     }
   }
 }
@@ -917,7 +1019,6 @@ kpa_status learned_sort_plan(u64 n_cap, u32 n_seg, Carver& c, LearnedWs* w) {
   order_plan(c, w->max_tiles, n_seg, &w->order);
   w->fb_lo = c.take<u64>(w->max_fb);
   w->fb_hi = c.take<u64>(w->max_fb);
-  w->fb_rhi = c.take<u64>(w->max_fb);
   w->fb_min = c.take<u64>(1);
   w->fb_max = c.take<u64>(1);
   w->fb_count = c.take<u32>(1);
@@ -932,9 +1033,9 @@ kpa_status learned_sort_plan(u64 n_cap, u32 n_seg, Carver& c, LearnedWs* w) {
   w->sm_hi = c.take<u64>(6ull * w->max_fb);
   w->pivot = c.take<u64>(w->max_fb);
   w->cnt3 = c.take<u64>(3ull * w->max_fb);
-  w->p_hist = c.take<u32>((u64)w->max_fb * RADIX);
   w->p_mask = c.take<u32>(w->max_fb);
-  w->p_tile_start = c.take<u32>((u64)w->max_fb + 1);
+  w->t_lt = c.take<u32>(max_tiles(n_cap, w->max_fb, TILE));
+  w->t_eq = c.take<u32>(max_tiles(n_cap, w->max_fb, TILE));
   // The radix path for what the pivot rounds leave: its own ping-pong buffer
   // and per-chunk state.
   return radix_sort_plan(n_cap, w->max_fb, c, &w->fb_radix);
@@ -980,19 +1081,18 @@ kpa_status learned_sort_launch(const u64* keys_in, const u32* rids_in, u64* keys
     KPA_CHECK(launch_tile_seg(lw.fb_tile_start, lw.max_fb, cnt_in[r],
                               max_tiles(lw.n_cap, lw.max_fb, TILE), lw.fb_tile_seg, st));
     KPA_LAUNCH("pivot_count", k_fb_count, dim3(2048), dim3(BLOCK), 0, st, keys_out, fl,
-               lw.fb_tile_start, lw.fb_tile_seg, lw.pivot, lw.cnt3);
-    KPA_LAUNCH("pivot_plan", k_fb_plan, dim3(64), dim3(BLOCK), 0, st, fl, lw.cnt3, lw.fb_rhi,
-               lw.p_hist, lw.p_mask, lw.sm_lo, lw.sm_hi, lw.rl_count + 2, 6 * lw.max_fb,
-               lw.rl_lo[r], lw.rl_hi[r], lw.rl_count + r, lw.max_fb, r == 0 ? stats : nullptr);
-    KPA_LAUNCH("pivot_copy", k_fb_copy, dim3(2048), dim3(BLOCK), 0, st, keys_out, rids_out, fl,
-               lw.fb_tile_start, lw.fb_tile_seg, lw.p_mask, lw.keys_tmp, lw.rids_tmp);
-    const SegList pl{lo_in[r], lw.fb_rhi, cnt_in[r], lw.max_fb};
-    DigitSortBufs pb{lw.keys_tmp,         lw.rids_tmp,          keys_out,
-                     rids_out,            lw.fb_radix.keys_tmp, lw.fb_radix.rids_tmp,
-                     lw.p_hist,           lw.p_mask,            lw.p_tile_start,
-                     lw.fb_radix.status0, lw.fb_radix.status1,  lw.fb_radix.counters,
-                     lw.fb_radix.max_tiles, lw.fb_radix.order};
-    KPA_CHECK(digit_sort_launch<PivotDF>(pl, PivotDF::Params{lw.pivot}, pb, st, false));
+               lw.fb_tile_start, lw.fb_tile_seg, lw.pivot, lw.cnt3, lw.t_lt, lw.t_eq);
+    KPA_LAUNCH("pivot_plan", k_fb_plan, dim3(64), dim3(BLOCK), 0, st, fl, lw.cnt3, lw.p_mask,
+               lw.sm_lo, lw.sm_hi, lw.rl_count + 2, 6 * lw.max_fb, lw.rl_lo[r],
+               lw.rl_hi[r], lw.rl_count + r, lw.max_fb, r == 0 ? stats : nullptr);
+    KPA_LAUNCH("pivot_prefix", k_fb_tscan, dim3(1024), dim3(1024), 0, st, fl, lw.fb_tile_start,
+               lw.p_mask, lw.t_lt, lw.t_eq);
+    KPA_LAUNCH("pivot_move", k_fb_move, dim3(2048), dim3(BLOCK), 0, st, keys_out, rids_out, fl,
+               lw.fb_tile_start, lw.fb_tile_seg, lw.pivot, lw.cnt3, lw.p_mask, lw.t_lt, lw.t_eq,
+               lw.keys_tmp, lw.rids_tmp);
+    KPA_LAUNCH("pivot_back", k_fb_back, dim3(2048), dim3(BLOCK), 0, st, keys_out, rids_out, fl,
+               lw.fb_tile_start, lw.fb_tile_seg, lw.pivot, lw.cnt3, lw.p_mask, lw.keys_tmp,
+               lw.rids_tmp);
   }
   KPA_LAUNCH("lds_sort_ranges", k_lds_sort_ranges, dim3(2048), dim3(FIN_THREADS), 0, st, keys_out,
              rids_out, lw.sm_lo, lw.sm_hi, lw.rl_count + 2, 6 * lw.max_fb);

@@ -96,7 +96,6 @@ struct LearnedWs {
   OrderBufs order;
   u64* fb_lo;      // oversize chunks: [lo, hi)
   u64* fb_hi;
-  u64* fb_rhi;     // hi for chunks to re-sort, lo for single-key chunks
   u64* fb_min;
   u64* fb_max;
   u32* fb_count;
@@ -111,9 +110,9 @@ struct LearnedWs {
   u64* sm_hi;
   u64* pivot;
   u64* cnt3;         // per chunk: below, equal, above the pivot
-  u32* p_hist;       // digit offsets for the pivot scatter (n * 8 * 256)
-  u32* p_mask;
-  u32* p_tile_start;
+  u32* p_mask;       // per chunk: 1 when it is split (holds more than its pivot key)
+  u32* t_lt;         // per tile of the chunk list: entries below / equal to the pivot,
+  u32* t_eq;         // then their counts in the chunk's earlier tiles
   u64 n_cap;
   u64 max_tiles;
   u64 max_ftiles;

@@ -55,9 +55,10 @@ __device__ __forceinline__ u32 part_offset(int j) {
 
 // First half of the stable rank: lanes holding the same digit ("peers") are
 // found with one ballot per digit bit; rank[j] = position of item j among the
-// tile's entries with the same digit that precede it in its wave.  On return
-// (after a barrier) whist[w][d] = entries with digit d in waves before w, and
-// thread t < 256 gets the tile's count of digit t (0 for other threads).
+// tile's entries with the same digit that precede it in its wave.  Threads
+// t < 256 then turn column t into whist[w][t] = entries with digit t in waves
+// before w and get the tile's count of digit t (0 for other threads); the
+// caller synchronizes before any thread reads another thread's column.
 // Item j is present iff bit j of `valid` is set.  Items are laid out as in
 // part_offset<NW, IT> (for NW*64*IT == TILE, as in tile_offset_t<NW>).
 template <int NW, int IT>

@@ -45,7 +45,16 @@ struct OrderBufs {
   u32* round0;     // round0[r] = first claim index of round r (max_tiles + 2)
   u32* ties;       // per tile count: next position among equal segments (max_tiles + 2)
   u32* pos;        // n_seg: position of the segment inside every round
+  // Per pass p (up to LIST_PASSES): the claim indices of the tiles whose
+  // segment is sorted in pass p, in claim order (lists + p*max_tiles), and
+  // per LIST_BLK claims their count, then offset; entry nblk: the list size.
+  u32* lists;
+  u32* lcount;  // LIST_PASSES * (nblk + 1)
 };
+
+constexpr int LIST_PASSES = 8;
+constexpr u32 LIST_BLK = 1024;  // claims per list-building workgroup
+__host__ __device__ inline u64 list_blocks(u64 max_tiles) { return (max_tiles + LIST_BLK - 1) / LIST_BLK; }
 
 inline void order_plan(Carver& c, u64 max_tiles, u32 n_seg, OrderBufs* o) {
   o->desc = c.take<TileDesc>(max_tiles);
@@ -53,6 +62,8 @@ inline void order_plan(Carver& c, u64 max_tiles, u32 n_seg, OrderBufs* o) {
   o->round0 = c.take<u32>(max_tiles + 2);
   o->ties = c.take<u32>(max_tiles + 2);
   o->pos = c.take<u32>(n_seg);
+  o->lists = c.take<u32>((u64)LIST_PASSES * max_tiles);
+  o->lcount = c.take<u32>((u64)LIST_PASSES * (list_blocks(max_tiles) + 1));
 }
 
 struct RadixDigit {

@@ -164,6 +164,27 @@ def test_forced_overflow_constant_model(K, orc):
     assert st[3] >= n - 2 and st[4] >= 1
 
 
+def test_pivot_split_heavy_key_with_light_neighbours(K, orc):
+    """One oversize chunk over many tiles (all knots 0: every key in bucket 0)
+    holding a heavy key and repeated light keys on both sides of it: the
+    three-way split around the heavy key must keep each class in input order
+    (the light parts are then sorted on chip)."""
+    rng = np.random.default_rng(9)
+    n = 300001
+    H = 1 << 40
+    keys = np.full(n, H, dtype=np.int64)
+    light = rng.choice(n, 3000, replace=False)
+    keys[light] = H + rng.integers(-2000, 2000, size=3000)
+    keys = keys.astype(np.uint64)
+    off = seg_offsets([n])
+    models, _ = fit_models(K, keys, off)
+    models.view(torch.uint8)[24:24 + 4 * 1025].view(torch.float32).zero_()
+    say("pivot split, heavy key with light neighbours")
+    rids = rng.permutation(n).astype(np.uint32)
+    st = check_learned(K, orc, keys, rids, off, models)
+    assert st[4] >= 1 and st[2] >= n - 3000   # split around the heavy key
+
+
 @pytest.mark.parametrize("bad", ["decreasing", "nan", "above_one"])
 def test_invalid_model_detected(K, orc, bad):
     n = 100001
@@ -199,3 +220,44 @@ def test_learned_equals_radix_bytes(K, orc):
     rk2, rr2 = K.kpa_sort_segmented(keys2, rids2, woff2, algo=K.KPA_SORT_RADIX)
     torch.cuda.synchronize()
     assert torch.equal(lk, rk2) and torch.equal(lr, rr2)
+
+
+def test_segments_beyond_2_31_entries(K, orc):
+    """Segments placed across and above entry 2^31 of a buffer of 2^31 + 2^20
+    + 4096 entries (only they are filled): tile bases at or above 2^31 must
+    stay unsigned 64-bit offsets in every pass (radix, then learned with
+    models fitted on the radix output)."""
+    n_cap = (1 << 31) + (1 << 20) + 4096
+    a0 = (1 << 31) - 3 * 4096 - 5
+    a1 = (1 << 31) + (1 << 19) + 11
+    a2 = (1 << 31) + (1 << 20) + 1000
+    m = a2 - a0
+    keys = np.concatenate([gen_keys("zipf_mix", a1 - a0, 51), gen_keys("zipf_rank", a2 - a1, 52)])
+    rids = np.random.default_rng(53).permutation(m).astype(np.uint32) + np.uint32(7)
+    ek, er = orc.sort_segmented(keys, rids, np.array([0, a1 - a0, m], dtype=np.uint64))
+    say(f"segments [{a0}, {a1}, {a2}) in a buffer of {n_cap} entries")
+    kin = torch.empty(n_cap, dtype=torch.int64, device="cuda")
+    rin = torch.empty(n_cap, dtype=torch.int32, device="cuda")
+    kin[a0:a2] = dev_u64(keys)
+    rin[a0:a2] = dev_u32(rids)
+    off = dev_u64(np.array([a0, a1, a2], dtype=np.uint64))
+    kout = torch.empty_like(kin)
+    rout = torch.empty_like(rin)
+    try:
+        K.kpa_sort_segmented(kin, rin, off, n_cap=n_cap, keys_out=kout, rids_out=rout)
+        torch.cuda.synchronize()
+        assert np.array_equal(u64(kout[a0:a2]), ek) and np.array_equal(u32(rout[a0:a2]), er)
+        models = K.kpa_pwl_fit(kout, off, 1024)
+        kout.zero_()
+        rout.zero_()
+        say("learned, same segments")
+        stats = K.new_sort_stats("cuda")
+        K.kpa_sort_segmented(kin, rin, off, n_cap=n_cap, algo=K.KPA_SORT_LEARNED, models=models,
+                             stats=stats, keys_out=kout, rids_out=rout)
+        torch.cuda.synchronize()
+        assert np.array_equal(u64(kout[a0:a2]), ek) and np.array_equal(u32(rout[a0:a2]), er)
+        st = stats.cpu().numpy()
+        assert int(st[1] + st[2] + st[3]) == m, st
+    finally:
+        del kin, rin, kout, rout
+        torch.cuda.empty_cache()
