@@ -6,7 +6,7 @@
 //   2. a single onesweep scatter pass with digit = window id, which reads the
 //      key and timestamp of each row and writes (key, rid) into its window.
 // The scatter is stable, so each window lists its rows in arrival order.
-#include "onesweep.hpp"
+#include "digit_sort.hpp"
 
 namespace kpa {
 
@@ -17,9 +17,38 @@ struct WinParams {
   u64 win_len;
   u64 limit;  // n_win * win_len (exclusive end of the last window, relative)
   double inv; // 1 / win_len
+  float inv_f;  // 1 / win_len in single precision
   u32 n_win;
   u32 fast;   // (n_win + 1) * win_len fits in 64 bits: quotient by estimate + correction
 };
+
+// Window starts of a workgroup's scatter: bound[w] = origin + w*win_len for
+// w = 0..n_win, saturated at 2^64-1 (nondecreasing).  Filled by all threads;
+// the caller synchronizes.
+__device__ __forceinline__ void fill_bounds(u64* bound, const WinParams& p) {
+  for (u32 w = threadIdx.x; w <= p.n_win; w += blockDim.x) {
+    u64 off, b;
+    const bool ovf = __builtin_mul_overflow((u64)w, p.win_len, &off) ||
+                     __builtin_add_overflow(p.origin, off, &b);
+    bound[w] = ovf ? ~0ull : b;
+  }
+}
+
+// Window of a timestamp from the table: a single-precision estimate of
+// (ts - origin) / win_len (its relative error is below 2^-21, so for fewer than
+// 256 windows it is within one of the quotient), corrected by comparing ts
+// with the two window starts around it.  Equals the integer quotient whenever
+// the quotient is below n_win; false for timestamps outside all windows.
+__device__ __forceinline__ bool window_of_table(u64 ts, const u64* bound, const WinParams& p,
+                                                u32& w) {
+  if (ts < bound[0] || ts >= bound[p.n_win]) return false;
+  u32 q = (u32)((float)(ts - p.origin) * p.inv_f);
+  q = q < p.n_win - 1 ? q : p.n_win - 1;
+  if (ts < bound[q]) --q;
+  else if (ts >= bound[q + 1]) ++q;
+  w = q;
+  return true;
+}
 
 // Window of a timestamp, exactly as the integer quotient (ts - origin) / win_len.
 __device__ __forceinline__ bool window_of(u64 ts, const WinParams& p, u32& w) {
@@ -46,30 +75,54 @@ __device__ __forceinline__ u64 load_ts(const unsigned char* row, u32 ts_off, u32
                    : (u64)*reinterpret_cast<const u32*>(row + ts_off);
 }
 
+constexpr int PART_HIST_U = 16;  // rows per thread in flight
+
+
+// Window histogram: each thread keeps PART_HIST_U row loads in flight; rows
+// of one window are counted per wave with one LDS atomic (consecutive rows
+// mostly share a window); the optional value column is copied out on the way.
 __global__ void __launch_bounds__(BLOCK) k_part_hist(const unsigned char* __restrict__ rows,
                                                      u64 n, u32 row_bytes, u32 ts_off, u32 ts_w,
                                                      WinParams wp, u32* __restrict__ counts,
                                                      u32 val_off, u32 val_w,
                                                      u64* __restrict__ out_vals) {
-  __shared__ u32 h[RADIX + 1];
+  __shared__ u32 h[WAVES][RADIX + 1];
   const u32 tid = threadIdx.x;
-  h[tid] = 0;
-  if (tid == 0) h[RADIX] = 0;
+  const u32 w = tid >> 6;
+  for (u32 i = tid; i < WAVES * (RADIX + 1); i += BLOCK) (&h[0][0])[i] = 0;
   __syncthreads();
   const u64 r0 = (u64)blockIdx.x * PART_HIST_ROWS;
   const u64 r1 = min(n, r0 + PART_HIST_ROWS);
-  for (u64 i = r0 + tid; i < r1; i += BLOCK) {
-    u32 w;
-    const unsigned char* row = rows + i * row_bytes;
-    if (out_vals) out_vals[i] = load_ts(row, val_off, val_w);
-    if (window_of(load_ts(row, ts_off, ts_w), wp, w))
-      atomicAdd(&h[w], 1u);
-    else
-      atomicAdd(&h[RADIX], 1u);
+  for (u64 b = r0; b < r1; b += (u64)BLOCK * PART_HIST_U) {
+    u64 ts[PART_HIST_U], vv[PART_HIST_U];
+#pragma unroll
+    for (int j = 0; j < PART_HIST_U; ++j) {
+      const u64 i = b + tid + (u64)j * BLOCK;
+      ts[j] = 0;
+      vv[j] = 0;
+      if (i < r1) {
+        const unsigned char* row = rows + i * row_bytes;
+        ts[j] = load_ts(row, ts_off, ts_w);
+        if (out_vals) vv[j] = load_ts(row, val_off, val_w);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < PART_HIST_U; ++j) {
+      const u64 i = b + tid + (u64)j * BLOCK;
+      const bool v = i < r1;
+      u32 win;
+      const u32 d = v && window_of(ts[j], wp, win) ? win : (u32)RADIX;
+      wave_hist_add(h[w], d, v);
+      if (v && out_vals) out_vals[i] = vv[j];
+    }
   }
   __syncthreads();
-  if (tid < wp.n_win && h[tid]) atomicAdd(&counts[tid], h[tid]);
-  if (tid == 0 && h[RADIX]) atomicAdd(&counts[RADIX], h[RADIX]);
+  for (u32 d = tid; d <= RADIX; d += BLOCK) {
+    u32 c = 0;
+#pragma unroll
+    for (int ww = 0; ww < WAVES; ++ww) c += h[ww][d];
+    if (c && (d < wp.n_win || d == RADIX)) atomicAdd(&counts[d], c);
+  }
 }
 
 // counts -> exclusive window offsets (u32 for the scatter, u64 for the caller).
@@ -89,42 +142,86 @@ __global__ void __launch_bounds__(BLOCK) k_part_scan(u32* __restrict__ counts, u
   }
 }
 
-__global__ void __launch_bounds__(BLOCK) k_part_pass(const unsigned char* __restrict__ rows,
-                                                     u64 n, u32 row_bytes, u32 key_off,
-                                                     u32 ts_off, u32 ts_w, WinParams wp,
-                                                     u32 rid_base, const u32* __restrict__ woff,
-                                                     u32 n_tiles, u32* __restrict__ status,
-                                                     u32* __restrict__ counter,
-                                                     u64* __restrict__ keys_out,
-                                                     u32* __restrict__ rids_out) {
-  __shared__ OnesweepSmem sm;
+// The scatter: persistent workgroups of PASS_WAVES waves (two per CU) claim
+// tiles in order.  (Prefetching the next tile's rows during the look-back, as
+// the sort passes do, needs the keys and timestamps of two tiles in registers
+// here and spills.)
+__global__ void __launch_bounds__(PASS_THREADS, PASS_WAVES / 2)
+    k_part_pass(const unsigned char* __restrict__ rows, u64 n, u32 row_bytes, u32 key_off,
+                u32 ts_off, u32 ts_w, WinParams wp, u32 rid_base, const u32* __restrict__ woff,
+                u32 n_tiles, u32* __restrict__ status, u32* __restrict__ counter,
+                u64* __restrict__ keys_out, u32* __restrict__ rids_out) {
+  __shared__ OnesweepSmemT<PASS_WAVES> sm;
+  __shared__ u64 bound[RADIX + 1];
   const u32 tid = threadIdx.x;
-  if (tid == 0) sm.tile = atomicAdd(counter, 1u);
-  __syncthreads();
-  const u32 tile = sm.tile;
-  if (tile >= n_tiles) return;
-  const u64 base = (u64)tile * TILE;
-  u64 kk[ITEMS];
-  u32 rr[ITEMS], dd[ITEMS];
-  u32 valid = 0;
+  fill_bounds(bound, wp);  // the claim below synchronizes
+  auto claim = [&]() -> u32 {
+    __syncthreads();
+    if (tid == 0) sm.tile = atomicAdd(counter, 1u);
+    __syncthreads();
+    return sm.tile;
+  };
+  u64 kk[PASS_ITEMS], tt[PASS_ITEMS];
+  u32 rr[PASS_ITEMS], dd[PASS_ITEMS];
+  u32 dpk[(PASS_ITEMS + 3) / 4];  // window digits, four to a word
+  // Row loads of a tile: timestamps, then (separately) keys.
+  auto load_ts_of = [&](u32 tile) {
+    const u64 base = (u64)tile * TILE;
 #pragma unroll
-  for (int j = 0; j < ITEMS; ++j) {
-    const u64 e = base + tile_offset(j);
-    kk[j] = 0;
-    dd[j] = 0;
-    rr[j] = rid_base + (u32)e;
-    if (e < n) {
-      const unsigned char* row = rows + e * row_bytes;
-      u32 w;
-      if (window_of(load_ts(row, ts_off, ts_w), wp, w)) {
-        kk[j] = *reinterpret_cast<const u64*>(row + key_off);
-        dd[j] = w;
+    for (int j = 0; j < PASS_ITEMS; ++j) {
+      const u64 e = base + tile_offset_t<PASS_WAVES>(j);
+      tt[j] = e < n ? load_ts(rows + e * row_bytes, ts_off, ts_w) : 0ull;
+    }
+  };
+  auto load_keys_of = [&](u32 tile) {
+    const u64 base = (u64)tile * TILE;
+#pragma unroll
+    for (int j = 0; j < PASS_ITEMS; ++j) {
+      const u64 e = base + tile_offset_t<PASS_WAVES>(j);
+      kk[j] = e < n ? *reinterpret_cast<const u64*>(rows + e * row_bytes + key_off) : 0ull;
+    }
+  };
+  // Window digits (packed into dpk) from the loaded timestamps.
+  auto digits = [&](u32 tile) -> u32 {
+    const u64 base = (u64)tile * TILE;
+    u32 valid = 0;
+#pragma unroll
+    for (int i = 0; i < (PASS_ITEMS + 3) / 4; ++i) dpk[i] = 0;
+#pragma unroll
+    for (int j = 0; j < PASS_ITEMS; ++j) {
+      const u64 e = base + tile_offset_t<PASS_WAVES>(j);
+      u32 win;
+      if (e < n && window_of_table(tt[j], bound, wp, win)) {
+        dpk[j >> 2] |= win << (8 * (j & 3));
         valid |= 1u << j;
       }
     }
-  }
+    return valid;
+  };
+  u32 tile = claim();
+  if (tile >= n_tiles) return;
+  load_ts_of(tile);
+  load_keys_of(tile);
+  u32 valid = digits(tile);
   const u64 my_base = tid < wp.n_win ? (u64)woff[tid] : 0ull;
-  onesweep_tile(sm, kk, rr, dd, valid, status, tile, tile, my_base, keys_out, rids_out);
+  while (true) {
+#pragma unroll
+    for (int j = 0; j < PASS_ITEMS; ++j) {
+      rr[j] = rid_base + (u32)((u64)tile * TILE + tile_offset_t<PASS_WAVES>(j));
+      dd[j] = (dpk[j >> 2] >> (8 * (j & 3))) & 255u;
+    }
+    u32 tile_count;
+    const u32 cnt_d = onesweep_rank_stage(sm, kk, rr, dd, valid, status, tile, tile, &tile_count);
+    onesweep_lookback_write(sm, status, tile, tile, cnt_d, tile_count, my_base, keys_out,
+                            rids_out);
+    const u32 next = claim();
+    if (next >= n_tiles) return;
+    load_ts_of(next);
+    load_keys_of(next);
+    const u32 nvalid = digits(next);
+    tile = next;
+    valid = nvalid;
+  }
 }
 
 struct PartWs {
@@ -188,6 +285,7 @@ kpa_status kpa_partition_windows(const void* rows, uint64_t n, const kpa_row_lay
   wp.fast = lim < ((unsigned __int128)1 << 64) ? 1u : 0u;
   wp.limit = wp.fast ? win_len * n_win : ~0ull;
   wp.inv = 1.0 / (double)win_len;
+  wp.inv_f = 1.0f / (float)win_len;
 
   KPA_CHECK(launch_fill_u32(w.counts, RADIX + 1, 0, stream));
   KPA_CHECK(launch_fill_u32(w.counter, 1, 0, stream));
@@ -201,7 +299,8 @@ kpa_status kpa_partition_windows(const void* rows, uint64_t n, const kpa_row_lay
   KPA_LAUNCH("part_scan", k_part_scan, dim3(1), dim3(BLOCK), 0, stream, w.counts, n_win, out_win_off,
                      out_oob);
   if (n) {
-    KPA_LAUNCH("part_pass", k_part_pass, dim3((u32)w.n_tiles), dim3(BLOCK), 0, stream, r, n,
+    const u32 grid = resident_grid(k_part_pass, (u32)w.n_tiles, PASS_THREADS);
+    KPA_LAUNCH("part_pass", k_part_pass, dim3(grid), dim3(PASS_THREADS), 0, stream, r, n,
                        layout->row_bytes, layout->key_off, layout->ts_off, layout->ts_w, wp,
                        rid_base, w.counts, (u32)w.n_tiles, w.status, w.counter, out_keys,
                        out_rids);

@@ -80,6 +80,27 @@ def test_partition_with_out_of_range_and_boundaries(K, orc, n):
     assert np.array_equal(u64(keys)[:m], ek) and np.array_equal(u32(rids)[:m], er)
 
 
+def test_partition_256_windows_every_edge(K, orc):
+    """256 windows of 1000 ns: timestamps on every window start, one before and
+    one after it, and random ones (the window of a timestamp is estimated in
+    single precision and corrected against the window starts)."""
+    W, nw, origin = 1000, 256, 77
+    edges = origin + np.arange(nw + 1, dtype=np.int64) * W
+    ts = np.concatenate([edges - 1, edges, edges + 1,
+                         origin + np.random.default_rng(5).integers(0, nw * W, 60000)])
+    n = len(ts)
+    rows = c2_rows(n, span=10 ** 6)
+    rows[:, 2] = torch.from_numpy(ts)
+    say(f"partition 256 windows n={n}")
+    keys, rids, off, oob = K.kpa_partition_windows(rows.cuda(), LAYOUT32, W, nw, win_origin=origin)
+    torch.cuda.synchronize()
+    ek, er, eoff, eoob = orc.partition(rows, LAYOUT32, W, nw, origin=origin)
+    assert int(oob.item()) == eoob == 3   # origin - 1, and the end of the last window and one after
+    assert np.array_equal(u64(off), eoff)
+    m = int(eoff[-1])
+    assert np.array_equal(u64(keys)[:m], ek) and np.array_equal(u32(rids)[:m], er)
+
+
 def test_partition_16byte_rows_and_huge_window_len(K, orc):
     rows = datagen.gen_c1(50000, seed=3)
     say("partition16")
