@@ -2,9 +2,10 @@
 // and coalesce a nonresident column over each contiguous run of equal keys)
 // and top-k groups by sum.
 //
-// Reduction in three launches over 4096-entry tiles of every segment:
+// Reduction over 4096-entry tiles of every segment:
 //   1. heads: per tile, the number of runs that start in it (keys only);
-//   2. scan (one workgroup): groups started before each tile; output slots of
+//   2. scan (three short launches: sums of 1024-tile blocks, their prefix,
+//      then each tile's): groups started before each tile; output slots of
 //      runs that cross a tile edge are zeroed;
 //   3. main: per tile, gather values, segmented scan in registers/LDS, write
 //      each run at its last entry in the tile -- stored when the run lies in
@@ -114,7 +115,19 @@ __global__ void __launch_bounds__(BLOCK) k_reduce_heads(const u64* __restrict__ 
   if (tile >= tile_start[n_seg]) return;
   const TileRange tr = tile_range(seg_off, tile_start, tile_seg, tile, TILE);
   const u32 tid = threadIdx.x;
-  for (u32 i = tid; i < tr.cnt; i += BLOCK) sk[pidx(i)] = keys[tr.base + i];
+  {
+    u64 kv[ITEMS];  // all loads of the thread in flight together
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      const u32 i = tid + j * BLOCK;
+      kv[j] = i < tr.cnt ? keys[tr.base + i] : 0ull;
+    }
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      const u32 i = tid + j * BLOCK;
+      if (i < tr.cnt) sk[pidx(i)] = kv[j];
+    }
+  }
   const bool has_prev = tr.base > tr.a;
   const u64 prev = has_prev ? keys[tr.base - 1] : 0ull;
   const bool has_next = tr.base + tr.cnt < tr.b;
@@ -140,48 +153,80 @@ __global__ void __launch_bounds__(BLOCK) k_reduce_heads(const u64* __restrict__ 
   }
 }
 
-// Pass 2 (one workgroup): groups started before each tile, first group of each
-// segment, and zeroed output slots for runs that cross a tile boundary (those
-// are accumulated with atomics in pass 3).
-__global__ void __launch_bounds__(1024) k_reduce_scan(const u32* __restrict__ heads,
-                                                      const u32* __restrict__ flags,
-                                                      const u32* __restrict__ tile_start,
-                                                      u32 n_seg, u64* __restrict__ gbase,
-                                                      u64* __restrict__ gseg_off,
-                                                      u64* __restrict__ o_cnt,
-                                                      u64* __restrict__ o_sum,
-                                                      u64* __restrict__ o_max) {
+// Pass 2: groups started before each tile, in three launches over blocks of
+// SCAN_TILES tiles: the heads of each block, the exclusive prefix of the block
+// sums (and the total), then each tile's prefix.  Output slots of runs that
+// cross a tile boundary are zeroed (those runs are accumulated with atomics
+// in pass 3), and the first tile of each segment gives the segment's first
+// group.
+constexpr u32 SCAN_TILES = 1024;
+
+__global__ void __launch_bounds__(SCAN_TILES) k_reduce_bsum(const u32* __restrict__ heads,
+                                                            const u32* __restrict__ tile_start,
+                                                            u32 n_seg, u64* __restrict__ bsum) {
+  __shared__ u64 red[SCAN_TILES / 64];
+  const u32 n_tiles = tile_start[n_seg];
+  const u32 t = blockIdx.x * SCAN_TILES + threadIdx.x;
+  u64 v = wave_sum((u64)(t < n_tiles ? heads[t] : 0u));
+  if (__lane_id() == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    u64 tot = 0;
+    for (u32 i = 0; i < SCAN_TILES / 64; ++i) tot += red[i];
+    bsum[blockIdx.x] = tot;
+  }
+}
+
+// One workgroup: exclusive prefix of the nb block sums in place; the total
+// is the number of groups (gseg_off[n_seg]).
+__global__ void __launch_bounds__(1024) k_reduce_btop(u64* __restrict__ bsum, u32 nb, u32 n_seg,
+                                                      u64* __restrict__ gseg_off) {
   __shared__ u64 wh[17];
   const u32 tid = threadIdx.x, lane = __lane_id(), w = tid >> 6;
-  const u32 n_tiles = tile_start[n_seg];
-  const u32 per = (n_tiles + 1023) / 1024;
-  const u32 t0 = min(n_tiles, tid * per), t1 = min(n_tiles, t0 + per);
+  const u32 per = (nb + 1023) / 1024;
+  const u32 b0 = min(nb, tid * per), b1 = min(nb, b0 + per);
   u64 H = 0;
-  for (u32 t = t0; t < t1; ++t) H += heads[t];
+  for (u32 b = b0; b < b1; ++b) H += bsum[b];
   u64 hi = H;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
-    u64 th = __shfl_up(hi, o, 64);
+    const u64 th = __shfl_up(hi, o, 64);
     if (lane >= (u32)o) hi += th;
   }
   if (lane == 63) wh[w] = hi;
   __syncthreads();
   u64 h = hi - H;
   for (u32 i = 0; i < w; ++i) h += wh[i];
-  for (u32 t = t0; t < t1; ++t) {
-    gbase[t] = h;
-    h += heads[t];
-    if (flags[t] & 1u) {
-      const u64 g = h - 1;
-      if (o_cnt) o_cnt[g] = 0;
-      if (o_sum) o_sum[g] = 0;
-      if (o_max) o_max[g] = 0;
-    }
+  for (u32 b = b0; b < b1; ++b) {
+    const u64 c = bsum[b];
+    bsum[b] = h;
+    h += c;
   }
-  if (tid == 1023) wh[16] = h;
-  __syncthreads();
-  for (u32 s = tid; s < n_seg; s += 1024) gseg_off[s] = gbase[tile_start[s]];
-  if (tid == 0) gseg_off[n_seg] = wh[16];
+  if (tid == 1023) gseg_off[n_seg] = h;
+}
+
+__global__ void __launch_bounds__(SCAN_TILES) k_reduce_bapply(
+    const u32* __restrict__ heads, const u32* __restrict__ flags,
+    const u32* __restrict__ tile_start, const u32* __restrict__ tile_seg, u32 n_seg,
+    const u64* __restrict__ bpre, u64* __restrict__ gbase, u64* __restrict__ gseg_off,
+    u64* __restrict__ o_cnt, u64* __restrict__ o_sum, u64* __restrict__ o_max) {
+  __shared__ u32 sc[SCAN_TILES / 64 + 1];
+  const u32 n_tiles = tile_start[n_seg];
+  const u32 t = blockIdx.x * SCAN_TILES + threadIdx.x;
+  const u32 hd = t < n_tiles ? heads[t] : 0u;
+  u32 tot;
+  const u32 ex = block_excl_sum<SCAN_TILES / 64>(hd, sc, &tot);
+  if (t >= n_tiles) return;
+  const u64 g0 = bpre[blockIdx.x] + ex;
+  gbase[t] = g0;
+  if (flags[t] & 1u) {
+    const u64 g = g0 + hd - 1;
+    if (o_cnt) o_cnt[g] = 0;
+    if (o_sum) o_sum[g] = 0;
+    if (o_max) o_max[g] = 0;
+  }
+  const u32 s = tile_seg[t];
+  if (tile_start[s] == t) gseg_off[s] = g0;
 }
 
 // Pass 3: gather values, segmented reduction of each tile in registers and
@@ -202,9 +247,23 @@ __global__ void __launch_bounds__(BLOCK) k_reduce_main(
   if (tile >= tile_start[n_seg]) return;
   const TileRange tr = tile_range(seg_off, tile_start, tile_seg, tile, TILE);
   const u32 tid = threadIdx.x;
-  for (u32 i = tid; i < tr.cnt; i += BLOCK) {
-    sk[pidx(i)] = keys[tr.base + i];
-    sr[pidx(i)] = rids[tr.base + i];
+  {
+    u64 kv[ITEMS];  // all loads of the thread in flight together
+    u32 rv[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      const u32 i = tid + j * BLOCK;
+      kv[j] = i < tr.cnt ? keys[tr.base + i] : 0ull;
+      rv[j] = i < tr.cnt ? rids[tr.base + i] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      const u32 i = tid + j * BLOCK;
+      if (i < tr.cnt) {
+        sk[pidx(i)] = kv[j];
+        sr[pidx(i)] = rv[j];
+      }
+    }
   }
   const bool has_prev = tr.base > tr.a;
   const u64 prev = has_prev ? keys[tr.base - 1] : 0ull;
@@ -284,6 +343,7 @@ void reduce_plan(u64 n_cap, u32 n_seg, Carver& c, ReduceWs* w) {
   w->heads = c.take<u32>(w->max_tiles);
   w->flags = c.take<u32>(w->max_tiles);
   w->gbase = c.take<u64>(w->max_tiles);
+  w->bsum = c.take<u64>(ceil_div(w->max_tiles, SCAN_TILES));
 }
 
 kpa_status reduce_launch(const u64* keys, const u32* rids, const u64* seg_off, u32 n_seg,
@@ -299,8 +359,13 @@ kpa_status reduce_launch(const u64* keys, const u32* rids, const u64* seg_off, u
   KPA_CHECK(launch_tile_seg(w.tile_start, n_seg, nullptr, w.max_tiles, w.tile_seg, st));
   KPA_LAUNCH("reduce_heads", k_reduce_heads, dim3((u32)w.max_tiles), dim3(BLOCK), 0, st, keys,
              seg_off, w.tile_start, w.tile_seg, n_seg, w.heads, w.flags);
-  KPA_LAUNCH("reduce_scan", k_reduce_scan, dim3(1), dim3(1024), 0, st, w.heads, w.flags,
-             w.tile_start, n_seg, w.gbase, o.gseg_off, o.cnt, o.sum, o.max);
+  const u32 nb = (u32)ceil_div(w.max_tiles, SCAN_TILES);
+  KPA_LAUNCH("reduce_scan", k_reduce_bsum, dim3(nb), dim3(SCAN_TILES), 0, st, w.heads,
+             w.tile_start, n_seg, w.bsum);
+  KPA_LAUNCH("reduce_scan", k_reduce_btop, dim3(1), dim3(1024), 0, st, w.bsum, nb, n_seg,
+             o.gseg_off);
+  KPA_LAUNCH("reduce_scan", k_reduce_bapply, dim3(nb), dim3(SCAN_TILES), 0, st, w.heads, w.flags,
+             w.tile_start, w.tile_seg, n_seg, w.bsum, w.gbase, o.gseg_off, o.cnt, o.sum, o.max);
   KPA_LAUNCH("reduce_main", k_reduce_main, dim3((u32)w.max_tiles), dim3(BLOCK), 0, st, keys, rids,
              seg_off, w.tile_start, w.tile_seg, n_seg, vs, w.gbase, o.gkey, o.cnt, o.sum, o.max,
              o.gstart);

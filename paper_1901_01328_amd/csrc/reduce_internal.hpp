@@ -25,6 +25,7 @@ struct ReduceWs {
   u32* heads;   // runs starting in each tile
   u32* flags;   // bit 0: the tile's last run continues into the next tile
   u64* gbase;   // groups started before each tile
+  u64* bsum;    // scan blocks: group counts, then their exclusive prefix
   u64 max_tiles;
 };
 
