@@ -135,7 +135,8 @@ kpa_status kpa_partition_windows(const void* rows, uint64_t n, const kpa_row_lay
  * bucket is finished in on-chip memory.  The knots are used as the shape of
  * the CDF over the segment's own key range: F(key) interpolates the knots at
  * n_seg*(key - min)/(max - min), with min/max the smallest and largest key of
- * the segment (counted in a first pass over the keys), so that a model fitted
+ * a sample of the segment (the first 256 keys of every 4096-entry tile; keys
+ * outside [min, max] go to the first or last bucket), so that a model fitted
  * on an earlier window still applies when the keys have moved by an offset;
  * the model's kmin/kmax record the range it was fitted on.  Buckets too large for that, or whose
  * order the model would break, are re-sorted by the radix path.  The model

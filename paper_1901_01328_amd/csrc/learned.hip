@@ -54,12 +54,15 @@ __device__ __forceinline__ void stat_add(kpa_sort_stats* st, int idx, u64 v) {
   if (st && v) atomicAdd(reinterpret_cast<unsigned long long*>(st) + idx, (unsigned long long)v);
 }
 
-// One workgroup per segment (grid-stride): validate the model, choose the
-// bucket count.
-// Smallest and largest key of every segment.  Each workgroup takes a
-// contiguous run of tiles, loads a tile with ITEMS independent loads per
-// thread, keeps the running extremes of the current segment and publishes
-// them (one atomic pair) when the segment changes and at the end.
+// Key range of every segment, estimated from a sample: the first BLOCK keys
+// of each of its TILE-entry tiles (one key in 16).  Only the model's
+// resolution depends on it: keys outside the estimate get F = 0 or 1 and land
+// in the first or last bucket, where they belong.  Each workgroup takes a
+// contiguous run of tiles and keeps SAMPLE_TILES tiles' loads in flight per
+// thread; it publishes a segment's extremes (one atomic pair) when the
+// segment changes and at the end.
+constexpr int SAMPLE_TILES = 16;
+
 __global__ void __launch_bounds__(BLOCK) k_seg_minmax(const u64* __restrict__ keys, SegList sl,
                                                       const u32* __restrict__ tile_start,
                                                       const u32* __restrict__ tile_seg,
@@ -98,23 +101,31 @@ __global__ void __launch_bounds__(BLOCK) k_seg_minmax(const u64* __restrict__ ke
     lo = ~0ull;
     hi = 0;
   };
-  for (u32 t = t0; t < t1; ++t) {
-    const u32 s = tile_seg[t];
-    if (s != cur) {
-      if (cur != NONE) publish();
-      cur = s;
-    }
-    const u64 base = sl.lo[s] + (u64)(t - tile_start[s]) * TILE;
-    const u64 end = min(sl.hi[s], base + TILE);
-    u64 k[ITEMS];
+  for (u32 tg = t0; tg < t1; tg += SAMPLE_TILES) {
+    u32 sg[SAMPLE_TILES];
+    u64 k[SAMPLE_TILES];
+    bool v[SAMPLE_TILES];
 #pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-      const u64 i = base + (u64)j * BLOCK + threadIdx.x;
-      k[j] = i < end ? keys[i] : 0ull;
+    for (int j = 0; j < SAMPLE_TILES; ++j) {
+      const u32 t = tg + j;
+      sg[j] = t < t1 ? tile_seg[t] : NONE;
+      v[j] = false;
+      k[j] = 0;
+      if (t < t1) {
+        const u32 s = sg[j];
+        const u64 i = sl.lo[s] + (u64)(t - tile_start[s]) * TILE + threadIdx.x;
+        v[j] = i < sl.hi[s];
+        if (v[j]) k[j] = keys[i];
+      }
     }
 #pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-      if (base + (u64)j * BLOCK + threadIdx.x < end) {
+    for (int j = 0; j < SAMPLE_TILES; ++j) {
+      if (sg[j] == NONE) break;
+      if (sg[j] != cur) {
+        if (cur != NONE) publish();
+        cur = sg[j];
+      }
+      if (v[j]) {
         lo = k[j] < lo ? k[j] : lo;
         hi = k[j] > hi ? k[j] : hi;
       }
@@ -192,6 +203,7 @@ struct FinishSmemT {
   u32 lstart[RADIX];
   u32 scan[NW + 1];
   u32 red[NW];
+  u32 red_inv[NW];
   u64 red64[2 * NW];
   float knots[KPA_PWL_MAX_SEG + 1];
   u64 skeys[FCAP + 1];
@@ -334,29 +346,46 @@ template <int IT>
 __device__ u32 lds_sort_model(FinishSmem& sm, const SegModel& m, u32 mcount) {
   const u32 tid = threadIdx.x;
   const u32 w = tid >> 6;
-  __syncthreads();
   u64 vor = 0, vand = ~0ull;
-  u32 rmax = 0;  // largest relative refined id
+  u32 rmax = 0;  // largest refined id relative to the chunk's first bucket
   bool inv = false;  // some entry's key is below its predecessor's
-  // sm.srel holds each entry's refined bucket id; make it relative to the
-  // chunk's first bucket
+  // sm.srel holds each entry's refined bucket id (the first rank pass makes
+  // it relative to the chunk's first bucket)
   const u32 base = (sm.srel[0] >> 8) << 8;
-  if (tid == 0) sm.flag = 0;
-  __syncthreads();
   for (u32 i = tid; i < mcount; i += FIN_THREADS) {
     const u64 k = sm.skeys[i];
     vor |= k;
     vand &= k;
     const u32 r = sm.srel[i] - base;
-    sm.srel[i] = r;
     rmax = r > rmax ? r : rmax;
     inv = inv || (i > 0 && k < sm.skeys[i - 1]);
   }
-  if (inv) sm.flag = 1;  // read after the barriers of the reductions below
-  block_or_and<FIN_WAVES>(vor, vand, sm.red64);
+  // one block reduction of all four (a single barrier)
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    vor |= __shfl_xor(vor, o, 64);
+    vand &= __shfl_xor(vand, o, 64);
+    const u32 r2 = __shfl_xor(rmax, o, 64);
+    rmax = r2 > rmax ? r2 : rmax;
+  }
+  const bool winv = ballot(inv) != 0;
+  if (__lane_id() == 0) {
+    sm.red64[w] = vor;
+    sm.red64[FIN_WAVES + w] = vand;
+    sm.red[w] = rmax;
+    sm.red_inv[w] = winv ? 1u : 0u;
+  }
+  __syncthreads();
+  inv = false;
+#pragma unroll
+  for (int q = 0; q < FIN_WAVES; ++q) {
+    vor |= sm.red64[q];
+    vand &= sm.red64[FIN_WAVES + q];
+    rmax = sm.red[q] > rmax ? sm.red[q] : rmax;
+    inv = inv || sm.red_inv[q] != 0;
+  }
   if (vor == vand) return CH_EQUAL;
-  rmax = ~block_min_u32<FIN_WAVES>(~rmax, sm.red);
-  if (!sm.flag) return CH_INORDER;
+  if (!inv) return CH_INORDER;
   if (!m.valid || rmax >= (1u << 16)) {
     lds_sort(sm, mcount);
     return CH_MOVED;
@@ -376,12 +405,11 @@ __device__ u32 lds_sort_model(FinishSmem& sm, const SegModel& m, u32 mcount) {
       const bool v = (valid >> j) & 1;
       kk[j] = v ? sm.skeys[o] : 0ull;
       rr[j] = v ? sm.srids[o] : 0u;
-      re[j] = v ? sm.srel[o] : 0u;
+      re[j] = v ? sm.srel[o] - (p == 0 ? base : 0u) : 0u;
       d[j] = (re[j] >> (8 * p)) & 255u;
     }
-    __syncthreads();
+    // items read before rank_tile's first barrier, overwritten after its last
     rank_tile(sm.whist, sm.lstart, sm.scan, d, valid, rank, &tc);
-    __syncthreads();
 #pragma unroll
     for (int j = 0; j < IT; ++j)
       if ((valid >> j) & 1) {
@@ -569,13 +597,17 @@ __global__ void __launch_bounds__(FIN_THREADS, 4) k_learned_finish(
   const u64 pos0 = a + (u64)k * FH;
   if (pos0 >= b) return;
   const SegModel m = segm[seg];
-  const lds_float* kn = bind_knots(m, sm.knots);
-  __syncthreads();
   const u32 span = (u32)min<u64>(FH, b - pos0);
   // bucket ids never decrease along the segment: no bucket starts in the
-  // stretch when the entry before it and its last entry share a bucket
-  if (k > 0 && model_bucket(m, kn, keys[pos0 - 1]) == model_bucket(m, kn, keys[pos0 - 1 + span]))
-    return;
+  // stretch when the entry before it and its last entry share a bucket (two
+  // evaluations with the knots read from global memory, before they are
+  // copied to LDS)
+  if (k > 0) {
+    const global_float* gk = (const global_float*)m.knots;
+    if (model_bucket(m, gk, keys[pos0 - 1]) == model_bucket(m, gk, keys[pos0 - 1 + span])) return;
+  }
+  const lds_float* kn = bind_knots(m, sm.knots);
+  __syncthreads();
 
   // --- window from L0: the entry before the stretch (k > 0) or pos0 = a ---
   const u64 L0 = k > 0 ? pos0 - 1 : pos0;

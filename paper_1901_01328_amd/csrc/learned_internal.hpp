@@ -12,7 +12,7 @@ constexpr u32 MAX_BUCKET_BITS = 16;
 
 // Per-segment model state prepared on the device from a kpa_pwl_model.
 struct SegModel {
-  u64 kmin, kmax;      // the segment's own smallest and largest key
+  u64 kmin, kmax;      // the segment's own key range (from a sample of its keys)
   float scale;         // nseg / hspan, 0 when hspan == 0
   u32 nseg;            // PWL segments
   u32 bits;            // log2 of the bucket count (0: one bucket)
@@ -82,7 +82,7 @@ struct LearnedWs {
   u64* keys_tmp;   // scatter ping-pong buffer; later the fallback's input
   u32* rids_tmp;
   SegModel* segm;  // n_seg
-  u64* cur_min;    // n_seg: smallest and largest key of each segment
+  u64* cur_min;    // n_seg: smallest and largest sampled key of each segment
   u64* cur_max;
   u32* ltile_start;  // tile map of the scatter passes (n_seg + 1)
   u32* ftile_start;  // tile map of the finishing pass (n_seg + 1)

@@ -113,9 +113,9 @@ __device__ bool lds_sort(SM& sm, u32 m) {
       rr[j] = ((valid >> j) & 1) ? sm.srids[o] : 0u;
       d[j] = (u32)(kk[j] >> (8 * p)) & 255u;
     }
-    __syncthreads();
+    // every thread has read its items before rank_tile's first barrier; the
+    // scatter below may overwrite them after its last one
     rank_tile(sm.whist, sm.lstart, sm.scan, d, valid, rank, &tc);
-    __syncthreads();
 #pragma unroll
     for (int j = 0; j < IT; ++j)
       if ((valid >> j) & 1) {

@@ -102,11 +102,22 @@ __device__ __forceinline__ u32 rank_count(u32 (&whist)[NW][RADIX], const u32 (&d
 }
 
 // Second half: lstart[d] = entries of the tile with a smaller digit;
-// *tile_count = present entries.  Ends with a barrier.
+// *tile_count = present entries.  The 256 digit counts sit in the first four
+// waves: each scans its 64 in registers, then adds the totals of the waves
+// before it (two barriers in all; ends with one).
 template <int NW>
 __device__ __forceinline__ void rank_starts(u32 total, u32* lstart, u32* scan, u32* tile_count) {
-  const u32 ex = block_excl_sum<NW>(threadIdx.x < RADIX ? total : 0u, scan, tile_count);
-  if (threadIdx.x < RADIX) lstart[threadIdx.x] = ex;
+  static_assert(NW * 64 >= RADIX && RADIX == 256, "digit counts span four waves");
+  const u32 tid = threadIdx.x, w = tid >> 6;
+  u32 incl = 0;
+  if (tid < RADIX) {  // whole waves
+    incl = wave_incl_sum(total);
+    if (__lane_id() == 63) scan[w] = incl;
+  }
+  __syncthreads();
+  const u32 s0 = scan[0], s1 = scan[1], s2 = scan[2], s3 = scan[3];
+  if (tid < RADIX) lstart[tid] = (w > 0 ? s0 : 0u) + (w > 1 ? s1 : 0u) + (w > 2 ? s2 : 0u) + incl - total;
+  *tile_count = s0 + s1 + s2 + s3;
   __syncthreads();
 }
 
