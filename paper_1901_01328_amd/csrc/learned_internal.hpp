@@ -49,7 +49,11 @@ __device__ __forceinline__ const lds_float* bind_knots(const SegModel& m, float*
 template <class KP>
 __device__ __forceinline__ float pwl_eval(const SegModel& m, const KP* kn, u64 key) {
   const u64 d = key > m.kmin ? (key - m.kmin) >> m.sh : 0ull;
-  const float hf = (float)(d < (u64)m.hspan ? (u32)d : m.hspan);
+  // the capped offset fits 32 bits: clamp on the two halves and convert from
+  // u32 (the same value, so the same float, as converting the u64)
+  const u32 dlo = (u32)d;
+  const u32 h = (u32)(d >> 32) != 0u ? m.hspan : (dlo < m.hspan ? dlo : m.hspan);
+  const float hf = __uint2float_rn(h);
   const float x = hf * m.scale;
   u32 j = (u32)x;
   j = j < m.nseg - 1 ? j : m.nseg - 1;
@@ -58,9 +62,11 @@ __device__ __forceinline__ float pwl_eval(const SegModel& m, const KP* kn, u64 k
   return __builtin_amdgcn_fmed3f(fmaf(f, b - a, a), a, b);
 }
 
+// With bits == 0 the cap is 0, so every key is in bucket 0 without a branch
+// (a branch per key would keep the compiler from overlapping the knot reads
+// of a thread's keys).
 template <class KP>
 __device__ __forceinline__ u32 model_bucket(const SegModel& m, const KP* kn, u64 key) {
-  if (m.bits == 0) return 0u;
   const float B = (float)(1u << m.bits);
   const u32 b = (u32)(pwl_eval(m, kn, key) * B);
   const u32 top = (1u << m.bits) - 1;
