@@ -666,14 +666,26 @@ __global__ void __launch_bounds__(FIN_THREADS, 4) k_learned_finish(
 
   if (endo == NONE) {
     // Oversize: no bucket starts among the FCAP+1 entries from the chunk's
-    // start after pos0 + FH; the bucket of the last of them runs on.
-    if (tid == 0) {
-      const u32 beta = sm.srel[want - 1] >> 8;
-      u64 lo = start + want - 1, hi = b;  // first p in (lo, hi] with p == b or bucket > beta
-      while (hi - lo > 1) {
-        const u64 mid = lo + (hi - lo) / 2;
-        if (model_bucket(m, kn, keys[mid]) > beta) hi = mid; else lo = mid;
+    // start after pos0 + FH; the bucket of the last of them runs on.  Its end
+    // is found by a FIN_THREADS-way search: every round each thread probes
+    // one position of (lo, hi) and the first probe past the bucket narrows
+    // the range (three rounds cover a 4M-entry segment).
+    const u32 beta = sm.srel[want - 1] >> 8;
+    u64 lo = start + want - 1, hi = b;  // first p in (lo, hi] with p == b or bucket > beta
+    while (hi - lo > 1) {
+      const u64 span = hi - lo;
+      auto probe = [&](u32 t) { return lo + 1 + ((span - 2) * t) / (FIN_THREADS - 1); };
+      const u64 q = probe(tid);  // in [lo + 1, hi - 1], nondecreasing in tid
+      const bool past = model_bucket(m, kn, keys[q]) > beta;
+      const u32 first = block_min_u32<FIN_WAVES>(past ? tid : NONE, sm.red);
+      if (first == NONE) {
+        lo = probe(FIN_THREADS - 1);
+      } else {
+        hi = probe(first);
+        if (first > 0) lo = probe(first - 1);
       }
+    }
+    if (tid == 0) {
       const u32 idx = atomicAdd(fb_count, 1u);
       if (idx < max_fb) {
         fb_lo[idx] = start;
