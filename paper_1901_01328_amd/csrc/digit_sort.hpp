@@ -455,6 +455,7 @@ __global__ void __launch_bounds__(PASS_THREADS, PASS_WAVES / 2)
   u64 kk[PASS_ITEMS];
   u32 rr[PASS_ITEMS];
   u32 valid = load(td, kk, rr);
+  typename DF::Staged stg = DF::fetch(prm, td.seg);  // the digit function of the next segment
   u32 bound = 0xFFFFFFFFu;  // segment whose digit function is in dfsm
   DF df;
   while (true) {
@@ -466,8 +467,8 @@ __global__ void __launch_bounds__(PASS_THREADS, PASS_WAVES / 2)
         tid < RADIX ? seg_start + bf.hist[((u64)td.seg * DF::PASSES + pass) * RADIX + tid] : 0ull;
     if (td.seg != bound) {
       // the previous tile's digits were computed before its barriers
-      df = DF(prm, td.seg);
-      df.bind(dfsm);
+      df = DF(stg);
+      df.bind_staged(stg, dfsm);
       if (DF::SMEM > 1) __syncthreads();
       bound = td.seg;
     }
@@ -480,6 +481,7 @@ __global__ void __launch_bounds__(PASS_THREADS, PASS_WAVES / 2)
     TileDesc nt;
     const bool more = claim(nt);
     const u32 nvalid = more ? load(nt, kk, rr) : 0u;
+    if (more && nt.seg != td.seg) stg = DF::fetch(prm, nt.seg);  // in flight during the write
     onesweep_lookback_write(sm, status_cur, td.g, td.t_in, cnt_d, tile_count, my_base, dst_k,
                             dst_r);
     if (!more) return;

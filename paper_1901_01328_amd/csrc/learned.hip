@@ -30,11 +30,42 @@ struct LearnedDF {
   static constexpr int SMEM = KPA_PWL_MAX_SEG + 1;  // floats of LDS for the knots
   struct Params {
     const SegModel* segm;
+    const kpa_pwl_model* models;  // segment s's knots: models[s].knots
+  };
+  // A segment's model and knots held in registers by a scatter workgroup: the
+  // loads are issued while the previous tile is written, and the knots go to
+  // LDS when the segment's tile starts.  Every knot of the array is read, so
+  // no load waits for the model.
+  static constexpr int KNOT_REGS = (KPA_PWL_MAX_SEG + 1 + PASS_THREADS - 1) / PASS_THREADS;
+  struct Staged {
+    SegModel m;
+    float k[KNOT_REGS];
   };
   SegModel m;
   const lds_float* kn;
   LearnedDF() = default;
   __device__ __forceinline__ LearnedDF(const Params& p, u32 seg) : m(p.segm[seg]) {}
+  __device__ __forceinline__ explicit LearnedDF(const Staged& s) : m(s.m) {}
+  static __device__ __forceinline__ Staged fetch(const Params& p, u32 seg) {
+    Staged s;
+    s.m = p.segm[seg];
+    const float* g = p.models[seg].knots;
+#pragma unroll
+    for (int i = 0; i < KNOT_REGS; ++i) {
+      const u32 j = threadIdx.x + (u32)i * PASS_THREADS;
+      s.k[i] = j <= (u32)KPA_PWL_MAX_SEG ? g[j] : 0.0f;
+    }
+    return s;
+  }
+  // All threads of a scatter workgroup; the caller synchronizes.
+  __device__ __forceinline__ void bind_staged(const Staged& s, float* lds) {
+#pragma unroll
+    for (int i = 0; i < KNOT_REGS; ++i) {
+      const u32 j = threadIdx.x + (u32)i * PASS_THREADS;
+      if (j <= (u32)KPA_PWL_MAX_SEG) lds[j] = s.k[i];
+    }
+    kn = (const lds_float*)lds;
+  }
   // All threads: copy the knots to LDS and evaluate from there (the caller
   // synchronizes before the first use).
   __device__ __forceinline__ void bind(float* sm) { kn = bind_knots(m, sm); }
@@ -1104,7 +1135,7 @@ kpa_status learned_sort_launch(const u64* keys_in, const u32* rids_in, u64* keys
   DigitSortBufs b{keys_in,     rids_in,      keys_out,   rids_out,       lw.keys_tmp,
                   lw.rids_tmp, lw.hist,      lw.seg_mask, lw.ltile_start, lw.status0,
                   lw.status1,  lw.counters,  lw.max_tiles, lw.order};
-  KPA_CHECK(digit_sort_launch<LearnedDF>(sl, LearnedDF::Params{lw.segm}, b, st));
+  KPA_CHECK(digit_sort_launch<LearnedDF>(sl, LearnedDF::Params{lw.segm, models}, b, st));
 
   KPA_CHECK(launch_seg_tiles_list(sl, FH, lw.ftile_start, st));
   KPA_CHECK(launch_tile_seg(lw.ftile_start, n_seg, sl.n_dev, lw.max_ftiles, lw.ftile_seg, st));

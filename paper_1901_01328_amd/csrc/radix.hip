@@ -24,8 +24,12 @@ struct RadixDF {
   static constexpr int SMEM = 1;
   __device__ __forceinline__ void bind(float*) {}
   struct Params {};
+  struct Staged {};
   RadixDF() = default;
   __device__ __forceinline__ RadixDF(const Params&, u32) {}
+  __device__ __forceinline__ explicit RadixDF(const Staged&) {}
+  static __device__ __forceinline__ Staged fetch(const Params&, u32) { return Staged{}; }
+  __device__ __forceinline__ void bind_staged(const Staged&, float*) {}
   __device__ __forceinline__ u32 digit(u64 k, u32 pass) const {
     return (u32)(k >> (8 * pass)) & 255u;
   }
