@@ -30,7 +30,8 @@ if ROOT not in sys.path:
 
 METRIC = "Mrec/s KPA group-by (learned vs radix sort), % HBM peak, p99 latency"
 HBM_PEAK_GBS = 8000.0
-# Algorithmic bytes per entry and launch of each pass.
+# Algorithmic bytes per entry and launch of each pass: the bytes the pass must
+# read and write for one entry, whatever the caches do.
 PASS_BYTES = {
     "radix_pass": 24,      # read key+rid, write key+rid
     "radix_hist": 8,       # read key
@@ -89,8 +90,9 @@ def parse():
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported "
-              "(the sharded design is described in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported (windows and "
+              "substreams would be sharded over GPUs, one huge window by key range; that is "
+              "not built)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

@@ -52,7 +52,7 @@ enum {
   KPA_EWORKSPACE = -2,   /* workspace too small; *needed bytes written where asked */
   KPA_ECAPACITY = -3,    /* an output exceeds the capacity the caller gave */
   KPA_EBUDGET = -4,      /* serving admission: memory budget exhausted */
-  KPA_EUNSUPPORTED = -5, /* size or parameter beyond what this build handles */
+  KPA_EUNSUPPORTED = -5, /* size or parameter beyond what the library supports */
   KPA_EHIP = -6          /* a HIP runtime call failed; see kpa_last_error_string() */
 };
 
