@@ -42,6 +42,31 @@ PASS_BYTES = {
 }
 
 
+COPY_GBS = None  # device copy rate on this GPU (read + write bytes per second), set in main
+
+
+def measure_copy_rate(dev, mib=1024, reps=5):
+    """Read+write GB/s of a plain device-to-device copy of `mib` MiB (torch
+    copy_), event-timed: the practical ceiling of a pass that reads and
+    writes the same bytes, reported beside the roofline's spec peak."""
+    import torch
+    src = torch.empty(mib << 20, dtype=torch.uint8, device=dev).fill_(1)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return round(2 * (mib << 20) / (ms / 1000) / 1e9, 1)
+
+
 def counted_traffic(kernel_row):
     """HBM bytes per dispatch of a kernel from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the scatter
@@ -105,6 +130,9 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    global COPY_GBS
+    if not a.probe_copy_mib:  # counter runs calibrate on their own first copy
+        COPY_GBS = measure_copy_rate(dev)
     if a.probe_copy_mib:
         src = torch.empty(a.probe_copy_mib << 20, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
@@ -188,6 +216,7 @@ def main():
         traffic = counted_traffic("k_ds_pass<RadixDF>") if dom == "radix_pass" and \
             n == 1 << 28 else None
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "copy_gbs": COPY_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": dom, "avg_ms": avg_ms, "bytes_per_launch": int(bytes_per_launch)}
 
@@ -383,6 +412,7 @@ def bench_c4(a):
             per_launch = 24 * act / pl["launches_per_step"]
         achieved = per_launch / (pl["avg_ms"] / 1000.0) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "copy_gbs": COPY_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "kernel": dom, "avg_ms": pl["avg_ms"], "bytes_per_launch": int(per_launch)}
     out = {
@@ -486,6 +516,7 @@ def bench_c3(a):
         per_launch = 24 * 2 * n * 8 / pl["launches_per_step"]   # all 8 digits vary
         achieved = per_launch / (pl["avg_ms"] / 1000.0) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "copy_gbs": COPY_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "kernel": "radix_pass", "avg_ms": pl["avg_ms"], "bytes_per_launch": int(per_launch)}
     out = {
