@@ -2,7 +2,7 @@
 //
 // A monotone model F (kpa_pwl_model: piecewise-linear CDF fitted on the sorted
 // KPA of an earlier window) maps each key to a bucket b = floor(B*F(key)),
-// B = 2^bits chosen per segment so that buckets hold about 1024 entries.
+// B = 2^bits chosen per segment so that buckets hold about 512 entries.
 // Because F never decreases, every key of bucket b precedes every key of
 // bucket b+1, so the sort reduces to
 //   1. a stable scatter by bucket id: one or two onesweep passes over the

@@ -7,7 +7,7 @@ namespace kpa {
 
 constexpr u32 FCAP = TILE;        // entries sorted on chip by one workgroup
 constexpr u32 FH = FCAP / 2;      // chunk stride of the finishing pass
-constexpr u32 BUCKET_TARGET = 1024;  // mean bucket size the bucket count aims at
+constexpr u32 BUCKET_TARGET = 512;  // mean bucket size the bucket count aims at
 constexpr u32 MAX_BUCKET_BITS = 16;
 
 // Per-segment model state prepared on the device from a kpa_pwl_model.
