@@ -382,7 +382,7 @@ __device__ u32 lds_sort_model(FinishSmem& sm, const SegModel& m, u32 mcount) {
   bool inv = false;  // some entry's key is below its predecessor's
   // sm.srel holds each entry's refined bucket id (the first rank pass makes
   // it relative to the chunk's first bucket)
-  const u32 base = (sm.srel[0] >> 8) << 8;
+  const u32 base = (sm.srel[0] >> REFINE_BITS) << REFINE_BITS;
   for (u32 i = tid; i < mcount; i += FIN_THREADS) {
     const u64 k = sm.skeys[i];
     vor |= k;
@@ -592,7 +592,7 @@ __device__ __forceinline__ void load_window(FinishSmem& sm, const SegModel& m, c
 __device__ __forceinline__ u32 first_edge(FinishSmem& sm, u32 lo, u32 hi) {
   u32 e = NONE;
   for (u32 o = lo + threadIdx.x; o < hi; o += FIN_THREADS)
-    if ((sm.srel[o] >> 8) != (sm.srel[o - 1] >> 8)) {
+    if ((sm.srel[o] >> REFINE_BITS) != (sm.srel[o - 1] >> REFINE_BITS)) {
       e = o;
       break;
     }
@@ -701,7 +701,7 @@ __global__ void __launch_bounds__(FIN_THREADS, 4) k_learned_finish(
     // is found by a FIN_THREADS-way search: every round each thread probes
     // one position of (lo, hi) and the first probe past the bucket narrows
     // the range (three rounds cover a 4M-entry segment).
-    const u32 beta = sm.srel[want - 1] >> 8;
+    const u32 beta = sm.srel[want - 1] >> REFINE_BITS;
     u64 lo = start + want - 1, hi = b;  // first p in (lo, hi] with p == b or bucket > beta
     while (hi - lo > 1) {
       const u64 span = hi - lo;

@@ -8,6 +8,10 @@ namespace kpa {
 constexpr u32 FCAP = TILE;        // entries sorted on chip by one workgroup
 constexpr u32 FH = FCAP / 2;      // chunk stride of the finishing pass
 constexpr u32 BUCKET_TARGET = 512;  // mean bucket size the bucket count aims at
+#ifndef KPA_REFINE_BITS
+#define KPA_REFINE_BITS 8
+#endif
+constexpr u32 REFINE_BITS = KPA_REFINE_BITS;  // bits of F below the bucket id used by the finish
 constexpr u32 MAX_BUCKET_BITS = 16;
 
 // Per-segment model state prepared on the device from a kpa_pwl_model.
@@ -73,14 +77,14 @@ __device__ __forceinline__ u32 model_bucket(const SegModel& m, const KP* kn, u64
   return b > top ? top : b;
 }
 
-// Bucket id refined by 8 more bits: floor(F * 2^(bits+8)), capped.  Scaling
-// by a power of two is exact, so model_fine(k) >> 8 == model_bucket(k) for
-// every key (bits <= 16, so the product stays below 2^24 and exact).
+// Bucket id refined by REFINE_BITS more bits: floor(F * 2^(bits+REFINE_BITS)),
+// capped.  Scaling by a power of two is exact, so model_fine(k) >> REFINE_BITS
+// == model_bucket(k) for every key.
 template <class KP>
 __device__ __forceinline__ u32 model_fine(const SegModel& m, const KP* kn, u64 key) {
-  const float B = (float)(1u << (m.bits + 8));
+  const float B = (float)(1u << (m.bits + REFINE_BITS));
   const u32 b = (u32)(pwl_eval(m, kn, key) * B);
-  const u32 top = (1u << (m.bits + 8)) - 1;
+  const u32 top = (1u << (m.bits + REFINE_BITS)) - 1;
   return b > top ? top : b;
 }
 
