@@ -69,13 +69,19 @@ struct LearnedDF {
   // All threads: copy the knots to LDS and evaluate from there (the caller
   // synchronizes before the first use).
   __device__ __forceinline__ void bind(float* sm) { kn = bind_knots(m, sm); }
+  // A bucket id of more than 8 bits is split evenly over the two passes (13
+  // bits: 7 + 6 rather than 8 + 5).  Bucket ids are spread evenly by design,
+  // so a pass's digit runs in a tile get longer, and its writes more
+  // contiguous, with fewer digit values.
+  __device__ __forceinline__ u32 lo_bits() const { return m.bits <= 8 ? 8u : (m.bits + 1) / 2; }
   __device__ __forceinline__ u32 digit(u64 k, u32 pass) const {
-    return (model_bucket(m, kn, k) >> (8 * pass)) & 255u;
+    const u32 b = model_bucket(m, kn, k), lb = lo_bits();
+    return pass == 0 ? (b & ((1u << lb) - 1)) : (b >> lb);
   }
   __device__ __forceinline__ void digits(u64 k, u32 (&d)[PASSES]) const {
-    const u32 b = model_bucket(m, kn, k);
-    d[0] = b & 255u;
-    d[1] = (b >> 8) & 255u;
+    const u32 b = model_bucket(m, kn, k), lb = lo_bits();
+    d[0] = b & ((1u << lb) - 1);
+    d[1] = b >> lb;
   }
 };
 
