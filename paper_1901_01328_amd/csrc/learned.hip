@@ -605,29 +605,65 @@ __device__ __forceinline__ u32 first_edge(FinishSmem& sm, u32 lo, u32 hi) {
   return block_min_u32<FIN_WAVES>(e, sm.red);
 }
 
-// Finishing pass: one workgroup per 2048-entry stretch [pos0, pos0+FH) of a
-// segment.  It owns the buckets whose first entry lies in its stretch: the
+// Finishing pass over the 2048-entry stretches [pos0, pos0+FH) of every
+// segment.  A stretch owns the buckets whose first entry lies in it: the
 // chunk [start, end) from its first bucket start to the first bucket start at
 // or after pos0+FH (or the segment end).  Chunks of at most FCAP entries are
 // sorted on chip; larger ones are listed for the pivot rounds.
 //
-// The workgroup reads keys from the entry before its stretch on, first
-// FIN_FIRST of them and, when the chunk's end is not among them, up to FCAP+1
-// from the chunk's start; row ids only of the chunk.  Other workgroups
-// rewrite neighbouring chunks meanwhile; a chunk's sort only permutes entries
-// inside the chunk's buckets, so the bucket of every position never changes
-// and the edges found do not depend on timing.
-__global__ void __launch_bounds__(FIN_THREADS, 4) k_learned_finish(
-    u64* __restrict__ keys, u32* __restrict__ rids, SegList sl,
-    const u32* __restrict__ ftile_start, const u32* __restrict__ ftile_seg,
-    const SegModel* __restrict__ segm,
-    u64* __restrict__ fb_lo, u64* __restrict__ fb_hi, u32* __restrict__ fb_count, u32 max_fb,
-    kpa_sort_stats* stats) {
-  __shared__ FinishSmem sm;
-  const u32 tid = threadIdx.x;
-  const u32 tile = blockIdx.x;
+// Step 1 (k_fin_active, one thread per stretch): bucket ids never decrease
+// along a segment, so a stretch other than a segment's first holds a bucket
+// start exactly when the entry before it and its last entry lie in different
+// buckets.  Those stretches are listed (about half of them on skewed keys);
+// the rest need no work.
+__global__ void __launch_bounds__(BLOCK) k_fin_active(const u64* __restrict__ keys, SegList sl,
+                                                      const u32* __restrict__ ftile_start,
+                                                      const u32* __restrict__ ftile_seg,
+                                                      const SegModel* __restrict__ segm,
+                                                      u32 max_ftiles, u32* __restrict__ active,
+                                                      u32* __restrict__ n_active) {
   const u32 n_seg = sl.n();
-  if (tile >= ftile_start[n_seg]) return;
+  const u32 total = min(ftile_start[n_seg], max_ftiles);
+  for (u32 t0 = blockIdx.x * BLOCK; t0 < total; t0 += gridDim.x * BLOCK) {
+    const u32 tile = t0 + threadIdx.x;
+    bool act = false;
+    if (tile < total) {
+      const u32 seg = ftile_seg[tile];
+      const u32 k = tile - ftile_start[seg];
+      const u64 a = sl.lo[seg], b = sl.hi[seg];
+      const u64 pos0 = a + (u64)k * FH;
+      if (pos0 < b) {
+        if (k == 0) {
+          act = true;
+        } else {
+          const SegModel m = segm[seg];
+          const u32 span = (u32)min<u64>(FH, b - pos0);
+          const global_float* gk = (const global_float*)m.knots;
+          act = model_bucket(m, gk, keys[pos0 - 1]) != model_bucket(m, gk, keys[pos0 - 1 + span]);
+        }
+      }
+    }
+    const u64 bal = ballot(act);
+    u32 wbase = 0;
+    if (__lane_id() == 0 && bal) wbase = atomicAdd(n_active, (u32)__popcll(bal));
+    wbase = __shfl(wbase, 0, 64);
+    if (act) active[wbase + (u32)__popcll(bal & lanemask_lt())] = tile;
+  }
+}
+
+// Step 2: one listed stretch's chunk.  The workgroup reads keys from the
+// entry before the stretch on, first FIN_FIRST of them and, when the chunk's
+// end is not among them, up to FCAP+1 from the chunk's start; row ids only of
+// the chunk.  Other workgroups rewrite neighbouring chunks meanwhile; a
+// chunk's sort only permutes entries inside the chunk's buckets, so the
+// bucket of every position never changes and the edges found do not depend on
+// timing.  Every return is uniform over the workgroup.
+__device__ __forceinline__ void finish_stretch(
+    FinishSmem& sm, u64* __restrict__ keys, u32* __restrict__ rids, const SegList& sl,
+    const u32* __restrict__ ftile_start, const u32* __restrict__ ftile_seg,
+    const SegModel* __restrict__ segm, u64* __restrict__ fb_lo, u64* __restrict__ fb_hi,
+    u32* __restrict__ fb_count, u32 max_fb, kpa_sort_stats* stats, u32 tile) {
+  const u32 tid = threadIdx.x;
   const u32 seg = ftile_seg[tile];
   const u32 k = tile - ftile_start[seg];
   const u64 a = sl.lo[seg], b = sl.hi[seg];
@@ -635,14 +671,6 @@ __global__ void __launch_bounds__(FIN_THREADS, 4) k_learned_finish(
   if (pos0 >= b) return;
   const SegModel m = segm[seg];
   const u32 span = (u32)min<u64>(FH, b - pos0);
-  // bucket ids never decrease along the segment: no bucket starts in the
-  // stretch when the entry before it and its last entry share a bucket (two
-  // evaluations with the knots read from global memory, before they are
-  // copied to LDS)
-  if (k > 0) {
-    const global_float* gk = (const global_float*)m.knots;
-    if (model_bucket(m, gk, keys[pos0 - 1]) == model_bucket(m, gk, keys[pos0 - 1 + span])) return;
-  }
   const lds_float* kn = bind_knots(m, sm.knots);
   __syncthreads();
 
@@ -752,6 +780,21 @@ __global__ void __launch_bounds__(FIN_THREADS, 4) k_learned_finish(
     keys[start + i] = sm.skeys[i];
     rids[start + i] = sm.srids[i];
   }
+}
+
+// One workgroup per listed stretch (the grid covers every stretch; the
+// workgroups past the list's end return at once).  A persistent loop over the
+// list needs more registers than the body alone and measured slower.
+__global__ void __launch_bounds__(FIN_THREADS, 4) k_learned_finish(
+    u64* __restrict__ keys, u32* __restrict__ rids, SegList sl,
+    const u32* __restrict__ ftile_start, const u32* __restrict__ ftile_seg,
+    const SegModel* __restrict__ segm, const u32* __restrict__ active,
+    const u32* __restrict__ n_active, u64* __restrict__ fb_lo, u64* __restrict__ fb_hi,
+    u32* __restrict__ fb_count, u32 max_fb, kpa_sort_stats* stats) {
+  __shared__ FinishSmem sm;
+  if (blockIdx.x >= *n_active) return;
+  finish_stretch(sm, keys, rids, sl, ftile_start, ftile_seg, segm, fb_lo, fb_hi, fb_count,
+                 max_fb, stats, active[blockIdx.x]);
 }
 
 // Sorts listed ranges of at most FCAP entries in place, one workgroup each.
@@ -1092,6 +1135,8 @@ kpa_status learned_sort_plan(u64 n_cap, u32 n_seg, Carver& c, LearnedWs* w) {
   w->ftile_start = c.take<u32>((u64)n_seg + 1);
   w->ltile_seg = c.take<u32>(w->max_tiles);
   w->ftile_seg = c.take<u32>(w->max_ftiles);
+  w->factive = c.take<u32>(w->max_ftiles);
+  w->fn_active = c.take<u32>(1);
   w->hist = c.take<u32>((u64)n_seg * 2 * RADIX);
   w->seg_mask = c.take<u32>(n_seg);
   w->status0 = c.take<u32>(w->max_tiles * RADIX);
@@ -1145,9 +1190,14 @@ kpa_status learned_sort_launch(const u64* keys_in, const u32* rids_in, u64* keys
 
   KPA_CHECK(launch_seg_tiles_list(sl, FH, lw.ftile_start, st));
   KPA_CHECK(launch_tile_seg(lw.ftile_start, n_seg, sl.n_dev, lw.max_ftiles, lw.ftile_seg, st));
-  KPA_LAUNCH("learned_finish", k_learned_finish, dim3((u32)lw.max_ftiles), dim3(FIN_THREADS), 0, st,
-             keys_out, rids_out, sl, lw.ftile_start, lw.ftile_seg, lw.segm, lw.fb_lo, lw.fb_hi,
-             lw.fb_count, lw.max_fb, stats);
+  KPA_CHECK(launch_fill_u32(lw.fn_active, 1, 0, st));
+  KPA_LAUNCH("learned_finish", k_fin_active,
+             dim3((u32)std::min<u64>(ceil_div(lw.max_ftiles, BLOCK), 4096)), dim3(BLOCK), 0, st,
+             keys_out, sl, lw.ftile_start, lw.ftile_seg, lw.segm, (u32)lw.max_ftiles, lw.factive,
+             lw.fn_active);
+  KPA_LAUNCH("learned_finish", k_learned_finish, dim3((u32)lw.max_ftiles), dim3(FIN_THREADS), 0,
+             st, keys_out, rids_out, sl, lw.ftile_start, lw.ftile_seg, lw.segm, lw.factive,
+             lw.fn_active, lw.fb_lo, lw.fb_hi, lw.fb_count, lw.max_fb, stats);
 
   // Pivot rounds over the oversize chunks: round 0 reads the finishing pass's
   // list, round 1 the parts round 0 left over; small parts collect in one list.
