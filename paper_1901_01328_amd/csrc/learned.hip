@@ -615,21 +615,24 @@ __device__ __forceinline__ u32 first_edge(FinishSmem& sm, u32 lo, u32 hi) {
 // along a segment, so a stretch other than a segment's first holds a bucket
 // start exactly when the entry before it and its last entry lie in different
 // buckets.  Those stretches are listed (about half of them on skewed keys);
-// the rest need no work.
+// the rest need no work.  A listed stretch is (segment << 32 | index in the
+// segment), so that its workgroup needs no lookup before the segment's data.
 __global__ void __launch_bounds__(BLOCK) k_fin_active(const u64* __restrict__ keys, SegList sl,
                                                       const u32* __restrict__ ftile_start,
                                                       const u32* __restrict__ ftile_seg,
                                                       const SegModel* __restrict__ segm,
-                                                      u32 max_ftiles, u32* __restrict__ active,
+                                                      u32 max_ftiles, u64* __restrict__ active,
                                                       u32* __restrict__ n_active) {
   const u32 n_seg = sl.n();
   const u32 total = min(ftile_start[n_seg], max_ftiles);
   for (u32 t0 = blockIdx.x * BLOCK; t0 < total; t0 += gridDim.x * BLOCK) {
     const u32 tile = t0 + threadIdx.x;
     bool act = false;
+    u64 item = 0;
     if (tile < total) {
       const u32 seg = ftile_seg[tile];
       const u32 k = tile - ftile_start[seg];
+      item = ((u64)seg << 32) | k;
       const u64 a = sl.lo[seg], b = sl.hi[seg];
       const u64 pos0 = a + (u64)k * FH;
       if (pos0 < b) {
@@ -647,7 +650,7 @@ __global__ void __launch_bounds__(BLOCK) k_fin_active(const u64* __restrict__ ke
     u32 wbase = 0;
     if (__lane_id() == 0 && bal) wbase = atomicAdd(n_active, (u32)__popcll(bal));
     wbase = __shfl(wbase, 0, 64);
-    if (act) active[wbase + (u32)__popcll(bal & lanemask_lt())] = tile;
+    if (act) active[wbase + (u32)__popcll(bal & lanemask_lt())] = item;
   }
 }
 
@@ -660,24 +663,39 @@ __global__ void __launch_bounds__(BLOCK) k_fin_active(const u64* __restrict__ ke
 // timing.  Every return is uniform over the workgroup.
 __device__ __forceinline__ void finish_stretch(
     FinishSmem& sm, u64* __restrict__ keys, u32* __restrict__ rids, const SegList& sl,
-    const u32* __restrict__ ftile_start, const u32* __restrict__ ftile_seg,
     const SegModel* __restrict__ segm, u64* __restrict__ fb_lo, u64* __restrict__ fb_hi,
-    u32* __restrict__ fb_count, u32 max_fb, kpa_sort_stats* stats, u32 tile) {
+    u32* __restrict__ fb_count, u32 max_fb, kpa_sort_stats* stats, u64 item) {
   const u32 tid = threadIdx.x;
-  const u32 seg = ftile_seg[tile];
-  const u32 k = tile - ftile_start[seg];
+  const u32 seg = (u32)(item >> 32);
+  const u32 k = (u32)item;
   const u64 a = sl.lo[seg], b = sl.hi[seg];
   const u64 pos0 = a + (u64)k * FH;
   if (pos0 >= b) return;
   const SegModel m = segm[seg];
   const u32 span = (u32)min<u64>(FH, b - pos0);
-  const lds_float* kn = bind_knots(m, sm.knots);
-  __syncthreads();
-
   // --- window from L0: the entry before the stretch (k > 0) or pos0 = a ---
+  // Its keys are in flight while the knots are copied to LDS.
   const u64 L0 = k > 0 ? pos0 - 1 : pos0;
   u32 have = (u32)min<u64>(FIN_FIRST, b - L0);
-  load_window<FIN_IT>(sm, m, kn, keys, L0, 0, have);
+  {
+    u64 kv[FIN_IT];
+#pragma unroll
+    for (int j = 0; j < FIN_IT; ++j) {
+      const u32 i = tid + j * FIN_THREADS;
+      kv[j] = i < have ? keys[L0 + i] : 0ull;
+    }
+    const lds_float* kn0 = bind_knots(m, sm.knots);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < FIN_IT; ++j) {
+      const u32 i = tid + j * FIN_THREADS;
+      if (i < have) {
+        sm.skeys[i] = kv[j];
+        sm.srel[i] = m.valid ? model_fine(m, kn0, kv[j]) : 0u;
+      }
+    }
+  }
+  const lds_float* kn = (const lds_float*)sm.knots;
   __syncthreads();
   u32 s0 = 0;  // window index of the chunk's first entry
   if (k > 0) {
@@ -787,14 +805,13 @@ __device__ __forceinline__ void finish_stretch(
 // list needs more registers than the body alone and measured slower.
 __global__ void __launch_bounds__(FIN_THREADS, 4) k_learned_finish(
     u64* __restrict__ keys, u32* __restrict__ rids, SegList sl,
-    const u32* __restrict__ ftile_start, const u32* __restrict__ ftile_seg,
-    const SegModel* __restrict__ segm, const u32* __restrict__ active,
+    const SegModel* __restrict__ segm, const u64* __restrict__ active,
     const u32* __restrict__ n_active, u64* __restrict__ fb_lo, u64* __restrict__ fb_hi,
     u32* __restrict__ fb_count, u32 max_fb, kpa_sort_stats* stats) {
   __shared__ FinishSmem sm;
   if (blockIdx.x >= *n_active) return;
-  finish_stretch(sm, keys, rids, sl, ftile_start, ftile_seg, segm, fb_lo, fb_hi, fb_count,
-                 max_fb, stats, active[blockIdx.x]);
+  finish_stretch(sm, keys, rids, sl, segm, fb_lo, fb_hi, fb_count, max_fb, stats,
+                 active[blockIdx.x]);
 }
 
 // Sorts listed ranges of at most FCAP entries in place, one workgroup each.
@@ -1135,7 +1152,7 @@ kpa_status learned_sort_plan(u64 n_cap, u32 n_seg, Carver& c, LearnedWs* w) {
   w->ftile_start = c.take<u32>((u64)n_seg + 1);
   w->ltile_seg = c.take<u32>(w->max_tiles);
   w->ftile_seg = c.take<u32>(w->max_ftiles);
-  w->factive = c.take<u32>(w->max_ftiles);
+  w->factive = c.take<u64>(w->max_ftiles);
   w->fn_active = c.take<u32>(1);
   w->hist = c.take<u32>((u64)n_seg * 2 * RADIX);
   w->seg_mask = c.take<u32>(n_seg);
@@ -1196,8 +1213,8 @@ kpa_status learned_sort_launch(const u64* keys_in, const u32* rids_in, u64* keys
              keys_out, sl, lw.ftile_start, lw.ftile_seg, lw.segm, (u32)lw.max_ftiles, lw.factive,
              lw.fn_active);
   KPA_LAUNCH("learned_finish", k_learned_finish, dim3((u32)lw.max_ftiles), dim3(FIN_THREADS), 0,
-             st, keys_out, rids_out, sl, lw.ftile_start, lw.ftile_seg, lw.segm, lw.factive,
-             lw.fn_active, lw.fb_lo, lw.fb_hi, lw.fb_count, lw.max_fb, stats);
+             st, keys_out, rids_out, sl, lw.segm, lw.factive, lw.fn_active, lw.fb_lo, lw.fb_hi,
+             lw.fb_count, lw.max_fb, stats);
 
   // Pivot rounds over the oversize chunks: round 0 reads the finishing pass's
   // list, round 1 the parts round 0 left over; small parts collect in one list.
