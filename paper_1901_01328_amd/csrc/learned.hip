@@ -3,13 +3,17 @@
 // A monotone model F (kpa_pwl_model: piecewise-linear CDF fitted on the sorted
 // KPA of an earlier window) maps each key to a bucket b = floor(B*F(key)),
 // B = 2^bits chosen per segment so that buckets hold about 512 entries.
+// F is applied over the segment's key range, taken from a sample of its keys.
 // Because F never decreases, every key of bucket b precedes every key of
 // bucket b+1, so the sort reduces to
-//   1. a stable scatter by bucket id: one or two onesweep passes over the
-//      bucket id's bytes (digit_sort.hpp with the model as digit function);
-//   2. a finishing pass: each workgroup owns the buckets that start in its
-//      2048-entry stretch of the output and sorts them (at most 4096 entries)
-//      in LDS with a stable LSD radix over the bytes that vary among them;
+//   1. a stable scatter by bucket id: one onesweep pass for up to 8 bits of
+//      bucket id, else two with the bits split evenly (digit_sort.hpp with
+//      the model as digit function);
+//   2. a finishing pass: the 2048-entry stretches of the output in which a
+//      bucket starts are listed, and a workgroup per listed stretch sorts the
+//      buckets that start in it (at most 4096 entries) in LDS: by a refined
+//      bucket id (8 more bits of F), then by key within runs of one refined
+//      id, with a byte-wise LSD radix as the fallback;
 //   3. oversize chunks (a bucket larger than the on-chip capacity, typically
 //      a heavy key plus a few light keys the model could not separate) are
 //      listed.  Each is split stably three ways around its most frequent key
