@@ -449,8 +449,12 @@ __device__ u32 lds_sort_model(FinishSmem& sm, const SegModel& m, u32 mcount) {
       re[j] = v ? sm.srel[o] - (p == 0 ? base : 0u) : 0u;
       d[j] = (re[j] >> (8 * p)) & 255u;
     }
-    // items read before rank_tile's first barrier, overwritten after its last
-    rank_tile(sm.whist, sm.lstart, sm.scan, d, valid, rank, &tc);
+    // items read before rank_tile's first barrier, overwritten after its last;
+    // a pass's digits are below 2^nbits (the second pass's: the chunk's
+    // bucket offset, a few bits)
+    const u32 top = p == 0 ? (rmax < 256u ? rmax : 255u) : (rmax >> 8);
+    const u32 nbits = top ? 32u - __clz(top) : 1u;
+    rank_tile(sm.whist, sm.lstart, sm.scan, d, valid, rank, &tc, nbits);
 #pragma unroll
     for (int j = 0; j < IT; ++j)
       if ((valid >> j) & 1) {

@@ -60,10 +60,12 @@ __device__ __forceinline__ u32 part_offset(int j) {
 // before w and get the tile's count of digit t (0 for other threads); the
 // caller synchronizes before any thread reads another thread's column.
 // Item j is present iff bit j of `valid` is set.  Items are laid out as in
-// part_offset<NW, IT> (for NW*64*IT == TILE, as in tile_offset_t<NW>).
+// part_offset<NW, IT> (for NW*64*IT == TILE, as in tile_offset_t<NW>).  Every
+// digit is below 2^nbits (nbits uniform over the workgroup): only those bits
+// are matched.
 template <int NW, int IT>
 __device__ __forceinline__ u32 rank_count(u32 (&whist)[NW][RADIX], const u32 (&d)[IT], u32 valid,
-                                          u32 (&rank)[IT]) {
+                                          u32 (&rank)[IT], u32 nbits = 8) {
   static_assert(NW * 64 * IT <= TILE && IT <= 32, "tile geometry");
   const u32 tid = threadIdx.x;
   const u32 w = tid >> 6;
@@ -79,9 +81,11 @@ __device__ __forceinline__ u32 rank_count(u32 (&whist)[NW][RADIX], const u32 (&d
     u64 peers = ballot(v);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
-      const bool bit = (dj >> b) & 1;
-      const u64 bal = ballot(bit);
-      peers &= bit ? bal : ~bal;
+      if ((u32)b < nbits) {
+        const bool bit = (dj >> b) & 1;
+        const u64 bal = ballot(bit);
+        peers &= bit ? bal : ~bal;
+      }
     }
     u32 before = wh[dj];
     const u32 below = (u32)__popcll(peers & lt);
@@ -125,8 +129,8 @@ __device__ __forceinline__ void rank_starts(u32 total, u32* lstart, u32* scan, u
 template <int NW, int IT>
 __device__ __forceinline__ u32 rank_tile(u32 (&whist)[NW][RADIX], u32* lstart, u32* scan,
                                          const u32 (&d)[IT], u32 valid, u32 (&rank)[IT],
-                                         u32* tile_count) {
-  const u32 total = rank_count<NW, IT>(whist, d, valid, rank);
+                                         u32* tile_count, u32 nbits = 8) {
+  const u32 total = rank_count<NW, IT>(whist, d, valid, rank, nbits);
   rank_starts<NW>(total, lstart, scan, tile_count);
   return total;
 }
