@@ -899,14 +899,19 @@ __global__ void __launch_bounds__(BLOCK) k_fb_pivot(const u64* __restrict__ keys
 }
 
 // Entries below / equal to the pivot, per tile of the chunk list and per
-// chunk (comparisons and wave sums; one atomic pair per tile).
+// chunk (comparisons and wave sums; one atomic pair per tile).  Each thread
+// also stores which of its entries (tile_offset layout) equal the pivot, so
+// that the move reads no key of the equal part and the copy back writes the
+// pivot only where another key stood.
 __global__ void __launch_bounds__(BLOCK) k_fb_count(const u64* __restrict__ keys, SegList sl,
                                                     const u32* __restrict__ tile_start,
                                                     const u32* __restrict__ tile_seg,
                                                     const u64* __restrict__ pivot,
                                                     u64* __restrict__ cnt3,
                                                     u32* __restrict__ t_lt,
-                                                    u32* __restrict__ t_eq) {
+                                                    u32* __restrict__ t_eq,
+                                                    uint16_t* __restrict__ t_eqbits) {
+  static_assert(ITEMS <= 16, "one 16-bit word of flags per thread and tile");
   __shared__ u64 red[2 * WAVES];
   const u32 n_seg = sl.n();
   const u32 total = tile_start[n_seg];
@@ -919,16 +924,19 @@ __global__ void __launch_bounds__(BLOCK) k_fb_count(const u64* __restrict__ keys
     u64 kv[ITEMS];
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
-      const u32 i = threadIdx.x + j * BLOCK;
-      kv[j] = i < cnt ? keys[base + i] : 0ull;
+      const u32 o = tile_offset(j);
+      kv[j] = o < cnt ? keys[base + o] : 0ull;
     }
+    u32 eqbits = 0;
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
-      if (threadIdx.x + j * BLOCK < cnt) {
+      if (tile_offset(j) < cnt) {
         lt += kv[j] < h;
         eq += kv[j] == h;
+        eqbits |= (u32)(kv[j] == h) << j;
       }
     }
+    t_eqbits[(u64)tile * BLOCK + threadIdx.x] = (uint16_t)eqbits;
     lt = wave_sum(lt);
     eq = wave_sum(eq);
     __syncthreads();
@@ -1060,6 +1068,7 @@ __global__ void __launch_bounds__(BLOCK) k_fb_move(const u64* __restrict__ keys,
                                                    const u32* __restrict__ p_mask,
                                                    const u32* __restrict__ t_lt,
                                                    const u32* __restrict__ t_eq,
+                                                   const uint16_t* __restrict__ t_eqbits,
                                                    u64* __restrict__ keys_tmp,
                                                    u32* __restrict__ rids_tmp) {
   __shared__ u32 whist[WAVES][RADIX];
@@ -1075,20 +1084,20 @@ __global__ void __launch_bounds__(BLOCK) k_fb_move(const u64* __restrict__ keys,
     u64 kk[ITEMS];
     u32 rr[ITEMS], d[ITEMS], rank[ITEMS];
     u32 valid = 0;
+    const u32 eqbits = t_eqbits[(u64)tile * BLOCK + threadIdx.x];
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
       const u32 o = tile_offset(j);
-      kk[j] = 0;
+      kk[j] = h;
       rr[j] = 0;
-      d[j] = 0;
       if (o < cnt) {
-        kk[j] = keys[base + o];
+        if (!((eqbits >> j) & 1)) kk[j] = keys[base + o];  // the equal part's keys are the pivot
         rr[j] = rids[base + o];
         valid |= 1u << j;
       }
     }
 #pragma unroll
-    for (int j = 0; j < ITEMS; ++j) d[j] = kk[j] < h ? 0u : (kk[j] == h ? 1u : 2u);
+    for (int j = 0; j < ITEMS; ++j) d[j] = ((eqbits >> j) & 1) ? 1u : (kk[j] < h ? 0u : 2u);
     __syncthreads();  // the previous tile's whist reads are done
     rank_count<WAVES, ITEMS>(whist, d, valid, rank);
     __syncthreads();  // rank_count turns the counts into cross-wave offsets after its barrier
@@ -1107,13 +1116,16 @@ __global__ void __launch_bounds__(BLOCK) k_fb_move(const u64* __restrict__ keys,
 }
 
 // The split chunks back into place: row ids from the temporary buffer; keys
-// from it too, except in the equal part, which is the pivot.
+// from it too, except in the equal part, which is the pivot: written only
+// where the chunk held another key before the split (the flags of k_fb_count
+// describe the entries at the same positions, in the same thread layout).
 __global__ void __launch_bounds__(BLOCK) k_fb_back(u64* __restrict__ keys, u32* __restrict__ rids,
                                                    SegList sl, const u32* __restrict__ tile_start,
                                                    const u32* __restrict__ tile_seg,
                                                    const u64* __restrict__ pivot,
                                                    const u64* __restrict__ cnt3,
                                                    const u32* __restrict__ p_mask,
+                                                   const uint16_t* __restrict__ t_eqbits,
                                                    const u64* __restrict__ keys_tmp,
                                                    const u32* __restrict__ rids_tmp) {
   const u32 n_seg = sl.n();
@@ -1125,21 +1137,23 @@ __global__ void __launch_bounds__(BLOCK) k_fb_back(u64* __restrict__ keys, u32* 
     if (!p_mask[seg]) continue;
     const u64 h = pivot[seg];
     const u64 e0 = a + cnt3[3 * seg], e1 = e0 + cnt3[3 * seg + 1];
+    const u32 eqbits = t_eqbits[(u64)tile * BLOCK + threadIdx.x];
     u64 kv[ITEMS];
     u32 rv[ITEMS];
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
-      const u64 p = base + threadIdx.x + j * BLOCK;
-      const bool in = threadIdx.x + j * BLOCK < cnt;
+      const u64 p = base + tile_offset(j);
+      const bool in = tile_offset(j) < cnt;
       rv[j] = in ? rids_tmp[p] : 0u;
       kv[j] = (in && (p < e0 || p >= e1)) ? keys_tmp[p] : h;
     }
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
-      const u64 p = base + threadIdx.x + j * BLOCK;
-      if (threadIdx.x + j * BLOCK < cnt) {
+      const u64 p = base + tile_offset(j);
+      if (tile_offset(j) < cnt) {
         rids[p] = rv[j];
-        keys[p] = kv[j];
+        // in the equal part the pivot is already there where the chunk held it
+        if (p < e0 || p >= e1 || !((eqbits >> j) & 1)) keys[p] = kv[j];
       }
     }
   }
@@ -1187,6 +1201,7 @@ kpa_status learned_sort_plan(u64 n_cap, u32 n_seg, Carver& c, LearnedWs* w) {
   w->p_mask = c.take<u32>(w->max_fb);
   w->t_lt = c.take<u32>(max_tiles(n_cap, w->max_fb, TILE));
   w->t_eq = c.take<u32>(max_tiles(n_cap, w->max_fb, TILE));
+  w->t_eqbits = c.take<uint16_t>(max_tiles(n_cap, w->max_fb, TILE) * BLOCK);
   // The radix path for what the pivot rounds leave: its own ping-pong buffer
   // and per-chunk state.
   return radix_sort_plan(n_cap, w->max_fb, c, &w->fb_radix);
@@ -1237,7 +1252,8 @@ kpa_status learned_sort_launch(const u64* keys_in, const u32* rids_in, u64* keys
     KPA_CHECK(launch_tile_seg(lw.fb_tile_start, lw.max_fb, cnt_in[r],
                               max_tiles(lw.n_cap, lw.max_fb, TILE), lw.fb_tile_seg, st));
     KPA_LAUNCH("pivot_count", k_fb_count, dim3(2048), dim3(BLOCK), 0, st, keys_out, fl,
-               lw.fb_tile_start, lw.fb_tile_seg, lw.pivot, lw.cnt3, lw.t_lt, lw.t_eq);
+               lw.fb_tile_start, lw.fb_tile_seg, lw.pivot, lw.cnt3, lw.t_lt, lw.t_eq,
+               lw.t_eqbits);
     KPA_LAUNCH("pivot_plan", k_fb_plan, dim3(64), dim3(BLOCK), 0, st, fl, lw.cnt3, lw.p_mask,
                lw.sm_lo, lw.sm_hi, lw.rl_count + 2, 6 * lw.max_fb, lw.rl_lo[r],
                lw.rl_hi[r], lw.rl_count + r, lw.max_fb, r == 0 ? stats : nullptr);
@@ -1245,10 +1261,10 @@ kpa_status learned_sort_launch(const u64* keys_in, const u32* rids_in, u64* keys
                lw.p_mask, lw.t_lt, lw.t_eq);
     KPA_LAUNCH("pivot_move", k_fb_move, dim3(2048), dim3(BLOCK), 0, st, keys_out, rids_out, fl,
                lw.fb_tile_start, lw.fb_tile_seg, lw.pivot, lw.cnt3, lw.p_mask, lw.t_lt, lw.t_eq,
-               lw.keys_tmp, lw.rids_tmp);
+               lw.t_eqbits, lw.keys_tmp, lw.rids_tmp);
     KPA_LAUNCH("pivot_back", k_fb_back, dim3(2048), dim3(BLOCK), 0, st, keys_out, rids_out, fl,
-               lw.fb_tile_start, lw.fb_tile_seg, lw.pivot, lw.cnt3, lw.p_mask, lw.keys_tmp,
-               lw.rids_tmp);
+               lw.fb_tile_start, lw.fb_tile_seg, lw.pivot, lw.cnt3, lw.p_mask, lw.t_eqbits,
+               lw.keys_tmp, lw.rids_tmp);
   }
   KPA_LAUNCH("lds_sort_ranges", k_lds_sort_ranges, dim3(2048), dim3(FIN_THREADS), 0, st, keys_out,
              rids_out, lw.sm_lo, lw.sm_hi, lw.rl_count + 2, 6 * lw.max_fb);

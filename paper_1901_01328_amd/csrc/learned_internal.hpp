@@ -125,6 +125,7 @@ struct LearnedWs {
   u32* p_mask;       // per chunk: 1 when it is split (holds more than its pivot key)
   u32* t_lt;         // per tile of the chunk list: entries below / equal to the pivot,
   u32* t_eq;         // then their counts in the chunk's earlier tiles
+  uint16_t* t_eqbits;  // per tile and thread: which of the thread's 16 entries equal the pivot
   u64 n_cap;
   u64 max_tiles;
   u64 max_ftiles;
