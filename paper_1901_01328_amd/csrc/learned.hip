@@ -1099,7 +1099,7 @@ __global__ void __launch_bounds__(BLOCK) k_fb_move(const u64* __restrict__ keys,
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) d[j] = ((eqbits >> j) & 1) ? 1u : (kk[j] < h ? 0u : 2u);
     __syncthreads();  // the previous tile's whist reads are done
-    rank_count<WAVES, ITEMS>(whist, d, valid, rank);
+    rank_count<WAVES, ITEMS>(whist, d, valid, rank, 2);  // classes 0..2: two digit bits
     __syncthreads();  // rank_count turns the counts into cross-wave offsets after its barrier
     const u32 lt0 = t_lt[tile], eq0 = t_eq[tile];
     const u64 LT = cnt3[3 * seg], EQ = cnt3[3 * seg + 1];
