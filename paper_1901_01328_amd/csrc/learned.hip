@@ -672,7 +672,8 @@ __global__ void __launch_bounds__(BLOCK) k_fin_active(const u64* __restrict__ ke
 __device__ __forceinline__ void finish_stretch(
     FinishSmem& sm, u64* __restrict__ keys, u32* __restrict__ rids, const SegList& sl,
     const SegModel* __restrict__ segm, u64* __restrict__ fb_lo, u64* __restrict__ fb_hi,
-    u32* __restrict__ fb_count, u32 max_fb, kpa_sort_stats* stats, u64 item) {
+    u32* __restrict__ fb_seg, u32* __restrict__ fb_count, u32 max_fb, kpa_sort_stats* stats,
+    u64 item) {
   const u32 tid = threadIdx.x;
   const u32 seg = (u32)(item >> 32);
   const u32 k = (u32)item;
@@ -781,6 +782,7 @@ __device__ __forceinline__ void finish_stretch(
       if (idx < max_fb) {
         fb_lo[idx] = start;
         fb_hi[idx] = hi;
+        fb_seg[idx] = seg;
       }
     }
     return;
@@ -815,18 +817,23 @@ __global__ void __launch_bounds__(FIN_THREADS, 4) k_learned_finish(
     u64* __restrict__ keys, u32* __restrict__ rids, SegList sl,
     const SegModel* __restrict__ segm, const u64* __restrict__ active,
     const u32* __restrict__ n_active, u64* __restrict__ fb_lo, u64* __restrict__ fb_hi,
-    u32* __restrict__ fb_count, u32 max_fb, kpa_sort_stats* stats) {
+    u32* __restrict__ fb_seg, u32* __restrict__ fb_count, u32 max_fb, kpa_sort_stats* stats) {
   __shared__ FinishSmem sm;
   if (blockIdx.x >= *n_active) return;
-  finish_stretch(sm, keys, rids, sl, segm, fb_lo, fb_hi, fb_count, max_fb, stats,
+  finish_stretch(sm, keys, rids, sl, segm, fb_lo, fb_hi, fb_seg, fb_count, max_fb, stats,
                  active[blockIdx.x]);
 }
 
 // Sorts listed ranges of at most FCAP entries in place, one workgroup each.
+// A range is a part of an oversize chunk, in bucket order; above FIN_THREADS
+// entries it is sorted as a finishing chunk is, by its segment's refined
+// bucket ids and then within runs of equal id.
 __global__ void __launch_bounds__(FIN_THREADS, 4) k_lds_sort_ranges(u64* __restrict__ keys,
                                                            u32* __restrict__ rids,
                                                            const u64* __restrict__ lo,
                                                            const u64* __restrict__ hi,
+                                                           const u32* __restrict__ seg,
+                                                           const SegModel* __restrict__ segm,
                                                            const u32* __restrict__ count,
                                                            u32 max_count) {
   __shared__ FinishSmem sm;
@@ -835,11 +842,37 @@ __global__ void __launch_bounds__(FIN_THREADS, 4) k_lds_sort_ranges(u64* __restr
     const u64 a = lo[r];
     const u32 m = (u32)(hi[r] - a);
     __syncthreads();
-    for (u32 i = threadIdx.x; i < m; i += FIN_THREADS) {
-      sm.skeys[i] = keys[a + i];
-      sm.srids[i] = rids[a + i];
+    if (m <= FIN_THREADS) {
+      for (u32 i = threadIdx.x; i < m; i += FIN_THREADS) {
+        sm.skeys[i] = keys[a + i];
+        sm.srids[i] = rids[a + i];
+      }
+    } else {
+      const SegModel md = segm[seg[r]];
+      const lds_float* kn = md.valid ? bind_knots(md, sm.knots) : nullptr;
+      __syncthreads();
+      for (u32 i = threadIdx.x; i < m; i += FIN_THREADS) {
+        const u64 k = keys[a + i];
+        sm.skeys[i] = k;
+        sm.srids[i] = rids[a + i];
+        sm.srel[i] = md.valid ? model_fine(md, kn, k) : 0u;
+      }
     }
-    const bool moved = m <= FIN_THREADS ? rank_sort_small(sm, m) : lds_sort(sm, m);
+    bool moved;
+    if (m <= FIN_THREADS) {
+      moved = rank_sort_small(sm, m);
+    } else {
+      const SegModel md = segm[seg[r]];
+      __syncthreads();  // the sort reads other threads' entries before its first barrier
+      u32 res;
+      if (m <= 2048)
+        res = lds_sort_model<4>(sm, md, m);
+      else if (m <= 3072)
+        res = lds_sort_model<6>(sm, md, m);
+      else
+        res = lds_sort_model<8>(sm, md, m);
+      moved = res == CH_MOVED;
+    }
     if (moved) {
       for (u32 i = threadIdx.x; i < m; i += FIN_THREADS) {
         keys[a + i] = sm.skeys[i];
@@ -964,11 +997,14 @@ __global__ void __launch_bounds__(BLOCK) k_fb_count(const u64* __restrict__ keys
 // One thread per chunk: whether the chunk
 // needs the scatter at all (not when it holds only the pivot key), and the
 // parts still to sort: on chip when small, else in the next round.
-__global__ void __launch_bounds__(BLOCK) k_fb_plan(SegList sl, const u64* __restrict__ cnt3,
+__global__ void __launch_bounds__(BLOCK) k_fb_plan(SegList sl, const u32* __restrict__ c_seg,
+                                                   const u64* __restrict__ cnt3,
                                                    u32* __restrict__ p_mask,
                                                    u64* __restrict__ sm_lo, u64* __restrict__ sm_hi,
+                                                   u32* __restrict__ sm_seg,
                                                    u32* __restrict__ sm_count, u32 sm_max,
                                                    u64* __restrict__ nx_lo, u64* __restrict__ nx_hi,
+                                                   u32* __restrict__ nx_seg,
                                                    u32* __restrict__ nx_count, u32 nx_max,
                                                    kpa_sort_stats* stats) {
   const u32 n = sl.n();
@@ -992,12 +1028,14 @@ __global__ void __launch_bounds__(BLOCK) k_fb_plan(SegList sl, const u64* __rest
         if (i < sm_max) {
           sm_lo[i] = parts_lo[p];
           sm_hi[i] = parts_lo[p] + parts_n[p];
+          sm_seg[i] = c_seg[c];
         }
       } else {
         const u32 i = atomicAdd(nx_count, 1u);
         if (i < nx_max) {
           nx_lo[i] = parts_lo[p];
           nx_hi[i] = parts_lo[p] + parts_n[p];
+          nx_seg[i] = c_seg[c];
         }
       }
     }
@@ -1184,6 +1222,7 @@ kpa_status learned_sort_plan(u64 n_cap, u32 n_seg, Carver& c, LearnedWs* w) {
   order_plan(c, w->max_tiles, n_seg, &w->order);
   w->fb_lo = c.take<u64>(w->max_fb);
   w->fb_hi = c.take<u64>(w->max_fb);
+  w->fb_seg = c.take<u32>(w->max_fb);
   w->fb_min = c.take<u64>(1);
   w->fb_max = c.take<u64>(1);
   w->fb_count = c.take<u32>(1);
@@ -1192,10 +1231,12 @@ kpa_status learned_sort_plan(u64 n_cap, u32 n_seg, Carver& c, LearnedWs* w) {
   for (int r = 0; r < 2; ++r) {
     w->rl_lo[r] = c.take<u64>(w->max_fb);
     w->rl_hi[r] = c.take<u64>(w->max_fb);
+    w->rl_seg[r] = c.take<u32>(w->max_fb);
   }
   w->rl_count = c.take<u32>(4);
   w->sm_lo = c.take<u64>(6ull * w->max_fb);
   w->sm_hi = c.take<u64>(6ull * w->max_fb);
+  w->sm_seg = c.take<u32>(6ull * w->max_fb);
   w->pivot = c.take<u64>(w->max_fb);
   w->cnt3 = c.take<u64>(3ull * w->max_fb);
   w->p_mask = c.take<u32>(w->max_fb);
@@ -1237,13 +1278,14 @@ kpa_status learned_sort_launch(const u64* keys_in, const u32* rids_in, u64* keys
              lw.fn_active);
   KPA_LAUNCH("learned_finish", k_learned_finish, dim3((u32)lw.max_ftiles), dim3(FIN_THREADS), 0,
              st, keys_out, rids_out, sl, lw.segm, lw.factive, lw.fn_active, lw.fb_lo, lw.fb_hi,
-             lw.fb_count, lw.max_fb, stats);
+             lw.fb_seg, lw.fb_count, lw.max_fb, stats);
 
   // Pivot rounds over the oversize chunks: round 0 reads the finishing pass's
   // list, round 1 the parts round 0 left over; small parts collect in one list.
   const u64* lo_in[2] = {lw.fb_lo, lw.rl_lo[0]};
   const u64* hi_in[2] = {lw.fb_hi, lw.rl_hi[0]};
   const u32* cnt_in[2] = {lw.fb_count, lw.rl_count + 0};
+  const u32* seg_in[2] = {lw.fb_seg, lw.rl_seg[0]};
   for (int r = 0; r < 2; ++r) {
     const SegList fl{lo_in[r], hi_in[r], cnt_in[r], lw.max_fb};
     KPA_LAUNCH("pivot_select", k_fb_pivot, dim3(1024), dim3(BLOCK), 0, st, keys_out, fl, lw.pivot,
@@ -1254,9 +1296,10 @@ kpa_status learned_sort_launch(const u64* keys_in, const u32* rids_in, u64* keys
     KPA_LAUNCH("pivot_count", k_fb_count, dim3(2048), dim3(BLOCK), 0, st, keys_out, fl,
                lw.fb_tile_start, lw.fb_tile_seg, lw.pivot, lw.cnt3, lw.t_lt, lw.t_eq,
                lw.t_eqbits);
-    KPA_LAUNCH("pivot_plan", k_fb_plan, dim3(64), dim3(BLOCK), 0, st, fl, lw.cnt3, lw.p_mask,
-               lw.sm_lo, lw.sm_hi, lw.rl_count + 2, 6 * lw.max_fb, lw.rl_lo[r],
-               lw.rl_hi[r], lw.rl_count + r, lw.max_fb, r == 0 ? stats : nullptr);
+    KPA_LAUNCH("pivot_plan", k_fb_plan, dim3(64), dim3(BLOCK), 0, st, fl, seg_in[r], lw.cnt3,
+               lw.p_mask, lw.sm_lo, lw.sm_hi, lw.sm_seg, lw.rl_count + 2, 6 * lw.max_fb,
+               lw.rl_lo[r], lw.rl_hi[r], lw.rl_seg[r], lw.rl_count + r, lw.max_fb,
+               r == 0 ? stats : nullptr);
     KPA_LAUNCH("pivot_prefix", k_fb_tscan, dim3(1024), dim3(1024), 0, st, fl, lw.fb_tile_start,
                lw.p_mask, lw.t_lt, lw.t_eq);
     KPA_LAUNCH("pivot_move", k_fb_move, dim3(2048), dim3(BLOCK), 0, st, keys_out, rids_out, fl,
@@ -1267,7 +1310,7 @@ kpa_status learned_sort_launch(const u64* keys_in, const u32* rids_in, u64* keys
                lw.keys_tmp, lw.rids_tmp);
   }
   KPA_LAUNCH("lds_sort_ranges", k_lds_sort_ranges, dim3(2048), dim3(FIN_THREADS), 0, st, keys_out,
-             rids_out, lw.sm_lo, lw.sm_hi, lw.rl_count + 2, 6 * lw.max_fb);
+             rids_out, lw.sm_lo, lw.sm_hi, lw.sm_seg, lw.segm, lw.rl_count + 2, 6 * lw.max_fb);
 
   // What two rounds did not resolve goes through the radix path.
   const SegList rl{lw.rl_lo[1], lw.rl_hi[1], lw.rl_count + 1, lw.max_fb};

@@ -108,6 +108,7 @@ struct LearnedWs {
   OrderBufs order;
   u64* fb_lo;      // oversize chunks: [lo, hi)
   u64* fb_hi;
+  u32* fb_seg;     // segment of each oversize chunk (its model sorts the chunk's small parts)
   u64* fb_min;
   u64* fb_max;
   u32* fb_count;
@@ -117,9 +118,11 @@ struct LearnedWs {
   // their most frequent key; parts still larger than FCAP go to round r+1
   u64* rl_lo[2];
   u64* rl_hi[2];
+  u32* rl_seg[2];
   u32* rl_count;     // [2] round lists, [2] small-range list
   u64* sm_lo;        // parts of at most FCAP entries, sorted on chip
   u64* sm_hi;
+  u32* sm_seg;
   u64* pivot;
   u64* cnt3;         // per chunk: below, equal, above the pivot
   u32* p_mask;       // per chunk: 1 when it is split (holds more than its pivot key)
