@@ -185,6 +185,33 @@ def test_pivot_split_heavy_key_with_light_neighbours(K, orc):
     assert st[4] >= 1 and st[2] >= n - 3000   # split around the heavy key
 
 
+def heavy_with_close_neighbours(seed, n=300001):
+    """Half the keys one heavy key H = 2^39; 6000 light keys within 2^18 of
+    it (with a model fitted on such data they share H's bucket but spread
+    over its refined ids); the rest uniform over [0, 2^40)."""
+    rng = np.random.default_rng(seed)
+    H = 1 << 39
+    keys = rng.integers(0, 1 << 40, size=n, dtype=np.int64)
+    idx = rng.permutation(n)
+    keys[idx[: n // 2]] = H
+    keys[idx[n // 2: n // 2 + 6000]] = H + rng.integers(-(1 << 18), 1 << 18, size=6000)
+    return keys.astype(np.uint64)
+
+
+def test_pivot_split_parts_sorted_by_model(K, orc):
+    """An oversize bucket holding a heavy key and a few thousand light keys
+    close to it, with a model fitted on an earlier draw: the split leaves
+    parts of 512 to FCAP entries, which are sorted on chip by their window's
+    refined bucket ids."""
+    off = seg_offsets([300001])
+    models, _ = fit_models(K, heavy_with_close_neighbours(21), off)
+    keys = heavy_with_close_neighbours(22)
+    say("pivot split, parts sorted by the model")
+    rids = np.random.default_rng(23).permutation(len(keys)).astype(np.uint32)
+    st = check_learned(K, orc, keys, rids, off, models)
+    assert st[4] >= 1   # an oversize bucket was split around its heavy key
+
+
 @pytest.mark.parametrize("bad", ["decreasing", "nan", "above_one"])
 def test_invalid_model_detected(K, orc, bad):
     n = 100001
