@@ -67,17 +67,21 @@ def measure_copy_rate(dev, mib=1024, reps=5):
     return round(2 * (mib << 20) / (ms / 1000) / 1e9, 1)
 
 
-def counted_traffic(kernel_row):
-    """HBM bytes per dispatch of a kernel from the committed counter summary
+RADIX_PASS_SOURCES = ("onesweep.hpp", "digit_sort.hpp", "radix.hip")
+LEARNED_PASS_SOURCES = ("onesweep.hpp", "digit_sort.hpp", "learned.hip", "learned_internal.hpp")
+
+
+def counted_traffic(kernel_row, summary="c2_radix_hbm_bytes.md", sources=RADIX_PASS_SOURCES):
+    """HBM bytes per dispatch of a kernel from a committed counter summary
     (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the scatter
     pass's sources changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "c2_radix_hbm_bytes.md")
+    path = os.path.join(ROOT, "profiles", summary)
     if not os.path.exists(path):
         return None
     text = open(path).read()
     h = hashlib.sha256()
-    for f in ("onesweep.hpp", "digit_sort.hpp", "radix.hip"):
+    for f in sources:
         with open(os.path.join(ROOT, "paper_1901_01328_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     if f"sha256 {h.hexdigest()[:16]}" not in text:
@@ -213,8 +217,11 @@ def main():
         bytes_per_launch = PASS_BYTES.get(dom, 24) * n * (active / n_win) / launches \
             if dom == "radix_pass" else PASS_BYTES.get(dom, 24) * n
         achieved = bytes_per_launch / (avg_ms / 1000.0) / 1e9
-        traffic = counted_traffic("k_ds_pass<RadixDF>") if dom == "radix_pass" and \
-            n == 1 << 28 else None
+        traffic = None
+        if n == 1 << 28:
+            traffic = counted_traffic("k_ds_pass<RadixDF>") if dom == "radix_pass" else \
+                counted_traffic("k_ds_pass<LearnedDF>", "c2_learned_hbm_bytes.md",
+                                LEARNED_PASS_SOURCES)
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "copy_gbs": COPY_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
