@@ -842,11 +842,13 @@ __global__ void __launch_bounds__(FIN_THREADS, 4) k_lds_sort_ranges(u64* __restr
     const u64 a = lo[r];
     const u32 m = (u32)(hi[r] - a);
     __syncthreads();
+    bool moved;
     if (m <= FIN_THREADS) {
       for (u32 i = threadIdx.x; i < m; i += FIN_THREADS) {
         sm.skeys[i] = keys[a + i];
         sm.srids[i] = rids[a + i];
       }
+      moved = rank_sort_small(sm, m);
     } else {
       const SegModel md = segm[seg[r]];
       const lds_float* kn = md.valid ? bind_knots(md, sm.knots) : nullptr;
@@ -857,12 +859,6 @@ __global__ void __launch_bounds__(FIN_THREADS, 4) k_lds_sort_ranges(u64* __restr
         sm.srids[i] = rids[a + i];
         sm.srel[i] = md.valid ? model_fine(md, kn, k) : 0u;
       }
-    }
-    bool moved;
-    if (m <= FIN_THREADS) {
-      moved = rank_sort_small(sm, m);
-    } else {
-      const SegModel md = segm[seg[r]];
       __syncthreads();  // the sort reads other threads' entries before its first barrier
       u32 res;
       if (m <= 2048)
