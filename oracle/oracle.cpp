@@ -3,10 +3,12 @@
 // Plain, slow, obviously correct definitions of what each step computes,
 // written from StreamBox-HBM (ASPLOS'19): Sec. 4.1 (KPA = resident key plus a
 // pointer to the full record), Table 2 (Extract, Materialize, Sort, Merge,
-// Join, Partition, Keyed reduction), Sec. 4.2 "Compound Operators" (windowing
-// as a partition on the timestamp column, keyed aggregation, temporal join)
-// and the benchmark list of Sec. 6 (windowed sum / median / average per key,
-// temporal join).
+// Join, Partition, Keyed and unkeyed reduction, Select, KeySwap), Sec. 4.2
+// "Compound Operators" (windowing as a partition on the timestamp column, with
+// fixed or sliding windows; keyed aggregation; temporal join), Sec. 4.3 (in-
+// place key update with write-back; Materialize coalesced with Extract) and
+// the benchmark list of Sec. 6 (top-k / sum / median / average / unique count
+// per key, average of a window, temporal join, windowed filter).
 //
 // Only tests, the smoke check and the benchmark's CPU-baseline leg may load
 // this library.  It shares no source, header or helper with the GPU library;
@@ -320,6 +322,268 @@ int orc_window_aggregate(const void* rows, u64 n, int row_bytes, int key_off, in
     for (u32 i = got; i < k; ++i) out_top_key[(u64)w * k + i] = out_top_sum[(u64)w * k + i] = 0;
   }
   *out_checksum = cs;
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Single-pass benchmarks of Sec. 6 (benchmark list) and the remaining Table 2
+// primitives.
+
+// TopK Per Key (Sec. 6, benchmark 1): for every distinct key, its k largest
+// values in descending order (a multiset: equal values repeat).  Output in
+// ascending key order: out_gkey[g], out_gcnt[g] (entries of the key),
+// out_tn[g] = min(k, count) and out_topv[g*k + j], j < out_tn[g] (the rest of
+// the row is set to 0).
+int orc_topk_per_key(const u64* keys, const u32* rids, u64 n, const void* rows, int row_bytes,
+                     int val_off, int val_w, u32 k, u64* out_gkey, u64* out_gcnt, u32* out_tn,
+                     u64* out_topv, u64* out_ngroups) {
+  if ((val_w != 4 && val_w != 8) || k == 0) return -1;
+  std::map<u64, std::vector<u64>> m;
+  for (u64 i = 0; i < n; ++i)
+    m[keys[i]].push_back(load_le(row_at(rows, rids[i], row_bytes) + val_off, val_w));
+  u64 g = 0;
+  for (auto& kv : m) {
+    std::vector<u64>& v = kv.second;
+    std::sort(v.begin(), v.end(), [](u64 a, u64 b) { return a > b; });
+    u32 t = (u32)std::min<u64>(k, v.size());
+    out_gkey[g] = kv.first;
+    out_gcnt[g] = v.size();
+    out_tn[g] = t;
+    for (u32 j = 0; j < k; ++j) out_topv[g * k + j] = j < t ? v[j] : 0;
+    ++g;
+  }
+  *out_ngroups = g;
+  return 0;
+}
+
+// Unique Count Per Key (Sec. 6, benchmark 6): for every distinct key, the
+// number of distinct values among its records.  Ascending key order.
+int orc_unique_count_by_key(const u64* keys, const u32* rids, u64 n, const void* rows,
+                            int row_bytes, int val_off, int val_w, u64* out_gkey, u64* out_uniq,
+                            u64* out_ngroups) {
+  if (val_w != 4 && val_w != 8) return -1;
+  std::map<u64, std::vector<u64>> m;
+  for (u64 i = 0; i < n; ++i)
+    m[keys[i]].push_back(load_le(row_at(rows, rids[i], row_bytes) + val_off, val_w));
+  u64 g = 0;
+  for (auto& kv : m) {
+    std::vector<u64>& v = kv.second;
+    std::sort(v.begin(), v.end());
+    out_gkey[g] = kv.first;
+    out_uniq[g] = (u64)(std::unique(v.begin(), v.end()) - v.begin());
+    ++g;
+  }
+  *out_ngroups = g;
+  return 0;
+}
+
+// Unkeyed reduction over windows (Table 2 "Unkeyed reduction"; Sec. 6,
+// benchmark 5 "Windowed Average All"): for each window w of the rows (window
+// rule as orc_partition), the number of rows, the exact sum of their values as
+// a 128-bit integer (out_sum_lo + 2^64 * out_sum_hi) and the largest value.
+// The average is sum / count (left to the caller, so that it stays exact).
+int orc_reduce_all_windows(const void* rows, u64 n, int row_bytes, int val_off, int val_w,
+                           int ts_off, int ts_w, u64 win_len, u64 origin, u32 n_win, u64* out_cnt,
+                           u64* out_sum_lo, u64* out_sum_hi, u64* out_max, u64* out_oob) {
+  if (win_len == 0 || (ts_w != 4 && ts_w != 8) || (val_w != 4 && val_w != 8)) return -1;
+  std::vector<unsigned __int128> sum(n_win, 0);
+  for (u32 w = 0; w < n_win; ++w) out_cnt[w] = out_max[w] = 0;
+  u64 oob = 0;
+  for (u64 i = 0; i < n; ++i) {
+    const unsigned char* r = row_at(rows, i, row_bytes);
+    u64 ts = load_le(r + ts_off, ts_w);
+    if (ts < origin || (ts - origin) / win_len >= n_win) {
+      ++oob;
+      continue;
+    }
+    u64 w = (ts - origin) / win_len;
+    u64 v = load_le(r + val_off, val_w);
+    out_cnt[w] += 1;
+    sum[w] += v;
+    if (v > out_max[w]) out_max[w] = v;
+  }
+  for (u32 w = 0; w < n_win; ++w) {
+    out_sum_lo[w] = (u64)sum[w];
+    out_sum_hi[w] = (u64)(sum[w] >> 64);
+  }
+  *out_oob = oob;
+  return 0;
+}
+
+// Select (Table 2: keep the pairs that pass a predicate, in their order).  For
+// every segment s of a KPA, entry i passes when x_i * den[s] <op> num[s], with
+// x_i the resident key (column 0) or the value of its row (column 1),
+// num[s] = num_lo[s] + 2^64 * num_hi[s] and the product taken exactly.
+// op: 0 '>', 1 '>=', 2 '<', 3 '<=', 4 '==', 5 '!='.  Survivors are written
+// back to back, segment after segment, with out_seg_off (n_seg + 1).
+int orc_select(const u64* keys, const u32* rids, const u64* seg_off, u32 n_seg, const void* rows,
+               int row_bytes, int val_off, int val_w, int column, int op, const u64* num_lo,
+               const u64* num_hi, const u64* den, u64* out_keys, u32* out_rids,
+               u64* out_seg_off) {
+  if (column != 0 && column != 1) return -1;
+  if (column == 1 && val_w != 4 && val_w != 8) return -1;
+  if (op < 0 || op > 5) return -1;
+  u64 pos = 0;
+  for (u32 s = 0; s < n_seg; ++s) {
+    out_seg_off[s] = pos;
+    unsigned __int128 rhs = ((unsigned __int128)num_hi[s] << 64) | num_lo[s];
+    for (u64 i = seg_off[s]; i < seg_off[s + 1]; ++i) {
+      u64 x = column == 0 ? keys[i] : load_le(row_at(rows, rids[i], row_bytes) + val_off, val_w);
+      unsigned __int128 lhs = (unsigned __int128)x * den[s];
+      bool keep = op == 0 ? lhs > rhs : op == 1 ? lhs >= rhs : op == 2 ? lhs < rhs
+                : op == 3 ? lhs <= rhs : op == 4 ? lhs == rhs : lhs != rhs;
+      if (keep) {
+        out_keys[pos] = keys[i];
+        out_rids[pos] = rids[i];
+        ++pos;
+      }
+    }
+  }
+  out_seg_off[n_seg] = pos;
+  return 0;
+}
+
+// Windowed Filter (Sec. 6, benchmark 8): the average of stream A's values in
+// window w filters the keys of stream B in the same window.  B's row passes
+// when its key is above that average, key > sum_A(w) / count_A(w), decided
+// exactly as key * count_A(w) > sum_A(w); a window of A without rows lets
+// nothing pass.  Output: B's passing (key, rid) per window in arrival order
+// (window rule as orc_partition), with out_win_off (n_win + 1).
+int orc_window_filter(const void* rows_a, u64 na, const void* rows_b, u64 nb, int row_bytes,
+                      int key_off, int val_off, int val_w, int ts_off, int ts_w, u64 win_len,
+                      u64 origin, u32 n_win, u64 rid_base_b, u64* out_keys, u32* out_rids,
+                      u64* out_win_off) {
+  if (win_len == 0 || (ts_w != 4 && ts_w != 8) || (val_w != 4 && val_w != 8)) return -1;
+  std::vector<u64> cnt(n_win, 0);
+  std::vector<unsigned __int128> sum(n_win, 0);
+  for (u64 i = 0; i < na; ++i) {
+    const unsigned char* r = row_at(rows_a, i, row_bytes);
+    u64 ts = load_le(r + ts_off, ts_w);
+    if (ts < origin || (ts - origin) / win_len >= n_win) continue;
+    u64 w = (ts - origin) / win_len;
+    cnt[w] += 1;
+    sum[w] += load_le(r + val_off, val_w);
+  }
+  std::vector<std::vector<std::pair<u64, u32>>> win(n_win);
+  for (u64 i = 0; i < nb; ++i) {
+    const unsigned char* r = row_at(rows_b, i, row_bytes);
+    u64 ts = load_le(r + ts_off, ts_w);
+    if (ts < origin || (ts - origin) / win_len >= n_win) continue;
+    u64 w = (ts - origin) / win_len;
+    u64 key = load_le(r + key_off, 8);
+    if (cnt[w] > 0 && (unsigned __int128)key * cnt[w] > sum[w])
+      win[w].push_back({key, (u32)(rid_base_b + i)});
+  }
+  u64 pos = 0;
+  for (u32 w = 0; w < n_win; ++w) {
+    out_win_off[w] = pos;
+    for (auto& e : win[w]) {
+      out_keys[pos] = e.first;
+      out_rids[pos] = e.second;
+      ++pos;
+    }
+  }
+  out_win_off[n_win] = pos;
+  return 0;
+}
+
+// KeySwap (Table 2: load a nonresident column and make it the resident key):
+// out_keys[i] = the column (col_w = 4 or 8 bytes at col_off, zero-extended)
+// of row rids[i].
+int orc_keyswap(const u32* rids, u64 n, const void* rows, int row_bytes, int col_off, int col_w,
+                u64* out_keys) {
+  if (col_w != 4 && col_w != 8) return -1;
+  for (u64 i = 0; i < n; ++i) out_keys[i] = load_le(row_at(rows, rids[i], row_bytes) + col_off, col_w);
+  return 0;
+}
+
+// In-place key update from a key-value table (Sec. 4.3, optimization 2; the
+// external join of the pipeline example): every resident key found among the
+// table's keys is replaced by the table's value for it; keys not in the table
+// are kept and counted in *out_missing.  The table's keys are distinct.
+int orc_key_update(u64* keys, u64 n, const u64* tkeys, const u64* tvals, u64 tn,
+                   u64* out_missing) {
+  std::map<u64, u64> t;
+  for (u64 j = 0; j < tn; ++j) t[tkeys[j]] = tvals[j];
+  u64 miss = 0;
+  for (u64 i = 0; i < n; ++i) {
+    auto it = t.find(keys[i]);
+    if (it == t.end()) ++miss;
+    else keys[i] = it->second;
+  }
+  *out_missing = miss;
+  return 0;
+}
+
+// Write-back of resident keys to their rows (Sec. 4.3, optimization 2): the
+// column at col_off (8 bytes) of row rids[i] becomes keys[i].  rids are
+// distinct.
+int orc_key_writeback(const u64* keys, const u32* rids, u64 n, void* rows, int row_bytes,
+                      int col_off) {
+  unsigned char* base = static_cast<unsigned char*>(rows);
+  for (u64 i = 0; i < n; ++i) {
+    unsigned char* p = base + (u64)rids[i] * row_bytes + col_off;
+    for (int b = 0; b < 8; ++b) p[b] = (unsigned char)(keys[i] >> (8 * b));
+  }
+  return 0;
+}
+
+// Materialize coalesced with Extract (Sec. 4.3, optimization 1): the rows in
+// KPA order (as orc_materialize) and, from those emitted rows, the next KPA on
+// the column at key_off: out_keys[i] = that column of output row i, out_rids[i]
+// = rid_base + i.
+int orc_materialize_extract(const u32* rids, u64 n, const void* rows, int row_bytes, int key_off,
+                            u64 rid_base, void* out_rows, u64* out_keys, u32* out_rids) {
+  unsigned char* o = static_cast<unsigned char*>(out_rows);
+  for (u64 i = 0; i < n; ++i) {
+    std::memcpy(o + i * row_bytes, row_at(rows, rids[i], row_bytes), row_bytes);
+    out_keys[i] = load_le(o + i * row_bytes + key_off, 8);
+    out_rids[i] = (u32)(rid_base + i);
+  }
+  return 0;
+}
+
+// Sliding windows (Sec. 4.2 "Windowing": windows of length win_len that start
+// every slide): window w covers [origin + w*slide, origin + w*slide + win_len),
+// 0 <= w < n_win, so a row belongs to every window whose range holds its
+// timestamp.  Per window, per distinct key (ascending): count, sum (mod 2^64)
+// and max of the values.  out_gseg_off (n_win + 1) delimits the windows'
+// groups; outputs hold up to cap groups in all.
+int orc_sliding_aggregate(const void* rows, u64 n, int row_bytes, int key_off, int val_off,
+                          int val_w, int ts_off, int ts_w, u64 win_len, u64 slide, u64 origin,
+                          u32 n_win, u64 cap, u64* out_gkey, u64* out_cnt, u64* out_sum,
+                          u64* out_max, u64* out_gseg_off) {
+  if (win_len == 0 || slide == 0 || (ts_w != 4 && ts_w != 8) || (val_w != 4 && val_w != 8))
+    return -1;
+  std::vector<std::map<u64, Agg>> maps(n_win);
+  for (u64 i = 0; i < n; ++i) {
+    const unsigned char* r = row_at(rows, i, row_bytes);
+    u64 ts = load_le(r + ts_off, ts_w);
+    if (ts < origin) continue;
+    u64 key = load_le(r + key_off, 8), v = load_le(r + val_off, val_w);
+    for (u32 w = 0; w < n_win; ++w) {
+      u64 lo = origin + (u64)w * slide;
+      if (ts >= lo && ts - lo < win_len) {
+        Agg& a = maps[w][key];
+        a.cnt += 1;
+        a.sum += v;
+        if (v > a.max) a.max = v;
+      }
+    }
+  }
+  u64 g = 0;
+  for (u32 w = 0; w < n_win; ++w) {
+    out_gseg_off[w] = g;
+    for (auto& kv : maps[w]) {
+      if (g >= cap) return -2;
+      out_gkey[g] = kv.first;
+      out_cnt[g] = kv.second.cnt;
+      out_sum[g] = kv.second.sum;
+      out_max[g] = kv.second.max;
+      ++g;
+    }
+  }
+  out_gseg_off[n_win] = g;
   return 0;
 }
 

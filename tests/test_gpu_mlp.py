@@ -3,15 +3,19 @@
 distillation to PWL knots, and the gain of the trained network over the
 untrained one in the learned-splitter sort (identical output either way).
 
-Tolerances: float32 sums over m samples carry a relative error of order
-m * 2^-24 in the worst case and far less for blocked sums; gradients must
-agree to rtol 2e-3 plus atol 1e-4 * max|g| (entries near zero are dominated by
-cancellation), the forward pass to 1e-5 absolute (values in [0, ~1])."""
+Tolerances: every gradient entry must lie within its own bound, derived in
+tests/mlp_bound.py from the kernel's float32 operation and summation order
+(first-order error propagation through the forward and backward pass, sums of
+256 samples per workgroup then the workgroups in order, so gamma_256 +
+gamma_nblk times the sum of the term magnitudes, plus whole terms of samples
+that sit on a ramp kink within their error); the forward pass to 1e-5
+absolute (values in [0, ~1])."""
 import numpy as np
 import pytest
 import torch
 
 from gpu_util import dev_u32, dev_u64, kpa_mod, need_gpu, say, u32, u64
+from mlp_bound import grad_bound
 from oracle import mlp as M
 
 pytestmark = pytest.mark.gpu
@@ -75,7 +79,13 @@ def test_loss_grad_matches_oracle(K, m):
     gg = g.cpu().numpy().astype(np.float64)
     scale = np.max(np.abs(eg))
     assert abs(float(loss.item()) - el) <= 1e-5 + 1e-3 * el
-    assert np.allclose(gg, eg, rtol=2e-3, atol=1e-4 * scale), np.max(np.abs(gg - eg)) / scale
+    bound, amb = grad_bound(p.astype(np.float32).astype(np.float64),
+                            x.cpu().numpy().astype(np.float64), y.cpu().numpy().astype(np.float64))
+    err = np.abs(gg - eg)
+    say(f"m={m}: max |err|/bound {np.max(err / np.maximum(bound, 1e-300)):.3g}, "
+        f"max |err|/max|g| {np.max(err) / scale:.3g}, bound/max|g| {np.max(bound) / scale:.3g}, "
+        f"samples on a kink {amb}")
+    assert np.all(err <= bound), np.argmax(err / np.maximum(bound, 1e-300))
     # deterministic: the same call gives the same bits
     loss2, g2 = K.kpa_mlp_loss_grad(pt, x, y)
     torch.cuda.synchronize()

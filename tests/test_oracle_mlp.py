@@ -87,3 +87,67 @@ def test_training_lowers_loss_on_skewed_cdf():
     l1, _ = mlp.loss_grad(p, x, y)
     assert l1 < 0.2 * l0
     assert np.all(p[mlp.weight_mask() > 0] >= 0)
+
+
+def _hand_net(w3, b3):
+    """h1 = ramp(4x - 1), ramp(2x); h2[o] = ramp(h1[1-o]); f = w3 . h2 + b3."""
+    H = mlp.H
+    W1 = np.zeros(H); b1 = np.zeros(H)
+    W2 = np.zeros((H, H)); b2 = np.zeros(H)
+    W3 = np.zeros(H)
+    W1[0], b1[0] = 4.0, -1.0
+    W1[1] = 2.0
+    W2[0, 1] = 1.0
+    W2[1, 0] = 1.0
+    W3[0], W3[1] = w3
+    return mlp.pack(W1, b1, W2, b2, W3, b3)
+
+
+def test_to_pwl_knots_hand_computed():
+    """Knots on the grid x_j = j/4 of two hand-built networks, worked by hand.
+
+    Net A, f = 0.8*ramp(2x) - 0.6*ramp(4x - 1) - 0.2:
+      x = 0: -0.2 -> clamp 0;  x = 1/4: 0.8*0.5 - 0 - 0.2 = 0.2;
+      x = 1/2: 0.8 - 0.6 - 0.2 = 0 -> running max 0.2;  x = 3/4, 1: 0 -> 0.2.
+    Net B, f = 0.5*ramp(2x) + 0.25*ramp(4x - 1) + 0.125:
+      0.125, 0.375, 0.875, 0.875, 0.875 (both ramps saturate at x = 1/2).
+    A grid of j/5 (x = 0.2: net B gives 0.325) or a missing running maximum
+    (net A would give 0 at x = 1/2) changes a knot.
+    """
+    ka = mlp.to_pwl(_hand_net((0.8, -0.6), -0.2), n_knots=5)
+    assert np.allclose(ka, [0.0, 0.2, 0.2, 0.2, 0.2], rtol=0, atol=1e-15)
+    kb = mlp.to_pwl(_hand_net((0.5, 0.25), 0.125), n_knots=5)
+    assert np.allclose(kb, [0.125, 0.375, 0.875, 0.875, 0.875], rtol=0, atol=1e-15)
+    # clamp at the top: f = 3*ramp(2x) -> 0, 1, 1, 1, 1 after clamping
+    kc = mlp.to_pwl(_hand_net((3.0, 0.0), 0.0), n_knots=5)
+    assert np.allclose(kc, [0.0, 1.0, 1.0, 1.0, 1.0], rtol=0, atol=1e-15)
+
+
+def test_to_pwl_default_grid_is_1024_segments():
+    """1025 knots at x_j = j/1024: net B's knot at j = 100 is
+    0.5*ramp(200/1024) + 0.25*ramp(400/1024 - 1) + 0.125 = 0.5*0.1953125 + 0.125."""
+    k = mlp.to_pwl(_hand_net((0.5, 0.25), 0.125))
+    assert k.shape == (1025,)
+    assert k[100] == 0.5 * (200 / 1024) + 0.125
+    assert k[256] == 0.5 * 0.5 + 0.125          # 4x - 1 = 0 exactly at x = 1/4
+    assert k[1024] == 0.875
+
+
+def test_gradient_bound_covers_float32_kernel_order():
+    """The derived per-element bound on the float32 gradient (tests/mlp_bound.py)
+    holds for a numpy float32 emulation of the kernel's order of operations,
+    and it is not vacuous: the bound stays a small multiple of the observed
+    error and far below the gradient's scale."""
+    from mlp_bound import float32_grad, grad_bound
+    rng = np.random.default_rng(11)
+    for m in (1, 255, 1000, 4096):
+        p = mlp.init_params(rng.random(mlp.N_PARAMS)).astype(np.float32).astype(np.float64)
+        x = np.sort(rng.random(m) ** 3).astype(np.float32).astype(np.float64)
+        y = (np.arange(m) / m).astype(np.float32).astype(np.float64)
+        _, g64 = mlp.loss_grad(p, x, y)
+        g32 = float32_grad(p, x, y)
+        b, amb = grad_bound(p, x, y)
+        err = np.abs(g32 - g64)
+        assert np.all(err <= b), (m, np.max(err / np.maximum(b, 1e-300)))
+        scale = np.max(np.abs(g64))
+        assert np.max(b) < 1e-3 * scale, (m, np.max(b) / scale)
