@@ -92,15 +92,22 @@ def _ptr(a: np.ndarray):
 def _u64a(x):
     if hasattr(x, "detach"):
         x = x.detach().cpu().numpy()
+    if isinstance(x, (list, tuple)):
+        # Python ints at or above 2^63 would become float64 under np.asarray
+        return np.array([int(v) for v in x], dtype=np.uint64)
     x = np.asarray(x)
     if x.dtype == np.int64:
         x = x.view(np.uint64)
+    if x.dtype.kind == "f":
+        raise TypeError("u64 arrays must be integers (floats would round)")
     return np.ascontiguousarray(x, dtype=np.uint64)
 
 
 def _u32a(x):
     if hasattr(x, "detach"):
         x = x.detach().cpu().numpy()
+    if isinstance(x, (list, tuple)):
+        return np.array([int(v) for v in x], dtype=np.uint32)
     x = np.asarray(x)
     if x.dtype == np.int32:
         x = x.view(np.uint32)
