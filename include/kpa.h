@@ -28,8 +28,10 @@
  *    different streams must not share a workspace.
  *  - Alignment: keys/u64 arrays 8-byte aligned, rids 4-byte aligned, row
  *    arenas 16-byte aligned, otherwise KPA_EINVAL.
- *  - Sizes: n = 0 is a valid no-op.  A single KPA or segment holds fewer than
- *    2^30 entries (KPA_EUNSUPPORTED otherwise); rids are 32-bit.
+ *  - Sizes: n = 0 is a valid no-op.  A KPA holds fewer than 2^32 entries
+ *    (rids are 32-bit).  A segment that a sort or keyed operation works on
+ *    holds fewer than 2^30 entries: a larger sort segment is copied through
+ *    unsorted and counted in kpa_sort_stats.unsupported_entries.
  *  - Keys are unsigned 64-bit and compared as unsigned.
  *  - Sums and products wrap modulo 2^64.
  */
@@ -71,6 +73,9 @@ typedef struct kpa_row_layout {
 int32_t kpa_version(void);
 /* Message of the last failing call on this thread ("" if none). */
 const char* kpa_last_error_string(void);
+/* The HIP error code behind the last KPA_EHIP status on this thread
+ * (hipSuccess if the last failure was not a HIP error). */
+int32_t kpa_last_hip_error(void);
 /* Sets *out to 1 if the current HIP device is gfx950, else 0. */
 kpa_status kpa_device_check(int32_t* out);
 
@@ -105,7 +110,7 @@ kpa_status kpa_extract(const void* rows, uint64_t n, const kpa_row_layout* layou
  * written back to back into out_keys/out_rids (device, capacity n each);
  * out_win_off (device, n_win+1 u64) receives the start of each window and the
  * total.  Rows outside all windows are not written; their number goes to
- * *out_oob (device u64).  1 <= n_win <= 256, win_len >= 1.
+ * *out_oob (device u64).  1 <= n_win <= 256, win_len >= 1, n < 2^32.
  * out_vals (device, n u64, may be NULL): the value column (layout->val_off,
  * zero-extended) of every row in arrival order, out_vals[i] for row i.  It is
  * a compact copy of one nonresident column: a keyed reduction can read its
@@ -117,6 +122,15 @@ kpa_status kpa_partition_windows(const void* rows, uint64_t n, const kpa_row_lay
                                  uint32_t rid_base, uint64_t* out_keys, uint32_t* out_rids,
                                  uint64_t* out_vals, uint64_t* out_win_off, uint64_t* out_oob,
                                  void* ws, size_t ws_bytes, hipStream_t stream);
+/* Partition of a KPA whose resident key is the timestamp (Table 2 Partition;
+ * the Window operator of the pipeline example partitions KPA(t)): entry i
+ * (keys[i], rids[i]) goes to the window of keys[i] (window rule as above),
+ * stably; out_keys/out_rids/out_win_off/out_oob as above.  n < 2^32.
+ * Workspace: kpa_partition_windows_workspace_size(n, n_win). */
+kpa_status kpa_partition_kpa(const uint64_t* keys, const uint32_t* rids, uint64_t n,
+                             uint64_t win_len, uint64_t win_origin, uint32_t n_win,
+                             uint64_t* out_keys, uint32_t* out_rids, uint64_t* out_win_off,
+                             uint64_t* out_oob, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Sort (Table 2: KPA(c) -> KPA(c), sequential access).  Stable sort by key:
@@ -166,6 +180,8 @@ typedef struct kpa_sort_stats {
   uint64_t fallback_entries;   /* entries re-sorted by the radix path */
   uint64_t fallback_buckets;   /* buckets re-sorted by the radix path */
   uint64_t order_violations;   /* buckets whose key range overlapped a neighbour */
+  uint64_t unsupported_entries; /* entries of segments of 2^30 or more entries: copied
+                                   through unsorted (the caller must check this) */
 } kpa_sort_stats;
 
 kpa_status kpa_sort_workspace_size(uint64_t n_cap, uint32_t n_seg, kpa_sort_algo algo,
@@ -267,7 +283,7 @@ kpa_status kpa_merge_runs(uint64_t* keys, uint32_t* rids, const uint64_t* run_of
                           size_t ws_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
- * Keyed reduction (Table 2; Sec. 4.1 per-key aggregation: scan a sorted KPA,
+ * Keyed reduction (Table 2; Sec. 4.2 keyed aggregation: scan a sorted KPA,
  * follow the pointers, coalesce a nonresident column over each run of equal
  * keys).  Input: a KPA sorted by key within each segment (segments as in
  * kpa_sort_segmented); rows: device arena of full records (the rids index it).
@@ -336,6 +352,130 @@ kpa_status kpa_join(const uint64_t* lk, const uint32_t* lr, const uint64_t* l_se
  * rows[rids[i]] (row_bytes each).  All device. */
 kpa_status kpa_materialize(const uint32_t* rids, uint64_t n, const void* rows, uint32_t row_bytes,
                            void* out_rows, hipStream_t stream);
+
+/* Materialize coalesced with Extract (Sec. 4.3, first optimization: as a
+ * primitive emits rows it extracts the KPA the next operator needs): out_rows
+ * as kpa_materialize, and from each emitted row the next KPA on the u64
+ * column at key_off: out_keys[i] = that column of out_rows row i, out_rids[i]
+ * = rid_base + i (pointers into out_rows).  All device; row_bytes a multiple
+ * of 8 in [8, 256]; key_off 8-aligned. */
+kpa_status kpa_materialize_extract(const uint32_t* rids, uint64_t n, const void* rows,
+                                   uint32_t row_bytes, uint32_t key_off, uint32_t rid_base,
+                                   void* out_rows, uint64_t* out_keys, uint32_t* out_rids,
+                                   hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * KeySwap (Table 2: KPA(c1) -> KPA(c2), random access): out_keys[i] = the
+ * column of width col_w (4 or 8, zero-extended) at col_off of row rids[i].
+ * The rids stay as they are, so (out_keys, rids) is the KPA on the new
+ * column.  All device.  out_keys may be the old key array. */
+kpa_status kpa_keyswap(const uint32_t* rids, uint64_t n, const void* rows, uint32_t row_bytes,
+                       uint32_t col_off, uint32_t col_w, uint64_t* out_keys, hipStream_t stream);
+
+/* In-place update of resident keys (Sec. 4.3, second optimization; the
+ * external join of the pipeline example, which replaces each key by the value
+ * a small key-value table in device memory holds for it): every keys[i] found
+ * among table_keys is replaced by the matching table_vals entry; keys not in
+ * the table are left as they are and counted in *out_missing (device u64,
+ * set by the call).  table_keys (device, table_n) must be ascending and
+ * distinct (otherwise the result is unspecified); tables of up to 2048
+ * entries are searched in on-chip memory. */
+kpa_status kpa_key_update(uint64_t* keys, uint64_t n, const uint64_t* table_keys,
+                          const uint64_t* table_vals, uint64_t table_n, uint64_t* out_missing,
+                          hipStream_t stream);
+
+/* Write-back of dirty resident keys (Sec. 4.3, second optimization): the u64
+ * column at col_off (8-aligned) of row rids[i] becomes keys[i], so that later
+ * KeySwap and Materialize read the updated value.  rows: device, written.
+ * Distinct rids write distinct rows; for repeated rids one of the writes
+ * wins. */
+kpa_status kpa_key_writeback(const uint64_t* keys, const uint32_t* rids, uint64_t n, void* rows,
+                             uint32_t row_bytes, uint32_t col_off, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Select (Table 2: KPA -> KPA, keep the pairs that pass; ParDo filters run as
+ * Select, Sec. 4.2).  For every segment s (segments as in kpa_sort_segmented)
+ * entry i passes when
+ *     x_i * den[s]  <op>  num[s]
+ * with x_i the resident key (KPA_SEL_KEY) or the value column of its row
+ * (KPA_SEL_VALUE, layout->val_off/val_w), the product taken exactly in 128
+ * bits and num[s] = num_lo[s] + 2^64 * num_hi[s].  num_hi (NULL: 0) and den
+ * (NULL: 1) are optional; with den = 1 and num_hi = 0 this is a plain
+ * threshold, and a ratio threshold such as an average sum/count is compared
+ * without rounding.  Survivors keep their order and are written back to back
+ * (segment after segment) to out_keys/out_rids (device, n_cap each);
+ * out_seg_off (device, n_seg+1) receives where each segment's survivors begin
+ * and the total.  rows may be NULL for KPA_SEL_KEY. */
+typedef enum kpa_select_column { KPA_SEL_KEY = 0, KPA_SEL_VALUE = 1 } kpa_select_column;
+typedef enum kpa_select_op {
+  KPA_SEL_GT = 0, KPA_SEL_GE = 1, KPA_SEL_LT = 2, KPA_SEL_LE = 3, KPA_SEL_EQ = 4, KPA_SEL_NE = 5
+} kpa_select_op;
+kpa_status kpa_select_workspace_size(uint64_t n_cap, uint32_t n_seg, size_t* bytes);
+kpa_status kpa_select(const uint64_t* keys, const uint32_t* rids, const uint64_t* seg_off,
+                      uint32_t n_seg, uint64_t n_cap, const void* rows,
+                      const kpa_row_layout* layout, kpa_select_column column, kpa_select_op op,
+                      const uint64_t* num_lo, const uint64_t* num_hi, const uint64_t* den,
+                      uint64_t* out_keys, uint32_t* out_rids, uint64_t* out_seg_off, void* ws,
+                      size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Unkeyed reduction over windows (Table 2 "Unkeyed reduction"; Sec. 6
+ * "Windowed Average All"): one pass over the rows; for each window w (window
+ * rule as kpa_partition_windows) out_cnt[w] = rows in the window,
+ * out_sum_lo[w] + 2^64 * out_sum_hi[w] = the exact sum of their values (a
+ * 128-bit integer, so the average sum/count can be taken without overflow),
+ * out_max[w] = the largest value; *out_oob = rows outside all windows.  Any
+ * output may be NULL.  1 <= n_win <= 256, n < 2^32.  All device. */
+kpa_status kpa_reduce_all_windows_workspace_size(uint32_t n_win, size_t* bytes);
+kpa_status kpa_reduce_all_windows(const void* rows, uint64_t n, const kpa_row_layout* layout,
+                                  uint64_t win_len, uint64_t win_origin, uint32_t n_win,
+                                  uint64_t* out_cnt, uint64_t* out_sum_lo, uint64_t* out_sum_hi,
+                                  uint64_t* out_max, uint64_t* out_oob, void* ws, size_t ws_bytes,
+                                  hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Per-key order statistics of the values (Sec. 6 benchmarks "TopK Per Key"
+ * and "Unique Count Per Key"), on a KPA sorted by key within segments, rows
+ * reached through the rids.  Groups as in kpa_reduce_by_key (out_gkey,
+ * out_gseg_off: device, capacity n_cap and n_seg+1).
+ * kpa_topk_per_key: per group g, out_gcnt[g] = its entries, out_gstart[g] =
+ * the index of its first entry, and its min(k, count) largest values in
+ * descending order at out_topv[out_gstart[g] + j], j < min(k, count) (equal
+ * values repeat; out_topv: device, n_cap u64, other slots untouched).
+ * 1 <= k <= 16.
+ * kpa_unique_count_by_key: out_uniq[g] = the number of distinct values of the
+ * group.
+ * Runs longer than 4096 entries are sorted by value through the radix sort's
+ * passes (a run of 2^30 or more entries is not supported). */
+kpa_status kpa_run_stats_workspace_size(uint64_t n_cap, uint32_t n_seg, size_t* bytes);
+kpa_status kpa_topk_per_key(const uint64_t* keys, const uint32_t* rids, const uint64_t* seg_off,
+                            uint32_t n_seg, uint64_t n_cap, const void* rows,
+                            const kpa_row_layout* layout, uint32_t k, uint64_t* out_gkey,
+                            uint64_t* out_gcnt, uint64_t* out_gstart, uint64_t* out_topv,
+                            uint64_t* out_gseg_off, void* ws, size_t ws_bytes,
+                            hipStream_t stream);
+kpa_status kpa_unique_count_by_key(const uint64_t* keys, const uint32_t* rids,
+                                   const uint64_t* seg_off, uint32_t n_seg, uint64_t n_cap,
+                                   const void* rows, const kpa_row_layout* layout,
+                                   uint64_t* out_gkey, uint64_t* out_uniq, uint64_t* out_gseg_off,
+                                   void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Sliding windows (Sec. 4.2 "Windowing": a sliding window is built from
+ * partitions whose range is the slide length).  With the rows partitioned into
+ * panes of one slide each, sorted and reduced per pane (gkey, gseg_off as
+ * produced by kpa_reduce_by_key over n_pane segments), window w of length
+ * panes_per_window slides covers panes w .. w+panes_per_window-1;
+ * n_win = n_pane - panes_per_window + 1 <= 65535.  Writes, window after
+ * window, the concatenation of those panes' groups as a KPA of (group key,
+ * group index): out_keys/out_rids (device, out_cap), out_seg_off (device,
+ * n_win+1; the last entry is the total, possibly above out_cap, in which case
+ * only the first out_cap entries are written).  Sorting each window's
+ * segment and reducing it with the pane groups' count, sum and max columns as
+ * values gives the sliding window's aggregates. */
+kpa_status kpa_window_panes(const uint64_t* gkey, const uint64_t* gseg_off, uint32_t n_pane,
+                            uint32_t panes_per_window, uint64_t* out_keys, uint32_t* out_rids,
+                            uint64_t* out_seg_off, uint64_t out_cap, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * CDF models for the learned-splitter sort.

@@ -287,8 +287,9 @@ kpa_status batch_launch(const u64* keys_in, const u32* rids_in, u64* keys_out, u
   if (cfg->large_algo == KPA_SORT_LEARNED)
     return learned_sort_launch(keys_in, rids_in, keys_out, rids_out, large, models, stats, w.lw,
                                st);
-  if (stats) KPA_CHECK(launch_fill_u64(reinterpret_cast<u64*>(stats), 6, 0, st));
-  return radix_sort_launch(keys_in, rids_in, keys_out, rids_out, large, w.rw, st);
+  if (stats) KPA_CHECK(launch_fill_u64(reinterpret_cast<u64*>(stats), STATS_WORDS, 0, st));
+  return radix_sort_launch(keys_in, rids_in, keys_out, rids_out, large, w.rw, st,
+                           stats_unsupported(stats));
 }
 
 kpa_status check_args(const uint64_t* keys_in, const uint32_t* rids_in, uint64_t* keys_out,

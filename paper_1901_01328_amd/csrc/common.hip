@@ -7,14 +7,20 @@
 namespace kpa {
 
 static thread_local char g_err[512] = "";
+static thread_local int g_hip_err = 0;
 
 void set_error(const char* fmt, ...) {
   va_list ap;
   va_start(ap, fmt);
   vsnprintf(g_err, sizeof(g_err), fmt, ap);
   va_end(ap);
+  g_hip_err = 0;
 }
-void clear_error() { g_err[0] = 0; }
+void set_hip_error(int code) { g_hip_err = code; }
+void clear_error() {
+  g_err[0] = 0;
+  g_hip_err = 0;
+}
 
 kpa_status check_layout(const kpa_row_layout* L, bool need_val, bool need_ts) {
   KPA_REQUIRE(L != nullptr, KPA_EINVAL, "layout is null");
@@ -170,6 +176,8 @@ extern "C" {
 int32_t kpa_version(void) { return 10000; }
 
 const char* kpa_last_error_string(void) { return kpa::g_err; }
+
+int32_t kpa_last_hip_error(void) { return kpa::g_hip_err; }
 
 kpa_status kpa_device_check(int32_t* out) {
   KPA_REQUIRE(out != nullptr, KPA_EINVAL, "out is null");

@@ -29,6 +29,7 @@ struct DigitSortBufs {
   u32* counters;    // [p]: tile claims of pass p; [15]: passes needed by any segment
   u64 max_tiles;
   OrderBufs order;
+  u64* unsupported;  // may be null: entries of segments too large to sort (copied through)
 };
 
 __device__ __forceinline__ void seg_tile_range(const SegList& sl, const u32* tile_start,
@@ -158,7 +159,8 @@ __global__ void __launch_bounds__(BLOCK) k_ds_prepare(SegList sl, const u32* __r
 // passes whose digit varies within the segment.
 template <class DF>
 __global__ void __launch_bounds__(BLOCK) k_ds_scan(SegList sl, u32* __restrict__ hist,
-                                                   u32* __restrict__ seg_mask) {
+                                                   u32* __restrict__ seg_mask,
+                                                   u64* __restrict__ unsupported) {
   __shared__ u32 sc[WAVES + 1];
   const u32 n_seg = sl.n();
   for (u32 s = blockIdx.x; s < n_seg; s += gridDim.x) {
@@ -174,8 +176,13 @@ __global__ void __launch_bounds__(BLOCK) k_ds_scan(SegList sl, u32* __restrict__
       if (!constant) mask |= 1u << p;
     }
     // Segments of 2^30 or more entries exceed the look-back word; they are
-    // left untouched (mask bit 31) rather than sorted wrongly.
-    if (threadIdx.x == 0) seg_mask[s] = n >= MAX_SEG_ENTRIES ? SEG_UNSUPPORTED : mask;
+    // copied through unsorted (mask bit 31) and counted, rather than sorted
+    // wrongly.
+    if (threadIdx.x == 0) {
+      seg_mask[s] = n >= MAX_SEG_ENTRIES ? SEG_UNSUPPORTED : mask;
+      if (n >= MAX_SEG_ENTRIES && unsupported)
+        atomicAdd(reinterpret_cast<unsigned long long*>(unsupported), (unsigned long long)n);
+    }
     __syncthreads();
   }
 }
@@ -301,10 +308,10 @@ __device__ __forceinline__ TileDesc uniform_desc(const TileDesc& d) {
 }
 
 // Per-pass claim lists: a tile is sorted in pass p when its segment's digit
-// p varies; pass 0 also takes the segments that need no pass (they are
-// copied), and unsupported segments are in no list.
+// p varies; pass 0 also takes the segments that need no pass and the
+// unsupported ones (both are copied).
 __device__ __forceinline__ bool in_pass(u32 mask, u32 p) {
-  if (mask & SEG_UNSUPPORTED) return false;
+  if (mask & SEG_UNSUPPORTED) return p == 0;
   return ((mask >> p) & 1u) || (p == 0 && mask == 0);
 }
 
@@ -316,10 +323,11 @@ __global__ void __launch_bounds__(LIST_BLK) k_ds_lcount(const u32* __restrict__ 
                                                         u32* __restrict__ lcount, u32 nblk) {
   const u32 total = tile_start[sl.n()];
   const u32 c = blockIdx.x * LIST_BLK + threadIdx.x;
-  const u32 mask = c < total ? desc[c].mask : SEG_UNSUPPORTED;
+  const bool have = c < total;  // claim slots past the last tile are in no list
+  const u32 mask = have ? desc[c].mask : 0u;
 #pragma unroll
   for (int p = 0; p < PASSES; ++p) {
-    const int cnt = __syncthreads_count(in_pass(mask, p));
+    const int cnt = __syncthreads_count(have && in_pass(mask, p));
     if (threadIdx.x == 0) lcount[(u64)p * (nblk + 1) + blockIdx.x] = (u32)cnt;
   }
 }
@@ -355,10 +363,11 @@ __global__ void __launch_bounds__(LIST_BLK) k_ds_lfill(const u32* __restrict__ t
   __shared__ u32 sm[17];
   const u32 total = tile_start[sl.n()];
   const u32 c = blockIdx.x * LIST_BLK + threadIdx.x;
-  const u32 mask = c < total ? desc[c].mask : SEG_UNSUPPORTED;
+  const bool have = c < total;  // claim slots past the last tile are in no list
+  const u32 mask = have ? desc[c].mask : 0u;
 #pragma unroll
   for (int p = 0; p < PASSES; ++p) {
-    const bool in = in_pass(mask, p);
+    const bool in = have && in_pass(mask, p);
     u32 tot;
     const u32 ex = block_excl_sum<16>(in ? 1u : 0u, sm, &tot);
     if (in) lists[(u64)p * max_tiles + lcount[(u64)p * (nblk + 1) + blockIdx.x] + ex] = c;
@@ -416,7 +425,7 @@ __global__ void __launch_bounds__(PASS_THREADS, PASS_WAVES / 2)
       const u32 k = first_lane(sm.tile);  // uniform: scalar loads below
       if (k >= nlist) return false;
       td = uniform_desc(bf.order.desc[full ? k : first_lane(list[k])]);
-      if (td.mask == 0) {
+      if (td.mask == 0 || (td.mask & SEG_UNSUPPORTED)) {
         if (bf.keys_in != bf.keys_out) {
           for (u32 i = tid; i < td.cnt; i += PASS_THREADS) {
             bf.keys_out[td.base + i] = bf.keys_in[td.base + i];
@@ -523,7 +532,8 @@ kpa_status digit_sort_launch(const SegList& sl, const typename DF::Params& prm,
     KPA_LAUNCH(radix ? "radix_hist" : "learned_hist", k_ds_hist<DF>, dim3(hist_blocks),
                dim3(BLOCK), 0, st, b.keys_in, sl, b.tile_start, prm, b.hist);
     KPA_LAUNCH(radix ? "radix_scan" : "learned_scan", k_ds_scan<DF>,
-               dim3(std::min<u32>(sl.n_max, 2048)), dim3(BLOCK), 0, st, sl, b.hist, b.seg_mask);
+               dim3(std::min<u32>(sl.n_max, 2048)), dim3(BLOCK), 0, st, sl, b.hist, b.seg_mask,
+               b.unsupported);
   }
   const dim3 seg_grid((u32)std::min<u64>(ceil_div(std::max<u32>(sl.n_max, 1), BLOCK), 1024));
   KPA_LAUNCH("sort_count", k_ds_count<0>, seg_grid, dim3(BLOCK), 0, st, sl, b.tile_start,

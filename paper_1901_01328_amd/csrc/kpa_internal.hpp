@@ -19,6 +19,7 @@ namespace kpa {
 // ----------------------------------------------------------------- errors --
 void set_error(const char* fmt, ...);
 void clear_error();
+void set_hip_error(int code);  // the HIP error behind the next KPA_EHIP
 
 #define KPA_REQUIRE(cond, code, ...) \
   do {                               \
@@ -34,6 +35,7 @@ void clear_error();
     if (e_ != hipSuccess) {                                                            \
       ::kpa::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, \
                        __LINE__);                                                      \
+      ::kpa::set_hip_error((int)e_);                                                   \
       return KPA_EHIP;                                                                 \
     }                                                                                  \
   } while (0)
@@ -44,6 +46,7 @@ void clear_error();
     if (e_ != hipSuccess) {                                                                  \
       ::kpa::set_error("kernel launch failed: %s (%s:%d)", hipGetErrorString(e_), __FILE__, \
                        __LINE__);                                                            \
+      ::kpa::set_hip_error((int)e_);                                                         \
       return KPA_EHIP;                                                                       \
     }                                                                                        \
   } while (0)

@@ -213,8 +213,11 @@ __global__ void __launch_bounds__(BLOCK) k_learned_setup(const kpa_pwl_model* __
       m.scale = (ok && m.hspan) ? (float)nseg / (float)m.hspan : 0.0f;
       m.valid = ok ? 1u : 0u;
       m.knots = M.knots;
+      // A segment too large for the look-back words keeps one bucket: it goes
+      // to the pivot rounds and the radix path whole (which copies what stays
+      // too large through and counts it).
       u32 bits = 0;
-      if (ok && n > FCAP) {
+      if (ok && n > FCAP && n < MAX_SEG_ENTRIES) {
         const u64 want = (n + BUCKET_TARGET - 1) / BUCKET_TARGET;
         while (bits < MAX_BUCKET_BITS && (1ull << bits) < want) ++bits;
       }
@@ -1248,7 +1251,7 @@ kpa_status learned_sort_launch(const u64* keys_in, const u32* rids_in, u64* keys
                                u32* rids_out, const SegList& sl, const kpa_pwl_model* models,
                                kpa_sort_stats* stats, const LearnedWs& lw, hipStream_t st) {
   const u32 n_seg = sl.n_max;
-  if (stats) KPA_CHECK(launch_fill_u64(reinterpret_cast<u64*>(stats), 6, 0, st));
+  if (stats) KPA_CHECK(launch_fill_u64(reinterpret_cast<u64*>(stats), STATS_WORDS, 0, st));
   KPA_CHECK(launch_fill_u32(lw.fb_count, 1, 0, st));
   KPA_CHECK(launch_fill_u32(lw.rl_count, 4, 0, st));
   KPA_CHECK(launch_seg_tiles_list(sl, TILE, lw.ltile_start, st));
@@ -1315,7 +1318,8 @@ kpa_status learned_sort_launch(const u64* keys_in, const u32* rids_in, u64* keys
                             max_tiles(lw.n_cap, lw.max_fb, TILE), lw.fb_tile_seg, st));
   KPA_LAUNCH("fallback_copy", k_fb_copy_all, dim3(2048), dim3(BLOCK), 0, st, keys_out, rids_out,
              rl, lw.fb_tile_start, lw.fb_tile_seg, lw.keys_tmp, lw.rids_tmp);
-  return radix_sort_launch(lw.keys_tmp, lw.rids_tmp, keys_out, rids_out, rl, lw.fb_radix, st);
+  return radix_sort_launch(lw.keys_tmp, lw.rids_tmp, keys_out, rids_out, rl, lw.fb_radix, st,
+                           stats_unsupported(stats));
 }
 
 }  // namespace kpa

@@ -2,15 +2,25 @@
 // timestamp column, the window length being the range of each partition).
 //
 // Two passes over the rows:
-//   1. histogram of window ids (plus out-of-range rows) into global counters;
+//   1. histogram of window ids (plus out-of-range rows) into global counters,
+//      one histogram per chunk of 2^29 rows;
 //   2. a single onesweep scatter pass with digit = window id, which reads the
 //      key and timestamp of each row and writes (key, rid) into its window.
 // The scatter is stable, so each window lists its rows in arrival order.
+// The look-back words hold 30-bit counts, so the tiles of each chunk form
+// their own look-back chain and start from the chunk's window offsets (the
+// windows' starts plus the rows of earlier chunks): any n below 2^32 works.
+//
+// The same kernels partition a KPA whose resident key is the timestamp
+// (rows = the key array read as 8-byte rows, rids taken from the KPA).
 #include "digit_sort.hpp"
 
 namespace kpa {
 
 constexpr u32 PART_HIST_ROWS = 1u << 16;  // rows per histogram workgroup
+constexpr u32 PART_CHUNK_LOG2 = 29;       // rows per look-back chain: 2^29
+constexpr u32 PART_CHUNK_TILES = (1u << PART_CHUNK_LOG2) / TILE;
+static_assert(((1u << PART_CHUNK_LOG2) % PART_HIST_ROWS) == 0, "histogram blocks inside chunks");
 
 struct WinParams {
   u64 origin;
@@ -93,6 +103,7 @@ __global__ void __launch_bounds__(BLOCK) k_part_hist(const unsigned char* __rest
   __syncthreads();
   const u64 r0 = (u64)blockIdx.x * PART_HIST_ROWS;
   const u64 r1 = min(n, r0 + PART_HIST_ROWS);
+  counts += (r0 >> PART_CHUNK_LOG2) * (RADIX + 1);
   for (u64 b = r0; b < r1; b += (u64)BLOCK * PART_HIST_U) {
     u64 ts[PART_HIST_U], vv[PART_HIST_U];
 #pragma unroll
@@ -125,20 +136,45 @@ __global__ void __launch_bounds__(BLOCK) k_part_hist(const unsigned char* __rest
   }
 }
 
-// counts -> exclusive window offsets (u32 for the scatter, u64 for the caller).
-__global__ void __launch_bounds__(BLOCK) k_part_scan(u32* __restrict__ counts, u32 n_win,
+// counts (per chunk) -> exclusive window offsets (u64 for the caller) and,
+// per chunk, where each window's rows of that chunk begin (u32, the
+// scatter's bases: n < 2^32).
+__global__ void __launch_bounds__(BLOCK) k_part_scan(const u32* __restrict__ counts,
+                                                     u32 n_chunks, u32 n_win,
+                                                     u32* __restrict__ woff,
                                                      u64* __restrict__ win_off,
                                                      u64* __restrict__ oob) {
-  __shared__ u32 sc[WAVES + 1];
-  const u32 tid = threadIdx.x;
-  const u32 c = tid < n_win ? counts[tid] : 0u;
-  u32 tot;
-  const u32 ex = block_excl_sum(c, sc, &tot);
-  counts[tid] = ex;
-  if (tid < n_win) win_off[tid] = ex;
+  __shared__ u64 sc[WAVES + 1];
+  const u32 tid = threadIdx.x, lane = __lane_id(), w = tid >> 6;
+  u64 c = 0;
+  if (tid < n_win)
+    for (u32 k = 0; k < n_chunks; ++k) c += counts[k * (RADIX + 1) + tid];
+  u64 incl = c;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const u64 t = __shfl_up(incl, o, 64);
+    if (lane >= (u32)o) incl += t;
+  }
+  if (lane == 63) sc[w] = incl;
+  __syncthreads();
+  u64 ex = incl - c, tot = 0;
+  for (u32 i = 0; i < WAVES; ++i) {
+    if (i < w) ex += sc[i];
+    tot += sc[i];
+  }
+  if (tid < n_win) {
+    win_off[tid] = ex;
+    u64 run = ex;
+    for (u32 k = 0; k < n_chunks; ++k) {
+      woff[k * RADIX + tid] = (u32)run;
+      run += counts[k * (RADIX + 1) + tid];
+    }
+  }
   if (tid == 0) {
     win_off[n_win] = tot;
-    *oob = counts[RADIX];
+    u64 o = 0;
+    for (u32 k = 0; k < n_chunks; ++k) o += counts[k * (RADIX + 1) + RADIX];
+    *oob = o;
   }
 }
 
@@ -148,7 +184,8 @@ __global__ void __launch_bounds__(BLOCK) k_part_scan(u32* __restrict__ counts, u
 // here and spills.)
 __global__ void __launch_bounds__(PASS_THREADS, PASS_WAVES / 2)
     k_part_pass(const unsigned char* __restrict__ rows, u64 n, u32 row_bytes, u32 key_off,
-                u32 ts_off, u32 ts_w, WinParams wp, u32 rid_base, const u32* __restrict__ woff,
+                u32 ts_off, u32 ts_w, WinParams wp, u32 rid_base,
+                const u32* __restrict__ rids_in, const u32* __restrict__ woff,
                 u32 n_tiles, u32* __restrict__ status, u32* __restrict__ counter,
                 u64* __restrict__ keys_out, u32* __restrict__ rids_out) {
   __shared__ OnesweepSmemT<PASS_WAVES> sm;
@@ -203,16 +240,18 @@ __global__ void __launch_bounds__(PASS_THREADS, PASS_WAVES / 2)
   load_ts_of(tile);
   load_keys_of(tile);
   u32 valid = digits(tile);
-  const u64 my_base = tid < wp.n_win ? (u64)woff[tid] : 0ull;
   while (true) {
+    const u32 chunk = tile / PART_CHUNK_TILES, t_in = tile % PART_CHUNK_TILES;
+    const u64 my_base = tid < wp.n_win ? (u64)woff[chunk * RADIX + tid] : 0ull;
 #pragma unroll
     for (int j = 0; j < PASS_ITEMS; ++j) {
-      rr[j] = rid_base + (u32)((u64)tile * TILE + tile_offset_t<PASS_WAVES>(j));
+      const u64 e = (u64)tile * TILE + tile_offset_t<PASS_WAVES>(j);
+      rr[j] = rids_in ? (e < n ? rids_in[e] : 0u) : rid_base + (u32)e;
       dd[j] = (dpk[j >> 2] >> (8 * (j & 3))) & 255u;
     }
     u32 tile_count;
-    const u32 cnt_d = onesweep_rank_stage(sm, kk, rr, dd, valid, status, tile, tile, &tile_count);
-    onesweep_lookback_write(sm, status, tile, tile, cnt_d, tile_count, my_base, keys_out,
+    const u32 cnt_d = onesweep_rank_stage(sm, kk, rr, dd, valid, status, tile, t_in, &tile_count);
+    onesweep_lookback_write(sm, status, tile, t_in, cnt_d, tile_count, my_base, keys_out,
                             rids_out);
     const u32 next = claim();
     if (next >= n_tiles) return;
@@ -225,17 +264,54 @@ __global__ void __launch_bounds__(PASS_THREADS, PASS_WAVES / 2)
 }
 
 struct PartWs {
-  u32* counts;  // RADIX + 1
+  u32* counts;  // per chunk: RADIX + 1 (windows, then out-of-range rows)
+  u32* woff;    // per chunk: RADIX window bases
   u32* counter;
   u32* status;
   u64 n_tiles;
+  u32 n_chunks;
 };
 
 static void part_plan(u64 n, Carver& c, PartWs* w) {
   w->n_tiles = ceil_div(n ? n : 1, TILE);
-  w->counts = c.take<u32>(RADIX + 1);
+  w->n_chunks = (u32)ceil_div(n ? n : 1, 1ull << PART_CHUNK_LOG2);
+  w->counts = c.take<u32>((u64)w->n_chunks * (RADIX + 1));
+  w->woff = c.take<u32>((u64)w->n_chunks * RADIX);
   w->counter = c.take<u32>(1);
   w->status = c.take<u32>(w->n_tiles * RADIX);
+}
+
+static kpa_status part_launch(const unsigned char* r, u64 n, u32 row_bytes, u32 key_off,
+                              u32 ts_off, u32 ts_w, u32 val_off, u32 val_w, u64 win_len,
+                              u64 win_origin, u32 n_win, u32 rid_base, const u32* rids_in,
+                              u64* out_keys, u32* out_rids, u64* out_vals, u64* out_win_off,
+                              u64* out_oob, const PartWs& w, hipStream_t stream) {
+  WinParams wp;
+  wp.origin = win_origin;
+  wp.win_len = win_len;
+  wp.n_win = n_win;
+  unsigned __int128 lim = (unsigned __int128)win_len * (n_win + 1);
+  wp.fast = lim < ((unsigned __int128)1 << 64) ? 1u : 0u;
+  wp.limit = wp.fast ? win_len * n_win : ~0ull;
+  wp.inv = 1.0 / (double)win_len;
+  wp.inv_f = 1.0f / (float)win_len;
+
+  KPA_CHECK(launch_fill_u32(w.counts, (u64)w.n_chunks * (RADIX + 1), 0, stream));
+  KPA_CHECK(launch_fill_u32(w.counter, 1, 0, stream));
+  KPA_CHECK(launch_fill_u32(w.status, w.n_tiles * RADIX, 0, stream));
+  if (n) {
+    KPA_LAUNCH("part_hist", k_part_hist, dim3((u32)ceil_div(n, PART_HIST_ROWS)), dim3(BLOCK), 0,
+               stream, r, n, row_bytes, ts_off, ts_w, wp, w.counts, val_off, val_w, out_vals);
+  }
+  KPA_LAUNCH("part_scan", k_part_scan, dim3(1), dim3(BLOCK), 0, stream, w.counts, w.n_chunks,
+             n_win, w.woff, out_win_off, out_oob);
+  if (n) {
+    const u32 grid = resident_grid(k_part_pass, (u32)w.n_tiles, PASS_THREADS);
+    KPA_LAUNCH("part_pass", k_part_pass, dim3(grid), dim3(PASS_THREADS), 0, stream, r, n,
+               row_bytes, key_off, ts_off, ts_w, wp, rid_base, rids_in, w.woff, (u32)w.n_tiles,
+               w.status, w.counter, out_keys, out_rids);
+  }
+  return KPA_OK;
 }
 
 }  // namespace kpa
@@ -266,8 +342,8 @@ kpa_status kpa_partition_windows(const void* rows, uint64_t n, const kpa_row_lay
   KPA_REQUIRE(n_win >= 1 && n_win <= RADIX, KPA_EUNSUPPORTED, "n_win must be in [1, 256]");
   KPA_REQUIRE(win_len >= 1, KPA_EINVAL, "win_len must be >= 1");
   KPA_REQUIRE(out_win_off && out_oob && ws, KPA_EINVAL, "null pointer");
-  KPA_REQUIRE(n < MAX_SEG_ENTRIES, KPA_EUNSUPPORTED, "n must be below 2^30");
-  KPA_REQUIRE(n + rid_base <= (1ull << 32), KPA_EUNSUPPORTED, "rids exceed 32 bits");
+  KPA_REQUIRE(n < (1ull << 32) && n + rid_base <= (1ull << 32), KPA_EUNSUPPORTED,
+              "n must be below 2^32 and rids must fit 32 bits");
   KPA_REQUIRE(n == 0 || (rows && out_keys && out_rids), KPA_EINVAL, "null pointer");
   KPA_REQUIRE(aligned(ws, 256) && aligned(out_win_off, 8) && aligned(out_oob, 8) &&
                   (n == 0 || (aligned(rows, 16) && aligned(out_keys, 8) && aligned(out_rids, 4))),
@@ -276,36 +352,33 @@ kpa_status kpa_partition_windows(const void* rows, uint64_t n, const kpa_row_lay
   PartWs w;
   part_plan(n, c, &w);
   KPA_REQUIRE(c.used <= ws_bytes, KPA_EWORKSPACE, "workspace too small: need %zu bytes", c.used);
+  return part_launch(static_cast<const unsigned char*>(rows), n, layout->row_bytes,
+                     layout->key_off, layout->ts_off, layout->ts_w, layout->val_off,
+                     layout->val_w, win_len, win_origin, n_win, rid_base, nullptr, out_keys,
+                     out_rids, out_vals, out_win_off, out_oob, w, stream);
+}
 
-  WinParams wp;
-  wp.origin = win_origin;
-  wp.win_len = win_len;
-  wp.n_win = n_win;
-  unsigned __int128 lim = (unsigned __int128)win_len * (n_win + 1);
-  wp.fast = lim < ((unsigned __int128)1 << 64) ? 1u : 0u;
-  wp.limit = wp.fast ? win_len * n_win : ~0ull;
-  wp.inv = 1.0 / (double)win_len;
-  wp.inv_f = 1.0f / (float)win_len;
-
-  KPA_CHECK(launch_fill_u32(w.counts, RADIX + 1, 0, stream));
-  KPA_CHECK(launch_fill_u32(w.counter, 1, 0, stream));
-  KPA_CHECK(launch_fill_u32(w.status, w.n_tiles * RADIX, 0, stream));
-  const auto* r = static_cast<const unsigned char*>(rows);
-  if (n) {
-    KPA_LAUNCH("part_hist", k_part_hist, dim3((u32)ceil_div(n, PART_HIST_ROWS)), dim3(BLOCK), 0,
-                       stream, r, n, layout->row_bytes, layout->ts_off, layout->ts_w, wp,
-                       w.counts, layout->val_off, layout->val_w, out_vals);
-  }
-  KPA_LAUNCH("part_scan", k_part_scan, dim3(1), dim3(BLOCK), 0, stream, w.counts, n_win, out_win_off,
-                     out_oob);
-  if (n) {
-    const u32 grid = resident_grid(k_part_pass, (u32)w.n_tiles, PASS_THREADS);
-    KPA_LAUNCH("part_pass", k_part_pass, dim3(grid), dim3(PASS_THREADS), 0, stream, r, n,
-                       layout->row_bytes, layout->key_off, layout->ts_off, layout->ts_w, wp,
-                       rid_base, w.counts, (u32)w.n_tiles, w.status, w.counter, out_keys,
-                       out_rids);
-  }
-  return KPA_OK;
+kpa_status kpa_partition_kpa(const uint64_t* keys, const uint32_t* rids, uint64_t n,
+                             uint64_t win_len, uint64_t win_origin, uint32_t n_win,
+                             uint64_t* out_keys, uint32_t* out_rids, uint64_t* out_win_off,
+                             uint64_t* out_oob, void* ws, size_t ws_bytes, hipStream_t stream) {
+  clear_error();
+  KPA_REQUIRE(n_win >= 1 && n_win <= RADIX, KPA_EUNSUPPORTED, "n_win must be in [1, 256]");
+  KPA_REQUIRE(win_len >= 1, KPA_EINVAL, "win_len must be >= 1");
+  KPA_REQUIRE(out_win_off && out_oob && ws, KPA_EINVAL, "null pointer");
+  KPA_REQUIRE(n < (1ull << 32), KPA_EUNSUPPORTED, "n must be below 2^32");
+  KPA_REQUIRE(n == 0 || (keys && rids && out_keys && out_rids), KPA_EINVAL, "null pointer");
+  KPA_REQUIRE(aligned(ws, 256) && aligned(out_win_off, 8) && aligned(out_oob, 8) &&
+                  (n == 0 || (aligned(keys, 8) && aligned(rids, 4) && aligned(out_keys, 8) &&
+                              aligned(out_rids, 4))),
+              KPA_EINVAL, "misaligned pointer");
+  Carver c(ws);
+  PartWs w;
+  part_plan(n, c, &w);
+  KPA_REQUIRE(c.used <= ws_bytes, KPA_EWORKSPACE, "workspace too small: need %zu bytes", c.used);
+  return part_launch(reinterpret_cast<const unsigned char*>(keys), n, 8, 0, 0, 8, 0, 8, win_len,
+                     win_origin, n_win, 0, rids, out_keys, out_rids, nullptr, out_win_off,
+                     out_oob, w, stream);
 }
 
 }  // extern "C"

@@ -97,10 +97,10 @@ kpa_status radix_sort_plan(u64 n_cap, u32 n_seg, Carver& c, RadixWs* w) {
 
 kpa_status radix_sort_launch(const u64* keys_in, const u32* rids_in, u64* keys_out,
                              u32* rids_out, const SegList& sl, const RadixWs& w,
-                             hipStream_t st) {
+                             hipStream_t st, u64* unsupported) {
   DigitSortBufs b{keys_in,    rids_in,       keys_out,   rids_out,  w.keys_tmp,
                   w.rids_tmp, w.hist,        w.seg_mask, w.tile_start, w.status0,
-                  w.status1,  w.counters,    w.max_tiles, w.order};
+                  w.status1,  w.counters,    w.max_tiles, w.order, unsupported};
   return digit_sort_launch<RadixDF>(sl, RadixDF::Params{}, b, st);
 }
 

@@ -1,4 +1,4 @@
-// Keyed reduction (Table 2; Sec. 4.1: scan a sorted KPA, follow the pointers
+// Keyed reduction (Table 2; Sec. 4.2 keyed aggregation: scan a sorted KPA, follow the pointers
 // and coalesce a nonresident column over each contiguous run of equal keys)
 // and top-k groups by sum.
 //
@@ -159,8 +159,6 @@ __global__ void __launch_bounds__(BLOCK) k_reduce_heads(const u64* __restrict__ 
 // cross a tile boundary are zeroed (those runs are accumulated with atomics
 // in pass 3), and the first tile of each segment gives the segment's first
 // group.
-constexpr u32 SCAN_TILES = 1024;
-
 __global__ void __launch_bounds__(SCAN_TILES) k_reduce_bsum(const u32* __restrict__ heads,
                                                             const u32* __restrict__ tile_start,
                                                             u32 n_seg, u64* __restrict__ bsum) {
@@ -219,7 +217,7 @@ __global__ void __launch_bounds__(SCAN_TILES) k_reduce_bapply(
   if (t >= n_tiles) return;
   const u64 g0 = bpre[blockIdx.x] + ex;
   gbase[t] = g0;
-  if (flags[t] & 1u) {
+  if (flags && (flags[t] & 1u)) {
     const u64 g = g0 + hd - 1;
     if (o_cnt) o_cnt[g] = 0;
     if (o_sum) o_sum[g] = 0;
@@ -334,6 +332,18 @@ __global__ void __launch_bounds__(BLOCK) k_reduce_main(
       }
     }
   }
+}
+
+kpa_status launch_tile_scan(const u32* counts, const u32* tile_start, const u32* tile_seg,
+                            u32 n_seg, u64 max_tiles, u64* bsum, u64* tbase, u64* seg_first,
+                            hipStream_t st) {
+  const u32 nb = (u32)ceil_div(max_tiles, SCAN_TILES);
+  KPA_LAUNCH("tile_scan", k_reduce_bsum, dim3(nb), dim3(SCAN_TILES), 0, st, counts, tile_start,
+             n_seg, bsum);
+  KPA_LAUNCH("tile_scan", k_reduce_btop, dim3(1), dim3(1024), 0, st, bsum, nb, n_seg, seg_first);
+  KPA_LAUNCH("tile_scan", k_reduce_bapply, dim3(nb), dim3(SCAN_TILES), 0, st, counts, nullptr,
+             tile_start, tile_seg, n_seg, bsum, tbase, seg_first, nullptr, nullptr, nullptr);
+  return KPA_OK;
 }
 
 void reduce_plan(u64 n_cap, u32 n_seg, Carver& c, ReduceWs* w) {

@@ -39,6 +39,15 @@ struct ReduceOut {
 };
 
 void reduce_plan(u64 n_cap, u32 n_seg, Carver& c, ReduceWs* w);
+
+// Exclusive prefix over the tiles of a tile map of per-tile counts (one u32
+// per tile): tbase[t] = sum of counts of tiles before t, seg_first[s] =
+// tbase of segment s's first tile, seg_first[n_seg] = the total.  bsum holds
+// ceil(max_tiles / 1024) u64.
+constexpr u32 SCAN_TILES = 1024;
+kpa_status launch_tile_scan(const u32* counts, const u32* tile_start, const u32* tile_seg,
+                            u32 n_seg, u64 max_tiles, u64* bsum, u64* tbase, u64* seg_first,
+                            hipStream_t st);
 kpa_status reduce_launch(const u64* keys, const u32* rids, const u64* seg_off, u32 n_seg,
                          const unsigned char* rows, const kpa_row_layout* L, bool need_val,
                          const ReduceOut& o, const ReduceWs& w, hipStream_t st);

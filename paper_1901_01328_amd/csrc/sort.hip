@@ -62,9 +62,10 @@ kpa_status kpa_sort_segmented(const uint64_t* keys_in, const uint32_t* rids_in,
   KPA_REQUIRE(c.used <= ws_bytes, KPA_EWORKSPACE, "workspace too small: need %zu bytes",
               c.used);
   if (algo == KPA_SORT_RADIX) {
+    if (stats) KPA_CHECK(launch_fill_u64(reinterpret_cast<u64*>(stats), STATS_WORDS, 0, stream));
     KPA_CHECK(radix_sort_launch(keys_in, rids_in, keys_out, rids_out,
-                                seg_list_from_offsets(seg_off, n_seg), rw, stream));
-    if (stats) KPA_CHECK(launch_fill_u64(reinterpret_cast<u64*>(stats), 6, 0, stream));
+                                seg_list_from_offsets(seg_off, n_seg), rw, stream,
+                                stats_unsupported(stats)));
   } else {
     KPA_CHECK(learned_sort_launch(keys_in, rids_in, keys_out, rids_out,
                                   seg_list_from_offsets(seg_off, n_seg), models, stats, lw,

@@ -86,7 +86,16 @@ struct RadixWs {
 };
 
 kpa_status radix_sort_plan(u64 n_cap, u32 n_seg, Carver& c, RadixWs* w);
+// unsupported (device, may be null): counts the entries of segments of 2^30
+// or more entries, which are copied through unsorted.
 kpa_status radix_sort_launch(const u64* keys_in, const u32* rids_in, u64* keys_out,
-                             u32* rids_out, const SegList& sl, const RadixWs& w, hipStream_t st);
+                             u32* rids_out, const SegList& sl, const RadixWs& w, hipStream_t st,
+                             u64* unsupported = nullptr);
+// Offset of kpa_sort_stats.unsupported_entries in u64 words; the struct's size.
+constexpr int STATS_UNSUPPORTED = 6;
+constexpr int STATS_WORDS = 7;
+inline u64* stats_unsupported(kpa_sort_stats* st) {
+  return st ? reinterpret_cast<u64*>(st) + STATS_UNSUPPORTED : nullptr;
+}
 
 }  // namespace kpa

@@ -37,7 +37,10 @@ KPA_Q_JOIN = 2
 KPA_PWL_MAX_SEG = 1024
 KPA_MLP_PARAMS = 1153
 PWL_MODEL_BYTES = 8 + 8 + 4 + 4 + 4 * (KPA_PWL_MAX_SEG + 1) + 12  # sizeof(kpa_pwl_model)
-SORT_STATS_WORDS = 6
+SORT_STATS_WORDS = 7
+KPA_SEL_KEY = 0
+KPA_SEL_VALUE = 1
+SELECT_OPS = {">": 0, ">=": 1, "<": 2, "<=": 3, "==": 4, "!=": 5}
 
 
 class KpaError(RuntimeError):
@@ -102,6 +105,7 @@ _lay = C.POINTER(kpa_row_layout)
 _SIGS = {
     "kpa_version": ([], C.c_int32),
     "kpa_last_error_string": ([], C.c_char_p),
+    "kpa_last_hip_error": ([], C.c_int32),
     "kpa_device_check": ([C.POINTER(C.c_int32)], C.c_int32),
     "kpa_profile_enable": ([C.c_int32], C.c_int32),
     "kpa_profile_collect": ([], C.c_int32),
@@ -155,6 +159,24 @@ _SIGS = {
     "kpa_join": ([_vp, _vp, _vp, _u64, _vp, _vp, _vp, _u64, _u32, _vp, _vp, _lay, _vp, _vp, _vp,
                   _u64, _vp, _vp, C.c_size_t, _vp], C.c_int32),
     "kpa_materialize": ([_vp, _u64, _vp, _u32, _vp, _vp], C.c_int32),
+    "kpa_materialize_extract": ([_vp, _u64, _vp, _u32, _u32, _u32, _vp, _vp, _vp, _vp], C.c_int32),
+    "kpa_keyswap": ([_vp, _u64, _vp, _u32, _u32, _u32, _vp, _vp], C.c_int32),
+    "kpa_key_update": ([_vp, _u64, _vp, _vp, _u64, _vp, _vp], C.c_int32),
+    "kpa_key_writeback": ([_vp, _vp, _u64, _vp, _u32, _u32, _vp], C.c_int32),
+    "kpa_select_workspace_size": ([_u64, _u32, _sz], C.c_int32),
+    "kpa_select": ([_vp, _vp, _vp, _u32, _u64, _vp, _lay, C.c_int, C.c_int, _vp, _vp, _vp, _vp,
+                    _vp, _vp, _vp, C.c_size_t, _vp], C.c_int32),
+    "kpa_reduce_all_windows_workspace_size": ([_u32, _sz], C.c_int32),
+    "kpa_reduce_all_windows": ([_vp, _u64, _lay, _u64, _u64, _u32, _vp, _vp, _vp, _vp, _vp, _vp,
+                                C.c_size_t, _vp], C.c_int32),
+    "kpa_run_stats_workspace_size": ([_u64, _u32, _sz], C.c_int32),
+    "kpa_topk_per_key": ([_vp, _vp, _vp, _u32, _u64, _vp, _lay, _u32, _vp, _vp, _vp, _vp, _vp,
+                          _vp, C.c_size_t, _vp], C.c_int32),
+    "kpa_unique_count_by_key": ([_vp, _vp, _vp, _u32, _u64, _vp, _lay, _vp, _vp, _vp, _vp,
+                                 C.c_size_t, _vp], C.c_int32),
+    "kpa_window_panes": ([_vp, _vp, _u32, _u32, _vp, _vp, _vp, _u64, _vp], C.c_int32),
+    "kpa_partition_kpa": ([_vp, _vp, _u64, _u64, _u64, _u32, _vp, _vp, _vp, _vp, _vp, C.c_size_t,
+                           _vp], C.c_int32),
     "kpa_pwl_fit": ([_vp, _vp, _u32, _u32, _vp, _vp], C.c_int32),
     "kpa_mlp_training_set": ([_vp, _u64, _u32, _vp, _vp, _vp, _vp], C.c_int32),
     "kpa_mlp_forward": ([_vp, _vp, _u32, _vp, _vp], C.c_int32),
@@ -556,6 +578,163 @@ def kpa_materialize(rids, rows, row_bytes, out_rows=None, stream=None):
         out_rows = torch.empty(max(n, 1) * row_bytes // 8, dtype=torch.int64, device=dev)
     _call("kpa_materialize", _p(rids), n, _p(rows), row_bytes, _p(out_rows), _stream(stream))
     return out_rows
+
+
+def kpa_last_hip_error():
+    return int(_lib.kpa_last_hip_error())
+
+
+def kpa_materialize_extract(rids, rows, row_bytes, key_off, rid_base=0, out_rows=None,
+                            out_keys=None, out_rids=None, stream=None):
+    """Returns (out_rows, keys, rids): rows in KPA order and the KPA on the column at
+    key_off of the emitted rows."""
+    n = rids.numel()
+    dev = rids.device
+    if out_rows is None:
+        out_rows = torch.empty(max(n, 1) * row_bytes // 8, dtype=torch.int64, device=dev)
+    out_keys = torch.empty(max(n, 1), dtype=torch.int64, device=dev) if out_keys is None else out_keys
+    out_rids = torch.empty(max(n, 1), dtype=torch.int32, device=dev) if out_rids is None else out_rids
+    _call("kpa_materialize_extract", _p(rids), n, _p(rows), row_bytes, key_off, rid_base,
+          _p(out_rows), _p(out_keys), _p(out_rids), _stream(stream))
+    return out_rows, out_keys, out_rids
+
+
+def kpa_keyswap(rids, rows, row_bytes, col_off, col_w=8, out_keys=None, stream=None):
+    n = rids.numel()
+    out_keys = torch.empty(max(n, 1), dtype=torch.int64, device=rids.device) \
+        if out_keys is None else out_keys
+    _call("kpa_keyswap", _p(rids), n, _p(rows), row_bytes, col_off, col_w, _p(out_keys),
+          _stream(stream))
+    return out_keys
+
+
+def kpa_key_update(keys, table_keys, table_vals, n=None, out_missing=None, stream=None):
+    """Updates keys in place from the sorted table; returns the device count of misses."""
+    n = keys.numel() if n is None else n
+    out_missing = torch.empty(1, dtype=torch.int64, device=keys.device) \
+        if out_missing is None else out_missing
+    _call("kpa_key_update", _p(keys), n, _p(table_keys), _p(table_vals), table_keys.numel(),
+          _p(out_missing), _stream(stream))
+    return out_missing
+
+
+def kpa_key_writeback(keys, rids, rows, row_bytes, col_off, n=None, stream=None):
+    n = keys.numel() if n is None else n
+    _call("kpa_key_writeback", _p(keys), _p(rids), n, _p(rows), row_bytes, col_off,
+          _stream(stream))
+
+
+def kpa_select(keys, rids, seg_off, num_lo, num_hi=None, den=None, op=">", column=KPA_SEL_KEY,
+               rows=None, layout=None, n_cap=None, outs=None, ws=None, stream=None):
+    """Survivors of x * den[s] <op> num[s] per segment: (keys, rids, seg_off)."""
+    n_seg = seg_off.numel() - 1
+    n_cap = keys.numel() if n_cap is None else n_cap
+    dev = keys.device
+    o = outs or {}
+    ok = o["keys"] if "keys" in o else torch.empty(max(n_cap, 1), dtype=torch.int64, device=dev)
+    orr = o["rids"] if "rids" in o else torch.empty(max(n_cap, 1), dtype=torch.int32, device=dev)
+    oo = o["seg_off"] if "seg_off" in o else torch.empty(n_seg + 1, dtype=torch.int64,
+                                                         device=dev)
+    ws = _ws(_ws_size("kpa_select_workspace_size", n_cap, n_seg), dev, ws)
+    L = layout_struct(layout) if layout is not None else None
+    _call("kpa_select", _p(keys), _p(rids), _p(seg_off), n_seg, n_cap, _p(rows),
+          C.byref(L) if L is not None else None, column, SELECT_OPS.get(op, op), _p(num_lo),
+          _p(num_hi), _p(den), _p(ok), _p(orr), _p(oo), _p(ws), ws.numel() * ws.element_size(),
+          _stream(stream))
+    return ok, orr, oo
+
+
+def kpa_reduce_all_windows(rows, layout, win_len, n_win, win_origin=0, n=None, outs=None,
+                           ws=None, stream=None):
+    """Per window: dict of cnt, sum_lo, sum_hi, max (device int64 [n_win]) and oob."""
+    n = rows_count(rows, layout) if n is None else n
+    dev = rows.device
+    o = dict(outs or {})
+    for name in ("cnt", "sum_lo", "sum_hi", "max"):
+        if name not in o:
+            o[name] = torch.empty(n_win, dtype=torch.int64, device=dev)
+    if "oob" not in o:
+        o["oob"] = torch.empty(1, dtype=torch.int64, device=dev)
+    ws = _ws(_ws_size("kpa_reduce_all_windows_workspace_size", n_win), dev, ws)
+    L = layout_struct(layout)
+    _call("kpa_reduce_all_windows", _p(rows), n, C.byref(L), win_len, win_origin, n_win,
+          _p(o["cnt"]), _p(o["sum_lo"]), _p(o["sum_hi"]), _p(o["max"]), _p(o["oob"]), _p(ws),
+          ws.numel() * ws.element_size(), _stream(stream))
+    return o
+
+
+def kpa_topk_per_key(keys, rids, seg_off, rows, layout, k, n_cap=None, outs=None, ws=None,
+                     stream=None):
+    """Returns dict gkey, gcnt, gstart, topv, gseg_off (device)."""
+    n_seg = seg_off.numel() - 1
+    n_cap = keys.numel() if n_cap is None else n_cap
+    dev = keys.device
+    cap = max(n_cap, 1)
+    o = dict(outs or {})
+    for name in ("gkey", "gcnt", "gstart", "topv"):
+        if name not in o:
+            o[name] = torch.empty(cap, dtype=torch.int64, device=dev)
+    if "gseg_off" not in o:
+        o["gseg_off"] = torch.empty(n_seg + 1, dtype=torch.int64, device=dev)
+    ws = _ws(_ws_size("kpa_run_stats_workspace_size", n_cap, n_seg), dev, ws)
+    L = layout_struct(layout)
+    _call("kpa_topk_per_key", _p(keys), _p(rids), _p(seg_off), n_seg, n_cap, _p(rows), C.byref(L),
+          k, _p(o["gkey"]), _p(o["gcnt"]), _p(o["gstart"]), _p(o["topv"]), _p(o["gseg_off"]),
+          _p(ws), ws.numel() * ws.element_size(), _stream(stream))
+    return o
+
+
+def kpa_unique_count_by_key(keys, rids, seg_off, rows, layout, n_cap=None, outs=None, ws=None,
+                            stream=None):
+    """Returns dict gkey, uniq, gseg_off (device)."""
+    n_seg = seg_off.numel() - 1
+    n_cap = keys.numel() if n_cap is None else n_cap
+    dev = keys.device
+    cap = max(n_cap, 1)
+    o = dict(outs or {})
+    for name in ("gkey", "uniq"):
+        if name not in o:
+            o[name] = torch.empty(cap, dtype=torch.int64, device=dev)
+    if "gseg_off" not in o:
+        o["gseg_off"] = torch.empty(n_seg + 1, dtype=torch.int64, device=dev)
+    ws = _ws(_ws_size("kpa_run_stats_workspace_size", n_cap, n_seg), dev, ws)
+    L = layout_struct(layout)
+    _call("kpa_unique_count_by_key", _p(keys), _p(rids), _p(seg_off), n_seg, n_cap, _p(rows),
+          C.byref(L), _p(o["gkey"]), _p(o["uniq"]), _p(o["gseg_off"]), _p(ws),
+          ws.numel() * ws.element_size(), _stream(stream))
+    return o
+
+
+def kpa_window_panes(gkey, gseg_off, panes_per_window, out_cap, outs=None, stream=None):
+    """(keys, rids, seg_off) of the sliding windows' concatenated pane groups."""
+    n_pane = gseg_off.numel() - 1
+    n_win = n_pane - panes_per_window + 1
+    dev = gkey.device
+    o = outs or {}
+    ok = o["keys"] if "keys" in o else torch.empty(max(out_cap, 1), dtype=torch.int64, device=dev)
+    orr = o["rids"] if "rids" in o else torch.empty(max(out_cap, 1), dtype=torch.int32,
+                                                    device=dev)
+    oo = o["seg_off"] if "seg_off" in o else torch.empty(n_win + 1, dtype=torch.int64,
+                                                         device=dev)
+    _call("kpa_window_panes", _p(gkey), _p(gseg_off), n_pane, panes_per_window, _p(ok), _p(orr),
+          _p(oo), out_cap, _stream(stream))
+    return ok, orr, oo
+
+
+def kpa_partition_kpa(keys, rids, win_len, n_win, win_origin=0, n=None, out_keys=None,
+                      out_rids=None, out_win_off=None, out_oob=None, ws=None, stream=None):
+    n = keys.numel() if n is None else n
+    dev = keys.device
+    out_keys = torch.empty(max(n, 1), dtype=torch.int64, device=dev) if out_keys is None else out_keys
+    out_rids = torch.empty(max(n, 1), dtype=torch.int32, device=dev) if out_rids is None else out_rids
+    out_win_off = (torch.empty(n_win + 1, dtype=torch.int64, device=dev)
+                   if out_win_off is None else out_win_off)
+    out_oob = torch.empty(1, dtype=torch.int64, device=dev) if out_oob is None else out_oob
+    ws = _ws(_ws_size("kpa_partition_windows_workspace_size", n, n_win), dev, ws)
+    _call("kpa_partition_kpa", _p(keys), _p(rids), n, win_len, win_origin, n_win, _p(out_keys),
+          _p(out_rids), _p(out_win_off), _p(out_oob), _p(ws), ws.numel() * ws.element_size(),
+          _stream(stream))
+    return out_keys, out_rids, out_win_off, out_oob
 
 
 def new_models(n, device):

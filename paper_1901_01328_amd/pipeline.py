@@ -3,6 +3,8 @@ buffers allocated once so that repeated steps allocate nothing.
 
 WindowAggregation: windowing (partition on the timestamp column) -> per-window
 sort of the KPA -> keyed reduction (count, sum, max) -> top-k keys by sum.
+SlidingAggregation: the same per key over sliding windows, built from panes
+(partitions one slide long, Sec. 4.2 "Windowing").
 """
 from __future__ import annotations
 
@@ -213,3 +215,59 @@ class JoinMedian:
         K.kpa_join(L["skeys"], L["srids"], L["off"], R["skeys"], R["srids"], R["off"], L["vals"],
                    R["vals"], VALUE_COLUMN, nl_cap=self.n[0], nr_cap=self.n[1], ws=self.ws_join,
                    stream=stream, outs=self.join)
+
+
+class SlidingAggregation:
+    """Per-key count, sum and max over sliding windows of length win_len that
+    start every `slide` (win_len a multiple of slide; Sec. 4.2 "Windowing"
+    partitions on the slide length).  A step partitions the rows into panes of
+    one slide, sorts and reduces every pane once, then builds each window from
+    its panes' groups (kpa_window_panes), sorts those by key and combines them:
+    counts and sums add, maxima take the largest.  Window w covers
+    [origin + w*slide, origin + w*slide + win_len), 0 <= w < n_win."""
+
+    def __init__(self, n, layout, win_len, slide, n_win, device="cuda", win_origin=0):
+        if win_len % slide:
+            raise ValueError("win_len must be a multiple of slide")
+        self.n, self.layout, self.slide, self.origin = n, layout, slide, win_origin
+        self.P = win_len // slide
+        self.n_win = n_win
+        self.n_pane = n_win + self.P - 1
+        d = torch.device(device)
+        cap = max(n, 1)
+        wcap = cap * self.P              # each pane group lies in at most P windows
+        self.wcap = wcap
+        i64 = dict(dtype=torch.int64, device=d)
+        i32 = dict(dtype=torch.int32, device=d)
+        u8 = dict(dtype=torch.uint8, device=d)
+        self.pane = WindowAggregation(n, layout, slide, self.n_pane, k=1, device=device,
+                                      win_origin=win_origin)
+        self.cat_keys = torch.empty(wcap, **i64)
+        self.cat_rids = torch.empty(wcap, **i32)
+        self.cat_off = torch.empty(n_win + 1, **i64)
+        self.s_keys = torch.empty(wcap, **i64)
+        self.s_rids = torch.empty(wcap, **i32)
+        self.ws_sort = torch.empty(K.kpa_sort_workspace_size(wcap, n_win), **u8)
+        self.ws_red = torch.empty(K._ws_size("kpa_reduce_by_key_workspace_size", wcap, n_win),
+                                  **u8)
+        self.wkey = torch.empty(wcap, **i64)
+        self.wseg = torch.empty(n_win + 1, **i64)
+        self.w = {name: torch.empty(wcap, **i64) for name in ("cnt", "sum", "max")}
+        self._scratch = {name: torch.empty(wcap, **i64) for name in ("cnt", "sum", "max")}
+
+    def step(self, rows, stream=None):
+        if self.n_pane > 256:
+            raise ValueError("at most 256 panes")
+        self.pane.step(rows, stream=stream)
+        K.kpa_window_panes(self.pane.gkey, self.pane.gseg, self.P, self.wcap, stream=stream,
+                           outs={"keys": self.cat_keys, "rids": self.cat_rids,
+                                 "seg_off": self.cat_off})
+        K.kpa_sort_segmented(self.cat_keys, self.cat_rids, self.cat_off, n_cap=self.wcap,
+                             keys_out=self.s_keys, rids_out=self.s_rids, ws=self.ws_sort,
+                             stream=stream)
+        # one keyed reduction per pane column: sum of counts, sum of sums, max of maxima
+        for col, want in (("cnt", "sum"), ("sum", "sum"), ("max", "max")):
+            outs = {"gkey": self.wkey, "gseg_off": self.wseg, want: self.w[col]}
+            K.kpa_reduce_by_key(self.s_keys, self.s_rids, self.cat_off, self.pane.g[col],
+                                VALUE_COLUMN, n_cap=self.wcap, want=(want,), ws=self.ws_red,
+                                stream=stream, outs=outs)

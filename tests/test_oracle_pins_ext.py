@@ -323,3 +323,14 @@ def test_sliding_equals_tumbling_when_slide_is_length(orc):
         g0, g1 = int(go[w]), int(go[w + 1])
         assert gk[g0:g1].tolist() == ek.tolist() and gs[g0:g1].tolist() == es.tolist()
         assert gc[g0:g1].tolist() == ec.tolist() and gm[g0:g1].tolist() == em.tolist()
+
+
+def test_thresholds_given_as_python_lists_stay_exact(orc):
+    """Lists of Python ints at or above 2^63 reach the oracle exactly (numpy's
+    default conversion of such a list is float64, which would round the
+    threshold 2^63 + 1 down to 2^63 and let the key 2^63 pass)."""
+    big = (1 << 63) + 1
+    keys = np.array([big - 1, big, big + 1], np.uint64)
+    rids = np.arange(3, dtype=np.uint32)
+    ok, orr, oo = orc.select(keys, rids, [0, 3], [big], [0], [1], ">=")
+    assert ok.tolist() == [big, big + 1] and orr.tolist() == [1, 2] and oo.tolist() == [0, 2]
