@@ -302,6 +302,23 @@ kpa_status kpa_reduce_by_key(const uint64_t* keys, const uint32_t* rids, const u
                              uint64_t* out_gseg_off, void* ws, size_t ws_bytes,
                              hipStream_t stream);
 
+/* The same keyed reduction for callers that cannot allocate (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): no
+ * workspace argument; the reduction's bookkeeping lives in a static 4 MiB
+ * device array of the library (one per GPU, held until the process ends), so
+ * the call allocates nothing.  It serves n_cap up to about 2^29 entries over a
+ * few segments (more: KPA_EUNSUPPORTED, nothing enqueued).  Every call on a
+ * GPU uses that GPU's one array: calls that overlap on one GPU (other
+ * streams, other threads) race and must be serialized by the caller.
+ * Per-kernel timing must be off (KPA_EINVAL otherwise).  Arguments and
+ * outputs as kpa_reduce_by_key. */
+kpa_status kpa_reduce_by_key_noalloc(const uint64_t* keys, const uint32_t* rids,
+                                     const uint64_t* seg_off, uint32_t n_seg, uint64_t n_cap,
+                                     const void* rows, const kpa_row_layout* layout,
+                                     uint64_t* out_gkey, uint64_t* out_cnt, uint64_t* out_sum,
+                                     uint64_t* out_max, uint64_t* out_gstart,
+                                     uint64_t* out_gseg_off, hipStream_t stream);
+
 /* Top-k groups per segment by sum: descending sum, ascending key among equal
  * sums (k <= 16).  gkey/gsum/gseg_off as produced by kpa_reduce_by_key.
  * out_key/out_sum: device, n_seg*k entries (segment s at s*k); out_n: device,

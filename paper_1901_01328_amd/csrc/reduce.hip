@@ -12,6 +12,8 @@
 //      the tile, added atomically when it crosses an edge.
 // Integer addition and max are associative and commutative (sums modulo
 // 2^64), so the result does not depend on how the work is split.
+#include <mutex>
+
 #include "reduce_internal.hpp"
 
 namespace kpa {
@@ -587,6 +589,80 @@ kpa_status kpa_reduce_by_key(const uint64_t* keys, const uint32_t* rids, const u
   ReduceWs w;
   reduce_plan(n_cap, n_seg, c, &w);
   KPA_REQUIRE(c.used <= ws_bytes, KPA_EWORKSPACE, "workspace too small: need %zu bytes", c.used);
+  ReduceOut o{out_gkey, out_cnt, out_sum, out_max, out_gstart, out_gseg_off};
+  return reduce_launch(keys, rids, seg_off, n_seg, static_cast<const unsigned char*>(rows),
+                       layout, need_val, o, w, stream);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------ no-allocation form --
+// The reduction's tile bookkeeping (tile map, run-head counts, group bases,
+// scan blocks) in a file-scope device array instead of a caller workspace.
+// Each device holds its own copy; its address is looked up once per device
+// and kept, and only that address is passed to kernels.
+
+namespace kpa {
+namespace {
+
+constexpr size_t REDUCE_SCRATCH_BYTES = 4u << 20;
+static __device__ __align__(256) unsigned char scratch[REDUCE_SCRATCH_BYTES];
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+// The current device's copy of the array (looked up on the device's first use).
+kpa_status scratch_ptr(void** out) {
+  int dev = 0;
+  KPA_HIP(hipGetDevice(&dev));
+  KPA_REQUIRE(dev >= 0 && dev < SCRATCH_MAX_DEVICES, KPA_EUNSUPPORTED,
+              "device index %d above %d", dev, SCRATCH_MAX_DEVICES - 1);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    KPA_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    KPA_REQUIRE(p != nullptr, KPA_EHIP, "no device address for the reduction's scratch array");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return KPA_OK;
+}
+
+}  // namespace
+}  // namespace kpa
+
+extern "C" {
+
+kpa_status kpa_reduce_by_key_noalloc(const uint64_t* keys, const uint32_t* rids,
+                                     const uint64_t* seg_off, uint32_t n_seg, uint64_t n_cap,
+                                     const void* rows, const kpa_row_layout* layout,
+                                     uint64_t* out_gkey, uint64_t* out_cnt, uint64_t* out_sum,
+                                     uint64_t* out_max, uint64_t* out_gstart,
+                                     uint64_t* out_gseg_off, hipStream_t stream) {
+  clear_error();
+  const bool need_val = out_sum || out_max;
+  if (need_val) KPA_CHECK(check_layout(layout, true, false));
+  if (n_seg == 0) return KPA_OK;
+  KPA_REQUIRE(keys && rids && seg_off && out_gkey && out_gseg_off, KPA_EINVAL, "null pointer");
+  KPA_REQUIRE(!need_val || rows, KPA_EINVAL, "rows needed for sum/max");
+  KPA_REQUIRE(aligned(keys, 8) && aligned(rids, 4) && aligned(seg_off, 8) &&
+                  aligned(out_gkey, 8) && aligned(out_gseg_off, 8) && (!rows || aligned(rows, 16)),
+              KPA_EINVAL, "misaligned pointer");
+  KPA_REQUIRE(n_cap < (1ull << 32), KPA_EUNSUPPORTED, "n_cap must be below 2^32");
+  KPA_REQUIRE(!prof_enabled(), KPA_EINVAL,
+              "per-kernel timing records events: turn it off for the no-allocation call");
+  Carver sizer(nullptr);
+  ReduceWs w;
+  reduce_plan(n_cap, n_seg, sizer, &w);
+  KPA_REQUIRE(sizer.used <= REDUCE_SCRATCH_BYTES, KPA_EUNSUPPORTED,
+              "n_cap %llu with %u segments needs %zu bytes of scratch; the static array holds "
+              "%zu (about 2^29 entries over a few segments)",
+              (unsigned long long)n_cap, n_seg, sizer.used, REDUCE_SCRATCH_BYTES);
+  void* base = nullptr;
+  KPA_CHECK(scratch_ptr(&base));
+  Carver c(base);
+  reduce_plan(n_cap, n_seg, c, &w);
   ReduceOut o{out_gkey, out_cnt, out_sum, out_max, out_gstart, out_gseg_off};
   return reduce_launch(keys, rids, seg_off, n_seg, static_cast<const unsigned char*>(rows),
                        layout, need_val, o, w, stream);

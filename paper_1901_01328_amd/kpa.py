@@ -149,6 +149,8 @@ _SIGS = {
     "kpa_reduce_by_key_workspace_size": ([_u64, _u32, _sz], C.c_int32),
     "kpa_reduce_by_key": ([_vp, _vp, _vp, _u32, _u64, _vp, _lay, _vp, _vp, _vp, _vp, _vp, _vp,
                            _vp, C.c_size_t, _vp], C.c_int32),
+    "kpa_reduce_by_key_noalloc": ([_vp, _vp, _vp, _u32, _u64, _vp, _lay, _vp, _vp, _vp, _vp,
+                                   _vp, _vp, _vp], C.c_int32),
     "kpa_topk_by_sum_workspace_size": ([_u64, _u32, _sz], C.c_int32),
     "kpa_topk_by_sum": ([_vp, _vp, _vp, _u32, _u64, _u32, _vp, _vp, _vp, _vp, C.c_size_t, _vp],
                         C.c_int32),
@@ -511,6 +513,21 @@ def kpa_reduce_by_key(keys, rids, seg_off, rows, layout, n_cap=None, want=("cnt"
           _p(outs_t.get("gstart")), _p(gseg), _p(ws), ws.numel() * ws.element_size(),
           _stream(stream))
     return gkey, outs_t, gseg
+
+
+def kpa_reduce_by_key_noalloc(keys, rids, seg_off, rows, layout, outs, n_cap=None,
+                              want=("cnt", "sum", "max"), stream=None):
+    """kpa_reduce_by_key without a workspace (the library's static scratch);
+    outs must hold every output tensor: gkey, gseg_off and the wanted ones."""
+    n_seg = seg_off.numel() - 1
+    n_cap = keys.numel() if n_cap is None else n_cap
+    L = layout_struct(layout)
+    _call("kpa_reduce_by_key_noalloc", _p(keys), _p(rids), _p(seg_off), n_seg, n_cap, _p(rows),
+          C.byref(L), _p(outs["gkey"]), _p(outs.get("cnt") if "cnt" in want else None),
+          _p(outs.get("sum") if "sum" in want else None),
+          _p(outs.get("max") if "max" in want else None), _p(outs.get("gstart")),
+          _p(outs["gseg_off"]), _stream(stream))
+    return outs
 
 
 def kpa_topk_by_sum(gkey, gsum, gseg_off, k=10, g_cap=None, ws=None, stream=None, outs=None):
