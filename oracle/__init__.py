@@ -66,7 +66,9 @@ def lib():
         L.orc_materialize_extract.argtypes = [_u32p, _u64, _vp, _i, _i, _u64, _vp, _u64p, _u32p]
         L.orc_sliding_aggregate.argtypes = [_vp, _u64, _i, _i, _i, _i, _i, _i, _u64, _u64, _u64,
                                             _u32, _u64, _u64p, _u64p, _u64p, _u64p, _u64p]
-        for f in ("orc_partition", "orc_extract", "orc_sort", "orc_sort_segmented", "orc_merge",
+        L.orc_sort_rows_windowed.argtypes = [_vp, _u64, _i, _i, _i, _i, _u64, _u64, _u32, _vp,
+                                             _u64p, _u64p]
+        for f in ("orc_sort_rows_windowed", "orc_partition", "orc_extract", "orc_sort", "orc_sort_segmented", "orc_merge",
                   "orc_reduce_by_key", "orc_topk_by_sum", "orc_median_by_key", "orc_join",
                   "orc_materialize", "orc_pwl_fit", "orc_window_aggregate", "orc_topk_per_key",
                   "orc_unique_count_by_key", "orc_reduce_all_windows", "orc_select",
@@ -338,3 +340,14 @@ def sliding_aggregate(rows, layout, win_len, slide, n_win, origin=0, cap=None):
                                     origin, n_win, cap, gk, gc, gs, gm, go))
     g = int(go[-1])
     return gk[:g], gc[:g], gs[:g], gm[:g], go
+
+
+def sort_rows_windowed(rows, layout, win_len, n_win, origin=0):
+    """(rows ordered by (window, key) stably as bytes, win_off[n_win+1], oob)."""
+    r = _rows_np(rows)
+    n = r.nbytes // layout.row_bytes
+    out = np.empty(max(n, 1) * layout.row_bytes, np.uint8)
+    off = np.empty(n_win + 1, np.uint64); oob = np.zeros(1, np.uint64)
+    _ck(lib().orc_sort_rows_windowed(_ptr(r), n, layout.row_bytes, layout.key_off, layout.ts_off,
+                                     layout.ts_w, win_len, origin, n_win, _ptr(out), off, oob))
+    return out[:n * layout.row_bytes], off, int(oob[0])

@@ -587,4 +587,35 @@ int orc_sliding_aggregate(const void* rows, u64 n, int row_bytes, int key_off, i
   return 0;
 }
 
+// Grouping on full records without KPAs (the "NoKPA" design of the ablation of
+// Sec. 7.3): the rows themselves are ordered by (window, key), stably, so each
+// window's rows come out grouped by key in arrival order within a key.  Rows
+// whose timestamp lies in no window (window rule as orc_partition) count as
+// window n_win and come last.  out_rows holds all n rows; out_win_off (n_win
+// + 1) delimits the windows; *out_oob counts the rows after out_win_off[n_win].
+int orc_sort_rows_windowed(const void* rows, u64 n, int row_bytes, int key_off, int ts_off,
+                           int ts_w, u64 win_len, u64 origin, u32 n_win, void* out_rows,
+                           u64* out_win_off, u64* out_oob) {
+  if (win_len == 0 || (ts_w != 4 && ts_w != 8)) return -1;
+  std::vector<std::pair<std::pair<u64, u64>, u64>> v(n);  // ((window, key), row)
+  for (u64 i = 0; i < n; ++i) {
+    const unsigned char* r = row_at(rows, i, row_bytes);
+    u64 ts = load_le(r + ts_off, ts_w);
+    u64 w = (ts < origin || (ts - origin) / win_len >= n_win) ? n_win : (ts - origin) / win_len;
+    v[i] = {{w, load_le(r + key_off, 8)}, i};
+  }
+  std::stable_sort(v.begin(), v.end(),
+                   [](const std::pair<std::pair<u64, u64>, u64>& a,
+                      const std::pair<std::pair<u64, u64>, u64>& b) { return a.first < b.first; });
+  unsigned char* o = static_cast<unsigned char*>(out_rows);
+  for (u64 i = 0; i < n; ++i) std::memcpy(o + i * row_bytes, row_at(rows, v[i].second, row_bytes), row_bytes);
+  u64 pos = 0;
+  for (u32 w = 0; w <= n_win; ++w) {
+    out_win_off[w] = pos;
+    while (pos < n && v[pos].first.first == w) ++pos;
+  }
+  *out_oob = n - out_win_off[n_win];
+  return 0;
+}
+
 }  // extern "C"

@@ -334,3 +334,43 @@ def test_thresholds_given_as_python_lists_stay_exact(orc):
     rids = np.arange(3, dtype=np.uint32)
     ok, orr, oo = orc.select(keys, rids, [0, 3], [big], [0], [1], ">=")
     assert ok.tolist() == [big, big + 1] and orr.tolist() == [1, 2] and oo.tolist() == [0, 2]
+
+
+# ------------------------------------------------------- full-row grouping --
+
+@pytest.mark.parametrize("seed", range(20))
+def test_sort_rows_windowed_brute_force(orc, seed):
+    rng = np.random.default_rng(1000 + seed)
+    W, nw, origin = int(rng.integers(1, 9)), int(rng.integers(1, 5)), int(rng.integers(0, 4))
+    n = int(rng.integers(0, 50))
+    q = random_quads(rng, n, int(rng.integers(1, 6)), origin + W * nw + 4, 1 << 64, extreme=True)
+    raw = pack32(q)
+    out, off, oob = orc.sort_rows_windowed(raw, LAYOUT32, W, nw, origin)
+
+    def win(ts):
+        return nw if ts < origin or (ts - origin) // W >= nw else (ts - origin) // W
+
+    order = sorted(range(n), key=lambda i: (win(q[i][2]), q[i][0], i))   # stable: ties by row
+    assert out.tobytes() == b"".join(bytes(raw[i * 32:(i + 1) * 32]) for i in order)
+    counts = [sum(1 for i in range(n) if win(q[i][2]) == w) for w in range(nw + 1)]
+    assert off.tolist() == [sum(counts[:w]) for w in range(nw + 1)]
+    assert oob == counts[nw]
+
+
+def test_sort_rows_then_scan_equals_kpa_grouping(orc):
+    """Grouping on full rows reaches the KPA path's per-key results: the sorted
+    rows of each window, scanned as a KPA with rids in row order, reduce to
+    the same groups as partition + sort + reduce on (key, pointer) pairs."""
+    rng = np.random.default_rng(1100)
+    q = random_quads(rng, 300, 12, 40, 1 << 64, extreme=True)
+    raw = pack32(q)
+    out, off, oob = orc.sort_rows_windowed(raw, LAYOUT32, 10, 3)
+    keys, rids, poff, poob = orc.partition(raw, LAYOUT32, 10, 3)
+    assert oob == poob and off[:4].tolist() == poff.tolist()
+    sk, sr = orc.sort_segmented(keys, rids, poff)
+    for w in range(3):
+        a, b = int(off[w]), int(off[w + 1])
+        rk, rr = orc.extract(out[a * 32:b * 32], LAYOUT32)
+        e1 = orc.reduce_by_key(rk, rr, out[a * 32:b * 32], LAYOUT32)
+        e2 = orc.reduce_by_key(sk[a:b], sr[a:b], raw, LAYOUT32)
+        assert all(np.array_equal(x, y) for x, y in zip(e1, e2))
