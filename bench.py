@@ -1,24 +1,30 @@
 """Benchmark of the KPA grouping hot path on one MI355X.
 
-Default workload (windowed aggregation at scale): 2^28 rows of 32 bytes {u64
-key Zipf s=1.1 over 2^20 distinct 64-bit keys, u64 value uniform [0, 2^20),
-u64 timestamp ns over 10 s with +-1 ms disorder, u64 pad}, 10 tumbling 1 s
-windows.  One step = partition the rows into window KPAs, sort every window's
-KPA, count/sum/max per key, top-10 keys by sum per window, with the rows
-already resident in device memory.  Prints one JSON line.
+Default workload (many substream windows with learned splitters): 4096
+substreams with one window each, window sizes log-uniform over [2^10, 2^22)
+rows (2,149,508,137 rows of 32 bytes {u64 key, u64 value uniform [0, 2^20),
+u64 timestamp, u64 pad}), rank-ordered Zipf keys whose exponent (0.8 -> 1.4
+over the substreams) and offset drift from epoch 0 to epoch 1.  Epoch 0 is
+sorted and its sorted KPAs train one piecewise-linear CDF model per window;
+epoch 1 is measured.  Two routes on the same epoch-1 bytes:
+  learned: extract + batched sort (learned splitters for the large windows)
+           + count/sum/max per key + the fit of next epoch's models;
+  radix:   extract + batched sort (LSD radix) + count/sum/max per key.
+Each step is one replay of a captured graph, with the rows resident in HBM.
+`value` is the learned route's Mrec/s; the radix route is reported beside it.
+Then the paper's two comparisons on this GPU (KPA vs grouping on full rows;
+sort vs hash GroupBy; --no-ablations skips them) and a short serving leg
+(Poisson bundles at 200M rec/s, p50/p99 window latency; --no-serve skips it).
 
---workload c4: 4096 substreams with one window each, sizes log-uniform over
-[2^10, 2^22) rows, rank-ordered Zipf keys whose exponent and offset drift from
-epoch 0 (the models' training data) to epoch 1 (measured).  One step = extract
-+ batched sort (learned or radix for the large windows) + count/sum/max per
-key of every window, replayed as one captured graph.
+Other workloads: --workload c2 (2^28 rows, 10 windows, one route), c3
+(temporal join + median), c5 (serving alone).
 
-  python bench.py [--steps K] [--warmup W] [--algo radix|learned] [--rows N]
-                  [--workload c2|c4]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c4|c2|c3|c5]
 """
 from __future__ import annotations
 
 import argparse
+import concurrent.futures as cf
 import json
 import os
 import sys
@@ -30,19 +36,28 @@ if ROOT not in sys.path:
 
 METRIC = "Mrec/s KPA group-by (learned vs radix sort), % HBM peak, p99 latency"
 HBM_PEAK_GBS = 8000.0
-# Algorithmic bytes per entry and launch of each pass: the bytes the pass must
-# read and write for one entry, whatever the caches do.
+# Algorithmic bytes per entry of each pass: what the pass must read and
+# write for one entry, whatever the caches do.  Passes over the large windows
+# only (the batched sort's multi-workgroup class) are marked "large".
 PASS_BYTES = {
-    "radix_pass": 24,      # read key+rid, write key+rid
-    "radix_hist": 8,       # read key
-    "part_pass": 44,       # read 32-byte row, write key+rid
-    "part_hist": 32,       # read the row (its timestamp spans the row's cache line share)
-    "reduce_main": 20,     # read key+rid, gather 8-byte value
-    "reduce_summary": 8,   # read key (plus the last run's values)
+    "radix_pass": 24,       # read key+rid, write key+rid (per entry of an active pass)
+    "radix_hist": 8,        # read key
+    "part_pass": 44,        # read 32-byte row, write key+rid
+    "part_hist": 32,        # read the row (its timestamp spans the row's cache line share)
+    "reduce_main": 20,      # read key+rid, gather 8-byte value
+    "extract": 52,          # read 32-byte row, write key+rid+value
+    "learned_scatter": 24,  # read key+rid, write key+rid (entries of large windows)
+    "learned_finish": 24,   # read key+rid, write key+rid (entries of large windows)
+    "learned_hist": 8,      # read key (entries of large windows)
 }
+LARGE_ONLY = {"learned_scatter", "learned_finish", "learned_hist", "radix_hist"}
 
 
 COPY_GBS = None  # device copy rate on this GPU (read + write bytes per second), set in main
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def measure_copy_rate(dev, mib=1024, reps=5):
@@ -67,14 +82,10 @@ def measure_copy_rate(dev, mib=1024, reps=5):
     return round(2 * (mib << 20) / (ms / 1000) / 1e9, 1)
 
 
-RADIX_PASS_SOURCES = ("onesweep.hpp", "digit_sort.hpp", "radix.hip")
-LEARNED_PASS_SOURCES = ("onesweep.hpp", "digit_sort.hpp", "learned.hip", "learned_internal.hpp")
-
-
-def counted_traffic(kernel_row, summary="c2_radix_hbm_bytes.md", sources=RADIX_PASS_SOURCES):
+def counted_traffic(kernel_row, summary, sources):
     """HBM bytes per dispatch of a kernel from a committed counter summary
-    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the scatter
-    pass's sources changed since the counters were taken."""
+    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the kernel's
+    sources changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", summary)
     if not os.path.exists(path):
@@ -93,23 +104,41 @@ def counted_traffic(kernel_row, summary="c2_radix_hbm_bytes.md", sources=RADIX_P
     return None
 
 
+# Counter summaries of the dominant kernels: (summary file, row, sources).
+TRAFFIC = {
+    ("c2", "radix_pass"): ("c2_radix_hbm_bytes.md", "k_ds_pass<RadixDF>",
+                           ("onesweep.hpp", "digit_sort.hpp", "radix.hip")),
+    ("c2", "learned_scatter"): ("c2_learned_hbm_bytes.md", "k_ds_pass<LearnedDF>",
+                                ("onesweep.hpp", "digit_sort.hpp", "learned.hip",
+                                 "learned_internal.hpp")),
+    ("c4", "reduce_main"): ("c4_reduce_hbm_bytes.md", "k_reduce_main",
+                            ("reduce.hip", "reduce_internal.hpp")),
+}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--algo", choices=["radix", "learned"], default="radix")
-    ap.add_argument("--rows", type=int, default=1 << 28)
+    ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5", "ablations"], default="c4")
+    ap.add_argument("--algo", choices=["radix", "learned"], default="radix", help="c2 only")
+    ap.add_argument("--rows", type=int, default=1 << 28, help="c2 rows")
     ap.add_argument("--cpu-rows", type=int, default=3 << 26,
-                    help="rows of the oracle's CPU-baseline sample")
+                    help="c2: rows of the oracle's CPU-baseline sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-check", action="store_true")
-    ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5"], default="c2")
+    ap.add_argument("--no-serve", action="store_true", help="c4: skip the serving leg")
+    ap.add_argument("--no-ablations", action="store_true",
+                    help="c4: skip the KPA-vs-full-rows and sort-vs-hash legs")
+    ap.add_argument("--serve-seconds", type=float, default=8.0, help="c4: serving leg length")
     ap.add_argument("--duration", type=float, default=30.0, help="c5: seconds of offered load")
     ap.add_argument("--rate", type=float, default=200e6, help="c5: offered records per second")
     ap.add_argument("--host-rows", action="store_true", help="c5: keep full rows in host memory")
     ap.add_argument("--c4-windows", type=int, default=4096)
     ap.add_argument("--c4-hi-log2", type=int, default=22)
+    ap.add_argument("--c4-route", choices=["both", "learned", "radix"], default="both",
+                    help="c4: routes to time (profiling runs of one route)")
     ap.add_argument("--no-tune", action="store_true", help="c4: default batch configuration")
     ap.add_argument("--probe-copy-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device (calibrates HBM byte counters)")
@@ -123,48 +152,450 @@ def main():
               "substreams would be sharded over GPUs, one huge window by key range; that is "
               "not built)", file=sys.stderr)
         sys.exit(2)
+    import torch
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    global COPY_GBS
+    if a.probe_copy_mib:  # counter runs calibrate on their own first copy
+        src = torch.empty(a.probe_copy_mib << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    else:
+        COPY_GBS = measure_copy_rate(dev)
+    out = {"c4": bench_c4, "c2": bench_c2, "c3": bench_c3, "c5": bench_c5,
+           "ablations": lambda a: {"metric": METRIC, "ablations": ablation_leg(a.steps, a.warmup)}
+           }[a.workload](a)
+    print(json.dumps(out), flush=True)
+
+
+def kernel_passes(K, steps, n, pass_bytes, n_large=None):
+    """Per-kernel launches per step, mean ms and algorithmic GB/s (recorded
+    with events on each launch's own stream since the last profile enable)."""
+    K.kpa_profile_collect()
+    passes = {}
+    for name in K.kpa_profile_names():
+        cnt, tot = K.kpa_profile_get(name)
+        if cnt == 0:
+            continue
+        avg = tot / cnt
+        entry = {"launches_per_step": cnt / steps, "avg_ms": round(avg, 4)}
+        if name in pass_bytes and name != "radix_pass":
+            m = n_large if (name in LARGE_ONLY and n_large is not None) else n
+            gbs = pass_bytes[name] * m / (avg / 1000.0) / 1e9
+            entry["alg_GBps"] = round(gbs, 1)
+            entry["hbm_frac"] = round(gbs / HBM_PEAK_GBS, 4)
+        passes[name] = entry
+    return passes
+
+
+def roofline(passes, name, bytes_per_launch, traffic=None):
+    pl = passes[name]
+    achieved = bytes_per_launch / (pl["avg_ms"] / 1000.0) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "copy_gbs": COPY_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic, "kernel": name, "avg_ms": pl["avg_ms"],
+            "launches_per_step": pl["launches_per_step"], "bytes_per_launch": int(bytes_per_launch)}
+
+
+def dominant(passes):
+    """The pass with the most time per step among those with a byte model."""
+    best, t = None, -1.0
+    for name, p in passes.items():
+        if name in PASS_BYTES:
+            tt = p["avg_ms"] * p["launches_per_step"]
+            if tt > t:
+                best, t = name, tt
+    return best
+
+
+def fingerprint(*tensors, chunk=1 << 27):
+    """A position-dependent 64-bit digest of int tensors (wrapping sums of
+    SplitMix64-finalized values): equal arrays give equal digests; a single
+    differing element changes it except with probability about 2^-64."""
+    import torch
+
+    from datagen.rows import mix64
+    acc = 0
+    for k, t in enumerate(tensors):
+        t = t.reshape(-1)
+        for s in range(0, t.numel(), chunk):
+            x = t[s:s + chunk].to(torch.int64)
+            i = torch.arange(s, s + x.numel(), dtype=torch.int64, device=t.device)
+            h = mix64(x ^ mix64(i * 2 + 1 + k * 0x51ED27)).sum()
+            acc = (acc + int(h.item())) & ((1 << 64) - 1)
+    return acc
+
+
+def bench_c4(a):
     import numpy as np
     import torch
 
     import datagen
     import paper_1901_01328_amd as P
     from datagen.rows import LAYOUT32
+    from paper_1901_01328_amd.pipeline import BatchAggregation
     K = P.load()
-    from paper_1901_01328_amd.pipeline import WindowAggregation
-
     dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    global COPY_GBS
-    if not a.probe_copy_mib:  # counter runs calibrate on their own first copy
-        COPY_GBS = measure_copy_rate(dev)
-    if a.probe_copy_mib:
-        src = torch.empty(a.probe_copy_mib << 20, dtype=torch.uint8, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
+    sizes = datagen.c4_window_sizes(a.c4_windows, hi_log2=a.c4_hi_log2)
+    n = int(sizes.sum())
+    n_seg = len(sizes)
+    t0 = time.time()
+    rows = datagen.gen_c4(0, sizes, device=dev)
+    torch.cuda.synchronize()
+    log(f"c4 epoch 0: {n} rows in {n_seg} windows generated in {time.time() - t0:.1f} s")
+    pipe = BatchAggregation(n, n_seg, LAYOUT32, device=dev, learned_ws=True)
+    pipe.set_sizes(sizes)
+    radix_cfg = K.batch_config(large_algo=K.KPA_SORT_RADIX)
+    pipe.step(rows, cfg=radix_cfg)
+    pipe.fit_models()                      # epoch 1's models: epoch 0's sorted windows
+    datagen.gen_c4(1, sizes, out=rows)
+    pipe.step(rows, cfg=radix_cfg)         # extracts epoch 1 (the tuner sorts pipe.keys)
+    torch.cuda.synchronize()
+    log(f"c4 epoch 1 generated; models fitted ({time.time() - t0:.1f} s)")
+
+    routes = ["learned", "radix"] if a.c4_route == "both" else [a.c4_route]
+    algo = {"learned": K.KPA_SORT_LEARNED, "radix": K.KPA_SORT_RADIX}
+    cfgs, tune_ms = {}, {}
+    for r in routes:
+        if a.no_tune:
+            cfgs[r], tune_ms[r] = K.batch_config(large_algo=algo[r]), None
+        else:
+            cfgs[r], tune_ms[r] = K.kpa_batch_autotune(
+                pipe.keys, pipe.rids, pipe.seg_off, large_algo=algo[r], n_cap=n,
+                models=pipe.models if r == "learned" else None, reps=2,
+                keys_out=pipe.skeys, rids_out=pipe.srids, ws=pipe.ws_sort)
+            log(f"autotuned {r}: {cfgs[r].as_dict()} ({tune_ms[r]:.2f} ms sort)")
+
+    stream = torch.cuda.Stream()
+    res = {}
+    for r in routes:
+        graph = pipe.capture(rows, stream, cfg=cfgs[r], fit_next=(r == "learned"))
+        for _ in range(a.warmup):
+            graph.launch(stream)
+        stream.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
-        del src, dst
-    if a.workload == "c4":
-        return bench_c4(a)
-    if a.workload == "c5":
-        return bench_c5(a)
-    if a.workload == "c3":
-        return bench_c3(a)
+        wall0 = time.perf_counter()
+        ev0.record(stream)
+        for _ in range(a.steps):
+            graph.launch(stream)
+        ev1.record(stream)
+        stream.synchronize()
+        wall = time.perf_counter() - wall0
+        ms = max(ev0.elapsed_time(ev1), wall * 1000) / a.steps
+        graph.destroy()
+        log(f"c4 {r}: {a.steps} graph replays, {ms:.3f} ms/step")
+        res[r] = {"ms": ms, "value": n / (ms / 1000.0) / 1e6}
+
+    # Per-kernel times: the same steps run eagerly with event timing per launch
+    # on the launch's own stream (outside the timed region above).
+    large = int(sizes[sizes > cfgs[routes[0]].mid_cap].sum())
+    prof_steps = 2
+    for r in routes:
+        K.kpa_profile_enable(True)
+        for _ in range(prof_steps):
+            pipe.step(rows, stream=stream, cfg=cfgs[r], fit_next=(r == "learned"))
+        stream.synchronize()
+        res[r]["passes"] = kernel_passes(K, prof_steps, n, PASS_BYTES,
+                                         n_large=int(sizes[sizes > cfgs[r].mid_cap].sum()))
+        K.kpa_profile_enable(False)
+        res[r]["sort_stats"] = pipe.stats.cpu().numpy().tolist()
+        # outputs of this route: whole-array digests, and the sampled windows' groups
+        stream.synchronize()
+        G = int(pipe.gseg[-1].item())
+        res[r]["digest"] = {"sorted_kpa": fingerprint(pipe.skeys, pipe.srids),
+                            "groups": fingerprint(pipe.gseg, *(t[:G] for t in (
+                                pipe.gkey, pipe.g["cnt"], pipe.g["sum"], pipe.g["max"])))}
+        off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+        goff = pipe.gseg.cpu().numpy().view(np.uint64)
+        sample = list(range(0, n_seg, 16))
+        grp = {}
+        for j in sample:
+            g0, g1 = int(goff[j]), int(goff[j + 1])
+            grp[j] = tuple(t[g0:g1].cpu().numpy().view(np.uint64).copy() for t in
+                           (pipe.gkey, pipe.g["cnt"], pipe.g["sum"], pipe.g["max"]))
+        res[r]["groups"] = grp
+
+    # Active radix passes of the large windows (their keys' varying bytes)
+    sk = pipe.skeys
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    act = 0
+    for j in np.nonzero(sizes > cfgs[routes[-1]].mid_cap)[0]:
+        seg = sk[int(off[j]):int(off[j + 1])]
+        x = seg ^ seg[0]
+        act += int(sizes[j]) * sum(1 for p in range(8) if bool((((x >> (8 * p)) & 255) != 0).any()))
+
+    # Oracle: every 16th window, per-key count/sum/max, compared with both routes
+    check, cpu = None, None
+    sample = list(range(0, n_seg, 16))
+    if not (a.no_check and a.no_cpu):
+        import oracle
+        host = {j: rows[off[j]:off[j + 1]].cpu() for j in sample}
+        threads = min(16, os.cpu_count() or 1)
+
+        def one(j):
+            rr = host[j]
+            keys, rids = oracle.extract(rr, LAYOUT32)
+            return j, oracle.reduce_by_key(keys, rids, rr, LAYOUT32)
+
+        t1 = time.perf_counter()
+        with cf.ThreadPoolExecutor(threads) as ex:
+            ores = dict(ex.map(one, sample))
+        dt = time.perf_counter() - t1
+        m = int(sum(sizes[j] for j in sample))
+        check = {"windows_checked": len(sample), "rows_checked": m}
+        for r in routes:
+            ok = all(len(ores[j][0]) == len(res[r]["groups"][j][0]) and
+                     all(np.array_equal(x, y) for x, y in zip(res[r]["groups"][j], ores[j]))
+                     for j in sample)
+            check[f"{r}_per_key_arrays_match_oracle"] = bool(ok)
+        if len(routes) == 2:
+            check["learned_equals_radix"] = {
+                k: res["learned"]["digest"][k] == res["radix"]["digest"][k]
+                for k in ("sorted_kpa", "groups")}
+        cpu = {"value": round(m / dt / 1e6, 3), "unit": "Mrec/s", "cores": threads,
+               "host_cores": os.cpu_count(), "kind": "oracle",
+               "sample": f"every 16th window ({len(sample)} windows, {m} rows): extract + "
+               f"ordered-map count/sum/max per key, {dt:.1f} s on {threads} threads"}
+        log(f"oracle: {dt:.1f} s on {threads} threads; check {check}")
+
+    # Roofline of the dominant kernel of the headline route
+    head = routes[0]
+    passes = res[head]["passes"]
+    dom = dominant(passes)
+    roof = None
+    if dom:
+        pl = passes[dom]
+        if dom == "radix_pass":
+            per_launch = 24 * act / pl["launches_per_step"]
+        elif dom in LARGE_ONLY:
+            per_launch = PASS_BYTES[dom] * large
+        else:
+            per_launch = PASS_BYTES[dom] * n
+        tr = TRAFFIC.get(("c4", dom))
+        traffic = counted_traffic(tr[1], tr[0], tr[2]) if tr else None
+        roof = roofline(passes, dom, per_launch, traffic)
+
+    serving, ablations = None, None
+    del pipe, rows, sk
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    if not a.no_ablations:
+        ablations = ablation_leg()
+    if not a.no_serve:
+        serving = serve_leg(a.rate, a.serve_seconds, host_rows=False)
+
+    out = {
+        "metric": METRIC, "value": round(res[head]["value"], 2), "unit": "Mrec/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(res[head]["ms"], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": f"{n_seg} substream windows (sizes log-uniform over "
+                   f"[2^10, 2^{a.c4_hi_log2}), {n} rows of 32 bytes), drifting rank-Zipf "
+                   "keys, PWL models fitted on the previous epoch; extract + batched sort + "
+                   "count/sum/max per key (+ next models' fit on the learned route), one "
+                   "graph replay per step", "route": head, "rows": n, "windows": n_seg,
+                   "batch_config": cfgs[head].as_dict(), "autotune_sort_ms": tune_ms[head]},
+        "roofline": roof, "cpu_baseline": cpu, "check": check,
+        "passes": passes, "sort_stats": res[head]["sort_stats"],
+    }
+    if len(routes) == 2:
+        rr = res["radix"]
+        out["radix"] = {"value": round(rr["value"], 2), "unit": "Mrec/s",
+                        "ms_per_step": round(rr["ms"], 4), "batch_config": cfgs["radix"].as_dict(),
+                        "passes": rr["passes"]}
+        out["speedup_learned_vs_radix"] = round(rr["ms"] / res["learned"]["ms"], 4)
+        rd = dominant(rr["passes"])
+        if rd == "radix_pass":
+            out["radix"]["roofline"] = roofline(rr["passes"], rd,
+                                                24 * act / rr["passes"][rd]["launches_per_step"])
+        elif rd:
+            m = int(sizes[sizes > cfgs["radix"].mid_cap].sum()) if rd in LARGE_ONLY else n
+            out["radix"]["roofline"] = roofline(rr["passes"], rd, PASS_BYTES[rd] * m)
+    if serving is not None:
+        out["serving"] = serving
+    if ablations is not None:
+        out["ablations"] = ablations
+    return out
+
+
+def timed(fn, steps, warmup):
+    """Mean ms of fn() over `steps` calls after `warmup`, event- and wall-timed
+    on the current stream (the larger of the two)."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return max(e0.elapsed_time(e1), (time.perf_counter() - w0) * 1000) / steps
+
+
+def ablation_leg(steps=5, warmup=2):
+    """The paper's two comparisons on this GPU, each against the KPA path on the
+    same bytes, with identical outputs:
+    * KPA vs full-row grouping (the design without KPAs, Sec. 7.3): 2^28
+      32-byte rows of the windowed workload, count/sum/max per key and top-10
+      per window, either by partition + KPA sort + keyed reduction or by
+      ordering the rows themselves by (window, key) and scanning them;
+    * sort vs hash GroupBy (Sec. 2.2): 10^8 16-byte rows {u64 key, u64 value},
+      count/sum/max per key, by extract + KPA sort + keyed reduction or by an
+      open-addressing hash table; with about 100 values per key (the paper's
+      setting: the table fits the 256 MB last-level cache) and with about 1.5
+      values per key (the table does not)."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_1901_01328_amd as P
+    from datagen.rows import LAYOUT32, RowLayout
+    from paper_1901_01328_amd.pipeline import VALUE_COLUMN, WindowAggregation
+    K = P.load()
+    dev = torch.device("cuda:0")
+    out = {}
+    # ---- KPA vs full rows
+    n, n_win, W = 1 << 28, 10, 10 ** 9
+    rows = datagen.gen_c2(n, seed=2, device=dev)
+    kpa = WindowAggregation(n, LAYOUT32, W, n_win, k=10, device=dev)
+    ms_kpa = timed(lambda: kpa.step(rows), steps, warmup)
+    i64 = dict(dtype=torch.int64, device=dev)
+    srows = torch.empty(n * 4, **i64)
+    off = torch.empty(n_win + 1, **i64)
+    oob = torch.empty(1, **i64)
+    nb = K._ws_size("kpa_reduce_by_key_workspace_size", n, n_win)
+    ws_red = torch.empty(nb, dtype=torch.uint8, device=dev)
+    c = __import__("ctypes").c_size_t(0)
+    K._call("kpa_sort_rows_windowed_workspace_size", n, 32, __import__("ctypes").byref(c))
+    ws_rows = torch.empty(int(c.value), dtype=torch.uint8, device=dev)
+    keys = torch.empty(n, **i64)
+    rids = torch.empty(n, dtype=torch.int32, device=dev)
+    gk = torch.empty(n, **i64)
+    g = {w: torch.empty(n, **i64) for w in ("cnt", "sum", "max")}
+    gseg = torch.empty(n_win + 1, **i64)
+    tk = torch.empty(n_win * 10, **i64)
+    tsum = torch.empty(n_win * 10, **i64)
+    tn = torch.empty(n_win, dtype=torch.int32, device=dev)
+    ws_top = torch.empty(K._ws_size("kpa_topk_by_sum_workspace_size", n, n_win),
+                         dtype=torch.uint8, device=dev)
+
+    def full_rows():
+        K.kpa_sort_rows_windowed(rows, LAYOUT32, W, n_win, n=n, out_rows=srows, out_win_off=off,
+                                 out_oob=oob, ws=ws_rows)
+        K.kpa_extract(srows, LAYOUT32, out_keys=keys, out_rids=rids, n=n)
+        K.kpa_reduce_by_key(keys, rids, off, srows, LAYOUT32, n_cap=n, ws=ws_red,
+                            outs=dict(g, gkey=gk, gseg_off=gseg))
+        K.kpa_topk_by_sum(gk, g["sum"], gseg, k=10, g_cap=n, ws=ws_top,
+                          outs={"key": tk, "sum": tsum, "n": tn})
+
+    ms_rows = timed(full_rows, steps, warmup)
+    G = int(gseg[-1].item())
+    same = (torch.equal(gseg, kpa.gseg) and torch.equal(gk[:G], kpa.gkey[:G]) and
+            all(torch.equal(g[w][:G], kpa.g[w][:G]) for w in g) and
+            torch.equal(tk, kpa.top_key) and torch.equal(tsum, kpa.top_sum))
+    out["kpa_vs_full_rows"] = {
+        "workload": "2^28 32-byte rows, Zipf keys over 2^20, 10 windows, count/sum/max per key "
+                    "+ top-10 by sum", "kpa_ms": round(ms_kpa, 3), "full_rows_ms": round(ms_rows, 3),
+        "kpa_mrec_per_s": round(n / ms_kpa / 1e3, 1),
+        "full_rows_mrec_per_s": round(n / ms_rows / 1e3, 1),
+        "kpa_speedup": round(ms_rows / ms_kpa, 3), "outputs_identical": bool(same)}
+    log(f"ablation KPA vs full rows: {out['kpa_vs_full_rows']}")
+    del rows, kpa, srows, keys, rids, gk, g, ws_rows, ws_red
+    torch.cuda.empty_cache()
+    # ---- sort vs hash GroupBy
+    KV16 = RowLayout(16, 0, 8, 8, 8, 8)
+    n = 10 ** 8
+    res = []
+    for n_keys in (1 << 20, 1 << 26):
+        i = torch.arange(n, dtype=torch.int64, device=dev)
+        table = datagen.key_table(n_keys, 77, dev)
+        kv = torch.empty((n, 2), **i64)
+        kv[:, 0] = table[datagen.uniform_int(datagen.splitmix64(78, 1, i), n_keys)]
+        kv[:, 1] = datagen.splitmix64(78, 2, i)
+        del i, table
+        keys = torch.empty(n, **i64)
+        rids = torch.empty(n, dtype=torch.int32, device=dev)
+        vals = torch.empty(n, **i64)
+        sk = torch.empty(n, **i64)
+        sr = torch.empty(n, dtype=torch.int32, device=dev)
+        soff = torch.tensor([0, n], **i64)
+        ws_sort = torch.empty(K.kpa_sort_workspace_size(n, 1), dtype=torch.uint8, device=dev)
+        ws_red = torch.empty(K._ws_size("kpa_reduce_by_key_workspace_size", n, 1),
+                             dtype=torch.uint8, device=dev)
+        gk = torch.empty(n, **i64)
+        g = {w: torch.empty(n, **i64) for w in ("cnt", "sum", "max")}
+        gseg = torch.empty(2, **i64)
+
+        def by_sort():
+            K.kpa_extract(kv, KV16, out_keys=keys, out_rids=rids, out_vals=vals, n=n)
+            K.kpa_sort_segmented(keys, rids, soff, n_cap=n, keys_out=sk, rids_out=sr, ws=ws_sort)
+            K.kpa_reduce_by_key(sk, sr, soff, vals, VALUE_COLUMN, n_cap=n, ws=ws_red,
+                                outs=dict(g, gkey=gk, gseg_off=gseg))
+
+        cap = 1 << int(np.ceil(np.log2(2 * n_keys)))
+        ws_hash = torch.empty(K._ws_size("kpa_hash_groupby_workspace_size", cap),
+                              dtype=torch.uint8, device=dev)
+        ho = {name: torch.empty(n_keys + 1, **i64) for name in ("gkey", "cnt", "sum", "max")}
+        ho["ngroups"] = torch.empty(1, **i64)
+
+        def by_hash():
+            K.kpa_hash_groupby(kv, KV16, cap, g_cap=n_keys + 1, n=n, outs=ho, ws=ws_hash)
+
+        ms_sort = timed(by_sort, steps, warmup)
+        ms_hash = timed(by_hash, steps, warmup)
+        G = int(gseg[-1].item())
+        Gh = int(ho["ngroups"].item())
+        same = G == Gh
+        if same:
+            hk, order = torch.sort(ho["gkey"][:Gh].view(torch.int64) ^ (-(1 << 63)))
+            same = torch.equal(gk[:G], ho["gkey"][:Gh][order]) and all(
+                torch.equal(g[w][:G], ho[w][:Gh][order]) for w in g)
+        res.append({"rows": n, "distinct_keys": G, "values_per_key": round(n / max(G, 1), 1),
+                    "hash_table_mib": round(cap * 32 / 2 ** 20, 1), "sort_ms": round(ms_sort, 3),
+                    "hash_ms": round(ms_hash, 3), "sort_speedup": round(ms_hash / ms_sort, 3),
+                    "outputs_identical": bool(same)})
+        log(f"ablation sort vs hash: {res[-1]}")
+        del kv, keys, rids, vals, sk, sr, ws_sort, ws_red, gk, g, ws_hash, ho
+        torch.cuda.empty_cache()
+    out["sort_vs_hash"] = {"workload": "10^8 16-byte rows {u64 key, u64 value}, count/sum/max "
+                           "per key; sort = extract + KPA radix sort + keyed reduction (groups in "
+                           "key order), hash = open-addressing table (groups in table order)",
+                           "points": res}
+    return out
+
+
+def bench_c2(a):
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_1901_01328_amd as P
+    from datagen.rows import LAYOUT32
+    from paper_1901_01328_amd.pipeline import WindowAggregation
+    K = P.load()
+    dev = torch.device("cuda:0")
     n = a.rows
     n_win, W = 10, 10 ** 9
     t0 = time.time()
     rows = datagen.gen_c2(n, seed=2, device=dev)
     torch.cuda.synchronize()
-    print(f"[bench] generated {n} rows on the GPU in {time.time() - t0:.1f} s", file=sys.stderr,
-          flush=True)
+    log(f"generated {n} rows on the GPU in {time.time() - t0:.1f} s")
     algo = K.KPA_SORT_LEARNED if a.algo == "learned" else K.KPA_SORT_RADIX
     pipe = WindowAggregation(n, LAYOUT32, W, n_win, algo=algo, k=10, device=dev)
     stream = torch.cuda.current_stream()
     for _ in range(a.warmup):
         pipe.step(rows)
     torch.cuda.synchronize()
-    print(f"[bench] warmup done ({a.warmup} steps)", file=sys.stderr, flush=True)
-
-    K.kpa_profile_enable(True)
+    # timed with per-kernel timing off
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -175,29 +606,19 @@ def main():
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
-    K.kpa_profile_collect()
-    ms_step = ev0.elapsed_time(ev1) / a.steps
-    ms_wall = wall * 1000 / a.steps
-    value = n / (max(ms_step, ms_wall) / 1000.0) / 1e6
-    print(f"[bench] timed {a.steps} steps: {ms_step:.3f} ms/step (events), {ms_wall:.3f} (wall)",
-          file=sys.stderr, flush=True)
-
-    passes = {}
-    for name in K.kpa_profile_names():
-        cnt, tot = K.kpa_profile_get(name)
-        if cnt == 0:
-            continue
-        avg = tot / cnt
-        entry = {"launches_per_step": cnt / a.steps, "avg_ms": round(avg, 4)}
-        if name in PASS_BYTES:
-            gbs = PASS_BYTES[name] * n / (avg / 1000.0) / 1e9
-            entry["alg_GBps"] = round(gbs, 1)
-            entry["hbm_frac"] = round(gbs / HBM_PEAK_GBS, 4)
-        passes[name] = entry
+    ms_step = max(ev0.elapsed_time(ev1), wall * 1000) / a.steps
+    value = n / (ms_step / 1000.0) / 1e6
+    log(f"timed {a.steps} steps: {ms_step:.3f} ms/step")
+    # per-kernel times from separate profiled steps
+    prof_steps = 3
+    K.kpa_profile_enable(True)
+    for _ in range(prof_steps):
+        pipe.step(rows)
+    torch.cuda.synchronize()
+    passes = kernel_passes(K, prof_steps, n, PASS_BYTES)
     K.kpa_profile_enable(False)
 
-    # Active radix passes: digits that vary inside a window are sorted; for
-    # these 64-bit keys all eight do in every window.
+    # Active radix passes: digits that vary inside a window
     sk = pipe.skeys
     off = pipe.win_off.cpu().numpy().view(np.uint64)
     active = 0
@@ -213,23 +634,14 @@ def main():
     roof = None
     if dom in passes:
         launches = passes[dom]["launches_per_step"]
-        avg_ms = passes[dom]["avg_ms"]
-        bytes_per_launch = PASS_BYTES.get(dom, 24) * n * (active / n_win) / launches \
-            if dom == "radix_pass" else PASS_BYTES.get(dom, 24) * n
-        achieved = bytes_per_launch / (avg_ms / 1000.0) / 1e9
-        traffic = None
-        if n == 1 << 28:
-            traffic = counted_traffic("k_ds_pass<RadixDF>") if dom == "radix_pass" else \
-                counted_traffic("k_ds_pass<LearnedDF>", "c2_learned_hbm_bytes.md",
-                                LEARNED_PASS_SOURCES)
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "copy_gbs": COPY_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": dom, "avg_ms": avg_ms, "bytes_per_launch": int(bytes_per_launch)}
+        bytes_per_launch = (24 * n * (active / n_win) / launches if dom == "radix_pass"
+                            else PASS_BYTES[dom] * n)
+        tr = TRAFFIC.get(("c2", dom))
+        traffic = counted_traffic(tr[1], tr[0], tr[2]) if (tr and n == 1 << 28) else None
+        roof = roofline(passes, dom, bytes_per_launch, traffic)
 
-    check = None
-    cpu = None
-    if not a.no_cpu or not a.no_check:
+    check, cpu = None, None
+    if not (a.no_cpu and a.no_check):
         import oracle
         m = min(a.cpu_rows, n)
         host = rows[:m].cpu()
@@ -238,204 +650,43 @@ def main():
         g, tk, ts, cs = oracle.window_aggregate(host, LAYOUT32, W, n_win, k=10, n_threads=threads)
         dt = time.perf_counter() - t1
         cpu = {"value": round(m / dt / 1e6, 3), "unit": "Mrec/s", "cores": threads,
-               "kind": "oracle", "sample": f"first {m} of {n} rows (all their windows), "
-               f"ordered-map keyed aggregation + top-10, {dt:.1f} s"}
-        # windows fully inside the sample must agree exactly with the GPU
+               "host_cores": os.cpu_count(), "kind": "oracle",
+               "sample": f"first {m} of {n} rows (all their windows), ordered-map keyed "
+               f"aggregation + top-10, {dt:.1f} s on {threads} threads"}
+        # windows wholly inside the sample: every per-key array and the top-10
+        full = [w for w in range(n_win) if (w + 1) * n / n_win + n / 1000 < m]
+        hk, hr, hoff, _ = oracle.partition(host, LAYOUT32, W, n_win)
         gs = pipe.gseg.cpu().numpy().view(np.uint64)
         tkg = pipe.top_key.cpu().numpy().view(np.uint64).reshape(n_win, 10)
         tsg = pipe.top_sum.cpu().numpy().view(np.uint64).reshape(n_win, 10)
-        full = [w for w in range(n_win) if (w + 1) * n / n_win + n / 1000 < m]
-        ok = all(int(gs[w + 1] - gs[w]) == int(g[w]) and np.array_equal(tkg[w], tk[w]) and
-                 np.array_equal(tsg[w], ts[w]) for w in full)
-        check = {"windows_checked": full, "groups_and_top10_match_oracle": bool(ok)}
-        print(f"[bench] oracle sample: {dt:.1f} s on {threads} threads; check {check}",
-              file=sys.stderr, flush=True)
 
-    out = {
-        "metric": METRIC,
-        "value": round(value, 2),
-        "unit": "Mrec/s",
-        "n_gpus": 1,
-        "steps": a.steps,
-        "warmup": a.warmup,
-        "ms_per_step": round(max(ms_step, ms_wall), 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u64",
-        "data": "synthetic",
-        "config": {"workload": "windowed keyed aggregation: 2^28 32-byte rows, Zipf s=1.1 keys "
-                   "over 2^20, 10 tumbling 1 s windows, count/sum/max per key + top-10 by sum",
-                   "rows": n, "row_bytes": 32, "windows": n_win, "sort": a.algo},
-        "roofline": roof,
-        "cpu_baseline": cpu,
-        "passes": passes,
-        "check": check,
-    }
-    print(json.dumps(out), flush=True)
+        def one(w):
+            a0, b0 = int(hoff[w]), int(hoff[w + 1])
+            return w, oracle.reduce_by_key(hk[a0:b0], hr[a0:b0], host, LAYOUT32)
 
+        with cf.ThreadPoolExecutor(threads) as ex:
+            ores = dict(ex.map(one, full))
+        ok = True
+        for w in full:
+            g0, g1 = int(gs[w]), int(gs[w + 1])
+            got = [t[g0:g1].cpu().numpy().view(np.uint64) for t in
+                   (pipe.gkey, pipe.g["cnt"], pipe.g["sum"], pipe.g["max"])]
+            ok = ok and g1 - g0 == int(g[w]) and \
+                all(np.array_equal(x, y) for x, y in zip(got, ores[w])) and \
+                np.array_equal(tkg[w], tk[w]) and np.array_equal(tsg[w], ts[w])
+        check = {"windows_checked": full, "per_key_arrays_and_top10_match_oracle": bool(ok)}
+        log(f"oracle sample: {dt:.1f} s on {threads} threads; check {check}")
 
-def kernel_passes(K, steps, n, pass_bytes):
-    """Per-kernel launches per step, mean ms and algorithmic GB/s (recorded
-    with events on each launch's own stream since the last profile enable)."""
-    K.kpa_profile_collect()
-    passes = {}
-    for name in K.kpa_profile_names():
-        cnt, tot = K.kpa_profile_get(name)
-        if cnt == 0:
-            continue
-        avg = tot / cnt
-        entry = {"launches_per_step": cnt / steps, "avg_ms": round(avg, 4)}
-        if name in pass_bytes:
-            gbs = pass_bytes[name] * n / (avg / 1000.0) / 1e9
-            entry["alg_GBps"] = round(gbs, 1)
-            entry["hbm_frac"] = round(gbs / HBM_PEAK_GBS, 4)
-        passes[name] = entry
-    return passes
-
-
-def bench_c4(a):
-    import concurrent.futures as cf
-
-    import numpy as np
-    import torch
-
-    import datagen
-    import oracle
-    import paper_1901_01328_amd as P
-    from datagen.rows import LAYOUT32
-    from paper_1901_01328_amd.pipeline import BatchAggregation
-    K = P.load()
-    dev = torch.device("cuda:0")
-    sizes = datagen.c4_window_sizes(a.c4_windows, hi_log2=a.c4_hi_log2)
-    n = int(sizes.sum())
-    n_seg = len(sizes)
-    algo = K.KPA_SORT_LEARNED if a.algo == "learned" else K.KPA_SORT_RADIX
-    t0 = time.time()
-    rows = datagen.gen_c4(0, sizes, device=dev)
-    torch.cuda.synchronize()
-    print(f"[bench] c4 epoch 0: {n} rows in {n_seg} windows generated in {time.time() - t0:.1f} s",
-          file=sys.stderr, flush=True)
-    pipe = BatchAggregation(n, n_seg, LAYOUT32, device=dev,
-                            learned_ws=algo == K.KPA_SORT_LEARNED)
-    pipe.set_sizes(sizes)
-    radix = K.batch_config(large_algo=K.KPA_SORT_RADIX)
-    pipe.step(rows, cfg=radix)
-    pipe.fit_models()                      # epoch 1's models: epoch 0's sorted windows
-    datagen.gen_c4(1, sizes, out=rows)
-    pipe.step(rows, cfg=radix)             # extracts epoch 1 (the tuner sorts pipe.keys)
-    torch.cuda.synchronize()
-    print(f"[bench] c4 epoch 1 generated; models fitted ({time.time() - t0:.1f} s)",
-          file=sys.stderr, flush=True)
-    if a.no_tune:
-        cfg, tune_ms = K.batch_config(large_algo=algo), None
-    else:
-        cfg, tune_ms = K.kpa_batch_autotune(
-            pipe.keys, pipe.rids, pipe.seg_off, large_algo=algo, n_cap=n,
-            models=pipe.models if algo == K.KPA_SORT_LEARNED else None, reps=2,
-            keys_out=pipe.skeys, rids_out=pipe.srids, ws=pipe.ws_sort)
-        print(f"[bench] autotuned {cfg.as_dict()} ({tune_ms:.2f} ms sort)", file=sys.stderr,
-              flush=True)
-    stream = torch.cuda.Stream()
-    graph = pipe.capture(rows, stream, cfg=cfg)
-    for _ in range(a.warmup):
-        graph.launch(stream)
-    stream.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    wall0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(a.steps):
-        graph.launch(stream)
-    ev1.record(stream)
-    stream.synchronize()
-    wall = time.perf_counter() - wall0
-    ms_step = max(ev0.elapsed_time(ev1), wall * 1000) / a.steps
-    value = n / (ms_step / 1000.0) / 1e6
-    print(f"[bench] c4 timed {a.steps} graph replays: {ms_step:.3f} ms/step", file=sys.stderr,
-          flush=True)
-    # Per-kernel times: the same step run eagerly with event timing per launch.
-    K.kpa_profile_enable(True)
-    prof_steps = 2
-    for _ in range(prof_steps):
-        pipe.step(rows, stream=stream, cfg=cfg)
-    stream.synchronize()
-    c4_bytes = dict(PASS_BYTES, extract=44)
-    passes = kernel_passes(K, prof_steps, n, c4_bytes)
-    K.kpa_profile_enable(False)
-    st = pipe.stats.cpu().numpy().tolist()
-    graph.destroy()
-
-    # Oracle: every 16th window (their rows copied to the host), per window
-    # the ordered-map keyed aggregation; the GPU's groups of those windows
-    # must match exactly.
-    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
-    sample = list(range(0, n_seg, 16))
-    goff = pipe.gseg.cpu().numpy().view(np.uint64)
-    gk, gc, gs, gm = (t.cpu().numpy().view(np.uint64) for t in
-                      (pipe.gkey, pipe.g["cnt"], pipe.g["sum"], pipe.g["max"]))
-    host = {j: rows[off[j]:off[j + 1]].cpu() for j in sample}
-    threads = min(16, os.cpu_count() or 1)
-
-    def one(j):
-        r = host[j]
-        keys, rids = oracle.extract(r, LAYOUT32)
-        return j, oracle.reduce_by_key(keys, rids, r, LAYOUT32)
-
-    t1 = time.perf_counter()
-    with cf.ThreadPoolExecutor(threads) as ex:
-        res = list(ex.map(one, sample))
-    dt = time.perf_counter() - t1
-    m = int(sum(sizes[j] for j in sample))
-    ok = True
-    for j, (ek, ec, es, em) in res:
-        a0, b0 = int(goff[j]), int(goff[j + 1])
-        ok = ok and b0 - a0 == len(ek) and np.array_equal(gk[a0:b0], ek) and \
-            np.array_equal(gc[a0:b0], ec) and np.array_equal(gs[a0:b0], es) and \
-            np.array_equal(gm[a0:b0], em)
-    check = {"windows_checked": len(sample), "groups_match_oracle": bool(ok)}
-    cpu = {"value": round(m / dt / 1e6, 3), "unit": "Mrec/s", "cores": threads, "kind": "oracle",
-           "sample": f"every 16th window ({len(sample)} windows, {m} rows): extract + "
-           f"ordered-map count/sum/max per key, {dt:.1f} s"}
-    dom = "radix_pass" if algo == K.KPA_SORT_RADIX else "learned_scatter"
-    roof = None
-    if dom in passes:
-        # bytes: 24 per entry of the large windows that take part in a launch;
-        # all of them for the learned scatter, the active windows for radix
-        large = int(sizes[sizes > cfg.mid_cap].sum())
-        pl = passes[dom]
-        per_launch = 24 * large if dom == "learned_scatter" else None
-        if per_launch is None:
-            # C4 keys vary in bits 12..31 (plus carries of the offset): count
-            # the radix passes each large window needs from its own keys
-            sk = pipe.skeys
-            act = 0
-            for j in np.nonzero(sizes > cfg.mid_cap)[0]:
-                seg = sk[int(off[j]):int(off[j + 1])]
-                x = seg ^ seg[0]
-                act += int(sizes[j]) * sum(1 for p in range(8)
-                                           if bool((((x >> (8 * p)) & 255) != 0).any()))
-            per_launch = 24 * act / pl["launches_per_step"]
-        achieved = per_launch / (pl["avg_ms"] / 1000.0) / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "copy_gbs": COPY_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": dom, "avg_ms": pl["avg_ms"], "bytes_per_launch": int(per_launch)}
-    out = {
+    return {
         "metric": METRIC, "value": round(value, 2), "unit": "Mrec/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": f"{n_seg} substream windows, log-uniform 2^10..2^{a.c4_hi_log2} "
-                   "rows of 32 bytes, drifting rank-Zipf keys; extract + batched sort + "
-                   "count/sum/max per key, one graph replay per step",
-                   "rows": n, "windows": n_seg, "sort": a.algo, "batch_config": cfg.as_dict(),
-                   "autotune_sort_ms": tune_ms},
-        "roofline": roof, "cpu_baseline": cpu, "passes": passes, "sort_stats": st,
-        "check": check,
+        "config": {"workload": "windowed keyed aggregation: 2^28 32-byte rows, Zipf s=1.1 keys "
+                   "over 2^20, 10 tumbling 1 s windows, count/sum/max per key + top-10 by sum",
+                   "rows": n, "row_bytes": 32, "windows": n_win, "sort": a.algo},
+        "roofline": roof, "cpu_baseline": cpu, "passes": passes, "check": check,
     }
-    print(json.dumps(out), flush=True)
 
 
 def bench_c3(a):
@@ -443,8 +694,6 @@ def bench_c3(a):
     over 2^24 (one key table for both), values uniform over u64, 10 tumbling
     1 s windows.  One step = partition + sort both streams, lower median per
     key on both, merge-join per window (count, sum of products mod 2^64)."""
-    import concurrent.futures as cf
-
     import numpy as np
     import torch
 
@@ -464,7 +713,6 @@ def bench_c3(a):
     for _ in range(a.warmup):
         pipe.step(rows_l, rows_r)
     torch.cuda.synchronize()
-    K.kpa_profile_enable(True)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -476,11 +724,14 @@ def bench_c3(a):
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     ms_step = max(ev0.elapsed_time(ev1), wall * 1000) / a.steps
-    passes = kernel_passes(K, a.steps, 2 * n, PASS_BYTES)
+    K.kpa_profile_enable(True)
+    for _ in range(2):
+        pipe.step(rows_l, rows_r)
+    torch.cuda.synchronize()
+    passes = kernel_passes(K, 2, 2 * n, PASS_BYTES)
     K.kpa_profile_enable(False)
     value = 2 * n / (ms_step / 1000.0) / 1e6
-    print(f"[bench] c3 timed {a.steps} steps: {ms_step:.3f} ms/step", file=sys.stderr, flush=True)
-    # oracle: two windows (every entry of them), both operators
+    log(f"c3 timed {a.steps} steps: {ms_step:.3f} ms/step")
     L, R = pipe.side
     hl, hr = rows_l.cpu(), rows_r.cpu()
     cnt = pipe.join["count"].cpu().numpy().view(np.uint64)
@@ -498,35 +749,33 @@ def bench_c3(a):
         rk, rr = win(hr, w)
         c, s_, _, _ = oracle.join(lk, lr, rk, rr, hl, hr, LAYOUT32)
         mk, mm = oracle.median_by_key(lk, lr, hl, LAYOUT32)
-        return w, c, s_, mk, mm, len(lk) + len(rk)
+        nk, nm = oracle.median_by_key(rk, rr, hr, LAYOUT32)
+        return w, c, s_, (mk, mm), (nk, nm), len(lk) + len(rk)
 
     with cf.ThreadPoolExecutor(len(checked)) as ex:
         res = list(ex.map(one, checked))
     dt = time.perf_counter() - t1
-    goff = L["med"]["gseg_off"].cpu().numpy().view(np.uint64)
-    gk = L["med"]["gkey"].cpu().numpy().view(np.uint64)
-    gm = L["med"]["gmed"].cpu().numpy().view(np.uint64)
     m_rows = 0
-    for w, c, s_, mk, mm, nr in res:
-        a0, b0 = int(goff[w]), int(goff[w + 1])
-        ok = ok and int(cnt[w]) == c and int(sp[w]) == s_ and np.array_equal(gk[a0:b0], mk) \
-            and np.array_equal(gm[a0:b0], mm)
+    for w, c, s_, lmed, rmed, nr in res:
+        ok = ok and int(cnt[w]) == c and int(sp[w]) == s_
+        for side, med in ((L, lmed), (R, rmed)):
+            goff = side["med"]["gseg_off"].cpu().numpy().view(np.uint64)
+            a0, b0 = int(goff[w]), int(goff[w + 1])
+            ok = ok and np.array_equal(side["med"]["gkey"][a0:b0].cpu().numpy().view(np.uint64),
+                                       med[0]) and \
+                np.array_equal(side["med"]["gmed"][a0:b0].cpu().numpy().view(np.uint64), med[1])
         m_rows += nr
-    check = {"windows_checked": checked, "join_and_left_median_match_oracle": bool(ok),
+    check = {"windows_checked": checked, "join_and_both_medians_match_oracle": bool(ok),
              "pairs_per_window": int(cnt[checked[0]])}
     cpu = {"value": round(m_rows / dt / 1e6, 3), "unit": "Mrec/s", "cores": len(checked),
-           "kind": "oracle", "sample": f"windows {checked} of both streams ({m_rows} rows): "
-           f"ordered-map join + median per key, {dt:.1f} s"}
+           "host_cores": os.cpu_count(), "kind": "oracle",
+           "sample": f"windows {checked} of both streams ({m_rows} rows): ordered-map join + "
+           f"median per key, {dt:.1f} s"}
     roof = None
     if "radix_pass" in passes:
         pl = passes["radix_pass"]
-        per_launch = 24 * 2 * n * 8 / pl["launches_per_step"]   # all 8 digits vary
-        achieved = per_launch / (pl["avg_ms"] / 1000.0) / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "copy_gbs": COPY_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "radix_pass", "avg_ms": pl["avg_ms"], "bytes_per_launch": int(per_launch)}
-    out = {
+        roof = roofline(passes, "radix_pass", 24 * 2 * n * 8 / pl["launches_per_step"])
+    return {
         "metric": METRIC, "value": round(value, 2), "unit": "Mrec/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
@@ -535,16 +784,15 @@ def bench_c3(a):
                    "uniform over 2^24, 10 tumbling 1 s windows", "rows": 2 * n, "windows": n_win},
         "roofline": roof, "cpu_baseline": cpu, "passes": passes, "check": check,
     }
-    print(json.dumps(out), flush=True)
 
 
-def bench_c5(a):
+def serve_leg(rate, duration, host_rows=False, pool_rows=1 << 25):
     """Serving: Poisson-arriving bundles (sizes log-uniform 2^13..2^20 rows)
     at the offered rate over 16 queries (8 windowed sums, 4 medians, 4 joins
     whose bundles alternate sides), 1 s tumbling windows with origins
     staggered by 1/16 s, a watermark per query every 100 ms of event time.
     Bundles are replayed from pinned pools of pre-generated rows, moved to
-    their event time at ingest.  Reports sustained Mrec/s and the p50/p99 of
+    their event time at ingest.  Returns sustained Mrec/s and the p50/p99 of
     window-close-to-result latency."""
     import numpy as np
     import torch
@@ -554,7 +802,6 @@ def bench_c5(a):
     from datagen.rows import LAYOUT32
     K = P.load()
     dev = torch.device("cuda:0")
-    pool_rows = 1 << 25
     t0 = time.time()
     pools = []
     for kind in ("sum", "c3"):
@@ -568,16 +815,15 @@ def bench_c5(a):
         del rows, i
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
-    print(f"[bench] c5 pools of {pool_rows} rows generated in {time.time() - t0:.1f} s",
-          file=sys.stderr, flush=True)
+    log(f"serving pools of {pool_rows} rows generated in {time.time() - t0:.1f} s")
     W = 10 ** 9
-    srv = K.Server(budget_bytes=64 << 30, slots=8, rows_in_host=1 if a.host_rows else 0,
+    srv = K.Server(budget_bytes=64 << 30, slots=8, rows_in_host=1 if host_rows else 0,
                    max_bundle_rows=1 << 20, max_pending=1024)
     kinds = [K.KPA_Q_SUM] * 8 + [K.KPA_Q_MEDIAN] * 4 + [K.KPA_Q_JOIN] * 4
     qids = [srv.add_query(k, LAYOUT32, W, q * (W // 16)) for q, k in enumerate(kinds)]
     rng = np.random.default_rng(55)
     mean_rows = (2 ** 20 - 2 ** 13) / np.log(2 ** 7)      # log-uniform mean
-    lam = a.rate / mean_rows                             # bundles per second
+    lam = rate / mean_rows                               # bundles per second
     side_next = [0] * len(qids)
     n_sub = 0
     last_wm = [0] * len(qids)
@@ -586,33 +832,32 @@ def bench_c5(a):
     last_print = 0.0
     while True:
         t_next += rng.exponential(1.0 / lam)
-        if t_next > a.duration:
+        if t_next > duration:
             break
         now = time.perf_counter() - start
         if t_next > now:
             time.sleep(t_next - now)
-        n = int(2 ** rng.uniform(13, 20))
+        nb = int(2 ** rng.uniform(13, 20))
         q = n_sub % len(qids)
         pool = pools[0] if kinds[q] == K.KPA_Q_SUM else pools[1]
-        off = int(rng.integers(0, pool_rows - n))
+        o = int(rng.integers(0, pool_rows - nb))
         side = 0
         if kinds[q] == K.KPA_Q_JOIN:
             side = side_next[q]
             side_next[q] ^= 1
         ev = int(t_next * 1e9) + W        # event time of the bundle (ns)
-        srv.submit(qids[q], pool[off:off + n], side=side, ts_base=ev, ts_lo=0, ts_hi=10 ** 6 - 1)
+        srv.submit(qids[q], pool[o:o + nb], side=side, ts_base=ev, ts_lo=0, ts_hi=10 ** 6 - 1)
         n_sub += 1
-        # watermarks: every 100 ms of event time, at the latest arrival
-        for qq in range(len(qids)):
+        for qq in range(len(qids)):       # watermarks: every 100 ms of event time
             if ev - last_wm[qq] >= 10 ** 8:
                 srv.watermark(qids[qq], ev)
                 last_wm[qq] = ev
         if now - last_print > 5:
             st = srv.stats()
-            print(f"[bench] c5 t={now:.1f}s bundles={n_sub} closed={st['windows_closed']} "
-                  f"p99={st['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
+            log(f"serving t={now:.1f}s bundles={n_sub} closed={st['windows_closed']} "
+                f"p99={st['p99_ms']:.1f} ms")
             last_print = now
-    end_ev = int(a.duration * 1e9) + 2 * W + 10 ** 6
+    end_ev = int(duration * 1e9) + 2 * W + 10 ** 6
     for qq in range(len(qids)):
         srv.watermark(qids[qq], end_ev)
     srv.drain(timeout_ms=120000)
@@ -621,22 +866,30 @@ def bench_c5(a):
     srv.close()
     lat = sorted(r["latency_ms"] for r in res)
     # the closes at the end (after the last watermark) are not steady state
-    steady = [r["latency_ms"] for r in res if r["window"] < int(a.duration) - 1]
-    steady.sort()
+    steady = sorted(r["latency_ms"] for r in res if r["window"] < int(duration) - 1)
     pct = (lambda v, p: v[min(len(v) - 1, int(p * (len(v) - 1) + 0.5))] if v else None)
-    out = {
-        "metric": METRIC, "value": round(st["mrec_per_s"], 2), "unit": "Mrec/s", "n_gpus": 1,
-        "steps": n_sub, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
+    return {"offered_mrec_per_s": rate / 1e6, "duration_s": duration, "bundles": n_sub,
+            "mrec_per_s": round(st["mrec_per_s"], 2),
+            "latency_ms": {"p50": pct(steady, 0.5), "p99": pct(steady, 0.99),
+                           "max": lat[-1] if lat else None, "windows": len(steady)},
+            "rows_in_host": bool(host_rows), "budget_gib": 64,
+            "queries": "8 sum + 4 median + 4 join, 1 s windows, watermark every 100 ms",
+            "server": st}
+
+
+def bench_c5(a):
+    s = serve_leg(a.rate, a.duration, host_rows=a.host_rows)
+    return {
+        "metric": METRIC, "value": s["mrec_per_s"], "unit": "Mrec/s", "n_gpus": 1,
+        "steps": s["bundles"], "warmup": 0, "ms_per_step": None, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": "serving: Poisson bundles of 2^13..2^20 32-byte rows at "
                    f"{a.rate / 1e6:.0f} M rec/s offered, 8 sum + 4 median + 4 join queries, "
                    "1 s windows, watermark every 100 ms", "duration_s": a.duration,
                    "rows_in_host": bool(a.host_rows), "budget_gib": 64},
-        "latency_ms": {"p50": pct(steady, 0.5), "p99": pct(steady, 0.99), "max": lat[-1] if lat
-                       else None, "windows": len(steady)},
-        "server": st, "roofline": None, "cpu_baseline": None,
+        "latency_ms": s["latency_ms"], "server": s["server"], "roofline": None,
+        "cpu_baseline": None,
     }
-    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

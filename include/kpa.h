@@ -495,6 +495,38 @@ kpa_status kpa_window_panes(const uint64_t* gkey, const uint64_t* gseg_off, uint
                             uint64_t* out_seg_off, uint64_t out_cap, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * The two alternatives the paper measures its KPA grouping against.
+ *
+ * Grouping on full rows (the design without KPAs of the ablation in Sec. 7.3):
+ * out_rows receives all n rows ordered by (window, key), stably, so each
+ * window's rows are grouped by key in arrival order; rows in no window (window
+ * rule as kpa_partition_windows) count as window n_win and come last.
+ * out_win_off (device, n_win+1) delimits the windows; *out_oob (device) counts
+ * the rows after out_win_off[n_win].  Nine onesweep passes move whole rows (the
+ * eight key bytes, then the window).  row_bytes 16 or 32, n < 2^30,
+ * 1 <= n_win <= 255; rows and out_rows device, not aliased. */
+kpa_status kpa_sort_rows_windowed_workspace_size(uint64_t n, uint32_t row_bytes, size_t* bytes);
+kpa_status kpa_sort_rows_windowed(const void* rows, uint64_t n, const kpa_row_layout* layout,
+                                  uint64_t win_len, uint64_t win_origin, uint32_t n_win,
+                                  void* out_rows, uint64_t* out_win_off, uint64_t* out_oob,
+                                  void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Hash GroupBy (Sec. 2.2: the random-access alternative, an open-addressing
+ * pre-allocated table): per distinct key of the rows, count, sum (mod 2^64)
+ * and max of the value column, in the table's order (not sorted by key).
+ * table_cap: slots, a power of two up to 2^31, larger than the number of
+ * distinct keys (linear probing).  Up to g_cap groups are written to
+ * out_gkey/out_cnt/out_sum/out_max (device; the last three may be NULL);
+ * *out_ngroups (device) receives the number of groups, or all ones when a key
+ * found no free slot (table_cap too small).  All device. */
+kpa_status kpa_hash_groupby_workspace_size(uint64_t table_cap, size_t* bytes);
+kpa_status kpa_hash_groupby(const void* rows, uint64_t n, const kpa_row_layout* layout,
+                            uint64_t table_cap, uint64_t* out_gkey, uint64_t* out_cnt,
+                            uint64_t* out_sum, uint64_t* out_max, uint64_t g_cap,
+                            uint64_t* out_ngroups, void* ws, size_t ws_bytes,
+                            hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * CDF models for the learned-splitter sort.
  *
  * kpa_pwl_fit: for each segment of a sorted KPA, kmin/kmax = first/last key and

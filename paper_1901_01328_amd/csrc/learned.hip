@@ -1271,7 +1271,7 @@ kpa_status learned_sort_launch(const u64* keys_in, const u32* rids_in, u64* keys
   KPA_CHECK(launch_seg_tiles_list(sl, FH, lw.ftile_start, st));
   KPA_CHECK(launch_tile_seg(lw.ftile_start, n_seg, sl.n_dev, lw.max_ftiles, lw.ftile_seg, st));
   KPA_CHECK(launch_fill_u32(lw.fn_active, 1, 0, st));
-  KPA_LAUNCH("learned_finish", k_fin_active,
+  KPA_LAUNCH("learned_finish_list", k_fin_active,
              dim3((u32)std::min<u64>(ceil_div(lw.max_ftiles, BLOCK), 4096)), dim3(BLOCK), 0, st,
              keys_out, sl, lw.ftile_start, lw.ftile_seg, lw.segm, (u32)lw.max_ftiles, lw.factive,
              lw.fn_active);

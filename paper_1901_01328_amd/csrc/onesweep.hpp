@@ -217,13 +217,12 @@ __device__ __forceinline__ u32 onesweep_rank_stage(OnesweepSmemT<NW>& sm, const 
 // lower index was claimed by a running workgroup before this one and
 // publishes its count before waiting on anything, so the loop ends; the
 // segment's first tile always holds a prefix.
+// The look-back alone: sets sm.gbase (each digit's global destination) and
+// sm.count, and ends with a barrier; the caller then writes the staged tile.
 template <int NW>
-__device__ __forceinline__ void onesweep_lookback_write(OnesweepSmemT<NW>& sm,
-                                                        u32* __restrict__ status, u32 tile,
-                                                        u32 tile_in_seg, u32 total,
-                                                        u32 tile_count, u64 my_digit_base,
-                                                        u64* __restrict__ keys_out,
-                                                        u32* __restrict__ rids_out) {
+__device__ __forceinline__ void onesweep_lookback(OnesweepSmemT<NW>& sm, u32* __restrict__ status,
+                                                  u32 tile, u32 tile_in_seg, u32 total,
+                                                  u32 tile_count, u64 my_digit_base) {
   const u32 tid = threadIdx.x;
   if (tid < RADIX) {
     u32* my = status + (u64)tile * RADIX + tid;
@@ -262,6 +261,16 @@ __device__ __forceinline__ void onesweep_lookback_write(OnesweepSmemT<NW>& sm,
   }
   if (tid == 0) sm.count = tile_count;
   __syncthreads();
+}
+
+template <int NW>
+__device__ __forceinline__ void onesweep_lookback_write(OnesweepSmemT<NW>& sm,
+                                                        u32* __restrict__ status, u32 tile,
+                                                        u32 tile_in_seg, u32 total,
+                                                        u32 tile_count, u64 my_digit_base,
+                                                        u64* __restrict__ keys_out,
+                                                        u32* __restrict__ rids_out) {
+  onesweep_lookback<NW>(sm, status, tile, tile_in_seg, total, tile_count, my_digit_base);
   write_staged<OnesweepSmemT<NW>, NW>(sm, keys_out, rids_out);
 }
 

@@ -176,6 +176,12 @@ _SIGS = {
                           _vp, C.c_size_t, _vp], C.c_int32),
     "kpa_unique_count_by_key": ([_vp, _vp, _vp, _u32, _u64, _vp, _lay, _vp, _vp, _vp, _vp,
                                  C.c_size_t, _vp], C.c_int32),
+    "kpa_sort_rows_windowed_workspace_size": ([_u64, _u32, _sz], C.c_int32),
+    "kpa_sort_rows_windowed": ([_vp, _u64, _lay, _u64, _u64, _u32, _vp, _vp, _vp, _vp, C.c_size_t,
+                                _vp], C.c_int32),
+    "kpa_hash_groupby_workspace_size": ([_u64, _sz], C.c_int32),
+    "kpa_hash_groupby": ([_vp, _u64, _lay, _u64, _vp, _vp, _vp, _vp, _u64, _vp, _vp, C.c_size_t,
+                          _vp], C.c_int32),
     "kpa_window_panes": ([_vp, _vp, _u32, _u32, _vp, _vp, _vp, _u64, _vp], C.c_int32),
     "kpa_partition_kpa": ([_vp, _vp, _u64, _u64, _u64, _u32, _vp, _vp, _vp, _vp, _vp, C.c_size_t,
                            _vp], C.c_int32),
@@ -718,6 +724,46 @@ def kpa_unique_count_by_key(keys, rids, seg_off, rows, layout, n_cap=None, outs=
     L = layout_struct(layout)
     _call("kpa_unique_count_by_key", _p(keys), _p(rids), _p(seg_off), n_seg, n_cap, _p(rows),
           C.byref(L), _p(o["gkey"]), _p(o["uniq"]), _p(o["gseg_off"]), _p(ws),
+          ws.numel() * ws.element_size(), _stream(stream))
+    return o
+
+
+def kpa_sort_rows_windowed(rows, layout, win_len, n_win, win_origin=0, n=None, out_rows=None,
+                           out_win_off=None, out_oob=None, ws=None, stream=None):
+    """Rows ordered by (window, key) stably, moving whole rows: (out_rows, win_off, oob)."""
+    n = rows_count(rows, layout) if n is None else n
+    dev = rows.device
+    if out_rows is None:
+        out_rows = torch.empty(max(n, 1) * layout.row_bytes // 8, dtype=torch.int64, device=dev)
+    out_win_off = (torch.empty(n_win + 1, dtype=torch.int64, device=dev)
+                   if out_win_off is None else out_win_off)
+    out_oob = torch.empty(1, dtype=torch.int64, device=dev) if out_oob is None else out_oob
+    nb = C.c_size_t(0)
+    _call("kpa_sort_rows_windowed_workspace_size", n, layout.row_bytes, C.byref(nb))
+    ws = _ws(int(nb.value), dev, ws)
+    L = layout_struct(layout)
+    _call("kpa_sort_rows_windowed", _p(rows), n, C.byref(L), win_len, win_origin, n_win,
+          _p(out_rows), _p(out_win_off), _p(out_oob), _p(ws), ws.numel() * ws.element_size(),
+          _stream(stream))
+    return out_rows, out_win_off, out_oob
+
+
+def kpa_hash_groupby(rows, layout, table_cap, g_cap=None, n=None, outs=None, ws=None,
+                     stream=None):
+    """Groups in table order: dict gkey, cnt, sum, max (device, g_cap) and ngroups."""
+    n = rows_count(rows, layout) if n is None else n
+    dev = rows.device
+    g_cap = table_cap + 1 if g_cap is None else g_cap
+    o = dict(outs or {})
+    for name in ("gkey", "cnt", "sum", "max"):
+        if name not in o:
+            o[name] = torch.empty(max(g_cap, 1), dtype=torch.int64, device=dev)
+    if "ngroups" not in o:
+        o["ngroups"] = torch.empty(1, dtype=torch.int64, device=dev)
+    ws = _ws(_ws_size("kpa_hash_groupby_workspace_size", table_cap), dev, ws)
+    L = layout_struct(layout)
+    _call("kpa_hash_groupby", _p(rows), n, C.byref(L), table_cap, _p(o["gkey"]), _p(o["cnt"]),
+          _p(o["sum"]), _p(o["max"]), g_cap, _p(o["ngroups"]), _p(ws),
           ws.numel() * ws.element_size(), _stream(stream))
     return o
 

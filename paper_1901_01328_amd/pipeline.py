@@ -127,6 +127,7 @@ class BatchAggregation:
         self.ws_red = torch.empty(K._ws_size("kpa_reduce_by_key_workspace_size", n_rows, n_seg),
                                   **u8)
         self.models = K.new_models(n_seg, d)
+        self.next_models = K.new_models(n_seg, d)
         self.stats = K.new_sort_stats(d)
 
     def set_sizes(self, sizes):
@@ -141,7 +142,11 @@ class BatchAggregation:
         on the next epoch's windows)."""
         K.kpa_pwl_fit(self.skeys, self.seg_off, 1024, models=self.models, stream=stream)
 
-    def step(self, rows, stream=None, cfg=None):
+    def step(self, rows, stream=None, cfg=None, fit_next=False):
+        """Extract, batched sort, keyed reduction.  With fit_next, the step also
+        fits each window's PWL model on its sorted KPA into next_models (the
+        models the next epoch's windows would be sorted with); the models in
+        use are not touched, so repeated steps do identical work."""
         cfg = self.cfg if cfg is None else cfg
         K.kpa_extract(rows, self.layout, out_keys=self.keys, out_rids=self.rids,
                       out_vals=self.vals, n=self.n, stream=stream)
@@ -155,12 +160,14 @@ class BatchAggregation:
         K.kpa_reduce_by_key(self.skeys, self.srids, self.seg_off, self.vals, VALUE_COLUMN,
                             n_cap=self.n, want=self.want, ws=self.ws_red, stream=stream,
                             outs=outs)
+        if fit_next:
+            K.kpa_pwl_fit(self.skeys, self.seg_off, 1024, models=self.next_models, stream=stream)
 
-    def capture(self, rows, stream, cfg=None):
+    def capture(self, rows, stream, cfg=None, fit_next=False):
         """A graph of one step on `stream` (replay with .launch())."""
         g = K.Graph.capture(stream)
         with g:
-            self.step(rows, stream=stream, cfg=cfg)
+            self.step(rows, stream=stream, cfg=cfg, fit_next=fit_next)
         return g
 
 
