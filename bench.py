@@ -121,7 +121,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5", "ablations"], default="c4")
+    ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5", "ablations", "adapt"],
+                    default="c4")
     ap.add_argument("--algo", choices=["radix", "learned"], default="radix", help="c2 only")
     ap.add_argument("--rows", type=int, default=1 << 28, help="c2 rows")
     ap.add_argument("--cpu-rows", type=int, default=3 << 26,
@@ -165,7 +166,7 @@ def main():
         del src, dst
     else:
         COPY_GBS = measure_copy_rate(dev)
-    out = {"c4": bench_c4, "c2": bench_c2, "c3": bench_c3, "c5": bench_c5,
+    out = {"c4": bench_c4, "c2": bench_c2, "c3": bench_c3, "c5": bench_c5, "adapt": bench_adapt,
            "ablations": lambda a: {"metric": METRIC, "ablations": ablation_leg(a.steps, a.warmup)}
            }[a.workload](a)
     print(json.dumps(out), flush=True)
@@ -786,14 +787,19 @@ def bench_c3(a):
     }
 
 
-def serve_leg(rate, duration, host_rows=False, pool_rows=1 << 25):
+def serve_leg(rate, duration, host_rows=False, pool_rows=1 << 25, rate_end=None, wm_lag_s=0.0,
+              server_cfg=None, trace=False):
     """Serving: Poisson-arriving bundles (sizes log-uniform 2^13..2^20 rows)
     at the offered rate over 16 queries (8 windowed sums, 4 medians, 4 joins
     whose bundles alternate sides), 1 s tumbling windows with origins
     staggered by 1/16 s, a watermark per query every 100 ms of event time.
     Bundles are replayed from pinned pools of pre-generated rows, moved to
     their event time at ingest.  Returns sustained Mrec/s and the p50/p99 of
-    window-close-to-result latency."""
+    window-close-to-result latency.  rate_end: the offered rate grows linearly
+    from `rate` to `rate_end` over the run; wm_lag_s: watermarks trail the
+    arrivals by that much event time (windows stay open longer); server_cfg:
+    overrides of the server configuration; trace: return the monitor's
+    samples (placement experiments)."""
     import numpy as np
     import torch
 
@@ -817,13 +823,19 @@ def serve_leg(rate, duration, host_rows=False, pool_rows=1 << 25):
     torch.cuda.empty_cache()
     log(f"serving pools of {pool_rows} rows generated in {time.time() - t0:.1f} s")
     W = 10 ** 9
-    srv = K.Server(budget_bytes=64 << 30, slots=8, rows_in_host=1 if host_rows else 0,
-                   max_bundle_rows=1 << 20, max_pending=1024)
+    cfg = dict(budget_bytes=64 << 30, slots=8, rows_in_host=1 if host_rows else 0,
+               max_bundle_rows=1 << 20, max_pending=1024)
+    cfg.update(server_cfg or {})
+    srv = K.Server(**cfg)
     kinds = [K.KPA_Q_SUM] * 8 + [K.KPA_Q_MEDIAN] * 4 + [K.KPA_Q_JOIN] * 4
     qids = [srv.add_query(k, LAYOUT32, W, q * (W // 16)) for q, k in enumerate(kinds)]
     rng = np.random.default_rng(55)
     mean_rows = (2 ** 20 - 2 ** 13) / np.log(2 ** 7)      # log-uniform mean
-    lam = rate / mean_rows                               # bundles per second
+
+    def lam_at(t):                                       # bundles per second at time t
+        r = rate if rate_end is None else rate + (rate_end - rate) * min(1.0, t / duration)
+        return r / mean_rows
+    lag = int(wm_lag_s * 1e9)
     side_next = [0] * len(qids)
     n_sub = 0
     last_wm = [0] * len(qids)
@@ -831,7 +843,7 @@ def serve_leg(rate, duration, host_rows=False, pool_rows=1 << 25):
     t_next = 0.0
     last_print = 0.0
     while True:
-        t_next += rng.exponential(1.0 / lam)
+        t_next += rng.exponential(1.0 / lam_at(t_next))
         if t_next > duration:
             break
         now = time.perf_counter() - start
@@ -849,9 +861,9 @@ def serve_leg(rate, duration, host_rows=False, pool_rows=1 << 25):
         srv.submit(qids[q], pool[o:o + nb], side=side, ts_base=ev, ts_lo=0, ts_hi=10 ** 6 - 1)
         n_sub += 1
         for qq in range(len(qids)):       # watermarks: every 100 ms of event time
-            if ev - last_wm[qq] >= 10 ** 8:
-                srv.watermark(qids[qq], ev)
-                last_wm[qq] = ev
+            if ev - lag - last_wm[qq] >= 10 ** 8:
+                srv.watermark(qids[qq], ev - lag)
+                last_wm[qq] = ev - lag
         if now - last_print > 5:
             st = srv.stats()
             log(f"serving t={now:.1f}s bundles={n_sub} closed={st['windows_closed']} "
@@ -863,18 +875,53 @@ def serve_leg(rate, duration, host_rows=False, pool_rows=1 << 25):
     srv.drain(timeout_ms=120000)
     st = srv.stats()
     res = srv.results()
+    tr = srv.trace() if trace else None
     srv.close()
     lat = sorted(r["latency_ms"] for r in res)
     # the closes at the end (after the last watermark) are not steady state
     steady = sorted(r["latency_ms"] for r in res if r["window"] < int(duration) - 1)
     pct = (lambda v, p: v[min(len(v) - 1, int(p * (len(v) - 1) + 0.5))] if v else None)
-    return {"offered_mrec_per_s": rate / 1e6, "duration_s": duration, "bundles": n_sub,
+    extra = {}
+    if tr is not None:
+        step = max(1, len(tr) // 40)
+        extra["trace"] = [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in t.items()}
+                          for t in tr[::step]]
+        extra["runs_total"] = sum(r["runs"] for r in res)
+        extra["runs_from_host"] = sum(r["runs_host"] for r in res)
+    return {**extra, "offered_mrec_per_s": rate / 1e6, "duration_s": duration, "bundles": n_sub,
             "mrec_per_s": round(st["mrec_per_s"], 2),
             "latency_ms": {"p50": pct(steady, 0.5), "p99": pct(steady, 0.99),
                            "max": lat[-1] if lat else None, "windows": len(steady)},
             "rows_in_host": bool(host_rows), "budget_gib": 64,
             "queries": "8 sum + 4 median + 4 join, 1 s windows, watermark every 100 ms",
             "server": st}
+
+
+def bench_adapt(a):
+    """The paper's two adaptation experiments (Sec. 7.3), with the capacity
+    tier a pinned host pool and a small device budget so that placement
+    matters: (a) the offered rate ramps from 200M to 1.6G rec/s over the run;
+    (b) watermarks trail the arrivals by 3 s at 400M rec/s, so windows stay
+    open and hold their KPAs longer.  Balanced placement (impact tags and the
+    demand balance knob) against all-device placement on the same input."""
+    runs = {}
+    base = dict(budget_bytes=6 << 30, host_pool_bytes=48 << 30, monitor_ms=10,
+                target_delay_ms=1000.0, rows_in_host=1)
+    for name, kw in (("rate_ramp", dict(rate=200e6, rate_end=1.6e9)),
+                     ("delayed_watermarks", dict(rate=400e6, wm_lag_s=3.0))):
+        for placement in ("balanced", "device"):
+            import paper_1901_01328_amd as P
+            K = P.load()
+            cfg = dict(base, placement=K.KPA_PLACE_BALANCED if placement == "balanced"
+                       else K.KPA_PLACE_DEVICE)
+            if placement == "device":
+                cfg.pop("host_pool_bytes")
+            log(f"adapt {name} {placement}")
+            r = serve_leg(duration=a.duration, host_rows=True, server_cfg=cfg,
+                          trace=placement == "balanced", **kw)
+            runs.setdefault(name, {})[placement] = r
+    return {"metric": METRIC, "workload": "adaptation: serving with a 6 GiB device budget, a "
+            "48 GiB pinned host pool, rows kept on the host", "runs": runs}
 
 
 def bench_c5(a):

@@ -624,7 +624,41 @@ typedef struct kpa_server_config {
   uint32_t max_pending;      /* queued bundles before submit applies back-pressure */
   uint32_t reserve_pct;      /* % of the pool reserved for window closes (<= 90) */
   uint32_t max_live_bundles; /* bundles admitted and not yet released */
+  /* Capacity tier (Sec. 5): pinned host memory that holds bundle KPAs (sorted
+   * keys and values) the placement sends there; kernels of the window close
+   * read them over the host link. */
+  uint64_t host_pool_bytes;  /* 0: no capacity tier */
+  uint32_t placement;        /* a kpa_placement */
+  uint32_t monitor_ms;       /* knob refresh interval (Sec. 5 samples every 10 ms) */
+  double target_delay_ms;    /* output delay target of the k_high rule */
+  double host_bw_gbs;        /* host-link bandwidth taken as full use (0: measured) */
+  uint32_t keep_groups;      /* 1: SUM and MEDIAN results carry their per-key arrays */
+  uint32_t seed;             /* seed of the placement draws */
 } kpa_server_config;
+
+/* Where new bundle KPAs go.  DEVICE: the device pool (HBM) only.  BALANCED:
+ * the paper's policy (Sec. 5): each bundle gets an impact tag from the window
+ * it feeds (High: one of the two next windows of its query to close; Low:
+ * later) and is placed in HBM with probability k_high or k_low (the demand
+ * balance knob), else in the host pool; window-close work (Urgent) always
+ * uses the reserved part of the device pool; when the device pool is full a
+ * bundle spills to the host pool whatever its tag.  HOST: every bundle KPA in
+ * the host pool. */
+typedef enum kpa_placement {
+  KPA_PLACE_DEVICE = 0, KPA_PLACE_BALANCED = 1, KPA_PLACE_HOST = 2
+} kpa_placement;
+
+/* One refresh of the demand balance knob (Sec. 5), as the server's monitor
+ * applies it every monitor_ms.  hbm_util: used fraction of the device pool;
+ * bw_util: host-link bytes moved in the interval over what the link carries
+ * at host_bw_gbs.  When capacity is the tighter resource (hbm_util exceeds
+ * bw_util by more than 0.1) new KPAs move toward the host (step -0.05), when
+ * bandwidth is, toward HBM (+0.05), else nothing changes.  The step goes to
+ * k_low unless k_low already sits at the end it moves toward; then to k_high,
+ * but only when the current output delay is at least 10% below the target
+ * (delay_ms <= 0.9 * target_ms).  Both stay in [0, 1]; they start at 1. */
+kpa_status kpa_balance_knob_update(double* k_low, double* k_high, double hbm_util,
+                                   double bw_util, double delay_ms, double target_ms);
 
 typedef struct kpa_window_result {
   uint32_t query;
@@ -639,6 +673,14 @@ typedef struct kpa_window_result {
   uint64_t top_key[10]; /* SUM: keys by descending sum, ascending key */
   uint64_t top_sum[10];
   double latency_ms;
+  /* keep_groups: the window's per-key arrays in host memory owned by the
+   * server until kpa_server_release_groups(groups_data): SUM: gkey[G], cnt[G],
+   * sum[G], max[G]; MEDIAN: gkey[G], median[G] (G = groups, ascending key).
+   * NULL otherwise (and for JOIN). groups_words = u64 words at groups_data. */
+  const uint64_t* groups_data;
+  uint64_t groups_words;
+  uint32_t runs;        /* bundle runs merged for the window (all sides) */
+  uint32_t runs_host;   /* of which read from the host pool */
 } kpa_window_result;
 /* digest: with m(z) the SplitMix64 finalizer (z ^= z>>30; z *= 0xBF58476D1CE4E5B9;
  * z ^= z>>27; z *= 0x94D049BB133111EB; z ^= z>>31), SUM: h = m(key ^ m(count ^
@@ -656,12 +698,34 @@ typedef struct kpa_server_stats {
   double p50_ms, p99_ms, max_ms; /* window latency */
   double elapsed_s;            /* first submit -> last result */
   double mrec_per_s;           /* admitted rows / elapsed_s */
+  uint64_t bundles_on_host;    /* bundle KPAs placed in the host pool */
+  uint64_t host_pool_bytes;    /* host pool in use now */
+  uint64_t host_pool_peak_bytes;
+  double k_low, k_high;        /* current demand balance knob */
+  double host_bw_gbs;          /* host-link bandwidth taken as full use */
 } kpa_server_statistics;
+
+/* One sample of the server's monitor (every monitor_ms). */
+typedef struct kpa_monitor_sample {
+  double t_s;            /* since the first submit */
+  double hbm_util;       /* device pool in use / its size */
+  double bw_util;        /* host-link bytes of the interval / what the link carries */
+  double k_low, k_high;
+  double delay_ms;       /* current output delay: largest latency of the last 16 windows */
+  uint64_t hbm_bytes;    /* device pool in use */
+  uint64_t host_bytes;   /* host pool in use */
+  uint64_t waits;        /* admissions that had to wait so far (back-pressure) */
+  uint64_t bundles_host; /* bundle KPAs placed in the host pool so far */
+} kpa_monitor_sample;
 
 typedef struct kpa_server_s* kpa_server;
 
 /* budget 64 GiB, 8 slots, rows in device memory, bundles up to 2^20 rows of
- * up to 32 bytes, 256 pending, 25% reserve, 65536 live bundles. */
+ * up to 32 bytes, 256 pending, 25% reserve, 65536 live bundles, no host pool,
+ * device placement, 10 ms monitor, 1000 ms target delay, host-link bandwidth
+ * measured, no per-key arrays, seed 1.  A bundle needs 16 bytes per row in a
+ * pool (plus its rows in the device pool unless rows_in_host); creation fails
+ * with KPA_EBUDGET when the largest bundle could never be admitted. */
 kpa_status kpa_server_config_default(kpa_server_config* cfg);
 kpa_status kpa_server_create(const kpa_server_config* cfg, kpa_server* out);
 /* A bundle's memory (sorted keys and values, plus the rows when they are kept
@@ -678,6 +742,12 @@ kpa_status kpa_server_poll(kpa_server server, kpa_window_result* out, int32_t* g
                            int32_t timeout_ms);
 kpa_status kpa_server_drain(kpa_server server, int32_t timeout_ms);
 kpa_status kpa_server_stats(kpa_server server, kpa_server_statistics* out);
+/* Frees the per-key arrays of a result (keep_groups). */
+kpa_status kpa_server_release_groups(kpa_server server, const uint64_t* groups_data);
+/* Copies up to cap monitor samples (the oldest first) and sets *n to the
+ * number copied; the server keeps the latest 65536. */
+kpa_status kpa_server_trace(kpa_server server, kpa_monitor_sample* out, uint32_t cap,
+                            uint32_t* n);
 kpa_status kpa_server_destroy(kpa_server server);
 
 #ifdef __cplusplus

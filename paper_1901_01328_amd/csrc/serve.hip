@@ -25,6 +25,14 @@
 // allocator; reserve_pct of it only serves window-close work, so closes can
 // always proceed and free the bundles that hold memory.  All streams run at
 // the default priority.
+//
+// Hybrid placement (Sec. 5): an optional pinned host pool is the capacity
+// tier.  Each bundle's KPA (sorted keys and values) goes to the device pool
+// or the host pool by its impact tag and the demand balance knob {k_low,
+// k_high}; a monitor thread samples device-pool use and host-link traffic
+// every monitor_ms and moves the knob.  A KPA placed on the host is sorted in
+// the slot's device scratch and copied out; the window close copies it back
+// over the host link when it merges the window's runs.
 #include "kpa_internal.hpp"
 
 #include <algorithm>
@@ -149,10 +157,16 @@ class Pool {
     free_[off] = bytes;
   }
   bool fits_ever(u64 bytes, bool urgent) const {
+    bytes = (bytes + ALIGN - 1) / ALIGN * ALIGN;
     return bytes + (urgent ? 0 : reserve_) <= size_;
   }
   u64 used() const { return size_ - free_bytes_; }
   u64 peak() const { return used_peak_; }
+  u64 size() const { return size_; }
+  bool owns(const void* p) const {
+    const char* c = static_cast<const char*>(p);
+    return base_ && c >= base_ && c < base_ + size_;
+  }
 
  private:
   char* base_ = nullptr;
@@ -167,8 +181,11 @@ struct Bundle {
   u64 n = 0;
   u64 w_lo = 0;      // first window
   u32 n_win = 0;
-  void* block = nullptr;  // pool memory: keys | values | rows (rows only when kept on the device)
+  void* block = nullptr;   // the KPA: keys | values, in the device or the host pool
   u64 bytes = 0;
+  bool on_host = false;    // the KPA is in the host pool
+  void* rblock = nullptr;  // device pool: the rows, when they are kept on the device
+  u64 rbytes = 0;
   u64* keys = nullptr;    // sorted runs of the windows, back to back
   u64* vals = nullptr;    // value of each sorted entry
   unsigned char* rows = nullptr;
@@ -219,6 +236,8 @@ struct Slot {
   void* sort_ws = nullptr;
   size_t sort_ws_bytes = 0;
   unsigned char* staging = nullptr;  // rows when they stay on the host
+  u64* okeys = nullptr;  // sorted keys and values of a KPA placed on the host (max_n)
+  u64* ovals = nullptr;
 };
 
 }  // namespace
@@ -253,7 +272,18 @@ struct kpa_server_s {
   bool started = false;
   kpa::Clock::time_point t_first, t_last;
 
-  std::thread dispatcher, closer;
+  // capacity tier and placement
+  char* hmem = nullptr;     // pinned host pool
+  kpa::Pool hpool;
+  double k_low = 1.0, k_high = 1.0;
+  u64 rng = 0;              // SplitMix64 counter of the placement draws
+  u64 n_host = 0;           // bundle KPAs placed on the host
+  u64 host_moved = 0;       // host-link bytes of host-pool KPAs (both directions)
+  double host_bw = 0.0;     // GB/s taken as full use of the host link
+  std::vector<kpa_monitor_sample> trace;
+  std::set<const uint64_t*> groups_out;  // per-key arrays handed to the caller
+
+  std::thread dispatcher, closer, monitor;
 };
 
 namespace kpa {
@@ -263,8 +293,8 @@ using Server = kpa_server_s;
 
 constexpr u32 RECORD_WORDS = MAX_BUNDLE_WINDOWS + 2;
 
-void fail(Server* s, kpa_status code, const char* what) {
-  std::lock_guard<std::mutex> lk(s->mu);
+// Stops the server with the first failure.  Caller holds the lock.
+void fail_locked(Server* s, kpa_status code, const char* what) {
   if (s->failed == KPA_OK) {
     s->failed = code;
     s->fail_msg = what;
@@ -278,6 +308,26 @@ void fail(Server* s, kpa_status code, const char* what) {
   s->cv_space.notify_all();
   s->cv_done.notify_all();
   s->cv_close.notify_all();
+}
+
+void fail(Server* s, kpa_status code, const char* what) {
+  std::lock_guard<std::mutex> lk(s->mu);
+  fail_locked(s, code, what);
+}
+
+// Placement draw of one bundle KPA (Sec. 5): true for the host pool.  High
+// bundles stay in HBM with probability k_high, Low ones with k_low.  Caller
+// holds the lock.
+bool place_on_host(Server* s, bool high) {
+  if (!s->hmem || s->cfg.placement == KPA_PLACE_DEVICE) return false;
+  if (s->cfg.placement == KPA_PLACE_HOST) return true;
+  s->rng += 0x9E3779B97F4A7C15ull;
+  u64 z = s->rng;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  const double u = (double)(z >> 11) * (1.0 / 9007199254740992.0);
+  return !(u < (high ? s->k_high : s->k_low));
 }
 
 hipEvent_t take_event(Server* s) {
@@ -295,7 +345,9 @@ u64 rnd(u64 x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 // Releases a bundle once no window needs it.  Caller holds the lock.
 void release_bundle(Server* s, Bundle* b) {
-  s->pool.release(b->block, b->bytes);
+  if (b->on_host) s->hpool.release(b->block, b->bytes);
+  else s->pool.release(b->block, b->bytes);
+  if (b->rblock) s->pool.release(b->rblock, b->rbytes);
   s->free_records.push_back((u32)((b->h_off - s->h_records) / RECORD_WORDS));
   if (b->done) s->event_pool.push_back(b->done);
   s->live_bundles.erase(b);
@@ -368,7 +420,18 @@ bool run_bundle(Server* s, const Cmd& c) {
       return true;
     }
     w_lo = std::max(w_lo, q.next_close);
-    const u64 bytes = rnd(c.n * 8) * 2 + (s->cfg.rows_in_host ? 0 : rnd(c.n * L.row_bytes));
+    const u64 kbytes = rnd(c.n * 8) * 2;                                  // sorted keys | values
+    const u64 rbytes = s->cfg.rows_in_host ? 0 : rnd(c.n * L.row_bytes);  // rows on the device
+    // impact tag: High when the bundle feeds one of its query's two next
+    // windows to close, Low when it feeds a later one
+    const bool want_host = place_on_host(s, w_lo < q.next_close + 2);
+    const bool never = (rbytes && !s->pool.fits_ever(rbytes, false)) ||
+                       (!s->pool.fits_ever(kbytes + rbytes, false) &&
+                        !(s->hmem && s->hpool.fits_ever(kbytes, false)));
+    if (never) {
+      fail_locked(s, KPA_EBUDGET, "a bundle can never fit the server's pools");
+      return false;
+    }
     bool waited = false;
     while (true) {
       if (s->stop) return false;
@@ -382,8 +445,22 @@ bool run_bundle(Server* s, const Cmd& c) {
         }
       }
       const bool rec_ok = !s->free_records.empty();
-      void* mem = nullptr;
-      if (si < s->slots.size() && rec_ok) mem = s->pool.try_alloc(bytes, false);
+      void *mem = nullptr, *rmem = nullptr;
+      bool on_host = false;
+      if (si < s->slots.size() && rec_ok) {
+        if (rbytes) rmem = s->pool.try_alloc(rbytes, false);
+        if (!rbytes || rmem) {
+          if (!want_host) mem = s->pool.try_alloc(kbytes, false);
+          if (!mem && s->hmem) {  // placed on the host, or spilled from a full device pool
+            mem = s->hpool.try_alloc(kbytes, false);
+            on_host = mem != nullptr;
+          }
+          if (!mem && rmem) {
+            s->pool.release(rmem, rbytes);
+            rmem = nullptr;
+          }
+        }
+      }
       if (mem) {
         b = new Bundle;
         b->q = c.q;
@@ -392,11 +469,17 @@ bool run_bundle(Server* s, const Cmd& c) {
         b->w_lo = w_lo;
         b->n_win = (u32)(w_hi - w_lo + 1);
         b->block = mem;
-        b->bytes = bytes;
+        b->bytes = kbytes;
+        b->on_host = on_host;
+        b->rblock = rmem;
+        b->rbytes = rbytes;
         b->keys = static_cast<u64*>(mem);
         b->vals = reinterpret_cast<u64*>(static_cast<char*>(mem) + rnd(c.n * 8));
-        if (!s->cfg.rows_in_host)
-          b->rows = reinterpret_cast<unsigned char*>(static_cast<char*>(mem) + 2 * rnd(c.n * 8));
+        if (rmem) b->rows = static_cast<unsigned char*>(rmem);
+        if (on_host) {
+          s->n_host++;
+          s->host_moved += 16 * c.n;  // the sorted KPA goes out over the host link
+        }
         const u32 rec = s->free_records.back();
         s->free_records.pop_back();
         b->h_off = s->h_records + (u64)rec * RECORD_WORDS;
@@ -429,14 +512,21 @@ bool run_bundle(Server* s, const Cmd& c) {
     rc = kpa_partition_windows(dev_rows, c.n, &L, q.win_len, q.origin + w_lo * q.win_len, b->n_win,
                                0, sl.pkeys, sl.prids, sl.pvals, sl.win_off, sl.oob, sl.part_ws,
                                sl.part_ws_bytes, sl.st);
+  // a KPA placed on the host is sorted into the slot's scratch and copied out
+  u64* okeys = b->on_host ? sl.okeys : b->keys;
+  u64* ovals = b->on_host ? sl.ovals : b->vals;
   if (rc == KPA_OK)
-    rc = kpa_sort_segmented(sl.pkeys, sl.prids, b->keys, sl.srids, sl.win_off, b->n_win, c.n,
+    rc = kpa_sort_segmented(sl.pkeys, sl.prids, okeys, sl.srids, sl.win_off, b->n_win, c.n,
                             KPA_SORT_RADIX, nullptr, nullptr, sl.sort_ws, sl.sort_ws_bytes, sl.st);
   if (rc == KPA_OK) {
     hipLaunchKernelGGL(k_gather_vals, dim3((u32)std::min<u64>(ceil_div(c.n, BLOCK), 2048)),
-                       dim3(BLOCK), 0, sl.st, sl.srids, sl.pvals, sl.win_off + b->n_win, b->vals);
+                       dim3(BLOCK), 0, sl.st, sl.srids, sl.pvals, sl.win_off + b->n_win, ovals);
     if (hipGetLastError() != hipSuccess) rc = KPA_EHIP;
   }
+  if (rc == KPA_OK && b->on_host &&
+      (hipMemcpyAsync(b->keys, okeys, c.n * 8, hipMemcpyDeviceToHost, sl.st) != hipSuccess ||
+       hipMemcpyAsync(b->vals, ovals, c.n * 8, hipMemcpyDeviceToHost, sl.st) != hipSuccess))
+    rc = KPA_EHIP;
   if (rc == KPA_OK &&
       (hipMemcpyAsync(b->h_off, sl.win_off, (b->n_win + 1) * sizeof(u64), hipMemcpyDeviceToHost,
                       sl.st) != hipSuccess ||
@@ -526,6 +616,7 @@ void dispatcher_main(Server* s) {
 struct CloseBufs {
   std::vector<std::pair<void*, u64>> held;
   Server* s;
+  bool never_fits = false;  // a buffer larger than the whole device pool was asked for
   explicit CloseBufs(Server* sv) : s(sv) {}
   void* take(u64 bytes) {
     std::unique_lock<std::mutex> lk(s->mu);
@@ -536,7 +627,10 @@ struct CloseBufs {
         held.emplace_back(p, bytes);
         return p;
       }
-      if (!s->pool.fits_ever(bytes, true)) return nullptr;
+      if (!s->pool.fits_ever(bytes, true)) {
+        never_fits = true;
+        return nullptr;
+      }
       s->cv_space.wait_for(lk, std::chrono::microseconds(200));
     }
   }
@@ -551,9 +645,10 @@ struct CloseBufs {
 // merges them into one sorted KPA whose rids index the concatenated values.
 // Returns the entry count, or -1 on failure.
 long long merge_side(Server* s, CloseBufs& cb, const CloseJob& j, int side, u64** out_k,
-                     u32** out_r, u64** out_v, hipStream_t st) {
+                     u32** out_r, u64** out_v, hipStream_t st, u32* runs, u32* runs_host) {
   std::vector<u64> off{0};
   std::vector<std::pair<const Bundle*, std::pair<u64, u64>>> parts;
+  u64 from_host = 0;
   for (const Bundle* b : j.runs[side]) {
     if (hipEventSynchronize(b->done) != hipSuccess) return -1;
     const u64 k = j.w - b->w_lo;
@@ -561,7 +656,16 @@ long long merge_side(Server* s, CloseBufs& cb, const CloseJob& j, int side, u64*
     if (e > a) {
       parts.push_back({b, {a, e - a}});
       off.push_back(off.back() + (e - a));
+      ++*runs;
+      if (b->on_host) {
+        ++*runs_host;
+        from_host += 16 * (e - a);
+      }
     }
+  }
+  if (from_host) {  // the host-pool runs come back over the host link
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->host_moved += from_host;
   }
   const u64 n = off.back();
   *out_k = nullptr;
@@ -581,10 +685,9 @@ long long merge_side(Server* s, CloseBufs& cb, const CloseJob& j, int side, u64*
   for (size_t i = 0; i < parts.size(); ++i) {
     const Bundle* b = parts[i].first;
     const u64 a = parts[i].second.first, len = parts[i].second.second;
-    if (hipMemcpyAsync(ck + off[i], b->keys + a, len * 8, hipMemcpyDeviceToDevice, st) !=
-            hipSuccess ||
-        hipMemcpyAsync(cv + off[i], b->vals + a, len * 8, hipMemcpyDeviceToDevice, st) !=
-            hipSuccess)
+    const hipMemcpyKind kind = b->on_host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    if (hipMemcpyAsync(ck + off[i], b->keys + a, len * 8, kind, st) != hipSuccess ||
+        hipMemcpyAsync(cv + off[i], b->vals + a, len * 8, kind, st) != hipSuccess)
       return -1;
   }
   hipLaunchKernelGGL(k_iota, dim3((u32)std::min<u64>(ceil_div(n, BLOCK), 4096)), dim3(BLOCK), 0,
@@ -598,10 +701,15 @@ long long merge_side(Server* s, CloseBufs& cb, const CloseJob& j, int side, u64*
   return (long long)n;
 }
 
-bool do_close(Server* s, const CloseJob& j, kpa_window_result* res) {
+bool do_close(Server* s, const CloseJob& j, kpa_window_result* res, bool* budget) {
   Query& q = *s->queries[j.q];
   hipStream_t st = s->close_st;
   CloseBufs cb(s);
+  struct BudgetFlag {
+    CloseBufs& cb;
+    bool* out;
+    ~BudgetFlag() { *out = cb.never_fits; }
+  } flag{cb, budget};
   std::memset(res, 0, sizeof(*res));
   res->query = j.q;
   res->kind = q.kind;
@@ -611,10 +719,14 @@ bool do_close(Server* s, const CloseJob& j, kpa_window_result* res) {
   u64* mv[2] = {nullptr, nullptr};
   long long n[2] = {0, 0};
   for (int sd = 0; sd < q.sides; ++sd) {
-    n[sd] = merge_side(s, cb, j, sd, &mk[sd], &mr[sd], &mv[sd], st);
+    n[sd] = merge_side(s, cb, j, sd, &mk[sd], &mr[sd], &mv[sd], st, &res->runs, &res->runs_host);
     if (n[sd] < 0) return false;
     res->rows[sd] = (u64)n[sd];
   }
+  // per-key columns to hand to the caller (keep_groups): device arrays of
+  // N entries each, the first G of them valid
+  u64* cols[4] = {nullptr, nullptr, nullptr, nullptr};
+  int ncols = 0;
   // small device results: [0..1] segment offsets side 0, [2..3] side 1,
   // [4] digest, [5] total, [6] groups / pairs, [7] sumprod, [8..9] scratch
   u64* small = static_cast<u64*>(cb.take(16 * sizeof(u64)));
@@ -644,6 +756,8 @@ bool do_close(Server* s, const CloseJob& j, kpa_window_result* res) {
         kpa_topk_by_sum(gk, gs, small + 8, 1, N, 10, top, top + 10,
                         reinterpret_cast<u32*>(top + 20), tws, twb, st) != KPA_OK)
       return false;
+    cols[0] = gk, cols[1] = gc, cols[2] = gs, cols[3] = gm;
+    ncols = 4;
     hipLaunchKernelGGL(k_digest, dim3(256), dim3(BLOCK), 0, st, gk, gc, gs, gm, small + 9,
                        small + 4);
     if (hipGetLastError() != hipSuccess ||
@@ -660,6 +774,8 @@ bool do_close(Server* s, const CloseJob& j, kpa_window_result* res) {
     if (kpa_median_by_key(mk[0], mr[0], small, 1, N, mv[0], &V, g, g + N, small + 8, mws,
                           mwb, st) != KPA_OK)
       return false;
+    cols[0] = g, cols[1] = g + N;
+    ncols = 2;
     hipLaunchKernelGGL(k_digest, dim3(256), dim3(BLOCK), 0, st, g, g + N, nullptr, nullptr,
                        small + 9, small + 4);
     if (hipGetLastError() != hipSuccess) return false;
@@ -693,6 +809,24 @@ bool do_close(Server* s, const CloseJob& j, kpa_window_result* res) {
       res->top_sum[i] = host[18 + i];
     }
   }
+  if (s->cfg.keep_groups && ncols && res->groups) {
+    const u64 G = res->groups;
+    uint64_t* h = new (std::nothrow) uint64_t[G * ncols];
+    if (!h) return false;
+    for (int c = 0; c < ncols; ++c)
+      if (hipMemcpyAsync(h + c * G, cols[c], G * 8, hipMemcpyDeviceToHost, st) != hipSuccess) {
+        delete[] h;
+        return false;
+      }
+    if (hipStreamSynchronize(st) != hipSuccess) {
+      delete[] h;
+      return false;
+    }
+    res->groups_data = h;
+    res->groups_words = G * ncols;
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->groups_out.insert(h);
+  }
   return true;
 }
 
@@ -711,8 +845,12 @@ void closer_main(Server* s) {
       s->closes.pop_front();
     }
     kpa_window_result r;
-    if (!do_close(s, j, &r)) {
-      fail(s, KPA_EHIP, "window close failed");
+    bool budget = false;
+    if (!do_close(s, j, &r, &budget)) {
+      if (budget)
+        fail(s, KPA_EBUDGET, "window close needs more memory than the device pool holds");
+      else
+        fail(s, KPA_EHIP, "window close failed");
       return;
     }
     const auto now = Clock::now();
@@ -733,6 +871,50 @@ void closer_main(Server* s) {
   }
 }
 
+// Every monitor_ms: device-pool use, host-link traffic of the interval and
+// the current output delay; the knob moves (balanced placement) and the
+// sample is kept for kpa_server_trace.
+constexpr size_t TRACE_CAP = 65536;
+
+void monitor_main(Server* s) {
+  u64 last_moved = 0;
+  Clock::time_point last = Clock::now();
+  std::unique_lock<std::mutex> lk(s->mu);
+  while (!s->stop) {
+    s->cv_done.wait_for(lk, std::chrono::milliseconds(s->cfg.monitor_ms));
+    if (s->stop) return;
+    const Clock::time_point now = Clock::now();
+    const double dt = std::chrono::duration<double>(now - last).count();
+    if (dt <= 0) continue;
+    const double cap = (double)(s->pool.size() - s->pool.size() / 100 * s->cfg.reserve_pct);
+    const double hbm = cap > 0 ? std::min(1.0, (double)s->pool.used() / cap) : 1.0;
+    const u64 moved = s->host_moved - last_moved;
+    const double bw = s->host_bw > 0 ? std::min(1.0, (double)moved / (dt * s->host_bw * 1e9)) : 0.0;
+    double delay = 0;
+    const size_t nl = s->lat_ms.size();
+    for (size_t i = nl > 16 ? nl - 16 : 0; i < nl; ++i) delay = std::max(delay, s->lat_ms[i]);
+    if (s->cfg.placement == KPA_PLACE_BALANCED)
+      (void)kpa_balance_knob_update(&s->k_low, &s->k_high, hbm, bw, delay,
+                                    s->cfg.target_delay_ms);
+    last = now;
+    last_moved = s->host_moved;
+    if (!s->started) continue;
+    kpa_monitor_sample m;
+    m.t_s = std::chrono::duration<double>(now - s->t_first).count();
+    m.hbm_util = hbm;
+    m.bw_util = bw;
+    m.k_low = s->k_low;
+    m.k_high = s->k_high;
+    m.delay_ms = delay;
+    m.hbm_bytes = s->pool.used();
+    m.host_bytes = s->hmem ? s->hpool.used() : 0;
+    m.waits = s->n_waits;
+    m.bundles_host = s->n_host;
+    if (s->trace.size() >= TRACE_CAP) s->trace.erase(s->trace.begin(), s->trace.begin() + TRACE_CAP / 2);
+    s->trace.push_back(m);
+  }
+}
+
 kpa_status check_server_config(const kpa_server_config* c) {
   KPA_REQUIRE(c != nullptr, KPA_EINVAL, "config is null");
   KPA_REQUIRE(c->slots >= 1 && c->slots <= 64, KPA_EINVAL, "slots must be in [1, 64]");
@@ -743,6 +925,13 @@ kpa_status check_server_config(const kpa_server_config* c) {
   KPA_REQUIRE(c->max_pending >= 1, KPA_EINVAL, "max_pending must be >= 1");
   KPA_REQUIRE(c->reserve_pct <= 90, KPA_EINVAL, "reserve_pct must be at most 90");
   KPA_REQUIRE(c->max_live_bundles >= 1, KPA_EINVAL, "max_live_bundles must be >= 1");
+  KPA_REQUIRE(c->placement <= KPA_PLACE_HOST, KPA_EINVAL, "bad placement");
+  KPA_REQUIRE(c->placement == KPA_PLACE_DEVICE || c->host_pool_bytes > 0, KPA_EINVAL,
+              "host placement needs a host pool (host_pool_bytes > 0)");
+  KPA_REQUIRE(c->monitor_ms >= 1 && c->monitor_ms <= 60000, KPA_EINVAL,
+              "monitor_ms must be in [1, 60000]");
+  KPA_REQUIRE(c->target_delay_ms > 0 && c->host_bw_gbs >= 0, KPA_EINVAL,
+              "target_delay_ms must be positive and host_bw_gbs not negative");
   return KPA_OK;
 }
 
@@ -757,6 +946,9 @@ void teardown(Server* s) {
   }
   if (s->dispatcher.joinable()) s->dispatcher.join();
   if (s->closer.joinable()) s->closer.join();
+  if (s->monitor.joinable()) s->monitor.join();
+  for (const uint64_t* g : s->groups_out) delete[] g;
+  s->groups_out.clear();
   (void)hipSetDevice(s->device);
   for (auto& sl : s->slots) {
     if (sl.st) (void)hipStreamSynchronize(sl.st);
@@ -774,6 +966,7 @@ void teardown(Server* s) {
   for (hipEvent_t e : s->event_pool) (void)hipEventDestroy(e);
   if (s->close_st) (void)hipStreamDestroy(s->close_st);
   if (s->h_records) (void)hipHostFree(s->h_records);
+  if (s->hmem) (void)hipHostFree(s->hmem);
   if (s->mem) (void)hipFree(s->mem);
 }
 
@@ -811,6 +1004,31 @@ kpa_status kpa_server_config_default(kpa_server_config* cfg) {
   cfg->max_pending = 256;
   cfg->reserve_pct = 25;
   cfg->max_live_bundles = 1u << 16;
+  cfg->host_pool_bytes = 0;
+  cfg->placement = KPA_PLACE_DEVICE;
+  cfg->monitor_ms = 10;
+  cfg->target_delay_ms = 1000.0;
+  cfg->host_bw_gbs = 0.0;
+  cfg->keep_groups = 0;
+  cfg->seed = 1;
+  return KPA_OK;
+}
+
+kpa_status kpa_balance_knob_update(double* k_low, double* k_high, double hbm_util,
+                                   double bw_util, double delay_ms, double target_ms) {
+  clear_error();
+  KPA_REQUIRE(k_low && k_high, KPA_EINVAL, "null knob");
+  constexpr double DELTA = 0.05, SLACK = 0.1, HEADROOM = 0.9;
+  double d = 0;
+  if (hbm_util > bw_util + SLACK) d = -DELTA;       // capacity is short: toward the host
+  else if (bw_util > hbm_util + SLACK) d = DELTA;   // the host link is short: toward HBM
+  if (d == 0) return KPA_OK;
+  const bool low_at_end = d < 0 ? *k_low <= 0.0 : *k_low >= 1.0;
+  if (!low_at_end) {
+    *k_low = std::min(1.0, std::max(0.0, *k_low + d));
+  } else if (delay_ms <= HEADROOM * target_ms) {
+    *k_high = std::min(1.0, std::max(0.0, *k_high + d));
+  }
   return KPA_OK;
 }
 
@@ -824,14 +1042,31 @@ kpa_status kpa_server_create(const kpa_server_config* cfg, kpa_server* out) {
   size_t part_ws = 0, sort_ws = 0;
   KPA_CHECK(kpa_partition_windows_workspace_size(mb, MAX_BUNDLE_WINDOWS, &part_ws));
   KPA_CHECK(kpa_sort_workspace_size(mb, MAX_BUNDLE_WINDOWS, KPA_SORT_RADIX, &sort_ws));
+  const bool host_tier = cfg->host_pool_bytes > 0;
   const u64 slot_bytes = rnd(mb * 8) + rnd(mb * 4) + rnd(mb * 8) + rnd(mb * 4) +
                          rnd((MAX_BUNDLE_WINDOWS + 2) * 8) +
                          rnd(part_ws) + rnd(sort_ws) +
-                         (cfg->rows_in_host ? rnd(mb * cfg->max_row_bytes) : 0);
+                         (cfg->rows_in_host ? rnd(mb * cfg->max_row_bytes) : 0) +
+                         (host_tier ? 2 * rnd(mb * 8) : 0);
   const u64 fixed = slot_bytes * cfg->slots;
   KPA_REQUIRE(cfg->budget_bytes > fixed + (64ull << 20), KPA_EBUDGET,
               "budget of %llu bytes does not cover the slots' scratch (%llu bytes)",
               (unsigned long long)cfg->budget_bytes, (unsigned long long)fixed);
+  {
+    // the largest bundle must be admissible: its rows (when kept on the
+    // device) and its KPA in the device pool, or the KPA in the host pool
+    const u64 pool_bytes = cfg->budget_bytes - fixed;
+    const u64 normal = pool_bytes - pool_bytes / 100 * cfg->reserve_pct;
+    const u64 rbytes = cfg->rows_in_host ? 0 : rnd(mb * cfg->max_row_bytes);
+    const u64 kbytes = 2 * rnd(mb * 8);
+    const bool fits = rbytes + kbytes <= normal ||
+                      (host_tier && rbytes <= normal && kbytes <= cfg->host_pool_bytes);
+    KPA_REQUIRE(fits, KPA_EBUDGET,
+                "a bundle of %llu rows needs %llu bytes of pool memory; the budget leaves %llu "
+                "(the rest is scratch and the close reserve)",
+                (unsigned long long)mb, (unsigned long long)(rbytes + kbytes),
+                (unsigned long long)normal);
+  }
   std::unique_ptr<Server> s(new (std::nothrow) Server);
   KPA_REQUIRE(s != nullptr, KPA_EINVAL, "out of host memory");
   s->cfg = *cfg;
@@ -867,6 +1102,12 @@ kpa_status kpa_server_create(const kpa_server_config* cfg, kpa_server* out) {
       sl.staging = reinterpret_cast<unsigned char*>(p);
       p += rnd(mb * cfg->max_row_bytes);
     }
+    if (host_tier) {
+      sl.okeys = reinterpret_cast<u64*>(p);
+      p += rnd(mb * 8);
+      sl.ovals = reinterpret_cast<u64*>(p);
+      p += rnd(mb * 8);
+    }
   }
   const u64 pool_bytes = cfg->budget_bytes - (u64)(p - s->mem);
   s->pool.init(p, pool_bytes, pool_bytes / 100 * cfg->reserve_pct);
@@ -887,9 +1128,43 @@ kpa_status kpa_server_create(const kpa_server_config* cfg, kpa_server* out) {
                         hipHostMallocDefault));
   s->free_records.reserve(cfg->max_live_bundles);
   for (u32 i = cfg->max_live_bundles; i > 0; --i) s->free_records.push_back(i - 1);
+  s->rng = 0x5851F42D4C957F2Dull ^ ((u64)cfg->seed << 17);
+  if (host_tier) {
+    const hipError_t he = hipHostMalloc(reinterpret_cast<void**>(&s->hmem), cfg->host_pool_bytes,
+                                        hipHostMallocDefault);
+    if (he != hipSuccess) {
+      s->hmem = nullptr;
+      KPA_REQUIRE(false, KPA_EBUDGET, "cannot allocate the %llu-byte host pool: %s",
+                  (unsigned long long)cfg->host_pool_bytes, hipGetErrorString(he));
+    }
+    s->hpool.init(s->hmem, cfg->host_pool_bytes, 0);
+    s->host_bw = cfg->host_bw_gbs;
+    if (s->host_bw <= 0) {
+      // what a pinned host-to-device copy moves per second on this machine
+      const u64 probe = std::min<u64>(cfg->host_pool_bytes, 64ull << 20) / ALIGN * ALIGN;
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      KPA_HIP(hipEventCreate(&e0));
+      KPA_HIP(hipEventCreate(&e1));
+      float ms = 0;
+      hipError_t pe = hipMemcpyAsync(p, s->hmem, probe, hipMemcpyHostToDevice,
+                                     s->close_st);
+      if (pe == hipSuccess) pe = hipEventRecord(e0, s->close_st);
+      if (pe == hipSuccess)
+        pe = hipMemcpyAsync(p, s->hmem, probe, hipMemcpyHostToDevice,
+                            s->close_st);
+      if (pe == hipSuccess) pe = hipEventRecord(e1, s->close_st);
+      if (pe == hipSuccess) pe = hipEventSynchronize(e1);
+      if (pe == hipSuccess) pe = hipEventElapsedTime(&ms, e0, e1);
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      KPA_HIP(pe);
+      s->host_bw = ms > 0 ? (double)probe / (ms * 1e-3) / 1e9 : 50.0;
+    }
+  }
   Server* raw = s.get();
   s->dispatcher = std::thread(dispatcher_main, raw);
   s->closer = std::thread(closer_main, raw);
+  s->monitor = std::thread(monitor_main, raw);
   guard.armed = false;
   *out = s.release();
   return KPA_OK;
@@ -1046,6 +1321,35 @@ kpa_status kpa_server_stats(kpa_server s, kpa_server_statistics* out) {
     out->elapsed_s = std::chrono::duration<double>(end - s->t_first).count();
     if (out->elapsed_s > 0) out->mrec_per_s = (double)s->n_rows / out->elapsed_s / 1e6;
   }
+  out->bundles_on_host = s->n_host;
+  out->host_pool_bytes = s->hmem ? s->hpool.used() : 0;
+  out->host_pool_peak_bytes = s->hmem ? s->hpool.peak() : 0;
+  out->k_low = s->k_low;
+  out->k_high = s->k_high;
+  out->host_bw_gbs = s->host_bw;
+  return KPA_OK;
+}
+
+kpa_status kpa_server_release_groups(kpa_server s, const uint64_t* groups_data) {
+  clear_error();
+  KPA_REQUIRE(s != nullptr, KPA_EINVAL, "server is null");
+  if (!groups_data) return KPA_OK;
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->groups_out.find(groups_data);
+  KPA_REQUIRE(it != s->groups_out.end(), KPA_EINVAL, "not a result of this server");
+  delete[] *it;
+  s->groups_out.erase(it);
+  return KPA_OK;
+}
+
+kpa_status kpa_server_trace(kpa_server s, kpa_monitor_sample* out, uint32_t cap, uint32_t* n) {
+  clear_error();
+  KPA_REQUIRE(s != nullptr && n != nullptr && (cap == 0 || out != nullptr), KPA_EINVAL,
+              "null argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  const u32 m = (u32)std::min<size_t>(cap, s->trace.size());
+  for (u32 i = 0; i < m; ++i) out[i] = s->trace[i];
+  *n = m;
   return KPA_OK;
 }
 

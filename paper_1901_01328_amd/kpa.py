@@ -62,7 +62,25 @@ class kpa_server_config(C.Structure):
     _fields_ = [("budget_bytes", C.c_uint64), ("slots", C.c_uint32), ("rows_in_host", C.c_uint32),
                 ("max_bundle_rows", C.c_uint64), ("max_row_bytes", C.c_uint32),
                 ("max_pending", C.c_uint32), ("reserve_pct", C.c_uint32),
-                ("max_live_bundles", C.c_uint32)]
+                ("max_live_bundles", C.c_uint32), ("host_pool_bytes", C.c_uint64),
+                ("placement", C.c_uint32), ("monitor_ms", C.c_uint32),
+                ("target_delay_ms", C.c_double), ("host_bw_gbs", C.c_double),
+                ("keep_groups", C.c_uint32), ("seed", C.c_uint32)]
+
+
+KPA_PLACE_DEVICE = 0
+KPA_PLACE_BALANCED = 1
+KPA_PLACE_HOST = 2
+
+
+class kpa_monitor_sample(C.Structure):
+    _fields_ = [("t_s", C.c_double), ("hbm_util", C.c_double), ("bw_util", C.c_double),
+                ("k_low", C.c_double), ("k_high", C.c_double), ("delay_ms", C.c_double),
+                ("hbm_bytes", C.c_uint64), ("host_bytes", C.c_uint64), ("waits", C.c_uint64),
+                ("bundles_host", C.c_uint64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class kpa_window_result(C.Structure):
@@ -70,13 +88,15 @@ class kpa_window_result(C.Structure):
                 ("rows", C.c_uint64 * 2), ("groups", C.c_uint64), ("total", C.c_uint64),
                 ("digest", C.c_uint64), ("n_top", C.c_uint32), ("reserved", C.c_uint32),
                 ("top_key", C.c_uint64 * 10), ("top_sum", C.c_uint64 * 10),
-                ("latency_ms", C.c_double)]
+                ("latency_ms", C.c_double), ("groups_data", C.POINTER(C.c_uint64)),
+                ("groups_words", C.c_uint64), ("runs", C.c_uint32), ("runs_host", C.c_uint32)]
 
     def as_dict(self):
         return {"query": self.query, "kind": self.kind, "window": self.window,
                 "rows": (self.rows[0], self.rows[1]), "groups": self.groups, "total": self.total,
                 "digest": self.digest, "top_key": list(self.top_key)[:self.n_top],
-                "top_sum": list(self.top_sum)[:self.n_top], "latency_ms": self.latency_ms}
+                "top_sum": list(self.top_sum)[:self.n_top], "latency_ms": self.latency_ms,
+                "runs": self.runs, "runs_host": self.runs_host}
 
 
 class kpa_server_statistics(C.Structure):
@@ -84,7 +104,10 @@ class kpa_server_statistics(C.Structure):
                 ("windows_closed", C.c_uint64), ("backpressure_waits", C.c_uint64),
                 ("pool_peak_bytes", C.c_uint64), ("pool_bytes", C.c_uint64),
                 ("p50_ms", C.c_double), ("p99_ms", C.c_double), ("max_ms", C.c_double),
-                ("elapsed_s", C.c_double), ("mrec_per_s", C.c_double)]
+                ("elapsed_s", C.c_double), ("mrec_per_s", C.c_double),
+                ("bundles_on_host", C.c_uint64), ("host_pool_bytes", C.c_uint64),
+                ("host_pool_peak_bytes", C.c_uint64), ("k_low", C.c_double),
+                ("k_high", C.c_double), ("host_bw_gbs", C.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -141,6 +164,10 @@ _SIGS = {
     "kpa_server_drain": ([_vp, C.c_int32], C.c_int32),
     "kpa_server_stats": ([_vp, C.POINTER(kpa_server_statistics)], C.c_int32),
     "kpa_server_destroy": ([_vp], C.c_int32),
+    "kpa_server_release_groups": ([_vp, C.POINTER(C.c_uint64)], C.c_int32),
+    "kpa_server_trace": ([_vp, C.POINTER(kpa_monitor_sample), _u32, C.POINTER(_u32)], C.c_int32),
+    "kpa_balance_knob_update": ([C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_double,
+                                 C.c_double, C.c_double, C.c_double], C.c_int32),
     "kpa_merge_workspace_size": ([_u64, _u64, _sz], C.c_int32),
     "kpa_merge": ([_vp, _vp, _u64, _vp, _vp, _u64, _vp, _vp, _vp, C.c_size_t, _vp], C.c_int32),
     "kpa_merge_runs_workspace_size": ([_u64, _sz], C.c_int32),
@@ -888,6 +915,14 @@ def kpa_ingest_bundle(host_rows, layout, dev_rows, ts_add=0, stream=None):
           _p(dev_rows), _stream(stream))
 
 
+def kpa_balance_knob_update(k_low, k_high, hbm_util, bw_util, delay_ms, target_ms):
+    """The knob after one refresh: (k_low, k_high)."""
+    lo, hi = C.c_double(k_low), C.c_double(k_high)
+    _call("kpa_balance_knob_update", C.byref(lo), C.byref(hi), hbm_util, bw_util, delay_ms,
+          target_ms)
+    return lo.value, hi.value
+
+
 def _ts_column(rows, layout):
     import numpy as np
     a = rows.numpy() if hasattr(rows, "numpy") else rows
@@ -906,7 +941,7 @@ class Server:
         c = kpa_server_config()
         _call("kpa_server_config_default", C.byref(c))
         for k, v in cfg.items():
-            setattr(c, k, int(v))
+            setattr(c, k, float(v) if k in ("target_delay_ms", "host_bw_gbs") else int(v))
         self.cfg = c
         h = C.c_void_p(None)
         _call("kpa_server_create", C.byref(c), C.byref(h))
@@ -937,10 +972,29 @@ class Server:
         _call("kpa_server_watermark", self.h, qid, t)
 
     def poll(self, timeout_ms=0):
+        """One finished window result (dict) or None; with keep_groups the
+        per-key arrays come as numpy uint64 arrays under "arrays" (SUM: gkey,
+        cnt, sum, max; MEDIAN: gkey, median) and the server's copy is freed."""
         r = kpa_window_result()
         got = C.c_int32(0)
         _call("kpa_server_poll", self.h, C.byref(r), C.byref(got), timeout_ms)
-        return r.as_dict() if got.value else None
+        if not got.value:
+            return None
+        d = r.as_dict()
+        if r.groups_data and r.groups_words:
+            import numpy as np
+            flat = np.ctypeslib.as_array(r.groups_data, shape=(r.groups_words,)).copy()
+            names = ("gkey", "cnt", "sum", "max") if r.kind == KPA_Q_SUM else ("gkey", "median")
+            G = r.groups
+            d["arrays"] = {nm: flat[i * G:(i + 1) * G] for i, nm in enumerate(names)}
+            _call("kpa_server_release_groups", self.h, r.groups_data)
+        return d
+
+    def trace(self, cap=65536):
+        buf = (kpa_monitor_sample * cap)()
+        n = C.c_uint32(0)
+        _call("kpa_server_trace", self.h, buf, cap, C.byref(n))
+        return [buf[i].as_dict() for i in range(n.value)]
 
     def results(self):
         out = []

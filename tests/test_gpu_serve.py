@@ -266,3 +266,90 @@ def test_ingest_rebases_timestamps(K):
     exp = rows.clone()
     exp[:, 2] += 7 * W + 3
     assert torch.equal(got, exp)
+
+
+# ------------------------------------------------ per-key arrays, placement --
+
+def run_collect(K, s, order, **cfg):
+    srv = K.Server(max_bundle_rows=1 << 14, **cfg)
+    kinds = {"sum": K.KPA_Q_SUM, "median": K.KPA_Q_MEDIAN, "join": K.KPA_Q_JOIN}
+    q = srv.add_query(kinds[s.kind], LAYOUT32, W, 0)
+    for bi in order:
+        side, rows = s.bundle(bi)
+        srv.submit(q, rows, side=side)
+        if bi % 3 == 2:
+            srv.watermark(q, s.watermark_after(bi))
+    srv.watermark(q, SPAN + W)
+    srv.drain(timeout_ms=60000)
+    res = {r["window"]: r for r in srv.results()}
+    st = srv.stats()
+    tr = srv.trace()
+    srv.close()
+    return res, st, tr
+
+
+@pytest.mark.parametrize("si", [0, 1])
+def test_per_key_arrays_match_oracle(K, orc, streams, oracle_results, si):
+    """keep_groups: each SUM / MEDIAN window result carries its per-key arrays,
+    compared element by element with the oracle's ordered-map results."""
+    s = streams[si]
+    say(f"serve per-key arrays {s.kind}")
+    res, st, _ = run_collect(K, s, range(len(s.parts)), budget_bytes=4 << 30, keep_groups=1)
+    ts = u64col(s.rows, 2)
+    assert set(res) == set(oracle_results[si])
+    for w, r in res.items():
+        m = np.nonzero(ts // W == w)[0]
+        keys, rids = u64col(s.rows, 0)[m], m.astype(np.uint32)
+        a = r["arrays"]
+        if s.kind == "sum":
+            ek, ec, es, em = orc.reduce_by_key(keys, rids, s.rows, LAYOUT32)
+            assert np.array_equal(a["gkey"], ek) and np.array_equal(a["cnt"], ec)
+            assert np.array_equal(a["sum"], es) and np.array_equal(a["max"], em)
+        else:
+            ek, emed = orc.median_by_key(keys, rids, s.rows, LAYOUT32)
+            assert np.array_equal(a["gkey"], ek) and np.array_equal(a["median"], emed)
+
+
+@pytest.mark.parametrize("si", [0, 2])
+def test_host_placement_matches_oracle(K, streams, oracle_results, si):
+    """Every bundle KPA in the pinned host pool (the capacity tier): the
+    window closes read the runs over the host link; results are unchanged."""
+    s = streams[si]
+    say(f"serve host placement {s.kind}")
+    res, st, _ = run_collect(K, s, range(len(s.parts)), budget_bytes=4 << 30,
+                             host_pool_bytes=1 << 30, placement=K.KPA_PLACE_HOST)
+    check_against_oracle({w: summary(r) for w, r in res.items()}, oracle_results[si])
+    assert st["bundles_on_host"] == st["bundles"] > 0
+    assert all(r["runs_host"] == r["runs"] for r in res.values())
+
+
+def test_balanced_placement_under_capacity_pressure(K, orc):
+    """Balanced placement when the open windows' KPAs exceed the device pool:
+    8M rows (128 MB of sorted keys and values) against a device pool of about
+    117 MB outside the close reserve, rows kept on the host, and the
+    watermark held back until every bundle is in.  The pool fills, bundles
+    spill to the host pool, the monitor moves the knob toward the host (k_low
+    falls), and every window's result still equals the oracle's."""
+    n = 8 << 20
+    rows = stream_rows("sum", n, 61)
+    exp = expected(orc, "sum", rows)
+    parts = bundles(n, 61, lo=12, hi=14)
+    say(f"serve balanced placement under pressure: {len(parts)} bundles")
+    srv = K.Server(budget_bytes=160 << 20, max_bundle_rows=1 << 14, slots=2, rows_in_host=1,
+                   host_pool_bytes=1 << 30, placement=K.KPA_PLACE_BALANCED, monitor_ms=1,
+                   target_delay_ms=10000, max_pending=1 << 20)
+    q = srv.add_query(K.KPA_Q_SUM, LAYOUT32, W, 0)
+    pinned = [rows[a:b].contiguous().pin_memory() for a, b in parts]
+    for r in pinned:
+        srv.submit(q, r)
+    srv.watermark(q, SPAN + W)             # every window closes only now
+    srv.drain(timeout_ms=120000)
+    res = {r["window"]: summary(r) for r in srv.results()}
+    st = srv.stats()
+    tr = srv.trace()
+    srv.close()
+    say(f"bundles {st['bundles']} on host {st['bundles_on_host']}, k_low {st['k_low']:.2f}, "
+        f"samples {len(tr)}")
+    check_against_oracle(res, exp)
+    assert st["bundles_on_host"] > 0
+    assert min(t["k_low"] for t in tr) < 1.0
