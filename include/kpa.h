@@ -55,7 +55,8 @@ enum {
   KPA_ECAPACITY = -3,    /* an output exceeds the capacity the caller gave */
   KPA_EBUDGET = -4,      /* serving admission: memory budget exhausted */
   KPA_EUNSUPPORTED = -5, /* size or parameter beyond what the library supports */
-  KPA_EHIP = -6          /* a HIP runtime call failed; see kpa_last_error_string() */
+  KPA_EHIP = -6,         /* a HIP runtime call failed; see kpa_last_error_string() */
+  KPA_ETIMEOUT = -7      /* a wait with a time limit ended before the work did */
 };
 
 /* Byte layout of a fixed-size little-endian row ("full record").  The key is a
@@ -608,11 +609,19 @@ kpa_status kpa_ingest_bundle(const void* host_rows, uint64_t n, const kpa_row_la
  * bundles and never refused.
  * kpa_server_poll: takes one finished result (waits up to timeout_ms; *got=0
  * if none).  kpa_server_drain: waits until every queued bundle and watermark
- * has been processed and every close has finished (timeout_ms < 0: no limit).
+ * has been processed and every close has finished (timeout_ms < 0: no limit;
+ * KPA_ETIMEOUT when the limit passes first, the server running on).
  * Latency of a window = time its result reached the host - time the closing
  * watermark was submitted.
  * A failure inside the server threads stops it; later calls return the
- * failing status with the message in kpa_last_error_string(). */
+ * failing status with the message in kpa_last_error_string().  Only window
+ * closes free pool memory, so nothing waits for memory that no close would
+ * free: a window close that needs more device memory than is free (the
+ * close reserve and unused pool) stops the server with KPA_EBUDGET; and when
+ * a bundle finds no memory or record while no close is queued or running,
+ * the server is stalled until a watermark closes a window: a blocking submit
+ * that finds the queue full then returns KPA_EBUDGET instead of waiting, and
+ * so does drain (the server runs on and a later watermark resumes it). */
 typedef enum kpa_query_kind { KPA_Q_SUM = 0, KPA_Q_MEDIAN = 1, KPA_Q_JOIN = 2 } kpa_query_kind;
 
 typedef struct kpa_server_config {
@@ -649,9 +658,10 @@ typedef enum kpa_placement {
 } kpa_placement;
 
 /* One refresh of the demand balance knob (Sec. 5), as the server's monitor
- * applies it every monitor_ms.  hbm_util: used fraction of the device pool;
- * bw_util: host-link bytes moved in the interval over what the link carries
- * at host_bw_gbs.  When capacity is the tighter resource (hbm_util exceeds
+ * applies it every monitor_ms.  hbm_util: fraction of the device pool
+ * outside the close reserve that bundles hold; bw_util: host-link use (rows
+ * in at ingest, host-pool KPAs out and back) over what the link carries at
+ * host_bw_gbs, smoothed over about 100 ms.  When capacity is the tighter resource (hbm_util exceeds
  * bw_util by more than 0.1) new KPAs move toward the host (step -0.05), when
  * bandwidth is, toward HBM (+0.05), else nothing changes.  The step goes to
  * k_low unless k_low already sits at the end it moves toward; then to k_high,
@@ -708,8 +718,9 @@ typedef struct kpa_server_stats {
 /* One sample of the server's monitor (every monitor_ms). */
 typedef struct kpa_monitor_sample {
   double t_s;            /* since the first submit */
-  double hbm_util;       /* device pool in use / its size */
-  double bw_util;        /* host-link bytes of the interval / what the link carries */
+  double hbm_util;       /* device pool held by bundles / the pool outside the close reserve */
+  double bw_util;        /* host-link use: bytes moved (rows in at ingest, host-pool KPAs
+                            out and back) / what the link carries, smoothed over ~100 ms */
   double k_low, k_high;
   double delay_ms;       /* current output delay: largest latency of the last 16 windows */
   uint64_t hbm_bytes;    /* device pool in use */

@@ -263,6 +263,7 @@ struct kpa_server_s {
   std::deque<kpa_window_result> results;
   u64 cmds_in = 0, cmds_done = 0, closes_in = 0, closes_done = 0;
   bool stop = false;
+  bool stalled = false;  // the dispatcher waits for memory that no queued close frees
   kpa_status failed = KPA_OK;
   std::string fail_msg;
 
@@ -279,6 +280,8 @@ struct kpa_server_s {
   u64 rng = 0;              // SplitMix64 counter of the placement draws
   u64 n_host = 0;           // bundle KPAs placed on the host
   u64 host_moved = 0;       // host-link bytes of host-pool KPAs (both directions)
+  u64 rows_moved = 0;       // host-link bytes of rows copied in at ingest
+  u64 close_bytes = 0;      // device pool held by window closes now (urgent work)
   double host_bw = 0.0;     // GB/s taken as full use of the host link
   std::vector<kpa_monitor_sample> trace;
   std::set<const uint64_t*> groups_out;  // per-key arrays handed to the caller
@@ -462,6 +465,7 @@ bool run_bundle(Server* s, const Cmd& c) {
         }
       }
       if (mem) {
+        s->stalled = false;
         b = new Bundle;
         b->q = c.q;
         b->side = c.side;
@@ -490,6 +494,7 @@ bool run_bundle(Server* s, const Cmd& c) {
         s->slots[si].used = true;
         s->n_bundles++;
         s->n_rows += c.n;
+        s->rows_moved += c.n * L.row_bytes;  // the rows come in over the host link
         break;
       }
       if (!waited) {
@@ -498,6 +503,15 @@ bool run_bundle(Server* s, const Cmd& c) {
       }
       // back-pressure: wait for a close to free memory, or for a slot
       early_watermarks(s, c.q, w_lo);
+      // stalled: memory or records are short and no close is queued or
+      // running; only a close frees them, so only a watermark that the
+      // producer has not sent yet can end the wait
+      const bool stalled = si < s->slots.size() && s->closes_in == s->closes_done;
+      if (stalled != s->stalled) {
+        s->stalled = stalled;
+        s->cv_space.notify_all();  // a blocked submit and drain look again
+        s->cv_done.notify_all();
+      }
       s->cv_space.wait_for(lk, std::chrono::microseconds(200));
     }
   }
@@ -613,30 +627,43 @@ void dispatcher_main(Server* s) {
 
 // -------------------------------------------------------------- closer --
 
+// Device memory of one close.  Only closes release pool memory (the bundles
+// of a closed window, and a close's own buffers when it ends), so a close that
+// finds too little free memory cannot wait for more: it reports the shortage
+// and the server stops with KPA_EBUDGET.  The short waits cover the
+// dispatcher, which may hold rows memory for a moment while it backs out of
+// an admission.
 struct CloseBufs {
   std::vector<std::pair<void*, u64>> held;
   Server* s;
-  bool never_fits = false;  // a buffer larger than the whole device pool was asked for
-  explicit CloseBufs(Server* sv) : s(sv) {}
+  bool short_mem = false;  // the close needs more device memory than is free
+  u64 asked = 0;           // bytes of the request that failed, and the close's total so far
+  u64 total = 0;
+  hipStream_t st;
+  CloseBufs(Server* sv, hipStream_t stream) : s(sv), st(stream) {}
   void* take(u64 bytes) {
     std::unique_lock<std::mutex> lk(s->mu);
-    while (true) {
+    for (int tries = 0; tries < 50; ++tries) {
       if (s->stop) return nullptr;
       void* p = s->pool.try_alloc(bytes, true);
       if (p) {
         held.emplace_back(p, bytes);
+        total += bytes;
+        s->close_bytes += bytes;
         return p;
-      }
-      if (!s->pool.fits_ever(bytes, true)) {
-        never_fits = true;
-        return nullptr;
       }
       s->cv_space.wait_for(lk, std::chrono::microseconds(200));
     }
+    short_mem = true;
+    asked = bytes;
+    return nullptr;
   }
   ~CloseBufs() {
+    // a close that fails part way may still have kernels in flight on them
+    if (!held.empty()) (void)hipStreamSynchronize(st);
     std::lock_guard<std::mutex> lk(s->mu);
     for (auto& h : held) s->pool.release(h.first, h.second);
+    s->close_bytes -= total;
     s->cv_space.notify_all();
   }
 };
@@ -701,15 +728,29 @@ long long merge_side(Server* s, CloseBufs& cb, const CloseJob& j, int side, u64*
   return (long long)n;
 }
 
-bool do_close(Server* s, const CloseJob& j, kpa_window_result* res, bool* budget) {
+bool do_close(Server* s, const CloseJob& j, kpa_window_result* res, std::string* budget) {
   Query& q = *s->queries[j.q];
   hipStream_t st = s->close_st;
-  CloseBufs cb(s);
+  CloseBufs cb(s, st);
   struct BudgetFlag {
     CloseBufs& cb;
-    bool* out;
-    ~BudgetFlag() { *out = cb.never_fits; }
-  } flag{cb, budget};
+    Server* s;
+    const CloseJob& j;
+    std::string* out;
+    ~BudgetFlag() {
+      if (!cb.short_mem) return;
+      char msg[320];
+      std::lock_guard<std::mutex> lk(s->mu);
+      std::snprintf(msg, sizeof(msg),
+                    "closing window %llu of query %u needs more device memory than is free "
+                    "(%llu bytes held by the close, %llu more asked, %llu of %llu pool bytes in "
+                    "use by open windows and the close)",
+                    (unsigned long long)j.w, j.q, (unsigned long long)cb.total,
+                    (unsigned long long)cb.asked, (unsigned long long)s->pool.used(),
+                    (unsigned long long)s->pool.size());
+      *out = msg;
+    }
+  } flag{cb, s, j, budget};
   std::memset(res, 0, sizeof(*res));
   res->query = j.q;
   res->kind = q.kind;
@@ -845,10 +886,10 @@ void closer_main(Server* s) {
       s->closes.pop_front();
     }
     kpa_window_result r;
-    bool budget = false;
+    std::string budget;
     if (!do_close(s, j, &r, &budget)) {
-      if (budget)
-        fail(s, KPA_EBUDGET, "window close needs more memory than the device pool holds");
+      if (!budget.empty())
+        fail(s, KPA_EBUDGET, budget.c_str());
       else
         fail(s, KPA_EHIP, "window close failed");
       return;
@@ -878,6 +919,7 @@ constexpr size_t TRACE_CAP = 65536;
 
 void monitor_main(Server* s) {
   u64 last_moved = 0;
+  double bw = 0.0;  // host-link use, smoothed over about 100 ms
   Clock::time_point last = Clock::now();
   std::unique_lock<std::mutex> lk(s->mu);
   while (!s->stop) {
@@ -886,10 +928,18 @@ void monitor_main(Server* s) {
     const Clock::time_point now = Clock::now();
     const double dt = std::chrono::duration<double>(now - last).count();
     if (dt <= 0) continue;
+    // capacity: the pool outside the close reserve, against what bundles
+    // hold (close scratch is urgent work from the reserve)
     const double cap = (double)(s->pool.size() - s->pool.size() / 100 * s->cfg.reserve_pct);
-    const double hbm = cap > 0 ? std::min(1.0, (double)s->pool.used() / cap) : 1.0;
-    const u64 moved = s->host_moved - last_moved;
-    const double bw = s->host_bw > 0 ? std::min(1.0, (double)moved / (dt * s->host_bw * 1e9)) : 0.0;
+    const u64 held = s->pool.used() - std::min(s->pool.used(), s->close_bytes);
+    const double hbm = cap > 0 ? std::min(1.0, (double)held / cap) : 1.0;
+    // link: rows in at ingest plus host-pool KPAs out and back
+    const u64 moved_now = s->host_moved + s->rows_moved;
+    const u64 moved = moved_now - last_moved;
+    const double inst =
+        s->host_bw > 0 ? std::min(1.0, (double)moved / (dt * s->host_bw * 1e9)) : 0.0;
+    const double a = dt / (dt + 0.1);
+    bw += a * (inst - bw);
     double delay = 0;
     const size_t nl = s->lat_ms.size();
     for (size_t i = nl > 16 ? nl - 16 : 0; i < nl; ++i) delay = std::max(delay, s->lat_ms[i]);
@@ -897,7 +947,7 @@ void monitor_main(Server* s) {
       (void)kpa_balance_knob_update(&s->k_low, &s->k_high, hbm, bw, delay,
                                     s->cfg.target_delay_ms);
     last = now;
-    last_moved = s->host_moved;
+    last_moved = moved_now;
     if (!s->started) continue;
     kpa_monitor_sample m;
     m.t_s = std::chrono::duration<double>(now - s->t_first).count();
@@ -1218,7 +1268,17 @@ kpa_status kpa_server_submit(kpa_server s, uint32_t qid, uint32_t side, const vo
     if (!blocking) {
       KPA_REQUIRE(false, KPA_EBUDGET, "pending queue full (back-pressure)");
     }
-    s->cv_space.wait(lk);
+    if (s->stalled) {
+      // a watermark sent meanwhile from another thread is applied within
+      // the dispatcher's next polls
+      s->cv_space.wait_for(lk, std::chrono::milliseconds(5));
+      KPA_REQUIRE(!s->stalled || s->cmds.size() < s->cfg.max_pending || s->failed != KPA_OK,
+                  KPA_EBUDGET,
+                  "pending queue full and the server stalled: the open windows hold all of the "
+                  "pool memory or bundle records, so only a later watermark can free them");
+    } else {
+      s->cv_space.wait(lk);
+    }
     KPA_REQUIRE(s->failed == KPA_OK, s->failed, "server failed: %s", s->fail_msg.c_str());
   }
   Cmd c;
@@ -1281,16 +1341,26 @@ kpa_status kpa_server_drain(kpa_server s, int32_t timeout_ms) {
   clear_error();
   KPA_REQUIRE(s != nullptr, KPA_EINVAL, "server is null");
   std::unique_lock<std::mutex> lk(s->mu);
-  auto idle = [&] {
+  auto done = [&] {
     return s->failed != KPA_OK ||
            (s->cmds_done == s->cmds_in && s->closes_done == s->closes_in);
   };
-  const bool ok = timeout_ms < 0 ? (s->cv_done.wait(lk, idle), true)
-                                 : s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms),
-                                                       idle);
-  KPA_REQUIRE(s->failed == KPA_OK, s->failed, "server failed: %s", s->fail_msg.c_str());
-  KPA_REQUIRE(ok, KPA_EBUDGET, "drain timed out (work still pending)");
-  return KPA_OK;
+  auto idle = [&] { return done() || s->stalled; };
+  const auto deadline = Clock::now() + std::chrono::milliseconds(std::max(timeout_ms, 0));
+  while (true) {
+    const bool ok = timeout_ms < 0 ? (s->cv_done.wait(lk, idle), true)
+                                   : s->cv_done.wait_until(lk, deadline, idle);
+    KPA_REQUIRE(s->failed == KPA_OK, s->failed, "server failed: %s", s->fail_msg.c_str());
+    KPA_REQUIRE(ok, KPA_ETIMEOUT, "drain timed out (work still pending)");
+    if (done()) return KPA_OK;
+    // stalled: a watermark sent meanwhile from another thread is applied
+    // within the dispatcher's next polls
+    s->cv_done.wait_for(lk, std::chrono::milliseconds(5), [&] { return done() || !s->stalled; });
+    KPA_REQUIRE(s->failed == KPA_OK, s->failed, "server failed: %s", s->fail_msg.c_str());
+    KPA_REQUIRE(done() || !s->stalled, KPA_EBUDGET,
+                "the server stalled: the open windows hold all of the pool memory or bundle "
+                "records, and no queued watermark closes one of them");
+  }
 }
 
 kpa_status kpa_server_stats(kpa_server s, kpa_server_statistics* out) {

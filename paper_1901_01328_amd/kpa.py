@@ -29,6 +29,7 @@ KPA_ECAPACITY = -3
 KPA_EBUDGET = -4
 KPA_EUNSUPPORTED = -5
 KPA_EHIP = -6
+KPA_ETIMEOUT = -7
 KPA_SORT_RADIX = 0
 KPA_SORT_LEARNED = 1
 KPA_Q_SUM = 0

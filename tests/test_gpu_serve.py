@@ -353,3 +353,76 @@ def test_balanced_placement_under_capacity_pressure(K, orc):
     check_against_oracle(res, exp)
     assert st["bundles_on_host"] > 0
     assert min(t["k_low"] for t in tr) < 1.0
+
+
+def one_window_bundle(n, seed):
+    """n rows whose timestamps all fall in window 0, pinned."""
+    rows = stream_rows("sum", n, seed)
+    rows[:, 2] = torch.arange(n, dtype=torch.int64) % (W // 2)
+    return rows.contiguous().pin_memory()
+
+
+def test_stalled_server_reports_instead_of_waiting(K):
+    """Bundles of one window fill the pool outside the close reserve and no
+    watermark comes: no close is queued, so only a watermark could free
+    memory.  A blocking submit that finds the pending queue full returns
+    KPA_EBUDGET instead of waiting for ever, so does drain, and the server
+    still shuts down."""
+    rows = one_window_bundle(1 << 13, 71)
+    srv = K.Server(budget_bytes=80 << 20, max_bundle_rows=1 << 13, max_pending=2, slots=1,
+                   reserve_pct=50)
+    q = srv.add_query(K.KPA_Q_SUM, LAYOUT32, W, 0)
+    say("serve stall: filling one window")
+    err = None
+    for i in range(2000):                  # the pool holds about 100 such bundles
+        try:
+            srv.submit(q, rows)
+        except K.KpaError as e:
+            err = e
+            break
+    assert err is not None and err.code == K.KPA_EBUDGET and "stalled" in str(err), err
+    with pytest.raises(K.KpaError) as d:
+        srv.drain(timeout_ms=20000)
+    assert d.value.code == K.KPA_EBUDGET and "stalled" in str(d.value)
+    st = srv.stats()
+    srv.close()
+    say(f"stalled after {i} bundles, {st['bundles']} admitted")
+    assert 50 < st["bundles"] < 200
+
+
+def test_close_short_of_memory_stops_the_server(K):
+    """With no close reserve, a window whose bundles hold 60% of the pool
+    cannot be merged (the close needs several times its runs' bytes).  The
+    closer cannot wait for memory that only closes free: the server stops
+    with KPA_EBUDGET and says which window, instead of hanging."""
+    rows = one_window_bundle(1 << 13, 72)
+    srv = K.Server(budget_bytes=80 << 20, max_bundle_rows=1 << 13, slots=1, reserve_pct=0,
+                   rows_in_host=1, max_pending=4096)
+    q = srv.add_query(K.KPA_Q_SUM, LAYOUT32, W, 0)
+    say("serve close short of memory")
+    for _ in range(360):                   # 360 x 2^13 rows x 16 B = 47 MB of runs
+        srv.submit(q, rows)
+    srv.watermark(q, W)
+    with pytest.raises(K.KpaError) as d:
+        srv.drain(timeout_ms=60000)
+    srv.close()
+    assert d.value.code == K.KPA_EBUDGET and "closing window 0" in str(d.value), d.value
+
+
+def test_drain_time_limit_is_a_timeout(K):
+    """drain with a time limit shorter than the work returns KPA_ETIMEOUT and
+    the server runs on; a later drain finishes."""
+    rows = one_window_bundle(1 << 16, 73)
+    srv = K.Server(budget_bytes=1 << 30, max_bundle_rows=1 << 16, slots=1, max_pending=4096,
+                   rows_in_host=1)
+    q = srv.add_query(K.KPA_Q_SUM, LAYOUT32, W, 0)
+    for _ in range(100):
+        srv.submit(q, rows)
+    srv.watermark(q, W)
+    with pytest.raises(K.KpaError) as d:
+        srv.drain(timeout_ms=1)
+    assert d.value.code == K.KPA_ETIMEOUT
+    srv.drain(timeout_ms=60000)
+    res = srv.results()
+    srv.close()
+    assert len(res) == 1 and res[0]["rows"][0] == 100 << 16
