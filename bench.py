@@ -50,7 +50,13 @@ PASS_BYTES = {
     "learned_finish": 24,   # read key+rid, write key+rid (entries of large windows)
     "learned_hist": 8,      # read key (entries of large windows)
 }
+# The same passes when the sort carries the staged value column beside the
+# KPA (8 more bytes read and written per entry and pass) and the reduction
+# reads keys and values in order.
+PASS_BYTES_KV = dict(PASS_BYTES, radix_pass=40, learned_scatter=40, learned_finish=40,
+                     reduce_main=16)
 LARGE_ONLY = {"learned_scatter", "learned_finish", "learned_hist", "radix_hist"}
+GROUP_BYTES = 32  # keyed reduction output per group: key, count, sum, max
 
 
 COPY_GBS = None  # device copy rate on this GPU (read + write bytes per second), set in main
@@ -172,9 +178,11 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def kernel_passes(K, steps, n, pass_bytes, n_large=None):
+def kernel_passes(K, steps, n, pass_bytes, n_large=None, extra=None):
     """Per-kernel launches per step, mean ms and algorithmic GB/s (recorded
-    with events on each launch's own stream since the last profile enable)."""
+    with events on each launch's own stream since the last profile enable).
+    extra: bytes per launch added to a kernel's per-entry bytes (the keyed
+    reduction's group outputs)."""
     K.kpa_profile_collect()
     passes = {}
     for name in K.kpa_profile_names():
@@ -185,7 +193,7 @@ def kernel_passes(K, steps, n, pass_bytes, n_large=None):
         entry = {"launches_per_step": cnt / steps, "avg_ms": round(avg, 4)}
         if name in pass_bytes and name != "radix_pass":
             m = n_large if (name in LARGE_ONLY and n_large is not None) else n
-            gbs = pass_bytes[name] * m / (avg / 1000.0) / 1e9
+            gbs = (pass_bytes[name] * m + (extra or {}).get(name, 0)) / (avg / 1000.0) / 1e9
             entry["alg_GBps"] = round(gbs, 1)
             entry["hbm_frac"] = round(gbs / HBM_PEAK_GBS, 4)
         passes[name] = entry
@@ -253,7 +261,8 @@ def bench_c4(a):
     pipe.step(rows, cfg=radix_cfg)
     pipe.fit_models()                      # epoch 1's models: epoch 0's sorted windows
     datagen.gen_c4(1, sizes, out=rows)
-    pipe.step(rows, cfg=radix_cfg)         # extracts epoch 1 (the tuner sorts pipe.keys)
+    pipe.step(rows, cfg=radix_cfg)
+    pipe.extract(rows)                     # epoch 1's keys: what the tuner sorts
     torch.cuda.synchronize()
     log(f"c4 epoch 1 generated; models fitted ({time.time() - t0:.1f} s)")
 
@@ -301,8 +310,14 @@ def bench_c4(a):
         for _ in range(prof_steps):
             pipe.step(rows, stream=stream, cfg=cfgs[r], fit_next=(r == "learned"))
         stream.synchronize()
-        res[r]["passes"] = kernel_passes(K, prof_steps, n, PASS_BYTES,
-                                         n_large=int(sizes[sizes > cfgs[r].mid_cap].sum()))
+        # the learned route carries the value column through its sort, the
+        # radix route's reduction follows the row ids (BatchAggregation's choice)
+        table = PASS_BYTES_KV if r == "learned" else PASS_BYTES
+        G = int(pipe.gseg[-1].item())
+        res[r]["groups_total"] = G
+        res[r]["passes"] = kernel_passes(K, prof_steps, n, table,
+                                         n_large=int(sizes[sizes > cfgs[r].mid_cap].sum()),
+                                         extra={"reduce_main": GROUP_BYTES * G})
         K.kpa_profile_enable(False)
         res[r]["sort_stats"] = pipe.stats.cpu().numpy().tolist()
         # outputs of this route: whole-array digests, and the sampled windows' groups
@@ -371,12 +386,14 @@ def bench_c4(a):
     roof = None
     if dom:
         pl = passes[dom]
+        tb = PASS_BYTES_KV if head == "learned" else PASS_BYTES
         if dom == "radix_pass":
-            per_launch = 24 * act / pl["launches_per_step"]
+            per_launch = tb[dom] * act / pl["launches_per_step"]
         elif dom in LARGE_ONLY:
-            per_launch = PASS_BYTES[dom] * large
+            per_launch = tb[dom] * large
         else:
-            per_launch = PASS_BYTES[dom] * n
+            per_launch = tb[dom] * n + (GROUP_BYTES * res[head]["groups_total"]
+                                        if dom == "reduce_main" else 0)
         tr = TRAFFIC.get(("c4", dom))
         traffic = counted_traffic(tr[1], tr[0], tr[2]) if tr else None
         roof = roofline(passes, dom, per_launch, traffic)
@@ -397,8 +414,8 @@ def bench_c4(a):
         "data": "synthetic",
         "config": {"workload": f"{n_seg} substream windows (sizes log-uniform over "
                    f"[2^10, 2^{a.c4_hi_log2}), {n} rows of 32 bytes), drifting rank-Zipf "
-                   "keys, PWL models fitted on the previous epoch; extract + batched sort + "
-                   "count/sum/max per key (+ next models' fit on the learned route), one "
+                   "keys, PWL models fitted on the previous epoch; extract + batched sort carrying "
+                   "the value column + count/sum/max per key (+ next models' fit on the learned route), one "
                    "graph replay per step", "route": head, "rows": n, "windows": n_seg,
                    "batch_config": cfgs[head].as_dict(), "autotune_sort_ms": tune_ms[head]},
         "roofline": roof, "cpu_baseline": cpu, "check": check,
@@ -412,11 +429,13 @@ def bench_c4(a):
         out["speedup_learned_vs_radix"] = round(rr["ms"] / res["learned"]["ms"], 4)
         rd = dominant(rr["passes"])
         if rd == "radix_pass":
-            out["radix"]["roofline"] = roofline(rr["passes"], rd,
-                                                24 * act / rr["passes"][rd]["launches_per_step"])
+            out["radix"]["roofline"] = roofline(
+                rr["passes"], rd, PASS_BYTES[rd] * act / rr["passes"][rd]["launches_per_step"])
         elif rd:
             m = int(sizes[sizes > cfgs["radix"].mid_cap].sum()) if rd in LARGE_ONLY else n
-            out["radix"]["roofline"] = roofline(rr["passes"], rd, PASS_BYTES[rd] * m)
+            out["radix"]["roofline"] = roofline(
+                rr["passes"], rd, PASS_BYTES[rd] * m + (GROUP_BYTES * rr["groups_total"]
+                                                       if rd == "reduce_main" else 0))
     if serving is not None:
         out["serving"] = serving
     if ablations is not None:

@@ -197,6 +197,25 @@ kpa_status kpa_sort(const uint64_t* keys_in, const uint32_t* rids_in, uint64_t n
                     uint64_t* keys_out, uint32_t* rids_out, kpa_sort_algo algo,
                     const kpa_pwl_model* model, kpa_sort_stats* stats, void* ws, size_t ws_bytes,
                     hipStream_t stream);
+/* The same sort with one 8-byte column carried beside the KPA: vals_in[i]
+ * belongs to entry i and vals_out receives it at that entry's sorted
+ * position (keys_out and rids_out exactly as kpa_sort_segmented writes them).
+ * A keyed reduction over that column then reads it in KPA order (row ids
+ * NULL in kpa_reduce_by_key) instead of following each row id to its record
+ * (Sec. 4.2 keyed aggregation dereferences one column per entry).  Costs 16
+ * bytes of traffic per entry and pass more than the KPA alone.  vals_in and
+ * vals_out: device, n_cap each, 8-byte aligned, not aliasing each other or
+ * the KPA arrays.  Workspace from kpa_sort_vals_workspace_size (larger than
+ * kpa_sort_workspace_size by the column's ping-pong buffers). */
+kpa_status kpa_sort_vals_workspace_size(uint64_t n_cap, uint32_t n_seg, kpa_sort_algo algo,
+                                        size_t* bytes);
+kpa_status kpa_sort_segmented_vals(const uint64_t* keys_in, const uint32_t* rids_in,
+                                   const uint64_t* vals_in, uint64_t* keys_out,
+                                   uint32_t* rids_out, uint64_t* vals_out,
+                                   const uint64_t* seg_off, uint32_t n_seg, uint64_t n_cap,
+                                   kpa_sort_algo algo, const kpa_pwl_model* models,
+                                   kpa_sort_stats* stats, void* ws, size_t ws_bytes,
+                                   hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Batched sort of many uneven segments (the windows of many substreams, all
@@ -231,6 +250,17 @@ kpa_status kpa_batch_sort(const uint64_t* keys_in, const uint32_t* rids_in, uint
                           uint64_t n_cap, const kpa_batch_config* cfg,
                           const kpa_pwl_model* models, kpa_sort_stats* stats, void* ws,
                           size_t ws_bytes, hipStream_t stream);
+/* kpa_batch_sort with one 8-byte column carried beside the KPA (as
+ * kpa_sort_segmented_vals: vals_out[j] is the value of the entry sorted to
+ * position j).  Workspace from kpa_batch_sort_vals_workspace_size. */
+kpa_status kpa_batch_sort_vals_workspace_size(uint64_t n_cap, uint32_t n_seg,
+                                              const kpa_batch_config* cfg, size_t* bytes);
+kpa_status kpa_batch_sort_vals(const uint64_t* keys_in, const uint32_t* rids_in,
+                               const uint64_t* vals_in, uint64_t* keys_out, uint32_t* rids_out,
+                               uint64_t* vals_out, const uint64_t* seg_off, uint32_t n_seg,
+                               uint64_t n_cap, const kpa_batch_config* cfg,
+                               const kpa_pwl_model* models, kpa_sort_stats* stats, void* ws,
+                               size_t ws_bytes, hipStream_t stream);
 /* Autotuner: times kpa_batch_sort on the given batch (one warm-up and `reps`
  * timed runs per candidate) over the class boundaries small_cap in {1024,
  * 2048, 4096} and mid_cap in {small_cap, 2^14, 2^16, 2^18}, and returns the
@@ -288,6 +318,10 @@ kpa_status kpa_merge_runs(uint64_t* keys, uint32_t* rids, const uint64_t* run_of
  * follow the pointers, coalesce a nonresident column over each run of equal
  * keys).  Input: a KPA sorted by key within each segment (segments as in
  * kpa_sort_segmented); rows: device arena of full records (the rids index it).
+ * rids may be NULL: entry i's row is then row i of `rows`, e.g. a value
+ * column that kpa_sort_segmented_vals or kpa_batch_sort_vals carried into
+ * the KPA's order, read with a layout of 8-byte rows (row_bytes 8, val_off 0,
+ * val_w 8).
  * A group is a maximal run of equal keys inside one segment.  For each group,
  * in order: out_gkey = key, out_cnt = entries, out_sum = sum of values mod
  * 2^64, out_max = largest value, out_gstart = index of its first entry.  Any

@@ -56,6 +56,7 @@ struct BatchWs {
   u32* counter;   // 1: next work-table item
   u64* keys_tmp;  // ping-pong buffer of the mid class (from the large path's plan)
   u32* rids_tmp;
+  u64* vals_tmp;  // the same for a value column (null without one)
   RadixWs rw;
   LearnedWs lw;
 };
@@ -101,28 +102,42 @@ __global__ void __launch_bounds__(1024) k_batch_classify(const u64* __restrict__
   }
 }
 
-// Small class: the whole segment in LDS.
+// Small class: the whole segment in LDS.  With a value column the on-chip
+// sort orders local indices, and row ids and values are gathered through
+// them from the segment's input (a few KB, in cache).
+template <bool VALS>
 __device__ void small_sort(BatchSmem& sm, const u64* __restrict__ keys_in,
-                           const u32* __restrict__ rids_in, u64* __restrict__ keys_out,
-                           u32* __restrict__ rids_out, u64 a, u32 n) {
+                           const u32* __restrict__ rids_in, const u64* __restrict__ vals_in,
+                           u64* __restrict__ keys_out, u32* __restrict__ rids_out,
+                           u64* __restrict__ vals_out, u64 a, u32 n) {
   const u32 tid = threadIdx.x;
   for (u32 i = tid; i < n; i += BLOCK) {
     sm.skeys[i] = keys_in[a + i];
-    sm.srids[i] = rids_in[a + i];
+    sm.srids[i] = VALS ? i : rids_in[a + i];
   }
   lds_sort(sm, n);  // begins with a barrier; leaves the result (or the input) in sm
   __syncthreads();
   for (u32 i = tid; i < n; i += BLOCK) {
     keys_out[a + i] = sm.skeys[i];
-    rids_out[a + i] = sm.srids[i];
+    if (VALS) {
+      const u32 o = sm.srids[i];
+      rids_out[a + i] = rids_in[a + o];
+      vals_out[a + i] = vals_in[a + o];
+    } else {
+      rids_out[a + i] = sm.srids[i];
+    }
   }
 }
 
-// Mid class: LSD radix over the varying bytes by one workgroup.
+// Mid class: LSD radix over the varying bytes by one workgroup.  With a
+// value column each tile's values follow its keys through the key slots of
+// LDS once the keys and row ids are written.
+template <bool VALS>
 __device__ void mid_sort(BatchSmem& sm, const u64* __restrict__ keys_in,
-                         const u32* __restrict__ rids_in, u64* __restrict__ keys_out,
-                         u32* __restrict__ rids_out, u64* __restrict__ keys_tmp,
-                         u32* __restrict__ rids_tmp, u64 a, u32 n) {
+                         const u32* __restrict__ rids_in, const u64* __restrict__ vals_in,
+                         u64* __restrict__ keys_out, u32* __restrict__ rids_out,
+                         u64* __restrict__ vals_out, u64* __restrict__ keys_tmp,
+                         u32* __restrict__ rids_tmp, u64* __restrict__ vals_tmp, u64 a, u32 n) {
   const u32 tid = threadIdx.x;
   u64 vor = 0, vand = ~0ull;
   for (u32 i = tid; i < n; i += BLOCK) {
@@ -141,6 +156,7 @@ __device__ void mid_sort(BatchSmem& sm, const u64* __restrict__ keys_in,
     for (u32 i = tid; i < n; i += BLOCK) {
       keys_out[a + i] = keys_in[a + i];
       rids_out[a + i] = rids_in[a + i];
+      if (VALS) vals_out[a + i] = vals_in[a + i];
     }
     return;
   }
@@ -166,10 +182,14 @@ __device__ void mid_sort(BatchSmem& sm, const u64* __restrict__ keys_in,
   u32 q = 0;
   for (u32 p = 0; p < 8; ++p) {
     if (!((amask >> p) & 1)) continue;
-    const u64* src_k = q == 0 ? keys_in : (((k_act - q) & 1) == 0 ? keys_out : keys_tmp);
-    const u32* src_r = q == 0 ? rids_in : (((k_act - q) & 1) == 0 ? rids_out : rids_tmp);
-    u64* dst_k = ((k_act - 1 - q) & 1) == 0 ? keys_out : keys_tmp;
-    u32* dst_r = ((k_act - 1 - q) & 1) == 0 ? rids_out : rids_tmp;
+    const bool first = q == 0, to_out = ((k_act - 1 - q) & 1) == 0;
+    const bool from_out = ((k_act - q) & 1) == 0;
+    const u64* src_k = first ? keys_in : (from_out ? keys_out : keys_tmp);
+    const u32* src_r = first ? rids_in : (from_out ? rids_out : rids_tmp);
+    const u64* src_v = first ? vals_in : (from_out ? vals_out : vals_tmp);
+    u64* dst_k = to_out ? keys_out : keys_tmp;
+    u32* dst_r = to_out ? rids_out : rids_tmp;
+    u64* dst_v = to_out ? vals_out : vals_tmp;
     for (u32 t = 0; t < n_tiles; ++t) {
       const u32 cnt = min((u32)TILE, n - t * TILE);
       const u64 base = a + (u64)t * TILE;
@@ -197,7 +217,18 @@ __device__ void mid_sort(BatchSmem& sm, const u64* __restrict__ keys_in,
       sm.dh[p][tid] = run + total;
       if (tid == 0) sm.count = tile_count;
       __syncthreads();
-      stage_scatter(sm, kk, rr, dd, rank, valid, dst_k, dst_r);
+      if (VALS) {
+        u32 pos[ITEMS];
+        stage_tile_pos<BatchSmem, ITEMS>(sm, kk, rr, dd, rank, valid, pos);
+        write_staged<BatchSmem, WAVES>(sm, dst_k, dst_r);
+        u64 vv[ITEMS];
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j)
+          vv[j] = ((valid >> j) & 1) ? src_v[base + tile_offset(j)] : 0ull;
+        write_staged_vals<BatchSmem, WAVES, ITEMS>(sm, vv, pos, valid, dst_v);
+      } else {
+        stage_scatter(sm, kk, rr, dd, rank, valid, dst_k, dst_r);
+      }
     }
     ++q;
     // the next pass reads what this one wrote (other threads' stores)
@@ -206,11 +237,13 @@ __device__ void mid_sort(BatchSmem& sm, const u64* __restrict__ keys_in,
   }
 }
 
+template <bool VALS>
 __global__ void __launch_bounds__(BLOCK, 2) k_batch_small_mid(
-    const u64* __restrict__ keys_in, const u32* __restrict__ rids_in, u64* __restrict__ keys_out,
-    u32* __restrict__ rids_out, u64* __restrict__ keys_tmp, u32* __restrict__ rids_tmp,
-    const u64* __restrict__ off, const u32* __restrict__ items, const u32* __restrict__ n_items,
-    u32* __restrict__ counter, u32 small_cap) {
+    const u64* __restrict__ keys_in, const u32* __restrict__ rids_in,
+    const u64* __restrict__ vals_in, u64* __restrict__ keys_out, u32* __restrict__ rids_out,
+    u64* __restrict__ vals_out, u64* __restrict__ keys_tmp, u32* __restrict__ rids_tmp,
+    u64* __restrict__ vals_tmp, const u64* __restrict__ off, const u32* __restrict__ items,
+    const u32* __restrict__ n_items, u32* __restrict__ counter, u32 small_cap) {
   __shared__ BatchSmem sm;
   const u32 total = *n_items;
   while (true) {
@@ -223,9 +256,10 @@ __global__ void __launch_bounds__(BLOCK, 2) k_batch_small_mid(
     const u64 a = off[s];
     const u32 n = (u32)(off[s + 1] - a);
     if (n <= small_cap)
-      small_sort(sm, keys_in, rids_in, keys_out, rids_out, a, n);
+      small_sort<VALS>(sm, keys_in, rids_in, vals_in, keys_out, rids_out, vals_out, a, n);
     else
-      mid_sort(sm, keys_in, rids_in, keys_out, rids_out, keys_tmp, rids_tmp, a, n);
+      mid_sort<VALS>(sm, keys_in, rids_in, vals_in, keys_out, rids_out, vals_out, keys_tmp,
+                     rids_tmp, vals_tmp, a, n);
   }
 }
 
@@ -239,20 +273,23 @@ kpa_status check_config(const kpa_batch_config* cfg) {
   return KPA_OK;
 }
 
-kpa_status batch_plan(u64 n_cap, u32 n_seg, const kpa_batch_config* cfg, Carver& c, BatchWs* w) {
+kpa_status batch_plan(u64 n_cap, u32 n_seg, const kpa_batch_config* cfg, Carver& c, BatchWs* w,
+                      bool vals = false) {
   w->large_lo = c.take<u64>(n_seg);
   w->large_hi = c.take<u64>(n_seg);
   w->items = c.take<u32>(n_seg);
   w->n_items = c.take<u32>(1);
   w->counter = c.take<u32>(1);
   if (cfg->large_algo == KPA_SORT_LEARNED) {
-    KPA_CHECK(learned_sort_plan(n_cap, n_seg, c, &w->lw));
+    KPA_CHECK(learned_sort_plan(n_cap, n_seg, c, &w->lw, vals));
     w->keys_tmp = w->lw.keys_tmp;
     w->rids_tmp = w->lw.rids_tmp;
+    w->vals_tmp = w->lw.vals_tmp;
   } else {
-    KPA_CHECK(radix_sort_plan(n_cap, n_seg, c, &w->rw));
+    KPA_CHECK(radix_sort_plan(n_cap, n_seg, c, &w->rw, vals));
     w->keys_tmp = w->rw.keys_tmp;
     w->rids_tmp = w->rw.rids_tmp;
+    w->vals_tmp = w->rw.vals_tmp;
   }
   return KPA_OK;
 }
@@ -264,7 +301,7 @@ u32 small_mid_grid(const kpa_batch_config* cfg) {
     hipDeviceProp_t p;
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess)
       return 1024;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_small_mid, BLOCK, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_small_mid<false>, BLOCK, 0) !=
             hipSuccess ||
         per_cu < 1)
       per_cu = 1;
@@ -273,23 +310,32 @@ u32 small_mid_grid(const kpa_batch_config* cfg) {
   return cfg->grid ? std::min<u32>(cfg->grid, 1u << 16) : resident;
 }
 
+// vals_in/vals_out: null, or a value column (the plan had vals).
 kpa_status batch_launch(const u64* keys_in, const u32* rids_in, u64* keys_out, u32* rids_out,
                         const u64* seg_off, u32 n_seg, const kpa_batch_config* cfg,
                         const kpa_pwl_model* models, kpa_sort_stats* stats, const BatchWs& w,
-                        hipStream_t st) {
+                        hipStream_t st, const u64* vals_in = nullptr, u64* vals_out = nullptr) {
+  KPA_REQUIRE(!vals_in || (vals_out && w.vals_tmp), KPA_EINVAL,
+              "a value column needs an output and a planned buffer");
   KPA_LAUNCH("batch_classify", k_batch_classify, dim3(1), dim3(1024), 0, st, seg_off, n_seg,
              cfg->mid_cap, w.large_lo, w.large_hi, w.items, w.n_items,
              w.counter);
-  KPA_LAUNCH("batch_small_mid", k_batch_small_mid, dim3(small_mid_grid(cfg)), dim3(BLOCK), 0, st,
-             keys_in, rids_in, keys_out, rids_out, w.keys_tmp, w.rids_tmp, seg_off, w.items,
-             w.n_items, w.counter, cfg->small_cap);
+  if (vals_in)
+    KPA_LAUNCH("batch_small_mid", k_batch_small_mid<true>, dim3(small_mid_grid(cfg)), dim3(BLOCK),
+               0, st, keys_in, rids_in, vals_in, keys_out, rids_out, vals_out, w.keys_tmp,
+               w.rids_tmp, w.vals_tmp, seg_off, w.items, w.n_items, w.counter, cfg->small_cap);
+  else
+    KPA_LAUNCH("batch_small_mid", k_batch_small_mid<false>, dim3(small_mid_grid(cfg)),
+               dim3(BLOCK), 0, st, keys_in, rids_in, nullptr, keys_out, rids_out, nullptr,
+               w.keys_tmp, w.rids_tmp, nullptr, seg_off, w.items, w.n_items, w.counter,
+               cfg->small_cap);
   const SegList large{w.large_lo, w.large_hi, nullptr, n_seg};
   if (cfg->large_algo == KPA_SORT_LEARNED)
     return learned_sort_launch(keys_in, rids_in, keys_out, rids_out, large, models, stats, w.lw,
-                               st);
+                               st, vals_in, vals_out);
   if (stats) KPA_CHECK(launch_fill_u64(reinterpret_cast<u64*>(stats), STATS_WORDS, 0, st));
   return radix_sort_launch(keys_in, rids_in, keys_out, rids_out, large, w.rw, st,
-                           stats_unsupported(stats));
+                           stats_unsupported(stats), vals_in, vals_out);
 }
 
 kpa_status check_args(const uint64_t* keys_in, const uint32_t* rids_in, uint64_t* keys_out,
@@ -406,6 +452,39 @@ kpa_status kpa_batch_sort(const uint64_t* keys_in, const uint32_t* rids_in, uint
   KPA_REQUIRE(c.used <= ws_bytes, KPA_EWORKSPACE, "workspace too small: need %zu bytes", c.used);
   return batch_launch(keys_in, rids_in, keys_out, rids_out, seg_off, n_seg, cfg, models, stats,
                       w, stream);
+}
+
+kpa_status kpa_batch_sort_vals_workspace_size(uint64_t n_cap, uint32_t n_seg,
+                                              const kpa_batch_config* cfg, size_t* bytes) {
+  clear_error();
+  KPA_REQUIRE(bytes != nullptr, KPA_EINVAL, "bytes is null");
+  KPA_CHECK(check_config(cfg));
+  Carver c(nullptr);
+  BatchWs w;
+  KPA_CHECK(batch_plan(n_cap, n_seg ? n_seg : 1, cfg, c, &w, true));
+  *bytes = c.used + 256;
+  return KPA_OK;
+}
+
+kpa_status kpa_batch_sort_vals(const uint64_t* keys_in, const uint32_t* rids_in,
+                               const uint64_t* vals_in, uint64_t* keys_out, uint32_t* rids_out,
+                               uint64_t* vals_out, const uint64_t* seg_off, uint32_t n_seg,
+                               uint64_t n_cap, const kpa_batch_config* cfg,
+                               const kpa_pwl_model* models, kpa_sort_stats* stats, void* ws,
+                               size_t ws_bytes, hipStream_t stream) {
+  clear_error();
+  KPA_CHECK(check_config(cfg));
+  if (n_seg == 0 || n_cap == 0) return KPA_OK;
+  KPA_CHECK(check_args(keys_in, rids_in, keys_out, rids_out, seg_off, n_cap, cfg, models, ws));
+  KPA_REQUIRE(vals_in && vals_out, KPA_EINVAL, "null pointer");
+  KPA_REQUIRE(vals_in != vals_out, KPA_EINVAL, "inputs must not alias outputs");
+  KPA_REQUIRE(aligned(vals_in, 8) && aligned(vals_out, 8), KPA_EINVAL, "misaligned pointer");
+  Carver c(ws);
+  BatchWs w;
+  KPA_CHECK(batch_plan(n_cap, n_seg, cfg, c, &w, true));
+  KPA_REQUIRE(c.used <= ws_bytes, KPA_EWORKSPACE, "workspace too small: need %zu bytes", c.used);
+  return batch_launch(keys_in, rids_in, keys_out, rids_out, seg_off, n_seg, cfg, models, stats,
+                      w, stream, vals_in, vals_out);
 }
 
 kpa_status kpa_batch_autotune(const uint64_t* keys_in, const uint32_t* rids_in,

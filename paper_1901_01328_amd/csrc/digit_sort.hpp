@@ -10,6 +10,10 @@
 
 #include "sort_internal.hpp"
 
+#include <map>
+#include <mutex>
+#include <utility>
+
 namespace kpa {
 
 constexpr int HIST_TILES_PER_BLOCK = 8;
@@ -30,6 +34,16 @@ struct DigitSortBufs {
   u64 max_tiles;
   OrderBufs order;
   u64* unsupported;  // may be null: entries of segments too large to sort (copied through)
+  // an optional value column carried through the same permutation (all
+  // three null when there is none)
+  const u64* vals_in = nullptr;
+  u64* vals_out = nullptr;
+  u64* vals_tmp = nullptr;
+  // in place: the data is in the output arrays (keys_in == keys_out); a
+  // segment with an even number of passes reads them in its first pass, one
+  // with an odd number is first copied to the tmp arrays (k_ds_copy_odd) so
+  // that its last pass still lands in the output
+  bool in_place = false;
 };
 
 __device__ __forceinline__ void seg_tile_range(const SegList& sl, const u32* tile_start,
@@ -374,6 +388,26 @@ __global__ void __launch_bounds__(LIST_BLK) k_ds_lfill(const u32* __restrict__ t
   }
 }
 
+// In-place sorts: the tiles of segments with an odd number of active
+// passes are copied to the tmp arrays, where their first pass reads them.
+template <int UNUSED = 0>
+__global__ void __launch_bounds__(BLOCK) k_ds_copy_odd(DigitSortBufs bf, SegList sl) {
+  const u32 n_seg = sl.n();
+  const u32 total = bf.tile_start[n_seg];
+  for (u32 tile = blockIdx.x; tile < total; tile += gridDim.x) {
+    u32 seg, t_in, cnt;
+    u64 a, b, base;
+    seg_tile_range(sl, bf.tile_start, n_seg, tile, seg, t_in, a, b, base, cnt);
+    const u32 m = bf.seg_mask[seg];
+    if (m == 0 || (m & SEG_UNSUPPORTED) || (__popc(m) & 1) == 0) continue;
+    for (u32 i = threadIdx.x; i < cnt; i += BLOCK) {
+      bf.keys_tmp[base + i] = bf.keys_out[base + i];
+      bf.rids_tmp[base + i] = bf.rids_out[base + i];
+      if (bf.vals_out) bf.vals_tmp[base + i] = bf.vals_out[base + i];
+    }
+  }
+}
+
 // Geometry of the scatter pass: PASS_WAVES waves per workgroup, so that two
 // workgroups per CU keep 4*PASS_WAVES/4 waves on each SIMD while the tile stays
 // TILE entries.
@@ -392,7 +426,11 @@ static_assert(PASS_THREADS >= RADIX && PASS_ITEMS * PASS_THREADS == TILE, "pass 
 // write.  The prefetched tile publishes its counts only after the current
 // one is written; every wait of a look-back still goes to a tile claimed
 // earlier, so the waits cannot form a cycle.
-template <class DF>
+//
+// VALS: the value column moves with the keys: after a tile's keys and row
+// ids are written, its values (loaded during the look-back) go through the
+// key slots of LDS to the same destinations.
+template <class DF, bool VALS>
 __global__ void __launch_bounds__(PASS_THREADS, PASS_WAVES / 2)
     k_ds_pass(DigitSortBufs bf, SegList sl, typename DF::Params prm, u32 pass,
               u32* __restrict__ status_cur, u32* __restrict__ status_next) {
@@ -430,6 +468,7 @@ __global__ void __launch_bounds__(PASS_THREADS, PASS_WAVES / 2)
           for (u32 i = tid; i < td.cnt; i += PASS_THREADS) {
             bf.keys_out[td.base + i] = bf.keys_in[td.base + i];
             bf.rids_out[td.base + i] = bf.rids_in[td.base + i];
+            if (VALS) bf.vals_out[td.base + i] = bf.vals_in[td.base + i];
           }
         }
         continue;
@@ -441,8 +480,9 @@ __global__ void __launch_bounds__(PASS_THREADS, PASS_WAVES / 2)
   // many of the segment's passes came before); returns the present-item bits.
   auto load = [&](const TileDesc& td, u64 (&kk)[PASS_ITEMS], u32 (&rr)[PASS_ITEMS]) -> u32 {
     const u32 k = __popc(td.mask), q = __popc(td.mask & ((1u << pass) - 1));
-    const u64* src_k = q == 0 ? bf.keys_in : (((k - q) & 1) == 0 ? bf.keys_out : bf.keys_tmp);
-    const u32* src_r = q == 0 ? bf.rids_in : (((k - q) & 1) == 0 ? bf.rids_out : bf.rids_tmp);
+    const bool from_in = q == 0 && !bf.in_place;
+    const u64* src_k = from_in ? bf.keys_in : (((k - q) & 1) == 0 ? bf.keys_out : bf.keys_tmp);
+    const u32* src_r = from_in ? bf.rids_in : (((k - q) & 1) == 0 ? bf.rids_out : bf.rids_tmp);
     u32 valid = 0;
 #pragma unroll
     for (int j = 0; j < PASS_ITEMS; ++j) {
@@ -485,14 +525,35 @@ __global__ void __launch_bounds__(PASS_THREADS, PASS_WAVES / 2)
 #pragma unroll
     for (int j = 0; j < PASS_ITEMS; ++j) dd[j] = ((valid >> j) & 1) ? df.digit(kk[j], pass) : 0u;
     u32 tile_count;
+    u32 pos[PASS_ITEMS];
     const u32 cnt_d =
-        onesweep_rank_stage(sm, kk, rr, dd, valid, status_cur, td.g, td.t_in, &tile_count);
+        VALS ? onesweep_rank_stage_pos(sm, kk, rr, dd, valid, status_cur, td.g, td.t_in,
+                                       &tile_count, pos)
+             : onesweep_rank_stage(sm, kk, rr, dd, valid, status_cur, td.g, td.t_in, &tile_count);
+    // this tile's values, in flight during the look-back and the key write
+    u64 vv[PASS_ITEMS];
+    if (VALS) {
+      const u64* src_v = (q == 0 && !bf.in_place)
+                             ? bf.vals_in
+                             : (((k - q) & 1) == 0 ? bf.vals_out : bf.vals_tmp);
+#pragma unroll
+      for (int j = 0; j < PASS_ITEMS; ++j) {
+        const u32 o = tile_offset_t<PASS_WAVES>(j);
+        vv[j] = ((valid >> j) & 1) ? src_v[td.base + o] : 0ull;
+      }
+    }
+    const u32 cur_valid = valid;
     TileDesc nt;
     const bool more = claim(nt);
     const u32 nvalid = more ? load(nt, kk, rr) : 0u;
     if (more && nt.seg != td.seg) stg = DF::fetch(prm, nt.seg);  // in flight during the write
     onesweep_lookback_write(sm, status_cur, td.g, td.t_in, cnt_d, tile_count, my_base, dst_k,
                             dst_r);
+    if (VALS) {
+      u64* dst_v = ((k - 1 - q) & 1) == 0 ? bf.vals_out : bf.vals_tmp;
+      write_staged_vals<OnesweepSmemT<PASS_WAVES>, PASS_WAVES, PASS_ITEMS>(sm, vv, pos, cur_valid,
+                                                                          dst_v);
+    }
     if (!more) return;
     td = nt;
     valid = nvalid;
@@ -500,20 +561,32 @@ __global__ void __launch_bounds__(PASS_THREADS, PASS_WAVES / 2)
 }
 
 // Workgroups of `threads` threads that fit on the device at once for a kernel
-// (persistent grids); computed once per kernel instantiation.
+// (persistent grids); computed once per kernel and thread count (kernels of
+// one signature share a function-pointer type, so the cache is keyed by the
+// kernel's address).
 template <class K>
 u32 resident_grid(K kernel, u32 cap, int threads = BLOCK) {
-  static u32 cached = 0;
-  if (!cached) {
+  static std::mutex mu;
+  static std::map<std::pair<const void*, int>, u32> cache;
+  const std::pair<const void*, int> key{reinterpret_cast<const void*>(kernel), threads};
+  u32 grid = 0;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) grid = it->second;
+  }
+  if (!grid) {
     int dev = 0, per_cu = 1;
     hipDeviceProp_t p;
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) return cap;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
         per_cu < 1)
       per_cu = 1;
-    cached = (u32)(p.multiProcessorCount * per_cu);
+    grid = (u32)(p.multiProcessorCount * per_cu);
+    std::lock_guard<std::mutex> lk(mu);
+    cache[key] = grid;
   }
-  return cached < cap ? cached : cap;
+  return grid < cap ? grid : cap;
 }
 
 // with_hist: count digits and derive offsets and pass masks here; otherwise
@@ -535,6 +608,10 @@ kpa_status digit_sort_launch(const SegList& sl, const typename DF::Params& prm,
                dim3(std::min<u32>(sl.n_max, 2048)), dim3(BLOCK), 0, st, sl, b.hist, b.seg_mask,
                b.unsupported);
   }
+  if (b.in_place)
+    KPA_LAUNCH("sort_copy_odd", k_ds_copy_odd<0>,
+               dim3((u32)std::min<u64>(std::max<u64>(b.max_tiles, 1), 4096)), dim3(BLOCK), 0, st,
+               b, sl);
   const dim3 seg_grid((u32)std::min<u64>(ceil_div(std::max<u32>(sl.n_max, 1), BLOCK), 1024));
   KPA_LAUNCH("sort_count", k_ds_count<0>, seg_grid, dim3(BLOCK), 0, st, sl, b.tile_start,
              b.order.more, b.counters);
@@ -553,14 +630,20 @@ kpa_status digit_sort_launch(const SegList& sl, const typename DF::Params& prm,
              nblk);
   KPA_LAUNCH("sort_lists", k_ds_lfill<DF::PASSES>, dim3(nblk), dim3(LIST_BLK), 0, st,
              b.tile_start, sl, b.order.desc, b.order.lcount, nblk, b.order.lists, b.max_tiles);
-  const u32 grid =
-      resident_grid(k_ds_pass<DF>, (u32)std::min<u64>(b.max_tiles, 1u << 20), PASS_THREADS);
+  const bool vals = b.vals_in != nullptr;
+  const u32 cap = (u32)std::min<u64>(b.max_tiles, 1u << 20);
+  const u32 grid = vals ? resident_grid(k_ds_pass<DF, true>, cap, PASS_THREADS)
+                        : resident_grid(k_ds_pass<DF, false>, cap, PASS_THREADS);
   const char* pname = radix ? "radix_pass" : (DF::PASSES == 2 ? "learned_scatter" : "pivot_scatter");
   for (u32 p = 0; p < (u32)DF::PASSES; ++p) {
     u32* cur = (p & 1) ? b.status1 : b.status0;
     u32* nxt = (p & 1) ? b.status0 : b.status1;
-    KPA_LAUNCH(pname, k_ds_pass<DF>, dim3(grid), dim3(PASS_THREADS), 0, st, b, sl, prm, p, cur,
-               nxt);
+    if (vals)
+      KPA_LAUNCH(pname, (k_ds_pass<DF, true>), dim3(grid), dim3(PASS_THREADS), 0, st, b, sl, prm,
+                 p, cur, nxt);
+    else
+      KPA_LAUNCH(pname, (k_ds_pass<DF, false>), dim3(grid), dim3(PASS_THREADS), 0, st, b, sl, prm,
+                 p, cur, nxt);
   }
   return KPA_OK;
 }

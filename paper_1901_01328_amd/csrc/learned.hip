@@ -672,8 +672,33 @@ __global__ void __launch_bounds__(BLOCK) k_fin_active(const u64* __restrict__ ke
 // chunk's sort only permutes entries inside the chunk's buckets, so the
 // bucket of every position never changes and the edges found do not depend on
 // timing.  Every return is uniform over the workgroup.
+//
+// VALS: the chunk also carries a value column.  The on-chip sort then
+// orders local indices instead of row ids, and after the keys are written
+// the chunk's row ids and values are read into the free LDS areas and
+// written in the sorted order.
+// Permutes the row ids and values of [start, start + m) in place by the local
+// indices in sm.srids (sm.srids[i] = old position of the entry now at i).
+// The caller has written the sorted keys; begins with a barrier.
+__device__ __forceinline__ void permute_rids_vals(FinishSmem& sm, u32* __restrict__ rids,
+                                                  u64* __restrict__ vals, u64 start, u32 m) {
+  __syncthreads();  // every thread has read the sorted keys from sm.skeys
+  for (u32 i = threadIdx.x; i < m; i += FIN_THREADS) {
+    sm.skeys[i] = vals[start + i];
+    sm.srel[i] = rids[start + i];
+  }
+  __syncthreads();
+  for (u32 i = threadIdx.x; i < m; i += FIN_THREADS) {
+    const u32 o = sm.srids[i];
+    vals[start + i] = sm.skeys[o];
+    rids[start + i] = sm.srel[o];
+  }
+}
+
+template <bool VALS>
 __device__ __forceinline__ void finish_stretch(
-    FinishSmem& sm, u64* __restrict__ keys, u32* __restrict__ rids, const SegList& sl,
+    FinishSmem& sm, u64* __restrict__ keys, u32* __restrict__ rids, u64* __restrict__ vals,
+    const SegList& sl,
     const SegModel* __restrict__ segm, u64* __restrict__ fb_lo, u64* __restrict__ fb_hi,
     u32* __restrict__ fb_seg, u32* __restrict__ fb_count, u32 max_fb, kpa_sort_stats* stats,
     u64 item) {
@@ -716,7 +741,7 @@ __device__ __forceinline__ void finish_stretch(
   }
   const u64 start = L0 + s0;
   // row ids of the chunk's likely extent, in flight during the search below
-  const u32 rguess = min(have - s0, FCAP);
+  const u32 rguess = VALS ? 0u : min(have - s0, FCAP);
   u32 rr[FIN_IT];
 #pragma unroll
   for (int j = 0; j < FIN_IT; ++j) {
@@ -792,12 +817,16 @@ __device__ __forceinline__ void finish_stretch(
   }
 
   const u32 mcount = endo;  // <= FCAP
+  if (VALS) {
+    for (u32 i = tid; i < mcount; i += FIN_THREADS) sm.srids[i] = i;
+  } else {
 #pragma unroll
-  for (int j = 0; j < FIN_IT; ++j) {
-    const u32 i = tid + j * FIN_THREADS;
-    if (i < mcount && i < rguess) sm.srids[i] = rr[j];
+    for (int j = 0; j < FIN_IT; ++j) {
+      const u32 i = tid + j * FIN_THREADS;
+      if (i < mcount && i < rguess) sm.srids[i] = rr[j];
+    }
+    for (u32 i = rguess + tid; i < mcount; i += FIN_THREADS) sm.srids[i] = rids[start + i];
   }
-  for (u32 i = rguess + tid; i < mcount; i += FIN_THREADS) sm.srids[i] = rids[start + i];
   u32 res;
   if (mcount <= 2048)
     res = lds_sort_model<4>(sm, m, mcount);
@@ -807,6 +836,11 @@ __device__ __forceinline__ void finish_stretch(
     res = lds_sort_model<8>(sm, m, mcount);
   if (tid == 0) stat_add(stats, res == CH_EQUAL ? ST_EQUAL : ST_ONCHIP, mcount);
   if (res != CH_MOVED) return;
+  if (VALS) {
+    for (u32 i = tid; i < mcount; i += FIN_THREADS) keys[start + i] = sm.skeys[i];
+    permute_rids_vals(sm, rids, vals, start, mcount);
+    return;
+  }
   for (u32 i = tid; i < mcount; i += FIN_THREADS) {
     keys[start + i] = sm.skeys[i];
     rids[start + i] = sm.srids[i];
@@ -816,23 +850,26 @@ __device__ __forceinline__ void finish_stretch(
 // One workgroup per listed stretch (the grid covers every stretch; the
 // workgroups past the list's end return at once).  A persistent loop over the
 // list needs more registers than the body alone and measured slower.
+template <bool VALS>
 __global__ void __launch_bounds__(FIN_THREADS, 4) k_learned_finish(
-    u64* __restrict__ keys, u32* __restrict__ rids, SegList sl,
+    u64* __restrict__ keys, u32* __restrict__ rids, u64* __restrict__ vals, SegList sl,
     const SegModel* __restrict__ segm, const u64* __restrict__ active,
     const u32* __restrict__ n_active, u64* __restrict__ fb_lo, u64* __restrict__ fb_hi,
     u32* __restrict__ fb_seg, u32* __restrict__ fb_count, u32 max_fb, kpa_sort_stats* stats) {
   __shared__ FinishSmem sm;
   if (blockIdx.x >= *n_active) return;
-  finish_stretch(sm, keys, rids, sl, segm, fb_lo, fb_hi, fb_seg, fb_count, max_fb, stats,
-                 active[blockIdx.x]);
+  finish_stretch<VALS>(sm, keys, rids, vals, sl, segm, fb_lo, fb_hi, fb_seg, fb_count, max_fb,
+                       stats, active[blockIdx.x]);
 }
 
 // Sorts listed ranges of at most FCAP entries in place, one workgroup each.
 // A range is a part of an oversize chunk, in bucket order; above FIN_THREADS
 // entries it is sorted as a finishing chunk is, by its segment's refined
 // bucket ids and then within runs of equal id.
+template <bool VALS>
 __global__ void __launch_bounds__(FIN_THREADS, 4) k_lds_sort_ranges(u64* __restrict__ keys,
                                                            u32* __restrict__ rids,
+                                                           u64* __restrict__ vals,
                                                            const u64* __restrict__ lo,
                                                            const u64* __restrict__ hi,
                                                            const u32* __restrict__ seg,
@@ -849,7 +886,7 @@ __global__ void __launch_bounds__(FIN_THREADS, 4) k_lds_sort_ranges(u64* __restr
     if (m <= FIN_THREADS) {
       for (u32 i = threadIdx.x; i < m; i += FIN_THREADS) {
         sm.skeys[i] = keys[a + i];
-        sm.srids[i] = rids[a + i];
+        sm.srids[i] = VALS ? i : rids[a + i];
       }
       moved = rank_sort_small(sm, m);
     } else {
@@ -859,7 +896,7 @@ __global__ void __launch_bounds__(FIN_THREADS, 4) k_lds_sort_ranges(u64* __restr
       for (u32 i = threadIdx.x; i < m; i += FIN_THREADS) {
         const u64 k = keys[a + i];
         sm.skeys[i] = k;
-        sm.srids[i] = rids[a + i];
+        sm.srids[i] = VALS ? i : rids[a + i];
         sm.srel[i] = md.valid ? model_fine(md, kn, k) : 0u;
       }
       __syncthreads();  // the sort reads other threads' entries before its first barrier
@@ -873,9 +910,14 @@ __global__ void __launch_bounds__(FIN_THREADS, 4) k_lds_sort_ranges(u64* __restr
       moved = res == CH_MOVED;
     }
     if (moved) {
-      for (u32 i = threadIdx.x; i < m; i += FIN_THREADS) {
-        keys[a + i] = sm.skeys[i];
-        rids[a + i] = sm.srids[i];
+      if (VALS) {
+        for (u32 i = threadIdx.x; i < m; i += FIN_THREADS) keys[a + i] = sm.skeys[i];
+        permute_rids_vals(sm, rids, vals, a, m);
+      } else {
+        for (u32 i = threadIdx.x; i < m; i += FIN_THREADS) {
+          keys[a + i] = sm.skeys[i];
+          rids[a + i] = sm.srids[i];
+        }
       }
     }
   }
@@ -1041,26 +1083,6 @@ __global__ void __launch_bounds__(BLOCK) k_fb_plan(SegList sl, const u32* __rest
   }
 }
 
-// Copies every listed chunk to the radix fallback's input buffer.
-__global__ void __launch_bounds__(BLOCK) k_fb_copy_all(const u64* __restrict__ keys,
-                                                       const u32* __restrict__ rids, SegList sl,
-                                                       const u32* __restrict__ tile_start,
-                                                       const u32* __restrict__ tile_seg,
-                                                       u64* __restrict__ keys_dst,
-                                                       u32* __restrict__ rids_dst) {
-  const u32 n_seg = sl.n();
-  const u32 total = tile_start[n_seg];
-  for (u32 tile = blockIdx.x; tile < total; tile += gridDim.x) {
-    u32 seg, t_in, cnt;
-    u64 a, b, base;
-    seg_tile_range(sl, tile_start, n_seg, tile, seg, t_in, a, b, base, cnt, tile_seg);
-    for (u32 i = threadIdx.x; i < cnt; i += BLOCK) {
-      keys_dst[base + i] = keys[base + i];
-      rids_dst[base + i] = rids[base + i];
-    }
-  }
-}
-
 // Per chunk to split (one workgroup each): the counts of entries below and
 // equal to the pivot in the chunk's earlier tiles (exclusive prefix over its
 // tiles, in place).
@@ -1107,7 +1129,9 @@ __global__ void __launch_bounds__(BLOCK) k_fb_move(const u64* __restrict__ keys,
                                                    const u32* __restrict__ t_eq,
                                                    const uint16_t* __restrict__ t_eqbits,
                                                    u64* __restrict__ keys_tmp,
-                                                   u32* __restrict__ rids_tmp) {
+                                                   u32* __restrict__ rids_tmp,
+                                                   const u64* __restrict__ vals,
+                                                   u64* __restrict__ vals_tmp) {
   __shared__ u32 whist[WAVES][RADIX];
   const u32 n_seg = sl.n();
   const u32 total = tile_start[n_seg];
@@ -1147,6 +1171,7 @@ __global__ void __launch_bounds__(BLOCK) k_fb_move(const u64* __restrict__ keys,
         const u64 dst = start[d[j]] + whist[w][d[j]] + rank[j];
         rids_tmp[dst] = rr[j];
         if (d[j] != 1) keys_tmp[dst] = kk[j];
+        if (vals) vals_tmp[dst] = vals[base + tile_offset(j)];
       }
     }
   }
@@ -1164,7 +1189,9 @@ __global__ void __launch_bounds__(BLOCK) k_fb_back(u64* __restrict__ keys, u32* 
                                                    const u32* __restrict__ p_mask,
                                                    const uint16_t* __restrict__ t_eqbits,
                                                    const u64* __restrict__ keys_tmp,
-                                                   const u32* __restrict__ rids_tmp) {
+                                                   const u32* __restrict__ rids_tmp,
+                                                   u64* __restrict__ vals,
+                                                   const u64* __restrict__ vals_tmp) {
   const u32 n_seg = sl.n();
   const u32 total = tile_start[n_seg];
   for (u32 tile = blockIdx.x; tile < total; tile += gridDim.x) {
@@ -1189,6 +1216,7 @@ __global__ void __launch_bounds__(BLOCK) k_fb_back(u64* __restrict__ keys, u32* 
       const u64 p = base + tile_offset(j);
       if (tile_offset(j) < cnt) {
         rids[p] = rv[j];
+        if (vals) vals[p] = vals_tmp[p];
         // in the equal part the pivot is already there where the chunk held it
         if (p < e0 || p >= e1 || !((eqbits >> j) & 1)) keys[p] = kv[j];
       }
@@ -1196,7 +1224,7 @@ __global__ void __launch_bounds__(BLOCK) k_fb_back(u64* __restrict__ keys, u32* 
   }
 }
 
-kpa_status learned_sort_plan(u64 n_cap, u32 n_seg, Carver& c, LearnedWs* w) {
+kpa_status learned_sort_plan(u64 n_cap, u32 n_seg, Carver& c, LearnedWs* w, bool vals) {
   w->n_cap = n_cap;
   w->max_tiles = max_tiles(n_cap, n_seg, TILE);
   w->max_ftiles = max_tiles(n_cap, n_seg, FH);
@@ -1204,6 +1232,7 @@ kpa_status learned_sort_plan(u64 n_cap, u32 n_seg, Carver& c, LearnedWs* w) {
   w->max_fb = (u32)(n_cap / FCAP + n_seg + 1);
   w->keys_tmp = c.take<u64>(n_cap);
   w->rids_tmp = c.take<u32>(n_cap);
+  w->vals_tmp = vals ? c.take<u64>(n_cap) : nullptr;
   w->segm = c.take<SegModel>(n_seg);
   w->cur_min = c.take<u64>(n_seg);
   w->cur_max = c.take<u64>(n_seg);
@@ -1244,12 +1273,18 @@ kpa_status learned_sort_plan(u64 n_cap, u32 n_seg, Carver& c, LearnedWs* w) {
   w->t_eqbits = c.take<uint16_t>(max_tiles(n_cap, w->max_fb, TILE) * BLOCK);
   // The radix path for what the pivot rounds leave: its own ping-pong buffer
   // and per-chunk state.
-  return radix_sort_plan(n_cap, w->max_fb, c, &w->fb_radix);
+  return radix_sort_plan(n_cap, w->max_fb, c, &w->fb_radix, vals, false);
 }
 
 kpa_status learned_sort_launch(const u64* keys_in, const u32* rids_in, u64* keys_out,
                                u32* rids_out, const SegList& sl, const kpa_pwl_model* models,
-                               kpa_sort_stats* stats, const LearnedWs& lw, hipStream_t st) {
+                               kpa_sort_stats* stats, const LearnedWs& lw, hipStream_t st,
+                               const u64* vals_in, u64* vals_out) {
+  KPA_REQUIRE(!vals_in || (vals_out && lw.vals_tmp), KPA_EINVAL,
+              "a value column needs an output and a planned buffer");
+  const bool vals = vals_in != nullptr;
+  u64* vtmp = vals ? lw.vals_tmp : nullptr;
+  u64* vout = vals ? vals_out : nullptr;
   const u32 n_seg = sl.n_max;
   if (stats) KPA_CHECK(launch_fill_u64(reinterpret_cast<u64*>(stats), STATS_WORDS, 0, st));
   KPA_CHECK(launch_fill_u32(lw.fb_count, 1, 0, st));
@@ -1263,9 +1298,10 @@ kpa_status learned_sort_launch(const u64* keys_in, const u32* rids_in, u64* keys
              lw.cur_max);
   KPA_LAUNCH("learned_setup", k_learned_setup, dim3(std::min<u32>(n_seg, 2048)), dim3(BLOCK), 0,
              st, models, sl, lw.cur_min, lw.cur_max, lw.segm, stats);
-  DigitSortBufs b{keys_in,     rids_in,      keys_out,   rids_out,       lw.keys_tmp,
+  DigitSortBufs b{keys_in,     rids_in,      keys_out,    rids_out,       lw.keys_tmp,
                   lw.rids_tmp, lw.hist,      lw.seg_mask, lw.ltile_start, lw.status0,
-                  lw.status1,  lw.counters,  lw.max_tiles, lw.order};
+                  lw.status1,  lw.counters,  lw.max_tiles, lw.order,     nullptr,
+                  vals_in,     vout,         vtmp};
   KPA_CHECK(digit_sort_launch<LearnedDF>(sl, LearnedDF::Params{lw.segm, models}, b, st));
 
   KPA_CHECK(launch_seg_tiles_list(sl, FH, lw.ftile_start, st));
@@ -1275,9 +1311,14 @@ kpa_status learned_sort_launch(const u64* keys_in, const u32* rids_in, u64* keys
              dim3((u32)std::min<u64>(ceil_div(lw.max_ftiles, BLOCK), 4096)), dim3(BLOCK), 0, st,
              keys_out, sl, lw.ftile_start, lw.ftile_seg, lw.segm, (u32)lw.max_ftiles, lw.factive,
              lw.fn_active);
-  KPA_LAUNCH("learned_finish", k_learned_finish, dim3((u32)lw.max_ftiles), dim3(FIN_THREADS), 0,
-             st, keys_out, rids_out, sl, lw.segm, lw.factive, lw.fn_active, lw.fb_lo, lw.fb_hi,
-             lw.fb_seg, lw.fb_count, lw.max_fb, stats);
+  if (vals)
+    KPA_LAUNCH("learned_finish", k_learned_finish<true>, dim3((u32)lw.max_ftiles),
+               dim3(FIN_THREADS), 0, st, keys_out, rids_out, vout, sl, lw.segm, lw.factive,
+               lw.fn_active, lw.fb_lo, lw.fb_hi, lw.fb_seg, lw.fb_count, lw.max_fb, stats);
+  else
+    KPA_LAUNCH("learned_finish", k_learned_finish<false>, dim3((u32)lw.max_ftiles),
+               dim3(FIN_THREADS), 0, st, keys_out, rids_out, vout, sl, lw.segm, lw.factive,
+               lw.fn_active, lw.fb_lo, lw.fb_hi, lw.fb_seg, lw.fb_count, lw.max_fb, stats);
 
   // Pivot rounds over the oversize chunks: round 0 reads the finishing pass's
   // list, round 1 the parts round 0 left over; small parts collect in one list.
@@ -1303,23 +1344,26 @@ kpa_status learned_sort_launch(const u64* keys_in, const u32* rids_in, u64* keys
                lw.p_mask, lw.t_lt, lw.t_eq);
     KPA_LAUNCH("pivot_move", k_fb_move, dim3(2048), dim3(BLOCK), 0, st, keys_out, rids_out, fl,
                lw.fb_tile_start, lw.fb_tile_seg, lw.pivot, lw.cnt3, lw.p_mask, lw.t_lt, lw.t_eq,
-               lw.t_eqbits, lw.keys_tmp, lw.rids_tmp);
+               lw.t_eqbits, lw.keys_tmp, lw.rids_tmp, vout, vtmp);
     KPA_LAUNCH("pivot_back", k_fb_back, dim3(2048), dim3(BLOCK), 0, st, keys_out, rids_out, fl,
                lw.fb_tile_start, lw.fb_tile_seg, lw.pivot, lw.cnt3, lw.p_mask, lw.t_eqbits,
-               lw.keys_tmp, lw.rids_tmp);
+               lw.keys_tmp, lw.rids_tmp, vout, vtmp);
   }
-  KPA_LAUNCH("lds_sort_ranges", k_lds_sort_ranges, dim3(2048), dim3(FIN_THREADS), 0, st, keys_out,
-             rids_out, lw.sm_lo, lw.sm_hi, lw.sm_seg, lw.segm, lw.rl_count + 2, 6 * lw.max_fb);
+  if (vals)
+    KPA_LAUNCH("lds_sort_ranges", k_lds_sort_ranges<true>, dim3(2048), dim3(FIN_THREADS), 0, st,
+               keys_out, rids_out, vout, lw.sm_lo, lw.sm_hi, lw.sm_seg, lw.segm, lw.rl_count + 2,
+               6 * lw.max_fb);
+  else
+    KPA_LAUNCH("lds_sort_ranges", k_lds_sort_ranges<false>, dim3(2048), dim3(FIN_THREADS), 0, st,
+               keys_out, rids_out, vout, lw.sm_lo, lw.sm_hi, lw.sm_seg, lw.segm, lw.rl_count + 2,
+               6 * lw.max_fb);
 
   // What two rounds did not resolve goes through the radix path.
   const SegList rl{lw.rl_lo[1], lw.rl_hi[1], lw.rl_count + 1, lw.max_fb};
-  KPA_CHECK(launch_seg_tiles_list(rl, TILE, lw.fb_tile_start, st));
-  KPA_CHECK(launch_tile_seg(lw.fb_tile_start, lw.max_fb, lw.rl_count + 1,
-                            max_tiles(lw.n_cap, lw.max_fb, TILE), lw.fb_tile_seg, st));
-  KPA_LAUNCH("fallback_copy", k_fb_copy_all, dim3(2048), dim3(BLOCK), 0, st, keys_out, rids_out,
-             rl, lw.fb_tile_start, lw.fb_tile_seg, lw.keys_tmp, lw.rids_tmp);
-  return radix_sort_launch(lw.keys_tmp, lw.rids_tmp, keys_out, rids_out, rl, lw.fb_radix, st,
-                           stats_unsupported(stats));
+  // in place, with the scatter passes' ping-pong buffers (free by now) as
+  // scratch
+  return radix_sort_inplace(keys_out, rids_out, vout, rl, lw.fb_radix, lw.keys_tmp, lw.rids_tmp,
+                            vtmp, st, stats_unsupported(stats));
 }
 
 }  // namespace kpa

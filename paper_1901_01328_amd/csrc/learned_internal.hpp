@@ -91,6 +91,7 @@ __device__ __forceinline__ u32 model_fine(const SegModel& m, const KP* kn, u64 k
 struct LearnedWs {
   u64* keys_tmp;   // scatter ping-pong buffer; later the fallback's input
   u32* rids_tmp;
+  u64* vals_tmp;   // the same for a value column (planned with one only, else null)
   SegModel* segm;  // n_seg
   u64* cur_min;    // n_seg: smallest and largest sampled key of each segment
   u64* cur_max;
@@ -136,9 +137,13 @@ struct LearnedWs {
   RadixWs fb_radix;  // radix sort of the re-sorted chunks
 };
 
-kpa_status learned_sort_plan(u64 n_cap, u32 n_seg, Carver& c, LearnedWs* w);
+// vals: also plan for a value column.
+kpa_status learned_sort_plan(u64 n_cap, u32 n_seg, Carver& c, LearnedWs* w, bool vals = false);
+// vals_in/vals_out (both or neither; the plan must have had vals): a value
+// column that follows the keys' permutation.
 kpa_status learned_sort_launch(const u64* keys_in, const u32* rids_in, u64* keys_out,
                                u32* rids_out, const SegList& sl, const kpa_pwl_model* models,
-                               kpa_sort_stats* stats, const LearnedWs& lw, hipStream_t st);
+                               kpa_sort_stats* stats, const LearnedWs& lw, hipStream_t st,
+                               const u64* vals_in = nullptr, u64* vals_out = nullptr);
 
 }  // namespace kpa

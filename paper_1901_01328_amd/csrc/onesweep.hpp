@@ -153,6 +153,50 @@ __device__ __forceinline__ void stage_tile(SM& sm, const u64 (&k)[IT], const u32
   __syncthreads();
 }
 
+// stage_tile that also returns each present item's LDS slot (pos), for a
+// second round that moves a value column through the same slots.
+template <class SM, int IT>
+__device__ __forceinline__ void stage_tile_pos(SM& sm, const u64 (&k)[IT], const u32 (&r)[IT],
+                                               const u32 (&d)[IT], const u32 (&rank)[IT],
+                                               u32 valid, u32 (&pos)[IT]) {
+  const u32 w = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < IT; ++j) {
+    pos[j] = 0;
+    if ((valid >> j) & 1) {
+      pos[j] = sm.lstart[d[j]] + sm.whist[w][d[j]] + rank[j];
+      sm.skeys[pos[j]] = k[j];
+      sm.srids[pos[j]] = r[j];
+      sm.sdig[pos[j]] = (unsigned char)d[j];
+    }
+  }
+  __syncthreads();
+}
+
+// Second round of a staged tile: after its keys and row ids are written
+// (write_staged), the items' values go through the key slots of LDS to the
+// same destinations.  pos: the slots stage_tile_pos returned.  Begins with a
+// barrier (every thread has read the staged keys) and ends without one.
+template <class SM, int NW, int IT>
+__device__ __forceinline__ void write_staged_vals(SM& sm, const u64 (&v)[IT], const u32 (&pos)[IT],
+                                                  u32 valid, u64* __restrict__ vals_out) {
+  constexpr int NT = NW * 64;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < IT; ++j)
+    if ((valid >> j) & 1) sm.skeys[pos[j]] = v[j];
+  __syncthreads();
+  const u32 n = sm.count;
+#pragma unroll
+  for (int j = 0; j < TILE / NT; ++j) {
+    const u32 i = threadIdx.x + j * NT;
+    if (i < n) {
+      const u32 dd = sm.sdig[i];
+      vals_out[sm.gbase[dd] + (i - sm.lstart[dd])] = sm.skeys[i];
+    }
+  }
+}
+
 // Writes the staged tile: each digit's entries contiguously from
 // sm.gbase[digit].  The caller has set sm.gbase and sm.count and passed a
 // barrier since.
@@ -205,6 +249,22 @@ __device__ __forceinline__ u32 onesweep_rank_stage(OnesweepSmemT<NW>& sm, const 
   if (tid < RADIX) st_status(status + (u64)tile * RADIX + tid, (tile_in_seg == 0 ? ST_PRE : ST_AGG) | total);
   rank_starts<NW>(total, sm.lstart, sm.scan, tile_count);
   stage_tile<OnesweepSmemT<NW>, IT>(sm, k, r, d, rank, valid);
+  return total;
+}
+
+// onesweep_rank_stage that also returns the items' LDS slots.
+template <int NW, int IT>
+__device__ __forceinline__ u32 onesweep_rank_stage_pos(OnesweepSmemT<NW>& sm, const u64 (&k)[IT],
+                                                       const u32 (&r)[IT], const u32 (&d)[IT],
+                                                       u32 valid, u32* __restrict__ status,
+                                                       u32 tile, u32 tile_in_seg,
+                                                       u32* tile_count, u32 (&pos)[IT]) {
+  const u32 tid = threadIdx.x;
+  u32 rank[IT];
+  const u32 total = rank_count<NW, IT>(sm.whist, d, valid, rank);
+  if (tid < RADIX) st_status(status + (u64)tile * RADIX + tid, (tile_in_seg == 0 ? ST_PRE : ST_AGG) | total);
+  rank_starts<NW>(total, sm.lstart, sm.scan, tile_count);
+  stage_tile_pos<OnesweepSmemT<NW>, IT>(sm, k, r, d, rank, valid, pos);
   return total;
 }
 

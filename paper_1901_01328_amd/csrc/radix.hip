@@ -79,10 +79,11 @@ kpa_status launch_seg_tiles_list(const SegList& sl, u32 tile, u32* tile_start, h
   return KPA_OK;
 }
 
-kpa_status radix_sort_plan(u64 n_cap, u32 n_seg, Carver& c, RadixWs* w) {
+kpa_status radix_sort_plan(u64 n_cap, u32 n_seg, Carver& c, RadixWs* w, bool vals, bool tmp) {
   const u64 tiles = max_tiles(n_cap, n_seg, TILE);
-  w->keys_tmp = c.take<u64>(n_cap);
-  w->rids_tmp = c.take<u32>(n_cap);
+  w->keys_tmp = tmp ? c.take<u64>(n_cap) : nullptr;
+  w->rids_tmp = tmp ? c.take<u32>(n_cap) : nullptr;
+  w->vals_tmp = tmp && vals ? c.take<u64>(n_cap) : nullptr;
   w->hist = c.take<u32>((u64)n_seg * 8 * RADIX);
   w->seg_mask = c.take<u32>(n_seg);
   w->tile_start = c.take<u32>((u64)n_seg + 1);
@@ -97,10 +98,24 @@ kpa_status radix_sort_plan(u64 n_cap, u32 n_seg, Carver& c, RadixWs* w) {
 
 kpa_status radix_sort_launch(const u64* keys_in, const u32* rids_in, u64* keys_out,
                              u32* rids_out, const SegList& sl, const RadixWs& w,
-                             hipStream_t st, u64* unsupported) {
+                             hipStream_t st, u64* unsupported, const u64* vals_in,
+                             u64* vals_out) {
+  KPA_REQUIRE(!vals_in || (vals_out && w.vals_tmp), KPA_EINVAL,
+              "a value column needs an output and a planned buffer");
   DigitSortBufs b{keys_in,    rids_in,       keys_out,   rids_out,  w.keys_tmp,
                   w.rids_tmp, w.hist,        w.seg_mask, w.tile_start, w.status0,
-                  w.status1,  w.counters,    w.max_tiles, w.order, unsupported};
+                  w.status1,  w.counters,    w.max_tiles, w.order, unsupported,
+                  vals_in,    vals_in ? vals_out : nullptr, vals_in ? w.vals_tmp : nullptr};
+  return digit_sort_launch<RadixDF>(sl, RadixDF::Params{}, b, st);
+}
+
+kpa_status radix_sort_inplace(u64* keys, u32* rids, u64* vals, const SegList& sl,
+                              const RadixWs& w, u64* tmp_k, u32* tmp_r, u64* tmp_v,
+                              hipStream_t st, u64* unsupported) {
+  KPA_REQUIRE(tmp_k && tmp_r && (!vals || tmp_v), KPA_EINVAL, "in-place sort needs scratch");
+  DigitSortBufs b{keys,  rids,   keys,       rids,          tmp_k,     tmp_r,
+                  w.hist, w.seg_mask, w.tile_start, w.status0, w.status1, w.counters,
+                  w.max_tiles, w.order, unsupported, vals, vals, vals ? tmp_v : nullptr, true};
   return digit_sort_launch<RadixDF>(sl, RadixDF::Params{}, b, st);
 }
 

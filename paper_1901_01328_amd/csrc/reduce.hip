@@ -254,7 +254,8 @@ __global__ void __launch_bounds__(BLOCK) k_reduce_main(
     for (int j = 0; j < ITEMS; ++j) {
       const u32 i = tid + j * BLOCK;
       kv[j] = i < tr.cnt ? keys[tr.base + i] : 0ull;
-      rv[j] = i < tr.cnt ? rids[tr.base + i] : 0u;
+      // without row ids, entry i's row is row i (values already in KPA order)
+      rv[j] = i < tr.cnt ? (rids ? rids[tr.base + i] : (u32)(tr.base + i)) : 0u;
     }
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
@@ -336,6 +337,197 @@ __global__ void __launch_bounds__(BLOCK) k_reduce_main(
   }
 }
 
+// ---- pass 3 when the values are already in KPA order (8-byte values, row
+// ids NULL): no gather; keys and values are loaded coalesced and staged one
+// after the other through the same LDS tile (so four workgroups fit a CU),
+// and the segmented scan across the wave runs on DPP lane moves.
+
+// Aggregate of a partial run inside one tile (a tile holds at most 4096
+// entries, so the count fits 32 bits); hp only when group starts are wanted.
+template <bool START>
+struct RunAgg {
+  u32 f, c;
+  u64 s, m;
+  u64 hp;
+};
+
+template <bool START>
+__device__ __forceinline__ RunAgg<START> run_combine(const RunAgg<START>& a,
+                                                     const RunAgg<START>& b) {
+  if (b.f) return b;
+  RunAgg<START> r;
+  r.f = a.f;
+  r.c = a.c + b.c;
+  r.s = a.s + b.s;
+  r.m = a.m > b.m ? a.m : b.m;
+  r.hp = START ? a.hp : 0ull;
+  return r;
+}
+
+// DPP lane moves (GFX9 encodings): row_shr:n shifts within rows of 16
+// lanes, row_bcast:15 / row_bcast:31 broadcast lane 15 / 31 of the rows
+// below into the rows that row_mask selects, wave_shr:1 shifts the whole
+// wave by one lane.  Lanes without a source (or outside row_mask) keep `old`.
+constexpr int DPP_ROW_SHR = 0x110, DPP_BCAST15 = 0x142, DPP_BCAST31 = 0x143, DPP_WAVE_SHR1 = 0x138;
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ u32 dpp32(u32 old, u32 v) {
+  return (u32)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROW_MASK, 0xF, false);
+}
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ u64 dpp64(u64 old, u64 v) {
+  const u32 lo = dpp32<CTRL, ROW_MASK>((u32)old, (u32)v);
+  const u32 hi = dpp32<CTRL, ROW_MASK>((u32)(old >> 32), (u32)(v >> 32));
+  return ((u64)hi << 32) | lo;
+}
+// The aggregate of the lane that the DPP control selects (identity where none).
+template <int CTRL, int ROW_MASK, bool START>
+__device__ __forceinline__ RunAgg<START> dpp_agg(const RunAgg<START>& a) {
+  RunAgg<START> r;
+  r.f = dpp32<CTRL, ROW_MASK>(0u, a.f);
+  r.c = dpp32<CTRL, ROW_MASK>(0u, a.c);
+  r.s = dpp64<CTRL, ROW_MASK>(0ull, a.s);
+  r.m = dpp64<CTRL, ROW_MASK>(0ull, a.m);
+  r.hp = START ? dpp64<CTRL, ROW_MASK>(0ull, a.hp) : 0ull;
+  return r;
+}
+
+// Inclusive segmented scan over the wave (Hillis-Steele within rows of 16,
+// then the two row broadcasts); the identity (all zero) fills lanes without
+// a source, and run_combine(identity, x) == x.
+template <bool START>
+__device__ __forceinline__ RunAgg<START> wave_incl_runscan(RunAgg<START> x) {
+  x = run_combine(dpp_agg<DPP_ROW_SHR + 1, 0xF>(x), x);
+  x = run_combine(dpp_agg<DPP_ROW_SHR + 2, 0xF>(x), x);
+  x = run_combine(dpp_agg<DPP_ROW_SHR + 4, 0xF>(x), x);
+  x = run_combine(dpp_agg<DPP_ROW_SHR + 8, 0xF>(x), x);
+  x = run_combine(dpp_agg<DPP_BCAST15, 0xA>(x), x);
+  x = run_combine(dpp_agg<DPP_BCAST31, 0xC>(x), x);
+  return x;
+}
+
+template <bool START>
+__global__ void __launch_bounds__(BLOCK) k_reduce_main_seq(
+    const u64* __restrict__ keys, const u64* __restrict__ vals, const u64* __restrict__ seg_off,
+    const u32* __restrict__ tile_start, const u32* __restrict__ tile_seg, u32 n_seg,
+    const u64* __restrict__ gbase, u64* __restrict__ o_key, u64* __restrict__ o_cnt,
+    u64* __restrict__ o_sum, u64* __restrict__ o_max, u64* __restrict__ o_start) {
+  __shared__ u64 st[PTILE];  // the tile's keys, then its values
+  __shared__ RunAgg<START> wsm[WAVES];
+  __shared__ u32 hsm[WAVES + 1];
+  const u32 tile = blockIdx.x;
+  if (tile >= tile_start[n_seg]) return;
+  const TileRange tr = tile_range(seg_off, tile_start, tile_seg, tile, TILE);
+  const u32 tid = threadIdx.x;
+  u64 k[ITEMS], v[ITEMS];
+  u64 before, after;
+  {
+    u64 kv[ITEMS], vv[ITEMS];  // all loads of the thread in flight together
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      const u32 i = tid + j * BLOCK;
+      kv[j] = i < tr.cnt ? keys[tr.base + i] : 0ull;
+      vv[j] = i < tr.cnt ? vals[tr.base + i] : 0ull;
+    }
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      const u32 i = tid + j * BLOCK;
+      if (i < tr.cnt) st[pidx(i)] = kv[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      const u32 idx = tid * ITEMS + j;
+      k[j] = idx < tr.cnt ? st[pidx(idx)] : 0ull;
+    }
+    const u32 last = tid * ITEMS + ITEMS;  // the next thread's first entry
+    before = tid > 0 && tid * ITEMS - 1 < tr.cnt ? st[pidx(tid * ITEMS - 1)] : 0ull;
+    after = last < tr.cnt ? st[pidx(last)] : 0ull;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      const u32 i = tid + j * BLOCK;
+      if (i < tr.cnt) st[pidx(i)] = vv[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      const u32 idx = tid * ITEMS + j;
+      v[j] = idx < tr.cnt ? st[pidx(idx)] : 0ull;
+    }
+  }
+  const bool has_prev = tr.base > tr.a;
+  const bool has_next = tr.base + tr.cnt < tr.b;
+  if (tid == 0) before = has_prev ? keys[tr.base - 1] : 0ull;
+  const u64 next = has_next ? keys[tr.base + tr.cnt] : 0ull;
+  const bool lead_has_prev = tid == 0 ? has_prev : true;
+  u32 hmask = 0, tmask = 0;
+  u64 prevk = before;
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    const u32 idx = tid * ITEMS + j;
+    if (idx < tr.cnt) {
+      const bool h = j == 0 ? (!lead_has_prev || k[j] != prevk) : (k[j] != prevk);
+      const bool lastent = idx + 1 == tr.cnt;
+      const u64 nk = j + 1 < ITEMS ? k[j + 1] : after;
+      const bool t = lastent ? (!has_next || k[j] != next) : (k[j] != nk);
+      hmask |= (u32)h << j;
+      tmask |= (u32)t << j;
+      prevk = k[j];
+    }
+  }
+  // this thread's aggregate, then the exclusive scan over the block
+  RunAgg<START> A{0u, 0u, 0ull, 0ull, 0ull};
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    const u32 idx = tid * ITEMS + j;
+    if (idx < tr.cnt)
+      A = run_combine(A, RunAgg<START>{(hmask >> j) & 1u, 1u, v[j], v[j], tr.base + idx});
+  }
+  u32 htot;
+  const u32 hex = block_excl_sum((u32)__popc(hmask), hsm, &htot);
+  const RunAgg<START> incl = wave_incl_runscan(A);
+  const u32 lane = __lane_id(), w = tid >> 6;
+  RunAgg<START> ex = dpp_agg<DPP_WAVE_SHR1, 0xF>(incl);
+  if (lane == 0) ex = RunAgg<START>{0u, 0u, 0ull, 0ull, 0ull};
+  if (lane == 63) wsm[w] = incl;
+  __syncthreads();
+  RunAgg<START> run{0u, 0u, 0ull, 0ull, 0ull};
+  for (u32 i = 0; i < w; ++i) run = run_combine(run, wsm[i]);
+  run = run_combine(run, ex);
+  const u64 gb = gbase[tile];
+  u32 hs = hex;
+#pragma unroll
+  for (int j = 0; j < ITEMS; ++j) {
+    const u32 idx = tid * ITEMS + j;
+    if (idx < tr.cnt) {
+      const u32 h = (hmask >> j) & 1u;
+      run = run_combine(run, RunAgg<START>{h, 1u, v[j], v[j], tr.base + idx});
+      hs += h;
+      const bool t = (tmask >> j) & 1u;
+      const bool cont = idx + 1 == tr.cnt && !t;  // the run goes on in the next tile
+      if (t || cont) {
+        const u64 gi = gb + hs - 1;
+        if (run.f && t) {  // the whole run lies in this tile
+          o_key[gi] = k[j];
+          if (o_cnt) o_cnt[gi] = run.c;
+          if (o_sum) o_sum[gi] = run.s;
+          if (o_max) o_max[gi] = run.m;
+          if (START) o_start[gi] = run.hp;
+        } else {
+          if (run.f) {
+            o_key[gi] = k[j];
+            if (START) o_start[gi] = run.hp;
+          }
+          if (o_cnt) atomicAdd(reinterpret_cast<unsigned long long*>(o_cnt + gi), (u64)run.c);
+          if (o_sum) atomicAdd(reinterpret_cast<unsigned long long*>(o_sum + gi), run.s);
+          if (o_max) atomicMax(reinterpret_cast<unsigned long long*>(o_max + gi), run.m);
+        }
+      }
+    }
+  }
+}
+
 kpa_status launch_tile_scan(const u32* counts, const u32* tile_start, const u32* tile_seg,
                             u32 n_seg, u64 max_tiles, u64* bsum, u64* tbase, u64* seg_first,
                             hipStream_t st) {
@@ -378,9 +570,20 @@ kpa_status reduce_launch(const u64* keys, const u32* rids, const u64* seg_off, u
              o.gseg_off);
   KPA_LAUNCH("reduce_scan", k_reduce_bapply, dim3(nb), dim3(SCAN_TILES), 0, st, w.heads, w.flags,
              w.tile_start, w.tile_seg, n_seg, w.bsum, w.gbase, o.gseg_off, o.cnt, o.sum, o.max);
-  KPA_LAUNCH("reduce_main", k_reduce_main, dim3((u32)w.max_tiles), dim3(BLOCK), 0, st, keys, rids,
-             seg_off, w.tile_start, w.tile_seg, n_seg, vs, w.gbase, o.gkey, o.cnt, o.sum, o.max,
-             o.gstart);
+  const bool seq = !rids && need_val && L && L->row_bytes == 8 && L->val_off == 0 &&
+                   L->val_w == 8;
+  if (seq && o.gstart)
+    KPA_LAUNCH("reduce_main", k_reduce_main_seq<true>, dim3((u32)w.max_tiles), dim3(BLOCK), 0, st,
+               keys, reinterpret_cast<const u64*>(rows), seg_off, w.tile_start, w.tile_seg,
+               n_seg, w.gbase, o.gkey, o.cnt, o.sum, o.max, o.gstart);
+  else if (seq)
+    KPA_LAUNCH("reduce_main", k_reduce_main_seq<false>, dim3((u32)w.max_tiles), dim3(BLOCK), 0,
+               st, keys, reinterpret_cast<const u64*>(rows), seg_off, w.tile_start, w.tile_seg,
+               n_seg, w.gbase, o.gkey, o.cnt, o.sum, o.max, o.gstart);
+  else
+    KPA_LAUNCH("reduce_main", k_reduce_main, dim3((u32)w.max_tiles), dim3(BLOCK), 0, st, keys,
+               rids, seg_off, w.tile_start, w.tile_seg, n_seg, vs, w.gbase, o.gkey, o.cnt, o.sum,
+               o.max, o.gstart);
   return KPA_OK;
 }
 
@@ -577,8 +780,7 @@ kpa_status kpa_reduce_by_key(const uint64_t* keys, const uint32_t* rids, const u
   const bool need_val = out_sum || out_max;
   if (need_val) KPA_CHECK(check_layout(layout, true, false));
   if (n_seg == 0) return KPA_OK;
-  KPA_REQUIRE(keys && rids && seg_off && out_gkey && out_gseg_off && ws, KPA_EINVAL,
-              "null pointer");
+  KPA_REQUIRE(keys && seg_off && out_gkey && out_gseg_off && ws, KPA_EINVAL, "null pointer");
   KPA_REQUIRE(!need_val || rows, KPA_EINVAL, "rows needed for sum/max");
   KPA_REQUIRE(aligned(keys, 8) && aligned(rids, 4) && aligned(seg_off, 8) &&
                   aligned(out_gkey, 8) && aligned(out_gseg_off, 8) && aligned(ws, 256) &&
@@ -644,7 +846,7 @@ kpa_status kpa_reduce_by_key_noalloc(const uint64_t* keys, const uint32_t* rids,
   const bool need_val = out_sum || out_max;
   if (need_val) KPA_CHECK(check_layout(layout, true, false));
   if (n_seg == 0) return KPA_OK;
-  KPA_REQUIRE(keys && rids && seg_off && out_gkey && out_gseg_off, KPA_EINVAL, "null pointer");
+  KPA_REQUIRE(keys && seg_off && out_gkey && out_gseg_off, KPA_EINVAL, "null pointer");
   KPA_REQUIRE(!need_val || rows, KPA_EINVAL, "rows needed for sum/max");
   KPA_REQUIRE(aligned(keys, 8) && aligned(rids, 4) && aligned(seg_off, 8) &&
                   aligned(out_gkey, 8) && aligned(out_gseg_off, 8) && (!rows || aligned(rows, 16)),

@@ -74,6 +74,7 @@ struct RadixDigit {
 struct RadixWs {
   u64* keys_tmp;
   u32* rids_tmp;
+  u64* vals_tmp;    // planned with a value column only (else null)
   u32* hist;        // n_seg * 8 * 256: digit counts, then exclusive offsets
   u32* seg_mask;    // n_seg: bit p set when pass p is needed
   u32* tile_start;  // n_seg + 1
@@ -85,12 +86,25 @@ struct RadixWs {
   u32 max_seg;
 };
 
-kpa_status radix_sort_plan(u64 n_cap, u32 n_seg, Carver& c, RadixWs* w);
+// vals: also plan the ping-pong buffer of a value column; tmp = false: no
+// ping-pong buffers at all (for radix_sort_inplace, which borrows them).
+kpa_status radix_sort_plan(u64 n_cap, u32 n_seg, Carver& c, RadixWs* w, bool vals = false,
+                           bool tmp = true);
 // unsupported (device, may be null): counts the entries of segments of 2^30
-// or more entries, which are copied through unsorted.
+// or more entries, which are copied through unsorted.  vals_in/vals_out
+// (both or neither; the plan must have had vals): a value column that
+// follows the keys' permutation.
 kpa_status radix_sort_launch(const u64* keys_in, const u32* rids_in, u64* keys_out,
                              u32* rids_out, const SegList& sl, const RadixWs& w, hipStream_t st,
-                             u64* unsupported = nullptr);
+                             u64* unsupported = nullptr, const u64* vals_in = nullptr,
+                             u64* vals_out = nullptr);
+// Sorts the segments of sl in place in keys/rids (and vals, may be null),
+// with tmp_* (n_cap each, the caller's scratch) as the ping-pong partner: a
+// segment with an odd number of active passes is first copied there.  The
+// plan may have been made with tmp = false.
+kpa_status radix_sort_inplace(u64* keys, u32* rids, u64* vals, const SegList& sl,
+                              const RadixWs& w, u64* tmp_k, u32* tmp_r, u64* tmp_v,
+                              hipStream_t st, u64* unsupported = nullptr);
 // Offset of kpa_sort_stats.unsupported_entries in u64 words; the struct's size.
 constexpr int STATS_UNSUPPORTED = 6;
 constexpr int STATS_WORDS = 7;

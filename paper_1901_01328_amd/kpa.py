@@ -143,10 +143,18 @@ _SIGS = {
     "kpa_sort_segmented": ([_vp, _vp, _vp, _vp, _vp, _u32, _u64, C.c_int, _vp, _vp, _vp,
                             C.c_size_t, _vp], C.c_int32),
     "kpa_sort": ([_vp, _vp, _u64, _vp, _vp, C.c_int, _vp, _vp, _vp, C.c_size_t, _vp], C.c_int32),
+    "kpa_sort_vals_workspace_size": ([_u64, _u32, C.c_int, _sz], C.c_int32),
+    "kpa_sort_segmented_vals": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _u32, _u64, C.c_int, _vp,
+                                 _vp, _vp, C.c_size_t, _vp], C.c_int32),
     "kpa_batch_config_default": ([C.c_int, C.POINTER(kpa_batch_config)], C.c_int32),
     "kpa_batch_sort_workspace_size": ([_u64, _u32, C.POINTER(kpa_batch_config), _sz], C.c_int32),
     "kpa_batch_sort": ([_vp, _vp, _vp, _vp, _vp, _u32, _u64, C.POINTER(kpa_batch_config), _vp,
                         _vp, _vp, C.c_size_t, _vp], C.c_int32),
+    "kpa_batch_sort_vals_workspace_size": ([_u64, _u32, C.POINTER(kpa_batch_config), _sz],
+                                           C.c_int32),
+    "kpa_batch_sort_vals": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _u32, _u64,
+                             C.POINTER(kpa_batch_config), _vp, _vp, _vp, C.c_size_t, _vp],
+                            C.c_int32),
     "kpa_batch_autotune": ([_vp, _vp, _vp, _vp, _vp, _u32, _u64, C.c_int, _vp, _vp, C.c_size_t,
                             _u32, C.c_char_p, C.POINTER(kpa_batch_config), C.POINTER(_f32), _vp],
                            C.c_int32),
@@ -373,6 +381,31 @@ def kpa_sort_segmented(keys_in, rids_in, seg_off, n_cap=None, algo=KPA_SORT_RADI
     return keys_out, rids_out
 
 
+def kpa_sort_vals_workspace_size(n_cap, n_seg=1, algo=KPA_SORT_RADIX):
+    return _ws_size("kpa_sort_vals_workspace_size", n_cap, n_seg, algo)
+
+
+def kpa_sort_segmented_vals(keys_in, rids_in, vals_in, seg_off, n_cap=None, algo=KPA_SORT_RADIX,
+                            models=None, stats=None, keys_out=None, rids_out=None, vals_out=None,
+                            ws=None, stream=None):
+    """kpa_sort_segmented with an 8-byte column carried beside the KPA;
+    returns (keys_out, rids_out, vals_out)."""
+    _check(keys_in, torch.int64, "keys_in")
+    _check(rids_in, torch.int32, "rids_in")
+    _check(vals_in, torch.int64, "vals_in")
+    n_seg = seg_off.numel() - 1
+    n_cap = keys_in.numel() if n_cap is None else n_cap
+    dev = keys_in.device
+    keys_out = torch.empty_like(keys_in) if keys_out is None else keys_out
+    rids_out = torch.empty_like(rids_in) if rids_out is None else rids_out
+    vals_out = torch.empty_like(vals_in) if vals_out is None else vals_out
+    ws = _ws(kpa_sort_vals_workspace_size(n_cap, n_seg, algo), dev, ws)
+    _call("kpa_sort_segmented_vals", _p(keys_in), _p(rids_in), _p(vals_in), _p(keys_out),
+          _p(rids_out), _p(vals_out), _p(seg_off), n_seg, n_cap, algo, _p(models), _p(stats),
+          _p(ws), ws.numel() * ws.element_size(), _stream(stream))
+    return keys_out, rids_out, vals_out
+
+
 def kpa_sort(keys_in, rids_in, algo=KPA_SORT_RADIX, model=None, stats=None, keys_out=None,
              rids_out=None, ws=None, stream=None):
     _check(keys_in, torch.int64, "keys_in")
@@ -417,6 +450,32 @@ def kpa_batch_sort(keys_in, rids_in, seg_off, cfg=None, n_cap=None, models=None,
           n_seg, n_cap, C.byref(cfg), _p(models), _p(stats), _p(ws),
           ws.numel() * ws.element_size(), _stream(stream))
     return keys_out, rids_out
+
+
+def kpa_batch_sort_vals_workspace_size(n_cap, n_seg, cfg):
+    return _ws_size("kpa_batch_sort_vals_workspace_size", n_cap, n_seg, C.byref(cfg))
+
+
+def kpa_batch_sort_vals(keys_in, rids_in, vals_in, seg_off, cfg=None, n_cap=None, models=None,
+                        stats=None, keys_out=None, rids_out=None, vals_out=None, ws=None,
+                        stream=None):
+    """kpa_batch_sort with an 8-byte column carried beside the KPA; returns
+    (keys_out, rids_out, vals_out)."""
+    _check(keys_in, torch.int64, "keys_in")
+    _check(rids_in, torch.int32, "rids_in")
+    _check(vals_in, torch.int64, "vals_in")
+    cfg = kpa_batch_config_default() if cfg is None else cfg
+    n_seg = seg_off.numel() - 1
+    n_cap = keys_in.numel() if n_cap is None else n_cap
+    dev = keys_in.device
+    keys_out = torch.empty_like(keys_in) if keys_out is None else keys_out
+    rids_out = torch.empty_like(rids_in) if rids_out is None else rids_out
+    vals_out = torch.empty_like(vals_in) if vals_out is None else vals_out
+    ws = _ws(kpa_batch_sort_vals_workspace_size(n_cap, n_seg, cfg), dev, ws)
+    _call("kpa_batch_sort_vals", _p(keys_in), _p(rids_in), _p(vals_in), _p(keys_out),
+          _p(rids_out), _p(vals_out), _p(seg_off), n_seg, n_cap, C.byref(cfg), _p(models),
+          _p(stats), _p(ws), ws.numel() * ws.element_size(), _stream(stream))
+    return keys_out, rids_out, vals_out
 
 
 def kpa_batch_autotune(keys_in, rids_in, seg_off, large_algo=KPA_SORT_RADIX, n_cap=None,

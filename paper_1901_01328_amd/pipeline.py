@@ -97,13 +97,24 @@ class BatchAggregation:
     batched sort (small / mid / large classes, radix or learned for the large
     ones) -> keyed reduction (count, sum, max) per window.  Every buffer is
     allocated here, so a step can be captured once in a graph and replayed.
+
+    carry_values: True: the sort carries the staged value column beside the
+    KPA (8 more bytes read and written per entry and pass) and the reduction
+    reads it in KPA order; False: the reduction follows each row id into the
+    staged column (a cache-line fetch per entry); None (default): carry on
+    the learned route (two scatter passes and the finishing pass) and follow
+    the row ids on the radix route (as many passes as key bytes vary).
+    Group keys land in the sort's input key array, which is dead once the
+    sort ran, and the sums in whichever value array the reduction does not
+    read, so results stay valid until the next step (pipe.g after a step).
     """
 
     def __init__(self, n_rows, n_seg, layout, cfg=None, device="cuda",
-                 want=("cnt", "sum", "max"), learned_ws=True):
+                 want=("cnt", "sum", "max"), learned_ws=True, carry_values=None):
         self.n, self.n_seg, self.layout = n_rows, n_seg, layout
         self.cfg = K.kpa_batch_config_default() if cfg is None else cfg
         self.want = tuple(want)
+        self.carry = carry_values
         d = torch.device(device)
         cap = max(n_rows, 1)
         i64 = dict(dtype=torch.int64, device=d)
@@ -113,16 +124,21 @@ class BatchAggregation:
         self.vals = torch.empty(cap, **i64)
         self.skeys = torch.empty(cap, **i64)
         self.srids = torch.empty(cap, **i32)
+        self.svals = torch.empty(cap, **i64)
         self.seg_off = torch.zeros(n_seg + 1, **i64)
-        self.gkey = torch.empty(cap, **i64)
-        self.g = {w: torch.empty(cap, **i64) for w in self.want}
+        self.gkey = self.keys
+        other = {w: torch.empty(cap, **i64) for w in self.want if w != "sum"}
+        # sums: into the value array the reduction does not read
+        self._g = {True: dict(other, **({"sum": self.vals} if "sum" in self.want else {})),
+                   False: dict(other, **({"sum": self.svals} if "sum" in self.want else {}))}
+        self.g = self._g[carry_values is not False]
         self.gseg = torch.empty(n_seg + 1, **i64)
         u8 = dict(dtype=torch.uint8, device=d)
-        sizes = [K.kpa_batch_sort_workspace_size(n_rows, n_seg, K.batch_config(
-            large_algo=K.KPA_SORT_RADIX))]
+        ws_size = (K.kpa_batch_sort_vals_workspace_size if carry_values is not False
+                   else K.kpa_batch_sort_workspace_size)
+        sizes = [ws_size(n_rows, n_seg, K.batch_config(large_algo=K.KPA_SORT_RADIX))]
         if learned_ws:
-            sizes.append(K.kpa_batch_sort_workspace_size(n_rows, n_seg, K.batch_config(
-                large_algo=K.KPA_SORT_LEARNED)))
+            sizes.append(ws_size(n_rows, n_seg, K.batch_config(large_algo=K.KPA_SORT_LEARNED)))
         self.ws_sort = torch.empty(max(sizes), **u8)
         self.ws_red = torch.empty(K._ws_size("kpa_reduce_by_key_workspace_size", n_rows, n_seg),
                                   **u8)
@@ -142,24 +158,43 @@ class BatchAggregation:
         on the next epoch's windows)."""
         K.kpa_pwl_fit(self.skeys, self.seg_off, 1024, models=self.models, stream=stream)
 
+    def extract(self, rows, stream=None):
+        """The step's first call alone: keys, row ids and the value column of
+        the current rows (what the sort reads; an autotuner times sorts of
+        them)."""
+        K.kpa_extract(rows, self.layout, out_keys=self.keys, out_rids=self.rids,
+                      out_vals=self.vals, n=self.n, stream=stream)
+
     def step(self, rows, stream=None, cfg=None, fit_next=False):
         """Extract, batched sort, keyed reduction.  With fit_next, the step also
         fits each window's PWL model on its sorted KPA into next_models (the
         models the next epoch's windows would be sorted with); the models in
         use are not touched, so repeated steps do identical work."""
         cfg = self.cfg if cfg is None else cfg
-        K.kpa_extract(rows, self.layout, out_keys=self.keys, out_rids=self.rids,
-                      out_vals=self.vals, n=self.n, stream=stream)
-        K.kpa_batch_sort(self.keys, self.rids, self.seg_off, cfg=cfg, n_cap=self.n,
-                         models=self.models if cfg.large_algo == K.KPA_SORT_LEARNED else None,
-                         stats=self.stats, keys_out=self.skeys, rids_out=self.srids,
-                         ws=self.ws_sort, stream=stream)
+        self.extract(rows, stream=stream)
+        models = self.models if cfg.large_algo == K.KPA_SORT_LEARNED else None
+        carry = self.carry if self.carry is not None else cfg.large_algo == K.KPA_SORT_LEARNED
+        self.g = self._g[carry]
+        if carry:
+            K.kpa_batch_sort_vals(self.keys, self.rids, self.vals, self.seg_off, cfg=cfg,
+                                  n_cap=self.n, models=models, stats=self.stats,
+                                  keys_out=self.skeys, rids_out=self.srids, vals_out=self.svals,
+                                  ws=self.ws_sort, stream=stream)
+        else:
+            K.kpa_batch_sort(self.keys, self.rids, self.seg_off, cfg=cfg, n_cap=self.n,
+                             models=models, stats=self.stats, keys_out=self.skeys,
+                             rids_out=self.srids, ws=self.ws_sort, stream=stream)
         outs = dict(self.g)
         outs["gkey"] = self.gkey
         outs["gseg_off"] = self.gseg
-        K.kpa_reduce_by_key(self.skeys, self.srids, self.seg_off, self.vals, VALUE_COLUMN,
-                            n_cap=self.n, want=self.want, ws=self.ws_red, stream=stream,
-                            outs=outs)
+        if carry:   # values already in KPA order: no row ids to follow
+            K.kpa_reduce_by_key(self.skeys, None, self.seg_off, self.svals, VALUE_COLUMN,
+                                n_cap=self.n, want=self.want, ws=self.ws_red, stream=stream,
+                                outs=outs)
+        else:
+            K.kpa_reduce_by_key(self.skeys, self.srids, self.seg_off, self.vals, VALUE_COLUMN,
+                                n_cap=self.n, want=self.want, ws=self.ws_red, stream=stream,
+                                outs=outs)
         if fit_next:
             K.kpa_pwl_fit(self.skeys, self.seg_off, 1024, models=self.next_models, stream=stream)
 

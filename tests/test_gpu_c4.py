@@ -50,14 +50,16 @@ def check_groups(pipe, groups, sizes):
         assert np.array_equal(gs[a:b], es) and np.array_equal(gm[a:b], em), j
 
 
-@pytest.mark.parametrize("control", [False, True])
-def test_c4_epochs_graph_learned_vs_radix(K, orc, control):
+@pytest.mark.parametrize("control,carry", [(False, True), (True, True), (False, False)])
+def test_c4_epochs_graph_learned_vs_radix(K, orc, control, carry):
+    """carry: the sort carries the value column and the reduction reads it in
+    order (else the reduction follows the row ids)."""
     sizes = sizes_for(300, 4, 18, seed=40 + int(control))
     n = int(sizes.sum())
     dev = torch.device("cuda")
-    say(f"c4 scaled n={n} windows={len(sizes)} control={control}")
+    say(f"c4 scaled n={n} windows={len(sizes)} control={control} carry={carry}")
     rows = datagen.gen_c4(0, sizes, device=dev, control=control)
-    pipe = K_pipe(K, n, len(sizes))
+    pipe = K_pipe(K, n, len(sizes), carry)
     pipe.set_sizes(sizes)
     radix = K.batch_config(large_algo=K.KPA_SORT_RADIX)
     learned = K.batch_config(large_algo=K.KPA_SORT_LEARNED)
@@ -66,6 +68,7 @@ def test_c4_epochs_graph_learned_vs_radix(K, orc, control):
     datagen.gen_c4(1, sizes, out=rows, control=control)
     torch.cuda.synchronize()
     rows_h = rows.cpu()
+    vals_h = rows_h[:, 1].numpy().view(np.uint64)
     sk, sr, groups = oracle_windows(orc, rows_h, sizes)
 
     stream = torch.cuda.Stream()
@@ -80,6 +83,8 @@ def test_c4_epochs_graph_learned_vs_radix(K, orc, control):
             say(f"{name} replay {rep}")
             assert np.array_equal(u64(pipe.skeys)[:n], sk)
             assert np.array_equal(u32(pipe.srids)[:n], sr)
+            if carry:   # the carried column: each entry's own row's value
+                assert np.array_equal(u64(pipe.svals)[:n], vals_h[sr.astype(np.int64)])
             check_groups(pipe, groups, sizes)
         g.destroy()
         outs[name] = pipe.stats.cpu().numpy().copy()
@@ -89,9 +94,9 @@ def test_c4_epochs_graph_learned_vs_radix(K, orc, control):
     assert st[1] + st[2] > 0            # entries finished on chip or single-key
 
 
-def K_pipe(K, n, n_seg):
+def K_pipe(K, n, n_seg, carry=True):
     from paper_1901_01328_amd.pipeline import BatchAggregation
-    return BatchAggregation(n, n_seg, LAYOUT32)
+    return BatchAggregation(n, n_seg, LAYOUT32, carry_values=carry)
 
 
 def test_c4_autotuned_config_same_output(K, orc):
@@ -101,6 +106,7 @@ def test_c4_autotuned_config_same_output(K, orc):
     pipe = K_pipe(K, n, len(sizes))
     pipe.set_sizes(sizes)
     pipe.step(rows)
+    pipe.extract(rows)
     torch.cuda.synchronize()
     best, ms = K.kpa_batch_autotune(pipe.keys, pipe.rids, pipe.seg_off, n_cap=n, reps=1)
     say(f"tuned {best.as_dict()} {ms:.3f} ms")

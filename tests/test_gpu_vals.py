@@ -1,0 +1,210 @@
+"""GPU parity of the sorts that carry an 8-byte column beside the KPA
+(kpa_sort_segmented_vals, kpa_batch_sort_vals) and of the keyed reduction
+that reads such a column in KPA order (row ids NULL).
+
+Keys and row ids must equal the oracle's stable segmented sort byte for
+byte, on every route (radix, learned with its finishing pass, oversize
+chunks, pivot rounds and radix fallback; the batch's small, mid and large
+classes).  The column must follow the entries exactly: the value of input
+entry i is a hash of its (unique) row id, so vals_out[j] must be that hash
+of rids_out[j]."""
+import numpy as np
+import pytest
+import torch
+
+from datagen.rows import RowLayout
+from gpu_util import dev_u32, dev_u64, kpa_mod, need_gpu, say, u32, u64
+from test_gpu_batch import batch_sizes, make_batch, prior_models
+from test_gpu_learned import fit_models, gen_keys, heavy_with_close_neighbours, seg_offsets
+
+pytestmark = pytest.mark.gpu
+
+VALUE_ROWS = RowLayout(8, 0, 0, 8, 0, 8)   # a value column read as 8-byte rows
+M1 = np.uint64(0xBF58476D1CE4E5B9)
+M2 = np.uint64(0x94D049BB133111EB)
+
+
+@pytest.fixture(scope="module")
+def K():
+    need_gpu()
+    return kpa_mod()
+
+
+def val_of(rids):
+    """The value carried by the entry with row id r: a 64-bit mix of r."""
+    z = rids.astype(np.uint64) + np.uint64(0x9E3779B97F4A7C15)
+    with np.errstate(over="ignore"):
+        z = (z ^ (z >> np.uint64(30))) * M1
+        z = (z ^ (z >> np.uint64(27))) * M2
+        return z ^ (z >> np.uint64(31))
+
+
+def check_vals(orc, keys, rids, off, ok, orr, ov, label):
+    ek, er = orc.sort_segmented(keys, rids, off)
+    gk, gr, gv = u64(ok), u32(orr), u64(ov)
+    assert np.array_equal(gk, ek), f"{label}: keys differ from the oracle"
+    assert np.array_equal(gr, er), f"{label}: rids differ from the oracle"
+    assert np.array_equal(gv, val_of(gr)), f"{label}: values do not follow their entries"
+
+
+def sort_vals(K, orc, keys, rids, off, algo, models=None, label=""):
+    say(f"sort vals {label} n={len(keys)} algo={algo}")
+    st = K.new_sort_stats("cuda")
+    ok, orr, ov = K.kpa_sort_segmented_vals(dev_u64(keys), dev_u32(rids), dev_u64(val_of(rids)),
+                                            dev_u64(off), algo=algo, models=models, stats=st)
+    torch.cuda.synchronize()
+    check_vals(orc, keys, rids, off, ok, orr, ov, label)
+    return st.cpu().numpy()
+
+
+@pytest.mark.parametrize("dist", ["uniform64", "zipf_mix", "few", "narrow"])
+@pytest.mark.parametrize("algo", ["radix", "learned"])
+def test_sort_vals_single_segment(K, orc, dist, algo):
+    n = 300_001
+    keys = gen_keys(dist, n, 31)
+    rids = np.random.default_rng(32).permutation(n).astype(np.uint32)
+    off = seg_offsets([n])
+    models = fit_models(K, keys, off)[0] if algo == "learned" else None
+    a = K.KPA_SORT_LEARNED if algo == "learned" else K.KPA_SORT_RADIX
+    sort_vals(K, orc, keys, rids, off, a, models, f"{algo} {dist}")
+
+
+def test_sort_vals_ragged_segments(K, orc):
+    sizes = [0, 1, 4095, 4096, 4097, 70_001, 0, 250_000, 3]
+    keys = gen_keys("zipf_mix", sum(sizes), 41)
+    rids = np.arange(len(keys), dtype=np.uint32)[::-1].copy()
+    off = seg_offsets(sizes)
+    models = fit_models(K, keys, off)[0]
+    for algo in (K.KPA_SORT_RADIX, K.KPA_SORT_LEARNED):
+        sort_vals(K, orc, keys, rids, off, algo, models, f"ragged {algo}")
+
+
+def test_sort_vals_learned_overflow_and_pivot_rounds(K, orc):
+    """All knots 0 (every key in one bucket): the whole segment goes through
+    the oversize path: pivot rounds, on-chip ranges and the radix fallback
+    all move the column."""
+    n = 200_003
+    keys = gen_keys("uniform64", n, 5)
+    off = seg_offsets([n])
+    models, _ = fit_models(K, keys, off)
+    models.view(torch.uint8)[24:24 + 4 * 1025].view(torch.float32).zero_()
+    rids = np.random.default_rng(6).permutation(n).astype(np.uint32)
+    st = sort_vals(K, orc, keys, rids, off, K.KPA_SORT_LEARNED, models, "overflow")
+    assert st[3] >= n - 2
+
+
+def test_sort_vals_learned_pivot_parts_on_chip(K, orc):
+    off = seg_offsets([300_001])
+    models, _ = fit_models(K, heavy_with_close_neighbours(21), off)
+    keys = heavy_with_close_neighbours(22)
+    rids = np.random.default_rng(23).permutation(len(keys)).astype(np.uint32)
+    st = sort_vals(K, orc, keys, rids, off, K.KPA_SORT_LEARNED, models, "pivot parts")
+    assert st[4] >= 1
+
+
+def test_sort_vals_learned_invalid_model(K, orc):
+    n = 100_001
+    keys = gen_keys("uniform64", n, 6)
+    off = seg_offsets([n])
+    models, _ = fit_models(K, keys, off)
+    knots = models.view(torch.uint8)[24:24 + 4 * 1025].view(torch.float32)
+    knots[500], knots[501] = 0.9, 0.1
+    rids = np.arange(n, dtype=np.uint32)
+    st = sort_vals(K, orc, keys, rids, off, K.KPA_SORT_LEARNED, models, "invalid model")
+    assert st[5] == 1
+
+
+def batch_vals(K, orc, keys, rids, off, cfg, models=None, label=""):
+    say(f"batch vals {label} n={len(keys)} n_seg={len(off) - 1} cfg={cfg.as_dict()}")
+    ok, orr, ov = K.kpa_batch_sort_vals(dev_u64(keys), dev_u32(rids), dev_u64(val_of(rids)),
+                                        dev_u64(off), cfg=cfg, models=models)
+    torch.cuda.synchronize()
+    check_vals(orc, keys, rids, off, ok, orr, ov, label)
+    return ok, orr, ov
+
+
+@pytest.mark.parametrize("small,mid,grid", [
+    (4096, 1 << 16, 0),        # all three classes
+    (1024, 1024, 0),           # no mid class
+    (0, 0, 0),                 # everything multi-workgroup
+    (4096, 1 << 20, 0),        # no large class
+    (2048, 1 << 14, 7),        # a 7-workgroup persistent grid
+])
+def test_batch_vals_radix(K, orc, small, mid, grid):
+    keys, rids, off = make_batch(batch_sizes(small + mid + grid + 1))
+    cfg = K.batch_config(small, mid, grid, K.KPA_SORT_RADIX)
+    batch_vals(K, orc, keys, rids, off, cfg, label=f"radix {small}/{mid}/{grid}")
+
+
+@pytest.mark.parametrize("small,mid", [(4096, 1 << 14), (1024, 1024)])
+def test_batch_vals_learned(K, orc, small, mid):
+    sizes = batch_sizes(12, n_rand=300, hi=18)
+    models = prior_models(K, orc, sizes)
+    keys, rids, off = make_batch(sizes, epoch=1)
+    cfg = K.batch_config(small, mid, 0, K.KPA_SORT_LEARNED)
+    batch_vals(K, orc, keys, rids, off, cfg, models=models, label=f"learned {small}/{mid}")
+
+
+def test_reduce_reads_carried_values_in_order(K, orc):
+    """Keyed reduction with row ids NULL over the carried column equals the
+    oracle's reduction through the row ids, segment by segment."""
+    sizes = batch_sizes(13, n_rand=200, hi=17)
+    models = prior_models(K, orc, sizes)
+    keys, rids, off = make_batch(sizes, epoch=1)
+    cfg = K.batch_config(1024, 1024, 0, K.KPA_SORT_LEARNED)
+    ok, orr, ov = batch_vals(K, orc, keys, rids, off, cfg, models=models, label="for reduce")
+    d_off = dev_u64(off)
+    gkey, g, gseg = K.kpa_reduce_by_key(ok, None, d_off, ov, VALUE_ROWS, n_cap=len(keys))
+    torch.cuda.synchronize()
+    # oracle: the sorted KPA's row ids index a value column (row r holds val_of(r))
+    col = val_of(np.arange(len(keys), dtype=np.uint32)).reshape(-1, 1)
+    sk, sr = orc.sort_segmented(keys, rids, off)
+    gs = u64(gseg)
+    for s in range(len(off) - 1):
+        a, b = int(off[s]), int(off[s + 1])
+        ek, ec, es, em = orc.reduce_by_key(sk[a:b], sr[a:b], col, VALUE_ROWS)
+        g0, g1 = int(gs[s]), int(gs[s + 1])
+        assert np.array_equal(u64(gkey)[g0:g1], ek), s
+        assert np.array_equal(u64(g["cnt"])[g0:g1], ec), s
+        assert np.array_equal(u64(g["sum"])[g0:g1], es), s
+        assert np.array_equal(u64(g["max"])[g0:g1], em), s
+
+
+def test_reduce_in_order_group_starts_and_row_layouts(K, orc):
+    """Row ids NULL with group starts wanted (the scan also carries each run's
+    first index), and with 32-byte rows already in KPA order (the general
+    path: entry i reads row i)."""
+    from datagen.rows import LAYOUT32
+    rng = np.random.default_rng(77)
+    sizes = [5000, 1, 0, 4096, 4097, 70_000, 12_289]
+    n = sum(sizes)
+    off = seg_offsets(sizes)
+    keys = np.repeat(rng.integers(0, 1 << 63, size=n // 7 + 1, dtype=np.uint64), 7)[:n]
+    keys = keys[rng.permutation(n)]
+    rows = np.zeros((n, 4), np.uint64)
+    rows[:, 0] = keys
+    rows[:, 1] = rng.integers(0, 1 << 64, size=n, dtype=np.uint64)
+    rids = np.arange(n, dtype=np.uint32)
+    sk, sr = orc.sort_segmented(keys, rids, off)
+    srows = rows[sr.astype(np.int64)]                 # rows in KPA order
+    svals = srows[:, 1].copy()
+    d_off = dev_u64(off)
+    gkey, g, gseg = K.kpa_reduce_by_key(dev_u64(sk), None, d_off, dev_u64(svals), VALUE_ROWS,
+                                        n_cap=n, want=("cnt", "sum", "max", "gstart"))
+    gkey2, g2, gseg2 = K.kpa_reduce_by_key(
+        dev_u64(sk), None, d_off,
+        torch.from_numpy(srows.view(np.int64)).to("cuda"), LAYOUT32, n_cap=n)
+    torch.cuda.synchronize()
+    gs = u64(gseg)
+    assert np.array_equal(gs, u64(gseg2))
+    for s in range(len(sizes)):
+        a, b = int(off[s]), int(off[s + 1])
+        ek, ec, es, em = orc.reduce_by_key(sk[a:b], sr[a:b], rows, LAYOUT32)
+        heads = a + np.flatnonzero(np.r_[True, sk[a + 1:b] != sk[a:b - 1]]) if b > a else []
+        g0, g1 = int(gs[s]), int(gs[s + 1])
+        for gk_, gg in ((gkey, g), (gkey2, g2)):
+            assert np.array_equal(u64(gk_)[g0:g1], ek), s
+            assert np.array_equal(u64(gg["cnt"])[g0:g1], ec), s
+            assert np.array_equal(u64(gg["sum"])[g0:g1], es), s
+            assert np.array_equal(u64(gg["max"])[g0:g1], em), s
+        assert np.array_equal(u64(g["gstart"])[g0:g1], np.asarray(heads, np.uint64)), s
