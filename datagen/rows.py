@@ -192,6 +192,49 @@ def gen_c3(n: int = 1 << 26, seed: int = 3, side: int = 0, device="cpu",
     return out
 
 
+# Advertising-event stream shaped like the Yahoo streaming benchmark's
+# (synthetic: no item of that benchmark is used).  32-byte rows
+# {ad_id, event_type, ts, campaign slot}; event types 0 (view), 1 (click),
+# 2 (purchase) uniform; ads uniform over n_camps * ads_per_camp ad keys plus
+# n_unknown keys absent from the ad table; the campaign slot holds
+# mix64(row index) until a pipeline writes a campaign there.
+YSB_VIEW = 0
+YSB_COLS = {"ad_id": 0, "event_type": 8, "ts": 16, "campaign": 24}
+LAYOUT_YSB = RowLayout(32, 0, 8, 8, 16, 8)   # key ad_id, value event_type, ts
+
+
+def ysb_tables(n_camps: int = 1000, ads_per_camp: int = 10, seed: int = 6, device="cpu"):
+    """(ad keys ascending, their campaign keys): the external key-value table."""
+    n_ads = n_camps * ads_per_camp
+    ads = key_table(n_ads, seed ^ 0xAD, device)
+    camps = key_table(n_camps, seed ^ 0xCA, device)[torch.arange(n_ads, device=device)
+                                                       // ads_per_camp]
+    # the store is looked up by ad key: hand it over in ascending key order
+    idx = torch.from_numpy(np.argsort(ads.cpu().numpy().view(np.uint64), kind="stable"))
+    idx = idx.to(device)
+    return ads[idx], camps[idx]
+
+
+def gen_ysb(n: int, seed: int = 6, device="cpu", n_camps: int = 1000, ads_per_camp: int = 10,
+            n_unknown: int = 16, span_ns: int = 10 ** 10, chunk: int = 1 << 24,
+            out: torch.Tensor | None = None):
+    if out is None:
+        out = torch.empty((n, 4), dtype=torch.int64, device=device)
+    n_ads = n_camps * ads_per_camp
+    ads = key_table(n_ads, seed ^ 0xAD, out.device)
+    unknown = key_table(n_unknown, seed ^ 0x0B, out.device) if n_unknown else ads[:0]
+    pool = torch.cat([ads, unknown])
+    jitter = 10 ** 6 if span_ns >= 10 ** 9 else max(1, span_ns // 10000)
+    for s in range(0, n, chunk):
+        e = min(n, s + chunk)
+        i = torch.arange(s, e, dtype=torch.int64, device=out.device)
+        out[s:e, 0] = pool[uniform_int(splitmix64(seed, 1, i), pool.numel())]
+        out[s:e, 1] = uniform_int(splitmix64(seed, 2, i), 3)
+        out[s:e, 2] = _jittered_ts(i, n, span_ns, jitter, seed)
+        out[s:e, 3] = mix64(i)
+    return out
+
+
 def c4_window_sizes(n_windows: int = 4096, seed: int = 4, lo_log2: int = 10,
                     hi_log2: int = 22) -> np.ndarray:
     """Substream window sizes, log-uniform over [2^lo, 2^hi): host-side metadata."""

@@ -264,12 +264,18 @@ def _ws_size(fn, *args):
     return int(n.value)
 
 
-def _ws(nbytes, device, ws=None):
+def _ws(nbytes, device, ws=None, stream=None):
+    """The caller's workspace, or a new one; a new one is marked as used on
+    `stream`, so that the caching allocator does not hand it out again
+    before the work enqueued there has finished with it."""
     if ws is not None:
         if ws.numel() * ws.element_size() < nbytes:
             raise ValueError(f"workspace of {ws.numel()} bytes < {nbytes}")
         return ws
-    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+    t = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+    if stream is not None:
+        t.record_stream(stream)
+    return t
 
 
 def _check(t, dtype, name):
@@ -352,7 +358,7 @@ def kpa_partition_windows(rows, layout, win_len, n_win, win_origin=0, rid_base=0
                    if out_win_off is None else out_win_off)
     out_oob = torch.empty(1, dtype=torch.int64, device=dev) if out_oob is None else out_oob
     nb = _ws_size("kpa_partition_windows_workspace_size", n, n_win)
-    ws = _ws(nb, dev, ws)
+    ws = _ws(nb, dev, ws, stream)
     L = layout_struct(layout)
     _call("kpa_partition_windows", _p(rows), n, C.byref(L), win_len, win_origin, n_win, rid_base,
           _p(out_keys), _p(out_rids), _p(out_vals), _p(out_win_off), _p(out_oob), _p(ws),
@@ -374,7 +380,7 @@ def kpa_sort_segmented(keys_in, rids_in, seg_off, n_cap=None, algo=KPA_SORT_RADI
     keys_out = torch.empty_like(keys_in) if keys_out is None else keys_out
     rids_out = torch.empty_like(rids_in) if rids_out is None else rids_out
     nb = kpa_sort_workspace_size(n_cap, n_seg, algo)
-    ws = _ws(nb, dev, ws)
+    ws = _ws(nb, dev, ws, stream)
     _call("kpa_sort_segmented", _p(keys_in), _p(rids_in), _p(keys_out), _p(rids_out), _p(seg_off),
           n_seg, n_cap, algo, _p(models), _p(stats), _p(ws), ws.numel() * ws.element_size(),
           _stream(stream))
@@ -399,7 +405,7 @@ def kpa_sort_segmented_vals(keys_in, rids_in, vals_in, seg_off, n_cap=None, algo
     keys_out = torch.empty_like(keys_in) if keys_out is None else keys_out
     rids_out = torch.empty_like(rids_in) if rids_out is None else rids_out
     vals_out = torch.empty_like(vals_in) if vals_out is None else vals_out
-    ws = _ws(kpa_sort_vals_workspace_size(n_cap, n_seg, algo), dev, ws)
+    ws = _ws(kpa_sort_vals_workspace_size(n_cap, n_seg, algo), dev, ws, stream)
     _call("kpa_sort_segmented_vals", _p(keys_in), _p(rids_in), _p(vals_in), _p(keys_out),
           _p(rids_out), _p(vals_out), _p(seg_off), n_seg, n_cap, algo, _p(models), _p(stats),
           _p(ws), ws.numel() * ws.element_size(), _stream(stream))
@@ -415,7 +421,7 @@ def kpa_sort(keys_in, rids_in, algo=KPA_SORT_RADIX, model=None, stats=None, keys
     keys_out = torch.empty_like(keys_in) if keys_out is None else keys_out
     rids_out = torch.empty_like(rids_in) if rids_out is None else rids_out
     nb = kpa_sort_workspace_size(n, 1, algo)
-    ws = _ws(nb, dev, ws)
+    ws = _ws(nb, dev, ws, stream)
     _call("kpa_sort", _p(keys_in), _p(rids_in), n, _p(keys_out), _p(rids_out), algo, _p(model),
           _p(stats), _p(ws), ws.numel() * ws.element_size(), _stream(stream))
     return keys_out, rids_out
@@ -445,7 +451,7 @@ def kpa_batch_sort(keys_in, rids_in, seg_off, cfg=None, n_cap=None, models=None,
     dev = keys_in.device
     keys_out = torch.empty_like(keys_in) if keys_out is None else keys_out
     rids_out = torch.empty_like(rids_in) if rids_out is None else rids_out
-    ws = _ws(kpa_batch_sort_workspace_size(n_cap, n_seg, cfg), dev, ws)
+    ws = _ws(kpa_batch_sort_workspace_size(n_cap, n_seg, cfg), dev, ws, stream)
     _call("kpa_batch_sort", _p(keys_in), _p(rids_in), _p(keys_out), _p(rids_out), _p(seg_off),
           n_seg, n_cap, C.byref(cfg), _p(models), _p(stats), _p(ws),
           ws.numel() * ws.element_size(), _stream(stream))
@@ -471,7 +477,7 @@ def kpa_batch_sort_vals(keys_in, rids_in, vals_in, seg_off, cfg=None, n_cap=None
     keys_out = torch.empty_like(keys_in) if keys_out is None else keys_out
     rids_out = torch.empty_like(rids_in) if rids_out is None else rids_out
     vals_out = torch.empty_like(vals_in) if vals_out is None else vals_out
-    ws = _ws(kpa_batch_sort_vals_workspace_size(n_cap, n_seg, cfg), dev, ws)
+    ws = _ws(kpa_batch_sort_vals_workspace_size(n_cap, n_seg, cfg), dev, ws, stream)
     _call("kpa_batch_sort_vals", _p(keys_in), _p(rids_in), _p(vals_in), _p(keys_out),
           _p(rids_out), _p(vals_out), _p(seg_off), n_seg, n_cap, C.byref(cfg), _p(models),
           _p(stats), _p(ws), ws.numel() * ws.element_size(), _stream(stream))
@@ -490,7 +496,7 @@ def kpa_batch_autotune(keys_in, rids_in, seg_off, large_algo=KPA_SORT_RADIX, n_c
     keys_out = torch.empty_like(keys_in) if keys_out is None else keys_out
     rids_out = torch.empty_like(rids_in) if rids_out is None else rids_out
     ws = _ws(kpa_batch_sort_workspace_size(n_cap, n_seg, kpa_batch_config_default(large_algo)),
-             dev, ws)
+             dev, ws, stream)
     best = kpa_batch_config()
     ms = C.c_float(0.0)
     _call("kpa_batch_autotune", _p(keys_in), _p(rids_in), _p(keys_out), _p(rids_out), _p(seg_off),
@@ -566,7 +572,7 @@ def kpa_merge(a_keys, a_rids, b_keys, b_rids, out_keys=None, out_rids=None, ws=N
     out_keys = torch.empty(na + nb_, dtype=torch.int64, device=dev) if out_keys is None else out_keys
     out_rids = torch.empty(na + nb_, dtype=torch.int32, device=dev) if out_rids is None else out_rids
     nb = _ws_size("kpa_merge_workspace_size", na, nb_)
-    ws = _ws(nb, dev, ws)
+    ws = _ws(nb, dev, ws, stream)
     _call("kpa_merge", _p(a_keys), _p(a_rids), na, _p(b_keys), _p(b_rids), nb_, _p(out_keys),
           _p(out_rids), _p(ws), ws.numel() * ws.element_size(), _stream(stream))
     return out_keys, out_rids
@@ -580,7 +586,7 @@ def kpa_merge_runs(keys, rids, run_off, out_keys=None, out_rids=None, ws=None, s
     out_keys = torch.empty_like(keys) if out_keys is None else out_keys
     out_rids = torch.empty_like(rids) if out_rids is None else out_rids
     nb = _ws_size("kpa_merge_runs_workspace_size", n)
-    ws = _ws(nb, dev, ws)
+    ws = _ws(nb, dev, ws, stream)
     _call("kpa_merge_runs", _p(keys), _p(rids), offs, len(run_off) - 1, _p(out_keys), _p(out_rids),
           _p(ws), ws.numel() * ws.element_size(), _stream(stream))
     return out_keys, out_rids
@@ -599,9 +605,10 @@ def kpa_reduce_by_key(keys, rids, seg_off, rows, layout, n_cap=None, want=("cnt"
     outs_t = {w: get(w, cap) for w in want}
     gseg = get("gseg_off", n_seg + 1)
     nb = _ws_size("kpa_reduce_by_key_workspace_size", n_cap, n_seg)
-    ws = _ws(nb, dev, ws)
-    L = layout_struct(layout)
-    _call("kpa_reduce_by_key", _p(keys), _p(rids), _p(seg_off), n_seg, n_cap, _p(rows), C.byref(L),
+    ws = _ws(nb, dev, ws, stream)
+    L = layout_struct(layout) if layout is not None else None   # counts only: no rows
+    _call("kpa_reduce_by_key", _p(keys), _p(rids), _p(seg_off), n_seg, n_cap, _p(rows),
+          C.byref(L) if L is not None else None,
           _p(gkey), _p(outs_t.get("cnt")), _p(outs_t.get("sum")), _p(outs_t.get("max")),
           _p(outs_t.get("gstart")), _p(gseg), _p(ws), ws.numel() * ws.element_size(),
           _stream(stream))
@@ -632,7 +639,7 @@ def kpa_topk_by_sum(gkey, gsum, gseg_off, k=10, g_cap=None, ws=None, stream=None
     osum = o["sum"] if "sum" in o else torch.empty(n_seg * k, dtype=torch.int64, device=dev)
     on = o["n"] if "n" in o else torch.empty(n_seg, dtype=torch.int32, device=dev)
     nb = _ws_size("kpa_topk_by_sum_workspace_size", g_cap, n_seg)
-    ws = _ws(nb, dev, ws)
+    ws = _ws(nb, dev, ws, stream)
     _call("kpa_topk_by_sum", _p(gkey), _p(gsum), _p(gseg_off), n_seg, g_cap, k, _p(ok), _p(osum),
           _p(on), _p(ws), ws.numel() * ws.element_size(), _stream(stream))
     return ok, osum, on
@@ -650,7 +657,7 @@ def kpa_median_by_key(keys, rids, seg_off, rows, layout, n_cap=None, ws=None, st
     gseg = o["gseg_off"] if "gseg_off" in o else torch.empty(n_seg + 1, dtype=torch.int64,
                                                                device=dev)
     nb = _ws_size("kpa_median_by_key_workspace_size", n_cap, n_seg)
-    ws = _ws(nb, dev, ws)
+    ws = _ws(nb, dev, ws, stream)
     L = layout_struct(layout)
     _call("kpa_median_by_key", _p(keys), _p(rids), _p(seg_off), n_seg, n_cap, _p(rows), C.byref(L),
           _p(gkey), _p(gmed), _p(gseg), _p(ws), ws.numel() * ws.element_size(), _stream(stream))
@@ -673,7 +680,7 @@ def kpa_join(lk, lr, l_seg_off, rk, rr, r_seg_off, rows_l, rows_r, layout, pairs
                                                             dtype=torch.int64, device=dev)
     npairs = o["npairs"] if "npairs" in o else torch.empty(1, dtype=torch.int64, device=dev)
     nb = _ws_size("kpa_join_workspace_size", nl_cap, nr_cap, n_seg)
-    ws = _ws(nb, dev, ws)
+    ws = _ws(nb, dev, ws, stream)
     L = layout_struct(layout)
     _call("kpa_join", _p(lk), _p(lr), _p(l_seg_off), nl_cap, _p(rk), _p(rr), _p(r_seg_off), nr_cap,
           n_seg, _p(rows_l), _p(rows_r), C.byref(L), _p(count), _p(sumprod), _p(pairs), pairs_cap,
@@ -745,7 +752,7 @@ def kpa_select(keys, rids, seg_off, num_lo, num_hi=None, den=None, op=">", colum
     orr = o["rids"] if "rids" in o else torch.empty(max(n_cap, 1), dtype=torch.int32, device=dev)
     oo = o["seg_off"] if "seg_off" in o else torch.empty(n_seg + 1, dtype=torch.int64,
                                                          device=dev)
-    ws = _ws(_ws_size("kpa_select_workspace_size", n_cap, n_seg), dev, ws)
+    ws = _ws(_ws_size("kpa_select_workspace_size", n_cap, n_seg), dev, ws, stream)
     L = layout_struct(layout) if layout is not None else None
     _call("kpa_select", _p(keys), _p(rids), _p(seg_off), n_seg, n_cap, _p(rows),
           C.byref(L) if L is not None else None, column, SELECT_OPS.get(op, op), _p(num_lo),
@@ -765,7 +772,7 @@ def kpa_reduce_all_windows(rows, layout, win_len, n_win, win_origin=0, n=None, o
             o[name] = torch.empty(n_win, dtype=torch.int64, device=dev)
     if "oob" not in o:
         o["oob"] = torch.empty(1, dtype=torch.int64, device=dev)
-    ws = _ws(_ws_size("kpa_reduce_all_windows_workspace_size", n_win), dev, ws)
+    ws = _ws(_ws_size("kpa_reduce_all_windows_workspace_size", n_win), dev, ws, stream)
     L = layout_struct(layout)
     _call("kpa_reduce_all_windows", _p(rows), n, C.byref(L), win_len, win_origin, n_win,
           _p(o["cnt"]), _p(o["sum_lo"]), _p(o["sum_hi"]), _p(o["max"]), _p(o["oob"]), _p(ws),
@@ -786,7 +793,7 @@ def kpa_topk_per_key(keys, rids, seg_off, rows, layout, k, n_cap=None, outs=None
             o[name] = torch.empty(cap, dtype=torch.int64, device=dev)
     if "gseg_off" not in o:
         o["gseg_off"] = torch.empty(n_seg + 1, dtype=torch.int64, device=dev)
-    ws = _ws(_ws_size("kpa_run_stats_workspace_size", n_cap, n_seg), dev, ws)
+    ws = _ws(_ws_size("kpa_run_stats_workspace_size", n_cap, n_seg), dev, ws, stream)
     L = layout_struct(layout)
     _call("kpa_topk_per_key", _p(keys), _p(rids), _p(seg_off), n_seg, n_cap, _p(rows), C.byref(L),
           k, _p(o["gkey"]), _p(o["gcnt"]), _p(o["gstart"]), _p(o["topv"]), _p(o["gseg_off"]),
@@ -807,7 +814,7 @@ def kpa_unique_count_by_key(keys, rids, seg_off, rows, layout, n_cap=None, outs=
             o[name] = torch.empty(cap, dtype=torch.int64, device=dev)
     if "gseg_off" not in o:
         o["gseg_off"] = torch.empty(n_seg + 1, dtype=torch.int64, device=dev)
-    ws = _ws(_ws_size("kpa_run_stats_workspace_size", n_cap, n_seg), dev, ws)
+    ws = _ws(_ws_size("kpa_run_stats_workspace_size", n_cap, n_seg), dev, ws, stream)
     L = layout_struct(layout)
     _call("kpa_unique_count_by_key", _p(keys), _p(rids), _p(seg_off), n_seg, n_cap, _p(rows),
           C.byref(L), _p(o["gkey"]), _p(o["uniq"]), _p(o["gseg_off"]), _p(ws),
@@ -827,7 +834,7 @@ def kpa_sort_rows_windowed(rows, layout, win_len, n_win, win_origin=0, n=None, o
     out_oob = torch.empty(1, dtype=torch.int64, device=dev) if out_oob is None else out_oob
     nb = C.c_size_t(0)
     _call("kpa_sort_rows_windowed_workspace_size", n, layout.row_bytes, C.byref(nb))
-    ws = _ws(int(nb.value), dev, ws)
+    ws = _ws(int(nb.value), dev, ws, stream)
     L = layout_struct(layout)
     _call("kpa_sort_rows_windowed", _p(rows), n, C.byref(L), win_len, win_origin, n_win,
           _p(out_rows), _p(out_win_off), _p(out_oob), _p(ws), ws.numel() * ws.element_size(),
@@ -847,7 +854,7 @@ def kpa_hash_groupby(rows, layout, table_cap, g_cap=None, n=None, outs=None, ws=
             o[name] = torch.empty(max(g_cap, 1), dtype=torch.int64, device=dev)
     if "ngroups" not in o:
         o["ngroups"] = torch.empty(1, dtype=torch.int64, device=dev)
-    ws = _ws(_ws_size("kpa_hash_groupby_workspace_size", table_cap), dev, ws)
+    ws = _ws(_ws_size("kpa_hash_groupby_workspace_size", table_cap), dev, ws, stream)
     L = layout_struct(layout)
     _call("kpa_hash_groupby", _p(rows), n, C.byref(L), table_cap, _p(o["gkey"]), _p(o["cnt"]),
           _p(o["sum"]), _p(o["max"]), g_cap, _p(o["ngroups"]), _p(ws),
@@ -880,7 +887,7 @@ def kpa_partition_kpa(keys, rids, win_len, n_win, win_origin=0, n=None, out_keys
     out_win_off = (torch.empty(n_win + 1, dtype=torch.int64, device=dev)
                    if out_win_off is None else out_win_off)
     out_oob = torch.empty(1, dtype=torch.int64, device=dev) if out_oob is None else out_oob
-    ws = _ws(_ws_size("kpa_partition_windows_workspace_size", n, n_win), dev, ws)
+    ws = _ws(_ws_size("kpa_partition_windows_workspace_size", n, n_win), dev, ws, stream)
     _call("kpa_partition_kpa", _p(keys), _p(rids), n, win_len, win_origin, n_win, _p(out_keys),
           _p(out_rids), _p(out_win_off), _p(out_oob), _p(ws), ws.numel() * ws.element_size(),
           _stream(stream))
@@ -939,7 +946,7 @@ def kpa_mlp_loss_grad(params, x, y, ws=None, stream=None):
     loss = torch.empty(1, dtype=torch.float32, device=x.device)
     grad = torch.empty(KPA_MLP_PARAMS, dtype=torch.float32, device=x.device)
     nb = _ws_size("kpa_mlp_loss_grad_workspace_size", m)
-    ws = _ws(nb, x.device, ws)
+    ws = _ws(nb, x.device, ws, stream)
     _call("kpa_mlp_loss_grad", _p(params), _p(x), _p(y), m, _p(loss), _p(grad), _p(ws),
           ws.numel() * ws.element_size(), _stream(stream))
     return loss, grad
@@ -955,7 +962,7 @@ def kpa_mlp_train(params, m, v, x, y, t0, steps, lr=1e-3, ws=None, stream=None):
     n = x.numel()
     loss = torch.empty(1, dtype=torch.float32, device=x.device)
     nb = _ws_size("kpa_mlp_loss_grad_workspace_size", n) + 4 * KPA_MLP_PARAMS + 512
-    ws = _ws(nb, x.device, ws)
+    ws = _ws(nb, x.device, ws, stream)
     _call("kpa_mlp_train", _p(params), _p(m), _p(v), _p(x), _p(y), n, t0, steps, lr, _p(loss),
           _p(ws), ws.numel() * ws.element_size(), _stream(stream))
     return loss

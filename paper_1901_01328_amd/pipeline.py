@@ -76,8 +76,10 @@ class WindowAggregation:
             # each model comes from an earlier window, never its own data.
             K.kpa_pwl_fit(self.skeys, self.win_off, 1024, models=self.next_models, stream=stream)
             mb = K.PWL_MODEL_BYTES
-            self.models[mb:].copy_(self.next_models[:-mb])
-            self.models[:mb].copy_(self.next_models[-mb:])
+            # on the step's stream: after the fit, before the next step's sort
+            with torch.cuda.stream(stream if stream is not None else torch.cuda.current_stream()):
+                self.models[mb:].copy_(self.next_models[:-mb])
+                self.models[:mb].copy_(self.next_models[-mb:])
             self.have_models = True
         outs = dict(self.g)
         outs["gkey"] = self.gkey
@@ -313,3 +315,86 @@ class SlidingAggregation:
             K.kpa_reduce_by_key(self.s_keys, self.s_rids, self.cat_off, self.pane.g[col],
                                 VALUE_COLUMN, n_cap=self.wcap, want=(want,), ws=self.ws_red,
                                 stream=stream, outs=outs)
+
+
+class AdPipeline:
+    """The advertising pipeline of the paper's pipeline example (Sec. 4.3,
+    shaped like the Yahoo streaming benchmark) on KPAs, over 32-byte rows
+    {ad_id, event_type, ts, campaign slot}:
+
+      Filter          Extract KPA(ad_id), Select the rows whose event type
+                      (the value column) equals `keep_type`;
+      External join   KeyUpdate: ad_id -> campaign in place from a small
+                      sorted key-value table in device memory, then
+                      write-back of the campaign into each row's slot;
+      Window          KeySwap to the timestamp, Partition KPA(t) into
+                      tumbling windows;
+      Keyed agg.      KeySwap to the campaign, segmented sort, count per key.
+
+    step() returns per-window (gkey, count, gseg_off) views and the number of
+    ads missing from the table (their ad_id stays the key, as the update
+    leaves them); rows are written (the campaign slot), as in the paper.
+    The survivor count of the filter is read back to the host once per step
+    (the later calls take it as their size)."""
+
+    def __init__(self, n_rows, table_keys, table_vals, win_len, n_win, keep_type=0,
+                 device="cuda", win_origin=0):
+        from datagen.rows import LAYOUT_YSB, YSB_COLS
+        self.n, self.win_len, self.n_win, self.origin = n_rows, win_len, n_win, win_origin
+        self.layout, self.cols = LAYOUT_YSB, YSB_COLS
+        self.tk, self.tv = table_keys, table_vals
+        d = torch.device(device)
+        cap = max(n_rows, 1)
+        i64 = dict(dtype=torch.int64, device=d)
+        i32 = dict(dtype=torch.int32, device=d)
+        self.keys = torch.empty(cap, **i64)
+        self.rids = torch.empty(cap, **i32)
+        self.fkeys = torch.empty(cap, **i64)
+        self.frids = torch.empty(cap, **i32)
+        self.pkeys = torch.empty(cap, **i64)
+        self.prids = torch.empty(cap, **i32)
+        self.skeys = torch.empty(cap, **i64)
+        self.srids = torch.empty(cap, **i32)
+        self.gkey = torch.empty(cap, **i64)
+        self.gcnt = torch.empty(cap, **i64)
+        self.one_seg = torch.tensor([0, n_rows], **i64)
+        self.foff = torch.empty(2, **i64)
+        self.woff = torch.empty(n_win + 1, **i64)
+        self.oob = torch.empty(1, **i64)
+        self.gseg = torch.empty(n_win + 1, **i64)
+        self.missing = torch.empty(1, **i64)
+        self.keep = torch.tensor([keep_type], **i64)
+        u8 = dict(dtype=torch.uint8, device=d)
+        self.ws_sel = torch.empty(K._ws_size("kpa_select_workspace_size", n_rows, 1), **u8)
+        self.ws_part = torch.empty(K._ws_size("kpa_partition_windows_workspace_size", n_rows,
+                                              n_win), **u8)
+        self.ws_sort = torch.empty(K.kpa_sort_workspace_size(n_rows, n_win), **u8)
+        self.ws_red = torch.empty(K._ws_size("kpa_reduce_by_key_workspace_size", n_rows, n_win),
+                                  **u8)
+
+    def step(self, rows, stream=None):
+        L, c = self.layout, self.cols
+        K.kpa_extract(rows, L, out_keys=self.keys, out_rids=self.rids, n=self.n, stream=stream)
+        K.kpa_select(self.keys, self.rids, self.one_seg, self.keep, op="==",
+                     column=K.KPA_SEL_VALUE, rows=rows, layout=L, n_cap=self.n,
+                     outs={"keys": self.fkeys, "rids": self.frids, "seg_off": self.foff},
+                     ws=self.ws_sel, stream=stream)
+        m = int(self.foff[1].item())       # survivors: the size of every later call
+        K.kpa_key_update(self.fkeys, self.tk, self.tv, n=m, out_missing=self.missing,
+                         stream=stream)
+        K.kpa_key_writeback(self.fkeys, self.frids, rows, 32, c["campaign"], n=m, stream=stream)
+        tkeys = K.kpa_keyswap(self.frids[:m], rows, 32, c["ts"], out_keys=self.fkeys,
+                              stream=stream)
+        K.kpa_partition_kpa(tkeys, self.frids, self.win_len, self.n_win, self.origin, n=m,
+                            out_keys=self.pkeys, out_rids=self.prids, out_win_off=self.woff,
+                            out_oob=self.oob, ws=self.ws_part, stream=stream)
+        p = int(self.woff[-1].item())      # entries inside the windows
+        K.kpa_keyswap(self.prids[:p], rows, 32, c["campaign"], out_keys=self.pkeys,
+                      stream=stream)
+        K.kpa_sort_segmented(self.pkeys, self.prids, self.woff, n_cap=max(p, 1),
+                             keys_out=self.skeys, rids_out=self.srids, ws=self.ws_sort,
+                             stream=stream)
+        K.kpa_reduce_by_key(self.skeys, self.srids, self.woff, None, None, n_cap=max(p, 1),
+                            want=("cnt",), ws=self.ws_red, stream=stream,
+                            outs={"gkey": self.gkey, "cnt": self.gcnt, "gseg_off": self.gseg})
+        return {"survivors": m, "in_windows": p}

@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 import torch
 
+import datagen
 from datagen.rows import LAYOUT16, LAYOUT32, RowLayout
 from gpu_util import dev_u32, dev_u64, kpa_mod, need_gpu, say, u32, u64
 
@@ -378,3 +379,44 @@ def test_sort_segment_of_2_30_entries_is_copied_and_counted(K):
     assert torch.equal(ok[:big], keys[:big]) and torch.equal(orr[:big], rids[:big])
     sk, idx = torch.sort(keys[big:], stable=True)
     assert torch.equal(ok[big:], sk) and torch.equal(orr[big:].long(), idx + big)
+
+
+@pytest.mark.parametrize("n,n_camps", [(300_001, 100), (70_000, 2000)])
+def test_ad_pipeline_counts_views_per_campaign_and_window(K, n, n_camps):
+    """The pipeline example of Sec. 4.3 (Select on the event type, KeyUpdate
+    ad -> campaign from a sorted table, write-back, KeySwap to time,
+    Partition, KeySwap to the campaign, sort, count) against its definition
+    counted directly on the host: per tumbling window, the number of view
+    events of each campaign (ads missing from the table keep their ad key).
+    The table of 2000 campaigns (20000 ads) is searched in device memory,
+    the one of 100 campaigns on chip."""
+    from paper_1901_01328_amd.pipeline import AdPipeline
+    W, n_win = 10 ** 9, 9                       # the last of 10 s of events lies outside
+    rows = datagen.gen_ysb(n, seed=n_camps, device="cuda", n_camps=n_camps, ads_per_camp=10)
+    rows_h = rows.cpu().numpy().view(np.uint64).copy()
+    tk, tv = datagen.ysb_tables(n_camps, 10, seed=n_camps, device="cuda")
+    pipe = AdPipeline(n, tk, tv, W, n_win)
+    say(f"ad pipeline n={n} campaigns={n_camps}")
+    info = pipe.step(rows)
+    torch.cuda.synchronize()
+    # the definition, counted on the host
+    table = dict(zip(tk.cpu().numpy().view(np.uint64).tolist(),
+                     tv.cpu().numpy().view(np.uint64).tolist()))
+    keep = rows_h[:, 1] == np.uint64(datagen.YSB_VIEW)
+    ads, ts = rows_h[keep, 0], rows_h[keep, 2]
+    camp = np.array([table.get(int(a), int(a)) for a in ads.tolist()], np.uint64)
+    win = ts // np.uint64(W)
+    inw = win < np.uint64(n_win)
+    assert info["survivors"] == int(keep.sum()) and info["in_windows"] == int(inw.sum())
+    missing = sum(1 for a in ads.tolist() if int(a) not in table)
+    assert int(pipe.missing.item()) == missing
+    gs = u64(pipe.gseg)
+    for w in range(n_win):
+        ks, cs = np.unique(camp[inw & (win == np.uint64(w))], return_counts=True)
+        g0, g1 = int(gs[w]), int(gs[w + 1])
+        assert np.array_equal(u64(pipe.gkey)[g0:g1], ks), w
+        assert np.array_equal(u64(pipe.gcnt)[g0:g1], cs.astype(np.uint64)), w
+    # write-back: kept rows hold their campaign, the others are untouched
+    after = rows.cpu().numpy().view(np.uint64)
+    assert np.array_equal(after[keep, 3], camp)
+    assert np.array_equal(after[~keep, 3], rows_h[~keep, 3])
