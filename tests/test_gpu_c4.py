@@ -108,7 +108,7 @@ def test_c4_autotuned_config_same_output(K, orc):
     pipe.step(rows)
     pipe.extract(rows)
     torch.cuda.synchronize()
-    best, ms = K.kpa_batch_autotune(pipe.keys, pipe.rids, pipe.seg_off, n_cap=n, reps=1)
+    best, ms = K.kpa_batch_autotune(pipe.keys, None, pipe.seg_off, n_cap=n, reps=1)
     say(f"tuned {best.as_dict()} {ms:.3f} ms")
     pipe.step(rows, cfg=best)
     torch.cuda.synchronize()

