@@ -45,7 +45,7 @@ PASS_BYTES = {
     "part_pass": 44,        # read 32-byte row, write key+rid
     "part_hist": 32,        # read the row (its timestamp spans the row's cache line share)
     "reduce_main": 20,      # read key+rid, gather 8-byte value
-    "extract": 52,          # read 32-byte row, write key+rid+value
+    "extract": 48,          # read 32-byte row, write key+value (the sort takes positions as rids)
     "learned_scatter": 24,  # read key+rid, write key+rid (entries of large windows)
     "learned_finish": 24,   # read key+rid, write key+rid (entries of large windows)
     "learned_hist": 8,      # read key (entries of large windows)
@@ -275,7 +275,7 @@ def bench_c4(a):
             cfgs[r], tune_ms[r] = K.batch_config(large_algo=algo[r]), None
         else:
             cfgs[r], tune_ms[r] = K.kpa_batch_autotune(
-                pipe.keys, pipe.rids, pipe.seg_off, large_algo=algo[r], n_cap=n,
+                pipe.keys, None, pipe.seg_off, large_algo=algo[r], n_cap=n,
                 models=pipe.models if r == "learned" else None, reps=2,
                 keys_out=pipe.skeys, rids_out=pipe.srids, ws=pipe.ws_sort)
             log(f"autotuned {r}: {cfgs[r].as_dict()} ({tune_ms[r]:.2f} ms sort)")

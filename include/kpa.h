@@ -94,7 +94,9 @@ kpa_status kpa_profile_names(char* buf, size_t len);
 /* ---------------------------------------------------------------------------
  * Extract (Table 2: bundle -> KPA, sequential).  keys[i] = u64 at key_off of
  * row i, rids[i] = rid_base + i.  rows: device, n rows.  out_keys/out_rids:
- * device, n entries each.  out_vals (device, n u64, may be NULL): the value
+ * device, n entries each; out_rids may be NULL when the sort that follows
+ * takes NULL row ids (then entry i's row id is i).  out_vals (device, n u64,
+ * may be NULL): the value
  * column (val_off, zero-extended) of row i, a compact copy a keyed reduction
  * can read as 8-byte rows (see kpa_partition_windows).
  */
@@ -141,6 +143,9 @@ kpa_status kpa_partition_kpa(const uint64_t* keys, const uint32_t* rids, uint64_
  * is sorted on its own; all segments go through the same launches.  n_cap is
  * a host-side upper bound on seg_off[n_seg] used to size launches.  keys_in
  * must not alias keys_out (likewise rids).  The inputs are not modified.
+ * rids_in may be NULL (here and in the batched and _vals forms): entry i's
+ * row id is then i, its position in keys_in (what kpa_extract with rid_base
+ * 0 writes), and no input row ids are read.
  *
  * algo KPA_SORT_RADIX: least-significant-digit radix sort with 8-bit digits;
  * digits that are constant within a segment are skipped.

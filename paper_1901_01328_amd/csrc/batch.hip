@@ -113,7 +113,7 @@ __device__ void small_sort(BatchSmem& sm, const u64* __restrict__ keys_in,
   const u32 tid = threadIdx.x;
   for (u32 i = tid; i < n; i += BLOCK) {
     sm.skeys[i] = keys_in[a + i];
-    sm.srids[i] = VALS ? i : rids_in[a + i];
+    sm.srids[i] = VALS ? i : (rids_in ? rids_in[a + i] : (u32)(a + i));
   }
   lds_sort(sm, n);  // begins with a barrier; leaves the result (or the input) in sm
   __syncthreads();
@@ -121,7 +121,7 @@ __device__ void small_sort(BatchSmem& sm, const u64* __restrict__ keys_in,
     keys_out[a + i] = sm.skeys[i];
     if (VALS) {
       const u32 o = sm.srids[i];
-      rids_out[a + i] = rids_in[a + o];
+      rids_out[a + i] = rids_in ? rids_in[a + o] : (u32)(a + o);
       vals_out[a + i] = vals_in[a + o];
     } else {
       rids_out[a + i] = sm.srids[i];
@@ -155,7 +155,7 @@ __device__ void mid_sort(BatchSmem& sm, const u64* __restrict__ keys_in,
   if (k_act == 0) {  // one key: the input order is the sorted order
     for (u32 i = tid; i < n; i += BLOCK) {
       keys_out[a + i] = keys_in[a + i];
-      rids_out[a + i] = rids_in[a + i];
+      rids_out[a + i] = rids_in ? rids_in[a + i] : (u32)(a + i);
       if (VALS) vals_out[a + i] = vals_in[a + i];
     }
     return;
@@ -201,7 +201,7 @@ __device__ void mid_sort(BatchSmem& sm, const u64* __restrict__ keys_in,
         const u32 o = tile_offset(j);
         if (o < cnt) {
           kk[j] = src_k[base + o];
-          rr[j] = src_r[base + o];
+          rr[j] = src_r ? src_r[base + o] : (u32)(base + o);  // no input rids: positions
           valid |= 1u << j;
         } else {
           kk[j] = 0;
@@ -342,8 +342,7 @@ kpa_status check_args(const uint64_t* keys_in, const uint32_t* rids_in, uint64_t
                       uint32_t* rids_out, const uint64_t* seg_off, uint64_t n_cap,
                       const kpa_batch_config* cfg, const kpa_pwl_model* models, void* ws) {
   KPA_CHECK(check_config(cfg));
-  KPA_REQUIRE(keys_in && rids_in && keys_out && rids_out && seg_off && ws, KPA_EINVAL,
-              "null pointer");
+  KPA_REQUIRE(keys_in && keys_out && rids_out && seg_off && ws, KPA_EINVAL, "null pointer");
   KPA_REQUIRE(keys_in != keys_out && rids_in != (const uint32_t*)rids_out, KPA_EINVAL,
               "inputs must not alias outputs");
   KPA_REQUIRE(aligned(keys_in, 8) && aligned(keys_out, 8) && aligned(rids_in, 4) &&

@@ -125,7 +125,7 @@ kpa_status launch_fill_u64(u64* p, u64 n, u64 v, hipStream_t st) {
   return KPA_OK;
 }
 
-// Extract: one thread per row, key copied, rid = base + row.
+// Extract: one thread per row, key copied, rid = base + row (when wanted).
 __global__ void __launch_bounds__(256) k_extract(const unsigned char* __restrict__ rows, u64 n,
                                                  u32 row_bytes, u32 key_off, u32 val_off,
                                                  u32 val_w, u32 rid_base, u64* __restrict__ keys,
@@ -134,7 +134,7 @@ __global__ void __launch_bounds__(256) k_extract(const unsigned char* __restrict
   u64 stride = (u64)gridDim.x * 256;
   for (; i < n; i += stride) {
     keys[i] = *reinterpret_cast<const u64*>(rows + i * row_bytes + key_off);
-    rids[i] = rid_base + (u32)i;
+    if (rids) rids[i] = rid_base + (u32)i;
     if (vals) vals[i] = load_val(rows, (u32)i, row_bytes, val_off, val_w);
   }
 }
@@ -195,7 +195,7 @@ kpa_status kpa_extract(const void* rows, uint64_t n, const kpa_row_layout* layou
   clear_error();
   KPA_CHECK(check_layout(layout, out_vals != nullptr, false));
   if (n == 0) return KPA_OK;
-  KPA_REQUIRE(rows && out_keys && out_rids, KPA_EINVAL, "null pointer");
+  KPA_REQUIRE(rows && out_keys, KPA_EINVAL, "null pointer");
   KPA_REQUIRE(aligned(rows, 16) && aligned(out_keys, 8) && aligned(out_rids, 4) &&
                   aligned(out_vals, 8),
               KPA_EINVAL, "misaligned pointer");

@@ -20,7 +20,7 @@ constexpr int HIST_TILES_PER_BLOCK = 8;
 
 struct DigitSortBufs {
   const u64* keys_in;
-  const u32* rids_in;
+  const u32* rids_in;  // may be null: entry i's row id is i
   u64* keys_out;
   u32* rids_out;
   u64* keys_tmp;
@@ -467,7 +467,7 @@ __global__ void __launch_bounds__(PASS_THREADS, PASS_WAVES / 2)
         if (bf.keys_in != bf.keys_out) {
           for (u32 i = tid; i < td.cnt; i += PASS_THREADS) {
             bf.keys_out[td.base + i] = bf.keys_in[td.base + i];
-            bf.rids_out[td.base + i] = bf.rids_in[td.base + i];
+            bf.rids_out[td.base + i] = bf.rids_in ? bf.rids_in[td.base + i] : (u32)(td.base + i);
             if (VALS) bf.vals_out[td.base + i] = bf.vals_in[td.base + i];
           }
         }
@@ -489,7 +489,7 @@ __global__ void __launch_bounds__(PASS_THREADS, PASS_WAVES / 2)
       const u32 o = tile_offset_t<PASS_WAVES>(j);
       if (o < td.cnt) {
         kk[j] = src_k[td.base + o];
-        rr[j] = src_r[td.base + o];
+        rr[j] = src_r ? src_r[td.base + o] : (u32)(td.base + o);  // no input rids: positions
         valid |= 1u << j;
       } else {
         kk[j] = 0;

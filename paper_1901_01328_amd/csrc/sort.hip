@@ -48,8 +48,7 @@ kpa_status sort_segmented(const uint64_t* keys_in, const uint32_t* rids_in, cons
   const bool vals = vals_in != nullptr;
   KPA_REQUIRE(algo == KPA_SORT_RADIX || algo == KPA_SORT_LEARNED, KPA_EINVAL, "bad algo");
   if (n_seg == 0 || n_cap == 0) return KPA_OK;
-  KPA_REQUIRE(keys_in && rids_in && keys_out && rids_out && seg_off && ws, KPA_EINVAL,
-              "null pointer");
+  KPA_REQUIRE(keys_in && keys_out && rids_out && seg_off && ws, KPA_EINVAL, "null pointer");
   KPA_REQUIRE(keys_in != keys_out && rids_in != (const uint32_t*)rids_out, KPA_EINVAL,
               "inputs must not alias outputs");
   KPA_REQUIRE(aligned(keys_in, 8) && aligned(keys_out, 8) && aligned(rids_in, 4) &&

@@ -332,13 +332,16 @@ def kpa_profile_names():
 
 
 def kpa_extract(rows, layout, rid_base=0, out_keys=None, out_rids=None, stream=None,
-                out_vals=None, n=None):
+                out_vals=None, n=None, with_rids=True):
     """Returns (keys, rids); out_vals (n int64), when given, also receives the
-    value column."""
+    value column.  with_rids=False: no row ids are written (rids is None)."""
     n = rows_count(rows, layout) if n is None else n
     dev = rows.device
     out_keys = torch.empty(n, dtype=torch.int64, device=dev) if out_keys is None else out_keys
-    out_rids = torch.empty(n, dtype=torch.int32, device=dev) if out_rids is None else out_rids
+    if not with_rids:
+        out_rids = None
+    elif out_rids is None:
+        out_rids = torch.empty(n, dtype=torch.int32, device=dev)
     L = layout_struct(layout)
     _call("kpa_extract", _p(rows), n, C.byref(L), rid_base, _p(out_keys), _p(out_rids),
           _p(out_vals), _stream(stream))
@@ -373,12 +376,14 @@ def kpa_sort_workspace_size(n_cap, n_seg=1, algo=KPA_SORT_RADIX):
 def kpa_sort_segmented(keys_in, rids_in, seg_off, n_cap=None, algo=KPA_SORT_RADIX, models=None,
                        stats=None, keys_out=None, rids_out=None, ws=None, stream=None):
     _check(keys_in, torch.int64, "keys_in")
-    _check(rids_in, torch.int32, "rids_in")
+    if rids_in is not None:   # None: row ids are the entries' positions
+        _check(rids_in, torch.int32, "rids_in")
     n_seg = seg_off.numel() - 1
     n_cap = keys_in.numel() if n_cap is None else n_cap
     dev = keys_in.device
     keys_out = torch.empty_like(keys_in) if keys_out is None else keys_out
-    rids_out = torch.empty_like(rids_in) if rids_out is None else rids_out
+    rids_out = (torch.empty(keys_in.numel(), dtype=torch.int32, device=dev)
+                if rids_out is None else rids_out)
     nb = kpa_sort_workspace_size(n_cap, n_seg, algo)
     ws = _ws(nb, dev, ws, stream)
     _call("kpa_sort_segmented", _p(keys_in), _p(rids_in), _p(keys_out), _p(rids_out), _p(seg_off),
@@ -397,13 +402,15 @@ def kpa_sort_segmented_vals(keys_in, rids_in, vals_in, seg_off, n_cap=None, algo
     """kpa_sort_segmented with an 8-byte column carried beside the KPA;
     returns (keys_out, rids_out, vals_out)."""
     _check(keys_in, torch.int64, "keys_in")
-    _check(rids_in, torch.int32, "rids_in")
+    if rids_in is not None:   # None: row ids are the entries' positions
+        _check(rids_in, torch.int32, "rids_in")
     _check(vals_in, torch.int64, "vals_in")
     n_seg = seg_off.numel() - 1
     n_cap = keys_in.numel() if n_cap is None else n_cap
     dev = keys_in.device
     keys_out = torch.empty_like(keys_in) if keys_out is None else keys_out
-    rids_out = torch.empty_like(rids_in) if rids_out is None else rids_out
+    rids_out = (torch.empty(keys_in.numel(), dtype=torch.int32, device=dev)
+                if rids_out is None else rids_out)
     vals_out = torch.empty_like(vals_in) if vals_out is None else vals_out
     ws = _ws(kpa_sort_vals_workspace_size(n_cap, n_seg, algo), dev, ws, stream)
     _call("kpa_sort_segmented_vals", _p(keys_in), _p(rids_in), _p(vals_in), _p(keys_out),
@@ -444,13 +451,15 @@ def kpa_batch_sort_workspace_size(n_cap, n_seg, cfg):
 def kpa_batch_sort(keys_in, rids_in, seg_off, cfg=None, n_cap=None, models=None, stats=None,
                    keys_out=None, rids_out=None, ws=None, stream=None):
     _check(keys_in, torch.int64, "keys_in")
-    _check(rids_in, torch.int32, "rids_in")
+    if rids_in is not None:   # None: row ids are the entries' positions
+        _check(rids_in, torch.int32, "rids_in")
     cfg = kpa_batch_config_default() if cfg is None else cfg
     n_seg = seg_off.numel() - 1
     n_cap = keys_in.numel() if n_cap is None else n_cap
     dev = keys_in.device
     keys_out = torch.empty_like(keys_in) if keys_out is None else keys_out
-    rids_out = torch.empty_like(rids_in) if rids_out is None else rids_out
+    rids_out = (torch.empty(keys_in.numel(), dtype=torch.int32, device=dev)
+                if rids_out is None else rids_out)
     ws = _ws(kpa_batch_sort_workspace_size(n_cap, n_seg, cfg), dev, ws, stream)
     _call("kpa_batch_sort", _p(keys_in), _p(rids_in), _p(keys_out), _p(rids_out), _p(seg_off),
           n_seg, n_cap, C.byref(cfg), _p(models), _p(stats), _p(ws),
@@ -468,14 +477,16 @@ def kpa_batch_sort_vals(keys_in, rids_in, vals_in, seg_off, cfg=None, n_cap=None
     """kpa_batch_sort with an 8-byte column carried beside the KPA; returns
     (keys_out, rids_out, vals_out)."""
     _check(keys_in, torch.int64, "keys_in")
-    _check(rids_in, torch.int32, "rids_in")
+    if rids_in is not None:   # None: row ids are the entries' positions
+        _check(rids_in, torch.int32, "rids_in")
     _check(vals_in, torch.int64, "vals_in")
     cfg = kpa_batch_config_default() if cfg is None else cfg
     n_seg = seg_off.numel() - 1
     n_cap = keys_in.numel() if n_cap is None else n_cap
     dev = keys_in.device
     keys_out = torch.empty_like(keys_in) if keys_out is None else keys_out
-    rids_out = torch.empty_like(rids_in) if rids_out is None else rids_out
+    rids_out = (torch.empty(keys_in.numel(), dtype=torch.int32, device=dev)
+                if rids_out is None else rids_out)
     vals_out = torch.empty_like(vals_in) if vals_out is None else vals_out
     ws = _ws(kpa_batch_sort_vals_workspace_size(n_cap, n_seg, cfg), dev, ws, stream)
     _call("kpa_batch_sort_vals", _p(keys_in), _p(rids_in), _p(vals_in), _p(keys_out),
@@ -489,12 +500,14 @@ def kpa_batch_autotune(keys_in, rids_in, seg_off, large_algo=KPA_SORT_RADIX, n_c
                        ws=None, stream=None):
     """Returns (best kpa_batch_config, its mean milliseconds)."""
     _check(keys_in, torch.int64, "keys_in")
-    _check(rids_in, torch.int32, "rids_in")
+    if rids_in is not None:   # None: row ids are the entries' positions
+        _check(rids_in, torch.int32, "rids_in")
     n_seg = seg_off.numel() - 1
     n_cap = keys_in.numel() if n_cap is None else n_cap
     dev = keys_in.device
     keys_out = torch.empty_like(keys_in) if keys_out is None else keys_out
-    rids_out = torch.empty_like(rids_in) if rids_out is None else rids_out
+    rids_out = (torch.empty(keys_in.numel(), dtype=torch.int32, device=dev)
+                if rids_out is None else rids_out)
     ws = _ws(kpa_batch_sort_workspace_size(n_cap, n_seg, kpa_batch_config_default(large_algo)),
              dev, ws, stream)
     best = kpa_batch_config()

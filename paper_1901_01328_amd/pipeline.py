@@ -121,9 +121,8 @@ class BatchAggregation:
         cap = max(n_rows, 1)
         i64 = dict(dtype=torch.int64, device=d)
         i32 = dict(dtype=torch.int32, device=d)
-        self.keys = torch.empty(cap, **i64)
-        self.rids = torch.empty(cap, **i32)
-        self.vals = torch.empty(cap, **i64)
+        self.keys = torch.empty(cap, **i64)   # no input rids: extract writes none and
+        self.vals = torch.empty(cap, **i64)   # the sort takes each entry's position
         self.skeys = torch.empty(cap, **i64)
         self.srids = torch.empty(cap, **i32)
         self.svals = torch.empty(cap, **i64)
@@ -164,8 +163,8 @@ class BatchAggregation:
         """The step's first call alone: keys, row ids and the value column of
         the current rows (what the sort reads; an autotuner times sorts of
         them)."""
-        K.kpa_extract(rows, self.layout, out_keys=self.keys, out_rids=self.rids,
-                      out_vals=self.vals, n=self.n, stream=stream)
+        K.kpa_extract(rows, self.layout, out_keys=self.keys, out_vals=self.vals, n=self.n,
+                      stream=stream, with_rids=False)
 
     def step(self, rows, stream=None, cfg=None, fit_next=False):
         """Extract, batched sort, keyed reduction.  With fit_next, the step also
@@ -178,12 +177,12 @@ class BatchAggregation:
         carry = self.carry if self.carry is not None else cfg.large_algo == K.KPA_SORT_LEARNED
         self.g = self._g[carry]
         if carry:
-            K.kpa_batch_sort_vals(self.keys, self.rids, self.vals, self.seg_off, cfg=cfg,
+            K.kpa_batch_sort_vals(self.keys, None, self.vals, self.seg_off, cfg=cfg,
                                   n_cap=self.n, models=models, stats=self.stats,
                                   keys_out=self.skeys, rids_out=self.srids, vals_out=self.svals,
                                   ws=self.ws_sort, stream=stream)
         else:
-            K.kpa_batch_sort(self.keys, self.rids, self.seg_off, cfg=cfg, n_cap=self.n,
+            K.kpa_batch_sort(self.keys, None, self.seg_off, cfg=cfg, n_cap=self.n,
                              models=models, stats=self.stats, keys_out=self.skeys,
                              rids_out=self.srids, ws=self.ws_sort, stream=stream)
         outs = dict(self.g)
