@@ -127,7 +127,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5", "ablations", "adapt", "ads"],
+    ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5", "ablations", "adapt", "ads",
+                                           "models"],
                     default="c4")
     ap.add_argument("--algo", choices=["radix", "learned"], default="radix", help="c2 only")
     ap.add_argument("--rows", type=int, default=1 << 28, help="c2 rows")
@@ -147,6 +148,8 @@ def parse():
     ap.add_argument("--c4-route", choices=["both", "learned", "radix"], default="both",
                     help="c4: routes to time (profiling runs of one route)")
     ap.add_argument("--no-tune", action="store_true", help="c4: default batch configuration")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="c4: time eager steps instead of graph replays (counter runs)")
     ap.add_argument("--probe-copy-mib", type=int, default=0,
                     help="first copy this many MiB device-to-device (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -173,7 +176,7 @@ def main():
     else:
         COPY_GBS = measure_copy_rate(dev)
     out = {"c4": bench_c4, "c2": bench_c2, "c3": bench_c3, "c5": bench_c5, "adapt": bench_adapt,
-           "ads": bench_ads,
+           "ads": bench_ads, "models": bench_models,
            "ablations": lambda a: {"metric": METRIC, "ablations": ablation_leg(a.steps, a.warmup)}
            }[a.workload](a)
     print(json.dumps(out), flush=True)
@@ -283,7 +286,17 @@ def bench_c4(a):
     stream = torch.cuda.Stream()
     res = {}
     for r in routes:
-        graph = pipe.capture(rows, stream, cfg=cfgs[r], fit_next=(r == "learned"))
+        fit = r == "learned"
+        if a.no_graph:   # eager steps (counter collection does not follow graph replays)
+            class _Eager:
+                def launch(self, st):
+                    pipe.step(rows, stream=st, cfg=cfgs[r], fit_next=fit)
+
+                def destroy(self):
+                    pass
+            graph = _Eager()
+        else:
+            graph = pipe.capture(rows, stream, cfg=cfgs[r], fit_next=fit)
         for _ in range(a.warmup):
             graph.launch(stream)
         stream.synchronize()
@@ -299,7 +312,8 @@ def bench_c4(a):
         wall = time.perf_counter() - wall0
         ms = max(ev0.elapsed_time(ev1), wall * 1000) / a.steps
         graph.destroy()
-        log(f"c4 {r}: {a.steps} graph replays, {ms:.3f} ms/step")
+        log(f"c4 {r}: {a.steps} {'eager steps' if a.no_graph else 'graph replays'}, "
+            f"{ms:.3f} ms/step")
         res[r] = {"ms": ms, "value": n / (ms / 1000.0) / 1e6}
 
     # Per-kernel times: the same steps run eagerly with event timing per launch
@@ -1048,6 +1062,82 @@ def bench_ads(a):
                        "ads, filter views, external join by key update + write-back, 10 x 1 s "
                        "windows, count per campaign", "survivors": info["survivors"]},
             "check": check}
+
+
+def bench_models(a):
+    """Where the learned sort's models come from: 8 substream windows of 2^22
+    keys shaped like C4's (substreams 0, 512, ..., 3584: rank-Zipf keys whose
+    exponent grows with the substream); epoch 0's sorted windows give (a) a
+    direct PWL fit per window and (b) the monotone MLP trained on the GPU per
+    window (4096 samples, 400 Adam steps, lr 1e-2) and distilled to PWL
+    knots.  Epoch 1's windows are then sorted by radix and by the learned
+    sort with each model set (identical output checked); reported: time to
+    build each model set, sort times and the learned path's counters."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_1901_01328_amd as P
+    K = P.load()
+    dev = torch.device("cuda:0")
+    subs, n = list(range(0, 4096, 512)), 1 << 22
+    off = torch.tensor([w * n for w in range(len(subs) + 1)], dtype=torch.int64, device=dev)
+
+    def keys(epoch):
+        return torch.cat([datagen.gen_c4_window(j, epoch, n, device=dev)[:, 0] for j in subs])
+
+    def timed(fn, reps=5):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            out = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps, out
+
+    k0 = keys(0)
+    sk0, _ = K.kpa_sort_segmented(k0, None, off)
+    ms_pwl, m_pwl = timed(lambda: K.kpa_pwl_fit(sk0, off, 1024), reps=3)
+    # one network per window, its random start drawn here and passed in
+    from datagen.rows import uniform_f64
+    u = uniform_f64(datagen.splitmix64(77, 1, torch.arange(
+        len(subs) * K.KPA_MLP_PARAMS, dtype=torch.int64, device=dev))).float()
+    m_mlp = K.new_models(len(subs), dev)
+    mb = K.PWL_MODEL_BYTES
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = []
+    for w in range(len(subs)):
+        model = m_mlp[w * mb:(w + 1) * mb]
+        x, y = K.kpa_mlp_training_set(sk0[w * n:(w + 1) * n], 4096, model)
+        p = K.kpa_mlp_init(u[w * K.KPA_MLP_PARAMS:(w + 1) * K.KPA_MLP_PARAMS].contiguous())
+        mm, vv = torch.zeros_like(p), torch.zeros_like(p)
+        losses.append(K.kpa_mlp_train(p, mm, vv, x, y, 1, 400, lr=1e-2))
+        K.kpa_mlp_to_pwl(p, model, 1024)
+    torch.cuda.synchronize()
+    ms_mlp = (time.perf_counter() - t0) * 1000
+    log(f"models: pwl fit {ms_pwl:.3f} ms, mlp train+distill {ms_mlp:.1f} ms")
+    k1 = keys(1)
+    res = {}
+    ms_r, (rk, rr) = timed(lambda: K.kpa_sort_segmented(k1, None, off))
+    res["radix"] = {"sort_ms": round(ms_r, 3)}
+    for name, models in (("learned_pwl", m_pwl), ("learned_mlp", m_mlp)):
+        st = K.new_sort_stats(dev)
+        ms_l, (lk, lr) = timed(lambda: K.kpa_sort_segmented(
+            k1, None, off, algo=K.KPA_SORT_LEARNED, models=models, stats=st))
+        s = st.cpu().numpy().tolist()
+        same = bool(torch.equal(lk, rk) and torch.equal(lr, rr))
+        res[name] = {"sort_ms": round(ms_l, 3), "speedup_vs_radix": round(ms_r / ms_l, 3),
+                     "finished_on_chip": s[1], "single_key_entries": s[2],
+                     "fallback_entries": s[3], "order_violations": s[5],
+                     "identical_to_radix": same}
+        log(f"{name}: {res[name]}")
+    return {"metric": METRIC, "workload": f"{len(subs)} windows of {n} keys (C4 substreams "
+            f"{subs[0]}..{subs[-1]}), epoch 0 -> models, epoch 1 sorted",
+            "model_build_ms": {"pwl_fit": round(ms_pwl, 3), "mlp_train_distill": round(ms_mlp, 1)},
+            "mlp_final_loss": [round(float(l.item()), 6) for l in losses], "sorts": res}
 
 
 def bench_c5(a):

@@ -603,6 +603,12 @@ kpa_status kpa_mlp_adam_step(float* params, const float* grad, float* adam_m, fl
 kpa_status kpa_mlp_train(float* params, float* adam_m, float* adam_v, const float* x,
                          const float* y, uint32_t m, uint32_t t0, uint32_t steps, float lr,
                          float* out_loss, void* ws, size_t ws_bytes, hipStream_t stream);
+/* Starting parameters from 1153 caller-supplied uniforms in [0, 1) (device;
+ * the network's random initialization drawn by the caller): W1 = 4 + 4u
+ * (slopes in [4, 8)), b1 = -W1 * (i + u')/32 (breakpoints spread over [0, 1]),
+ * W2 = (0.5 + u)/32, b2 = -0.25 + 0.5u, W3 = (0.5 + u)/32, b3 = 0; u, u'
+ * the uniform at the parameter's own index, u' the one at index 32 + i. */
+kpa_status kpa_mlp_init(const float* uniforms, float* params, hipStream_t stream);
 /* Distill the network into model->knots: F_j = running max of clamp(f(j/n_seg),
  * 0, 1), j = 0..n_seg; kmin/kmax are kept from kpa_mlp_training_set. */
 kpa_status kpa_mlp_to_pwl(const float* params, uint32_t n_seg_model, kpa_pwl_model* model,

@@ -193,6 +193,33 @@ __global__ void __launch_bounds__(BLOCK) k_mlp_adam(float* __restrict__ p, const
   p[e] = w;
 }
 
+// Starting parameters from caller-supplied uniforms u in [0, 1) (one per
+// parameter; the last is unused): the first layer's ramps get slopes in
+// [4, 8) and breakpoints spread over [0, 1] (one per 1/32 interval), the
+// second layer starts near an average of its inputs, the output near their
+// mean; all weights nonnegative.
+__global__ void __launch_bounds__(BLOCK) k_mlp_init(const float* __restrict__ u,
+                                                    float* __restrict__ p) {
+  const int e = blockIdx.x * BLOCK + threadIdx.x;
+  if (e >= NP) return;
+  float v;
+  if (e < OFF_B1) {
+    v = 4.0f + 4.0f * u[e];
+  } else if (e < OFF_W2) {
+    const int i = e - OFF_B1;
+    v = -(4.0f + 4.0f * u[i]) * (((float)i + u[OFF_B1 + i]) / (float)H);
+  } else if (e < OFF_B2) {
+    v = (0.5f + u[e]) / (float)H;
+  } else if (e < OFF_W3) {
+    v = -0.25f + 0.5f * u[e];
+  } else if (e < OFF_B3) {
+    v = (0.5f + u[e]) / (float)H;
+  } else {
+    v = 0.0f;
+  }
+  p[e] = v;
+}
+
 // Knots of the network's CDF at x = j / S: clamp to [0, 1], running maximum.
 __global__ void __launch_bounds__(1024) k_mlp_to_pwl(const float* __restrict__ params, u32 S,
                                                      kpa_pwl_model* __restrict__ model) {
@@ -305,6 +332,14 @@ kpa_status kpa_mlp_train(float* params, float* adam_m, float* adam_v, const floa
     KPA_LAUNCH("mlp_adam", k_mlp_adam, dim3((u32)ceil_div(NP, BLOCK)), dim3(BLOCK), 0, stream, params,
                grad, adam_m, adam_v, t0 + i, lr, 0.9f, 0.999f, 1e-8f);
   }
+  return KPA_OK;
+}
+
+kpa_status kpa_mlp_init(const float* uniforms, float* params, hipStream_t stream) {
+  clear_error();
+  KPA_REQUIRE(uniforms && params, KPA_EINVAL, "null pointer");
+  KPA_LAUNCH("mlp_init", k_mlp_init, dim3((u32)ceil_div(NP, BLOCK)), dim3(BLOCK), 0, stream,
+             uniforms, params);
   return KPA_OK;
 }
 

@@ -230,6 +230,7 @@ _SIGS = {
     "kpa_mlp_train": ([_vp, _vp, _vp, _vp, _vp, _u32, _u32, _u32, _f32, _vp, _vp, C.c_size_t,
                        _vp], C.c_int32),
     "kpa_mlp_to_pwl": ([_vp, _u32, _vp, _vp], C.c_int32),
+    "kpa_mlp_init": ([_vp, _vp, _vp], C.c_int32),
 }
 
 EXPORTED = []
@@ -979,6 +980,16 @@ def kpa_mlp_train(params, m, v, x, y, t0, steps, lr=1e-3, ws=None, stream=None):
     _call("kpa_mlp_train", _p(params), _p(m), _p(v), _p(x), _p(y), n, t0, steps, lr, _p(loss),
           _p(ws), ws.numel() * ws.element_size(), _stream(stream))
     return loss
+
+
+def kpa_mlp_init(uniforms, params=None, stream=None):
+    """Starting parameters of the network from KPA_MLP_PARAMS uniforms."""
+    if uniforms.dtype != torch.float32 or uniforms.numel() < KPA_MLP_PARAMS:
+        raise ValueError(f"need {KPA_MLP_PARAMS} float32 uniforms")
+    params = torch.empty(KPA_MLP_PARAMS, dtype=torch.float32, device=uniforms.device) \
+        if params is None else params
+    _call("kpa_mlp_init", _p(uniforms), _p(params), _stream(stream))
+    return params
 
 
 def kpa_mlp_to_pwl(params, model, n_seg_model=1024, stream=None):

@@ -162,3 +162,13 @@ def test_trained_network_gains_over_untrained(K, orc):
     # entries needing more than the model's buckets: pivot splits and fallbacks
     assert stats["trained"][3] < stats["untrained"][3]
     assert stats["trained"][1] > stats["untrained"][1]
+
+
+def test_init_matches_oracle(K):
+    """The network's starting parameters from the same uniforms, on the GPU
+    (float32) and in the oracle (float64)."""
+    u = np.random.default_rng(11).random(M.N_PARAMS)
+    p = K.kpa_mlp_init(torch.tensor(u, dtype=torch.float32, device="cuda"))
+    torch.cuda.synchronize()
+    e = M.init_params(u.astype(np.float32).astype(np.float64))
+    np.testing.assert_allclose(p.cpu().numpy().astype(np.float64), e, rtol=2e-6, atol=1e-7)
