@@ -311,8 +311,14 @@ kpa_status kpa_merge(const uint64_t* a_keys, const uint32_t* a_rids, uint64_t na
                      uint64_t* out_keys, uint32_t* out_rids, void* ws, size_t ws_bytes,
                      hipStream_t stream);
 /* Merge n_runs consecutive sorted runs [run_off[r], run_off[r+1]) of one array
- * (run_off: HOST array of n_runs+1 u64) into one sorted KPA; ties keep run
- * order.  keys/rids are used as scratch and hold garbage afterwards. */
+ * (run_off: HOST array of n_runs+1 u64) into one sorted KPA of
+ * n = run_off[n_runs] - run_off[0] entries at out_keys/out_rids[0, n); ties
+ * keep run order.  keys/rids are used as scratch and hold garbage afterwards.
+ * Pairwise rounds over the nonempty runs (Sec. 4.2: merges of sorted KPAs at
+ * window close); with up to 1024 nonempty runs each round is two launches
+ * over all of its pairs and the call makes no host-to-device copy, so it can
+ * be captured in a graph (offsets frozen at capture); more runs are merged
+ * pair by pair. */
 kpa_status kpa_merge_runs_workspace_size(uint64_t n, size_t* bytes);
 kpa_status kpa_merge_runs(uint64_t* keys, uint32_t* rids, const uint64_t* run_off,
                           uint32_t n_runs, uint64_t* out_keys, uint32_t* out_rids, void* ws,

@@ -37,16 +37,16 @@ struct MergeSmem {
   u32 r[TILE];
 };
 
-__global__ void __launch_bounds__(BLOCK) k_merge_tiles(const u64* __restrict__ ak,
-                                                       const u32* __restrict__ ar, u64 na,
-                                                       const u64* __restrict__ bk,
-                                                       const u32* __restrict__ br, u64 nb,
-                                                       const u64* __restrict__ split,
-                                                       u64* __restrict__ ok, u32* __restrict__ orr) {
-  __shared__ MergeSmem sm;
-  const u64 t = blockIdx.x;
+// Output tile t (entries [t*TILE, min((t+1)*TILE, na+nb)) of the merge of A
+// and B) from the splits at its two ends, split[0] and split[1].
+__device__ __forceinline__ void merge_tile(MergeSmem& sm, const u64* __restrict__ ak,
+                                           const u32* __restrict__ ar, u64 na,
+                                           const u64* __restrict__ bk,
+                                           const u32* __restrict__ br, u64 nb,
+                                           const u64* __restrict__ split, u64 t,
+                                           u64* __restrict__ ok, u32* __restrict__ orr) {
   const u64 d0 = t * TILE, d1 = min(d0 + TILE, na + nb);
-  const u64 i0 = split[t], i1 = split[t + 1];
+  const u64 i0 = split[0], i1 = split[1];
   const u64 j0 = d0 - i0, j1 = d1 - i1;
   const u32 la = (u32)(i1 - i0), lb = (u32)(j1 - j0);
   // A part at [0, la), B part at [la, la + lb)
@@ -94,6 +94,77 @@ __global__ void __launch_bounds__(BLOCK) k_merge_tiles(const u64* __restrict__ a
     ok[d0 + x] = sm.k[x];
     orr[d0 + x] = sm.r[x];
   }
+}
+
+__global__ void __launch_bounds__(BLOCK) k_merge_tiles(const u64* __restrict__ ak,
+                                                       const u32* __restrict__ ar, u64 na,
+                                                       const u64* __restrict__ bk,
+                                                       const u32* __restrict__ br, u64 nb,
+                                                       const u64* __restrict__ split,
+                                                       u64* __restrict__ ok, u32* __restrict__ orr) {
+  __shared__ MergeSmem sm;
+  merge_tile(sm, ak, ar, na, bk, br, nb, split + blockIdx.x, blockIdx.x, ok, orr);
+}
+
+// One round of the pairwise merge of many runs, all pairs in one launch.
+// Pair q merges A = src[a0, a1) and B = src[a1, b1) into dst[a0, b1) (b1 = a1
+// for an unpaired last run, which is copied); t0 = output tiles of the pairs
+// before it.  The round's split array holds, pair after pair, the splits at
+// each of a pair's tiles + 1 boundaries: pair q's start at t0 + q.
+struct MergePair {
+  u64 a0, a1, b1, t0;
+};
+constexpr u32 PAIR_CHUNK = 64;  // descriptors copied per launch (2 KiB of arguments)
+struct PairChunk {
+  MergePair p[PAIR_CHUNK];
+};
+// Pairs planned per call on the device path; more nonempty runs take the
+// per-pair launches.
+constexpr u32 MR_PLAN_RUNS = 1024;
+constexpr u64 MR_PLAN_DESC = MR_PLAN_RUNS + 64;  // all rounds' pairs (< runs + rounds)
+
+__global__ void __launch_bounds__(PAIR_CHUNK) k_merge_desc(PairChunk c, u32 cnt,
+                                                           MergePair* __restrict__ out) {
+  if (threadIdx.x < cnt) out[threadIdx.x] = c.p[threadIdx.x];
+}
+
+// Largest q < n_pairs with key(q) <= x, key nondecreasing in q and key(0) = 0.
+template <typename KeyOf>
+__device__ __forceinline__ u32 last_le(u32 n_pairs, u64 x, KeyOf key) {
+  u32 lo = 0, hi = n_pairs - 1;
+  while (lo < hi) {
+    const u32 mid = (lo + hi + 1) >> 1;
+    if (key(mid) <= x) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void __launch_bounds__(BLOCK) k_merge_round_splits(const u64* __restrict__ src,
+                                                              const MergePair* __restrict__ pr,
+                                                              u32 n_pairs, u64 n_bounds,
+                                                              u64* __restrict__ split) {
+  const u64 g = (u64)blockIdx.x * BLOCK + threadIdx.x;
+  if (g >= n_bounds) return;
+  const u32 q = last_le(n_pairs, g, [&](u32 i) { return pr[i].t0 + i; });
+  const MergePair p = pr[q];
+  const u64 na = p.a1 - p.a0, nb = p.b1 - p.a1;
+  const u64 d = min((g - p.t0 - q) * (u64)TILE, na + nb);
+  split[g] = merge_split(src + p.a0, na, src + p.a1, nb, d);
+}
+
+__global__ void __launch_bounds__(BLOCK) k_merge_round_tiles(const u64* __restrict__ sk,
+                                                             const u32* __restrict__ sr,
+                                                             const MergePair* __restrict__ pr,
+                                                             u32 n_pairs,
+                                                             const u64* __restrict__ split,
+                                                             u64* __restrict__ dk,
+                                                             u32* __restrict__ dr) {
+  __shared__ MergeSmem sm;
+  const u64 b = blockIdx.x;
+  const u32 q = last_le(n_pairs, b, [&](u32 i) { return pr[i].t0; });
+  const MergePair p = pr[q];
+  merge_tile(sm, sk + p.a0, sr + p.a0, p.a1 - p.a0, sk + p.a1, sr + p.a1, p.b1 - p.a1,
+             split + p.t0 + q + (b - p.t0), b - p.t0, dk + p.a0, dr + p.a0);
 }
 
 __global__ void __launch_bounds__(BLOCK) k_copy_kpa(const u64* __restrict__ k, const u32* __restrict__ r,
@@ -157,14 +228,20 @@ kpa_status kpa_merge_runs_workspace_size(uint64_t n, size_t* bytes) {
   Carver c(nullptr);
   c.take<u64>(n);
   c.take<u32>(n);
-  c.take<u64>(ceil_div(n, TILE) + 2);
+  c.take<u64>(ceil_div(n, TILE) + 2 + 2 * (u64)MR_PLAN_RUNS);
+  c.take<MergePair>(MR_PLAN_DESC);
   *bytes = c.used + 256;
   return KPA_OK;
 }
 
 // Pairwise rounds: runs 2k and 2k+1 merge into run k of the next round (an
 // unpaired last run is carried over), alternating between the caller's arrays
-// and a workspace copy; the last round writes the output.
+// and a workspace copy; the last round writes the output.  Empty runs are
+// dropped first.  Up to MR_PLAN_RUNS runs, every round is one split launch
+// and one tile launch over all of its pairs, whose descriptors are planned on
+// the host and copied into the workspace by kernel arguments (so the call
+// holds no host-to-device copy and can be captured); beyond that, each pair
+// is merged by its own launches.
 kpa_status kpa_merge_runs(uint64_t* keys, uint32_t* rids, const uint64_t* run_off, uint32_t n_runs,
                           uint64_t* out_keys, uint32_t* out_rids, void* ws, size_t ws_bytes,
                           hipStream_t stream) {
@@ -183,41 +260,72 @@ kpa_status kpa_merge_runs(uint64_t* keys, uint32_t* rids, const uint64_t* run_of
   Carver c(ws);
   u64* tk = c.take<u64>(n);
   u32* tr = c.take<u32>(n);
-  u64* split = c.take<u64>(ceil_div(n, TILE) + 2);
+  u64* split = c.take<u64>(ceil_div(n, TILE) + 2 + 2 * (u64)MR_PLAN_RUNS);
+  MergePair* desc = c.take<MergePair>(MR_PLAN_DESC);
   const u64 base = run_off[0];
-  std::vector<u64> off(run_off, run_off + n_runs + 1);
-  for (auto& o : off) o -= base;
+  std::vector<u64> off{0};
+  for (u32 r = 0; r < n_runs; ++r)
+    if (run_off[r + 1] > run_off[r]) off.push_back(run_off[r + 1] - base);
   u64* ck = keys + base;
   u32* cr = rids + base;
-  if (n_runs == 1) {
+  if (off.size() == 2) {
     KPA_LAUNCH("copy_kpa", k_copy_kpa, dim3((u32)std::min<u64>(ceil_div(n, BLOCK), 8192)),
                dim3(BLOCK), 0, stream, ck, cr, n, out_keys, out_rids);
     return KPA_OK;
+  }
+  const bool planned = off.size() - 1 <= MR_PLAN_RUNS;
+  // Rounds on the host: each round's pairs and its output tiles.
+  struct Round {
+    u64 first, pairs, tiles;
+  };
+  std::vector<MergePair> pairs;
+  std::vector<Round> rounds;
+  for (std::vector<u64> o = off; o.size() > 2;) {
+    const size_t runs = o.size() - 1;
+    Round rd{pairs.size(), 0, 0};
+    std::vector<u64> next{0};
+    for (size_t p = 0; p < runs; p += 2) {
+      const u64 b1 = p + 1 < runs ? o[p + 2] : o[p + 1];
+      pairs.push_back(MergePair{o[p], o[p + 1], b1, rd.tiles});
+      rd.tiles += ceil_div(b1 - o[p], TILE);
+      next.push_back(b1);
+    }
+    rd.pairs = pairs.size() - rd.first;
+    rounds.push_back(rd);
+    o.swap(next);
+  }
+  if (planned) {
+    for (size_t i = 0; i < pairs.size(); i += PAIR_CHUNK) {
+      PairChunk chunk;
+      const u32 cnt = (u32)std::min<size_t>(PAIR_CHUNK, pairs.size() - i);
+      for (u32 j = 0; j < cnt; ++j) chunk.p[j] = pairs[i + j];
+      KPA_LAUNCH("merge_desc", k_merge_desc, dim3(1), dim3(PAIR_CHUNK), 0, stream, chunk, cnt,
+                 desc + i);
+    }
   }
   // buffers: current source, and the next destination
   u64* src_k = ck;
   u32* src_r = cr;
   bool src_is_ws = false;
-  while (off.size() > 2) {
-    const size_t runs = off.size() - 1;
-    const bool last = runs <= 2;
+  for (size_t ri = 0; ri < rounds.size(); ++ri) {
+    const Round& rd = rounds[ri];
+    const bool last = ri + 1 == rounds.size();
     u64* dst_k = last ? out_keys : (src_is_ws ? ck : tk);
     u32* dst_r = last ? out_rids : (src_is_ws ? cr : tr);
-    std::vector<u64> next{0};
-    for (size_t p = 0; p < runs; p += 2) {
-      const u64 a0 = off[p], a1 = off[p + 1];
-      if (p + 1 < runs) {
-        const u64 b1 = off[p + 2];
-        KPA_CHECK(merge_launch(src_k + a0, src_r + a0, a1 - a0, src_k + a1, src_r + a1, b1 - a1,
-                               dst_k + a0, dst_r + a0, split, stream));
-        next.push_back(b1);
-      } else {
-        KPA_LAUNCH("copy_kpa", k_copy_kpa, dim3((u32)std::min<u64>(ceil_div(a1 - a0, BLOCK), 8192)),
-                   dim3(BLOCK), 0, stream, src_k + a0, src_r + a0, a1 - a0, dst_k + a0, dst_r + a0);
-        next.push_back(a1);
+    if (planned) {
+      const u64 bounds = rd.tiles + rd.pairs;
+      KPA_LAUNCH("merge_splits", k_merge_round_splits, dim3((u32)ceil_div(bounds, BLOCK)),
+                 dim3(BLOCK), 0, stream, src_k, desc + rd.first, (u32)rd.pairs, bounds, split);
+      KPA_LAUNCH("merge_tiles", k_merge_round_tiles, dim3((u32)rd.tiles), dim3(BLOCK), 0, stream,
+                 src_k, src_r, desc + rd.first, (u32)rd.pairs, split, dst_k, dst_r);
+    } else {
+      for (u64 q = rd.first; q < rd.first + rd.pairs; ++q) {
+        const MergePair& p = pairs[q];
+        KPA_CHECK(merge_launch(src_k + p.a0, src_r + p.a0, p.a1 - p.a0, src_k + p.a1,
+                               src_r + p.a1, p.b1 - p.a1, dst_k + p.a0, dst_r + p.a0, split,
+                               stream));
       }
     }
-    off.swap(next);
     src_k = dst_k;
     src_r = dst_r;
     src_is_ws = !src_is_ws;

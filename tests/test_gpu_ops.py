@@ -38,25 +38,34 @@ def test_merge(K, orc, na, nb):
     assert np.array_equal(u64(ok)[:na + nb], ek) and np.array_equal(u32(orr)[:na + nb], er)
 
 
-@pytest.mark.parametrize("sizes", [[10], [3, 0, 9], [4096] * 7, [0, 50000, 1, 0, 7777, 30000, 2],
-                                   [1000] * 16])
-def test_merge_runs(K, orc, sizes):
-    rng = np.random.default_rng(len(sizes))
-    ks, rs = [], []
+MANY_RUNS = [int(x) for x in np.random.default_rng(11).integers(0, 9000, 300)]
+
+
+# Up to 1024 nonempty runs every round is one launch pair over all its pairs;
+# 1100 runs take the per-pair launches.  lead: entries before the first run
+# (run_off[0] > 0).
+@pytest.mark.parametrize("sizes,lead", [([10], 0), ([3, 0, 9], 0), ([4096] * 7, 0),
+                                        ([0, 50000, 1, 0, 7777, 30000, 2], 0), ([1000] * 16, 0),
+                                        ([5000, 4096, 4097, 1, 8191, 8193, 0, 12288], 13),
+                                        (MANY_RUNS, 0), ([1] * 300, 5), ([3] * 1100, 0),
+                                        ([0, 0, 6000, 0], 7)])
+def test_merge_runs(K, orc, sizes, lead):
+    rng = np.random.default_rng(len(sizes) + lead)
+    ks, rs = [rng.integers(0, 1 << 63, lead, dtype=np.uint64)], [np.zeros(lead, np.uint32)]
     base = 0
     for s in sizes:
         k, r = sorted_kpa(orc, rng, s, 200, base)
         ks.append(k)
         rs.append(r)
         base += s
-    keys = np.concatenate(ks) if ks else np.zeros(0, np.uint64)
-    rids = np.concatenate(rs) if rs else np.zeros(0, np.uint32)
-    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
-    say(f"merge_runs {sizes}")
+    keys = np.concatenate(ks)
+    rids = np.concatenate(rs)
+    off = (lead + np.concatenate([[0], np.cumsum(sizes)])).astype(np.uint64)
+    say(f"merge_runs {len(sizes)} runs, {base} entries, lead {lead}")
     ok, orr = K.kpa_merge_runs(dev_u64(keys), dev_u32(rids), off.tolist())
     torch.cuda.synchronize()
-    ek, er = orc.sort(keys, rids)   # stable: equal keys keep run order
-    n = int(off[-1])
+    ek, er = orc.sort(keys[lead:], rids[lead:])   # stable: equal keys keep run order
+    n = base
     assert np.array_equal(u64(ok)[:n], ek) and np.array_equal(u32(orr)[:n], er)
 
 
