@@ -117,7 +117,10 @@ TRAFFIC = {
     ("c2", "learned_scatter"): ("c2_learned_hbm_bytes.md", "k_ds_pass<LearnedDF>",
                                 ("onesweep.hpp", "digit_sort.hpp", "learned.hip",
                                  "learned_internal.hpp")),
-    ("c4", "reduce_main"): ("c4_reduce_hbm_bytes.md", "k_reduce_main",
+    ("c4", "learned_scatter"): ("c4_learned_hbm_bytes.md", "k_ds_pass<LearnedDF, true>",
+                                ("onesweep.hpp", "digit_sort.hpp", "learned.hip",
+                                 "learned_internal.hpp")),
+    ("c4", "reduce_main"): ("c4_reduce_hbm_bytes.md", "k_reduce_main_seq<false>",
                             ("reduce.hip", "reduce_internal.hpp")),
 }
 

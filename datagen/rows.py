@@ -273,13 +273,10 @@ def gen_c4_window(j: int, epoch: int, n: int, seed: int = 4, device="cpu",
     o = (j << 40) + (epoch << 26)
     if out is None:
         out = torch.empty((n, 4), dtype=torch.int64, device=dev)
-    if control:
-        out[:, 0] = o + _srl(mix64(r), 32)
-    else:
-        out[:, 0] = o + (r - 1) * (1 << 12)
-    out[:, 1] = _srl(splitmix64(sseed, 2, i), 44)
-    out[:, 2] = (i * 10 ** 9) // max(n, 1)
-    out[:, 3] = mix64(i)
+    key = o + _srl(mix64(r), 32) if control else o + (r - 1) * (1 << 12)
+    # one interleaving write (no strided column copies)
+    torch.stack([key, _srl(splitmix64(sseed, 2, i), 44), (i * 10 ** 9) // max(n, 1), mix64(i)],
+                dim=1, out=out)
     return out
 
 
