@@ -14,6 +14,8 @@
 // 2^64), so the result does not depend on how the work is split.
 #include <mutex>
 
+#include <type_traits>
+
 #include "reduce_internal.hpp"
 
 namespace kpa {
@@ -281,11 +283,14 @@ __global__ void __launch_bounds__(BLOCK) k_reduce_main(
   u32 hmask = 0, tmask = 0;
   u64 before = tid == 0 ? prev : (tid * ITEMS - 1 < tr.cnt ? sk[pidx(tid * ITEMS - 1)] : 0ull);
   const bool lead_has_prev = tid == 0 ? has_prev : true;
+  u64 kr[ITEMS];  // the thread's keys (sk is reused for the outputs below)
 #pragma unroll
   for (int j = 0; j < ITEMS; ++j) {
     const u32 idx = tid * ITEMS + j;
+    kr[j] = 0ull;
     if (idx < tr.cnt) {
       const u64 k = sk[pidx(idx)];
+      kr[j] = k;
       const bool h = j == 0 ? (!lead_has_prev || k != before) : (k != before);
       const bool last = idx + 1 == tr.cnt;
       const u64 after = last ? next : sk[pidx(idx + 1)];
@@ -305,36 +310,45 @@ __global__ void __launch_bounds__(BLOCK) k_reduce_main(
   const u32 hex = block_excl_sum((u32)__popc(hmask), hsm, &htot);
   SegAgg run = block_excl_segscan<WAVES>(A, seg_identity(), wsm);
   const u64 gb = gbase[tile];
-  u32 hs = hex;
+  // Group columns gathered in LDS one at a time and written contiguously (as
+  // in k_reduce_main_seq); sk is free: the scans above end with barriers.
+  const bool last_goes_on = has_next && tr.cnt && keys[tr.base + tr.cnt - 1] == next;
+  const u32 nfull = htot - (last_goes_on && htot ? 1u : 0u);
+  const SegAgg run0 = run;
+  auto column = [&](auto fc, u64* __restrict__ out) {
+    constexpr int F = decltype(fc)::value;
+    SegAgg r = run0;
+    u32 hs = hex;
 #pragma unroll
-  for (int j = 0; j < ITEMS; ++j) {
-    const u32 idx = tid * ITEMS + j;
-    if (idx < tr.cnt) {
-      const u32 h = (hmask >> j) & 1u;
-      run = seg_combine(run, SegAgg{h, 1ull, v[j], v[j], tr.base + idx});
-      hs += h;
-      const bool t = (tmask >> j) & 1u;
-      const bool cont = idx + 1 == tr.cnt && !t;  // the run goes on in the next tile
-      if (t || cont) {
-        const u64 gi = gb + hs - 1;
-        if (run.f && t) {  // the whole run lies in this tile
-          o_key[gi] = sk[pidx(idx)];
-          if (o_cnt) o_cnt[gi] = run.c;
-          if (o_sum) o_sum[gi] = run.s;
-          if (o_max) o_max[gi] = run.m;
-          if (o_start) o_start[gi] = run.hp;
-        } else {
-          if (run.f) {
-            o_key[gi] = sk[pidx(idx)];
-            if (o_start) o_start[gi] = run.hp;
+    for (int j = 0; j < ITEMS; ++j) {
+      const u32 idx = tid * ITEMS + j;
+      if (idx < tr.cnt) {
+        const u32 h = (hmask >> j) & 1u;
+        r = seg_combine(r, SegAgg{h, 1ull, v[j], v[j], tr.base + idx});
+        hs += h;
+        const bool t = (tmask >> j) & 1u;
+        const bool cont = idx + 1 == tr.cnt && !t;  // the run goes on in the next tile
+        if (t || cont) {
+          if (r.f) sk[hs - 1] = F == 0 ? kr[j] : F == 1 ? r.c : F == 2 ? r.s : F == 3 ? r.m : r.hp;
+          if (F == 0 && !(r.f && t)) {
+            const u64 gi = gb + hs - 1;
+            if (o_cnt) atomicAdd(reinterpret_cast<unsigned long long*>(o_cnt + gi), r.c);
+            if (o_sum) atomicAdd(reinterpret_cast<unsigned long long*>(o_sum + gi), r.s);
+            if (o_max) atomicMax(reinterpret_cast<unsigned long long*>(o_max + gi), r.m);
           }
-          if (o_cnt) atomicAdd(reinterpret_cast<unsigned long long*>(o_cnt + gi), run.c);
-          if (o_sum) atomicAdd(reinterpret_cast<unsigned long long*>(o_sum + gi), run.s);
-          if (o_max) atomicMax(reinterpret_cast<unsigned long long*>(o_max + gi), run.m);
         }
       }
     }
-  }
+    __syncthreads();
+    const u32 lim = (F == 0 || F == 4) ? htot : nfull;
+    for (u32 i = tid; i < lim; i += BLOCK) out[gb + i] = sk[i];
+    __syncthreads();
+  };
+  column(std::integral_constant<int, 0>(), o_key);
+  if (o_cnt) column(std::integral_constant<int, 1>(), o_cnt);
+  if (o_sum) column(std::integral_constant<int, 2>(), o_sum);
+  if (o_max) column(std::integral_constant<int, 3>(), o_max);
+  if (o_start) column(std::integral_constant<int, 4>(), o_start);
 }
 
 // ---- pass 3 when the values are already in KPA order (8-byte values, row
@@ -407,7 +421,7 @@ __device__ __forceinline__ RunAgg<START> wave_incl_runscan(RunAgg<START> x) {
 }
 
 template <bool START>
-__global__ void __launch_bounds__(BLOCK) k_reduce_main_seq(
+__global__ void __launch_bounds__(BLOCK, 4) k_reduce_main_seq(
     const u64* __restrict__ keys, const u64* __restrict__ vals, const u64* __restrict__ seg_off,
     const u32* __restrict__ tile_start, const u32* __restrict__ tile_seg, u32 n_seg,
     const u64* __restrict__ gbase, u64* __restrict__ o_key, u64* __restrict__ o_cnt,
@@ -496,36 +510,55 @@ __global__ void __launch_bounds__(BLOCK) k_reduce_main_seq(
   for (u32 i = 0; i < w; ++i) run = run_combine(run, wsm[i]);
   run = run_combine(run, ex);
   const u64 gb = gbase[tile];
-  u32 hs = hex;
+  // The groups that start in the tile are gb + [0, htot).  Their columns are
+  // gathered in LDS one at a time (st is free again: every thread has read
+  // its entries before the barriers above), each by a walk over the thread's
+  // entries, and written out contiguously: stores of single 8-byte words
+  // from the lanes that end runs reach memory as separate partial writes.
+  // A run that goes on into the next tile holds the tile's last group; its
+  // count, sum and maximum are accumulated with atomics (here and in the
+  // next tiles) onto the zeros the scan pass left there, as are those of a
+  // run that began in an earlier tile.
+  const bool last_goes_on = has_next && tr.cnt && keys[tr.base + tr.cnt - 1] == next;
+  const u32 nfull = htot - (last_goes_on && htot ? 1u : 0u);
+  const RunAgg<START> run0 = run;
+  // column F (0 key, 1 count, 2 sum, 3 max, 4 start) into `out`; the walk of
+  // column 0 also issues the atomics, and the keys are dead after it
+  auto column = [&](auto fc, u64* __restrict__ out) {
+    constexpr int F = decltype(fc)::value;
+    RunAgg<START> r = run0;
+    u32 hs = hex;
 #pragma unroll
-  for (int j = 0; j < ITEMS; ++j) {
-    const u32 idx = tid * ITEMS + j;
-    if (idx < tr.cnt) {
-      const u32 h = (hmask >> j) & 1u;
-      run = run_combine(run, RunAgg<START>{h, 1u, v[j], v[j], tr.base + idx});
-      hs += h;
-      const bool t = (tmask >> j) & 1u;
-      const bool cont = idx + 1 == tr.cnt && !t;  // the run goes on in the next tile
-      if (t || cont) {
-        const u64 gi = gb + hs - 1;
-        if (run.f && t) {  // the whole run lies in this tile
-          o_key[gi] = k[j];
-          if (o_cnt) o_cnt[gi] = run.c;
-          if (o_sum) o_sum[gi] = run.s;
-          if (o_max) o_max[gi] = run.m;
-          if (START) o_start[gi] = run.hp;
-        } else {
-          if (run.f) {
-            o_key[gi] = k[j];
-            if (START) o_start[gi] = run.hp;
+    for (int j = 0; j < ITEMS; ++j) {
+      const u32 idx = tid * ITEMS + j;
+      if (idx < tr.cnt) {
+        const u32 h = (hmask >> j) & 1u;
+        r = run_combine(r, RunAgg<START>{h, 1u, v[j], v[j], tr.base + idx});
+        hs += h;
+        const bool t = (tmask >> j) & 1u;
+        const bool cont = idx + 1 == tr.cnt && !t;  // the run goes on in the next tile
+        if (t || cont) {
+          if (r.f)
+            st[hs - 1] = F == 0 ? k[j] : F == 1 ? (u64)r.c : F == 2 ? r.s : F == 3 ? r.m : r.hp;
+          if (F == 0 && !(r.f && t)) {
+            const u64 gi = gb + hs - 1;
+            if (o_cnt) atomicAdd(reinterpret_cast<unsigned long long*>(o_cnt + gi), (u64)r.c);
+            if (o_sum) atomicAdd(reinterpret_cast<unsigned long long*>(o_sum + gi), r.s);
+            if (o_max) atomicMax(reinterpret_cast<unsigned long long*>(o_max + gi), r.m);
           }
-          if (o_cnt) atomicAdd(reinterpret_cast<unsigned long long*>(o_cnt + gi), (u64)run.c);
-          if (o_sum) atomicAdd(reinterpret_cast<unsigned long long*>(o_sum + gi), run.s);
-          if (o_max) atomicMax(reinterpret_cast<unsigned long long*>(o_max + gi), run.m);
         }
       }
     }
-  }
+    __syncthreads();
+    const u32 lim = (F == 0 || F == 4) ? htot : nfull;
+    for (u32 i = tid; i < lim; i += BLOCK) out[gb + i] = st[i];
+    __syncthreads();
+  };
+  column(std::integral_constant<int, 0>(), o_key);
+  if (o_cnt) column(std::integral_constant<int, 1>(), o_cnt);
+  if (o_sum) column(std::integral_constant<int, 2>(), o_sum);
+  if (o_max) column(std::integral_constant<int, 3>(), o_max);
+  if (START) column(std::integral_constant<int, 4>(), o_start);
 }
 
 kpa_status launch_tile_scan(const u32* counts, const u32* tile_start, const u32* tile_seg,

@@ -171,16 +171,20 @@ def test_reduce_reads_carried_values_in_order(K, orc):
         assert np.array_equal(u64(g["max"])[g0:g1], em), s
 
 
-def test_reduce_in_order_group_starts_and_row_layouts(K, orc):
+# rep: entries per key.  7: a few hundred groups per 4096-entry tile (group
+# columns gathered on chip); 1: a group per entry (written directly); 3000:
+# runs across tile edges, tiles of one or two groups.
+@pytest.mark.parametrize("rep", [7, 1, 3000])
+def test_reduce_in_order_group_starts_and_row_layouts(K, orc, rep):
     """Row ids NULL with group starts wanted (the scan also carries each run's
     first index), and with 32-byte rows already in KPA order (the general
     path: entry i reads row i)."""
     from datagen.rows import LAYOUT32
-    rng = np.random.default_rng(77)
+    rng = np.random.default_rng(77 + rep)
     sizes = [5000, 1, 0, 4096, 4097, 70_000, 12_289]
     n = sum(sizes)
     off = seg_offsets(sizes)
-    keys = np.repeat(rng.integers(0, 1 << 63, size=n // 7 + 1, dtype=np.uint64), 7)[:n]
+    keys = np.repeat(rng.integers(0, 1 << 63, size=n // rep + 1, dtype=np.uint64), rep)[:n]
     keys = keys[rng.permutation(n)]
     rows = np.zeros((n, 4), np.uint64)
     rows[:, 0] = keys
@@ -195,15 +199,17 @@ def test_reduce_in_order_group_starts_and_row_layouts(K, orc):
     gkey2, g2, gseg2 = K.kpa_reduce_by_key(
         dev_u64(sk), None, d_off,
         torch.from_numpy(srows.view(np.int64)).to("cuda"), LAYOUT32, n_cap=n)
+    gkey3, g3, gseg3 = K.kpa_reduce_by_key(dev_u64(sk), None, d_off, dev_u64(svals), VALUE_ROWS,
+                                           n_cap=n)      # without group starts
     torch.cuda.synchronize()
     gs = u64(gseg)
-    assert np.array_equal(gs, u64(gseg2))
+    assert np.array_equal(gs, u64(gseg2)) and np.array_equal(gs, u64(gseg3))
     for s in range(len(sizes)):
         a, b = int(off[s]), int(off[s + 1])
         ek, ec, es, em = orc.reduce_by_key(sk[a:b], sr[a:b], rows, LAYOUT32)
         heads = a + np.flatnonzero(np.r_[True, sk[a + 1:b] != sk[a:b - 1]]) if b > a else []
         g0, g1 = int(gs[s]), int(gs[s + 1])
-        for gk_, gg in ((gkey, g), (gkey2, g2)):
+        for gk_, gg in ((gkey, g), (gkey2, g2), (gkey3, g3)):
             assert np.array_equal(u64(gk_)[g0:g1], ek), s
             assert np.array_equal(u64(gg["cnt"])[g0:g1], ec), s
             assert np.array_equal(u64(gg["sum"])[g0:g1], es), s
