@@ -155,15 +155,68 @@ __device__ __forceinline__ u32 find_seg(const u32* tile_start, u32 n_seg, u32 t)
 // sign-extends (a 64-bit index assembled from two halves stays unsigned).
 __device__ __forceinline__ u32 first_lane(u32 v) { return (u32)__builtin_amdgcn_readfirstlane(v); }
 
+// DPP lane moves (GFX9 encodings): row_shr:n shifts within rows of 16
+// lanes, row_bcast:15 / row_bcast:31 broadcast lane 15 / 31 of the rows
+// below into the rows that row_mask selects, wave_shr:1 shifts the whole
+// wave by one lane.  Lanes without a source (or outside row_mask) keep `old`.
+// A DPP move reads another lane's register directly, with no trip through
+// LDS as a shuffle takes.
+constexpr int DPP_ROW_SHR = 0x110, DPP_BCAST15 = 0x142, DPP_BCAST31 = 0x143, DPP_WAVE_SHR1 = 0x138;
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ u32 dpp32(u32 old, u32 v) {
+  return (u32)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROW_MASK, 0xF, false);
+}
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ u64 dpp64(u64 old, u64 v) {
+  const u32 lo = dpp32<CTRL, ROW_MASK>((u32)old, (u32)v);
+  const u32 hi = dpp32<CTRL, ROW_MASK>((u32)(old >> 32), (u32)(v >> 32));
+  return ((u64)hi << 32) | lo;
+}
+template <int CTRL, int ROW_MASK, class T>
+__device__ __forceinline__ T dpp_move(T old, T v) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit lanes");
+  if constexpr (sizeof(T) == 8)
+    return (T)dpp64<CTRL, ROW_MASK>((u64)old, (u64)v);
+  else
+    return (T)dpp32<CTRL, ROW_MASK>((u32)old, (u32)v);
+}
+
+// Inclusive scan over the wave (Hillis-Steele within rows of 16 lanes, then
+// the two row broadcasts): lane l gets op over lanes 0..l, op(earlier, later)
+// associative with identity e.  Every lane of the wave must be active.
+template <class T, class Op>
+__device__ __forceinline__ T wave_incl_scan(T v, T e, Op op) {
+  v = op(dpp_move<DPP_ROW_SHR + 1, 0xF>(e, v), v);
+  v = op(dpp_move<DPP_ROW_SHR + 2, 0xF>(e, v), v);
+  v = op(dpp_move<DPP_ROW_SHR + 4, 0xF>(e, v), v);
+  v = op(dpp_move<DPP_ROW_SHR + 8, 0xF>(e, v), v);
+  v = op(dpp_move<DPP_BCAST15, 0xA>(e, v), v);
+  v = op(dpp_move<DPP_BCAST31, 0xC>(e, v), v);
+  return v;
+}
+
+// Lane 63's value, the same in every lane (a scalar read).
+template <class T>
+__device__ __forceinline__ T lane63(T v) {
+  if constexpr (sizeof(T) == 8) {
+    const u32 lo = (u32)__builtin_amdgcn_readlane((int)(u32)(u64)v, 63);
+    const u32 hi = (u32)__builtin_amdgcn_readlane((int)(u32)((u64)v >> 32), 63);
+    return (T)(((u64)hi << 32) | lo);
+  } else {
+    return (T)(u32)__builtin_amdgcn_readlane((int)(u32)v, 63);
+  }
+}
+
+// op over the whole wave, in every lane.  Every lane must be active.
+template <class T, class Op>
+__device__ __forceinline__ T wave_reduce(T v, T e, Op op) {
+  return lane63(wave_incl_scan(v, e, op));
+}
+
 // Wave-wide inclusive sum of u32.
 __device__ __forceinline__ u32 wave_incl_sum(u32 v) {
-  u32 l = __lane_id();
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    u32 t = __shfl_up(v, o, 64);
-    if (l >= (u32)o) v += t;
-  }
-  return v;
+  return wave_incl_scan(v, 0u, [](u32 a, u32 b) { return a + b; });
 }
 
 // Block-wide exclusive sum of one u32 per thread (NW waves of 64 threads);

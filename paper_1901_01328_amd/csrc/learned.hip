@@ -405,13 +405,9 @@ __device__ u32 lds_sort_model(FinishSmem& sm, const SegModel& m, u32 mcount) {
     inv = inv || (i > 0 && k < sm.skeys[i - 1]);
   }
   // one block reduction of all four (a single barrier)
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    vor |= __shfl_xor(vor, o, 64);
-    vand &= __shfl_xor(vand, o, 64);
-    const u32 r2 = __shfl_xor(rmax, o, 64);
-    rmax = r2 > rmax ? r2 : rmax;
-  }
+  vor = wave_reduce(vor, (u64)0, [](u64 x, u64 y) { return x | y; });
+  vand = wave_reduce(vand, ~(u64)0, [](u64 x, u64 y) { return x & y; });
+  rmax = wave_reduce(rmax, 0u, [](u32 x, u32 y) { return x > y ? x : y; });
   const bool winv = ballot(inv) != 0;
   if (__lane_id() == 0) {
     sm.red64[w] = vor;
@@ -494,15 +490,10 @@ __device__ u32 lds_sort_model(FinishSmem& sm, const SegModel& m, u32 mcount) {
     lastm |= (u32)la << j;
     invm |= (u32)inv << j;
     // run start of position i: max start position <= i (wave scan + carry)
-    u32 v = st ? i : 0u;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const u32 t = __shfl_up(v, o, 64);
-      if (lane >= (u32)o) v = t > v ? t : v;
-    }
+    u32 v = wave_incl_scan(st ? i : 0u, 0u, [](u32 x, u32 y) { return x > y ? x : y; });
     v = carry > v ? carry : v;
     rs[j] = v;
-    carry = __shfl(v, 63, 64);
+    carry = lane63(v);
   }
   // earlier waves' last run start
   sm.red[w] = carry;

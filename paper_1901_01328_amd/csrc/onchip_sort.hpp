@@ -10,11 +10,7 @@ namespace kpa {
 // Block-wide reductions over NW waves (sm: NW u32, resp. 2*NW u64).
 template <int NW = WAVES>
 __device__ __forceinline__ u32 block_min_u32(u32 v, u32* sm) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const u32 t = __shfl_xor(v, o, 64);
-    v = t < v ? t : v;
-  }
+  v = wave_reduce(v, 0xFFFFFFFFu, [](u32 a, u32 b) { return a < b ? a : b; });
   __syncthreads();
   if (__lane_id() == 0) sm[threadIdx.x >> 6] = v;
   __syncthreads();
@@ -26,11 +22,8 @@ __device__ __forceinline__ u32 block_min_u32(u32 v, u32* sm) {
 
 template <int NW = WAVES>
 __device__ __forceinline__ void block_or_and(u64& o, u64& a, u64* sm) {
-#pragma unroll
-  for (int s = 32; s > 0; s >>= 1) {
-    o |= __shfl_xor(o, s, 64);
-    a &= __shfl_xor(a, s, 64);
-  }
+  o = wave_reduce(o, (u64)0, [](u64 x, u64 y) { return x | y; });
+  a = wave_reduce(a, ~(u64)0, [](u64 x, u64 y) { return x & y; });
   __syncthreads();
   if (__lane_id() == 0) {
     sm[threadIdx.x >> 6] = o;

@@ -378,22 +378,6 @@ __device__ __forceinline__ RunAgg<START> run_combine(const RunAgg<START>& a,
   return r;
 }
 
-// DPP lane moves (GFX9 encodings): row_shr:n shifts within rows of 16
-// lanes, row_bcast:15 / row_bcast:31 broadcast lane 15 / 31 of the rows
-// below into the rows that row_mask selects, wave_shr:1 shifts the whole
-// wave by one lane.  Lanes without a source (or outside row_mask) keep `old`.
-constexpr int DPP_ROW_SHR = 0x110, DPP_BCAST15 = 0x142, DPP_BCAST31 = 0x143, DPP_WAVE_SHR1 = 0x138;
-
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ u32 dpp32(u32 old, u32 v) {
-  return (u32)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROW_MASK, 0xF, false);
-}
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ u64 dpp64(u64 old, u64 v) {
-  const u32 lo = dpp32<CTRL, ROW_MASK>((u32)old, (u32)v);
-  const u32 hi = dpp32<CTRL, ROW_MASK>((u32)(old >> 32), (u32)(v >> 32));
-  return ((u64)hi << 32) | lo;
-}
 // The aggregate of the lane that the DPP control selects (identity where none).
 template <int CTRL, int ROW_MASK, bool START>
 __device__ __forceinline__ RunAgg<START> dpp_agg(const RunAgg<START>& a) {
