@@ -828,8 +828,35 @@ __device__ __forceinline__ void finish_stretch(
   if (tid == 0) stat_add(stats, res == CH_EQUAL ? ST_EQUAL : ST_ONCHIP, mcount);
   if (res != CH_MOVED) return;
   if (VALS) {
+    // The chunk's row ids and values are loaded into registers (entry
+    // tid + j*FIN_THREADS in slot j) while the sorted keys are written, then
+    // go through the free LDS areas into the new order.
+    constexpr int PF = (int)(FCAP / FIN_THREADS);
+    static_assert(FCAP % FIN_THREADS == 0, "a chunk spreads evenly over the threads");
+    u64 pv[PF];
+    u32 pr[PF];
+#pragma unroll
+    for (int j = 0; j < PF; ++j) {
+      const u32 i = tid + j * FIN_THREADS;
+      pv[j] = i < mcount ? vals[start + i] : 0ull;
+      pr[j] = i < mcount ? rids[start + i] : 0u;
+    }
     for (u32 i = tid; i < mcount; i += FIN_THREADS) keys[start + i] = sm.skeys[i];
-    permute_rids_vals(sm, rids, vals, start, mcount);
+    __syncthreads();  // every thread has read the sorted keys
+#pragma unroll
+    for (int j = 0; j < PF; ++j) {
+      const u32 i = tid + j * FIN_THREADS;
+      if (i < mcount) {
+        sm.skeys[i] = pv[j];
+        sm.srel[i] = pr[j];
+      }
+    }
+    __syncthreads();
+    for (u32 i = tid; i < mcount; i += FIN_THREADS) {
+      const u32 o = sm.srids[i];  // old position of the entry now at i
+      vals[start + i] = sm.skeys[o];
+      rids[start + i] = sm.srel[o];
+    }
     return;
   }
   for (u32 i = tid; i < mcount; i += FIN_THREADS) {
