@@ -47,7 +47,7 @@ PASS_BYTES = {
     "reduce_main": 20,      # read key+rid, gather 8-byte value
     "extract": 48,          # read 32-byte row, write key+value (the sort takes positions as rids)
     "learned_scatter": 24,  # read key+rid, write key+rid (entries of large windows)
-    "learned_finish": 24,   # read key+rid, write key+rid (entries of large windows)
+    "learned_finish": 24,   # read key+rid, write key+rid (entries finished on chip)
     "learned_hist": 8,      # read key (entries of large windows)
 }
 # The same passes when the sort carries the staged value column beside the
@@ -185,11 +185,13 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def kernel_passes(K, steps, n, pass_bytes, n_large=None, extra=None):
+def kernel_passes(K, steps, n, pass_bytes, n_large=None, extra=None, entries=None):
     """Per-kernel launches per step, mean ms and algorithmic GB/s (recorded
     with events on each launch's own stream since the last profile enable).
     extra: bytes per launch added to a kernel's per-entry bytes (the keyed
-    reduction's group outputs)."""
+    reduction's group outputs).  entries: per-launch entry counts that
+    replace n (the finishing pass works only on the entries of the chunks it
+    sorts on chip: kpa_sort_stats.finished_on_chip)."""
     K.kpa_profile_collect()
     passes = {}
     for name in K.kpa_profile_names():
@@ -200,6 +202,7 @@ def kernel_passes(K, steps, n, pass_bytes, n_large=None, extra=None):
         entry = {"launches_per_step": cnt / steps, "avg_ms": round(avg, 4)}
         if name in pass_bytes and name != "radix_pass":
             m = n_large if (name in LARGE_ONLY and n_large is not None) else n
+            m = (entries or {}).get(name, m)
             gbs = (pass_bytes[name] * m + (extra or {}).get(name, 0)) / (avg / 1000.0) / 1e9
             entry["alg_GBps"] = round(gbs, 1)
             entry["hbm_frac"] = round(gbs / HBM_PEAK_GBS, 4)
@@ -333,11 +336,12 @@ def bench_c4(a):
         table = PASS_BYTES_KV if r == "learned" else PASS_BYTES
         G = int(pipe.gseg[-1].item())
         res[r]["groups_total"] = G
+        res[r]["sort_stats"] = pipe.stats.cpu().numpy().tolist()
         res[r]["passes"] = kernel_passes(K, prof_steps, n, table,
                                          n_large=int(sizes[sizes > cfgs[r].mid_cap].sum()),
-                                         extra={"reduce_main": GROUP_BYTES * G})
+                                         extra={"reduce_main": GROUP_BYTES * G},
+                                         entries={"learned_finish": res[r]["sort_stats"][1]})
         K.kpa_profile_enable(False)
-        res[r]["sort_stats"] = pipe.stats.cpu().numpy().tolist()
         # outputs of this route: whole-array digests, and the sampled windows' groups
         stream.synchronize()
         G = int(pipe.gseg[-1].item())
@@ -653,7 +657,8 @@ def bench_c2(a):
     for _ in range(prof_steps):
         pipe.step(rows)
     torch.cuda.synchronize()
-    passes = kernel_passes(K, prof_steps, n, PASS_BYTES)
+    onchip = int(pipe.stats.cpu()[1]) if a.algo == "learned" else 0
+    passes = kernel_passes(K, prof_steps, n, PASS_BYTES, entries={"learned_finish": onchip})
     K.kpa_profile_enable(False)
 
     # Active radix passes: digits that vary inside a window
