@@ -115,3 +115,87 @@ def test_c4_autotuned_config_same_output(K, orc):
     sk, sr, groups = oracle_windows(orc, rows.cpu(), sizes)
     assert np.array_equal(u64(pipe.skeys)[:n], sk) and np.array_equal(u32(pipe.srids)[:n], sr)
     check_groups(pipe, groups, sizes)
+
+
+def _digest(*tensors, chunk=1 << 26):
+    """Position-weighted wrapping sum of int64 words (the weights are odd, so
+    a single differing element always changes it)."""
+    acc = torch.zeros((), dtype=torch.int64, device="cuda")
+    for k, t in enumerate(tensors):
+        t = t.reshape(-1).to(torch.int64)
+        for s in range(0, t.numel(), chunk):
+            x = t[s:s + chunk]
+            i = torch.arange(s, s + x.numel(), dtype=torch.int64, device=x.device)
+            acc += (x * (2 * i + 1 + 2 * k)).sum()
+    return int(acc.item())
+
+
+def test_c4_full_size_sampled_windows(K, orc):
+    """The headline workload at its full size (4096 substream windows,
+    2.15G 32-byte rows) in the launch configuration the benchmark times: one
+    captured graph per route with the autotuned batch configuration, the
+    learned route's models fitted on the previous epoch.  Every 64th window
+    and the largest one are checked against the oracle (sorted KPA and
+    count/sum/max per key); the two routes' whole outputs (sorted KPA, group
+    offsets and columns) are compared through position-weighted digests."""
+    from paper_1901_01328_amd.pipeline import BatchAggregation
+    torch.cuda.empty_cache()
+    dev = torch.device("cuda")
+    sizes = datagen.c4_window_sizes(4096)
+    n, n_seg = int(sizes.sum()), len(sizes)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    say(f"c4 full size: {n} rows in {n_seg} windows")
+    rows = datagen.gen_c4(0, sizes, device=dev)
+    pipe = BatchAggregation(n, n_seg, LAYOUT32, device=dev, learned_ws=True)
+    pipe.set_sizes(sizes)
+    radix_cfg = K.batch_config(large_algo=K.KPA_SORT_RADIX)
+    pipe.step(rows, cfg=radix_cfg)
+    pipe.fit_models()
+    datagen.gen_c4(1, sizes, out=rows)
+    pipe.step(rows, cfg=radix_cfg)
+    pipe.extract(rows)
+    torch.cuda.synchronize()
+    cfgs = {}
+    for route, algo in (("learned", K.KPA_SORT_LEARNED), ("radix", K.KPA_SORT_RADIX)):
+        cfgs[route], ms = K.kpa_batch_autotune(
+            pipe.keys, None, pipe.seg_off, large_algo=algo, n_cap=n,
+            models=pipe.models if route == "learned" else None, reps=1,
+            keys_out=pipe.skeys, rids_out=pipe.srids, ws=pipe.ws_sort)
+        say(f"tuned {route}: {cfgs[route].as_dict()} ({ms:.2f} ms)")
+    sample = sorted(set(range(0, n_seg, 64)) | {int(np.argmax(sizes))})
+    expect = {}
+    for j in sample:
+        a, b = int(off[j]), int(off[j + 1])
+        rh = rows[a:b].cpu()
+        k, r = orc.extract(rh, LAYOUT32)
+        sk, sr = orc.sort(k, r)
+        expect[j] = (sk, sr.astype(np.uint64) + np.uint64(a),
+                     orc.reduce_by_key(sk, sr, rh, LAYOUT32))
+    say(f"oracle: {len(sample)} windows, {sum(len(e[0]) for e in expect.values())} rows")
+    stream = torch.cuda.Stream()
+    digests = {}
+    for route in ("learned", "radix"):
+        g = pipe.capture(rows, stream, cfg=cfgs[route], fit_next=route == "learned")
+        torch.cuda.synchronize()
+        g.launch(stream)
+        stream.synchronize()
+        g.destroy()
+        say(f"{route} step done")
+        G = int(pipe.gseg[-1].item())
+        digests[route] = (_digest(pipe.skeys, pipe.srids),
+                          _digest(pipe.gseg, *(t[:G] for t in (pipe.gkey, pipe.g["cnt"],
+                                                               pipe.g["sum"], pipe.g["max"]))))
+        goff = u64(pipe.gseg)
+        for j in sample:
+            a, b = int(off[j]), int(off[j + 1])
+            sk, sr, (ek, ec, es, em) = expect[j]
+            assert np.array_equal(u64(pipe.skeys[a:b]), sk), (route, j)
+            assert np.array_equal(u32(pipe.srids[a:b]).astype(np.uint64), sr), (route, j)
+            ga, gb = int(goff[j]), int(goff[j + 1])
+            assert gb - ga == len(ek), (route, j)
+            assert np.array_equal(u64(pipe.gkey[ga:gb]), ek), (route, j)
+            for name, e in (("cnt", ec), ("sum", es), ("max", em)):
+                assert np.array_equal(u64(pipe.g[name][ga:gb]), e), (route, j, name)
+    assert digests["learned"] == digests["radix"]
+    del pipe, rows
+    torch.cuda.empty_cache()
