@@ -561,52 +561,6 @@ __device__ u32 lds_sort_model(FinishSmem& sm, const SegModel& m, u32 mcount) {
   return CH_MOVED;
 }
 
-#ifndef KPA_FIN_EXTRA
-#define KPA_FIN_EXTRA 1024
-#endif
-// Entries a finishing workgroup reads first: the entry before its stretch,
-// the stretch, and KPA_FIN_EXTRA more, within which most chunks end.
-constexpr u32 FIN_FIRST = FH + 1 + KPA_FIN_EXTRA;
-static_assert(FIN_FIRST <= FCAP + 1, "the first read fits the window");
-constexpr int FIN_IT = (FIN_FIRST + FIN_THREADS - 1) / FIN_THREADS;
-
-// Window entries [from, to): keys from keys[g + i] and their refined ids.
-// Each thread issues all its loads of a batch of N entries before using any,
-// so that one memory latency covers the batch.
-template <int N>
-__device__ __forceinline__ void load_window(FinishSmem& sm, const SegModel& m, const lds_float* kn,
-                                            const u64* __restrict__ keys, u64 g, u32 from,
-                                            u32 to) {
-  for (u32 b = from; b < to; b += N * FIN_THREADS) {
-    u64 kv[N];
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-      const u32 i = b + threadIdx.x + j * FIN_THREADS;
-      kv[j] = i < to ? keys[g + i] : 0ull;
-    }
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-      const u32 i = b + threadIdx.x + j * FIN_THREADS;
-      if (i < to) {
-        sm.skeys[i] = kv[j];
-        sm.srel[i] = m.valid ? model_fine(m, kn, kv[j]) : 0u;
-      }
-    }
-  }
-}
-
-// First window index o in [lo, hi) (lo >= 1) where a bucket starts, i.e. whose
-// bucket differs from that of o - 1; NONE when there is none.
-__device__ __forceinline__ u32 first_edge(FinishSmem& sm, u32 lo, u32 hi) {
-  u32 e = NONE;
-  for (u32 o = lo + threadIdx.x; o < hi; o += FIN_THREADS)
-    if ((sm.srel[o] >> REFINE_BITS) != (sm.srel[o - 1] >> REFINE_BITS)) {
-      e = o;
-      break;
-    }
-  return block_min_u32<FIN_WAVES>(e, sm.red);
-}
-
 // Finishing pass over the 2048-entry stretches [pos0, pos0+FH) of every
 // segment.  A stretch owns the buckets whose first entry lies in it: the
 // chunk [start, end) from its first bucket start to the first bucket start at
@@ -616,20 +570,24 @@ __device__ __forceinline__ u32 first_edge(FinishSmem& sm, u32 lo, u32 hi) {
 // Step 1 (k_fin_active, one thread per stretch): bucket ids never decrease
 // along a segment, so a stretch other than a segment's first holds a bucket
 // start exactly when the entry before it and its last entry lie in different
-// buckets.  Those stretches are listed (about half of them on skewed keys);
-// the rest need no work.  A listed stretch is (segment << 32 | index in the
-// segment), so that its workgroup needs no lookup before the segment's data.
+// buckets; its first bucket start is then found by binary search.  edge[t]
+// is that start's offset in stretch t (0 for a segment's first stretch),
+// NONE when the stretch holds none.  The stretches that hold one are listed
+// (about half of them on skewed keys); the rest need no work.  A listed
+// stretch is (segment << 32 | index in the segment), so that its workgroup
+// needs no lookup before the segment's data.
 __global__ void __launch_bounds__(BLOCK) k_fin_active(const u64* __restrict__ keys, SegList sl,
                                                       const u32* __restrict__ ftile_start,
                                                       const u32* __restrict__ ftile_seg,
                                                       const SegModel* __restrict__ segm,
-                                                      u32 max_ftiles, u64* __restrict__ active,
+                                                      u32 max_ftiles, u32* __restrict__ edge,
+                                                      u64* __restrict__ active,
                                                       u32* __restrict__ n_active) {
   const u32 n_seg = sl.n();
   const u32 total = min(ftile_start[n_seg], max_ftiles);
   for (u32 t0 = blockIdx.x * BLOCK; t0 < total; t0 += gridDim.x * BLOCK) {
     const u32 tile = t0 + threadIdx.x;
-    bool act = false;
+    u32 e = NONE;
     u64 item = 0;
     if (tile < total) {
       const u32 seg = ftile_seg[tile];
@@ -639,15 +597,26 @@ __global__ void __launch_bounds__(BLOCK) k_fin_active(const u64* __restrict__ ke
       const u64 pos0 = a + (u64)k * FH;
       if (pos0 < b) {
         if (k == 0) {
-          act = true;
+          e = 0;
         } else {
           const SegModel m = segm[seg];
           const u32 span = (u32)min<u64>(FH, b - pos0);
           const global_float* gk = (const global_float*)m.knots;
-          act = model_bucket(m, gk, keys[pos0 - 1]) != model_bucket(m, gk, keys[pos0 - 1 + span]);
+          const u32 b0 = model_bucket(m, gk, keys[pos0 - 1]);
+          if (model_bucket(m, gk, keys[pos0 - 1 + span]) != b0) {
+            // first offset o in [1, span] whose entry pos0 - 1 + o leaves bucket b0
+            u32 lo = 1, hi = span;
+            while (lo < hi) {
+              const u32 mid = (lo + hi) >> 1;
+              if (model_bucket(m, gk, keys[pos0 - 1 + mid]) != b0) hi = mid; else lo = mid + 1;
+            }
+            e = lo - 1;
+          }
         }
       }
+      edge[tile] = e;
     }
+    const bool act = e != NONE;
     const u64 bal = ballot(act);
     u32 wbase = 0;
     if (__lane_id() == 0 && bal) wbase = atomicAdd(n_active, (u32)__popcll(bal));
@@ -656,18 +625,16 @@ __global__ void __launch_bounds__(BLOCK) k_fin_active(const u64* __restrict__ ke
   }
 }
 
-// Step 2: one listed stretch's chunk.  The workgroup reads keys from the
-// entry before the stretch on, first FIN_FIRST of them and, when the chunk's
-// end is not among them, up to FCAP+1 from the chunk's start; row ids only of
-// the chunk.  Other workgroups rewrite neighbouring chunks meanwhile; a
-// chunk's sort only permutes entries inside the chunk's buckets, so the
-// bucket of every position never changes and the edges found do not depend on
-// timing.  Every return is uniform over the workgroup.
+// Step 2: one listed stretch's chunk.  Its start is the stretch's first
+// bucket start; its end, the first bucket start of a later stretch of the
+// segment (edge[], read FIN_THREADS stretches at a time) or the segment end.
+// The workgroup reads the chunk's keys (and row ids); every return is
+// uniform over the workgroup.
 //
 // VALS: the chunk also carries a value column.  The on-chip sort then
-// orders local indices instead of row ids, and after the keys are written
-// the chunk's row ids and values are read into the free LDS areas and
-// written in the sorted order.
+// orders local indices instead of row ids; the chunk's row ids and values
+// are loaded into registers while the sorted keys are written, and go
+// through the free LDS areas into the new order.
 // Permutes the row ids and values of [start, start + m) in place by the local
 // indices in sm.srids (sm.srids[i] = old position of the entry now at i).
 // The caller has written the sorted keys; begins with a barrier.
@@ -689,7 +656,7 @@ __device__ __forceinline__ void permute_rids_vals(FinishSmem& sm, u32* __restric
 template <bool VALS>
 __device__ __forceinline__ void finish_stretch(
     FinishSmem& sm, u64* __restrict__ keys, u32* __restrict__ rids, u64* __restrict__ vals,
-    const SegList& sl,
+    const SegList& sl, const u32* __restrict__ ftile_start, const u32* __restrict__ edge,
     const SegModel* __restrict__ segm, u64* __restrict__ fb_lo, u64* __restrict__ fb_hi,
     u32* __restrict__ fb_seg, u32* __restrict__ fb_count, u32 max_fb, kpa_sort_stats* stats,
     u64 item) {
@@ -699,125 +666,55 @@ __device__ __forceinline__ void finish_stretch(
   const u64 a = sl.lo[seg], b = sl.hi[seg];
   const u64 pos0 = a + (u64)k * FH;
   if (pos0 >= b) return;
-  const SegModel m = segm[seg];
-  const u32 span = (u32)min<u64>(FH, b - pos0);
-  // --- window from L0: the entry before the stretch (k > 0) or pos0 = a ---
-  // Its keys are in flight while the knots are copied to LDS.
-  const u64 L0 = k > 0 ? pos0 - 1 : pos0;
-  u32 have = (u32)min<u64>(FIN_FIRST, b - L0);
-  {
-    u64 kv[FIN_IT];
-#pragma unroll
-    for (int j = 0; j < FIN_IT; ++j) {
-      const u32 i = tid + j * FIN_THREADS;
-      kv[j] = i < have ? keys[L0 + i] : 0ull;
-    }
-    const lds_float* kn0 = bind_knots(m, sm.knots);
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < FIN_IT; ++j) {
-      const u32 i = tid + j * FIN_THREADS;
-      if (i < have) {
-        sm.skeys[i] = kv[j];
-        sm.srel[i] = m.valid ? model_fine(m, kn0, kv[j]) : 0u;
-      }
+  const u32 f0 = ftile_start[seg];
+  const u32 nst = (u32)((b - a + FH - 1) / FH);  // stretches holding entries
+  const u64 start = pos0 + edge[f0 + k];
+  u64 end = b;
+  for (u32 k2 = k + 1; k2 < nst; k2 += FIN_THREADS) {
+    const u32 kk = k2 + tid;
+    const bool found = kk < nst && edge[f0 + kk] != NONE;
+    const u32 first = block_min_u32<FIN_WAVES>(found ? tid : NONE, sm.red);
+    if (first != NONE) {
+      end = a + (u64)(k2 + first) * FH + edge[f0 + k2 + first];
+      break;
     }
   }
-  const lds_float* kn = (const lds_float*)sm.knots;
-  __syncthreads();
-  u32 s0 = 0;  // window index of the chunk's first entry
-  if (k > 0) {
-    s0 = first_edge(sm, 1, span + 1);
-    if (s0 == NONE) return;  // the bucket at pos0 started earlier and covers the stretch
-  }
-  const u64 start = L0 + s0;
-  // row ids of the chunk's likely extent, in flight during the search below
-  const u32 rguess = VALS ? 0u : min(have - s0, FCAP);
-  u32 rr[FIN_IT];
-#pragma unroll
-  for (int j = 0; j < FIN_IT; ++j) {
-    const u32 i = tid + j * FIN_THREADS;
-    rr[j] = i < rguess ? rids[start + i] : 0u;
-  }
-  if (s0 > 0) {  // move the chunk to window index 0
-    u64 kk[FIN_IT];
-    u32 re[FIN_IT];
-#pragma unroll
-    for (int j = 0; j < FIN_IT; ++j) {
-      const u32 i = tid + j * FIN_THREADS;
-      if (s0 + i < have) {
-        kk[j] = sm.skeys[s0 + i];
-        re[j] = sm.srel[s0 + i];
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < FIN_IT; ++j) {
-      const u32 i = tid + j * FIN_THREADS;
-      if (s0 + i < have) {
-        sm.skeys[i] = kk[j];
-        sm.srel[i] = re[j];
-      }
-    }
-    __syncthreads();
-    have -= s0;
-  }
-
-  // --- the chunk's end: the first bucket start at or after pos0 + FH ------
-  const u32 e_lo = (u32)(pos0 + FH - start);  // >= 1: start < pos0 + FH
-  const u32 want = (u32)min<u64>(FCAP + 1, b - start);
-  u32 endo = first_edge(sm, e_lo, have);
-  if (endo == NONE && have < want) {
-    load_window<8>(sm, m, kn, keys, start, have, want);
-    __syncthreads();
-    endo = first_edge(sm, max(e_lo, have), want);
-    have = want;
-  }
-  if (endo == NONE && want == b - start && want <= FCAP) endo = want;  // the segment's end
-
-  if (endo == NONE) {
-    // Oversize: no bucket starts among the FCAP+1 entries from the chunk's
-    // start after pos0 + FH; the bucket of the last of them runs on.  Its end
-    // is found by a FIN_THREADS-way search: every round each thread probes
-    // one position of (lo, hi) and the first probe past the bucket narrows
-    // the range (three rounds cover a 4M-entry segment).
-    const u32 beta = sm.srel[want - 1] >> REFINE_BITS;
-    u64 lo = start + want - 1, hi = b;  // first p in (lo, hi] with p == b or bucket > beta
-    while (hi - lo > 1) {
-      const u64 span = hi - lo;
-      auto probe = [&](u32 t) { return lo + 1 + ((span - 2) * t) / (FIN_THREADS - 1); };
-      const u64 q = probe(tid);  // in [lo + 1, hi - 1], nondecreasing in tid
-      const bool past = model_bucket(m, kn, keys[q]) > beta;
-      const u32 first = block_min_u32<FIN_WAVES>(past ? tid : NONE, sm.red);
-      if (first == NONE) {
-        lo = probe(FIN_THREADS - 1);
-      } else {
-        hi = probe(first);
-        if (first > 0) lo = probe(first - 1);
-      }
-    }
+  if (end - start > FCAP) {  // oversize: listed for the pivot rounds
     if (tid == 0) {
       const u32 idx = atomicAdd(fb_count, 1u);
       if (idx < max_fb) {
         fb_lo[idx] = start;
-        fb_hi[idx] = hi;
+        fb_hi[idx] = end;
         fb_seg[idx] = seg;
       }
     }
     return;
   }
-
-  const u32 mcount = endo;  // <= FCAP
-  if (VALS) {
-    for (u32 i = tid; i < mcount; i += FIN_THREADS) sm.srids[i] = i;
-  } else {
+  const u32 mcount = (u32)(end - start);  // <= FCAP
+  const SegModel m = segm[seg];
+  {
+    constexpr int IT = (int)(FCAP / FIN_THREADS);
+    u64 kv[IT];  // in flight while the knots are copied to LDS
+    u32 rv[IT];
 #pragma unroll
-    for (int j = 0; j < FIN_IT; ++j) {
+    for (int j = 0; j < IT; ++j) {
       const u32 i = tid + j * FIN_THREADS;
-      if (i < mcount && i < rguess) sm.srids[i] = rr[j];
+      kv[j] = i < mcount ? keys[start + i] : 0ull;
+      rv[j] = VALS ? i : (i < mcount ? rids[start + i] : 0u);
     }
-    for (u32 i = rguess + tid; i < mcount; i += FIN_THREADS) sm.srids[i] = rids[start + i];
+    const lds_float* kn = bind_knots(m, sm.knots);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < IT; ++j) {
+      const u32 i = tid + j * FIN_THREADS;
+      if (i < mcount) {
+        sm.skeys[i] = kv[j];
+        sm.srids[i] = rv[j];
+        sm.srel[i] = m.valid ? model_fine(m, kn, kv[j]) : 0u;
+      }
+    }
   }
+  __syncthreads();  // the sort reads other threads' entries before its first barrier
   u32 res;
   if (mcount <= 2048)
     res = lds_sort_model<4>(sm, m, mcount);
@@ -871,13 +768,14 @@ __device__ __forceinline__ void finish_stretch(
 template <bool VALS>
 __global__ void __launch_bounds__(FIN_THREADS, 4) k_learned_finish(
     u64* __restrict__ keys, u32* __restrict__ rids, u64* __restrict__ vals, SegList sl,
+    const u32* __restrict__ ftile_start, const u32* __restrict__ edge,
     const SegModel* __restrict__ segm, const u64* __restrict__ active,
     const u32* __restrict__ n_active, u64* __restrict__ fb_lo, u64* __restrict__ fb_hi,
     u32* __restrict__ fb_seg, u32* __restrict__ fb_count, u32 max_fb, kpa_sort_stats* stats) {
   __shared__ FinishSmem sm;
   if (blockIdx.x >= *n_active) return;
-  finish_stretch<VALS>(sm, keys, rids, vals, sl, segm, fb_lo, fb_hi, fb_seg, fb_count, max_fb,
-                       stats, active[blockIdx.x]);
+  finish_stretch<VALS>(sm, keys, rids, vals, sl, ftile_start, edge, segm, fb_lo, fb_hi, fb_seg,
+                       fb_count, max_fb, stats, active[blockIdx.x]);
 }
 
 // Sorts listed ranges of at most FCAP entries in place, one workgroup each.
@@ -1259,6 +1157,7 @@ kpa_status learned_sort_plan(u64 n_cap, u32 n_seg, Carver& c, LearnedWs* w, bool
   w->ltile_seg = c.take<u32>(w->max_tiles);
   w->ftile_seg = c.take<u32>(w->max_ftiles);
   w->factive = c.take<u64>(w->max_ftiles);
+  w->fedge = c.take<u32>(w->max_ftiles);
   w->fn_active = c.take<u32>(1);
   w->hist = c.take<u32>((u64)n_seg * 2 * RADIX);
   w->seg_mask = c.take<u32>(n_seg);
@@ -1327,15 +1226,17 @@ kpa_status learned_sort_launch(const u64* keys_in, const u32* rids_in, u64* keys
   KPA_CHECK(launch_fill_u32(lw.fn_active, 1, 0, st));
   KPA_LAUNCH("learned_finish_list", k_fin_active,
              dim3((u32)std::min<u64>(ceil_div(lw.max_ftiles, BLOCK), 4096)), dim3(BLOCK), 0, st,
-             keys_out, sl, lw.ftile_start, lw.ftile_seg, lw.segm, (u32)lw.max_ftiles, lw.factive,
-             lw.fn_active);
+             keys_out, sl, lw.ftile_start, lw.ftile_seg, lw.segm, (u32)lw.max_ftiles, lw.fedge,
+             lw.factive, lw.fn_active);
   if (vals)
     KPA_LAUNCH("learned_finish", k_learned_finish<true>, dim3((u32)lw.max_ftiles),
-               dim3(FIN_THREADS), 0, st, keys_out, rids_out, vout, sl, lw.segm, lw.factive,
+               dim3(FIN_THREADS), 0, st, keys_out, rids_out, vout, sl, lw.ftile_start, lw.fedge,
+               lw.segm, lw.factive,
                lw.fn_active, lw.fb_lo, lw.fb_hi, lw.fb_seg, lw.fb_count, lw.max_fb, stats);
   else
     KPA_LAUNCH("learned_finish", k_learned_finish<false>, dim3((u32)lw.max_ftiles),
-               dim3(FIN_THREADS), 0, st, keys_out, rids_out, vout, sl, lw.segm, lw.factive,
+               dim3(FIN_THREADS), 0, st, keys_out, rids_out, vout, sl, lw.ftile_start, lw.fedge,
+               lw.segm, lw.factive,
                lw.fn_active, lw.fb_lo, lw.fb_hi, lw.fb_seg, lw.fb_count, lw.max_fb, stats);
 
   // Pivot rounds over the oversize chunks: round 0 reads the finishing pass's

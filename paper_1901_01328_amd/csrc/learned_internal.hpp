@@ -100,6 +100,7 @@ struct LearnedWs {
   u32* ltile_seg;    // segment of each scatter tile (max_tiles)
   u32* ftile_seg;    // segment of each finishing stretch (max_ftiles)
   u64* factive;      // stretches that hold a bucket start: segment << 32 | index (max_ftiles)
+  u32* fedge;        // per stretch: offset of its first bucket start, NONE if none (max_ftiles)
   u32* fn_active;
   u32* hist;       // n_seg * 8 * 256 (only 2 passes used)
   u32* seg_mask;
