@@ -238,15 +238,19 @@ kpa_status kpa_sort_segmented_vals(const uint64_t* keys_in, const uint32_t* rids
  * persistent kernel; segment sizes are read from seg_off on the device only,
  * so a captured graph of this call serves any segmentation with the same
  * n_seg and n_cap.  small_cap <= 4096, small_cap <= mid_cap < 2^30; grid = 0
- * sizes the persistent kernel to the workgroups resident at once. */
+ * sizes the persistent kernel to the workgroups resident at once.
+ * bucket_log2 (learned large path): the bucket count of a segment of n
+ * entries is the power of two nearest above n / 2^bucket_log2, in 6..12;
+ * 0: 9 (512-entry buckets). */
 typedef struct kpa_batch_config {
   uint32_t small_cap;
   uint32_t mid_cap;
   uint32_t grid;
   uint32_t large_algo; /* a kpa_sort_algo */
+  uint32_t bucket_log2;
 } kpa_batch_config;
 
-/* small_cap 4096, mid_cap 65536, grid 0. */
+/* small_cap 4096, mid_cap 65536, grid 0, bucket_log2 0. */
 kpa_status kpa_batch_config_default(kpa_sort_algo large_algo, kpa_batch_config* cfg);
 kpa_status kpa_batch_sort_workspace_size(uint64_t n_cap, uint32_t n_seg,
                                          const kpa_batch_config* cfg, size_t* bytes);
@@ -268,8 +272,10 @@ kpa_status kpa_batch_sort_vals(const uint64_t* keys_in, const uint32_t* rids_in,
                                size_t ws_bytes, hipStream_t stream);
 /* Autotuner: times kpa_batch_sort on the given batch (one warm-up and `reps`
  * timed runs per candidate) over the class boundaries small_cap in {1024,
- * 2048, 4096} and mid_cap in {small_cap, 2^14, 2^16, 2^18}, and returns the
- * fastest configuration in *best (its mean time in *best_ms, may be NULL).
+ * 2048, 4096} and mid_cap in {small_cap, 2^14, 2^16, 2^18}, then, for the
+ * learned large path, the bucket size 2^bucket_log2 in {256, 512, 1024} at the
+ * best boundaries, and returns the fastest configuration in *best (its mean
+ * time in *best_ms, may be NULL).
  * cache_path (host file, may be NULL): a text file of earlier results keyed by
  * the batch's signature (segment count, capacity, large_algo and a coarse
  * histogram of segment sizes); a hit returns the stored result without timing,

@@ -270,6 +270,8 @@ kpa_status check_config(const kpa_batch_config* cfg) {
               "mid_cap must lie in [small_cap, 2^30)");
   KPA_REQUIRE(cfg->large_algo == KPA_SORT_RADIX || cfg->large_algo == KPA_SORT_LEARNED,
               KPA_EINVAL, "bad large_algo");
+  KPA_REQUIRE(cfg->bucket_log2 == 0 || (cfg->bucket_log2 >= 6 && cfg->bucket_log2 <= 12),
+              KPA_EINVAL, "bucket_log2 must be 0 or lie in [6, 12]");
   return KPA_OK;
 }
 
@@ -332,7 +334,8 @@ kpa_status batch_launch(const u64* keys_in, const u32* rids_in, u64* keys_out, u
   const SegList large{w.large_lo, w.large_hi, nullptr, n_seg};
   if (cfg->large_algo == KPA_SORT_LEARNED)
     return learned_sort_launch(keys_in, rids_in, keys_out, rids_out, large, models, stats, w.lw,
-                               st, vals_in, vals_out);
+                               st, vals_in, vals_out,
+                               cfg->bucket_log2 ? cfg->bucket_log2 : BUCKET_LOG2);
   if (stats) KPA_CHECK(launch_fill_u64(reinterpret_cast<u64*>(stats), STATS_WORDS, 0, st));
   return radix_sort_launch(keys_in, rids_in, keys_out, rids_out, large, w.rw, st,
                            stats_unsupported(stats), vals_in, vals_out);
@@ -385,8 +388,9 @@ bool cache_lookup(const char* path, const std::string& sig, kpa_batch_config* cf
       continue;
     kpa_batch_config c{};
     float t = 0;
-    if (std::sscanf(bar + 1, " small_cap=%u mid_cap=%u grid=%u large_algo=%u ms=%f",
-                    &c.small_cap, &c.mid_cap, &c.grid, &c.large_algo, &t) == 5 &&
+    c.bucket_log2 = 0;
+    if (std::sscanf(bar + 1, " small_cap=%u mid_cap=%u grid=%u large_algo=%u bucket_log2=%u ms=%f",
+                    &c.small_cap, &c.mid_cap, &c.grid, &c.large_algo, &c.bucket_log2, &t) == 6 &&
         check_config(&c) == KPA_OK) {
       *cfg = c;  // the last entry for a signature wins
       *ms = t;
@@ -402,8 +406,8 @@ void cache_store(const char* path, const std::string& sig, const kpa_batch_confi
   if (!path) return;
   FILE* f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "%s| small_cap=%u mid_cap=%u grid=%u large_algo=%u ms=%.4f\n", sig.c_str(),
-               c.small_cap, c.mid_cap, c.grid, c.large_algo, ms);
+  std::fprintf(f, "%s| small_cap=%u mid_cap=%u grid=%u large_algo=%u bucket_log2=%u ms=%.4f\n",
+               sig.c_str(), c.small_cap, c.mid_cap, c.grid, c.large_algo, c.bucket_log2, ms);
   std::fclose(f);
 }
 
@@ -421,6 +425,7 @@ kpa_status kpa_batch_config_default(kpa_sort_algo large_algo, kpa_batch_config* 
   cfg->mid_cap = 1u << 16;
   cfg->grid = 0;
   cfg->large_algo = (uint32_t)large_algo;
+  cfg->bucket_log2 = 0;
   return check_config(cfg);
 }
 
@@ -521,7 +526,7 @@ kpa_status kpa_batch_autotune(const uint64_t* keys_in, const uint32_t* rids_in,
   const u32 mids[] = {0, 1u << 14, 1u << 16, 1u << 18};
   for (u32 sc : smalls)
     for (u32 mc : mids) {
-      kpa_batch_config c{sc, std::max(sc, mc), 0, (uint32_t)large_algo};
+      kpa_batch_config c{sc, std::max(sc, mc), 0, (uint32_t)large_algo, 0};
       if (mc != 0 && mc <= sc) continue;
       cand.push_back(c);
     }
@@ -533,26 +538,47 @@ kpa_status kpa_batch_autotune(const uint64_t* keys_in, const uint32_t* rids_in,
   }
   float best_t = INFINITY;
   kpa_status rc = KPA_OK;
-  for (const kpa_batch_config& c : cand) {
+  // Times one candidate (one warm-up, then `reps` runs) and keeps it if it
+  // is the fastest so far.
+  auto try_config = [&](const kpa_batch_config& c) {
     rc = kpa_batch_sort(keys_in, rids_in, keys_out, rids_out, seg_off, n_seg, n_cap, &c, models,
-                        nullptr, ws, ws_bytes, stream);  // warm-up
-    if (rc != KPA_OK) break;
-    if (hipEventRecord(e0, stream) != hipSuccess) { rc = KPA_EHIP; break; }
+                        nullptr, ws, ws_bytes, stream);
+    if (rc != KPA_OK) return;
+    if (hipEventRecord(e0, stream) != hipSuccess) {
+      rc = KPA_EHIP;
+      set_error("event record failed in the autotuner");
+      return;
+    }
     for (u32 r = 0; r < reps && rc == KPA_OK; ++r)
       rc = kpa_batch_sort(keys_in, rids_in, keys_out, rids_out, seg_off, n_seg, n_cap, &c,
                           models, nullptr, ws, ws_bytes, stream);
-    if (rc != KPA_OK) break;
+    if (rc != KPA_OK) return;
     float ms = 0;
     if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
         hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
       rc = KPA_EHIP;
       set_error("event timing failed in the autotuner");
-      break;
+      return;
     }
     ms /= (float)reps;
     if (ms < best_t) {
       best_t = ms;
       *best = c;
+    }
+  };
+  for (const kpa_batch_config& c : cand) {
+    try_config(c);
+    if (rc != KPA_OK) break;
+  }
+  // The learned large path's bucket size, at the best class boundaries (the
+  // candidates above ran with the default 2^9).
+  if (rc == KPA_OK && large_algo == KPA_SORT_LEARNED) {
+    const kpa_batch_config base = *best;
+    for (u32 bl : {8u, 10u}) {
+      kpa_batch_config c = base;
+      c.bucket_log2 = bl;
+      try_config(c);
+      if (rc != KPA_OK) break;
     }
   }
   (void)hipEventDestroy(e0);

@@ -184,7 +184,7 @@ __global__ void __launch_bounds__(BLOCK) k_learned_setup(const kpa_pwl_model* __
                                                          const u64* __restrict__ cur_min,
                                                          const u64* __restrict__ cur_max,
                                                          SegModel* __restrict__ segm,
-                                                         kpa_sort_stats* stats) {
+                                                         kpa_sort_stats* stats, u32 bucket_log2) {
   const u32 n_seg = sl.n();
   for (u32 s = blockIdx.x; s < n_seg; s += gridDim.x) {
     const kpa_pwl_model& M = models[s];
@@ -218,7 +218,7 @@ __global__ void __launch_bounds__(BLOCK) k_learned_setup(const kpa_pwl_model* __
       // too large through and counts it).
       u32 bits = 0;
       if (ok && n > FCAP && n < MAX_SEG_ENTRIES) {
-        const u64 want = (n + BUCKET_TARGET - 1) / BUCKET_TARGET;
+        const u64 want = (n + (1ull << bucket_log2) - 1) >> bucket_log2;
         while (bits < MAX_BUCKET_BITS && (1ull << bits) < want) ++bits;
       }
       m.bits = bits;
@@ -1196,7 +1196,7 @@ kpa_status learned_sort_plan(u64 n_cap, u32 n_seg, Carver& c, LearnedWs* w, bool
 kpa_status learned_sort_launch(const u64* keys_in, const u32* rids_in, u64* keys_out,
                                u32* rids_out, const SegList& sl, const kpa_pwl_model* models,
                                kpa_sort_stats* stats, const LearnedWs& lw, hipStream_t st,
-                               const u64* vals_in, u64* vals_out) {
+                               const u64* vals_in, u64* vals_out, u32 bucket_log2) {
   KPA_REQUIRE(!vals_in || (vals_out && lw.vals_tmp), KPA_EINVAL,
               "a value column needs an output and a planned buffer");
   const bool vals = vals_in != nullptr;
@@ -1214,7 +1214,7 @@ kpa_status learned_sort_launch(const u64* keys_in, const u32* rids_in, u64* keys
              dim3(BLOCK), 0, st, keys_in, sl, lw.ltile_start, lw.ltile_seg, lw.cur_min,
              lw.cur_max);
   KPA_LAUNCH("learned_setup", k_learned_setup, dim3(std::min<u32>(n_seg, 2048)), dim3(BLOCK), 0,
-             st, models, sl, lw.cur_min, lw.cur_max, lw.segm, stats);
+             st, models, sl, lw.cur_min, lw.cur_max, lw.segm, stats, bucket_log2);
   DigitSortBufs b{keys_in,     rids_in,      keys_out,    rids_out,       lw.keys_tmp,
                   lw.rids_tmp, lw.hist,      lw.seg_mask, lw.ltile_start, lw.status0,
                   lw.status1,  lw.counters,  lw.max_tiles, lw.order,     nullptr,

@@ -7,7 +7,7 @@ namespace kpa {
 
 constexpr u32 FCAP = TILE;        // entries sorted on chip by one workgroup
 constexpr u32 FH = FCAP / 2;      // chunk stride of the finishing pass
-constexpr u32 BUCKET_TARGET = 512;  // mean bucket size the bucket count aims at
+constexpr u32 BUCKET_LOG2 = 9;  // default mean bucket size the bucket count aims at: 2^9
 #ifndef KPA_REFINE_BITS
 #define KPA_REFINE_BITS 8
 #endif
@@ -142,9 +142,11 @@ struct LearnedWs {
 kpa_status learned_sort_plan(u64 n_cap, u32 n_seg, Carver& c, LearnedWs* w, bool vals = false);
 // vals_in/vals_out (both or neither; the plan must have had vals): a value
 // column that follows the keys' permutation.
+// bucket_log2: the mean bucket size the bucket count aims at is 2^bucket_log2.
 kpa_status learned_sort_launch(const u64* keys_in, const u32* rids_in, u64* keys_out,
                                u32* rids_out, const SegList& sl, const kpa_pwl_model* models,
                                kpa_sort_stats* stats, const LearnedWs& lw, hipStream_t st,
-                               const u64* vals_in = nullptr, u64* vals_out = nullptr);
+                               const u64* vals_in = nullptr, u64* vals_out = nullptr,
+                               u32 bucket_log2 = BUCKET_LOG2);
 
 }  // namespace kpa

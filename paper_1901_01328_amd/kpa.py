@@ -53,7 +53,7 @@ class KpaError(RuntimeError):
 
 class kpa_batch_config(C.Structure):
     _fields_ = [("small_cap", C.c_uint32), ("mid_cap", C.c_uint32), ("grid", C.c_uint32),
-                ("large_algo", C.c_uint32)]
+                ("large_algo", C.c_uint32), ("bucket_log2", C.c_uint32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -441,8 +441,9 @@ def kpa_batch_config_default(large_algo=KPA_SORT_RADIX):
     return cfg
 
 
-def batch_config(small_cap=4096, mid_cap=1 << 16, grid=0, large_algo=KPA_SORT_RADIX):
-    return kpa_batch_config(small_cap, mid_cap, grid, large_algo)
+def batch_config(small_cap=4096, mid_cap=1 << 16, grid=0, large_algo=KPA_SORT_RADIX,
+                 bucket_log2=0):
+    return kpa_batch_config(small_cap, mid_cap, grid, large_algo, bucket_log2)
 
 
 def kpa_batch_sort_workspace_size(n_cap, n_seg, cfg):

@@ -55,6 +55,15 @@ def test_host_side_errors_without_gpu():
     assert b"row_bytes" in lib.kpa_last_error_string()
     rc = lib.kpa_topk_by_sum(None, None, None, 1, 10, 17, None, None, None, None, 0, None)
     assert rc == k.KPA_EUNSUPPORTED
+    # batch configuration: the learned path's mean bucket size 2^bucket_log2
+    cfg = k.kpa_batch_config()
+    assert lib.kpa_batch_config_default(k.KPA_SORT_LEARNED, ctypes.byref(cfg)) == 0
+    assert cfg.bucket_log2 == 0
+    for bl, want in ((0, 0), (6, 0), (12, 0), (5, k.KPA_EINVAL), (13, k.KPA_EINVAL)):
+        cfg.bucket_log2 = bl
+        assert lib.kpa_batch_sort_workspace_size(1 << 20, 4, ctypes.byref(cfg),
+                                                 ctypes.byref(n)) == want, bl
+    assert b"bucket_log2" in lib.kpa_last_error_string()
 
 
 def test_server_config_checked_on_the_host():

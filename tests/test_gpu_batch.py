@@ -116,14 +116,27 @@ def prior_models(K, orc, sizes):
     return K.kpa_pwl_fit(dev_u64(sk), dev_u64(off))
 
 
-@pytest.mark.parametrize("mid", [1 << 14, 4096])
-def test_batch_learned_matches_oracle(K, orc, mid):
+@pytest.mark.parametrize("mid,bucket_log2", [(1 << 14, 0), (4096, 0), (1 << 14, 6), (4096, 12)])
+def test_batch_learned_matches_oracle(K, orc, mid, bucket_log2):
+    """Learned large path against the oracle, at the default bucket size and
+    at the smallest (64) and largest (4096) mean bucket sizes allowed."""
     sizes = batch_sizes(11, n_rand=300, hi=18)
     models = prior_models(K, orc, sizes)
     keys, rids, off = make_batch(sizes, epoch=1)
-    cfg = K.batch_config(4096, mid, 0, K.KPA_SORT_LEARNED)
-    st = check(K, orc, keys, rids, off, cfg, models=models, label=f"learned mid={mid}")
+    cfg = K.batch_config(4096, mid, 0, K.KPA_SORT_LEARNED, bucket_log2)
+    st = check(K, orc, keys, rids, off, cfg, models=models,
+               label=f"learned mid={mid} bucket_log2={bucket_log2}")
     assert st[0] > 0  # buckets were formed for the large segments
+    # the bucket count of each large segment is the power of two nearest
+    # above n / 2^bucket_log2 (one bucket for a segment that fits on chip)
+    bl = bucket_log2 or 9
+    want = 0
+    for n in (int(x) for x in sizes if x > mid):
+        bits = 0
+        while n > 4096 and bits < 16 and (1 << bits) < -(-n // (1 << bl)):
+            bits += 1
+        want += 1 << bits
+    assert int(st[0]) == want
 
 
 def test_batch_learned_workspace_reused_with_fewer_large_windows(K, orc):
