@@ -112,9 +112,9 @@ def counted_traffic(kernel_row, summary, sources):
 
 # Counter summaries of the dominant kernels: (summary file, row, sources).
 TRAFFIC = {
-    ("c2", "radix_pass"): ("c2_radix_hbm_bytes.md", "k_ds_pass<RadixDF>",
+    ("c2", "radix_pass"): ("c2_radix_hbm_bytes.md", "k_ds_pass<RadixDF, false>",
                            ("onesweep.hpp", "digit_sort.hpp", "radix.hip")),
-    ("c2", "learned_scatter"): ("c2_learned_hbm_bytes.md", "k_ds_pass<LearnedDF>",
+    ("c2", "learned_scatter"): ("c2_learned_hbm_bytes.md", "k_ds_pass<LearnedDF, false>",
                                 ("onesweep.hpp", "digit_sort.hpp", "learned.hip",
                                  "learned_internal.hpp")),
     ("c4", "learned_scatter"): ("c4_learned_hbm_bytes.md", "k_ds_pass<LearnedDF, true>",
