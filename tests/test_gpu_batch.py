@@ -246,3 +246,24 @@ def test_autotune_and_cache(K, orc, tmp_path):
     best2, ms2 = K.kpa_batch_autotune(kd, rd, od, reps=1, cache_path=path)
     assert best2.as_dict() == best.as_dict() and abs(ms2 - ms) < 1e-3
     check(K, orc, keys, rids, off, best, label="tuned")
+
+
+def test_autotune_learned_bucket_size_and_cache(K, orc, tmp_path):
+    """The learned large path's tuning also picks the mean bucket size; the
+    cache line carries it back, and the tuned configuration sorts exactly."""
+    sizes = batch_sizes(13, n_rand=120, hi=19)
+    models = prior_models(K, orc, sizes)
+    keys, rids, off = make_batch(sizes, epoch=1)
+    path = str(tmp_path / "tune_learned.txt")
+    kd, rd, od = dev_u64(keys), dev_u32(rids), dev_u64(off)
+    say("autotune learned")
+    best, ms = K.kpa_batch_autotune(kd, rd, od, large_algo=K.KPA_SORT_LEARNED, models=models,
+                                    reps=1, cache_path=path)
+    assert ms > 0 and best.large_algo == K.KPA_SORT_LEARNED
+    assert best.bucket_log2 in (0, 8, 10)
+    line = open(path).read().strip().splitlines()
+    assert len(line) == 1 and f"bucket_log2={best.bucket_log2} " in line[0]
+    best2, ms2 = K.kpa_batch_autotune(kd, rd, od, large_algo=K.KPA_SORT_LEARNED, models=models,
+                                      reps=1, cache_path=path)
+    assert best2.as_dict() == best.as_dict() and abs(ms2 - ms) < 1e-3
+    check(K, orc, keys, rids, off, best, models=models, label="tuned learned")
