@@ -385,13 +385,16 @@ kpa_status kpa_topk_by_sum(const uint64_t* gkey, const uint64_t* gsum, const uin
 /* Median per key (Sec. 6 "Windowed Median Per Key"; percentile by key via sort
  * and reduction, Sec. 4.2): for each group (as in kpa_reduce_by_key) the lower
  * median of its values, v[(c-1)/2] of the ascending values.  Outputs: out_gkey,
- * out_med (device, capacity n_cap), out_gseg_off (device, n_seg+1). */
+ * out_med (device, capacity n_cap), out_gseg_off (device, n_seg+1).  out_cnt
+ * and out_sum (device, capacity n_cap each, may be NULL): each group's count
+ * and sum of values (mod 2^64), as kpa_reduce_by_key gives them; the values
+ * are read once for both the medians and the sums. */
 kpa_status kpa_median_by_key_workspace_size(uint64_t n_cap, uint32_t n_seg, size_t* bytes);
 kpa_status kpa_median_by_key(const uint64_t* keys, const uint32_t* rids, const uint64_t* seg_off,
                              uint32_t n_seg, uint64_t n_cap, const void* rows,
                              const kpa_row_layout* layout, uint64_t* out_gkey, uint64_t* out_med,
-                             uint64_t* out_gseg_off, void* ws, size_t ws_bytes,
-                             hipStream_t stream);
+                             uint64_t* out_gseg_off, uint64_t* out_cnt, uint64_t* out_sum,
+                             void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Join (Table 2: two sorted KPAs, one pass; Sec. 4.2 "Temporal Join").  For
@@ -415,6 +418,25 @@ kpa_status kpa_join(const uint64_t* lk, const uint32_t* lr, const uint64_t* l_se
                     uint64_t* out_count, uint64_t* out_sumprod, uint64_t* out_pairs,
                     uint64_t pairs_cap, uint64_t* out_npairs, void* ws, size_t ws_bytes,
                     hipStream_t stream);
+
+/* Join of two run lists (Table 2 Join; Sec. 4.2 "Temporal Join"), for callers
+ * that already hold each side's groups: per segment s, the runs of equal keys
+ * of L and of R (key, count, sum of values), keys ascending and unique within
+ * a segment of a list, as kpa_reduce_by_key or kpa_median_by_key (with out_cnt
+ * and out_sum) write them.  A key present on both sides contributes
+ * count_L*count_R pairs and sum_L*sum_R to the sum of value products, so
+ * out_count[s] and out_sumprod[s] (device, n_seg u64 each) equal kpa_join's on
+ * the KPAs the lists come from.  l_gseg_off/r_gseg_off: device, n_seg+1 each
+ * (group offsets per segment); gl_cap/gr_cap: host upper bounds on the groups
+ * of each list (< 2^32; too small a bound gives wrong sums, never an access
+ * beyond the workspace).  No pairs are written. */
+kpa_status kpa_join_runs_workspace_size(uint64_t gl_cap, uint64_t gr_cap, uint32_t n_seg,
+                                        size_t* bytes);
+kpa_status kpa_join_runs(const uint64_t* l_gkey, const uint64_t* l_cnt, const uint64_t* l_sum,
+                         const uint64_t* l_gseg_off, uint64_t gl_cap, const uint64_t* r_gkey,
+                         const uint64_t* r_cnt, const uint64_t* r_sum, const uint64_t* r_gseg_off,
+                         uint64_t gr_cap, uint32_t n_seg, uint64_t* out_count,
+                         uint64_t* out_sumprod, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Materialize (Table 2: KPA -> bundle, random access): out_rows[i] =

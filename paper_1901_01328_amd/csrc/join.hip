@@ -33,8 +33,9 @@ struct JoinSides {
 };
 
 __global__ void __launch_bounds__(BLOCK) k_join_splits(JoinSides js, const u32* __restrict__ tile_start,
-                                                       u32 n_seg, u64* __restrict__ split) {
-  const u32 total = tile_start[n_seg];
+                                                       u32 n_seg, u64* __restrict__ split,
+                                                       u32 max_t) {
+  const u32 total = min(tile_start[n_seg], max_t);  // split holds max_t entries
   for (u32 t = blockIdx.x * BLOCK + threadIdx.x; t < total; t += gridDim.x * BLOCK) {
     const u32 s = find_seg(tile_start, n_seg, t);
     const u64 l0 = js.goff_l[s], nl = js.goff_l[s + 1] - l0;
@@ -216,6 +217,22 @@ static void join_plan(u64 nl, u64 nr, u32 n_seg, Carver& c, JoinWs* w) {
   w->tile_pairs = c.take<u64>(w->max_tiles);
 }
 
+// Workspace of a join over run lists given by the caller: the merge-path
+// tiles only.
+struct JoinRunsWs {
+  u32* tile_start;
+  u64* split;
+  u64* tile_pairs;
+  u64 max_tiles;
+};
+
+static void join_runs_plan(u64 gl, u64 gr, u32 n_seg, Carver& c, JoinRunsWs* w) {
+  w->max_tiles = max_tiles(gl + gr, n_seg, JT);
+  w->tile_start = c.take<u32>((u64)n_seg + 1);
+  w->split = c.take<u64>(w->max_tiles);
+  w->tile_pairs = c.take<u64>(w->max_tiles);
+}
+
 }  // namespace kpa
 
 using namespace kpa;
@@ -276,7 +293,7 @@ kpa_status kpa_join(const uint64_t* lk, const uint32_t* lr, const uint64_t* l_se
   JoinSides js{w.gk_l, w.gc_l, w.gs_l, w.gst_l, w.goff_l, w.gk_r, w.gc_r, w.gs_r, w.gst_r, w.goff_r};
   KPA_CHECK(launch_seg_tiles(w.goff_l, w.goff_r, n_seg, JT, w.tile_start, stream));
   KPA_LAUNCH("join_splits", k_join_splits, dim3((u32)std::min<u64>(ceil_div(w.max_tiles, BLOCK), 4096)),
-             dim3(BLOCK), 0, stream, js, w.tile_start, n_seg, w.split);
+             dim3(BLOCK), 0, stream, js, w.tile_start, n_seg, w.split, (u32)w.max_tiles);
   KPA_LAUNCH("join_match", k_join_match<false>, dim3((u32)w.max_tiles), dim3(BLOCK), 0, stream, js,
              w.tile_start, n_seg, w.split, out_count, out_sumprod, w.tile_pairs, lr, rr, out_pairs,
              pairs_cap);
@@ -289,6 +306,54 @@ kpa_status kpa_join(const uint64_t* lk, const uint32_t* lr, const uint64_t* l_se
                w.tile_start, n_seg, w.split, out_count, out_sumprod, w.tile_pairs, lr, rr,
                out_pairs, pairs_cap);
   }
+  return KPA_OK;
+}
+
+kpa_status kpa_join_runs_workspace_size(uint64_t gl_cap, uint64_t gr_cap, uint32_t n_seg,
+                                        size_t* bytes) {
+  clear_error();
+  KPA_REQUIRE(bytes, KPA_EINVAL, "bytes is null");
+  Carver c(nullptr);
+  JoinRunsWs w;
+  join_runs_plan(gl_cap, gr_cap, n_seg ? n_seg : 1, c, &w);
+  *bytes = c.used + 256;
+  return KPA_OK;
+}
+
+kpa_status kpa_join_runs(const uint64_t* l_gkey, const uint64_t* l_cnt, const uint64_t* l_sum,
+                         const uint64_t* l_gseg_off, uint64_t gl_cap, const uint64_t* r_gkey,
+                         const uint64_t* r_cnt, const uint64_t* r_sum, const uint64_t* r_gseg_off,
+                         uint64_t gr_cap, uint32_t n_seg, uint64_t* out_count,
+                         uint64_t* out_sumprod, void* ws, size_t ws_bytes, hipStream_t stream) {
+  clear_error();
+  if (n_seg == 0) return KPA_OK;
+  KPA_REQUIRE(l_gseg_off && r_gseg_off && out_count && out_sumprod && ws, KPA_EINVAL,
+              "null pointer");
+  KPA_REQUIRE((gl_cap == 0 || (l_gkey && l_cnt && l_sum)) &&
+                  (gr_cap == 0 || (r_gkey && r_cnt && r_sum)),
+              KPA_EINVAL, "null pointer");
+  KPA_REQUIRE(aligned(l_gkey, 8) && aligned(l_cnt, 8) && aligned(l_sum, 8) &&
+                  aligned(r_gkey, 8) && aligned(r_cnt, 8) && aligned(r_sum, 8) &&
+                  aligned(l_gseg_off, 8) && aligned(r_gseg_off, 8) && aligned(out_count, 8) &&
+                  aligned(out_sumprod, 8) && aligned(ws, 256),
+              KPA_EINVAL, "misaligned pointer");
+  KPA_REQUIRE(gl_cap < (1ull << 32) && gr_cap < (1ull << 32), KPA_EUNSUPPORTED,
+              "run lists must hold fewer than 2^32 groups");
+  Carver c(ws);
+  JoinRunsWs w;
+  join_runs_plan(gl_cap, gr_cap, n_seg, c, &w);
+  KPA_REQUIRE(c.used <= ws_bytes, KPA_EWORKSPACE, "workspace too small: need %zu bytes", c.used);
+  KPA_CHECK(launch_fill_u64(out_count, n_seg, 0, stream));
+  KPA_CHECK(launch_fill_u64(out_sumprod, n_seg, 0, stream));
+  // group starts are needed only to emit pairs, which this call does not
+  JoinSides js{l_gkey, l_cnt, l_sum, nullptr, l_gseg_off, r_gkey, r_cnt, r_sum, nullptr,
+               r_gseg_off};
+  KPA_CHECK(launch_seg_tiles(l_gseg_off, r_gseg_off, n_seg, JT, w.tile_start, stream));
+  KPA_LAUNCH("join_splits", k_join_splits, dim3((u32)std::min<u64>(ceil_div(w.max_tiles, BLOCK), 4096)),
+             dim3(BLOCK), 0, stream, js, w.tile_start, n_seg, w.split, (u32)w.max_tiles);
+  KPA_LAUNCH("join_match", k_join_match<false>, dim3((u32)w.max_tiles), dim3(BLOCK), 0, stream, js,
+             w.tile_start, n_seg, w.split, out_count, out_sumprod, w.tile_pairs, nullptr, nullptr,
+             nullptr, 0);
   return KPA_OK;
 }
 

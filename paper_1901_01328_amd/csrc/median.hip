@@ -32,7 +32,8 @@ __global__ void __launch_bounds__(BLOCK) k_median_small(MedSrc src, const u64* _
                                                         u32* __restrict__ mid_list,
                                                         u32* __restrict__ mid_count,
                                                         u32* __restrict__ big_list,
-                                                        u32* __restrict__ big_count) {
+                                                        u32* __restrict__ big_count,
+                                                        u64* __restrict__ out_sum) {
   const u64 G = gseg_off[n_seg];
   for (u64 g = (u64)blockIdx.x * BLOCK + threadIdx.x; g < G; g += (u64)gridDim.x * BLOCK) {
     const u64 c = gcnt[g], s = gstart[g];
@@ -44,6 +45,12 @@ __global__ void __launch_bounds__(BLOCK) k_median_small(MedSrc src, const u64* _
     u64 v[MED_SMALL];
 #pragma unroll
     for (u32 i = 0; i < MED_SMALL; ++i) v[i] = i < c ? src.val(s + i) : ~0ull;
+    if (out_sum) {
+      u64 sum = 0;
+#pragma unroll
+      for (u32 i = 0; i < MED_SMALL; ++i) sum += i < c ? v[i] : 0ull;
+      out_sum[g] = sum;
+    }
     const u32 h = (u32)(c - 1) / 2;
     u64 med = 0;
 #pragma unroll
@@ -64,8 +71,10 @@ __global__ void __launch_bounds__(BLOCK) k_median_mid(MedSrc src, const u64* __r
                                                       const u64* __restrict__ gstart,
                                                       const u32* __restrict__ list,
                                                       const u32* __restrict__ count,
-                                                      u64* __restrict__ out_med) {
+                                                      u64* __restrict__ out_med,
+                                                      u64* __restrict__ out_sum) {
   __shared__ u64 v[MED_MID];
+  __shared__ u64 red[WAVES];
   const u32 n = *count;
   for (u32 q = blockIdx.x; q < n; q += gridDim.x) {
     const u32 g = list[q];
@@ -74,8 +83,22 @@ __global__ void __launch_bounds__(BLOCK) k_median_mid(MedSrc src, const u64* __r
     u32 p2 = 1;
     while (p2 < c) p2 <<= 1;
     __syncthreads();
-    for (u32 i = threadIdx.x; i < p2; i += BLOCK) v[i] = i < c ? src.val(s + i) : ~0ull;
+    u64 part = 0;  // this thread's share of the group's sum
+    for (u32 i = threadIdx.x; i < p2; i += BLOCK) {
+      const u64 x = i < c ? src.val(s + i) : ~0ull;
+      v[i] = x;
+      part += i < c ? x : 0ull;
+    }
+    if (out_sum) {  // uniform
+      part = wave_sum(part);
+      if (__lane_id() == 0) red[threadIdx.x >> 6] = part;
+    }
     __syncthreads();
+    if (out_sum && threadIdx.x == 0) {
+      u64 sum = 0;
+      for (int w = 0; w < WAVES; ++w) sum += red[w];
+      out_sum[g] = sum;
+    }
     // bitonic sort of p2 values, ascending
     for (u32 k = 2; k <= p2; k <<= 1) {
       for (u32 j = k >> 1; j > 0; j >>= 1) {
@@ -101,14 +124,17 @@ __global__ void __launch_bounds__(BLOCK) k_median_big(MedSrc src, const u64* __r
                                                       const u64* __restrict__ gstart,
                                                       const u32* __restrict__ list,
                                                       const u32* __restrict__ count,
-                                                      u64* __restrict__ out_med) {
+                                                      u64* __restrict__ out_med,
+                                                      u64* __restrict__ out_sum) {
   __shared__ u32 h[MED_BINS];
   __shared__ u64 sel[2];
+  __shared__ u64 red[WAVES];
   const u32 n = *count;
   for (u32 q = blockIdx.x; q < n; q += gridDim.x) {
     const u32 g = list[q];
     const u64 c = gcnt[g], s = gstart[g];
     u64 prefix = 0, rank = (c - 1) / 2;
+    u64 part = 0;  // this thread's share of the group's sum (first byte pass)
     for (int byte = 7; byte >= 0; --byte) {
       const u32 shift = 8 * byte;
       const u64 himask = byte == 7 ? 0ull : (~0ull << (shift + 8));
@@ -117,6 +143,7 @@ __global__ void __launch_bounds__(BLOCK) k_median_big(MedSrc src, const u64* __r
       __syncthreads();
       for (u64 i = threadIdx.x; i < c; i += BLOCK) {
         const u64 x = src.val(s + i);
+        if (byte == 7) part += x;
         if ((x & himask) == prefix) atomicAdd(&h[(x >> shift) & 255], 1u);
       }
       __syncthreads();
@@ -135,6 +162,16 @@ __global__ void __launch_bounds__(BLOCK) k_median_big(MedSrc src, const u64* __r
       rank = sel[1];
     }
     if (threadIdx.x == 0) out_med[g] = prefix;
+    if (out_sum) {  // uniform; red is read by thread 0 only after the barrier
+      part = wave_sum(part);
+      if (__lane_id() == 0) red[threadIdx.x >> 6] = part;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        u64 sum = 0;
+        for (int w = 0; w < WAVES; ++w) sum += red[w];
+        out_sum[g] = sum;
+      }
+    }
   }
 }
 
@@ -176,34 +213,36 @@ kpa_status kpa_median_by_key_workspace_size(uint64_t n_cap, uint32_t n_seg, size
 kpa_status kpa_median_by_key(const uint64_t* keys, const uint32_t* rids, const uint64_t* seg_off,
                              uint32_t n_seg, uint64_t n_cap, const void* rows,
                              const kpa_row_layout* layout, uint64_t* out_gkey, uint64_t* out_med,
-                             uint64_t* out_gseg_off, void* ws, size_t ws_bytes,
-                             hipStream_t stream) {
+                             uint64_t* out_gseg_off, uint64_t* out_cnt, uint64_t* out_sum,
+                             void* ws, size_t ws_bytes, hipStream_t stream) {
   clear_error();
   KPA_CHECK(check_layout(layout, true, false));
   if (n_seg == 0) return KPA_OK;
   KPA_REQUIRE(keys && rids && seg_off && rows && out_gkey && out_med && out_gseg_off && ws,
               KPA_EINVAL, "null pointer");
   KPA_REQUIRE(aligned(keys, 8) && aligned(rids, 4) && aligned(rows, 16) && aligned(out_med, 8) &&
-                  aligned(out_gkey, 8) && aligned(out_gseg_off, 8) && aligned(ws, 256),
+                  aligned(out_gkey, 8) && aligned(out_gseg_off, 8) && aligned(ws, 256) &&
+                  aligned(out_cnt, 8) && aligned(out_sum, 8),
               KPA_EINVAL, "misaligned pointer");
   KPA_REQUIRE(n_cap < (1ull << 32), KPA_EUNSUPPORTED, "n_cap must be below 2^32");
   Carver c(ws);
   MedianWs w;
   median_plan(n_cap, n_seg, c, &w);
   KPA_REQUIRE(c.used <= ws_bytes, KPA_EWORKSPACE, "workspace too small: need %zu bytes", c.used);
-  ReduceOut o{out_gkey, w.gcnt, nullptr, nullptr, w.gstart, out_gseg_off};
+  u64* gcnt = out_cnt ? out_cnt : w.gcnt;  // the counts go where the caller wants them
+  ReduceOut o{out_gkey, gcnt, nullptr, nullptr, w.gstart, out_gseg_off};
   KPA_CHECK(reduce_launch(keys, rids, seg_off, n_seg, nullptr, nullptr, false, o, w.red, stream));
   KPA_CHECK(launch_fill_u32(w.counts, 2, 0, stream));
   MedSrc src{rids, static_cast<const unsigned char*>(rows), layout->row_bytes, layout->val_off,
              layout->val_w};
   const u32 grid = (u32)std::min<u64>(ceil_div(n_cap ? n_cap : 1, BLOCK), 8192);
-  KPA_LAUNCH("median_small", k_median_small, dim3(grid), dim3(BLOCK), 0, stream, src, w.gcnt,
+  KPA_LAUNCH("median_small", k_median_small, dim3(grid), dim3(BLOCK), 0, stream, src, gcnt,
              w.gstart, out_gseg_off, n_seg, out_med, w.mid_list, w.counts, w.big_list,
-             w.counts + 1);
-  KPA_LAUNCH("median_mid", k_median_mid, dim3(2048), dim3(BLOCK), 0, stream, src, w.gcnt, w.gstart,
-             w.mid_list, w.counts, out_med);
-  KPA_LAUNCH("median_big", k_median_big, dim3(512), dim3(BLOCK), 0, stream, src, w.gcnt, w.gstart,
-             w.big_list, w.counts + 1, out_med);
+             w.counts + 1, out_sum);
+  KPA_LAUNCH("median_mid", k_median_mid, dim3(2048), dim3(BLOCK), 0, stream, src, gcnt, w.gstart,
+             w.mid_list, w.counts, out_med, out_sum);
+  KPA_LAUNCH("median_big", k_median_big, dim3(512), dim3(BLOCK), 0, stream, src, gcnt, w.gstart,
+             w.big_list, w.counts + 1, out_med, out_sum);
   return KPA_OK;
 }
 

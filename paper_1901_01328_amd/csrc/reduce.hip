@@ -425,7 +425,7 @@ __global__ void __launch_bounds__(BLOCK, 4) k_reduce_main_seq(
     for (int j = 0; j < ITEMS; ++j) {
       const u32 i = tid + j * BLOCK;
       kv[j] = i < tr.cnt ? keys[tr.base + i] : 0ull;
-      vv[j] = i < tr.cnt ? vals[tr.base + i] : 0ull;
+      vv[j] = vals && i < tr.cnt ? vals[tr.base + i] : 0ull;
     }
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
@@ -441,17 +441,21 @@ __global__ void __launch_bounds__(BLOCK, 4) k_reduce_main_seq(
     const u32 last = tid * ITEMS + ITEMS;  // the next thread's first entry
     before = tid > 0 && tid * ITEMS - 1 < tr.cnt ? st[pidx(tid * ITEMS - 1)] : 0ull;
     after = last < tr.cnt ? st[pidx(last)] : 0ull;
-    __syncthreads();
 #pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-      const u32 i = tid + j * BLOCK;
-      if (i < tr.cnt) st[pidx(i)] = vv[j];
-    }
-    __syncthreads();
+    for (int j = 0; j < ITEMS; ++j) v[j] = 0ull;
+    if (vals) {  // uniform: without values (runs only) the second staging round is skipped
+      __syncthreads();
 #pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-      const u32 idx = tid * ITEMS + j;
-      v[j] = idx < tr.cnt ? st[pidx(idx)] : 0ull;
+      for (int j = 0; j < ITEMS; ++j) {
+        const u32 i = tid + j * BLOCK;
+        if (i < tr.cnt) st[pidx(i)] = vv[j];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < ITEMS; ++j) {
+        const u32 idx = tid * ITEMS + j;
+        v[j] = idx < tr.cnt ? st[pidx(idx)] : 0ull;
+      }
     }
   }
   const bool has_prev = tr.base > tr.a;
@@ -587,16 +591,21 @@ kpa_status reduce_launch(const u64* keys, const u32* rids, const u64* seg_off, u
              o.gseg_off);
   KPA_LAUNCH("reduce_scan", k_reduce_bapply, dim3(nb), dim3(SCAN_TILES), 0, st, w.heads, w.flags,
              w.tile_start, w.tile_seg, n_seg, w.bsum, w.gbase, o.gseg_off, o.cnt, o.sum, o.max);
-  const bool seq = !rids && need_val && L && L->row_bytes == 8 && L->val_off == 0 &&
-                   L->val_w == 8;
+  // In KPA order (8-byte values, no row ids), or no values at all (runs,
+  // counts and group starts only): the sequential kernel, which reads no
+  // row ids; values are read through the row ids otherwise.
+  const bool in_order = !rids && need_val && L && L->row_bytes == 8 && L->val_off == 0 &&
+                        L->val_w == 8;
+  const bool seq = in_order || !need_val;
+  const u64* seq_vals = in_order ? reinterpret_cast<const u64*>(rows) : nullptr;
   if (seq && o.gstart)
     KPA_LAUNCH("reduce_main", k_reduce_main_seq<true>, dim3((u32)w.max_tiles), dim3(BLOCK), 0, st,
-               keys, reinterpret_cast<const u64*>(rows), seg_off, w.tile_start, w.tile_seg,
-               n_seg, w.gbase, o.gkey, o.cnt, o.sum, o.max, o.gstart);
+               keys, seq_vals, seg_off, w.tile_start, w.tile_seg, n_seg, w.gbase, o.gkey, o.cnt,
+               o.sum, o.max, o.gstart);
   else if (seq)
     KPA_LAUNCH("reduce_main", k_reduce_main_seq<false>, dim3((u32)w.max_tiles), dim3(BLOCK), 0,
-               st, keys, reinterpret_cast<const u64*>(rows), seg_off, w.tile_start, w.tile_seg,
-               n_seg, w.gbase, o.gkey, o.cnt, o.sum, o.max, o.gstart);
+               st, keys, seq_vals, seg_off, w.tile_start, w.tile_seg, n_seg, w.gbase, o.gkey,
+               o.cnt, o.sum, o.max, o.gstart);
   else
     KPA_LAUNCH("reduce_main", k_reduce_main, dim3((u32)w.max_tiles), dim3(BLOCK), 0, st, keys,
                rids, seg_off, w.tile_start, w.tile_seg, n_seg, vs, w.gbase, o.gkey, o.cnt, o.sum,

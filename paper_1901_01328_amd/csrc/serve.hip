@@ -812,8 +812,8 @@ bool do_close(Server* s, const CloseJob& j, kpa_window_result* res, std::string*
     if (!g || kpa_median_by_key_workspace_size(N, 1, &mwb) != KPA_OK) return false;
     void* mws = cb.take(mwb);
     if (!mws) return false;
-    if (kpa_median_by_key(mk[0], mr[0], small, 1, N, mv[0], &V, g, g + N, small + 8, mws,
-                          mwb, st) != KPA_OK)
+    if (kpa_median_by_key(mk[0], mr[0], small, 1, N, mv[0], &V, g, g + N, small + 8, nullptr,
+                          nullptr, mws, mwb, st) != KPA_OK)
       return false;
     cols[0] = g, cols[1] = g + N;
     ncols = 2;

@@ -191,9 +191,12 @@ _SIGS = {
     "kpa_topk_by_sum": ([_vp, _vp, _vp, _u32, _u64, _u32, _vp, _vp, _vp, _vp, C.c_size_t, _vp],
                         C.c_int32),
     "kpa_median_by_key_workspace_size": ([_u64, _u32, _sz], C.c_int32),
-    "kpa_median_by_key": ([_vp, _vp, _vp, _u32, _u64, _vp, _lay, _vp, _vp, _vp, _vp, C.c_size_t,
-                           _vp], C.c_int32),
+    "kpa_median_by_key": ([_vp, _vp, _vp, _u32, _u64, _vp, _lay, _vp, _vp, _vp, _vp, _vp, _vp,
+                           C.c_size_t, _vp], C.c_int32),
     "kpa_join_workspace_size": ([_u64, _u64, _u32, _sz], C.c_int32),
+    "kpa_join_runs_workspace_size": ([_u64, _u64, _u32, _sz], C.c_int32),
+    "kpa_join_runs": ([_vp, _vp, _vp, _vp, _u64, _vp, _vp, _vp, _vp, _u64, _u32, _vp, _vp, _vp,
+                       C.c_size_t, _vp], C.c_int32),
     "kpa_join": ([_vp, _vp, _vp, _u64, _vp, _vp, _vp, _u64, _u32, _vp, _vp, _lay, _vp, _vp, _vp,
                   _u64, _vp, _vp, C.c_size_t, _vp], C.c_int32),
     "kpa_materialize": ([_vp, _u64, _vp, _u32, _vp, _vp], C.c_int32),
@@ -662,6 +665,8 @@ def kpa_topk_by_sum(gkey, gsum, gseg_off, k=10, g_cap=None, ws=None, stream=None
 
 def kpa_median_by_key(keys, rids, seg_off, rows, layout, n_cap=None, ws=None, stream=None,
                       outs=None):
+    """Returns (gkey, gmed, gseg_off); outs may also name "cnt" and "sum"
+    arrays, which then receive each group's count and sum of values."""
     n_seg = seg_off.numel() - 1
     n_cap = keys.numel() if n_cap is None else n_cap
     dev = keys.device
@@ -675,7 +680,8 @@ def kpa_median_by_key(keys, rids, seg_off, rows, layout, n_cap=None, ws=None, st
     ws = _ws(nb, dev, ws, stream)
     L = layout_struct(layout)
     _call("kpa_median_by_key", _p(keys), _p(rids), _p(seg_off), n_seg, n_cap, _p(rows), C.byref(L),
-          _p(gkey), _p(gmed), _p(gseg), _p(ws), ws.numel() * ws.element_size(), _stream(stream))
+          _p(gkey), _p(gmed), _p(gseg), _p(o.get("cnt")), _p(o.get("sum")), _p(ws),
+          ws.numel() * ws.element_size(), _stream(stream))
     return gkey, gmed, gseg
 
 
@@ -701,6 +707,26 @@ def kpa_join(lk, lr, l_seg_off, rk, rr, r_seg_off, rows_l, rows_r, layout, pairs
           n_seg, _p(rows_l), _p(rows_r), C.byref(L), _p(count), _p(sumprod), _p(pairs), pairs_cap,
           _p(npairs), _p(ws), ws.numel() * ws.element_size(), _stream(stream))
     return count, sumprod, pairs, npairs
+
+
+def kpa_join_runs(l_gkey, l_cnt, l_sum, l_gseg_off, r_gkey, r_cnt, r_sum, r_gseg_off,
+                  gl_cap=None, gr_cap=None, ws=None, stream=None, outs=None):
+    """Per-segment pair count and sum of value products from two run lists
+    (key, count, sum per group); returns (count, sumprod)."""
+    n_seg = l_gseg_off.numel() - 1
+    gl_cap = l_gkey.numel() if gl_cap is None else gl_cap
+    gr_cap = r_gkey.numel() if gr_cap is None else gr_cap
+    dev = l_gkey.device
+    o = outs or {}
+    count = o["count"] if "count" in o else torch.empty(n_seg, dtype=torch.int64, device=dev)
+    sumprod = o["sumprod"] if "sumprod" in o else torch.empty(n_seg, dtype=torch.int64,
+                                                               device=dev)
+    nb = _ws_size("kpa_join_runs_workspace_size", gl_cap, gr_cap, n_seg)
+    ws = _ws(nb, dev, ws, stream)
+    _call("kpa_join_runs", _p(l_gkey), _p(l_cnt), _p(l_sum), _p(l_gseg_off), gl_cap, _p(r_gkey),
+          _p(r_cnt), _p(r_sum), _p(r_gseg_off), gr_cap, n_seg, _p(count), _p(sumprod), _p(ws),
+          ws.numel() * ws.element_size(), _stream(stream))
+    return count, sumprod
 
 
 def kpa_materialize(rids, rows, row_bytes, out_rows=None, stream=None):

@@ -212,11 +212,16 @@ class JoinMedian:
     (Sec. 4.2 temporal join; Sec. 6 windowed median per key): each stream is
     partitioned into window KPAs (value column staged), each window's KPA is
     sorted, the lower median of every key is computed on both streams, and
-    the two sorted KPAs are merge-joined window by window (count and sum of
-    value products mod 2^64)."""
+    the two streams are merge-joined window by window (count and sum of
+    value products mod 2^64).  The median pass also writes each key's count
+    and sum of values, so the join intersects those two run lists
+    (kpa_join_runs) and reads no value again; join_runs=False joins the
+    sorted KPAs themselves (kpa_join), which reduces each side once more."""
 
-    def __init__(self, n_l, n_r, layout, win_len, n_win, device="cuda", win_origin=0):
+    def __init__(self, n_l, n_r, layout, win_len, n_win, device="cuda", win_origin=0,
+                 join_runs=True):
         self.n = (n_l, n_r)
+        self.join_runs = join_runs
         self.layout, self.win_len, self.n_win, self.origin = layout, win_len, n_win, win_origin
         d = torch.device(device)
         i64 = dict(dtype=torch.int64, device=d)
@@ -238,8 +243,12 @@ class JoinMedian:
                 "ws_med": torch.empty(K._ws_size("kpa_median_by_key_workspace_size", n, n_win),
                                       **u8),
             }
+            if join_runs:  # each key's count and sum, written by the median pass
+                sd["med"]["cnt"] = torch.empty(cap, **i64)
+                sd["med"]["sum"] = torch.empty(cap, **i64)
             self.side.append(sd)
-        self.ws_join = torch.empty(K._ws_size("kpa_join_workspace_size", n_l, n_r, n_win), **u8)
+        jws = ("kpa_join_runs_workspace_size" if join_runs else "kpa_join_workspace_size")
+        self.ws_join = torch.empty(K._ws_size(jws, n_l, n_r, n_win), **u8)
         self.join = {"count": torch.empty(n_win, **i64), "sumprod": torch.empty(n_win, **i64),
                      "npairs": torch.empty(1, **i64)}
 
@@ -255,9 +264,15 @@ class JoinMedian:
             K.kpa_median_by_key(sd["skeys"], sd["srids"], sd["off"], sd["vals"], VALUE_COLUMN,
                                 n_cap=n, ws=sd["ws_med"], stream=stream, outs=sd["med"])
         L, R = self.side
-        K.kpa_join(L["skeys"], L["srids"], L["off"], R["skeys"], R["srids"], R["off"], L["vals"],
-                   R["vals"], VALUE_COLUMN, nl_cap=self.n[0], nr_cap=self.n[1], ws=self.ws_join,
-                   stream=stream, outs=self.join)
+        if self.join_runs:
+            lm, rm = L["med"], R["med"]
+            K.kpa_join_runs(lm["gkey"], lm["cnt"], lm["sum"], lm["gseg_off"], rm["gkey"],
+                            rm["cnt"], rm["sum"], rm["gseg_off"], gl_cap=self.n[0],
+                            gr_cap=self.n[1], ws=self.ws_join, stream=stream, outs=self.join)
+        else:
+            K.kpa_join(L["skeys"], L["srids"], L["off"], R["skeys"], R["srids"], R["off"],
+                       L["vals"], R["vals"], VALUE_COLUMN, nl_cap=self.n[0], nr_cap=self.n[1],
+                       ws=self.ws_join, stream=stream, outs=self.join)
 
 
 class SlidingAggregation:

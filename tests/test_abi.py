@@ -64,6 +64,18 @@ def test_host_side_errors_without_gpu():
         assert lib.kpa_batch_sort_workspace_size(1 << 20, 4, ctypes.byref(cfg),
                                                  ctypes.byref(n)) == want, bl
     assert b"bucket_log2" in lib.kpa_last_error_string()
+    # run-list join: pointers and sizes are checked before anything is enqueued
+    fake = ctypes.c_void_p(1 << 20)          # aligned, never dereferenced on these paths
+    rc = lib.kpa_join_runs(fake, fake, fake, fake, 10, fake, fake, fake, fake, 10, 2, None, fake,
+                           fake, 1 << 20, None)
+    assert rc == k.KPA_EINVAL
+    rc = lib.kpa_join_runs(fake, fake, fake, fake, 1 << 32, fake, fake, fake, fake, 10, 2, fake,
+                           fake, fake, 1 << 20, None)
+    assert rc == k.KPA_EUNSUPPORTED
+    rc = lib.kpa_join_runs(fake, fake, fake, fake, 1000, fake, fake, fake, fake, 1000, 2, fake,
+                           fake, fake, 16, None)
+    assert rc == k.KPA_EWORKSPACE
+    assert lib.kpa_join_runs_workspace_size(1000, 1000, 2, ctypes.byref(n)) == 0 and n.value > 16
 
 
 def test_server_config_checked_on_the_host():

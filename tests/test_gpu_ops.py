@@ -156,6 +156,42 @@ def test_join_no_match_and_empty_windows(K, orc):
     assert int(u64(npairs)[0]) == 0
 
 
+@pytest.mark.parametrize("n,n_keys,span", [(5000, 1 << 20, None), (70001, 30000, None),
+                                           (200000, 1 << 24, None), (40000, 7, None),
+                                           (3000, 1 << 24, 3 * 10 ** 5)])
+def test_join_runs_equals_join(K, orc, n, n_keys, span):
+    """The join of two run lists (each key's count and sum, from the median
+    pass) equals the join of the sorted KPAs and the oracle, window by
+    window; the last case leaves windows 3..9 empty on both sides."""
+    W, nw = 10 ** 5, 10
+    kw = {} if span is None else {"span": span}
+    L = c3_rows(n, 0, n_keys, **kw)
+    R = c3_rows(n + 17, 1, n_keys, **kw)
+    dl, dr = L.cuda(), R.cuda()
+    lk, lr, loff = windows(K, dl, LAYOUT32, W, nw)
+    rk, rr, roff = windows(K, dr, LAYOUT32, W, nw)
+    say(f"join runs n={n} keys={n_keys}")
+    runs = []
+    for k_, r_, o_, d_ in ((lk, lr, loff, dl), (rk, rr, roff, dr)):
+        o = {"cnt": torch.empty(k_.numel(), dtype=torch.int64, device="cuda"),
+             "sum": torch.empty(k_.numel(), dtype=torch.int64, device="cuda")}
+        gk, _, gseg = K.kpa_median_by_key(k_, r_, o_, d_, LAYOUT32, outs=o)
+        runs.append((gk, o["cnt"], o["sum"], gseg))
+    (a, b, c, d), (e, f, g, h) = runs
+    cnt, sp = K.kpa_join_runs(a, b, c, d, e, f, g, h)
+    cnt2, sp2, _, _ = K.kpa_join(lk, lr, loff, rk, rr, roff, dl, dr, LAYOUT32)
+    torch.cuda.synchronize()
+    assert np.array_equal(u64(cnt), u64(cnt2)) and np.array_equal(u64(sp), u64(sp2))
+    hl = orc.partition(L, LAYOUT32, W, nw)
+    hr = orc.partition(R, LAYOUT32, W, nw)
+    for w in range(nw):
+        a0, a1 = int(hl[2][w]), int(hl[2][w + 1])
+        b0, b1 = int(hr[2][w]), int(hr[2][w + 1])
+        ec, es, _, _ = orc.join(hl[0][a0:a1], hl[1][a0:a1], hr[0][b0:b1], hr[1][b0:b1], L, R,
+                                LAYOUT32)
+        assert int(u64(cnt)[w]) == ec and int(u64(sp)[w]) == es, w
+
+
 def median_expect(orc, keys, rids, off, rows, layout):
     gk, gm, goff = [], [], [0]
     for a, b in zip(off[:-1], off[1:]):
@@ -182,7 +218,10 @@ def test_median_by_key(K, orc, case):
     d = rows.cuda()
     sk, sr, off = windows(K, d, lay, W, nw)
     say(f"median {case}")
-    gk, gm, gseg = K.kpa_median_by_key(sk, sr, off, d, lay)
+    cap = sk.numel()
+    sums = {"cnt": torch.empty(cap, dtype=torch.int64, device="cuda"),
+            "sum": torch.empty(cap, dtype=torch.int64, device="cuda")}
+    gk, gm, gseg = K.kpa_median_by_key(sk, sr, off, d, lay, outs=sums)
     torch.cuda.synchronize()
     hk, hr, hoff, _ = orc.partition(rows, lay, W, nw)
     ek, em, eoff = median_expect(orc, hk, hr, hoff, rows, lay)
@@ -190,3 +229,15 @@ def test_median_by_key(K, orc, case):
     g = int(eoff[-1])
     assert np.array_equal(u64(gk)[:g], ek)
     assert np.array_equal(u64(gm)[:g], em)
+    # the counts and value sums written on the way equal the keyed reduction's
+    ec, es = [], []
+    for a, b in zip(hoff[:-1], hoff[1:]):
+        _, c, sm, _ = orc.reduce_by_key(hk[int(a):int(b)], hr[int(a):int(b)], rows, lay)
+        ec.append(c)
+        es.append(sm)
+    assert np.array_equal(u64(sums["cnt"])[:g], np.concatenate(ec))
+    assert np.array_equal(u64(sums["sum"])[:g], np.concatenate(es))
+    # without them the medians are the same
+    gk2, gm2, _ = K.kpa_median_by_key(sk, sr, off, d, lay)
+    torch.cuda.synchronize()
+    assert np.array_equal(u64(gm2)[:g], em) and np.array_equal(u64(gk2)[:g], ek)
