@@ -80,7 +80,8 @@ __global__ void __launch_bounds__(BLOCK) k_join_match(JoinSides js, const u32* _
   const u32 la = (u32)(i1 - i0), lb = (u32)(j1 - j0);
   for (u32 x = threadIdx.x; x < lb; x += BLOCK) sm.rk[x] = js.gk_r[r0 + j0 + x];
   __syncthreads();
-  // thread t takes L runs [t*16, t*16+16) of the tile, in order
+  // when pairs are emitted, thread t takes L runs [t*16, t*16+16) of the
+  // tile, in order (its pairs then follow those of thread t-1)
   u64 cnt = 0, sp = 0, npairs = 0;
   const u32 a0 = threadIdx.x * ITEMS, a1 = min(la, a0 + ITEMS);
   // R run matching L run a of the tile, or ~0
@@ -95,16 +96,18 @@ __global__ void __launch_bounds__(BLOCK) k_join_match(JoinSides js, const u32* _
     if (a + 1 == la && j1 < nr && js.gk_r[r0 + j1] == key) return j1;
     return ~0ull;
   };
-  for (u32 a = a0; a < a1; ++a) {
-    const u64 jm = match(a);
-    if (jm != ~0ull) {
-      const u64 cl = js.gc_l[l0 + i0 + a], cr = js.gc_r[r0 + jm];
-      cnt += cl * cr;
-      sp += js.gs_l[l0 + i0 + a] * js.gs_r[r0 + jm];
-      npairs += cl * cr;
-    }
-  }
   if (!EMIT) {
+    // Totals only: the order of the runs does not matter, so lane i of a wave
+    // takes run i of each 256-run stretch and the loads of the L runs (and of
+    // the matched R runs, which ascend with them) coalesce.
+    for (u32 a = threadIdx.x; a < la; a += BLOCK) {
+      const u64 jm = match(a);
+      if (jm != ~0ull) {
+        const u64 cl = js.gc_l[l0 + i0 + a], cr = js.gc_r[r0 + jm];
+        cnt += cl * cr;
+        sp += js.gs_l[l0 + i0 + a] * js.gs_r[r0 + jm];
+      }
+    }
     cnt = wave_sum(cnt);
     sp = wave_sum(sp);
     __syncthreads();
@@ -124,6 +127,10 @@ __global__ void __launch_bounds__(BLOCK) k_join_match(JoinSides js, const u32* _
       tile_pairs[tile] = c;
     }
     return;
+  }
+  for (u32 a = a0; a < a1; ++a) {
+    const u64 jm = match(a);
+    if (jm != ~0ull) npairs += js.gc_l[l0 + i0 + a] * js.gc_r[r0 + jm];
   }
   // exclusive scan of the threads' pair counts (u64) within the tile
   u64 incl = npairs;
