@@ -350,8 +350,9 @@ def test_pipeline_twice_same_result(K, orc):
 @pytest.mark.parametrize("algo", ["learned", "radix"])
 def test_window_pipeline_routes_match_oracle(K, orc, algo):
     """The windowed pipeline over three batches (the learned route's models
-    come from the previous batch's windows): per-window count/sum/max per
-    key against the oracle."""
+    come from the previous batch's windows; its first batch sorts by radix):
+    the sorted window KPAs and per-window count/sum/max per key against the
+    oracle after every batch."""
     from paper_1901_01328_amd.pipeline import WindowAggregation
     n, W, nw = 400001, 10 ** 5, 10
     a = K.KPA_SORT_LEARNED if algo == "learned" else K.KPA_SORT_RADIX
@@ -361,15 +362,17 @@ def test_window_pipeline_routes_match_oracle(K, orc, algo):
         say(f"window pipeline {algo} batch {batch}")
         p.step(rows.cuda())
         torch.cuda.synchronize()
-    hk, hr, hoff, _ = orc.partition(rows, LAYOUT32, W, nw)
-    gseg = u64(p.gseg)
-    for w in range(nw):
-        a0, b0 = int(hoff[w]), int(hoff[w + 1])
-        sk, sr = orc.sort(hk[a0:b0], hr[a0:b0])
-        ek, ec, es, em = orc.reduce_by_key(sk, sr, rows, LAYOUT32)
-        g0, g1 = int(gseg[w]), int(gseg[w + 1])
-        assert g1 - g0 == len(ek), w
-        assert np.array_equal(u64(p.gkey)[g0:g1], ek), w
-        assert np.array_equal(u64(p.g["cnt"])[g0:g1], ec), w
-        assert np.array_equal(u64(p.g["sum"])[g0:g1], es), w
-        assert np.array_equal(u64(p.g["max"])[g0:g1], em), w
+        hk, hr, hoff, _ = orc.partition(rows, LAYOUT32, W, nw)
+        gseg = u64(p.gseg)
+        for w in range(nw):
+            a0, b0 = int(hoff[w]), int(hoff[w + 1])
+            sk, sr = orc.sort(hk[a0:b0], hr[a0:b0])
+            assert np.array_equal(u64(p.skeys)[a0:b0], sk) and np.array_equal(
+                u32(p.srids)[a0:b0], sr), (batch, w)
+            ek, ec, es, em = orc.reduce_by_key(sk, sr, rows, LAYOUT32)
+            g0, g1 = int(gseg[w]), int(gseg[w + 1])
+            assert g1 - g0 == len(ek), (batch, w)
+            assert np.array_equal(u64(p.gkey)[g0:g1], ek), (batch, w)
+            assert np.array_equal(u64(p.g["cnt"])[g0:g1], ec), (batch, w)
+            assert np.array_equal(u64(p.g["sum"])[g0:g1], es), (batch, w)
+            assert np.array_equal(u64(p.g["max"])[g0:g1], em), (batch, w)
