@@ -16,7 +16,7 @@
 
 namespace kpa {
 
-constexpr int HIST_TILES_PER_BLOCK = 8;
+constexpr int HIST_TILES_PER_BLOCK = 8;  // most tiles a histogram workgroup takes at a time
 
 struct DigitSortBufs {
   const u64* keys_in;
@@ -83,7 +83,7 @@ template <class DF>
 __global__ void __launch_bounds__(BLOCK) k_ds_hist(const u64* __restrict__ keys, SegList sl,
                                                    const u32* __restrict__ tile_start,
                                                    typename DF::Params prm,
-                                                   u32* __restrict__ hist) {
+                                                   u32* __restrict__ hist, u32 tpb) {
   __shared__ u32 h[WAVES][DF::PASSES][RADIX];
   __shared__ float dfsm[DF::SMEM];
   const u32 tid = threadIdx.x;
@@ -106,9 +106,8 @@ __global__ void __launch_bounds__(BLOCK) k_ds_hist(const u64* __restrict__ keys,
   for (int p = 0; p < DF::PASSES; ++p)
 #pragma unroll
     for (int ww = 0; ww < WAVES; ++ww) h[ww][p][tid] = 0;
-  for (u32 t0 = blockIdx.x * HIST_TILES_PER_BLOCK; t0 < total;
-       t0 += gridDim.x * HIST_TILES_PER_BLOCK) {
-    const u32 t1 = min(total, t0 + HIST_TILES_PER_BLOCK);
+  for (u32 t0 = blockIdx.x * tpb; t0 < total; t0 += gridDim.x * tpb) {
+    const u32 t1 = min(total, t0 + tpb);
     u32 cur = find_seg(tile_start, n_seg, t0);
     DF df(prm, cur);
     __syncthreads();
@@ -601,9 +600,13 @@ kpa_status digit_sort_launch(const SegList& sl, const typename DF::Params& prm,
              with_hist ? b.hist : nullptr, (u32)DF::PASSES, b.status0, b.counters, b.order,
              b.max_tiles);
   if (with_hist) {
-    const u32 hist_blocks = (u32)std::min<u64>(ceil_div(b.max_tiles, HIST_TILES_PER_BLOCK), 4096);
+    // tiles per workgroup: up to HIST_TILES_PER_BLOCK, fewer for small sorts
+    // (a bundle's) so that they still spread over many workgroups
+    const u32 tpb = (u32)std::min<u64>(HIST_TILES_PER_BLOCK,
+                                       std::max<u64>(1, ceil_div(b.max_tiles, 2048)));
+    const u32 hist_blocks = (u32)std::min<u64>(ceil_div(b.max_tiles, tpb), 4096);
     KPA_LAUNCH(radix ? "radix_hist" : "learned_hist", k_ds_hist<DF>, dim3(hist_blocks),
-               dim3(BLOCK), 0, st, b.keys_in, sl, b.tile_start, prm, b.hist);
+               dim3(BLOCK), 0, st, b.keys_in, sl, b.tile_start, prm, b.hist, tpb);
     KPA_LAUNCH(radix ? "radix_scan" : "learned_scan", k_ds_scan<DF>,
                dim3(std::min<u32>(sl.n_max, 2048)), dim3(BLOCK), 0, st, sl, b.hist, b.seg_mask,
                b.unsupported);

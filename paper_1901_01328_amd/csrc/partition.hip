@@ -17,7 +17,7 @@
 
 namespace kpa {
 
-constexpr u32 PART_HIST_ROWS = 1u << 16;  // rows per histogram workgroup
+constexpr u32 PART_HIST_ROWS = 1u << 16;  // most rows per histogram workgroup
 constexpr u32 PART_CHUNK_LOG2 = 29;       // rows per look-back chain: 2^29
 constexpr u32 PART_CHUNK_TILES = (1u << PART_CHUNK_LOG2) / TILE;
 static_assert(((1u << PART_CHUNK_LOG2) % PART_HIST_ROWS) == 0, "histogram blocks inside chunks");
@@ -95,14 +95,14 @@ __global__ void __launch_bounds__(BLOCK) k_part_hist(const unsigned char* __rest
                                                      u64 n, u32 row_bytes, u32 ts_off, u32 ts_w,
                                                      WinParams wp, u32* __restrict__ counts,
                                                      u32 val_off, u32 val_w,
-                                                     u64* __restrict__ out_vals) {
+                                                     u64* __restrict__ out_vals, u32 rpb) {
   __shared__ u32 h[WAVES][RADIX + 1];
   const u32 tid = threadIdx.x;
   const u32 w = tid >> 6;
   for (u32 i = tid; i < WAVES * (RADIX + 1); i += BLOCK) (&h[0][0])[i] = 0;
   __syncthreads();
-  const u64 r0 = (u64)blockIdx.x * PART_HIST_ROWS;
-  const u64 r1 = min(n, r0 + PART_HIST_ROWS);
+  const u64 r0 = (u64)blockIdx.x * rpb;
+  const u64 r1 = min(n, r0 + rpb);
   counts += (r0 >> PART_CHUNK_LOG2) * (RADIX + 1);
   for (u64 b = r0; b < r1; b += (u64)BLOCK * PART_HIST_U) {
     u64 ts[PART_HIST_U], vv[PART_HIST_U];
@@ -300,8 +300,14 @@ static kpa_status part_launch(const unsigned char* r, u64 n, u32 row_bytes, u32 
   KPA_CHECK(launch_fill_u32(w.counter, 1, 0, stream));
   KPA_CHECK(launch_fill_u32(w.status, w.n_tiles * RADIX, 0, stream));
   if (n) {
-    KPA_LAUNCH("part_hist", k_part_hist, dim3((u32)ceil_div(n, PART_HIST_ROWS)), dim3(BLOCK), 0,
-               stream, r, n, row_bytes, ts_off, ts_w, wp, w.counts, val_off, val_w, out_vals);
+    // rows per workgroup: a power of two from BLOCK*PART_HIST_U up to
+    // PART_HIST_ROWS (so that a chunk holds whole workgroups), small enough
+    // that a bundle of a few hundred thousand rows still spreads over dozens
+    // of workgroups
+    u32 rpb = BLOCK * PART_HIST_U;
+    while (rpb < PART_HIST_ROWS && (u64)rpb * 1024 < n) rpb <<= 1;
+    KPA_LAUNCH("part_hist", k_part_hist, dim3((u32)ceil_div(n, rpb)), dim3(BLOCK), 0, stream, r,
+               n, row_bytes, ts_off, ts_w, wp, w.counts, val_off, val_w, out_vals, rpb);
   }
   KPA_LAUNCH("part_scan", k_part_scan, dim3(1), dim3(BLOCK), 0, stream, w.counts, w.n_chunks,
              n_win, w.woff, out_win_off, out_oob);
