@@ -192,6 +192,40 @@ def test_join_runs_equals_join(K, orc, n, n_keys, span):
         assert int(u64(cnt)[w]) == ec and int(u64(sp)[w]) == es, w
 
 
+def test_median_and_sums_at_every_size_class_edge(K, orc):
+    """Groups of exactly the sizes where the median changes method (one
+    thread up to 16 values, one workgroup in LDS up to 4096, radix selection
+    above), with values that wrap the 64-bit sum: medians, counts and sums
+    against the oracle.  Keys interleave in arrival order, so every group is
+    spread over the window."""
+    sizes = [1, 2, 15, 16, 17, 18, 255, 4095, 4096, 4097, 9001]
+    rng = np.random.default_rng(41)
+    keys = np.repeat(rng.integers(1, 2 ** 63, len(sizes), dtype=np.int64), sizes)
+    rng.shuffle(keys)
+    n = len(keys)
+    rows = torch.zeros((n, 4), dtype=torch.int64)
+    rows[:, 0] = torch.from_numpy(keys)
+    rows[:, 1] = torch.from_numpy(rng.integers(-2 ** 63, 2 ** 63 - 1, n, dtype=np.int64))
+    rows[::7, 1] = 99                   # repeated values
+    rows[:, 2] = torch.arange(n) * 10   # one window
+    d = rows.cuda()
+    sk, sr, off = windows(K, d, LAYOUT32, 10 ** 9, 1)
+    say(f"median edges n={n}")
+    sums = {"cnt": torch.empty(n, dtype=torch.int64, device="cuda"),
+            "sum": torch.empty(n, dtype=torch.int64, device="cuda")}
+    gk, gm, gseg = K.kpa_median_by_key(sk, sr, off, d, LAYOUT32, outs=sums)
+    torch.cuda.synchronize()
+    hk, hr, hoff, _ = orc.partition(rows, LAYOUT32, 10 ** 9, 1)
+    sk_, sr_ = orc.sort(hk, hr)
+    ek, em = orc.median_by_key(sk_, sr_, rows, LAYOUT32)
+    _, ec, es, _ = orc.reduce_by_key(sk_, sr_, rows, LAYOUT32)
+    g = len(ek)
+    assert g == len(sizes) and int(u64(gseg)[1]) == g
+    assert sorted(ec.tolist()) == sorted(sizes)
+    assert np.array_equal(u64(gk)[:g], ek) and np.array_equal(u64(gm)[:g], em)
+    assert np.array_equal(u64(sums["cnt"])[:g], ec) and np.array_equal(u64(sums["sum"])[:g], es)
+
+
 def median_expect(orc, keys, rids, off, rows, layout):
     gk, gm, goff = [], [], [0]
     for a, b in zip(off[:-1], off[1:]):
